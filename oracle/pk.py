@@ -1,0 +1,127 @@
+"""Binned power spectrum and its covariance across realizations.
+Test infrastructure only.
+
+Sec. 3.2 of the paper estimates the spectrum of a map phi by a DFT, squaring
+the modulus and averaging over the modes of a shell (eq. Def spec):
+P^(l) = (1/V) (1/N_l) sum_{l' in shell} |phi~(l')|^2, phi~ the Fourier
+transform with the cell area as measure, V the survey area.  For counts the
+map is the galaxy contrast delta_g = (N/f - N^)/N^ on unmasked cells (zero
+where f = 0) with N^ = N_tot / sum f (eq. Estim); no shot noise is
+subtracted.  The spectrum covariance is estimated from many realizations and
+normalised as C_ab = <P_a P_b> / (<P_a><P_b>) - 1 (the matrix in eq. cuminfo).
+
+With phi~(q) = h^d F(q), F the plain DFT sum_x phi(x) exp(-2 pi i q.x / N), and
+V = N^d h^d this is P^_b = (h^d / N^d) mean_{q in b} |F(q)|^2.
+
+Readings taken here:
+
+* Shells are linear in |k| on (0, k_Ny], k_Ny = pi / h (the pixel scale of
+  Sec. 3.3), for a cubic grid: mode q (signed frequencies q~_i = q_i for
+  q_i <= N/2, else q_i - N) is in shell b when b < nb |k| / k_Ny <= b + 1,
+  i.e. |k| / k_Ny = 2 |q~| / N.  Evaluated exactly in integers: b + 1 is the
+  smallest s >= 0 with s^2 N^2 >= 4 nb^2 |q~|^2.  The DC mode and corner modes
+  beyond k_Ny are in no shell.  (The paper bins in ln l; the linear rule is
+  the configuration used here.)
+* N_b counts every full-grid mode (q and -q separately).
+* Covariance across R realizations: the unbiased Cov_ab with 1/(R - 1), and
+  the paper's normalised C_ab with 1/R sample means.
+
+Parity: pinned by Parseval's identity, the single-plane-wave closed form, the
+white-noise level, a brute-force shell enumeration in Python integers, the
+closed-form expected survey power of a Gaussian field, and numpy.cov.  See
+``tests/test_oracle_pk.py``.
+"""
+
+import numpy as np
+
+
+def signed_freq(n):
+    """q~ = q for q <= n/2, q - n otherwise."""
+    q = np.arange(n)
+    return np.where(q <= n // 2, q, q - n)
+
+
+def shell_index(n, nbins):
+    """Shell of every mode of a cubic grid (shape n), -1 where the mode is in no shell."""
+    n = tuple(int(x) for x in n)
+    if len(set(n)) != 1:
+        raise ValueError("shell rule is defined for cubic grids")
+    N = n[0]
+    grids = np.meshgrid(*[signed_freq(N).astype(np.int64) for _ in n], indexing="ij")
+    q2 = sum(g * g for g in grids)
+    t = 4 * int(nbins) ** 2 * q2
+    # r = smallest integer with r*r >= t (exact integer ceil-sqrt)
+    r = np.floor(np.sqrt(t.astype(np.float64))).astype(np.int64)
+    r = np.where(r * r < t, r + 1, r)
+    r = np.where((r - 1) * (r - 1) >= t, r - 1, r)
+    r = np.where(r * r < t, r + 1, r)
+    s = -(-r // N)  # ceil(r / N): smallest s with s*N >= r
+    b = s - 1
+    return np.where((b >= 0) & (b < nbins), b, -1)
+
+
+def shell_stats(n, h, nbins):
+    """(N_b, mean |k| per shell) for a cubic grid with cell side h."""
+    n = tuple(int(x) for x in n)
+    b = shell_index(n, nbins)
+    N = n[0]
+    grids = np.meshgrid(*[signed_freq(N).astype(np.float64) for _ in n], indexing="ij")
+    kmag = 2.0 * np.pi * np.sqrt(sum(g * g for g in grids)) / (N * h)
+    sel = b >= 0
+    nmodes = np.bincount(b[sel], minlength=nbins).astype(np.int64)
+    ksum = np.bincount(b[sel], weights=kmag[sel], minlength=nbins)
+    with np.errstate(invalid="ignore", divide="ignore"):
+        kmean = ksum / nmodes
+    return nmodes, kmean
+
+
+def contrast_from_counts(counts, ntot=None, mask=None):
+    """delta_g = (N/f - N^)/N^ on f != 0, zero elsewhere; N^ = N_tot / sum f (eq. Estim)."""
+    counts = np.asarray(counts, dtype=np.float64)
+    f = np.ones_like(counts) if mask is None else np.asarray(mask, dtype=np.float64)
+    tot = counts.sum() if ntot is None else float(ntot)
+    nhat = tot / f.sum()
+    out = np.zeros_like(counts)
+    on = f != 0
+    out[on] = (counts[on] / f[on] - nhat) / nhat
+    return out
+
+
+def power_spectrum(phi, h, nbins):
+    """P^_b = (h^d / N^d) mean_{q in b} |F(q)|^2 for one map phi (eq. Def spec)."""
+    phi = np.asarray(phi, dtype=np.float64)
+    n = phi.shape
+    F = np.fft.fftn(phi)
+    p2 = (F.real ** 2 + F.imag ** 2)
+    b = shell_index(n, nbins)
+    sel = b >= 0
+    nmodes = np.bincount(b[sel], minlength=nbins)
+    sums = np.bincount(b[sel], weights=p2[sel], minlength=nbins)
+    with np.errstate(invalid="ignore", divide="ignore"):
+        mean = sums / nmodes
+    return (h ** phi.ndim / float(np.prod(n))) * mean
+
+
+def estimate_pk(maps, h, nbins, kind="field", ntot=None, mask=None):
+    """Spectra of a stack of maps (count, *N).  kind: 'field' or 'counts'."""
+    maps = np.asarray(maps)
+    out = np.empty((maps.shape[0], nbins), dtype=np.float64)
+    for k in range(maps.shape[0]):
+        if kind == "counts":
+            phi = contrast_from_counts(maps[k], None if ntot is None else ntot[k], mask)
+        else:
+            phi = maps[k]
+        out[k] = power_spectrum(phi, h, nbins)
+    return out
+
+
+def covariance(pk):
+    """(Cov with 1/(R-1), paper-normalised C with 1/R means) of spectra pk (R, nb)."""
+    pk = np.asarray(pk, dtype=np.float64)
+    R = pk.shape[0]
+    mean = pk.sum(axis=0) / R
+    d = pk - mean
+    cov = (d.T @ d) / (R - 1)
+    second = (pk.T @ pk) / R
+    cpaper = second / np.outer(mean, mean) - 1.0
+    return cov, cpaper

@@ -1,0 +1,106 @@
+"""Pins for the oracle's spectrum estimator, shells and covariance (CPU only)."""
+
+import itertools
+import math
+
+import numpy as np
+import pytest
+
+from oracle import embedding, fields, pk
+
+
+def brute_shell(q, N, nbins):
+    """Smallest s >= 0 with s^2 N^2 >= 4 nb^2 |q~|^2, by counting up in Python integers."""
+    qt = [x if x <= N // 2 else x - N for x in q]
+    t = 4 * nbins * nbins * sum(x * x for x in qt)
+    s = 0
+    while s * s * N * N < t:
+        s += 1
+    b = s - 1
+    return b if 0 <= b < nbins else -1
+
+
+@pytest.mark.parametrize("N,d,nbins", [(16, 2, 8), (12, 2, 5), (8, 3, 4), (10, 1, 3)])
+def test_shells_match_integer_enumeration(N, d, nbins):
+    b = pk.shell_index((N,) * d, nbins)
+    for q in itertools.product(range(N), repeat=d):
+        assert b[q] == brute_shell(q, N, nbins), q
+
+
+def test_shell_edges_follow_pixel_scale():
+    """Outer edge of the last shell is k_Ny = pi / h, the pixel scale pi N / L of Sec. 3.3."""
+    import json
+    import os
+    gold = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "paper_values.json")))
+    N = gold["survey_cells_per_side"]["value"]
+    L = math.radians(gold["survey_side_deg"]["value"])
+    h = L / N
+    nmodes, kmean = pk.shell_stats((N, N), h, 20)
+    kny = math.pi * N / L
+    assert abs(kny - 3088) < 1          # pixel scale of the 128^2 W1 map
+    assert kmean[-1] <= kny and kmean[-1] > kny * 0.9
+    # the axis Nyquist mode (|q~| = N/2) lies in the last shell
+    assert pk.shell_index((N, N), 20)[N // 2, 0] == 19
+
+
+def test_plane_wave_closed_form():
+    N, nb, h = 16, 8, 0.5
+    q0 = (3, 1)
+    x = np.arange(N)
+    phi = np.cos(2 * np.pi * (q0[0] * x[:, None] + q0[1] * x[None, :]) / N)
+    P = pk.power_spectrum(phi, h, nb)
+    b = pk.shell_index((N, N), nb)
+    nmodes, _ = pk.shell_stats((N, N), h, nb)
+    expect = np.zeros(nb)
+    bb = b[q0]
+    expect[bb] = (h ** 2 / N ** 2) * 2 * (N * N / 2) ** 2 / nmodes[bb]
+    assert np.allclose(P, expect, atol=1e-12)
+
+
+def test_white_noise_level():
+    rng = np.random.default_rng(0)
+    N, nb, h, s2 = 64, 16, 2.0, 0.7
+    maps = rng.normal(0, math.sqrt(s2), (200, N, N))
+    P = pk.estimate_pk(maps, h, nb).mean(axis=0)
+    assert np.all(np.abs(P / (s2 * h * h) - 1) < 0.05)
+
+
+def test_expected_survey_power_closed_form():
+    """<|F(q)|^2> = sum_d prod(N - |d_i|) xi(d) exp(-2 pi i q.d / N) for the exact Gaussian field."""
+    N, nb = 12, 6
+    xi = dict(kind="exp", sigma2=1.0, a=2.0)
+    plan = embedding.plan((N, N), (1.0, 1.0), xi)
+    R = 3000
+    g = fields.generate_fields(plan, seed=2, request_id=0, first_realization=0, count=R)
+    Pm = pk.estimate_pk(g, 1.0, nb)
+    # closed form per mode
+    d = np.arange(-N + 1, N)
+    w = (N - np.abs(d))[:, None] * (N - np.abs(d))[None, :]
+    r = np.hypot(d[:, None], d[None, :])
+    K = w * np.exp(-r / 2.0)
+    q = np.arange(N)
+    E = np.exp(-2j * np.pi * np.outer(q, d) / N)
+    F2 = (E @ K @ E.T).real
+    b = pk.shell_index((N, N), nb)
+    nmodes = np.bincount(b[b >= 0], minlength=nb)
+    expect = np.bincount(b[b >= 0], weights=F2[b >= 0], minlength=nb) / nmodes / N ** 2
+    se = Pm.std(axis=0) / math.sqrt(R)
+    assert np.all(np.abs(Pm.mean(axis=0) - expect) < 5 * se)
+
+
+def test_contrast_from_counts_hand_example():
+    c = np.array([[2, 0], [4, 2]])
+    assert np.array_equal(pk.contrast_from_counts(c), np.array([[0.0, -1.0], [1.0, 0.0]]))
+    f = np.array([[1.0, 0.0], [0.5, 1.0]])
+    # N^ = 8 / 2.5 = 3.2; masked cell -> 0
+    out = pk.contrast_from_counts(c, mask=f)
+    assert np.allclose(out, [[(2 - 3.2) / 3.2, 0.0], [(8 - 3.2) / 3.2, (2 - 3.2) / 3.2]])
+
+
+def test_covariance_matches_numpy_and_paper_form():
+    rng = np.random.default_rng(4)
+    P = rng.gamma(5.0, 1.0, (300, 7))
+    cov, cp = pk.covariance(P)
+    assert np.allclose(cov, np.cov(P, rowvar=False), rtol=1e-13, atol=1e-14)
+    m = P.mean(axis=0)
+    assert np.allclose(cp, np.mean(P[:, :, None] * P[:, None, :], axis=0) / np.outer(m, m) - 1, rtol=1e-12)
