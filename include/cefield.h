@@ -1,0 +1,214 @@
+/*
+ * cefield.h -- C ABI of the MI355X (gfx950) circulant-embedding Gaussian field
+ * generator.
+ *
+ * Method: Carron, Wolk & Szapudi (2014), "On fast generation of cosmological
+ * random fields", arXiv:1406.6072.  A survey grid of N_i cells per axis is
+ * embedded in a periodic grid of M_i = 2 N_i cells; the DFT of the two-point
+ * function on that grid gives the circulant eigenvalues; seeded complex white
+ * noise scaled by their square root and inverse-transformed gives two exact,
+ * independent Gaussian realizations (real and imaginary parts) on the survey
+ * cells; these are exponentiated (lognormal) and Poisson sampled, and the
+ * binned power spectrum and its covariance are estimated from them.
+ *
+ * Conventions for every entry point:
+ *  - All functions are C, never throw, and return a ce_status.  Argument
+ *    errors are detected on the host before anything is enqueued.
+ *  - Device pointers are plain HIP device addresses owned by the caller (for
+ *    example PyTorch tensors); host pointers are marked "host".  Outputs are
+ *    written, never accumulated into, unless stated.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the null stream).  All
+ *    device work is enqueued asynchronously on it; the caller synchronises.
+ *  - A ce_ctx owns scratch memory.  Calls on one ctx must not overlap in time
+ *    (use one ctx per stream / thread, or serialise).
+ *  - Layouts are row-major with the last axis fastest.  A stack of `count`
+ *    maps is count x N_0 x ... x N_{d-1}.  Realization r = 2j + s comes from
+ *    pair j: s = 0 is the real part, s = 1 the imaginary part.
+ *  - Supported: d = 2 or 3, every N_i even and >= 4, M_i a product of the
+ *    primes 2, 3, 5, 7, 11, 13, 17, 19, 23, 29, 31 and at most 4096, each
+ *    embedding with fewer than 2^32 cells.  Other sizes return
+ *    CE_E_UNSUPPORTED.
+ */
+#ifndef CEFIELD_H
+#define CEFIELD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  CE_OK = 0,
+  CE_E_INVALID = 1,      /* bad argument (null pointer, bad size, odd first realization, ...) */
+  CE_E_NOT_PSD = 2,      /* embedding spectrum negative beyond round-off: the method does not apply */
+  CE_E_OOM = 3,          /* device allocation failed or exceeds the ctx HBM budget */
+  CE_E_UNSUPPORTED = 4,  /* geometry or option not implemented (see the limits above) */
+  CE_E_DEVICE = 5,       /* HIP runtime error */
+  CE_E_SAMPLER = 6       /* a device-side sampler/estimator condition was flagged (see ce_ctx_check) */
+} ce_status;
+
+typedef enum { CE_F32 = 0, CE_F64 = 1 } ce_precision;
+
+typedef enum {
+  CE_XI_TABLE = 0,   /* table on the lag octant, see ce_xi.table */
+  CE_XI_EXP = 1,     /* p[0] exp(-r / p[1]) */
+  CE_XI_POWEXP = 2   /* p[0] (1 + r/p[1])^(-p[2]) exp(-r/p[3]); p[3] <= 0 means no cut-off */
+} ce_xi_kind;
+
+/* Survey grid: ndim axes of n[i] cells of side h[i] (the grid of Sec. 2, x = h i, i = 0..N-1). */
+typedef struct {
+  int32_t ndim;
+  int64_t n[3];
+  double h[3];
+} ce_geometry;
+
+/* Two-point function xi of the Gaussian field (isotropic kinds use r = |x| in units of h).
+ * CE_XI_TABLE: host FP64 array of xi at lags (l_0 h_0, ..., l_{d-1} h_{d-1}) for
+ * l_i in [0, N_i], row-major, shape (N_0+1) x ... ; it must describe a function that is
+ * even in every axis.  The table is copied during ce_plan_embedding. */
+typedef struct {
+  int32_t kind;
+  double p[4];
+  const double* table;
+} ce_xi;
+
+typedef struct {
+  double lambda_min;     /* smallest circulant eigenvalue before clamping (DFT of the lag table) */
+  double lambda_max;     /* largest */
+  double sigma2;         /* xi(0): variance of each cell */
+  int64_t n_negative;    /* eigenvalues below zero (full embedding grid, before clamping) */
+  int64_t n_clamped;     /* eigenvalues set to zero (= n_negative when the plan is accepted) */
+  size_t device_bytes;   /* device memory held by the plan */
+} ce_plan_info;
+
+typedef struct ce_ctx ce_ctx;
+typedef struct ce_plan ce_plan;
+
+/* Map kinds for ce_estimate_pk. */
+typedef enum {
+  CE_MAP_FIELD = 0,        /* real maps in the given precision; the spectrum of the map itself */
+  CE_MAP_COUNTS_DELTAG = 1 /* int32 counts; the spectrum of delta_g = (N/f - N^)/N^ (Sec. 3.2) */
+} ce_map_kind;
+
+const char* ce_status_string(ce_status s);
+
+/* Library version string (static storage). */
+const char* ce_version(void);
+
+/* Create a context on HIP device `device`.  hbm_budget_bytes bounds the scratch and
+ * plan memory the ctx may hold (0 = no bound).  Errors: CE_E_INVALID, CE_E_DEVICE. */
+ce_status ce_ctx_create(int device, size_t hbm_budget_bytes, ce_ctx** out);
+void ce_ctx_destroy(ce_ctx* ctx);
+
+/* Synchronise the ctx's last stream and report device-side flags: CE_E_SAMPLER if a Poisson
+ * draw exceeded its step bound or a counts map had N_tot = 0 since the last check. */
+ce_status ce_ctx_check(ce_ctx* ctx, void* stream);
+
+/* Embedding plan (Sec. 2, eqs. grid and Specd; condition).
+ * Builds the lag table c(m) = xi(h lag(m)) on the (2N)^d periodic grid (lag index N stands for
+ * -N, the minimum image), takes its FP64 DFT on the device (the circulant eigenvalues lambda,
+ * P~ = h^d lambda), and checks lambda >= 0 (eq. condition).  If lambda_min < -neg_tol *
+ * lambda_max the plan is rejected with CE_E_NOT_PSD and *out is left NULL; otherwise negative
+ * values are clamped to 0.  neg_tol < 0 selects the default 1e-13.  The plan keeps
+ * sqrt(lambda / M^d) on the eigenvalue octant in `precision` on the device; `info` (nullable)
+ * is filled in both cases.  Synchronous.  Errors: CE_E_INVALID, CE_E_UNSUPPORTED, CE_E_OOM,
+ * CE_E_NOT_PSD, CE_E_DEVICE. */
+ce_status ce_plan_embedding(ce_ctx* ctx, const ce_geometry* geom, const ce_xi* xi,
+                            ce_precision precision, double neg_tol, ce_plan** out,
+                            ce_plan_info* info);
+void ce_plan_release(ce_plan* plan);
+ce_status ce_plan_get_info(const ce_plan* plan, ce_plan_info* info);
+
+/* Copy the FP64 eigenvalue octant lambda(q), q_i in [0, N_i] (before clamping), row-major
+ * (N_0+1) x ..., into device buffer out (caller owns, (N_0+1)...(N_{d-1}+1) doubles). */
+ce_status ce_plan_eigenvalues(const ce_plan* plan, double* out, void* stream);
+
+/* Gaussian realizations (Sec. 2, eq. Papos2 and the discrete construction after eq. Specd).
+ * For pair j the modes are X(q) = sqrt(M^d lambda(q)) (a + i b), a, b iid N(0,1) from
+ * Philox4x32-10 (key = seed, counter (floor(l/2), j, request_id, 0), l the row-major embedding
+ * cell index; words x0,x1 -> cell 2p, x2,x3 -> cell 2p+1; Box-Muller), Z = M^-d sum_q X(q)
+ * exp(+2 pi i q.m/M) restricted to m_i in [0, N_i); realization 2j = Re Z, 2j+1 = Im Z.
+ * Writes realizations first_realization .. +count-1 (first_realization even) to out_fields:
+ * count x N^d elements of float (CE_F32 plan) or double (CE_F64 plan).
+ * Errors: CE_E_INVALID, CE_E_OOM, CE_E_DEVICE. */
+ce_status ce_generate_fields(ce_ctx* ctx, const ce_plan* plan, uint64_t seed, uint32_t request_id,
+                             uint64_t first_realization, int64_t count, void* out_fields,
+                             void* stream);
+
+/* Lognormal density and Poisson counts (Sec. 3.1, step i and eq. sampling).
+ * For each cell: delta = exp(g - sigma2/2) - 1 in the plan precision (sigma2 = xi(0));
+ * mu = (nbar f) (1 + delta) in FP64 from delta as stored; count ~ Poisson(mu) by FP64 chunked
+ * inversion (chunks of mean 64; chunk c of survey cell l in realization r uses the 52-bit
+ * uniform from Philox4x32-10 with key = seed and counter (l, floor(r/2), request_id, 1 + c),
+ * words x0,x1 for even r and x2,x3 for odd r).  fields: count x N^d (plan precision).
+ * mask_f (nullable; f = 1 when NULL): N^d floats in [0, 1].  out_delta (nullable): like fields.
+ * out_counts: count x N^d int32.  out_ntot (nullable): count int64 totals.
+ * first_realization must equal the realization index of fields[0] (it selects the streams).
+ * Errors: CE_E_INVALID, CE_E_DEVICE. */
+ce_status ce_lognormal_poisson(ce_ctx* ctx, const ce_plan* plan, const void* fields, int64_t count,
+                               double nbar, const float* mask_f, uint64_t seed,
+                               uint32_t request_id, uint64_t first_realization, void* out_delta,
+                               int32_t* out_counts, int64_t* out_ntot, void* stream);
+
+/* Binned power spectrum (Sec. 3.2, eq. Def spec with the contrast of eq. Estim).
+ * P_b = (h^d / N^d) (1/N_b) sum_{q in b} |F(q)|^2, F the DFT of the map (CE_MAP_FIELD) or of
+ * delta_g = (N/f - N^)/N^ on f != 0 and 0 elsewhere, N^ = N_tot / sum f (CE_MAP_COUNTS_DELTAG;
+ * ntot nullable -> computed; mask_f nullable -> f = 1).  Shells are linear in |k| on
+ * (0, pi/h]: mode q (signed frequencies q~) is in shell b when b < nbins 2|q~|/N <= b+1
+ * (decided exactly in integers; cubic grids with equal h only).  maps: count x N^d of float /
+ * double (FIELD, per `precision`) or int32 (COUNTS).  out_pk: count x nbins doubles (device).
+ * out_nmodes (nullable, device, nbins int64), out_kmean (nullable, device, nbins doubles: the
+ * mean |k| = 2 pi |q~| / (N h) of each shell).  Bin sums are accumulated in FP64 in a fixed
+ * order (bitwise reproducible).  Errors: CE_E_INVALID, CE_E_UNSUPPORTED, CE_E_DEVICE. */
+ce_status ce_estimate_pk(ce_ctx* ctx, const ce_geometry* geom, ce_precision precision,
+                         ce_map_kind kind, const void* maps, int64_t count, const int64_t* ntot,
+                         const float* mask_f, int32_t nbins, double* out_pk, int64_t* out_nmodes,
+                         double* out_kmean, void* stream);
+
+/* Spectrum covariance across realizations (Sec. 3.2: covariance from many simulations; the
+ * normalised matrix of eq. cuminfo).  pk: count x nbins doubles (device).  out_cov (nullable):
+ * nbins^2, Cov_ab = 1/(count-1) sum_r (P_ra - mean_a)(P_rb - mean_b).  out_cnorm (nullable):
+ * nbins^2, C_ab = (1/count) sum_r P_ra P_rb / (mean_a mean_b) - 1.  FP64, fixed order.
+ * Errors: CE_E_INVALID (count < 2), CE_E_DEVICE. */
+ce_status ce_pk_covariance(ce_ctx* ctx, const double* pk, int64_t count, int32_t nbins,
+                           double* out_cov, double* out_cnorm, void* stream);
+
+/* The whole hot path fused: generate `count` realizations (as ce_generate_fields), lognormal +
+ * Poisson counts (as ce_lognormal_poisson, f = 1, the same seed for fields and counts), the
+ * counts spectrum (as ce_estimate_pk with CE_MAP_COUNTS_DELTAG) and, when out_cov or out_cnorm
+ * is given and count >= 2, its covariance.  The noise is generated inside the first FFT pass,
+ * the crop / lognormal / Poisson / first forward transform run in the epilogue of the last
+ * inverse pass, and the shell sums in the epilogue of the last forward pass.  Every output
+ * pointer except out_pk is nullable; results equal the unfused calls within the stated
+ * tolerances (counts and N_tot exactly).  Errors: as the unfused calls. */
+ce_status ce_pipeline_run(ce_ctx* ctx, const ce_plan* plan, uint64_t seed, uint32_t request_id,
+                          uint64_t first_realization, int64_t count, double nbar, int32_t nbins,
+                          void* out_fields, void* out_delta, int32_t* out_counts,
+                          int64_t* out_ntot, double* out_pk, double* out_cov, double* out_cnorm,
+                          void* stream);
+
+/* Shell table of a cubic grid on the host: N_b and mean |k| per shell (same rule as
+ * ce_estimate_pk).  nmodes, kmean: host arrays of nbins.  Errors: CE_E_INVALID, CE_E_UNSUPPORTED. */
+ce_status ce_shell_table(const ce_geometry* geom, int32_t nbins, int64_t* nmodes, double* kmean);
+
+/* FFT factorisation chosen for a line length (host; for inspection).  Writes up to 16 radices
+ * into radices (host) and their number into *nstages.  CE_E_UNSUPPORTED if L is not covered. */
+ce_status ce_fft_factors(int32_t length, int32_t* radices, int32_t* nstages);
+
+/* Debug / test: Philox4x32-10 words for counters (ctr[0] + i, ctr[1], ctr[2], ctr[3]),
+ * i in [0, n_calls), key = seed; out_words: device, 4 n_calls uint32 (x0..x3 per call). */
+ce_status ce_debug_philox(uint64_t seed, const uint32_t ctr[4], int64_t n_calls,
+                          uint32_t* out_words, void* stream);
+
+/* Debug / test: the complex normals eps(q) of one pair (before scaling), M^d complex values
+ * (interleaved re, im) in the plan precision, row-major over the embedding grid. */
+ce_status ce_debug_noise(const ce_plan* plan, uint64_t seed, uint32_t request_id, uint64_t pair,
+                         void* out, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CEFIELD_H */

@@ -1,0 +1,327 @@
+"""Thin ctypes binding of the C ABI in include/cefield.h.
+
+Argument marshalling only: every step of the generator runs in the HIP
+library.  Device buffers are torch CUDA tensors (their data_ptr is passed);
+streams default to torch's current stream.  Sizes and dtypes of the tensors
+are checked here so the library never receives an undersized buffer.  If the
+shared library has not been built, importing fails loudly: there is no CPU
+fallback.
+"""
+
+import ctypes
+import os
+
+import torch  # noqa: F401  (loads the HIP runtime the library links against)
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libcefield.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError("libcefield.so is not built; run __graft_entry__.build() (hipcc for gfx950)")
+
+_lib = ctypes.CDLL(LIB_PATH)
+
+OK, E_INVALID, E_NOT_PSD, E_OOM, E_UNSUPPORTED, E_DEVICE, E_SAMPLER = range(7)
+F32, F64 = 0, 1
+XI_TABLE, XI_EXP, XI_POWEXP = 0, 1, 2
+MAP_FIELD, MAP_COUNTS_DELTAG = 0, 1
+
+c_void_p = ctypes.c_void_p
+c_i32, c_i64, c_u32, c_u64, c_f64, c_size = (ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32,
+                                              ctypes.c_uint64, ctypes.c_double, ctypes.c_size_t)
+
+
+class Geometry(ctypes.Structure):
+    _fields_ = [("ndim", c_i32), ("n", c_i64 * 3), ("h", c_f64 * 3)]
+
+
+class Xi(ctypes.Structure):
+    _fields_ = [("kind", c_i32), ("p", c_f64 * 4), ("table", ctypes.POINTER(c_f64))]
+
+
+class PlanInfo(ctypes.Structure):
+    _fields_ = [("lambda_min", c_f64), ("lambda_max", c_f64), ("sigma2", c_f64),
+                ("n_negative", c_i64), ("n_clamped", c_i64), ("device_bytes", c_size)]
+
+
+def _sig(name, res, *args):
+    f = getattr(_lib, name)
+    f.restype = res
+    f.argtypes = list(args)
+    return f
+
+
+_status_string = _sig("ce_status_string", ctypes.c_char_p, c_i32)
+_version = _sig("ce_version", ctypes.c_char_p)
+_ctx_create = _sig("ce_ctx_create", c_i32, c_i32, c_size, ctypes.POINTER(c_void_p))
+_ctx_destroy = _sig("ce_ctx_destroy", None, c_void_p)
+_ctx_check = _sig("ce_ctx_check", c_i32, c_void_p, c_void_p)
+_plan_embedding = _sig("ce_plan_embedding", c_i32, c_void_p, ctypes.POINTER(Geometry), ctypes.POINTER(Xi), c_i32,
+                       c_f64, ctypes.POINTER(c_void_p), ctypes.POINTER(PlanInfo))
+_plan_release = _sig("ce_plan_release", None, c_void_p)
+_plan_get_info = _sig("ce_plan_get_info", c_i32, c_void_p, ctypes.POINTER(PlanInfo))
+_plan_eigenvalues = _sig("ce_plan_eigenvalues", c_i32, c_void_p, c_void_p, c_void_p)
+_generate_fields = _sig("ce_generate_fields", c_i32, c_void_p, c_void_p, c_u64, c_u32, c_u64, c_i64, c_void_p,
+                        c_void_p)
+_lognormal_poisson = _sig("ce_lognormal_poisson", c_i32, c_void_p, c_void_p, c_void_p, c_i64, c_f64, c_void_p, c_u64,
+                          c_u32, c_u64, c_void_p, c_void_p, c_void_p, c_void_p)
+_estimate_pk = _sig("ce_estimate_pk", c_i32, c_void_p, ctypes.POINTER(Geometry), c_i32, c_i32, c_void_p, c_i64,
+                    c_void_p, c_void_p, c_i32, c_void_p, c_void_p, c_void_p, c_void_p)
+_pk_covariance = _sig("ce_pk_covariance", c_i32, c_void_p, c_void_p, c_i64, c_i32, c_void_p, c_void_p, c_void_p)
+_pipeline_run = _sig("ce_pipeline_run", c_i32, c_void_p, c_void_p, c_u64, c_u32, c_u64, c_i64, c_f64, c_i32,
+                     c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p)
+_shell_table = _sig("ce_shell_table", c_i32, ctypes.POINTER(Geometry), c_i32, c_void_p, c_void_p)
+_fft_factors = _sig("ce_fft_factors", c_i32, c_i32, c_void_p, c_void_p)
+_debug_philox = _sig("ce_debug_philox", c_i32, c_u64, c_void_p, c_i64, c_void_p, c_void_p)
+_debug_noise = _sig("ce_debug_noise", c_i32, c_void_p, c_u64, c_u32, c_u64, c_void_p, c_void_p)
+
+EXPORTED = ["ce_status_string", "ce_version", "ce_ctx_create", "ce_ctx_destroy", "ce_ctx_check",
+            "ce_plan_embedding", "ce_plan_release", "ce_plan_get_info", "ce_plan_eigenvalues",
+            "ce_generate_fields", "ce_lognormal_poisson", "ce_estimate_pk", "ce_pk_covariance",
+            "ce_pipeline_run", "ce_shell_table", "ce_fft_factors", "ce_debug_philox", "ce_debug_noise"]
+
+
+class CeError(RuntimeError):
+    def __init__(self, status, where):
+        super().__init__("%s: %s (status %d)" % (where, status_string(status), status))
+        self.status = status
+
+
+class NotPSDError(CeError):
+    def __init__(self, status, where, info):
+        super().__init__(status, where)
+        self.info = info
+
+
+def status_string(s):
+    return _status_string(int(s)).decode()
+
+
+def version():
+    return _version().decode()
+
+
+def _check(st, where):
+    if st != OK:
+        raise CeError(st, where)
+
+
+def _stream(stream):
+    if stream is None:
+        return c_void_p(torch.cuda.current_stream().cuda_stream)
+    if isinstance(stream, torch.cuda.Stream):
+        return c_void_p(stream.cuda_stream)
+    return c_void_p(int(stream))
+
+
+def _ptr(t, dtype=None, numel=None, name="buffer"):
+    """data_ptr of a CUDA tensor after dtype / contiguity / size checks (None -> NULL)."""
+    if t is None:
+        return None
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError("%s must be a CUDA tensor" % name)
+    if not t.is_contiguous():
+        raise ValueError("%s must be contiguous" % name)
+    if dtype is not None and t.dtype != dtype:
+        raise TypeError("%s must have dtype %s, got %s" % (name, dtype, t.dtype))
+    if numel is not None and t.numel() < numel:
+        raise ValueError("%s holds %d elements, needs %d" % (name, t.numel(), numel))
+    return c_void_p(t.data_ptr())
+
+
+def geometry(n, h=None):
+    n = tuple(int(x) for x in n)
+    h = tuple(float(x) for x in (h if h is not None else (1.0,) * len(n)))
+    g = Geometry()
+    g.ndim = len(n)
+    for i in range(3):
+        g.n[i] = n[i] if i < len(n) else 1
+        g.h[i] = h[i] if i < len(h) else 1.0
+    return g
+
+
+def xi_spec(xi):
+    """ctypes Xi from the dict form used by the tests ({'kind': 'exp'|'powexp'|'table', ...})."""
+    x = Xi()
+    kind = xi["kind"]
+    keep = None
+    if kind == "exp":
+        x.kind = XI_EXP
+        x.p[0], x.p[1] = float(xi["sigma2"]), float(xi["a"])
+    elif kind == "powexp":
+        x.kind = XI_POWEXP
+        x.p[0], x.p[1] = float(xi["sigma2"]), float(xi["r0"])
+        x.p[2], x.p[3] = float(xi.get("gamma", 1.8)), float(xi.get("rc", 0.0))
+    elif kind == "table":
+        import numpy as np
+        keep = np.ascontiguousarray(xi["table"], dtype=np.float64)
+        x.kind = XI_TABLE
+        x.table = keep.ctypes.data_as(ctypes.POINTER(c_f64))
+    else:
+        raise ValueError("unknown xi kind %r" % kind)
+    return x, keep
+
+
+def _info_dict(pi):
+    return dict(lambda_min=pi.lambda_min, lambda_max=pi.lambda_max, sigma2=pi.sigma2,
+                n_negative=pi.n_negative, n_clamped=pi.n_clamped, device_bytes=pi.device_bytes)
+
+
+# ---- entry points (same names as the C ABI, without the ce_ prefix) ----------
+
+def ctx_create(device=0, hbm_budget_bytes=0):
+    h = c_void_p()
+    _check(_ctx_create(int(device), int(hbm_budget_bytes), ctypes.byref(h)), "ce_ctx_create")
+    return h
+
+
+def ctx_destroy(ctx):
+    _ctx_destroy(ctx)
+
+
+def ctx_check(ctx, stream=None):
+    return _ctx_check(ctx, None if stream is None else _stream(stream))
+
+
+class Plan:
+    """Owning handle of a ce_plan with the geometry it was built for."""
+
+    def __init__(self, handle, n, h, precision, info):
+        self.handle, self.n, self.h, self.precision, self.info = handle, tuple(n), tuple(h), precision, info
+
+    @property
+    def cells(self):
+        c = 1
+        for x in self.n:
+            c *= x
+        return c
+
+    @property
+    def embedding_cells(self):
+        return self.cells * 2 ** len(self.n)
+
+    @property
+    def dtype(self):
+        return torch.float64 if self.precision == F64 else torch.float32
+
+    def release(self):
+        if self.handle:
+            _plan_release(self.handle)
+            self.handle = None
+
+
+def plan_embedding(ctx, n, h, xi, precision, neg_tol=-1.0):
+    g = geometry(n, h)
+    x, keep = xi_spec(xi)
+    out = c_void_p()
+    pi = PlanInfo()
+    st = _plan_embedding(ctx, ctypes.byref(g), ctypes.byref(x), int(precision), float(neg_tol), ctypes.byref(out),
+                         ctypes.byref(pi))
+    del keep
+    if st == E_NOT_PSD:
+        raise NotPSDError(st, "ce_plan_embedding", _info_dict(pi))
+    _check(st, "ce_plan_embedding")
+    return Plan(out, g.n[:g.ndim], g.h[:g.ndim], int(precision), _info_dict(pi))
+
+
+def plan_release(plan):
+    plan.release()
+
+
+def plan_get_info(plan):
+    pi = PlanInfo()
+    _check(_plan_get_info(plan.handle, ctypes.byref(pi)), "ce_plan_get_info")
+    return _info_dict(pi)
+
+
+def plan_eigenvalues(plan, out, stream=None):
+    noct = 1
+    for x in plan.n:
+        noct *= x + 1
+    _check(_plan_eigenvalues(plan.handle, _ptr(out, torch.float64, noct, "out"), _stream(stream)),
+           "ce_plan_eigenvalues")
+
+
+def generate_fields(ctx, plan, seed, request_id, first_realization, count, out_fields, stream=None):
+    _check(_generate_fields(ctx, plan.handle, int(seed), int(request_id), int(first_realization), int(count),
+                            _ptr(out_fields, plan.dtype, count * plan.cells, "out_fields"), _stream(stream)),
+           "ce_generate_fields")
+
+
+def lognormal_poisson(ctx, plan, fields, count, nbar, mask_f, seed, request_id, first_realization,
+                      out_delta, out_counts, out_ntot, stream=None):
+    cells = plan.cells
+    _check(_lognormal_poisson(ctx, plan.handle, _ptr(fields, plan.dtype, count * cells, "fields"), int(count),
+                              float(nbar), _ptr(mask_f, torch.float32, cells, "mask_f"), int(seed), int(request_id),
+                              int(first_realization), _ptr(out_delta, plan.dtype, count * cells, "out_delta"),
+                              _ptr(out_counts, torch.int32, count * cells, "out_counts"),
+                              _ptr(out_ntot, torch.int64, count, "out_ntot"), _stream(stream)),
+           "ce_lognormal_poisson")
+
+
+def estimate_pk(ctx, n, h, precision, kind, maps, count, ntot, mask_f, nbins, out_pk, out_nmodes=None,
+                out_kmean=None, stream=None):
+    g = geometry(n, h)
+    cells = 1
+    for x in n:
+        cells *= int(x)
+    mdt = torch.int32 if kind == MAP_COUNTS_DELTAG else (torch.float64 if precision == F64 else torch.float32)
+    _check(_estimate_pk(ctx, ctypes.byref(g), int(precision), int(kind), _ptr(maps, mdt, count * cells, "maps"),
+                        int(count), _ptr(ntot, torch.int64, count, "ntot"), _ptr(mask_f, torch.float32, cells, "mask"),
+                        int(nbins), _ptr(out_pk, torch.float64, count * nbins, "out_pk"),
+                        _ptr(out_nmodes, torch.int64, nbins, "out_nmodes"),
+                        _ptr(out_kmean, torch.float64, nbins, "out_kmean"), _stream(stream)),
+           "ce_estimate_pk")
+
+
+def pk_covariance(ctx, pk, count, nbins, out_cov, out_cnorm, stream=None):
+    _check(_pk_covariance(ctx, _ptr(pk, torch.float64, count * nbins, "pk"), int(count), int(nbins),
+                          _ptr(out_cov, torch.float64, nbins * nbins, "out_cov"),
+                          _ptr(out_cnorm, torch.float64, nbins * nbins, "out_cnorm"), _stream(stream)),
+           "ce_pk_covariance")
+
+
+def pipeline_run(ctx, plan, seed, request_id, first_realization, count, nbar, nbins, out_pk, out_fields=None,
+                 out_delta=None, out_counts=None, out_ntot=None, out_cov=None, out_cnorm=None, stream=None):
+    cells = plan.cells
+    _check(_pipeline_run(ctx, plan.handle, int(seed), int(request_id), int(first_realization), int(count),
+                         float(nbar), int(nbins), _ptr(out_fields, plan.dtype, count * cells, "out_fields"),
+                         _ptr(out_delta, plan.dtype, count * cells, "out_delta"),
+                         _ptr(out_counts, torch.int32, count * cells, "out_counts"),
+                         _ptr(out_ntot, torch.int64, count, "out_ntot"),
+                         _ptr(out_pk, torch.float64, count * nbins, "out_pk"),
+                         _ptr(out_cov, torch.float64, nbins * nbins, "out_cov"),
+                         _ptr(out_cnorm, torch.float64, nbins * nbins, "out_cnorm"), _stream(stream)),
+           "ce_pipeline_run")
+
+
+def shell_table(n, h, nbins):
+    import numpy as np
+    g = geometry(n, h)
+    nm = np.zeros(nbins, dtype=np.int64)
+    km = np.zeros(nbins, dtype=np.float64)
+    _check(_shell_table(ctypes.byref(g), int(nbins), nm.ctypes.data_as(c_void_p), km.ctypes.data_as(c_void_p)),
+           "ce_shell_table")
+    return nm, km
+
+
+def fft_factors(length):
+    import numpy as np
+    r = np.zeros(16, dtype=np.int32)
+    ns = c_i32()
+    _check(_fft_factors(int(length), r.ctypes.data_as(c_void_p), ctypes.byref(ns)), "ce_fft_factors")
+    return [int(x) for x in r[:ns.value]]
+
+
+def debug_philox(seed, ctr, n_calls, out_words, stream=None):
+    import numpy as np
+    c = np.ascontiguousarray(ctr, dtype=np.uint32)
+    _check(_debug_philox(int(seed), c.ctypes.data_as(c_void_p), int(n_calls),
+                         _ptr(out_words, torch.int32, 4 * n_calls, "out_words"), _stream(stream)),
+           "ce_debug_philox")
+
+
+def debug_noise(plan, seed, request_id, pair, out, stream=None):
+    _check(_debug_noise(plan.handle, int(seed), int(request_id), int(pair),
+                        _ptr(out, plan.dtype, 2 * plan.embedding_cells, "out"), _stream(stream)),
+           "ce_debug_noise")

@@ -1,0 +1,899 @@
+// Host side of the C ABI declared in include/cefield.h: contexts, embedding
+// plans, FFT factorisation, pass geometry, scratch memory and the entry points.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "../../include/cefield.h"
+#include "ce_internal.hpp"
+
+using namespace ce;
+
+namespace {
+
+constexpr double kDefaultNegTol = 1e-13;
+constexpr size_t kLdsBudget = 80 * 1024;   // per workgroup: two workgroups fit one CU
+constexpr int kMaxSide = 4096;
+constexpr int kPrimes[] = {3, 5, 7, 11, 13, 17, 19, 23, 29, 31};
+
+#define CE_HIP(expr)                                   \
+  do {                                                 \
+    hipError_t e_ = (expr);                            \
+    if (e_ != hipSuccess) return hip_status(e_);       \
+  } while (0)
+
+#define CE_TRY(expr)                                   \
+  do {                                                 \
+    ce_status s_ = (expr);                             \
+    if (s_ != CE_OK) return s_;                        \
+  } while (0)
+
+ce_status hip_status(hipError_t e) { return e == hipErrorOutOfMemory ? CE_E_OOM : CE_E_DEVICE; }
+
+// ---- FFT factorisation ------------------------------------------------------
+
+bool factor_length(int L, std::vector<int>& rad) {
+  rad.clear();
+  if (L < 2 || L > kMaxSide) return false;
+  int n = L;
+  std::vector<int> odd;
+  for (int p : kPrimes)
+    while (n % p == 0) {
+      odd.push_back(p);
+      n /= p;
+    }
+  if (n & (n - 1)) return false;
+  int e = 0;
+  while ((1 << e) < n) ++e;
+  std::vector<int> p2;
+  int n4 = e / 4, rem = e % 4;
+  if (rem == 1 && n4 >= 1) {
+    for (int i = 0; i < n4 - 1; ++i) p2.push_back(16);
+    p2.push_back(8);
+    p2.push_back(4);
+  } else if (rem == 2 && n4 >= 1) {
+    for (int i = 0; i < n4 - 1; ++i) p2.push_back(16);
+    p2.push_back(8);
+    p2.push_back(8);
+  } else {
+    for (int i = 0; i < n4; ++i) p2.push_back(16);
+    if (rem == 3) p2.push_back(8);
+    if (rem == 2) p2.push_back(4);
+    if (rem == 1) p2.push_back(2);
+  }
+  for (int p : odd) rad.push_back(p);
+  for (int p : p2) rad.push_back(p);
+  if (rad.size() > (size_t)kMaxStages) return false;
+  return !rad.empty();
+}
+
+int line_pitch_host(int L) { return L + (L >> 4) + 1; }
+
+// Lines of length L (FFT), K kept; A x B lines per item.  Chooses R (power of two,
+// lines per workgroup) within the LDS budget and the 1024-thread limit.
+bool mixed_radix(const FftDesc& f) {
+  for (int i = 0; i < f.nst; ++i)
+    if (f.rad[i] & (f.rad[i] - 1)) return true;
+  return false;
+}
+
+LineGeom make_geom(int L, int K, int64_t A, int64_t B, int64_t nitems, int64_t in_item, int64_t out_item,
+                   size_t elem, bool mix, int rmin, int rmax, size_t extra_per_line = 0) {
+  LineGeom g;
+  g.nbuf = mix ? 2 : 1;
+  g.L = L;
+  g.K = K;
+  g.A = A;
+  g.B = B;
+  g.nitems = nitems;
+  g.in_item = in_item;
+  g.out_item = out_item;
+  g.nlanes = (L + kEPT - 1) / kEPT;
+  g.lpitch = line_pitch_host(L);
+  const size_t per_line = (size_t)g.lpitch * elem * g.nbuf + extra_per_line;
+  int R = 1;
+  while (R * 2 <= rmax && (size_t)(R * 2) * per_line <= kLdsBudget && R * 2 * g.nlanes <= kMaxWG) R *= 2;
+  if (R < rmin) R = rmin;
+  g.R = R;
+  const int64_t nlines = A * B;
+  g.groups_per_item = (nlines + R - 1) / R;
+  return g;
+}
+
+// Twiddle tables: tw[k] = exp(-2 pi i k / L), FP64 accurate, stored in the pass precision.
+struct TwKey {
+  int L, prec;
+  bool operator<(const TwKey& o) const { return std::tie(L, prec) < std::tie(o.L, o.prec); }
+};
+
+}  // namespace
+
+// ---- context -----------------------------------------------------------------
+
+struct ce_ctx {
+  int device = 0;
+  size_t budget = 0;
+  size_t held = 0;  // bytes of scratch + twiddles + shell tables
+  hipStream_t own = nullptr;
+  hipStream_t last = nullptr;
+  uint32_t* flags = nullptr;
+  std::mutex mu;
+  std::map<TwKey, void*> tw;
+  std::map<std::tuple<int, int, int>, std::pair<int64_t*, std::vector<double>>> shells;
+  struct Buf {
+    void* p = nullptr;
+    size_t n = 0;
+  };
+  Buf ws[8];
+
+  ce_status alloc(void** p, size_t bytes) {
+    if (budget && held + bytes > budget) return CE_E_OOM;
+    hipError_t e = hipMalloc(p, bytes ? bytes : 1);
+    if (e != hipSuccess) return hip_status(e);
+    held += bytes;
+    return CE_OK;
+  }
+  void release(void* p, size_t bytes) {
+    if (p) {
+      (void)hipFree(p);
+      held -= bytes;
+    }
+  }
+  // scratch slot i with at least `bytes`
+  ce_status scratch(int i, size_t bytes, void** out) {
+    Buf& b = ws[i];
+    if (b.n < bytes) {
+      if (b.p) {
+        (void)hipDeviceSynchronize();
+        release(b.p, b.n);
+        b.p = nullptr;
+        b.n = 0;
+      }
+      void* p = nullptr;
+      CE_TRY(alloc(&p, bytes));
+      b.p = p;
+      b.n = bytes;
+    }
+    *out = b.p;
+    return CE_OK;
+  }
+  ce_status twiddles(int L, int prec, const void** out) {
+    auto it = tw.find({L, prec});
+    if (it != tw.end()) {
+      *out = it->second;
+      return CE_OK;
+    }
+    const size_t elem = prec ? 16 : 8;
+    std::vector<double> d(2 * (size_t)L);
+    for (int k = 0; k < L; ++k) {
+      // reduce the angle to the first octant for accuracy
+      const long double a = 2.0L * 3.14159265358979323846264338327950288L * (long double)k / (long double)L;
+      d[2 * k] = (double)std::cos(a);
+      d[2 * k + 1] = (double)-std::sin(a);
+    }
+    void* p = nullptr;
+    CE_TRY(alloc(&p, elem * L));
+    if (prec) {
+      CE_HIP(hipMemcpy(p, d.data(), elem * L, hipMemcpyHostToDevice));
+    } else {
+      std::vector<float> f(2 * (size_t)L);
+      for (size_t i = 0; i < f.size(); ++i) f[i] = (float)d[i];
+      CE_HIP(hipMemcpy(p, f.data(), elem * L, hipMemcpyHostToDevice));
+    }
+    tw[{L, prec}] = p;
+    *out = p;
+    return CE_OK;
+  }
+};
+
+struct ce_plan {
+  ce_ctx* ctx = nullptr;
+  int ndim = 0;
+  int n[3] = {1, 1, 1};
+  int M[3] = {1, 1, 1};
+  double h[3] = {1, 1, 1};
+  int prec = 0;
+  ce_plan_info info{};
+  double* lam = nullptr;  // FP64 eigenvalue octant (before clamping)
+  void* sq = nullptr;     // sqrt(lambda/M^d) octant in plan precision
+  int64_t noct = 0;
+  size_t bytes_lam = 0, bytes_sq = 0;
+};
+
+namespace {
+
+ce_status build_fft(ce_ctx* ctx, int L, int prec, FftDesc& f) {
+  std::vector<int> rad;
+  if (!factor_length(L, rad)) return CE_E_UNSUPPORTED;
+  f.L = L;
+  f.nst = (int)rad.size();
+  for (int i = 0; i < f.nst; ++i) f.rad[i] = rad[i];
+  return ctx->twiddles(L, prec, &f.tw);
+}
+
+ce_status check_geometry(const ce_geometry* g) {
+  if (!g) return CE_E_INVALID;
+  if (g->ndim < 2 || g->ndim > 3) return g->ndim == 1 ? CE_E_UNSUPPORTED : CE_E_INVALID;
+  double cells = 1;
+  for (int i = 0; i < g->ndim; ++i) {
+    if (g->n[i] < 4 || (g->n[i] & 1)) return g->n[i] < 1 ? CE_E_INVALID : CE_E_UNSUPPORTED;
+    if (!(g->h[i] > 0) || !std::isfinite(g->h[i])) return CE_E_INVALID;
+    if (2 * g->n[i] > kMaxSide) return CE_E_UNSUPPORTED;
+    std::vector<int> r;
+    if (!factor_length((int)(2 * g->n[i]), r) || !factor_length((int)g->n[i], r)) return CE_E_UNSUPPORTED;
+    cells *= 2.0 * (double)g->n[i];
+  }
+  if (cells >= 4294967296.0) return CE_E_UNSUPPORTED;
+  return CE_OK;
+}
+
+bool is_cubic(const ce_geometry* g) {
+  for (int i = 1; i < g->ndim; ++i)
+    if (g->n[i] != g->n[0] || g->h[i] != g->h[0]) return false;
+  return true;
+}
+
+// Shell table of a cubic grid: nmodes and mean |k| (host, exact integers).
+void shell_table_host(int N, int ndim, double h, int nb, std::vector<int64_t>& nm, std::vector<double>& km) {
+  nm.assign(nb, 0);
+  std::vector<double> ks(nb, 0.0);
+  const int64_t T = 4ll * nb * nb;
+  const int64_t NN = (int64_t)N * N;
+  const int n1 = ndim >= 2 ? N : 1, n2 = ndim >= 3 ? N : 1;
+  for (int a = 0; a < N; ++a) {
+    const int64_t qa = a <= N / 2 ? a : a - N;
+    for (int b = 0; b < n1; ++b) {
+      const int64_t qb = b <= N / 2 ? b : b - N;
+      for (int c = 0; c < n2; ++c) {
+        const int64_t qc = ndim >= 3 ? (c <= N / 2 ? c : c - N) : 0;
+        const int64_t q2 = qa * qa + qb * qb + qc * qc;
+        const int64_t t = T * q2;
+        // smallest s >= 0 with s^2 N^2 >= t
+        int64_t s = (int64_t)std::sqrt((double)t / (double)NN);
+        while (s > 0 && (s - 1) * (s - 1) * NN >= t) --s;
+        while (s * s * NN < t) ++s;
+        const int64_t bin = s - 1;
+        if (bin >= 0 && bin < nb) {
+          nm[bin] += 1;
+          ks[bin] += 2.0 * M_PI * std::sqrt((double)q2) / ((double)N * h);
+        }
+      }
+    }
+  }
+  km.assign(nb, 0.0);
+  for (int i = 0; i < nb; ++i) km[i] = nm[i] ? ks[i] / (double)nm[i] : NAN;
+}
+
+ce_status device_shells(ce_ctx* ctx, int N, int ndim, double h, int nb, int64_t** nm_dev,
+                        const std::vector<double>** km_host) {
+  auto key = std::make_tuple(N, ndim, nb);
+  auto it = ctx->shells.find(key);
+  if (it == ctx->shells.end()) {
+    std::vector<int64_t> nm;
+    std::vector<double> km;
+    shell_table_host(N, ndim, 1.0, nb, nm, km);
+    void* p = nullptr;
+    CE_TRY(ctx->alloc(&p, sizeof(int64_t) * nb));
+    CE_HIP(hipMemcpy(p, nm.data(), sizeof(int64_t) * nb, hipMemcpyHostToDevice));
+    it = ctx->shells.emplace(key, std::make_pair(static_cast<int64_t*>(p), km)).first;
+  }
+  *nm_dev = it->second.first;
+  *km_host = &it->second.second;
+  (void)h;
+  return CE_OK;
+}
+
+hipStream_t as_stream(void* s) { return static_cast<hipStream_t>(s); }
+
+}  // namespace
+
+// ---- entry points ---------------------------------------------------------------
+
+extern "C" {
+
+const char* ce_status_string(ce_status s) {
+  switch (s) {
+    case CE_OK: return "ok";
+    case CE_E_INVALID: return "invalid argument";
+    case CE_E_NOT_PSD: return "embedding spectrum is negative (the embedding is not positive semi-definite)";
+    case CE_E_OOM: return "out of device memory or over the context budget";
+    case CE_E_UNSUPPORTED: return "unsupported geometry or option";
+    case CE_E_DEVICE: return "HIP runtime error";
+    case CE_E_SAMPLER: return "device-side sampler or estimator condition flagged";
+  }
+  return "unknown status";
+}
+
+const char* ce_version(void) { return "cefield 0.1 (gfx950)"; }
+
+ce_status ce_ctx_create(int device, size_t hbm_budget_bytes, ce_ctx** out) {
+  if (!out) return CE_E_INVALID;
+  *out = nullptr;
+  int n = 0;
+  CE_HIP(hipGetDeviceCount(&n));
+  if (device < 0 || device >= n) return CE_E_INVALID;
+  CE_HIP(hipSetDevice(device));
+  auto ctx = std::make_unique<ce_ctx>();
+  ctx->device = device;
+  ctx->budget = hbm_budget_bytes;
+  CE_HIP(hipStreamCreate(&ctx->own));
+  void* f = nullptr;
+  CE_TRY(ctx->alloc(&f, 16));
+  ctx->flags = static_cast<uint32_t*>(f);
+  CE_HIP(hipMemset(ctx->flags, 0, 16));
+  *out = ctx.release();
+  return CE_OK;
+}
+
+void ce_ctx_destroy(ce_ctx* ctx) {
+  if (!ctx) return;
+  (void)hipSetDevice(ctx->device);
+  (void)hipDeviceSynchronize();
+  for (auto& b : ctx->ws)
+    if (b.p) (void)hipFree(b.p);
+  for (auto& kv : ctx->tw) (void)hipFree(kv.second);
+  for (auto& kv : ctx->shells) (void)hipFree(kv.second.first);
+  if (ctx->flags) (void)hipFree(ctx->flags);
+  if (ctx->own) (void)hipStreamDestroy(ctx->own);
+  delete ctx;
+}
+
+ce_status ce_ctx_check(ce_ctx* ctx, void* stream) {
+  if (!ctx) return CE_E_INVALID;
+  CE_HIP(hipSetDevice(ctx->device));
+  hipStream_t s = stream ? as_stream(stream) : ctx->last;
+  CE_HIP(hipStreamSynchronize(s));
+  uint32_t f = 0;
+  CE_HIP(hipMemcpy(&f, ctx->flags, sizeof(f), hipMemcpyDeviceToHost));
+  if (f) {
+    CE_HIP(hipMemset(ctx->flags, 0, sizeof(uint32_t)));
+    return CE_E_SAMPLER;
+  }
+  return CE_OK;
+}
+
+ce_status ce_plan_embedding(ce_ctx* ctx, const ce_geometry* geom, const ce_xi* xi, ce_precision precision,
+                            double neg_tol, ce_plan** out, ce_plan_info* info) {
+  if (!ctx || !geom || !xi || !out) return CE_E_INVALID;
+  *out = nullptr;
+  if (precision != CE_F32 && precision != CE_F64) return CE_E_INVALID;
+  CE_TRY(check_geometry(geom));
+  if (xi->kind == CE_XI_TABLE) {
+    if (!xi->table) return CE_E_INVALID;
+  } else if (xi->kind == CE_XI_EXP) {
+    if (!(xi->p[1] > 0)) return CE_E_INVALID;
+  } else if (xi->kind == CE_XI_POWEXP) {
+    if (!(xi->p[1] > 0)) return CE_E_INVALID;
+  } else {
+    return CE_E_INVALID;
+  }
+  if (neg_tol < 0) neg_tol = kDefaultNegTol;
+  std::lock_guard<std::mutex> lock(ctx->mu);
+  CE_HIP(hipSetDevice(ctx->device));
+  hipStream_t s = ctx->own;
+
+  auto plan = std::make_unique<ce_plan>();
+  plan->ctx = ctx;
+  plan->ndim = geom->ndim;
+  plan->prec = precision == CE_F64 ? 1 : 0;
+  int32_t O[3] = {1, 1, 1};
+  double h[3] = {1, 1, 1};
+  int64_t noct = 1;
+  for (int i = 0; i < geom->ndim; ++i) {
+    plan->n[i] = (int)geom->n[i];
+    plan->M[i] = 2 * (int)geom->n[i];
+    plan->h[i] = geom->h[i];
+    O[i] = plan->n[i] + 1;
+    h[i] = geom->h[i];
+    noct *= O[i];
+  }
+  plan->noct = noct;
+
+  double* bufA = nullptr;
+  double* bufB = nullptr;
+  plan->bytes_lam = sizeof(double) * noct;
+  CE_TRY(ctx->alloc((void**)&bufA, plan->bytes_lam));
+  ce_status st = ctx->alloc((void**)&bufB, plan->bytes_lam);
+  if (st != CE_OK) {
+    ctx->release(bufA, plan->bytes_lam);
+    return st;
+  }
+  auto fail = [&](ce_status e) {
+    (void)hipStreamSynchronize(s);
+    ctx->release(bufA, plan->bytes_lam);
+    ctx->release(bufB, plan->bytes_lam);
+    return e;
+  };
+
+  // lag octant c(l) = xi(h l)  (eq. grid: lags -N..N-1, minimum image)
+  if (xi->kind == CE_XI_TABLE) {
+    if (hipMemcpyAsync(bufA, xi->table, plan->bytes_lam, hipMemcpyHostToDevice, s) != hipSuccess)
+      return fail(CE_E_DEVICE);
+  } else {
+    double p[4] = {xi->p[0], xi->p[1], xi->p[2], xi->p[3]};
+    if (launch_lag_octant(geom->ndim, O, h, xi->kind, p, bufA, s) != hipSuccess) return fail(CE_E_DEVICE);
+  }
+  // eq. Specd: DFT over the doubled grid, separable; the lag table is even in each
+  // axis so each axis is a DCT-I of the octant (length-M FFT of the even extension).
+  double* src = bufA;
+  double* dst = bufB;
+  for (int d = 0; d < geom->ndim; ++d) {
+    int64_t A = 1, B = 1;
+    for (int i = 0; i < d; ++i) A *= O[i];
+    for (int i = d + 1; i < geom->ndim; ++i) B *= O[i];
+    FftDesc f;
+    st = build_fft(ctx, plan->M[d], 1, f);
+    if (st != CE_OK) return fail(st);
+    LineGeom g = make_geom(plan->M[d], O[d], A, B, 1, 0, 0, 16, mixed_radix(f), 1, B > 1 ? 64 : 1024);
+    DctArgs a;
+    a.in = src;
+    a.out = dst;
+    a.M = plan->M[d];
+    if (launch_dct_axis(g, f, a, s) != hipSuccess) return fail(CE_E_DEVICE);
+    std::swap(src, dst);
+  }
+  // eq. condition: lambda >= 0
+  double* stats = nullptr;
+  unsigned long long* nneg = nullptr;
+  const size_t stat_bytes = sizeof(double) * 512 + 64;
+  st = ctx->alloc((void**)&stats, stat_bytes);
+  if (st != CE_OK) return fail(st);
+  nneg = reinterpret_cast<unsigned long long*>(stats + 512);
+  std::vector<double> hs(512);
+  unsigned long long hneg = 0;
+  bool ok = hipMemsetAsync(nneg, 0, 8, s) == hipSuccess &&
+            launch_lambda_stats(src, geom->ndim, O, noct, stats, nneg, s) == hipSuccess &&
+            hipMemcpyAsync(hs.data(), stats, sizeof(double) * 512, hipMemcpyDeviceToHost, s) == hipSuccess &&
+            hipMemcpyAsync(&hneg, nneg, 8, hipMemcpyDeviceToHost, s) == hipSuccess &&
+            hipStreamSynchronize(s) == hipSuccess;
+  ctx->release(stats, stat_bytes);
+  if (!ok) return fail(CE_E_DEVICE);
+  double lmin = INFINITY, lmax = -INFINITY;
+  for (int i = 0; i < 256; ++i) {
+    lmin = std::min(lmin, hs[2 * i]);
+    lmax = std::max(lmax, hs[2 * i + 1]);
+  }
+  // xi(0): the first element of the lag octant
+  const double sigma2 = xi->kind == CE_XI_TABLE ? xi->table[0] : xi->p[0];
+  ce_plan_info pi{};
+  pi.lambda_min = lmin;
+  pi.lambda_max = lmax;
+  pi.sigma2 = sigma2;
+  pi.n_negative = (int64_t)hneg;
+  pi.n_clamped = 0;
+  if (!(lmax > 0) || lmin < -neg_tol * lmax || !std::isfinite(lmin) || !std::isfinite(lmax)) {
+    if (info) *info = pi;
+    return fail(CE_E_NOT_PSD);
+  }
+  pi.n_clamped = pi.n_negative;
+  // sqrt(lambda / M^d) in the plan precision (Papos2 scale folded with the 1/M^d of the inverse DFT)
+  double cells = 1;
+  for (int d = 0; d < geom->ndim; ++d) cells *= plan->M[d];
+  plan->bytes_sq = (plan->prec ? 8 : 4) * (size_t)noct;
+  st = ctx->alloc(&plan->sq, plan->bytes_sq);
+  if (st != CE_OK) return fail(st);
+  if (launch_sqrt_table(src, noct, 1.0 / cells, plan->prec, plan->sq, s) != hipSuccess ||
+      hipStreamSynchronize(s) != hipSuccess) {
+    ctx->release(plan->sq, plan->bytes_sq);
+    return fail(CE_E_DEVICE);
+  }
+  plan->lam = src;
+  ctx->release(src == bufA ? bufB : bufA, plan->bytes_lam);
+  pi.device_bytes = plan->bytes_lam + plan->bytes_sq;
+  plan->info = pi;
+  if (info) *info = pi;
+  *out = plan.release();
+  return CE_OK;
+}
+
+void ce_plan_release(ce_plan* plan) {
+  if (!plan) return;
+  ce_ctx* ctx = plan->ctx;
+  std::lock_guard<std::mutex> lock(ctx->mu);
+  (void)hipSetDevice(ctx->device);
+  (void)hipDeviceSynchronize();
+  ctx->release(plan->lam, plan->bytes_lam);
+  ctx->release(plan->sq, plan->bytes_sq);
+  delete plan;
+}
+
+ce_status ce_plan_get_info(const ce_plan* plan, ce_plan_info* info) {
+  if (!plan || !info) return CE_E_INVALID;
+  *info = plan->info;
+  return CE_OK;
+}
+
+ce_status ce_plan_eigenvalues(const ce_plan* plan, double* out, void* stream) {
+  if (!plan || !out) return CE_E_INVALID;
+  CE_HIP(hipSetDevice(plan->ctx->device));
+  CE_HIP(hipMemcpyAsync(out, plan->lam, plan->bytes_lam, hipMemcpyDeviceToDevice, as_stream(stream)));
+  return CE_OK;
+}
+
+}  // extern "C"
+
+// ---- pipeline driver ---------------------------------------------------------------
+
+namespace {
+
+struct InverseSetup {
+  FftDesc fM[3];   // lengths M_i
+  FftDesc fN[3];   // lengths N_i
+};
+
+ce_status setup_ffts(ce_ctx* ctx, const ce_plan* p, InverseSetup& s) {
+  for (int d = 0; d < p->ndim; ++d) {
+    CE_TRY(build_fft(ctx, p->M[d], p->prec, s.fM[d]));
+    CE_TRY(build_fft(ctx, p->n[d], p->prec, s.fN[d]));
+  }
+  return CE_OK;
+}
+
+NoiseArgs noise_args(const ce_plan* p, uint64_t seed, uint32_t rid, uint64_t first_pair) {
+  NoiseArgs n;
+  n.k0 = (uint32_t)(seed & 0xFFFFFFFFu);
+  n.k1 = (uint32_t)(seed >> 32);
+  n.rid = rid;
+  n.first_pair = first_pair;
+  n.ndim = p->ndim;
+  for (int d = 0; d < 3; ++d) {
+    n.M[d] = d < p->ndim ? p->M[d] : 1;
+    n.O[d] = d < p->ndim ? p->n[d] + 1 : 1;
+  }
+  n.sq = p->sq;
+  return n;
+}
+
+// Inverse passes for `npairs` pairs starting at pair index first_pair, through the
+// last pass whose epilogue is `epi` (rows along the last axis).
+ce_status run_inverse(ce_ctx* ctx, const ce_plan* p, const InverseSetup& fs, uint64_t seed, uint32_t rid,
+                      uint64_t first_pair, int64_t npairs, RowEpi epi, hipStream_t s) {
+  const size_t elem = p->prec ? 16 : 8;
+  const int d = p->ndim;
+  const int64_t M0 = p->M[0], M1 = p->M[1], M2 = d == 3 ? p->M[2] : 1;
+  const int64_t N0 = p->n[0], N1 = p->n[1];
+  const NoiseArgs na = noise_args(p, seed, rid, first_pair);
+  // pass 1: axis 0 with the noise prologue; lines b over the remaining axes
+  const int64_t B1 = M1 * M2;
+  const int64_t y1_item = N0 * B1;
+  void* y1 = nullptr;
+  CE_TRY(ctx->scratch(0, elem * (size_t)(y1_item * npairs), &y1));
+  LineGeom g1 = make_geom((int)M0, (int)N0, 1, B1, npairs, 0, y1_item, elem, mixed_radix(fs.fM[0]), 2, 32);
+  CE_HIP(launch_noise_pass(p->prec, g1, fs.fM[0], na, y1, s));
+  const void* last_in = y1;
+  int64_t rows = N0;
+  if (d == 3) {
+    // pass 2: axis 1, lines (m0, q2)
+    const int64_t y2_item = N0 * N1 * M2;
+    void* y2 = nullptr;
+    CE_TRY(ctx->scratch(1, elem * (size_t)(y2_item * npairs), &y2));
+    LineGeom g2 = make_geom((int)M1, (int)N1, N0, M2, npairs, y1_item, y2_item, elem, mixed_radix(fs.fM[1]), 1, 32);
+    CE_HIP(launch_line_pass(p->prec, +1, g2, fs.fM[1], y1, y2, s));
+    last_in = y2;
+    rows = N0 * N1;
+  }
+  const int last = d - 1;
+  const int64_t Ml = p->M[last], Nl = p->n[last];
+  LineGeom gl = make_geom((int)Ml, (int)Nl, rows, 1, npairs, rows * Ml, 0, elem,
+                          mixed_radix(fs.fM[last]) || (epi.mode == 2 && mixed_radix(epi.fwd)), 1, 1024);
+  CE_HIP(launch_row_inverse(p->prec, gl, fs.fM[last], epi, last_in, s));
+  return CE_OK;
+}
+
+// Forward passes after the separated first forward pass (H rows of W), ending in the
+// shell sums; partials per item.
+ce_status run_forward_bins(ce_ctx* ctx, int ndim, const int* n, int prec, int64_t nitems, void* H, int nb,
+                           double** partials_out, int64_t* groups_out, hipStream_t s) {
+  const size_t elem = prec ? 16 : 8;
+  const int N = n[0];
+  const int W = 2 * (n[ndim - 1] / 2 + 1);
+  const int64_t rows = ndim == 3 ? (int64_t)n[0] * n[1] : n[0];
+  const int64_t H_item = rows * W;
+  if (ndim == 3) {
+    FftDesc f1;
+    CE_TRY(build_fft(ctx, n[1], prec, f1));
+    LineGeom g2 = make_geom(n[1], n[1], n[0], W, nitems, H_item, H_item, elem, mixed_radix(f1), 1, 32);
+    CE_HIP(launch_line_pass(prec, -1, g2, f1, H, H, s));
+  }
+  FftDesc f0;
+  CE_TRY(build_fft(ctx, n[0], prec, f0));
+  const int64_t Bb = ndim == 3 ? (int64_t)n[1] * W : W;
+  LineGeom gb = make_geom(n[0], n[0], 1, Bb, nitems, H_item, 0, elem, mixed_radix(f0), 1, 32, (size_t)nb * 8);
+  void* part = nullptr;
+  CE_TRY(ctx->scratch(3, sizeof(double) * (size_t)(nitems * gb.groups_per_item * 2 * nb), &part));
+  BinArgs ba;
+  ba.ndim = ndim;
+  ba.N = N;
+  ba.nb = nb;
+  ba.W = W;
+  ba.partials = static_cast<double*>(part);
+  CE_HIP(launch_bin_pass(prec, gb, f0, ba, H, s));
+  *partials_out = ba.partials;
+  *groups_out = gb.groups_per_item;
+  return CE_OK;
+}
+
+int64_t survey_cells(const ce_plan* p) {
+  int64_t c = 1;
+  for (int d = 0; d < p->ndim; ++d) c *= p->n[d];
+  return c;
+}
+
+// pairs per chunk so that the scratch stays within a cap
+int64_t chunk_pairs(const ce_plan* p, int64_t npairs, size_t cap) {
+  const size_t elem = p->prec ? 16 : 8;
+  double per = 1;
+  for (int d = 0; d < p->ndim; ++d) per *= p->M[d];
+  per = per / 2 * elem * 2.0;  // pass-1 and pass-2 intermediates (upper bound)
+  int64_t c = (int64_t)((double)cap / per);
+  if (c < 1) c = 1;
+  return std::min(c, npairs);
+}
+
+constexpr size_t kScratchCap = size_t(8) << 30;
+
+}  // namespace
+
+extern "C" {
+
+ce_status ce_generate_fields(ce_ctx* ctx, const ce_plan* plan, uint64_t seed, uint32_t request_id,
+                             uint64_t first_realization, int64_t count, void* out_fields, void* stream) {
+  if (!ctx || !plan || !out_fields || count <= 0 || (first_realization & 1)) return CE_E_INVALID;
+  if (plan->ctx != ctx) return CE_E_INVALID;
+  if ((first_realization + (uint64_t)count + 1) / 2 > 0xFFFFFFFFull) return CE_E_INVALID;
+  std::lock_guard<std::mutex> lock(ctx->mu);
+  CE_HIP(hipSetDevice(ctx->device));
+  hipStream_t s = as_stream(stream);
+  ctx->last = s;
+  InverseSetup fs;
+  CE_TRY(setup_ffts(ctx, plan, fs));
+  const int64_t npairs = (count + 1) / 2;
+  const int64_t cp = chunk_pairs(plan, npairs, kScratchCap);
+  const int64_t ncells = survey_cells(plan);
+  const size_t elem = plan->prec ? 8 : 4;
+  for (int64_t j = 0; j < npairs; j += cp) {
+    const int64_t np = std::min(cp, npairs - j);
+    RowEpi e;
+    e.mode = 1;
+    e.ncells = ncells;
+    e.count = std::min<int64_t>(count - 2 * j, 2 * np);
+    e.real_off = 0;
+    e.fields = static_cast<char*>(out_fields) + elem * (size_t)(2 * j * ncells);
+    CE_TRY(run_inverse(ctx, plan, fs, seed, request_id, first_realization / 2 + j, np, e, s));
+  }
+  return CE_OK;
+}
+
+ce_status ce_lognormal_poisson(ce_ctx* ctx, const ce_plan* plan, const void* fields, int64_t count, double nbar,
+                               const float* mask_f, uint64_t seed, uint32_t request_id, uint64_t first_realization,
+                               void* out_delta, int32_t* out_counts, int64_t* out_ntot, void* stream) {
+  if (!ctx || !plan || !fields || !out_counts || count <= 0) return CE_E_INVALID;
+  if (!(nbar >= 0) || !std::isfinite(nbar)) return CE_E_INVALID;
+  if ((first_realization + (uint64_t)count) / 2 > 0xFFFFFFFFull) return CE_E_INVALID;
+  std::lock_guard<std::mutex> lock(ctx->mu);
+  CE_HIP(hipSetDevice(ctx->device));
+  hipStream_t s = as_stream(stream);
+  ctx->last = s;
+  const int64_t ncells = survey_cells(plan);
+  void* acc = nullptr;
+  CE_TRY(ctx->scratch(4, sizeof(unsigned long long) * (size_t)count, &acc));
+  auto* ntot = static_cast<unsigned long long*>(acc);
+  CE_HIP(launch_zero_u64(ntot, count, s));
+  CE_HIP(launch_lognormal_poisson(plan->prec, fields, count, ncells, 0.5 * plan->info.sigma2, nbar, mask_f,
+                                  (uint32_t)(seed & 0xFFFFFFFFu), (uint32_t)(seed >> 32), request_id,
+                                  first_realization, out_delta, out_counts, ntot, ctx->flags, s));
+  if (out_ntot) CE_HIP(launch_copy_ntot(ntot, out_ntot, count, s));
+  return CE_OK;
+}
+
+ce_status ce_shell_table(const ce_geometry* geom, int32_t nbins, int64_t* nmodes, double* kmean) {
+  if (!geom || !nmodes || !kmean || nbins <= 0) return CE_E_INVALID;
+  if (geom->ndim < 1 || geom->ndim > 3) return CE_E_INVALID;
+  for (int i = 0; i < geom->ndim; ++i)
+    if (geom->n[i] < 2 || (geom->n[i] & 1) || !(geom->h[i] > 0)) return CE_E_INVALID;
+  if (!is_cubic(geom)) return CE_E_UNSUPPORTED;
+  std::vector<int64_t> nm;
+  std::vector<double> km;
+  shell_table_host((int)geom->n[0], geom->ndim, geom->h[0], nbins, nm, km);
+  std::memcpy(nmodes, nm.data(), sizeof(int64_t) * nbins);
+  std::memcpy(kmean, km.data(), sizeof(double) * nbins);
+  return CE_OK;
+}
+
+ce_status ce_fft_factors(int32_t length, int32_t* radices, int32_t* nstages) {
+  if (!radices || !nstages) return CE_E_INVALID;
+  std::vector<int> r;
+  if (!factor_length(length, r)) return CE_E_UNSUPPORTED;
+  *nstages = (int32_t)r.size();
+  for (size_t i = 0; i < r.size(); ++i) radices[i] = r[i];
+  return CE_OK;
+}
+
+ce_status ce_estimate_pk(ce_ctx* ctx, const ce_geometry* geom, ce_precision precision, ce_map_kind kind,
+                         const void* maps, int64_t count, const int64_t* ntot, const float* mask_f, int32_t nbins,
+                         double* out_pk, int64_t* out_nmodes, double* out_kmean, void* stream) {
+  if (!ctx || !geom || !maps || !out_pk || count <= 0 || nbins <= 0) return CE_E_INVALID;
+  if (precision != CE_F32 && precision != CE_F64) return CE_E_INVALID;
+  if (kind != CE_MAP_FIELD && kind != CE_MAP_COUNTS_DELTAG) return CE_E_INVALID;
+  CE_TRY(check_geometry(geom));
+  if (!is_cubic(geom)) return CE_E_UNSUPPORTED;
+  std::lock_guard<std::mutex> lock(ctx->mu);
+  CE_HIP(hipSetDevice(ctx->device));
+  hipStream_t s = as_stream(stream);
+  ctx->last = s;
+  const int prec = precision == CE_F64 ? 1 : 0;
+  const int ndim = geom->ndim;
+  int n[3] = {1, 1, 1};
+  int64_t ncells = 1;
+  for (int d = 0; d < ndim; ++d) {
+    n[d] = (int)geom->n[d];
+    ncells *= n[d];
+  }
+  const int64_t nitems = (count + 1) / 2;
+  const int Nl = n[ndim - 1];
+  const int W = 2 * (Nl / 2 + 1);
+  const int64_t rows = ncells / Nl;
+  const size_t elem = prec ? 16 : 8;
+
+  PairLoad pl;
+  pl.kind = kind == CE_MAP_FIELD ? 0 : 1;
+  pl.maps = maps;
+  pl.count = count;
+  pl.ncells = ncells;
+  pl.mask = mask_f;
+  pl.fsum = (double)ncells;
+  if (pl.kind == 1) {
+    if (mask_f) {
+      std::vector<float> hm(ncells);
+      CE_HIP(hipMemcpyAsync(hm.data(), mask_f, sizeof(float) * ncells, hipMemcpyDeviceToHost, s));
+      CE_HIP(hipStreamSynchronize(s));
+      double fs = 0;
+      for (float v : hm) fs += (double)v;
+      pl.fsum = fs;
+    }
+    if (ntot) {
+      pl.ntot = ntot;
+    } else {
+      void* acc = nullptr;
+      CE_TRY(ctx->scratch(4, sizeof(unsigned long long) * (size_t)count * 2, &acc));
+      auto* u = static_cast<unsigned long long*>(acc);
+      auto* sgn = reinterpret_cast<int64_t*>(u + count);
+      CE_HIP(launch_zero_u64(u, count, s));
+      CE_HIP(launch_count_totals(static_cast<const int32_t*>(maps), count, ncells, u, s));
+      CE_HIP(launch_copy_ntot(u, sgn, count, s));
+      pl.ntot = sgn;
+    }
+  }
+  void* H = nullptr;
+  CE_TRY(ctx->scratch(2, elem * (size_t)(nitems * rows * W), &H));
+  pl.H = H;
+  pl.H_item = rows * W;
+  FftDesc fl;
+  CE_TRY(build_fft(ctx, Nl, prec, fl));
+  LineGeom g1 = make_geom(Nl, Nl, rows, 1, nitems, 0, 0, elem, mixed_radix(fl), 1, 1024);
+  CE_HIP(launch_pair_forward(prec, g1, fl, pl, s));
+  double* partials = nullptr;
+  int64_t groups = 0;
+  CE_TRY(run_forward_bins(ctx, ndim, n, prec, nitems, H, nbins, &partials, &groups, s));
+  int64_t* nm = nullptr;
+  const std::vector<double>* km = nullptr;
+  CE_TRY(device_shells(ctx, n[0], ndim, geom->h[0], nbins, &nm, &km));
+  const double norm = std::pow(geom->h[0], ndim) / (double)ncells;
+  CE_HIP(launch_bin_reduce(partials, nitems, groups, nbins, count, nm, norm, 0, nullptr, nullptr, (double)ncells,
+                           out_pk, ctx->flags, s));
+  if (out_nmodes) CE_HIP(hipMemcpyAsync(out_nmodes, nm, sizeof(int64_t) * nbins, hipMemcpyDeviceToDevice, s));
+  if (out_kmean) {
+    std::vector<double> k(*km);
+    for (double& v : k) v /= geom->h[0];
+    CE_HIP(hipMemcpyAsync(out_kmean, k.data(), sizeof(double) * nbins, hipMemcpyHostToDevice, s));
+    CE_HIP(hipStreamSynchronize(s));
+  }
+  return CE_OK;
+}
+
+ce_status ce_pk_covariance(ce_ctx* ctx, const double* pk, int64_t count, int32_t nbins, double* out_cov,
+                           double* out_cnorm, void* stream) {
+  if (!ctx || !pk || count < 2 || nbins <= 0) return CE_E_INVALID;
+  if (!out_cov && !out_cnorm) return CE_OK;
+  CE_HIP(hipSetDevice(ctx->device));
+  CE_HIP(launch_covariance(pk, count, nbins, out_cov, out_cnorm, as_stream(stream)));
+  return CE_OK;
+}
+
+ce_status ce_pipeline_run(ce_ctx* ctx, const ce_plan* plan, uint64_t seed, uint32_t request_id,
+                          uint64_t first_realization, int64_t count, double nbar, int32_t nbins, void* out_fields,
+                          void* out_delta, int32_t* out_counts, int64_t* out_ntot, double* out_pk, double* out_cov,
+                          double* out_cnorm, void* stream) {
+  if (!ctx || !plan || !out_pk || count <= 0 || nbins <= 0 || (first_realization & 1)) return CE_E_INVALID;
+  if (!(nbar >= 0) || !std::isfinite(nbar)) return CE_E_INVALID;
+  if (plan->ctx != ctx) return CE_E_INVALID;
+  for (int d = 1; d < plan->ndim; ++d)
+    if (plan->n[d] != plan->n[0] || plan->h[d] != plan->h[0]) return CE_E_UNSUPPORTED;
+  {
+    std::lock_guard<std::mutex> lock(ctx->mu);
+    CE_HIP(hipSetDevice(ctx->device));
+    hipStream_t s = as_stream(stream);
+    ctx->last = s;
+    InverseSetup fs;
+    CE_TRY(setup_ffts(ctx, plan, fs));
+    const int ndim = plan->ndim;
+    const int64_t ncells = survey_cells(plan);
+    const int Nl = plan->n[ndim - 1];
+    const int W = 2 * (Nl / 2 + 1);
+    const int64_t rows = ncells / Nl;
+    const size_t elem = plan->prec ? 16 : 8;
+    const size_t relem = plan->prec ? 8 : 4;
+    const int64_t npairs = (count + 1) / 2;
+    const int64_t cp = chunk_pairs(plan, npairs, kScratchCap);
+    void* acc = nullptr;
+    CE_TRY(ctx->scratch(4, sizeof(unsigned long long) * (size_t)(2 * npairs), &acc));
+    auto* ntot = static_cast<unsigned long long*>(acc);
+    CE_HIP(launch_zero_u64(ntot, 2 * npairs, s));
+    int64_t* nm = nullptr;
+    const std::vector<double>* km = nullptr;
+    CE_TRY(device_shells(ctx, plan->n[0], ndim, plan->h[0], nbins, &nm, &km));
+    const double norm = std::pow(plan->h[0], ndim) / (double)ncells;
+    for (int64_t j = 0; j < npairs; j += cp) {
+      const int64_t np = std::min(cp, npairs - j);
+      void* H = nullptr;
+      CE_TRY(ctx->scratch(2, elem * (size_t)(np * rows * W), &H));
+      RowEpi e;
+      e.mode = 2;
+      e.ncells = ncells;
+      e.count = std::min<int64_t>(count - 2 * j, 2 * np);
+      e.real_off = 0;
+      e.fields = out_fields ? static_cast<char*>(out_fields) + relem * (size_t)(2 * j * ncells) : nullptr;
+      e.delta = out_delta ? static_cast<char*>(out_delta) + relem * (size_t)(2 * j * ncells) : nullptr;
+      e.counts = out_counts ? out_counts + 2 * j * ncells : nullptr;
+      e.ntot = ntot + 2 * j;
+      e.flags = ctx->flags;
+      e.s2half = 0.5 * plan->info.sigma2;
+      e.nbar = nbar;
+      e.k0 = (uint32_t)(seed & 0xFFFFFFFFu);
+      e.k1 = (uint32_t)(seed >> 32);
+      e.rid = request_id;
+      e.first_pair = first_realization / 2 + j;
+      e.fwd = fs.fN[ndim - 1];
+      e.H = H;
+      e.H_item = rows * W;
+      CE_TRY(run_inverse(ctx, plan, fs, seed, request_id, first_realization / 2 + j, np, e, s));
+      double* partials = nullptr;
+      int64_t groups = 0;
+      CE_TRY(run_forward_bins(ctx, ndim, plan->n, plan->prec, np, H, nbins, &partials, &groups, s));
+      CE_HIP(launch_bin_reduce(partials, np, groups, nbins, e.count, nm, norm, 1, ntot + 2 * j, nullptr,
+                               (double)ncells, out_pk + 2 * j * nbins, ctx->flags, s));
+    }
+    if (out_ntot) CE_HIP(launch_copy_ntot(ntot, out_ntot, count, s));
+    if (count >= 2 && (out_cov || out_cnorm)) CE_HIP(launch_covariance(out_pk, count, nbins, out_cov, out_cnorm, s));
+  }
+  return CE_OK;
+}
+
+ce_status ce_debug_philox(uint64_t seed, const uint32_t ctr[4], int64_t n_calls, uint32_t* out_words, void* stream) {
+  if (!ctr || !out_words || n_calls <= 0) return CE_E_INVALID;
+  CE_HIP(launch_debug_philox((uint32_t)(seed & 0xFFFFFFFFu), (uint32_t)(seed >> 32), ctr, n_calls, out_words,
+                             as_stream(stream)));
+  return CE_OK;
+}
+
+ce_status ce_debug_noise(const ce_plan* plan, uint64_t seed, uint32_t request_id, uint64_t pair, void* out,
+                         void* stream) {
+  if (!plan || !out || pair > 0xFFFFFFFFull) return CE_E_INVALID;
+  CE_HIP(hipSetDevice(plan->ctx->device));
+  int64_t cells = 1;
+  for (int d = 0; d < plan->ndim; ++d) cells *= plan->M[d];
+  const NoiseArgs n = noise_args(plan, seed, request_id, 0);
+  CE_HIP(launch_debug_noise(plan->prec, n, pair, cells, out, as_stream(stream)));
+  return CE_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,368 @@
+// Device building blocks for gfx950: complex arithmetic, the Philox4x32-10
+// counter generator, uniform and Box-Muller maps, radix DFTs and the in-place
+// LDS Stockham stage used by every line-transform pass.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "ce_internal.hpp"
+
+namespace ce {
+
+template <typename T>
+struct cpx {
+  T x, y;
+};
+
+template <typename T>
+__device__ __forceinline__ cpx<T> c_add(cpx<T> a, cpx<T> b) { return {a.x + b.x, a.y + b.y}; }
+template <typename T>
+__device__ __forceinline__ cpx<T> c_sub(cpx<T> a, cpx<T> b) { return {a.x - b.x, a.y - b.y}; }
+template <typename T>
+__device__ __forceinline__ cpx<T> c_mul(cpx<T> a, cpx<T> b) {
+  return {a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
+}
+template <typename T>
+__device__ __forceinline__ cpx<T> c_conj(cpx<T> a) { return {a.x, -a.y}; }
+template <typename T>
+__device__ __forceinline__ cpx<T> c_scale(cpx<T> a, T s) { return {a.x * s, a.y * s}; }
+// multiply by S*i (S = +1 or -1)
+template <int S, typename T>
+__device__ __forceinline__ cpx<T> c_rot(cpx<T> a) {
+  return S > 0 ? cpx<T>{-a.y, a.x} : cpx<T>{a.y, -a.x};
+}
+
+// ---------------------------------------------------------------------------
+// Philox4x32-10 (Salmon, Moraes, Dror & Shaw, SC'11): ten rounds of two
+// 32x32->64 multiplies by odd constants; the high halves are XOR-ed with the
+// other two words and the round key, the key advances by two Weyl constants.
+struct Words4 {
+  uint32_t x0, x1, x2, x3;
+};
+
+__device__ __forceinline__ Words4 philox4x32_10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
+                                                uint32_t k0, uint32_t k1) {
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    if (r) {
+      k0 += 0x9E3779B9u;
+      k1 += 0xBB67AE85u;
+    }
+    const uint64_t pa = (uint64_t)c0 * 0xD2511F53ull;
+    const uint64_t pb = (uint64_t)c2 * 0xCD9E8D57ull;
+    const uint32_t n0 = (uint32_t)(pb >> 32) ^ c1 ^ k0;
+    const uint32_t n2 = (uint32_t)(pa >> 32) ^ c3 ^ k1;
+    c1 = (uint32_t)pb;
+    c3 = (uint32_t)pa;
+    c0 = n0;
+    c2 = n2;
+  }
+  return {c0, c1, c2, c3};
+}
+
+// Uniform in (0, 1): (x + 1/2) 2^-32.  FP64 exactly; FP32 as the single rounding
+// of that value computed from float(x) (relative error below 2^-23).
+__device__ __forceinline__ double unit64(uint32_t x) { return ((double)x + 0.5) * 0x1p-32; }
+__device__ __forceinline__ float unit32(uint32_t x) { return __fmaf_rn((float)x, 0x1p-32f, 0x1p-33f); }
+// 52-bit uniform from two words, exact in FP64.
+__device__ __forceinline__ double unit52(uint32_t x0, uint32_t x1) {
+  const uint64_t v = ((uint64_t)x0 << 20) | (uint64_t)(x1 >> 12);
+  return ((double)v + 0.5) * 0x1p-52;
+}
+
+// Box-Muller: (r cos 2 pi u2, r sin 2 pi u2), r = sqrt(-2 ln u1).
+__device__ __forceinline__ cpx<double> box_muller(double u1, double u2) {
+  const double r = sqrt(-2.0 * log(u1));
+  double s, c;
+  sincospi(2.0 * u2, &s, &c);
+  return {r * c, r * s};
+}
+__device__ __forceinline__ cpx<float> box_muller(float u1, float u2) {
+  const float r = sqrtf(-2.0f * logf(u1));
+  float s, c;
+  sincospif(2.0f * u2, &s, &c);
+  return {r * c, r * s};
+}
+
+template <typename T>
+__device__ __forceinline__ cpx<T> normal_pair(uint32_t a, uint32_t b);
+template <>
+__device__ __forceinline__ cpx<double> normal_pair<double>(uint32_t a, uint32_t b) {
+  return box_muller(unit64(a), unit64(b));
+}
+template <>
+__device__ __forceinline__ cpx<float> normal_pair<float>(uint32_t a, uint32_t b) {
+  return box_muller(unit32(a), unit32(b));
+}
+
+// ---------------------------------------------------------------------------
+// LDS addressing: one padding slot every 16 elements breaks the power-of-two
+// strides of the Stockham writes; lines are a pitch apart (odd offset).
+__device__ __forceinline__ int pidx(int i) { return i + (i >> 4); }
+__host__ __device__ inline int line_pitch(int L) { return L + (L >> 4) + 1; }
+
+// Workgroup id -> logical tile so consecutive tiles share an XCD (and its L2):
+// hardware places workgroup i on XCD i % 8.
+__device__ __forceinline__ int64_t xcd_tile(int64_t i, int64_t G) {
+  const int64_t q = G >> 3, rem = G & 7;
+  const int64_t x = i & 7, k = i >> 3;
+  return x * q + (x < rem ? x : rem) + k;
+}
+
+// ---------------------------------------------------------------------------
+// Radix DFTs, X_k = sum_n v_n exp(S 2 pi i n k / R).
+
+// cos / sin (2 pi m / 16), m = 0..15
+__device__ constexpr double kC16[16] = {1.0, 0.92387953251128675613, 0.70710678118654752440,
+                                        0.38268343236508977173, 0.0, -0.38268343236508977173,
+                                        -0.70710678118654752440, -0.92387953251128675613, -1.0,
+                                        -0.92387953251128675613, -0.70710678118654752440,
+                                        -0.38268343236508977173, 0.0, 0.38268343236508977173,
+                                        0.70710678118654752440, 0.92387953251128675613};
+__device__ constexpr double kS16[16] = {0.0, 0.38268343236508977173, 0.70710678118654752440,
+                                        0.92387953251128675613, 1.0, 0.92387953251128675613,
+                                        0.70710678118654752440, 0.38268343236508977173, 0.0,
+                                        -0.38268343236508977173, -0.70710678118654752440,
+                                        -0.92387953251128675613, -1.0, -0.92387953251128675613,
+                                        -0.70710678118654752440, -0.38268343236508977173};
+
+// multiply by exp(S 2 pi i m / 16) for a compile-time m in [0, 8)
+template <int S, int M, typename T>
+__device__ __forceinline__ cpx<T> tw16(cpx<T> a) {
+  if constexpr (M == 0) {
+    return a;
+  } else if constexpr (M == 4) {
+    return c_rot<S>(a);
+  } else {
+    const T c = (T)kC16[M], s = (T)(S * kS16[M]);
+    return {a.x * c - a.y * s, a.x * s + a.y * c};
+  }
+}
+
+template <int R, int S, typename T>
+struct Pow2Dft;
+
+template <int S, typename T>
+struct Pow2Dft<1, S, T> {
+  static __device__ __forceinline__ void run(cpx<T>*) {}
+};
+
+template <int S, typename T>
+struct Pow2Dft<2, S, T> {
+  static __device__ __forceinline__ void run(cpx<T>* v) {
+    const cpx<T> a = v[0], b = v[1];
+    v[0] = c_add(a, b);
+    v[1] = c_sub(a, b);
+  }
+};
+
+template <int R, int S, typename T>
+struct Pow2Dft {
+  template <int K>
+  static __device__ __forceinline__ void combine(cpx<T>* v, const cpx<T>* e, const cpx<T>* o) {
+    if constexpr (K < R / 2) {
+      const cpx<T> t = tw16<S, K*(16 / R)>(o[K]);
+      v[K] = c_add(e[K], t);
+      v[K + R / 2] = c_sub(e[K], t);
+      combine<K + 1>(v, e, o);
+    }
+  }
+  static __device__ __forceinline__ void run(cpx<T>* v) {
+    cpx<T> e[R / 2], o[R / 2];
+#pragma unroll
+    for (int n = 0; n < R / 2; ++n) {
+      e[n] = v[2 * n];
+      o[n] = v[2 * n + 1];
+    }
+    Pow2Dft<R / 2, S, T>::run(e);
+    Pow2Dft<R / 2, S, T>::run(o);
+    combine<0>(v, e, o);
+  }
+};
+
+// Odd radix R, streamed: pairs n, R-n share cosines and sines, so only
+// cos/sin(2 pi m / R) for m = 1..(R-1)/2 are needed (held in registers); each
+// output pair X_k, X_{R-k} is stored as soon as it is formed.  The line's root
+// table gives tw[m L / R] = exp(-2 pi i m / R).
+template <int R, int S, typename T>
+__device__ __forceinline__ void odd_dft_store(const cpx<T>* v, const T* cs, const T* sn, cpx<T>* dst, int base,
+                                              int Ns, int keep) {
+  constexpr int H = (R - 1) / 2;
+  cpx<T> x0 = v[0];
+#pragma unroll
+  for (int n = 1; n <= H; ++n) x0 = c_add(x0, c_add(v[n], v[R - n]));
+  if (base < keep) dst[pidx(base)] = x0;
+#pragma unroll
+  for (int k = 1; k <= H; ++k) {
+    cpx<T> a = v[0], b = {T(0), T(0)};
+#pragma unroll
+    for (int n = 1; n <= H; ++n) {
+      const int m = (n * k) % R;  // compile-time after unrolling
+      const int mm = m <= H ? m : R - m;
+      const T c = cs[mm];
+      const T s = m <= H ? sn[mm] : -sn[mm];
+      const cpx<T> sp = c_add(v[n], v[R - n]);
+      const cpx<T> dm = c_sub(v[n], v[R - n]);
+      a.x += sp.x * c;
+      a.y += sp.y * c;
+      b.x += dm.x * s;
+      b.y += dm.y * s;
+    }
+    const cpx<T> ib = c_rot<S>(b);
+    const int o1 = base + k * Ns, o2 = base + (R - k) * Ns;
+    if (o1 < keep) dst[pidx(o1)] = c_add(a, ib);
+    if (o2 < keep) dst[pidx(o2)] = c_sub(a, ib);
+  }
+}
+
+// One in-place Stockham stage on an LDS line (Govindaraju et al. 2008 indexing):
+// butterfly j reads elements j + r L/R, twiddles by exp(S 2 pi i r (j mod Ns)/(Ns R)),
+// and writes (j/Ns) Ns R + (j mod Ns) + r Ns.  All reads precede all writes
+// (workgroup barrier), so the stage is in place.  With keep < L only outputs below
+// keep are written (pruned last stage).  Power-of-two radices only.
+template <typename T, int R, int S>
+__device__ __forceinline__ void stockham_stage(cpx<T>* line, int L, int Ns, int lane, int nlanes, bool active,
+                                               const cpx<T>* __restrict__ tw, int keep) {
+  constexpr int NB = (kEPT + R - 1) / R;
+  const int nb = L / R;
+  cpx<T> v[NB][R];
+#pragma unroll
+  for (int b = 0; b < NB; ++b) {
+    const int j = lane + b * nlanes;
+    if (active && j < nb) {
+#pragma unroll
+      for (int r = 0; r < R; ++r) v[b][r] = line[pidx(j + r * nb)];
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int b = 0; b < NB; ++b) {
+    const int j = lane + b * nlanes;
+    if (active && j < nb) {
+      const int k = j % Ns;
+      if (Ns > 1) {
+        const int step = k * (L / (Ns * R));
+#pragma unroll
+        for (int r = 1; r < R; ++r) {
+          cpx<T> w = tw[r * step];
+          if (S > 0) w.y = -w.y;
+          v[b][r] = c_mul(v[b][r], w);
+        }
+      }
+      Pow2Dft<R, S, T>::run(v[b]);
+      const int base = (j / Ns) * Ns * R + k;
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const int o = base + r * Ns;
+        if (o < keep) line[pidx(o)] = v[b][r];
+      }
+    }
+  }
+  __syncthreads();
+}
+
+// Out-of-place Stockham stage (src -> dst LDS lines), any supported radix; one
+// butterfly at a time, so the register footprint is one radix.
+template <typename T, int R, int S>
+__device__ __forceinline__ void pingpong_stage(const cpx<T>* src, cpx<T>* dst, int L, int Ns, int lane, int nlanes,
+                                               bool active, const cpx<T>* __restrict__ tw, int keep) {
+  constexpr bool kPow2 = (R & (R - 1)) == 0;
+  constexpr int H = (R - 1) / 2;
+  const int nb = L / R;
+  T cs[H + 1], sn[H + 1];
+  if constexpr (!kPow2) {
+    const int Lr = L / R;
+#pragma unroll
+    for (int m = 1; m <= H; ++m) {
+      const cpx<T> w = tw[m * Lr];
+      cs[m] = w.x;
+      sn[m] = -w.y;
+    }
+  }
+  if (active) {
+    for (int j = lane; j < nb; j += nlanes) {
+      cpx<T> v[R];
+#pragma unroll
+      for (int r = 0; r < R; ++r) v[r] = src[pidx(j + r * nb)];
+      const int k = j % Ns;
+      if (Ns > 1) {
+        const int step = k * (L / (Ns * R));
+#pragma unroll
+        for (int r = 1; r < R; ++r) {
+          cpx<T> w = tw[r * step];
+          if (S > 0) w.y = -w.y;
+          v[r] = c_mul(v[r], w);
+        }
+      }
+      const int base = (j / Ns) * Ns * R + k;
+      if constexpr (kPow2) {
+        Pow2Dft<R, S, T>::run(v);
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          const int o = base + r * Ns;
+          if (o < keep) dst[pidx(o)] = v[r];
+        }
+      } else {
+        odd_dft_store<R, S, T>(v, cs, sn, dst, base, Ns, keep);
+      }
+    }
+  }
+  __syncthreads();
+}
+
+// Full line FFT over the stages of f.rad.  Every thread of the workgroup must
+// call it (barriers inside); threads without a line pass active = false.
+// MIX = false: power-of-two radices, in place in buffer a, registers staged
+// across the barrier.  MIX = true: any radix, ping-pong between a and b.
+// Returns the buffer that holds the result.
+template <typename T, int S, bool MIX>
+__device__ cpx<T>* line_fft(cpx<T>* a, cpx<T>* b, const FftDesc& f, int lane, int nlanes, bool active, int keep) {
+  const cpx<T>* __restrict__ tw = static_cast<const cpx<T>*>(f.tw);
+  const int L = f.L;
+  int Ns = 1;
+  if constexpr (!MIX) {
+    for (int s = 0; s < f.nst; ++s) {
+      const int R = f.rad[s];
+      const int kp = (s == f.nst - 1) ? keep : L;
+      switch (R) {
+        case 2: stockham_stage<T, 2, S>(a, L, Ns, lane, nlanes, active, tw, kp); break;
+        case 4: stockham_stage<T, 4, S>(a, L, Ns, lane, nlanes, active, tw, kp); break;
+        case 8: stockham_stage<T, 8, S>(a, L, Ns, lane, nlanes, active, tw, kp); break;
+        default: stockham_stage<T, 16, S>(a, L, Ns, lane, nlanes, active, tw, kp); break;
+      }
+      Ns *= R;
+    }
+    return a;
+  } else {
+    cpx<T>* src = a;
+    cpx<T>* dst = b;
+    for (int s = 0; s < f.nst; ++s) {
+      const int R = f.rad[s];
+      const int kp = (s == f.nst - 1) ? keep : L;
+      switch (R) {
+        case 2: pingpong_stage<T, 2, S>(src, dst, L, Ns, lane, nlanes, active, tw, kp); break;
+        case 4: pingpong_stage<T, 4, S>(src, dst, L, Ns, lane, nlanes, active, tw, kp); break;
+        case 8: pingpong_stage<T, 8, S>(src, dst, L, Ns, lane, nlanes, active, tw, kp); break;
+        case 16: pingpong_stage<T, 16, S>(src, dst, L, Ns, lane, nlanes, active, tw, kp); break;
+        case 3: pingpong_stage<T, 3, S>(src, dst, L, Ns, lane, nlanes, active, tw, kp); break;
+        case 5: pingpong_stage<T, 5, S>(src, dst, L, Ns, lane, nlanes, active, tw, kp); break;
+        case 7: pingpong_stage<T, 7, S>(src, dst, L, Ns, lane, nlanes, active, tw, kp); break;
+        case 11: pingpong_stage<T, 11, S>(src, dst, L, Ns, lane, nlanes, active, tw, kp); break;
+        case 13: pingpong_stage<T, 13, S>(src, dst, L, Ns, lane, nlanes, active, tw, kp); break;
+        case 17: pingpong_stage<T, 17, S>(src, dst, L, Ns, lane, nlanes, active, tw, kp); break;
+        case 19: pingpong_stage<T, 19, S>(src, dst, L, Ns, lane, nlanes, active, tw, kp); break;
+        case 23: pingpong_stage<T, 23, S>(src, dst, L, Ns, lane, nlanes, active, tw, kp); break;
+        case 29: pingpong_stage<T, 29, S>(src, dst, L, Ns, lane, nlanes, active, tw, kp); break;
+        default: pingpong_stage<T, 31, S>(src, dst, L, Ns, lane, nlanes, active, tw, kp); break;
+      }
+      cpx<T>* t = src;
+      src = dst;
+      dst = t;
+      Ns *= R;
+    }
+    return src;
+  }
+}
+
+}  // namespace ce

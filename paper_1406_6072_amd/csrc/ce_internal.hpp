@@ -1,0 +1,127 @@
+// Internal interface between the host API (ce_api.cpp) and the device code
+// (ce_kernels.hip).  Plain structs passed by value as kernel arguments.
+#pragma once
+
+#include <hip/hip_runtime_api.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace ce {
+
+constexpr int kMaxStages = 16;
+constexpr int kEPT = 16;        // FFT elements held per thread
+constexpr int kMaxWG = 512;
+
+// One FFT line length: radices of the mixed-radix Stockham stages and the
+// device table of forward roots tw[k] = exp(-2 pi i k / L) in the pass precision.
+struct FftDesc {
+  int32_t L = 0;
+  int32_t nst = 0;
+  int32_t rad[kMaxStages] = {};
+  const void* tw = nullptr;
+};
+
+// A batch of line transforms.  Lines are (a, b), a in [0, A), b in [0, B); line
+// element i of the input is at in + item*in_item + (a*L + i)*B + b, of the output at
+// out + item*out_item + (a*K + i)*B + b.  R consecutive flattened line ids a*B + b
+// form one workgroup; nlanes threads serve one line.
+struct LineGeom {
+  int64_t A = 0, B = 0;
+  int64_t in_item = 0, out_item = 0;
+  int64_t nitems = 0;
+  int64_t groups_per_item = 0;
+  int32_t L = 0, K = 0;
+  int32_t R = 0, nlanes = 0;
+  int32_t lpitch = 0;          // LDS elements per line buffer
+  int32_t nbuf = 1;            // LDS buffers per line: 1 (in place) or 2 (ping-pong, mixed radix)
+};
+
+// Noise prologue of the first inverse pass (lines along axis 0 of the embedding).
+struct NoiseArgs {
+  uint32_t k0 = 0, k1 = 0, rid = 0;
+  uint64_t first_pair = 0;
+  int32_t ndim = 0;
+  int32_t M[3] = {1, 1, 1};
+  int32_t O[3] = {1, 1, 1};    // octant sides N_i + 1
+  const void* sq = nullptr;    // sqrt(lambda / M^d) on the octant (pass precision)
+};
+
+// Epilogue of the last inverse pass (rows along the last axis).
+struct RowEpi {
+  int32_t mode = 0;            // 0: complex store, 1: fields, 2: fused lognormal/Poisson/forward
+  int64_t ncells = 0;          // survey cells per realization
+  int64_t count = 0;           // realizations covered by this call
+  int64_t real_off = 0;        // local realization index of item 0's real part
+  void* fields = nullptr;      // nullable (pass precision)
+  void* delta = nullptr;       // nullable (pass precision)
+  int32_t* counts = nullptr;   // nullable
+  unsigned long long* ntot = nullptr;  // per local realization (zeroed by the host)
+  uint32_t* flags = nullptr;
+  double s2half = 0, nbar = 0;
+  uint32_t k0 = 0, k1 = 0, rid = 0;
+  uint64_t first_pair = 0;
+  FftDesc fwd;                 // forward FFT of the packed counts row (length K)
+  void* H = nullptr;           // separated spectra rows: W = 2 (K/2 + 1) complex per row
+  int64_t H_item = 0;
+};
+
+// Prologue of the standalone spectrum's first pass (rows of two real maps packed).
+struct PairLoad {
+  int32_t kind = 0;            // 0: real maps in pass precision, 1: int32 counts -> contrast
+  const void* maps = nullptr;
+  int64_t count = 0;           // maps in the stack
+  int64_t ncells = 0;
+  const int64_t* ntot = nullptr;   // counts kind
+  const float* mask = nullptr;     // counts kind, nullable
+  double fsum = 0;             // sum of mask (or ncells)
+  void* H = nullptr;
+  int64_t H_item = 0;
+};
+
+// Binning epilogue of the last forward pass (lines along axis 0 of the spectra).
+struct BinArgs {
+  int32_t ndim = 0, N = 0, nb = 0, W = 0;
+  double* partials = nullptr;  // [item][group][2][nb]
+};
+
+// Plan-time DCT-I of the lag octant along one axis (FP64).
+struct DctArgs {
+  const double* in = nullptr;
+  double* out = nullptr;
+  int32_t M = 0;               // even-extension length along the axis
+};
+
+// ---- launchers (ce_kernels.hip) -------------------------------------------
+hipError_t launch_lag_octant(int ndim, const int32_t* O, const double* h, int kind, const double* p,
+                             double* out, hipStream_t s);
+hipError_t launch_dct_axis(const LineGeom& g, const FftDesc& f, const DctArgs& a, hipStream_t s);
+hipError_t launch_lambda_stats(const double* lam, int ndim, const int32_t* O, int64_t n, double* stats,
+                               unsigned long long* nneg, hipStream_t s);
+hipError_t launch_sqrt_table(const double* lam, int64_t n, double inv_cells, int prec, void* out,
+                             hipStream_t s);
+hipError_t launch_noise_pass(int prec, const LineGeom& g, const FftDesc& f, const NoiseArgs& n, void* out,
+                             hipStream_t s);
+hipError_t launch_line_pass(int prec, int dir, const LineGeom& g, const FftDesc& f, const void* in, void* out,
+                            hipStream_t s);
+hipError_t launch_row_inverse(int prec, const LineGeom& g, const FftDesc& f, const RowEpi& e, const void* in,
+                              hipStream_t s);
+hipError_t launch_pair_forward(int prec, const LineGeom& g, const FftDesc& f, const PairLoad& p, hipStream_t s);
+hipError_t launch_bin_pass(int prec, const LineGeom& g, const FftDesc& f, const BinArgs& b, const void* in,
+                           hipStream_t s);
+hipError_t launch_bin_reduce(const double* partials, int64_t nitems, int64_t groups, int nb, int64_t count,
+                             const int64_t* nmodes, double norm, int scale_kind, const unsigned long long* ntot_u,
+                             const int64_t* ntot_s, double ncells, double* pk, uint32_t* flags, hipStream_t s);
+hipError_t launch_lognormal_poisson(int prec, const void* fields, int64_t count, int64_t ncells, double s2half,
+                                    double nbar, const float* mask, uint32_t k0, uint32_t k1, uint32_t rid,
+                                    uint64_t first_real, void* delta, int32_t* counts, unsigned long long* ntot,
+                                    uint32_t* flags, hipStream_t s);
+hipError_t launch_count_totals(const int32_t* counts, int64_t count, int64_t ncells, unsigned long long* ntot,
+                               hipStream_t s);
+hipError_t launch_copy_ntot(const unsigned long long* src, int64_t* dst, int64_t n, hipStream_t s);
+hipError_t launch_covariance(const double* pk, int64_t count, int nb, double* cov, double* cnorm, hipStream_t s);
+hipError_t launch_debug_philox(uint32_t k0, uint32_t k1, const uint32_t* ctr, int64_t n, uint32_t* out,
+                               hipStream_t s);
+hipError_t launch_debug_noise(int prec, const NoiseArgs& n, uint64_t pair, int64_t cells, void* out, hipStream_t s);
+hipError_t launch_zero_u64(unsigned long long* p, int64_t n, hipStream_t s);
+
+}  // namespace ce

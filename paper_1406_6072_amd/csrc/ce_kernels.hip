@@ -1,0 +1,955 @@
+// gfx950 kernels of the circulant-embedding generator.
+//
+// Every multi-dimensional FFT is a sequence of line passes.  A pass loads R
+// lines into LDS (coalesced: rows are contiguous, strided lines are read R
+// consecutive lines at a time), runs the in-place Stockham stages, and writes
+// only the outputs that are kept.  The inverse transform of the embedding is
+// pruned per axis to the survey half (Sec. 2: only the restriction to the
+// survey is used); the first pass synthesises the noise in its prologue and
+// the last pass crops / exponentiates / samples in its epilogue.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+
+#include "ce_device.hpp"
+#include "ce_internal.hpp"
+
+namespace ce {
+
+// ---------------------------------------------------------------------------
+// helpers
+
+struct PassPos {
+  int64_t item, grp, line0;
+  int nl;
+};
+
+__device__ __forceinline__ PassPos pass_pos(const LineGeom& g) {
+  const int64_t t = xcd_tile((int64_t)blockIdx.x, (int64_t)gridDim.x);
+  PassPos p;
+  p.item = t / g.groups_per_item;
+  p.grp = t - p.item * g.groups_per_item;
+  p.line0 = p.grp * g.R;
+  const int64_t nlines = g.A * g.B;
+  const int64_t left = nlines - p.line0;
+  p.nl = (int)(left < g.R ? left : g.R);
+  return p;
+}
+
+template <typename T>
+__device__ __forceinline__ cpx<T>* lds_lines() {
+  extern __shared__ __align__(16) unsigned char ce_smem[];
+  return reinterpret_cast<cpx<T>*>(ce_smem);
+}
+
+// Load nl lines of length L (complex) into LDS.
+template <typename T>
+__device__ __forceinline__ void load_lines(cpx<T>* lds, const cpx<T>* __restrict__ in, const LineGeom& g,
+                                           const PassPos& pp) {
+  const cpx<T>* base = in + pp.item * g.in_item;
+  const int L = g.L;
+  const int tid = threadIdx.x, nthr = blockDim.x;
+  if (g.B == 1) {
+    const int r = tid / g.nlanes, lane = tid - r * g.nlanes;
+    if (r < pp.nl) {
+      const cpx<T>* src = base + (pp.line0 + r) * (int64_t)L;
+      cpx<T>* dst = lds + r * g.lpitch;
+      for (int i = lane; i < L; i += g.nlanes) dst[pidx(i)] = src[i];
+    }
+  } else {
+    const int R = g.R;
+    const int r = tid % R, c0 = tid / R, step = nthr / R;
+    if (r < pp.nl) {
+      const int64_t ln = pp.line0 + r;
+      const int64_t a = ln / g.B, b = ln - a * g.B;
+      const cpx<T>* src = base + a * (int64_t)L * g.B + b;
+      cpx<T>* dst = lds + r * g.lpitch;
+      for (int i = c0; i < L; i += step) dst[pidx(i)] = src[(int64_t)i * g.B];
+    }
+  }
+}
+
+// Store the first K elements of each LDS line.
+template <typename T>
+__device__ __forceinline__ void store_lines(const cpx<T>* lds, cpx<T>* __restrict__ out, const LineGeom& g,
+                                            const PassPos& pp) {
+  cpx<T>* base = out + pp.item * g.out_item;
+  const int K = g.K;
+  const int tid = threadIdx.x, nthr = blockDim.x;
+  if (g.B == 1) {
+    const int r = tid / g.nlanes, lane = tid - r * g.nlanes;
+    if (r < pp.nl) {
+      cpx<T>* dst = base + (pp.line0 + r) * (int64_t)K;
+      const cpx<T>* src = lds + r * g.lpitch;
+      for (int i = lane; i < K; i += g.nlanes) dst[i] = src[pidx(i)];
+    }
+  } else {
+    const int R = g.R;
+    const int r = tid % R, c0 = tid / R, step = nthr / R;
+    if (r < pp.nl) {
+      const int64_t ln = pp.line0 + r;
+      const int64_t a = ln / g.B, b = ln - a * g.B;
+      cpx<T>* dst = base + a * (int64_t)K * g.B + b;
+      const cpx<T>* src = lds + r * g.lpitch;
+      for (int i = c0; i < K; i += step) dst[(int64_t)i * g.B] = src[pidx(i)];
+    }
+  }
+}
+
+__device__ __forceinline__ int mirror(int q, int M) { return q <= M - q ? q : M - q; }
+
+// LDS buffers of line r: a (always), b (ping-pong kernels only, after all a buffers).
+template <typename T>
+__device__ __forceinline__ cpx<T>* buf_a(cpx<T>* lds, const LineGeom& g, int r) { return lds + r * g.lpitch; }
+template <typename T>
+__device__ __forceinline__ cpx<T>* buf_b(cpx<T>* lds, const LineGeom& g, int r) {
+  return lds + (g.R + r) * g.lpitch;
+}
+// Base of the buffer set that holds the result after an FFT of f.
+template <typename T, bool MIX>
+__device__ __forceinline__ cpx<T>* result_base(cpx<T>* lds, const LineGeom& g, const FftDesc& f) {
+  return (MIX && (f.nst & 1)) ? lds + g.R * g.lpitch : lds;
+}
+
+// ---------------------------------------------------------------------------
+// Poisson sampling by FP64 chunked inversion (no contraction: every step is a
+// separately rounded IEEE operation, so an FP64 reference reproduces it).
+
+constexpr int kMaxPoissonSteps = 4096;
+constexpr double kChunkMean = 64.0;
+constexpr double kMaxMu = 6.7108864e7;  // 2^20 chunks
+
+__device__ __forceinline__ int poisson_chunk(double u, double m, uint32_t* flags) {
+  double p = exp(-m);
+  double F = p;
+  int k = 0;
+  while (u > F && p > 0.0) {
+    ++k;
+    p = __ddiv_rn(__dmul_rn(p, m), (double)k);
+    F = __dadd_rn(F, p);
+    if (k >= kMaxPoissonSteps) {
+      atomicOr(flags, 1u);
+      break;
+    }
+  }
+  return k;
+}
+
+__device__ __forceinline__ int chunk_count(double mu) {
+  return mu > 0.0 ? (int)ceil(mu * (1.0 / kChunkMean)) : 0;
+}
+
+__device__ __forceinline__ double chunk_mean(double mu, int c, int K) {
+  return c == K - 1 ? __dsub_rn(mu, kChunkMean * (double)(K - 1)) : kChunkMean;
+}
+
+// Counts of the two realizations of a pair at one cell; counter (cell, pair, rid, 1 + chunk).
+__device__ __forceinline__ void poisson_pair(double mua, double mub, bool has_b, uint32_t cell, uint32_t pair,
+                                             uint32_t rid, uint32_t k0, uint32_t k1, uint32_t* flags, int& na,
+                                             int& nb) {
+  na = 0;
+  nb = 0;
+  if (!(mua <= kMaxMu) || (has_b && !(mub <= kMaxMu))) {
+    atomicOr(flags, 2u);
+    na = -1;
+    nb = -1;
+    return;
+  }
+  const int Ka = chunk_count(mua);
+  const int Kb = has_b ? chunk_count(mub) : 0;
+  const int Kmax = Ka > Kb ? Ka : Kb;
+  for (int c = 0; c < Kmax; ++c) {
+    const Words4 w = philox4x32_10(cell, pair, rid, 1u + (uint32_t)c, k0, k1);
+    if (c < Ka) na += poisson_chunk(unit52(w.x0, w.x1), chunk_mean(mua, c, Ka), flags);
+    if (c < Kb) nb += poisson_chunk(unit52(w.x2, w.x3), chunk_mean(mub, c, Kb), flags);
+  }
+}
+
+template <typename T>
+__device__ __forceinline__ T lognormal_delta(T g, T s2half);
+template <>
+__device__ __forceinline__ float lognormal_delta<float>(float g, float s2half) {
+  return expf(g - s2half) - 1.0f;
+}
+template <>
+__device__ __forceinline__ double lognormal_delta<double>(double g, double s2half) {
+  return exp(g - s2half) - 1.0;
+}
+
+// mu = (nbar f) (1 + delta) from delta as stored
+__device__ __forceinline__ double intensity(double nbar, double f, double delta) {
+  return __dmul_rn(__dmul_rn(nbar, f), __dadd_rn(1.0, delta));
+}
+
+// ---------------------------------------------------------------------------
+// Plan kernels (FP64)
+
+__global__ void k_lag_octant(int ndim, int32_t O0, int32_t O1, int32_t O2, double h0, double h1, double h2,
+                             int kind, double p0, double p1, double p2, double p3, double* __restrict__ out) {
+  const int64_t n = (int64_t)O0 * O1 * O2;
+  for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < n;
+       idx += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t l2 = idx % O2, t = idx / O2;
+    const int64_t l1 = t % O1, l0 = t / O1;
+    const double x0 = h0 * (double)l0, x1 = h1 * (double)l1, x2 = h2 * (double)l2;
+    double rr = x0 * x0;
+    if (ndim > 1) rr += x1 * x1;
+    if (ndim > 2) rr += x2 * x2;
+    const double r = sqrt(rr);
+    double v;
+    if (kind == 1) {
+      v = p0 * exp(-r / p1);
+    } else {
+      v = p0 * pow(1.0 + r / p1, -p2);
+      if (p3 > 0) v *= exp(-r / p3);
+    }
+    out[idx] = v;
+  }
+}
+
+// DCT-I along one axis of the lag octant via a length-M complex FFT of the even
+// extension e(m) = c(min(m, M - m)); keeps Re of outputs q in [0, M/2].
+template <bool MIX>
+__global__ void __launch_bounds__(512) k_dct_axis(LineGeom g, FftDesc f, DctArgs d) {
+  cpx<double>* lds = lds_lines<double>();
+  const PassPos pp = pass_pos(g);
+  const int Od = d.M / 2 + 1;
+  const int tid = threadIdx.x, nthr = blockDim.x;
+  {
+    const int R = g.R;
+    const int r = tid % R, c0 = tid / R, step = nthr / R;
+    if (r < pp.nl) {
+      const int64_t ln = pp.line0 + r;
+      const int64_t a = ln / g.B, b = ln - a * g.B;
+      const double* src = d.in + a * (int64_t)Od * g.B + b;
+      cpx<double>* dst = lds + r * g.lpitch;
+      for (int i = c0; i < d.M; i += step) dst[pidx(i)] = {src[(int64_t)mirror(i, d.M) * g.B], 0.0};
+    }
+  }
+  __syncthreads();
+  const int r = tid / g.nlanes, lane = tid - r * g.nlanes;
+  const bool active = r < pp.nl;
+  line_fft<double, -1, MIX>(buf_a(lds, g, r), buf_b(lds, g, r), f, lane, g.nlanes, active, Od);
+  const cpx<double>* res = result_base<double, MIX>(lds, g, f);
+  {
+    const int R = g.R;
+    const int rr = tid % R, c0 = tid / R, step = nthr / R;
+    if (rr < pp.nl) {
+      const int64_t ln = pp.line0 + rr;
+      const int64_t a = ln / g.B, b = ln - a * g.B;
+      double* dst = d.out + a * (int64_t)Od * g.B + b;
+      const cpx<double>* src = res + rr * g.lpitch;
+      for (int i = c0; i < Od; i += step) dst[(int64_t)i * g.B] = src[pidx(i)].x;
+    }
+  }
+}
+
+// min / max of the eigenvalue octant per block; negatives counted with their
+// multiplicity on the full grid (2 per axis unless q_i is 0 or N_i).
+__global__ void k_lambda_stats(const double* __restrict__ lam, int ndim, int32_t O0, int32_t O1, int32_t O2,
+                               int64_t n, double* __restrict__ stats, unsigned long long* __restrict__ nneg) {
+  __shared__ double smin[256], smax[256];
+  __shared__ unsigned long long sneg;
+  if (threadIdx.x == 0) sneg = 0;
+  __syncthreads();
+  double mn = INFINITY, mx = -INFINITY;
+  unsigned long long neg = 0;
+  for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < n;
+       idx += (int64_t)gridDim.x * blockDim.x) {
+    const double v = lam[idx];
+    mn = fmin(mn, v);
+    mx = fmax(mx, v);
+    if (v < 0) {
+      const int64_t l2 = idx % O2, t = idx / O2;
+      const int64_t l1 = t % O1, l0 = t / O1;
+      unsigned long long m = (l0 == 0 || l0 == O0 - 1) ? 1 : 2;
+      if (ndim > 1) m *= (l1 == 0 || l1 == O1 - 1) ? 1 : 2;
+      if (ndim > 2) m *= (l2 == 0 || l2 == O2 - 1) ? 1 : 2;
+      neg += m;
+    }
+  }
+  smin[threadIdx.x] = mn;
+  smax[threadIdx.x] = mx;
+  if (neg) atomicAdd(&sneg, neg);
+  __syncthreads();
+  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) {
+      smin[threadIdx.x] = fmin(smin[threadIdx.x], smin[threadIdx.x + s]);
+      smax[threadIdx.x] = fmax(smax[threadIdx.x], smax[threadIdx.x + s]);
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    stats[2 * blockIdx.x] = smin[0];
+    stats[2 * blockIdx.x + 1] = smax[0];
+    if (sneg) atomicAdd(nneg, sneg);
+  }
+}
+
+template <typename T>
+__global__ void k_sqrt_table(const double* __restrict__ lam, int64_t n, double inv_cells, T* __restrict__ out) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const double v = lam[i];
+    out[i] = (T)sqrt((v > 0.0 ? v : 0.0) * inv_cells);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// First inverse pass: noise synthesised in the prologue (Sec. 2, eq. Papos2),
+// lines along axis 0 of the embedding; cells 2p and 2p+1 share one Philox call
+// and lie on adjacent lines.
+
+template <typename T>
+__device__ __forceinline__ T sq_at(const T* __restrict__ sq, const NoiseArgs& n, int q0, int64_t b) {
+  int64_t o = mirror(q0, n.M[0]);
+  if (n.ndim == 2) {
+    o = o * n.O[1] + mirror((int)b, n.M[1]);
+  } else {
+    const int q1 = (int)(b / n.M[2]), q2 = (int)(b - (int64_t)q1 * n.M[2]);
+    o = (o * n.O[1] + mirror(q1, n.M[1])) * n.O[2] + mirror(q2, n.M[2]);
+  }
+  return sq[o];
+}
+
+template <typename T, bool MIX>
+__global__ void __launch_bounds__(512) k_noise_pass(LineGeom g, FftDesc f, NoiseArgs n, cpx<T>* __restrict__ out) {
+  cpx<T>* lds = lds_lines<T>();
+  const PassPos pp = pass_pos(g);
+  const int L = g.L;
+  const int tid = threadIdx.x, nthr = blockDim.x;
+  const T* __restrict__ sq = static_cast<const T*>(n.sq);
+  const uint32_t pair = (uint32_t)(n.first_pair + pp.item);
+  {
+    const int H = g.R / 2;  // line pairs
+    const int rp = tid % H, c0 = tid / H, step = nthr / H;
+    if (2 * rp < pp.nl) {
+      const int64_t b = pp.line0 + 2 * rp;  // even line id = flattened index over axes 1..d-1
+      cpx<T>* d0 = lds + (2 * rp) * g.lpitch;
+      cpx<T>* d1 = d0 + g.lpitch;
+      for (int i = c0; i < L; i += step) {
+        const uint64_t cell = (uint64_t)i * (uint64_t)g.B + (uint64_t)b;
+        const Words4 w = philox4x32_10((uint32_t)(cell >> 1), pair, n.rid, 0u, n.k0, n.k1);
+        const cpx<T> e0 = normal_pair<T>(w.x0, w.x1);
+        const cpx<T> e1 = normal_pair<T>(w.x2, w.x3);
+        const T s0 = sq_at(sq, n, i, b), s1 = sq_at(sq, n, i, b + 1);
+        d0[pidx(i)] = c_scale(e0, s0);
+        d1[pidx(i)] = c_scale(e1, s1);
+      }
+    }
+  }
+  __syncthreads();
+  const int r = tid / g.nlanes, lane = tid - r * g.nlanes;
+  line_fft<T, +1, MIX>(buf_a(lds, g, r), buf_b(lds, g, r), f, lane, g.nlanes, r < pp.nl, g.K);
+  store_lines(result_base<T, MIX>(lds, g, f), out, g, pp);
+}
+
+// Generic complex line pass (inner axes of 3-D transforms), pruned to K outputs.
+// In place is allowed: a group reads all its lines before writing them.
+template <typename T, int S, bool MIX>
+__global__ void __launch_bounds__(512) k_line_pass(LineGeom g, FftDesc f, const cpx<T>* in, cpx<T>* out) {
+  cpx<T>* lds = lds_lines<T>();
+  const PassPos pp = pass_pos(g);
+  load_lines(lds, in, g, pp);
+  __syncthreads();
+  const int r = threadIdx.x / g.nlanes, lane = threadIdx.x - r * g.nlanes;
+  line_fft<T, S, MIX>(buf_a(lds, g, r), buf_b(lds, g, r), f, lane, g.nlanes, r < pp.nl, g.K);
+  store_lines(result_base<T, MIX>(lds, g, f), out, g, pp);
+}
+
+// ---------------------------------------------------------------------------
+// Forward transform of a packed pair row (a + i b) followed by the Hermitian
+// separation F_a(k) = (G(k) + conj G(-k))/2, F_b(k) = (G(k) - conj G(-k))/(2i)
+// for k in [0, K/2]; row written as [F_a(0..K/2) | F_b(0..K/2)].
+template <typename T, bool MIX>
+__device__ __forceinline__ void forward_separate(cpx<T>* line, cpx<T>* other, const FftDesc& fwd, int lane,
+                                                 int nlanes, bool active, cpx<T>* __restrict__ Hrow) {
+  line = line_fft<T, -1, MIX>(line, other, fwd, lane, nlanes, active, fwd.L);
+  if (active) {
+    const int K = fwd.L, Kh = K / 2 + 1;
+    for (int c = lane; c < 2 * Kh; c += nlanes) {
+      const int s = c >= Kh, k = c - s * Kh;
+      const cpx<T> gk = line[pidx(k)];
+      const cpx<T> gm = line[pidx(k ? K - k : 0)];
+      cpx<T> v;
+      if (!s) {
+        v = {(gk.x + gm.x) * T(0.5), (gk.y - gm.y) * T(0.5)};
+      } else {
+        // (gk - conj gm) / (2 i)
+        v = {(gk.y + gm.y) * T(0.5), -(gk.x - gm.x) * T(0.5)};
+      }
+      Hrow[c] = v;
+    }
+  }
+}
+
+// Last inverse pass: rows along the last axis, pruned to the survey, with the
+// crop epilogue (Sec. 2) and optionally the lognormal / Poisson step (Sec. 3.1)
+// and the first forward transform of the counts (Sec. 3.2).
+template <typename T, bool MIX>
+__global__ void __launch_bounds__(512) k_row_inverse(LineGeom g, FftDesc f, RowEpi e, const cpx<T>* in) {
+  cpx<T>* lds = lds_lines<T>();
+  __shared__ unsigned long long tot[2];
+  const PassPos pp = pass_pos(g);
+  if (threadIdx.x < 2) tot[threadIdx.x] = 0;
+  load_lines(lds, in, g, pp);
+  __syncthreads();
+  const int r = threadIdx.x / g.nlanes, lane = threadIdx.x - r * g.nlanes;
+  const bool active = r < pp.nl;
+  cpx<T>* line = line_fft<T, +1, MIX>(buf_a(lds, g, r), buf_b(lds, g, r), f, lane, g.nlanes, active, g.K);
+  cpx<T>* other = (line == buf_a(lds, g, r)) ? buf_b(lds, g, r) : buf_a(lds, g, r);
+
+  const int K = g.K;
+  const int64_t row = pp.line0 + r;
+  const int64_t ra = e.real_off + 2 * pp.item;  // local realization of the real part
+  const bool has_b = ra + 1 < e.count;
+  if (e.mode == 1) {
+    if (active) {
+      T* fa = static_cast<T*>(e.fields) + ra * e.ncells + row * K;
+      T* fb = fa + e.ncells;
+      for (int i = lane; i < K; i += g.nlanes) {
+        const cpx<T> z = line[pidx(i)];
+        fa[i] = z.x;
+        if (has_b) fb[i] = z.y;
+      }
+    }
+    return;
+  }
+  // fused epilogue
+  unsigned long long sa = 0, sb = 0;
+  if (active) {
+    const uint32_t pair = (uint32_t)(e.first_pair + pp.item);
+    const T s2h = (T)e.s2half;
+    T* fa = e.fields ? static_cast<T*>(e.fields) + ra * e.ncells + row * K : nullptr;
+    T* da = e.delta ? static_cast<T*>(e.delta) + ra * e.ncells + row * K : nullptr;
+    int32_t* ca = e.counts ? e.counts + ra * e.ncells + row * K : nullptr;
+    for (int i = lane; i < K; i += g.nlanes) {
+      const cpx<T> z = line[pidx(i)];
+      const T dla = lognormal_delta<T>(z.x, s2h);
+      const T dlb = lognormal_delta<T>(z.y, s2h);
+      const double mua = intensity(e.nbar, 1.0, (double)dla);
+      const double mub = intensity(e.nbar, 1.0, (double)dlb);
+      int na, nb;
+      poisson_pair(mua, mub, has_b, (uint32_t)(row * K + i), pair, e.rid, e.k0, e.k1, e.flags, na, nb);
+      if (fa) {
+        fa[i] = z.x;
+        if (has_b) fa[i + e.ncells] = z.y;
+      }
+      if (da) {
+        da[i] = dla;
+        if (has_b) da[i + e.ncells] = dlb;
+      }
+      if (ca) {
+        ca[i] = na;
+        if (has_b) ca[i + e.ncells] = nb;
+      }
+      sa += (unsigned long long)na;
+      sb += (unsigned long long)nb;
+      line[pidx(i)] = {(T)na, (T)nb};
+    }
+  }
+  if (sa) atomicAdd(&tot[0], sa);
+  if (sb) atomicAdd(&tot[1], sb);
+  __syncthreads();
+  if (threadIdx.x == 0 && tot[0]) atomicAdd(&e.ntot[ra], tot[0]);
+  if (threadIdx.x == 1 && tot[1] && has_b) atomicAdd(&e.ntot[ra + 1], tot[1]);
+  cpx<T>* Hrow = static_cast<cpx<T>*>(e.H) + pp.item * e.H_item + row * (int64_t)(2 * (K / 2 + 1));
+  forward_separate<T, MIX>(line, other, e.fwd, lane, g.nlanes, active, Hrow);
+}
+
+// Standalone spectrum, first pass: rows of two maps packed as a + i b (the
+// contrast delta_g for counts, Sec. 3.2 eq. Estim), forward transform, separation.
+template <typename T, bool MIX>
+__global__ void __launch_bounds__(512) k_pair_forward(LineGeom g, FftDesc f, PairLoad p) {
+  cpx<T>* lds = lds_lines<T>();
+  const PassPos pp = pass_pos(g);
+  const int K = f.L;
+  const int r = threadIdx.x / g.nlanes, lane = threadIdx.x - r * g.nlanes;
+  const bool active = r < pp.nl;
+  cpx<T>* line = buf_a(lds, g, r);
+  const int64_t row = pp.line0 + r;
+  const int64_t ma = 2 * pp.item;
+  const bool has_b = ma + 1 < p.count;
+  if (active) {
+    if (p.kind == 0) {
+      const T* a = static_cast<const T*>(p.maps) + ma * p.ncells + row * K;
+      for (int i = lane; i < K; i += g.nlanes) line[pidx(i)] = {a[i], has_b ? a[i + p.ncells] : T(0)};
+    } else {
+      const int32_t* a = static_cast<const int32_t*>(p.maps) + ma * p.ncells + row * K;
+      const double nha = (double)p.ntot[ma] / p.fsum;
+      const double nhb = has_b ? (double)p.ntot[ma + 1] / p.fsum : 1.0;
+      for (int i = lane; i < K; i += g.nlanes) {
+        const double f = p.mask ? (double)p.mask[row * K + i] : 1.0;
+        double va = 0.0, vb = 0.0;
+        if (f != 0.0) {
+          va = ((double)a[i] / f - nha) / nha;
+          if (has_b) vb = ((double)a[i + p.ncells] / f - nhb) / nhb;
+        }
+        line[pidx(i)] = {(T)va, (T)vb};
+      }
+    }
+  }
+  __syncthreads();
+  cpx<T>* Hrow = static_cast<cpx<T>*>(p.H) + pp.item * p.H_item + row * (int64_t)(2 * (K / 2 + 1));
+  forward_separate<T, MIX>(line, buf_b(lds, g, r), f, lane, g.nlanes, active, Hrow);
+}
+
+// ---------------------------------------------------------------------------
+// Last forward pass with the shell sums of eq. Def spec.  Line b of the
+// separated spectra holds (k_1 [3-D], s, k_last) with k_last in [0, N/2]; after
+// the transform along axis 0 each (line, shell) task sums |F|^2 over the k_0
+// range of that shell (exact integer bounds), and the lines are combined per
+// (realization, shell) in a fixed order: the sums are bitwise reproducible.
+
+__device__ __forceinline__ int64_t isqrt64(int64_t v) {
+  if (v <= 0) return 0;
+  int64_t s = (int64_t)sqrt((double)v);
+  while (s * s > v) --s;
+  while ((s + 1) * (s + 1) <= v) ++s;
+  return s;
+}
+
+template <typename T, bool MIX>
+__global__ void __launch_bounds__(512) k_bin_pass(LineGeom g, FftDesc f, BinArgs bn, const cpx<T>* in) {
+  cpx<T>* lds = lds_lines<T>();
+  const PassPos pp = pass_pos(g);
+  double* part = reinterpret_cast<double*>(lds + g.nbuf * g.R * g.lpitch);  // [R][nb]
+  load_lines(lds, in, g, pp);
+  __syncthreads();
+  const int r = threadIdx.x / g.nlanes, lane = threadIdx.x - r * g.nlanes;
+  line_fft<T, -1, MIX>(buf_a(lds, g, r), buf_b(lds, g, r), f, lane, g.nlanes, r < pp.nl, f.L);
+  const cpx<T>* res = result_base<T, MIX>(lds, g, f);
+
+  const int N = bn.N, Nh = N / 2, nb = bn.nb, W = bn.W, Kh = Nh + 1;
+  const int64_t Tq = 4ll * nb * nb;
+  for (int task = threadIdx.x; task < g.R * nb; task += blockDim.x) {
+    const int lr = task / nb, b = task - lr * nb;
+    double acc = 0.0;
+    if (lr < pp.nl) {
+      const int64_t ln = pp.line0 + lr;
+      const int kl = (int)(ln % W);
+      const int s = kl >= Kh;
+      const int kz = kl - s * Kh;
+      int64_t p2 = (int64_t)kz * kz;
+      if (bn.ndim == 3) {
+        int k1 = (int)(ln / W);
+        if (k1 > Nh) k1 -= N;
+        p2 += (int64_t)k1 * k1;
+      }
+      const int64_t D0 = (int64_t)b * N * ((int64_t)b * N);
+      const int64_t D1 = (int64_t)(b + 1) * N * ((int64_t)(b + 1) * N);
+      const int64_t top = D1 - Tq * p2;
+      if (top >= 0) {
+        int64_t hi = isqrt64(top / Tq);
+        if (hi > Nh) hi = Nh;
+        const int64_t low = D0 - Tq * p2;
+        const int64_t lo = low >= 0 ? isqrt64(low / Tq) + 1 : 0;
+        const cpx<T>* line = res + lr * g.lpitch;
+        for (int64_t a = lo; a <= hi; ++a) {
+          const cpx<T> v = line[pidx((int)a)];
+          acc += (double)v.x * (double)v.x + (double)v.y * (double)v.y;
+          if (a != 0 && a != Nh) {
+            const cpx<T> u = line[pidx(N - (int)a)];
+            acc += (double)u.x * (double)u.x + (double)u.y * (double)u.y;
+          }
+        }
+        if (kz != 0 && kz != Nh) acc *= 2.0;
+      }
+    }
+    part[task] = acc;
+  }
+  __syncthreads();
+  for (int t = threadIdx.x; t < 2 * nb; t += blockDim.x) {
+    const int s = t / nb, b = t - s * nb;
+    double acc = 0.0;
+    for (int lr = 0; lr < pp.nl; ++lr) {
+      const int kl = (int)((pp.line0 + lr) % W);
+      if ((kl >= Kh) == s) acc += part[lr * nb + b];
+    }
+    bn.partials[((pp.item * g.groups_per_item + pp.grp) * 2 + s) * nb + b] = acc;
+  }
+}
+
+// pk[r][b] = norm * scale_r * sum_groups partial / N_b
+__global__ void k_bin_reduce(const double* __restrict__ partials, int64_t nitems, int64_t groups, int nb,
+                             int64_t count, const int64_t* __restrict__ nmodes, double norm, int scale_kind,
+                             const unsigned long long* __restrict__ ntot, double ncells, double* __restrict__ pk,
+                             uint32_t* flags) {
+  const int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (idx >= nitems * 2 * nb) return;
+  const int b = (int)(idx % nb);
+  const int64_t rs = idx / nb;  // 2 * item + s
+  if (rs >= count) return;
+  const int64_t item = rs / 2, s = rs - 2 * item;
+  double acc = 0.0;
+  for (int64_t gidx = 0; gidx < groups; ++gidx) acc += partials[((item * groups + gidx) * 2 + s) * nb + b];
+  double scale = 1.0;
+  if (scale_kind == 1) {
+    const double nt = (double)ntot[rs];
+    if (nt == 0.0) atomicOr(flags, 4u);
+    const double nhat = nt / ncells;
+    scale = 1.0 / (nhat * nhat);
+  }
+  pk[rs * nb + b] = norm * scale * acc / (double)nmodes[b];
+}
+
+__global__ void k_covariance(const double* __restrict__ pk, int64_t R, int nb, double* __restrict__ cov,
+                             double* __restrict__ cnorm) {
+  const int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (idx >= (int64_t)nb * nb) return;
+  const int a = (int)(idx / nb), b = (int)(idx % nb);
+  double ma = 0.0, mb = 0.0;
+  for (int64_t r = 0; r < R; ++r) {
+    ma += pk[r * nb + a];
+    mb += pk[r * nb + b];
+  }
+  ma /= (double)R;
+  mb /= (double)R;
+  double c = 0.0, s2 = 0.0;
+  for (int64_t r = 0; r < R; ++r) {
+    const double pa = pk[r * nb + a], pb = pk[r * nb + b];
+    c += (pa - ma) * (pb - mb);
+    s2 += pa * pb;
+  }
+  if (cov) cov[idx] = c / (double)(R - 1);
+  if (cnorm) cnorm[idx] = (s2 / (double)R) / (ma * mb) - 1.0;
+}
+
+// ---------------------------------------------------------------------------
+// Standalone lognormal + Poisson (one thread per realization and cell).
+template <typename T>
+__global__ void k_lognormal_poisson(const T* __restrict__ fields, int64_t count, int64_t ncells, double s2half,
+                                    double nbar, const float* __restrict__ mask, uint32_t k0, uint32_t k1,
+                                    uint32_t rid, uint64_t first_real, T* __restrict__ delta,
+                                    int32_t* __restrict__ counts, unsigned long long* __restrict__ ntot,
+                                    uint32_t* flags) {
+  __shared__ unsigned long long acc;
+  const int64_t blocks_per_map = (ncells + blockDim.x - 1) / blockDim.x;
+  const int64_t k = blockIdx.x / blocks_per_map;
+  const int64_t cell = (blockIdx.x - k * blocks_per_map) * blockDim.x + threadIdx.x;
+  if (threadIdx.x == 0) acc = 0;
+  __syncthreads();
+  if (k < count && cell < ncells) {
+    const uint64_t rr = first_real + (uint64_t)k;
+    const T g = fields[k * ncells + cell];
+    const T d = lognormal_delta<T>(g, (T)s2half);
+    const double f = mask ? (double)mask[cell] : 1.0;
+    const double mu = intensity(nbar, f, (double)d);
+    int n = 0;
+    if (!(mu <= kMaxMu)) {
+      atomicOr(flags, 2u);
+      n = -1;
+    } else {
+      const int K = chunk_count(mu);
+      for (int c = 0; c < K; ++c) {
+        const Words4 w = philox4x32_10((uint32_t)cell, (uint32_t)(rr >> 1), rid, 1u + (uint32_t)c, k0, k1);
+        const double u = (rr & 1) ? unit52(w.x2, w.x3) : unit52(w.x0, w.x1);
+        n += poisson_chunk(u, chunk_mean(mu, c, K), flags);
+      }
+    }
+    if (delta) delta[k * ncells + cell] = d;
+    counts[k * ncells + cell] = n;
+    if (n > 0) atomicAdd(&acc, (unsigned long long)n);
+  }
+  __syncthreads();
+  if (threadIdx.x == 0 && acc && ntot) atomicAdd(&ntot[k], acc);
+}
+
+__global__ void k_count_totals(const int32_t* __restrict__ counts, int64_t count, int64_t ncells,
+                               unsigned long long* __restrict__ ntot) {
+  __shared__ unsigned long long acc;
+  const int64_t blocks_per_map = (ncells + blockDim.x - 1) / blockDim.x;
+  const int64_t k = blockIdx.x / blocks_per_map;
+  const int64_t cell = (blockIdx.x - k * blocks_per_map) * blockDim.x + threadIdx.x;
+  if (threadIdx.x == 0) acc = 0;
+  __syncthreads();
+  if (k < count && cell < ncells) {
+    const int32_t v = counts[k * ncells + cell];
+    if (v > 0) atomicAdd(&acc, (unsigned long long)v);
+  }
+  __syncthreads();
+  if (threadIdx.x == 0 && acc) atomicAdd(&ntot[k], acc);
+}
+
+__global__ void k_copy_ntot(const unsigned long long* __restrict__ src, int64_t* __restrict__ dst, int64_t n) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < n) dst[i] = (int64_t)src[i];
+}
+
+__global__ void k_zero_u64(unsigned long long* p, int64_t n) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0;
+}
+
+__global__ void k_debug_philox(uint32_t k0, uint32_t k1, uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
+                               int64_t n, uint32_t* __restrict__ out) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const Words4 w = philox4x32_10(c0 + (uint32_t)i, c1, c2, c3, k0, k1);
+  out[4 * i + 0] = w.x0;
+  out[4 * i + 1] = w.x1;
+  out[4 * i + 2] = w.x2;
+  out[4 * i + 3] = w.x3;
+}
+
+template <typename T>
+__global__ void k_debug_noise(NoiseArgs n, uint32_t pair, int64_t cells, cpx<T>* __restrict__ out) {
+  const int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (2 * p >= cells) return;
+  const Words4 w = philox4x32_10((uint32_t)p, pair, n.rid, 0u, n.k0, n.k1);
+  out[2 * p] = normal_pair<T>(w.x0, w.x1);
+  out[2 * p + 1] = normal_pair<T>(w.x2, w.x3);
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+
+// Workgroups may use more than 64 KB of the 160 KB LDS of a gfx950 CU once the
+// kernel's dynamic-LDS limit is raised.
+#define CE_LAUNCH(kernel, grid, block, lds, stream, ...)                                                     \
+  do {                                                                                                     \
+    if ((lds) > 65536)                                                                                     \
+      (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&kernel),                                    \
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)(lds));                   \
+    hipLaunchKernelGGL(kernel, grid, block, lds, stream, __VA_ARGS__);                                      \
+  } while (0)
+
+static size_t lines_lds_bytes(const LineGeom& g, size_t elem) { return (size_t)g.nbuf * g.R * g.lpitch * elem; }
+
+static dim3 pass_grid(const LineGeom& g) { return dim3((unsigned)(g.nitems * g.groups_per_item)); }
+static dim3 pass_block(const LineGeom& g) {
+  const int t = g.R * g.nlanes;
+  return dim3((unsigned)((t + 63) / 64 * 64));
+}
+
+hipError_t launch_lag_octant(int ndim, const int32_t* O, const double* h, int kind, const double* p, double* out,
+                             hipStream_t s) {
+  const int64_t n = (int64_t)O[0] * O[1] * O[2];
+  const int blocks = (int)((n + 255) / 256 < 65536 ? (n + 255) / 256 : 65536);
+  hipLaunchKernelGGL(k_lag_octant, dim3(blocks), dim3(256), 0, s, ndim, O[0], O[1], O[2], h[0], h[1], h[2], kind,
+                     p[0], p[1], p[2], p[3], out);
+  return hipGetLastError();
+}
+
+hipError_t launch_dct_axis(const LineGeom& g, const FftDesc& f, const DctArgs& a, hipStream_t s) {
+  const size_t lds = lines_lds_bytes(g, sizeof(cpx<double>));
+  bool mix = false;
+  for (int i = 0; i < f.nst; ++i) mix |= (f.rad[i] & (f.rad[i] - 1)) != 0;
+  if (mix != (g.nbuf == 2)) return hipErrorInvalidValue;
+  if (mix)
+    CE_LAUNCH(k_dct_axis<true>, pass_grid(g), pass_block(g), lds, s, g, f, a);
+  else
+    CE_LAUNCH(k_dct_axis<false>, pass_grid(g), pass_block(g), lds, s, g, f, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_lambda_stats(const double* lam, int ndim, const int32_t* O, int64_t n, double* stats,
+                               unsigned long long* nneg, hipStream_t s) {
+  hipLaunchKernelGGL(k_lambda_stats, dim3(256), dim3(256), 0, s, lam, ndim, O[0], O[1], O[2], n, stats, nneg);
+  return hipGetLastError();
+}
+
+hipError_t launch_sqrt_table(const double* lam, int64_t n, double inv_cells, int prec, void* out, hipStream_t s) {
+  const int blocks = (int)((n + 255) / 256 < 65536 ? (n + 255) / 256 : 65536);
+  if (prec == 0)
+    hipLaunchKernelGGL(k_sqrt_table<float>, dim3(blocks), dim3(256), 0, s, lam, n, inv_cells,
+                       static_cast<float*>(out));
+  else
+    hipLaunchKernelGGL(k_sqrt_table<double>, dim3(blocks), dim3(256), 0, s, lam, n, inv_cells,
+                       static_cast<double*>(out));
+  return hipGetLastError();
+}
+
+static bool nbuf_ok(const LineGeom& g, bool mix) { return mix == (g.nbuf == 2); }
+
+static bool is_mixed(const FftDesc& f) {
+  for (int i = 0; i < f.nst; ++i)
+    if (f.rad[i] & (f.rad[i] - 1)) return true;
+  return false;
+}
+
+hipError_t launch_noise_pass(int prec, const LineGeom& g, const FftDesc& f, const NoiseArgs& n, void* out,
+                             hipStream_t s) {
+  const bool mix = is_mixed(f);
+  if (!nbuf_ok(g, mix) || g.R < 2 || (g.R & 1) || (g.B & 1)) return hipErrorInvalidValue;
+  if (prec == 0) {
+    const size_t lds = lines_lds_bytes(g, sizeof(cpx<float>));
+    if (mix)
+      CE_LAUNCH((k_noise_pass<float, true>), pass_grid(g), pass_block(g), lds, s, g, f, n,
+                         static_cast<cpx<float>*>(out));
+    else
+      CE_LAUNCH((k_noise_pass<float, false>), pass_grid(g), pass_block(g), lds, s, g, f, n,
+                         static_cast<cpx<float>*>(out));
+  } else {
+    const size_t lds = lines_lds_bytes(g, sizeof(cpx<double>));
+    if (mix)
+      CE_LAUNCH((k_noise_pass<double, true>), pass_grid(g), pass_block(g), lds, s, g, f, n,
+                         static_cast<cpx<double>*>(out));
+    else
+      CE_LAUNCH((k_noise_pass<double, false>), pass_grid(g), pass_block(g), lds, s, g, f, n,
+                         static_cast<cpx<double>*>(out));
+  }
+  return hipGetLastError();
+}
+
+template <typename T>
+static void line_pass_t(int dir, bool mix, const LineGeom& g, const FftDesc& f, const void* in, void* out,
+                        hipStream_t s) {
+  const size_t lds = lines_lds_bytes(g, sizeof(cpx<T>));
+  const cpx<T>* i = static_cast<const cpx<T>*>(in);
+  cpx<T>* o = static_cast<cpx<T>*>(out);
+  if (dir > 0) {
+    if (mix)
+      CE_LAUNCH((k_line_pass<T, 1, true>), pass_grid(g), pass_block(g), lds, s, g, f, i, o);
+    else
+      CE_LAUNCH((k_line_pass<T, 1, false>), pass_grid(g), pass_block(g), lds, s, g, f, i, o);
+  } else {
+    if (mix)
+      CE_LAUNCH((k_line_pass<T, -1, true>), pass_grid(g), pass_block(g), lds, s, g, f, i, o);
+    else
+      CE_LAUNCH((k_line_pass<T, -1, false>), pass_grid(g), pass_block(g), lds, s, g, f, i, o);
+  }
+}
+
+hipError_t launch_line_pass(int prec, int dir, const LineGeom& g, const FftDesc& f, const void* in, void* out,
+                            hipStream_t s) {
+  const bool mix = is_mixed(f);
+  if (!nbuf_ok(g, mix)) return hipErrorInvalidValue;
+  if (prec == 0)
+    line_pass_t<float>(dir, mix, g, f, in, out, s);
+  else
+    line_pass_t<double>(dir, mix, g, f, in, out, s);
+  return hipGetLastError();
+}
+
+template <typename T>
+static void row_inverse_t(bool mix, const LineGeom& g, const FftDesc& f, const RowEpi& e, const void* in,
+                          hipStream_t s) {
+  const size_t lds = lines_lds_bytes(g, sizeof(cpx<T>));
+  const cpx<T>* i = static_cast<const cpx<T>*>(in);
+  if (mix)
+    CE_LAUNCH((k_row_inverse<T, true>), pass_grid(g), pass_block(g), lds, s, g, f, e, i);
+  else
+    CE_LAUNCH((k_row_inverse<T, false>), pass_grid(g), pass_block(g), lds, s, g, f, e, i);
+}
+
+hipError_t launch_row_inverse(int prec, const LineGeom& g, const FftDesc& f, const RowEpi& e, const void* in,
+                              hipStream_t s) {
+  const bool mix = is_mixed(f) || (e.mode == 2 && is_mixed(e.fwd));
+  if (!nbuf_ok(g, mix)) return hipErrorInvalidValue;
+  if (prec == 0)
+    row_inverse_t<float>(mix, g, f, e, in, s);
+  else
+    row_inverse_t<double>(mix, g, f, e, in, s);
+  return hipGetLastError();
+}
+
+template <typename T>
+static void pair_forward_t(bool mix, const LineGeom& g, const FftDesc& f, const PairLoad& p, hipStream_t s) {
+  const size_t lds = lines_lds_bytes(g, sizeof(cpx<T>));
+  if (mix)
+    CE_LAUNCH((k_pair_forward<T, true>), pass_grid(g), pass_block(g), lds, s, g, f, p);
+  else
+    CE_LAUNCH((k_pair_forward<T, false>), pass_grid(g), pass_block(g), lds, s, g, f, p);
+}
+
+hipError_t launch_pair_forward(int prec, const LineGeom& g, const FftDesc& f, const PairLoad& p, hipStream_t s) {
+  if (!nbuf_ok(g, is_mixed(f))) return hipErrorInvalidValue;
+  if (prec == 0)
+    pair_forward_t<float>(is_mixed(f), g, f, p, s);
+  else
+    pair_forward_t<double>(is_mixed(f), g, f, p, s);
+  return hipGetLastError();
+}
+
+template <typename T>
+static void bin_pass_t(bool mix, const LineGeom& g, const FftDesc& f, const BinArgs& b, const void* in,
+                       hipStream_t s) {
+  const size_t lds = lines_lds_bytes(g, sizeof(cpx<T>)) + (size_t)g.R * b.nb * sizeof(double);
+  const cpx<T>* i = static_cast<const cpx<T>*>(in);
+  if (mix)
+    CE_LAUNCH((k_bin_pass<T, true>), pass_grid(g), pass_block(g), lds, s, g, f, b, i);
+  else
+    CE_LAUNCH((k_bin_pass<T, false>), pass_grid(g), pass_block(g), lds, s, g, f, b, i);
+}
+
+hipError_t launch_bin_pass(int prec, const LineGeom& g, const FftDesc& f, const BinArgs& b, const void* in,
+                           hipStream_t s) {
+  if (!nbuf_ok(g, is_mixed(f))) return hipErrorInvalidValue;
+  if (prec == 0)
+    bin_pass_t<float>(is_mixed(f), g, f, b, in, s);
+  else
+    bin_pass_t<double>(is_mixed(f), g, f, b, in, s);
+  return hipGetLastError();
+}
+
+hipError_t launch_bin_reduce(const double* partials, int64_t nitems, int64_t groups, int nb, int64_t count,
+                             const int64_t* nmodes, double norm, int scale_kind, const unsigned long long* ntot_u,
+                             const int64_t* ntot_s, double ncells, double* pk, uint32_t* flags, hipStream_t s) {
+  (void)ntot_s;
+  const int64_t n = nitems * 2 * nb;
+  hipLaunchKernelGGL(k_bin_reduce, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, partials, nitems, groups, nb,
+                     count, nmodes, norm, scale_kind, ntot_u, ncells, pk, flags);
+  return hipGetLastError();
+}
+
+hipError_t launch_lognormal_poisson(int prec, const void* fields, int64_t count, int64_t ncells, double s2half,
+                                    double nbar, const float* mask, uint32_t k0, uint32_t k1, uint32_t rid,
+                                    uint64_t first_real, void* delta, int32_t* counts, unsigned long long* ntot,
+                                    uint32_t* flags, hipStream_t s) {
+  const int64_t bpm = (ncells + 255) / 256;
+  const dim3 grid((unsigned)(bpm * count));
+  if (prec == 0)
+    hipLaunchKernelGGL(k_lognormal_poisson<float>, grid, dim3(256), 0, s, static_cast<const float*>(fields), count,
+                       ncells, s2half, nbar, mask, k0, k1, rid, first_real, static_cast<float*>(delta), counts, ntot,
+                       flags);
+  else
+    hipLaunchKernelGGL(k_lognormal_poisson<double>, grid, dim3(256), 0, s, static_cast<const double*>(fields),
+                       count, ncells, s2half, nbar, mask, k0, k1, rid, first_real, static_cast<double*>(delta),
+                       counts, ntot, flags);
+  return hipGetLastError();
+}
+
+hipError_t launch_count_totals(const int32_t* counts, int64_t count, int64_t ncells, unsigned long long* ntot,
+                               hipStream_t s) {
+  const int64_t bpm = (ncells + 255) / 256;
+  hipLaunchKernelGGL(k_count_totals, dim3((unsigned)(bpm * count)), dim3(256), 0, s, counts, count, ncells, ntot);
+  return hipGetLastError();
+}
+
+hipError_t launch_copy_ntot(const unsigned long long* src, int64_t* dst, int64_t n, hipStream_t s) {
+  hipLaunchKernelGGL(k_copy_ntot, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, src, dst, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_covariance(const double* pk, int64_t count, int nb, double* cov, double* cnorm, hipStream_t s) {
+  const int64_t n = (int64_t)nb * nb;
+  hipLaunchKernelGGL(k_covariance, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, pk, count, nb, cov, cnorm);
+  return hipGetLastError();
+}
+
+hipError_t launch_debug_philox(uint32_t k0, uint32_t k1, const uint32_t* ctr, int64_t n, uint32_t* out,
+                               hipStream_t s) {
+  hipLaunchKernelGGL(k_debug_philox, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, k0, k1, ctr[0], ctr[1],
+                     ctr[2], ctr[3], n, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_debug_noise(int prec, const NoiseArgs& n, uint64_t pair, int64_t cells, void* out, hipStream_t s) {
+  const int64_t np = cells / 2;
+  const dim3 grid((unsigned)((np + 255) / 256));
+  if (prec == 0)
+    hipLaunchKernelGGL(k_debug_noise<float>, grid, dim3(256), 0, s, n, (uint32_t)pair, cells,
+                       static_cast<cpx<float>*>(out));
+  else
+    hipLaunchKernelGGL(k_debug_noise<double>, grid, dim3(256), 0, s, n, (uint32_t)pair, cells,
+                       static_cast<cpx<double>*>(out));
+  return hipGetLastError();
+}
+
+hipError_t launch_zero_u64(unsigned long long* p, int64_t n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_zero_u64, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p, n);
+  return hipGetLastError();
+}
+
+}  // namespace ce

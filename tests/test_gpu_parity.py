@@ -1,0 +1,324 @@
+"""GPU parity: the HIP library (through the C ABI) against the FP64 oracle on
+identical Philox streams.
+
+Tolerances (relative L2 per realization unless stated):
+  Philox words          bit-exact
+  normals               FP32 1e-6,  FP64 1e-14
+  eigenvalues           1e-12 * lambda_max (absolute)
+  fields                FP32 1e-5,  FP64 1e-12
+  delta (from GPU g)    FP32 1e-5,  FP64 1e-12
+  counts, N_tot         bit-exact (oracle fed the GPU's delta)
+  P(k) per shell        FP32 1e-5,  FP64 1e-12 (oracle fed the GPU's maps)
+  covariance            1e-12 (oracle fed the GPU's spectra)
+"""
+
+import math
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+from oracle import embedding, fields as ofields, lognormal_poisson as olp, philox, pk as opk  # noqa: E402
+
+TOL_FIELD = {0: 1e-5, 1: 1e-12}
+TOL_PK = {0: 1e-5, 1: 1e-12}
+
+
+@pytest.fixture(scope="module")
+def ce():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1406_6072_amd import binding
+    ctx = binding.ctx_create(0)
+    yield binding, ctx
+    binding.ctx_destroy(ctx)
+
+
+def rel(a, b):
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    return float(np.linalg.norm((a - b).ravel()) / max(np.linalg.norm(b.ravel()), 1e-300))
+
+
+def dt(prec):
+    return torch.float64 if prec == 1 else torch.float32
+
+
+def gpu_fields(b, ctx, plan, seed, rid, first, count):
+    out = torch.empty(count * plan.cells, dtype=plan.dtype, device="cuda")
+    b.generate_fields(ctx, plan, seed, rid, first, count, out)
+    torch.cuda.synchronize()
+    return out
+
+
+def test_philox_words_bit_exact(ce):
+    b, _ = ce
+    for seed, ctr in [(0, (0, 0, 0, 0)), (0x0123456789ABCDEF, (5, 7, 9, 11)),
+                      (2 ** 64 - 1, (2 ** 32 - 1000, 1, 2, 3))]:
+        n = 4096
+        out = torch.empty(4 * n, dtype=torch.int32, device="cuda")
+        b.debug_philox(seed, ctr, n, out)
+        torch.cuda.synchronize()
+        got = out.cpu().numpy().view(np.uint32).reshape(n, 4)
+        ref = philox.philox4x32_10(np.uint64(ctr[0]) + np.arange(n, dtype=np.uint64), ctr[1], ctr[2], ctr[3],
+                                   philox.key_from_seed(seed))
+        assert np.array_equal(got, np.stack(ref, axis=1))
+
+
+@pytest.mark.parametrize("prec,tol", [(1, 1e-14), (0, 1e-6)])
+@pytest.mark.parametrize("n", [(12, 10), (6, 8, 4)])
+def test_noise_normals(ce, prec, tol, n):
+    b, ctx = ce
+    xi = dict(kind="exp", sigma2=1.0, a=1.0)
+    plan = b.plan_embedding(ctx, n, (1.0,) * len(n), xi, prec)
+    out = torch.empty(2 * plan.embedding_cells, dtype=plan.dtype, device="cuda")
+    b.debug_noise(plan, 3, 5, 7, out)
+    torch.cuda.synchronize()
+    got = out.cpu().numpy().astype(np.float64)
+    got = (got[0::2] + 1j * got[1::2]).reshape(tuple(2 * x for x in n))
+    ref = ofields.pair_noise(tuple(2 * x for x in n), 3, 5, 7)
+    assert rel(got.view(np.float64), ref.view(np.float64)) <= tol
+    plan.release()
+
+
+PLAN_CASES = [
+    ((64, 64), (1.0, 1.0), dict(kind="exp", sigma2=0.5, a=8.0)),
+    ((24, 20), (1.0, 0.5), dict(kind="powexp", sigma2=1.0, r0=2.0, gamma=1.8, rc=30.0)),
+    ((8, 6, 10), (1.0, 1.0, 1.0), dict(kind="exp", sigma2=0.8, a=1.0)),
+    ((48, 40), (1.0, 1.0), dict(kind="exp", sigma2=1.0, a=3.0)),
+    ((62, 34), (1.0, 1.0), dict(kind="exp", sigma2=1.0, a=2.0)),
+]
+
+
+@pytest.mark.parametrize("n,h,xi", PLAN_CASES)
+def test_plan_eigenvalues(ce, n, h, xi):
+    b, ctx = ce
+    ref = embedding.plan(n, h, xi)
+    plan = b.plan_embedding(ctx, n, h, xi, 1)
+    oct_shape = tuple(x + 1 for x in n)
+    out = torch.empty(int(np.prod(oct_shape)), dtype=torch.float64, device="cuda")
+    b.plan_eigenvalues(plan, out)
+    torch.cuda.synchronize()
+    lam = out.cpu().numpy().reshape(oct_shape)
+    ref_oct = ref["lam"][tuple(slice(0, x + 1) for x in n)]
+    lmax = ref["lambda_max"]
+    # the oracle clamps; compare against its unclamped spectrum
+    raw = embedding.eigenvalues(embedding.lag_table(n, h, xi))[tuple(slice(0, x + 1) for x in n)]
+    assert np.max(np.abs(lam - raw)) <= 1e-12 * lmax
+    assert np.max(np.abs(np.maximum(lam, 0) - ref_oct)) <= 1e-12 * lmax
+    info = plan.info
+    assert abs(info["lambda_max"] - lmax) <= 1e-12 * lmax
+    assert abs(info["lambda_min"] - ref["lambda_min"]) <= 1e-12 * lmax
+    assert info["n_negative"] == ref["n_negative"]
+    assert info["sigma2"] == ref["sigma2"]
+    plan.release()
+
+
+def test_not_psd_rejected(ce):
+    b, ctx = ce
+    n = (32, 32, 32)
+    xi = dict(kind="powexp", sigma2=1.0, r0=10.0, gamma=1.8, rc=0.0)
+    with pytest.raises(embedding.NotPSD) as ref:
+        embedding.plan(n, (1.0,) * 3, xi)
+    with pytest.raises(b.NotPSDError) as err:
+        b.plan_embedding(ctx, n, (1.0,) * 3, xi, 0)
+    lmax = ref.value.info["lambda_max"]
+    assert abs(err.value.info["lambda_min"] - ref.value.info["lambda_min"]) <= 1e-12 * lmax
+    assert err.value.info["n_negative"] == ref.value.info["n_negative"]
+
+
+FIELD_CASES = [
+    # name, n, h, xi, prec, first, count
+    ("small_2d_f64", (64, 64), (1.0, 1.0), dict(kind="exp", sigma2=0.5, a=8.0), 1, 0, 100),
+    ("pow2_2d_f32_odd_count", (256, 256), (1.0, 1.0), dict(kind="powexp", sigma2=1.0, r0=4.0, gamma=1.8, rc=300.0),
+     0, 6, 5),
+    ("rect_2d_f32_mixed", (96, 80), (1.0, 0.5), dict(kind="exp", sigma2=1.0, a=3.0), 0, 0, 4),
+    ("primes_2d_f64", (62, 34), (1.0, 1.0), dict(kind="exp", sigma2=1.0, a=2.0), 1, 2, 3),
+    ("vol_3d_f64", (16, 12, 20), (1.0, 1.0, 1.0), dict(kind="exp", sigma2=0.8, a=1.5), 1, 0, 3),
+    ("vol_3d_f32", (32, 32, 32), (1.0, 1.0, 1.0), dict(kind="powexp", sigma2=2.0, r0=1.5, gamma=1.8, rc=100.0),
+     0, 0, 4),
+]
+
+
+@pytest.mark.parametrize("name,n,h,xi,prec,first,count", FIELD_CASES, ids=[c[0] for c in FIELD_CASES])
+def test_fields_match_oracle(ce, name, n, h, xi, prec, first, count):
+    b, ctx = ce
+    print("case", name, flush=True)
+    ref_plan = embedding.plan(n, h, xi)
+    ref = ofields.generate_fields(ref_plan, 9, 4, first, count)
+    plan = b.plan_embedding(ctx, n, h, xi, prec)
+    got = gpu_fields(b, ctx, plan, 9, 4, first, count).cpu().numpy().reshape((count,) + n)
+    errs = [rel(got[k], ref[k]) for k in range(count)]
+    assert max(errs) <= TOL_FIELD[prec], errs
+    plan.release()
+
+
+@pytest.mark.parametrize("prec", [1, 0])
+@pytest.mark.parametrize("first", [4, 3])
+@pytest.mark.parametrize("masked", [False, True])
+def test_lognormal_poisson_parity(ce, prec, first, masked):
+    b, ctx = ce
+    n, xi, nbar = (64, 64), dict(kind="exp", sigma2=0.5, a=8.0), 5.0
+    plan = b.plan_embedding(ctx, n, (1.0, 1.0), xi, prec)
+    count = 5
+    g = gpu_fields(b, ctx, plan, 1, 2, 0, count)
+    mask = None
+    mask_np = None
+    if masked:
+        rng = np.random.default_rng(0)
+        mask_np = rng.random(n).astype(np.float32)
+        mask_np[mask_np < 0.3] = 0.0
+        mask = torch.from_numpy(mask_np.ravel()).cuda()
+    delta = torch.empty_like(g)
+    counts = torch.empty(count * plan.cells, dtype=torch.int32, device="cuda")
+    ntot = torch.empty(count, dtype=torch.int64, device="cuda")
+    b.lognormal_poisson(ctx, plan, g, count, nbar, mask, 11, 2, first, delta, counts, ntot)
+    torch.cuda.synchronize()
+    assert b.ctx_check(ctx) == 0
+    gh = g.cpu().numpy().astype(np.float64).reshape((count,) + n)
+    dh = delta.cpu().numpy().reshape((count,) + n)
+    ref_delta = olp.lognormal_delta(gh, plan.info["sigma2"])
+    assert max(rel(dh[k], ref_delta[k]) for k in range(count)) <= TOL_FIELD[prec]
+    _, ref_counts, ref_ntot = olp.lognormal_poisson(gh, plan.info["sigma2"], nbar, 11, 2, first,
+                                                    mask=mask_np, delta=dh)
+    assert np.array_equal(counts.cpu().numpy().reshape((count,) + n), ref_counts)
+    assert np.array_equal(ntot.cpu().numpy(), ref_ntot)
+    plan.release()
+
+
+@pytest.mark.parametrize("prec", [1, 0])
+@pytest.mark.parametrize("n,nb", [((64, 64), 32), ((16, 16, 16), 8), ((48, 48), 12)])
+def test_pk_field_parity(ce, prec, n, nb):
+    b, ctx = ce
+    xi = dict(kind="exp", sigma2=1.0, a=2.0)
+    plan = b.plan_embedding(ctx, n, (1.0,) * len(n), xi, prec)
+    count = 5
+    g = gpu_fields(b, ctx, plan, 3, 0, 0, count)
+    out = torch.empty(count * nb, dtype=torch.float64, device="cuda")
+    nm = torch.empty(nb, dtype=torch.int64, device="cuda")
+    km = torch.empty(nb, dtype=torch.float64, device="cuda")
+    b.estimate_pk(ctx, n, (1.0,) * len(n), prec, b.MAP_FIELD, g, count, None, None, nb, out, nm, km)
+    torch.cuda.synchronize()
+    gh = g.cpu().numpy().astype(np.float64).reshape((count,) + n)
+    ref = opk.estimate_pk(gh, 1.0, nb)
+    got = out.cpu().numpy().reshape(count, nb)
+    assert np.max(np.abs(got / ref - 1)) <= TOL_PK[prec]
+    onm, okm = opk.shell_stats(n, 1.0, nb)
+    assert np.array_equal(nm.cpu().numpy(), onm)
+    assert np.allclose(km.cpu().numpy(), okm, rtol=1e-13)
+    plan.release()
+
+
+@pytest.mark.parametrize("prec", [1, 0])
+@pytest.mark.parametrize("masked,given_ntot", [(False, True), (False, False), (True, True)])
+def test_pk_counts_parity(ce, prec, masked, given_ntot):
+    b, ctx = ce
+    n, nb, nbar = (64, 64), 32, 5.0
+    plan = b.plan_embedding(ctx, n, (1.0, 1.0), dict(kind="exp", sigma2=0.5, a=8.0), prec)
+    count = 4
+    g = gpu_fields(b, ctx, plan, 5, 1, 0, count)
+    mask = mask_np = None
+    if masked:
+        mask_np = np.ones(n, dtype=np.float32)
+        mask_np[10:20, 30:50] = 0.0
+        mask_np[40:, :8] = 0.75
+        mask = torch.from_numpy(mask_np.ravel()).cuda()
+    counts = torch.empty(count * plan.cells, dtype=torch.int32, device="cuda")
+    ntot = torch.empty(count, dtype=torch.int64, device="cuda")
+    b.lognormal_poisson(ctx, plan, g, count, nbar, mask, 6, 1, 0, None, counts, ntot)
+    out = torch.empty(count * nb, dtype=torch.float64, device="cuda")
+    b.estimate_pk(ctx, n, (1.0, 1.0), prec, b.MAP_COUNTS_DELTAG, counts, count, ntot if given_ntot else None, mask,
+                  nb, out)
+    torch.cuda.synchronize()
+    ch = counts.cpu().numpy().reshape((count,) + n)
+    ref = opk.estimate_pk(ch, 1.0, nb, kind="counts", ntot=ntot.cpu().numpy(), mask=mask_np)
+    got = out.cpu().numpy().reshape(count, nb)
+    assert np.max(np.abs(got / ref - 1)) <= TOL_PK[prec]
+    plan.release()
+
+
+def test_covariance_parity(ce):
+    b, ctx = ce
+    rng = np.random.default_rng(1)
+    R, nb = 40, 9
+    P = rng.gamma(4.0, 1.0, (R, nb))
+    pk = torch.from_numpy(P.ravel()).cuda()
+    cov = torch.empty(nb * nb, dtype=torch.float64, device="cuda")
+    cn = torch.empty(nb * nb, dtype=torch.float64, device="cuda")
+    b.pk_covariance(ctx, pk, R, nb, cov, cn)
+    torch.cuda.synchronize()
+    rc, rn = opk.covariance(P)
+    assert rel(cov.cpu().numpy(), rc.ravel()) <= 1e-12
+    assert rel(cn.cpu().numpy(), rn.ravel()) <= 1e-12
+
+
+PIPE_CASES = [((64, 64), dict(kind="exp", sigma2=0.5, a=8.0), 1, 32, 7),
+              ((128, 128), dict(kind="powexp", sigma2=1.0, r0=4.0, gamma=1.8, rc=300.0), 0, 32, 6),
+              ((16, 16, 16), dict(kind="exp", sigma2=0.8, a=1.5), 0, 8, 3),
+              ((48, 48), dict(kind="exp", sigma2=1.0, a=3.0), 1, 12, 4)]
+
+
+@pytest.mark.parametrize("n,xi,prec,nb,count", PIPE_CASES)
+def test_pipeline_matches_unfused_and_oracle(ce, n, xi, prec, nb, count):
+    b, ctx = ce
+    print("pipeline case", n, prec, flush=True)
+    nbar, seed, rid, first = 5.0, 21, 3, 2
+    plan = b.plan_embedding(ctx, n, (1.0,) * len(n), xi, prec)
+    cells = plan.cells
+    f = torch.empty(count * cells, dtype=plan.dtype, device="cuda")
+    d = torch.empty_like(f)
+    c = torch.empty(count * cells, dtype=torch.int32, device="cuda")
+    nt = torch.empty(count, dtype=torch.int64, device="cuda")
+    p = torch.empty(count * nb, dtype=torch.float64, device="cuda")
+    cov = torch.empty(nb * nb, dtype=torch.float64, device="cuda")
+    cn = torch.empty(nb * nb, dtype=torch.float64, device="cuda")
+    b.pipeline_run(ctx, plan, seed, rid, first, count, nbar, nb, p, f, d, c, nt, cov, cn)
+    torch.cuda.synchronize()
+    assert b.ctx_check(ctx) == 0
+    # unfused calls on the same streams
+    f2 = gpu_fields(b, ctx, plan, seed, rid, first, count)
+    assert torch.equal(f, f2)
+    d2 = torch.empty_like(f)
+    c2 = torch.empty_like(c)
+    nt2 = torch.empty_like(nt)
+    b.lognormal_poisson(ctx, plan, f2, count, nbar, None, seed, rid, first, d2, c2, nt2)
+    p2 = torch.empty_like(p)
+    b.estimate_pk(ctx, n, (1.0,) * len(n), prec, b.MAP_COUNTS_DELTAG, c2, count, nt2, None, nb, p2)
+    torch.cuda.synchronize()
+    assert torch.equal(d, d2)
+    assert torch.equal(c, c2)
+    assert torch.equal(nt, nt2)
+    assert np.max(np.abs(p.cpu().numpy() / p2.cpu().numpy() - 1)) <= TOL_PK[prec]
+    # oracle: fields, counts from the GPU delta, spectra from the GPU counts, covariance from GPU spectra
+    ref_plan = embedding.plan(n, (1.0,) * len(n), xi)
+    ref_f = ofields.generate_fields(ref_plan, seed, rid, first, count)
+    fh = f.cpu().numpy().reshape((count,) + n)
+    assert max(rel(fh[k], ref_f[k]) for k in range(count)) <= TOL_FIELD[prec]
+    dh = d.cpu().numpy().reshape((count,) + n)
+    _, rc, rn = olp.lognormal_poisson(fh.astype(np.float64), plan.info["sigma2"], nbar, seed, rid, first, delta=dh)
+    assert np.array_equal(c.cpu().numpy().reshape((count,) + n), rc)
+    assert np.array_equal(nt.cpu().numpy(), rn)
+    rp = opk.estimate_pk(rc, 1.0, nb, kind="counts", ntot=rn)
+    assert np.max(np.abs(p.cpu().numpy().reshape(count, nb) / rp - 1)) <= TOL_PK[prec]
+    rcov, rcn = opk.covariance(p.cpu().numpy().reshape(count, nb))
+    assert rel(cov.cpu().numpy(), rcov.ravel()) <= 1e-12
+    assert rel(cn.cpu().numpy(), rcn.ravel()) <= 1e-12
+    plan.release()
+
+
+def test_pipeline_is_bitwise_deterministic(ce):
+    b, ctx = ce
+    n, nb, count = (128, 128), 32, 6
+    plan = b.plan_embedding(ctx, n, (1.0, 1.0), dict(kind="exp", sigma2=1.0, a=5.0), 0)
+    outs = []
+    for _ in range(2):
+        p = torch.empty(count * nb, dtype=torch.float64, device="cuda")
+        c = torch.empty(count * plan.cells, dtype=torch.int32, device="cuda")
+        b.pipeline_run(ctx, plan, 1, 0, 0, count, 0.3, nb, p, out_counts=c)
+        torch.cuda.synchronize()
+        outs.append((p.cpu(), c.cpu()))
+    assert torch.equal(outs[0][0], outs[1][0]) and torch.equal(outs[0][1], outs[1][1])
+    plan.release()
