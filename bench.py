@@ -1,0 +1,256 @@
+#!/usr/bin/env python3
+"""Throughput of the fused circulant-embedding hot path on one MI355X.
+
+One step = one batch of the whole path through the C ABI (ce_pipeline_run):
+noise -> scaled inverse FFT pruned to the survey -> crop -> lognormal ->
+Poisson counts -> counts P(k) in shells -> spectrum covariance, for the
+2-D 1024^2 survey in a 2048^2 embedding (FP32, 256 realizations per step,
+nbar = 0.3, 128 shells).  The embedding plan (lag table + FP64 eigenvalue FFT
++ non-negativity check) is built once per (geometry, xi) key before the timed
+region, as a serving cache would; its time is reported as plan_ms.
+
+Printed: one JSON line with throughput, per-step latency, the roofline of the
+dominant kernel (HIP-event durations measured inside the timed region), the
+plain FP64 comparator (FP64, unfused, unpruned, one realization per launch
+chain) and the CPU oracle on a bounded sample.
+"""
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "cropped realizations/s + % peak HBM GB/s vs plain FP64 path; p50/p99 latency"
+HBM_PEAK_GBS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="batched_2d")
+    ap.add_argument("--plain-realizations", type=int, default=8)
+    ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--copy-calibration-mib", type=int, default=0,
+                    help="also run a plain device copy of this size (for counter calibration)")
+    return ap.parse_args()
+
+
+def workload_description(w, name):
+    n = w["n"]
+    d = len(n)
+    side = "x".join(str(x) for x in n)
+    emb = "x".join(str(2 * x) for x in n)
+    return ("%dD survey %s cells in %s periodic embedding, xi=%s, %s, %d realizations per step, "
+            "lognormal + Poisson nbar=%g, %d-shell P(k) + covariance (%s)"
+            % (d, side, emb, w["xi"], w["precision"].upper(), w["realizations"], w["nbar"], w["nbins"], name))
+
+
+def kernel_bytes(name, n, prec, pairs, nb, count):
+    """Algorithmic HBM bytes of one launch of a pipeline kernel over `pairs` pairs."""
+    d = len(n)
+    ce = 16 if prec == "f64" else 8   # complex element
+    N0, Nl = n[0], n[-1]
+    M = [2 * x for x in n]
+    cells = 1
+    for x in n:
+        cells *= x
+    W = 2 * (Nl // 2 + 1)
+    rows = cells // Nl
+    H = rows * W * ce
+    octant = 1
+    for x in n:
+        octant *= x + 1
+    octant *= (8 if prec == "f64" else 4)
+    if name == "noise_inverse_axis0":
+        y1 = N0 * (M[1] * (M[2] if d == 3 else 1)) * ce
+        return pairs * y1 + octant
+    if name == "inverse_axis1":
+        y1 = N0 * M[1] * M[2] * ce
+        y2 = N0 * n[1] * M[2] * ce
+        return pairs * (y1 + y2)
+    if name == "inverse_last_fused":
+        yin = rows * M[-1] * ce
+        return pairs * (yin + 2 * cells * 4 + H)
+    if name == "forward_axis1":
+        return pairs * 2 * H
+    if name == "forward_axis0_bins":
+        return pairs * H
+    if name == "bin_reduce":
+        return count * nb * 8
+    if name == "covariance":
+        return count * nb * 8 + 2 * nb * nb * 8
+    return 0
+
+
+def cpu_oracle_sample(w, seconds):
+    """The FP64 oracle (as it stands) on whole pairs of the same workload until `seconds` pass."""
+    import numpy as np
+    from oracle import embedding, fields, lognormal_poisson, pk
+    t0 = time.perf_counter()
+    plan = embedding.plan(w["n"], w["h"], w["xi"])
+    t_plan = time.perf_counter() - t0
+    pairs = 0
+    spectra = []
+    t0 = time.perf_counter()
+    while True:
+        g = fields.generate_fields(plan, w["seed"], w["request_id"], 2 * pairs, 2)
+        _, counts, ntot = lognormal_poisson.lognormal_poisson(g, plan["sigma2"], w["nbar"], w["seed"],
+                                                              w["request_id"], 2 * pairs)
+        spectra.append(pk.estimate_pk(counts, 1.0, w["nbins"], kind="counts", ntot=ntot))
+        pairs += 1
+        if time.perf_counter() - t0 >= seconds or pairs >= 64:
+            break
+    allp = np.concatenate(spectra)
+    pk.covariance(allp)
+    dt = time.perf_counter() - t0
+    return dict(value=2 * pairs / dt, unit="realizations/s", cores=1, kind="oracle",
+                sample="%d pairs (%d realizations) of the timed workload, full pipeline incl. covariance; "
+                       "plan %.1f s excluded" % (pairs, 2 * pairs, t_plan),
+                seconds=dt)
+
+
+def main():
+    args = parse()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path (see DESIGN.md, sharding); "
+              "run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_1406_6072_amd import binding as b
+    from synth import workloads
+
+    w = workloads.WORKLOADS[args.workload]
+    prec = b.F64 if w["precision"] == "f64" else b.F32
+    n, h, nb, R, nbar = w["n"], w["h"], w["nbins"], w["realizations"], w["nbar"]
+    dev = torch.device("cuda:0")
+    ctx = b.ctx_create(0)
+    stream = torch.cuda.current_stream()
+
+    t0 = time.perf_counter()
+    plan = b.plan_embedding(ctx, n, h, w["xi"], prec)
+    plan_ms = (time.perf_counter() - t0) * 1e3
+    cells = plan.cells
+    pk_out = torch.empty(R * nb, dtype=torch.float64, device=dev)
+    counts = torch.empty(R * cells, dtype=torch.int32, device=dev)
+    ntot = torch.empty(R, dtype=torch.int64, device=dev)
+    cov = torch.empty(nb * nb, dtype=torch.float64, device=dev)
+    cnorm = torch.empty(nb * nb, dtype=torch.float64, device=dev)
+
+    def step(i):
+        b.pipeline_run(ctx, plan, w["seed"], w["request_id"], i * R * 2, R, nbar, nb, pk_out,
+                       out_counts=counts, out_ntot=ntot, out_cov=cov, out_cnorm=cnorm, stream=stream)
+
+    for i in range(args.warmup):
+        step(i)
+    torch.cuda.synchronize()
+    if b.ctx_check(ctx) != 0:
+        raise RuntimeError("device flagged a sampler condition during warm-up")
+    b.ctx_profile_read(ctx)
+    b.ctx_set_profiling(ctx, True)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ev[0].record(stream)
+    for i in range(args.steps):
+        step(args.warmup + i)
+        ev[i + 1].record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    b.ctx_set_profiling(ctx, False)
+    prof = b.ctx_profile_read(ctx)
+    step_ms = np.array([ev[i].elapsed_time(ev[i + 1]) for i in range(args.steps)])
+    gpu_ms = float(ev[0].elapsed_time(ev[-1]))
+    ms_per_step = 1e3 * wall / args.steps
+    value = R * args.steps / wall
+
+    pairs = (R + 1) // 2
+    kernels = {}
+    total_bytes = 0
+    for name, (ms, launches) in prof.items():
+        per = kernel_bytes(name, n, w["precision"], pairs, nb, R)
+        avg = ms / launches
+        total_bytes += per * launches / args.steps
+        kernels[name] = dict(avg_ms=round(avg, 4), launches=int(launches // args.steps),
+                             alg_bytes=per, alg_GBs=round(per / (avg * 1e-3) / 1e9, 1),
+                             share=round(ms / sum(v[0] for v in prof.values()), 3))
+    dom = max(prof.items(), key=lambda kv: kv[1][0])[0]
+    dk = kernels[dom]
+    achieved = dk["alg_GBs"]
+    roofline = dict(kernel=dom, bound="hbm", achieved=achieved, peak=HBM_PEAK_GBS, unit="GB/s",
+                    frac=round(achieved / HBM_PEAK_GBS, 4), traffic=None)
+    pipe_GBs = total_bytes / (np.median(step_ms) * 1e-3) / 1e9
+
+    out = dict(metric=METRIC, value=round(value, 1), unit="realizations/s", n_gpus=1, steps=args.steps,
+               warmup=args.warmup, ms_per_step=round(ms_per_step, 4), higher_is_better=True, scaling="weak",
+               vs_baseline=None, dtype=w["precision"], data="synthetic",
+               config=dict(workload=workload_description(w, args.workload), survey=list(n),
+                           embedding=[2 * x for x in n], realizations_per_step=R, nbar=nbar, shells=nb,
+                           precision=w["precision"]),
+               latency_ms=dict(p50=round(float(np.percentile(step_ms, 50)), 4),
+                               p99=round(float(np.percentile(step_ms, 99)), 4), gpu_total=round(gpu_ms, 3)),
+               pipeline_hbm=dict(alg_bytes_per_step=int(total_bytes), alg_GBs=round(pipe_GBs, 1),
+                                 frac_of_peak=round(pipe_GBs / HBM_PEAK_GBS, 4)),
+               roofline=roofline, kernels=kernels, plan_ms=round(plan_ms, 2))
+
+    if not args.no_plain:
+        # plain FP64 comparator: FP64 plan, unpruned inverse FFT, unfused, one realization per chain
+        b.ctx_set_option(ctx, b.OPT_UNPRUNED, 1)
+        p64 = b.plan_embedding(ctx, n, h, w["xi"], b.F64)
+        f1 = torch.empty(cells, dtype=torch.float64, device=dev)
+        c1 = torch.empty(cells, dtype=torch.int32, device=dev)
+        t1 = torch.empty(1, dtype=torch.int64, device=dev)
+        pk1 = torch.empty(args.plain_realizations * nb, dtype=torch.float64, device=dev)
+
+        def plain(r):
+            b.generate_fields(ctx, p64, w["seed"], w["request_id"], 2 * r, 1, f1, stream)
+            b.lognormal_poisson(ctx, p64, f1, 1, nbar, None, w["seed"], w["request_id"], 2 * r, None, c1, t1, stream)
+            b.estimate_pk(ctx, n, h, b.F64, b.MAP_COUNTS_DELTAG, c1, 1, t1, None, nb, pk1[r * nb:(r + 1) * nb],
+                          stream=stream)
+
+        plain(0)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for r in range(args.plain_realizations):
+            plain(r)
+        b.pk_covariance(ctx, pk1, args.plain_realizations, nb, cov, cnorm, stream)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        b.ctx_set_option(ctx, b.OPT_UNPRUNED, 0)
+        pv = args.plain_realizations / dt
+        out["plain_fp64"] = dict(value=round(pv, 1), unit="realizations/s",
+                                 realizations=args.plain_realizations,
+                                 form="FP64, unpruned inverse FFT, unfused calls, one realization (Re) per chain")
+        out["speedup_vs_plain_fp64"] = round(value / pv, 1)
+        p64.release()
+
+    if args.copy_calibration_mib:
+        nbytes = args.copy_calibration_mib << 20
+        src = torch.empty(nbytes // 4, dtype=torch.float32, device=dev).fill_(1.0)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        out["copy_calibration_bytes"] = 2 * nbytes
+
+    plan.release()
+    b.ctx_destroy(ctx)
+
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_oracle_sample(w, args.cpu_seconds)
+        out["speedup_vs_cpu_oracle"] = round(value / out["cpu_baseline"]["value"], 1)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -106,6 +106,23 @@ void ce_ctx_destroy(ce_ctx* ctx);
  * draw exceeded its step bound or a counts map had N_tot = 0 since the last check. */
 ce_status ce_ctx_check(ce_ctx* ctx, void* stream);
 
+/* Context options.
+ * CE_OPT_UNPRUNED (default 0): when non-zero, ce_generate_fields computes every output of every
+ * inverse pass on the full (2N)^d embedding and crops to the survey only when storing -- the
+ * plain, unpruned form of the method, kept as a comparator.  Results are identical up to
+ * rounding order.  Errors: CE_E_INVALID. */
+typedef enum { CE_OPT_UNPRUNED = 1 } ce_option;
+ce_status ce_ctx_set_option(ce_ctx* ctx, int32_t option, int64_t value);
+
+/* Profiling: with enable != 0 every kernel the ctx launches is bracketed by HIP events on its
+ * launch stream.  ce_ctx_profile_read synchronises on those events and reports, per kernel
+ * name, the summed duration and the launch count since the previous read (which it resets).
+ * names: host buffer of max * 32 bytes (NUL-terminated names); total_ms, launches: host arrays
+ * of max; *n receives the number of entries written.  Errors: CE_E_INVALID, CE_E_DEVICE. */
+ce_status ce_ctx_set_profiling(ce_ctx* ctx, int32_t enable);
+ce_status ce_ctx_profile_read(ce_ctx* ctx, int32_t max, char* names, double* total_ms, int64_t* launches,
+                              int32_t* n);
+
 /* Embedding plan (Sec. 2, eqs. grid and Specd; condition).
  * Builds the lag table c(m) = xi(h lag(m)) on the (2N)^d periodic grid (lag index N stands for
  * -N, the minimum image), takes its FP64 DFT on the device (the circulant eigenvalues lambda,

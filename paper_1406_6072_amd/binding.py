@@ -56,6 +56,10 @@ _version = _sig("ce_version", ctypes.c_char_p)
 _ctx_create = _sig("ce_ctx_create", c_i32, c_i32, c_size, ctypes.POINTER(c_void_p))
 _ctx_destroy = _sig("ce_ctx_destroy", None, c_void_p)
 _ctx_check = _sig("ce_ctx_check", c_i32, c_void_p, c_void_p)
+_ctx_set_option = _sig("ce_ctx_set_option", c_i32, c_void_p, c_i32, c_i64)
+_ctx_set_profiling = _sig("ce_ctx_set_profiling", c_i32, c_void_p, c_i32)
+_ctx_profile_read = _sig("ce_ctx_profile_read", c_i32, c_void_p, c_i32, c_void_p, c_void_p, c_void_p,
+                         ctypes.POINTER(c_i32))
 _plan_embedding = _sig("ce_plan_embedding", c_i32, c_void_p, ctypes.POINTER(Geometry), ctypes.POINTER(Xi), c_i32,
                        c_f64, ctypes.POINTER(c_void_p), ctypes.POINTER(PlanInfo))
 _plan_release = _sig("ce_plan_release", None, c_void_p)
@@ -76,6 +80,7 @@ _debug_philox = _sig("ce_debug_philox", c_i32, c_u64, c_void_p, c_i64, c_void_p,
 _debug_noise = _sig("ce_debug_noise", c_i32, c_void_p, c_u64, c_u32, c_u64, c_void_p, c_void_p)
 
 EXPORTED = ["ce_status_string", "ce_version", "ce_ctx_create", "ce_ctx_destroy", "ce_ctx_check",
+            "ce_ctx_set_option", "ce_ctx_set_profiling", "ce_ctx_profile_read",
             "ce_plan_embedding", "ce_plan_release", "ce_plan_get_info", "ce_plan_eigenvalues",
             "ce_generate_fields", "ce_lognormal_poisson", "ce_estimate_pk", "ce_pk_covariance",
             "ce_pipeline_run", "ce_shell_table", "ce_fft_factors", "ce_debug_philox", "ce_debug_noise"]
@@ -181,6 +186,31 @@ def ctx_destroy(ctx):
 
 def ctx_check(ctx, stream=None):
     return _ctx_check(ctx, None if stream is None else _stream(stream))
+
+
+OPT_UNPRUNED = 1
+
+
+def ctx_set_option(ctx, option, value):
+    _check(_ctx_set_option(ctx, int(option), int(value)), "ce_ctx_set_option")
+
+
+def ctx_set_profiling(ctx, enable):
+    _check(_ctx_set_profiling(ctx, 1 if enable else 0), "ce_ctx_set_profiling")
+
+
+def ctx_profile_read(ctx, max_entries=64):
+    """{kernel name: (total ms, launches)} since the previous read."""
+    names = ctypes.create_string_buffer(32 * max_entries)
+    ms = (c_f64 * max_entries)()
+    nl = (c_i64 * max_entries)()
+    n = c_i32()
+    _check(_ctx_profile_read(ctx, max_entries, names, ms, nl, ctypes.byref(n)), "ce_ctx_profile_read")
+    out = {}
+    for i in range(n.value):
+        nm = names.raw[32 * i:32 * (i + 1)].split(b"\0", 1)[0].decode()
+        out[nm] = (ms[i], nl[i])
+    return out
 
 
 class Plan:

@@ -39,6 +39,15 @@ constexpr int kPrimes[] = {3, 5, 7, 11, 13, 17, 19, 23, 29, 31};
 
 ce_status hip_status(hipError_t e) { return e == hipErrorOutOfMemory ? CE_E_OOM : CE_E_DEVICE; }
 
+// Launch `expr` on stream s; with profiling on, bracket it with events under `name`.
+#define CE_PROF(ctx, name, s, expr)                        \
+  do {                                                     \
+    hipEvent_t b_ = nullptr;                               \
+    if ((ctx)->prof) (ctx)->prof_begin(name, s, &b_);      \
+    CE_HIP(expr);                                          \
+    if (b_) (void)hipEventRecord(b_, s);                   \
+  } while (0)
+
 // ---- FFT factorisation ------------------------------------------------------
 
 bool factor_length(int L, std::vector<int>& rad) {
@@ -134,6 +143,43 @@ struct ce_ctx {
     size_t n = 0;
   };
   Buf ws[8];
+
+  // per-kernel timing with HIP events on the launch stream
+  struct ProfRec {
+    const char* name;
+    hipEvent_t a, b;
+  };
+  bool prof = false;
+  bool unpruned = false;  // inverse passes keep every embedding output (comparator form)
+  std::vector<ProfRec> pending;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> pool;
+  std::map<std::string, std::pair<double, int64_t>> agg;
+
+  void prof_begin(const char* name, hipStream_t s, hipEvent_t* b) {
+    std::pair<hipEvent_t, hipEvent_t> ev{nullptr, nullptr};
+    if (!pool.empty()) {
+      ev = pool.back();
+      pool.pop_back();
+    } else if (hipEventCreate(&ev.first) != hipSuccess || hipEventCreate(&ev.second) != hipSuccess) {
+      *b = nullptr;
+      return;
+    }
+    (void)hipEventRecord(ev.first, s);
+    pending.push_back({name, ev.first, ev.second});
+    *b = ev.second;
+  }
+  void prof_resolve() {
+    for (auto& r : pending) {
+      float ms = 0;
+      if (hipEventSynchronize(r.b) == hipSuccess && hipEventElapsedTime(&ms, r.a, r.b) == hipSuccess) {
+        auto& e = agg[r.name];
+        e.first += ms;
+        e.second += 1;
+      }
+      pool.push_back({r.a, r.b});
+    }
+    pending.clear();
+  }
 
   ce_status alloc(void** p, size_t bytes) {
     if (budget && held + bytes > budget) return CE_E_OOM;
@@ -342,9 +388,50 @@ void ce_ctx_destroy(ce_ctx* ctx) {
     if (b.p) (void)hipFree(b.p);
   for (auto& kv : ctx->tw) (void)hipFree(kv.second);
   for (auto& kv : ctx->shells) (void)hipFree(kv.second.first);
+  ctx->prof_resolve();
+  for (auto& ev : ctx->pool) {
+    (void)hipEventDestroy(ev.first);
+    (void)hipEventDestroy(ev.second);
+  }
   if (ctx->flags) (void)hipFree(ctx->flags);
   if (ctx->own) (void)hipStreamDestroy(ctx->own);
   delete ctx;
+}
+
+ce_status ce_ctx_set_profiling(ce_ctx* ctx, int32_t enable) {
+  if (!ctx) return CE_E_INVALID;
+  std::lock_guard<std::mutex> lock(ctx->mu);
+  ctx->prof = enable != 0;
+  return CE_OK;
+}
+
+ce_status ce_ctx_profile_read(ce_ctx* ctx, int32_t max, char* names, double* total_ms, int64_t* launches,
+                              int32_t* n) {
+  if (!ctx || !n || max < 0 || (max > 0 && (!names || !total_ms || !launches))) return CE_E_INVALID;
+  std::lock_guard<std::mutex> lock(ctx->mu);
+  CE_HIP(hipSetDevice(ctx->device));
+  ctx->prof_resolve();
+  int32_t i = 0;
+  for (auto& kv : ctx->agg) {
+    if (i >= max) break;
+    std::memset(names + 32 * i, 0, 32);
+    std::strncpy(names + 32 * i, kv.first.c_str(), 31);
+    total_ms[i] = kv.second.first;
+    launches[i] = kv.second.second;
+    ++i;
+  }
+  *n = i;
+  ctx->agg.clear();
+  return CE_OK;
+}
+
+ce_status ce_ctx_set_option(ce_ctx* ctx, int32_t option, int64_t value) {
+  if (!ctx) return CE_E_INVALID;
+  std::lock_guard<std::mutex> lock(ctx->mu);
+  switch (option) {
+    case CE_OPT_UNPRUNED: ctx->unpruned = value != 0; return CE_OK;
+    default: return CE_E_INVALID;
+  }
 }
 
 ce_status ce_ctx_check(ce_ctx* ctx, void* stream) {
@@ -559,33 +646,40 @@ ce_status run_inverse(ce_ctx* ctx, const ce_plan* p, const InverseSetup& fs, uin
                       uint64_t first_pair, int64_t npairs, RowEpi epi, hipStream_t s) {
   const size_t elem = p->prec ? 16 : 8;
   const int d = p->ndim;
+  // the unpruned comparator form keeps all M outputs of every axis and crops at the end
+  const bool full = ctx->unpruned && epi.mode == 1;
   const int64_t M0 = p->M[0], M1 = p->M[1], M2 = d == 3 ? p->M[2] : 1;
-  const int64_t N0 = p->n[0], N1 = p->n[1];
+  const int64_t K0 = full ? M0 : p->n[0], K1 = full ? M1 : p->n[1];
   const NoiseArgs na = noise_args(p, seed, rid, first_pair);
   // pass 1: axis 0 with the noise prologue; lines b over the remaining axes
   const int64_t B1 = M1 * M2;
-  const int64_t y1_item = N0 * B1;
+  const int64_t y1_item = K0 * B1;
   void* y1 = nullptr;
   CE_TRY(ctx->scratch(0, elem * (size_t)(y1_item * npairs), &y1));
-  LineGeom g1 = make_geom((int)M0, (int)N0, 1, B1, npairs, 0, y1_item, elem, mixed_radix(fs.fM[0]), 2, 32);
-  CE_HIP(launch_noise_pass(p->prec, g1, fs.fM[0], na, y1, s));
+  LineGeom g1 = make_geom((int)M0, (int)K0, 1, B1, npairs, 0, y1_item, elem, mixed_radix(fs.fM[0]), 2, 32);
+  CE_PROF(ctx, "noise_inverse_axis0", s, launch_noise_pass(p->prec, g1, fs.fM[0], na, y1, s));
   const void* last_in = y1;
-  int64_t rows = N0;
+  int64_t rows = K0;
   if (d == 3) {
     // pass 2: axis 1, lines (m0, q2)
-    const int64_t y2_item = N0 * N1 * M2;
+    const int64_t y2_item = K0 * K1 * M2;
     void* y2 = nullptr;
     CE_TRY(ctx->scratch(1, elem * (size_t)(y2_item * npairs), &y2));
-    LineGeom g2 = make_geom((int)M1, (int)N1, N0, M2, npairs, y1_item, y2_item, elem, mixed_radix(fs.fM[1]), 1, 32);
-    CE_HIP(launch_line_pass(p->prec, +1, g2, fs.fM[1], y1, y2, s));
+    LineGeom g2 = make_geom((int)M1, (int)K1, K0, M2, npairs, y1_item, y2_item, elem, mixed_radix(fs.fM[1]), 1, 32);
+    CE_PROF(ctx, "inverse_axis1", s, launch_line_pass(p->prec, +1, g2, fs.fM[1], y1, y2, s));
     last_in = y2;
-    rows = N0 * N1;
+    rows = K0 * K1;
   }
   const int last = d - 1;
-  const int64_t Ml = p->M[last], Nl = p->n[last];
-  LineGeom gl = make_geom((int)Ml, (int)Nl, rows, 1, npairs, rows * Ml, 0, elem,
+  const int64_t Ml = p->M[last], Kl = full ? Ml : p->n[last];
+  epi.rows_per_m0 = d == 3 ? K1 : 1;
+  epi.keep0 = p->n[0];
+  epi.keep1 = d == 3 ? p->n[1] : 1;
+  epi.keep_last = p->n[last];
+  LineGeom gl = make_geom((int)Ml, (int)Kl, rows, 1, npairs, rows * Ml, 0, elem,
                           mixed_radix(fs.fM[last]) || (epi.mode == 2 && mixed_radix(epi.fwd)), 1, 1024);
-  CE_HIP(launch_row_inverse(p->prec, gl, fs.fM[last], epi, last_in, s));
+  CE_PROF(ctx, epi.mode == 2 ? "inverse_last_fused" : "inverse_last_fields", s,
+          launch_row_inverse(p->prec, gl, fs.fM[last], epi, last_in, s));
   return CE_OK;
 }
 
@@ -602,7 +696,7 @@ ce_status run_forward_bins(ce_ctx* ctx, int ndim, const int* n, int prec, int64_
     FftDesc f1;
     CE_TRY(build_fft(ctx, n[1], prec, f1));
     LineGeom g2 = make_geom(n[1], n[1], n[0], W, nitems, H_item, H_item, elem, mixed_radix(f1), 1, 32);
-    CE_HIP(launch_line_pass(prec, -1, g2, f1, H, H, s));
+    CE_PROF(ctx, "forward_axis1", s, launch_line_pass(prec, -1, g2, f1, H, H, s));
   }
   FftDesc f0;
   CE_TRY(build_fft(ctx, n[0], prec, f0));
@@ -616,7 +710,7 @@ ce_status run_forward_bins(ce_ctx* ctx, int ndim, const int* n, int prec, int64_
   ba.nb = nb;
   ba.W = W;
   ba.partials = static_cast<double*>(part);
-  CE_HIP(launch_bin_pass(prec, gb, f0, ba, H, s));
+  CE_PROF(ctx, "forward_axis0_bins", s, launch_bin_pass(prec, gb, f0, ba, H, s));
   *partials_out = ba.partials;
   *groups_out = gb.groups_per_item;
   return CE_OK;
@@ -688,7 +782,7 @@ ce_status ce_lognormal_poisson(ce_ctx* ctx, const ce_plan* plan, const void* fie
   CE_TRY(ctx->scratch(4, sizeof(unsigned long long) * (size_t)count, &acc));
   auto* ntot = static_cast<unsigned long long*>(acc);
   CE_HIP(launch_zero_u64(ntot, count, s));
-  CE_HIP(launch_lognormal_poisson(plan->prec, fields, count, ncells, 0.5 * plan->info.sigma2, nbar, mask_f,
+  CE_PROF(ctx, "lognormal_poisson", s, launch_lognormal_poisson(plan->prec, fields, count, ncells, 0.5 * plan->info.sigma2, nbar, mask_f,
                                   (uint32_t)(seed & 0xFFFFFFFFu), (uint32_t)(seed >> 32), request_id,
                                   first_realization, out_delta, out_counts, ntot, ctx->flags, s));
   if (out_ntot) CE_HIP(launch_copy_ntot(ntot, out_ntot, count, s));
@@ -780,7 +874,7 @@ ce_status ce_estimate_pk(ce_ctx* ctx, const ce_geometry* geom, ce_precision prec
   FftDesc fl;
   CE_TRY(build_fft(ctx, Nl, prec, fl));
   LineGeom g1 = make_geom(Nl, Nl, rows, 1, nitems, 0, 0, elem, mixed_radix(fl), 1, 1024);
-  CE_HIP(launch_pair_forward(prec, g1, fl, pl, s));
+  CE_PROF(ctx, "forward_rows_pair", s, launch_pair_forward(prec, g1, fl, pl, s));
   double* partials = nullptr;
   int64_t groups = 0;
   CE_TRY(run_forward_bins(ctx, ndim, n, prec, nitems, H, nbins, &partials, &groups, s));
@@ -788,7 +882,7 @@ ce_status ce_estimate_pk(ce_ctx* ctx, const ce_geometry* geom, ce_precision prec
   const std::vector<double>* km = nullptr;
   CE_TRY(device_shells(ctx, n[0], ndim, geom->h[0], nbins, &nm, &km));
   const double norm = std::pow(geom->h[0], ndim) / (double)ncells;
-  CE_HIP(launch_bin_reduce(partials, nitems, groups, nbins, count, nm, norm, 0, nullptr, nullptr, (double)ncells,
+  CE_PROF(ctx, "bin_reduce", s, launch_bin_reduce(partials, nitems, groups, nbins, count, nm, norm, 0, nullptr, nullptr, (double)ncells,
                            out_pk, ctx->flags, s));
   if (out_nmodes) CE_HIP(hipMemcpyAsync(out_nmodes, nm, sizeof(int64_t) * nbins, hipMemcpyDeviceToDevice, s));
   if (out_kmean) {
@@ -869,11 +963,12 @@ ce_status ce_pipeline_run(ce_ctx* ctx, const ce_plan* plan, uint64_t seed, uint3
       double* partials = nullptr;
       int64_t groups = 0;
       CE_TRY(run_forward_bins(ctx, ndim, plan->n, plan->prec, np, H, nbins, &partials, &groups, s));
-      CE_HIP(launch_bin_reduce(partials, np, groups, nbins, e.count, nm, norm, 1, ntot + 2 * j, nullptr,
+      CE_PROF(ctx, "bin_reduce", s, launch_bin_reduce(partials, np, groups, nbins, e.count, nm, norm, 1, ntot + 2 * j, nullptr,
                                (double)ncells, out_pk + 2 * j * nbins, ctx->flags, s));
     }
     if (out_ntot) CE_HIP(launch_copy_ntot(ntot, out_ntot, count, s));
-    if (count >= 2 && (out_cov || out_cnorm)) CE_HIP(launch_covariance(out_pk, count, nbins, out_cov, out_cnorm, s));
+    if (count >= 2 && (out_cov || out_cnorm))
+      CE_PROF(ctx, "covariance", s, launch_covariance(out_pk, count, nbins, out_cov, out_cnorm, s));
   }
   return CE_OK;
 }

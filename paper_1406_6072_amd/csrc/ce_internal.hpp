@@ -50,6 +50,9 @@ struct NoiseArgs {
 struct RowEpi {
   int32_t mode = 0;            // 0: complex store, 1: fields, 2: fused lognormal/Poisson/forward
   int64_t ncells = 0;          // survey cells per realization
+  int64_t rows_per_m0 = 1;     // input rows per axis-0 index (3-D: the axis-1 extent of the input)
+  int32_t keep0 = 0, keep1 = 1;  // survey extents of axes 0 and 1 (3-D); rows outside are dropped
+  int32_t keep_last = 0;       // survey extent of the last axis
   int64_t count = 0;           // realizations covered by this call
   int64_t real_off = 0;        // local realization index of item 0's real part
   void* fields = nullptr;      // nullable (pass precision)

@@ -403,10 +403,13 @@ __global__ void __launch_bounds__(512) k_row_inverse(LineGeom g, FftDesc f, RowE
   const int64_t ra = e.real_off + 2 * pp.item;  // local realization of the real part
   const bool has_b = ra + 1 < e.count;
   if (e.mode == 1) {
-    if (active) {
-      T* fa = static_cast<T*>(e.fields) + ra * e.ncells + row * K;
+    // rows outside the survey exist only in the unpruned form
+    const int64_t m0 = row / e.rows_per_m0, m1 = row - m0 * e.rows_per_m0;
+    if (active && m0 < e.keep0 && m1 < e.keep1) {
+      const int64_t crow = m0 * e.keep1 + m1;
+      T* fa = static_cast<T*>(e.fields) + ra * e.ncells + crow * e.keep_last;
       T* fb = fa + e.ncells;
-      for (int i = lane; i < K; i += g.nlanes) {
+      for (int i = lane; i < e.keep_last; i += g.nlanes) {
         const cpx<T> z = line[pidx(i)];
         fa[i] = z.x;
         if (has_b) fb[i] = z.y;
