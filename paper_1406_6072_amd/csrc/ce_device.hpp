@@ -78,11 +78,11 @@ __device__ __forceinline__ cpx<double> box_muller(double u1, double u2) {
   sincospi(2.0 * u2, &s, &c);
   return {r * c, r * s};
 }
+// FP32: the hardware transcendentals -- v_log_f32 is log2 (-2 ln u = -2 ln2 log2 u) and
+// v_sin_f32 / v_cos_f32 take their argument in revolutions, i.e. sin(2 pi u2) directly.
 __device__ __forceinline__ cpx<float> box_muller(float u1, float u2) {
-  const float r = sqrtf(-2.0f * logf(u1));
-  float s, c;
-  sincospif(2.0f * u2, &s, &c);
-  return {r * c, r * s};
+  const float r = __builtin_amdgcn_sqrtf(-1.38629436111989061883f * __builtin_amdgcn_logf(u1));
+  return {r * __builtin_amdgcn_cosf(u2), r * __builtin_amdgcn_sinf(u2)};
 }
 
 template <typename T>
@@ -216,6 +216,44 @@ __device__ __forceinline__ void odd_dft_store(const cpx<T>* v, const T* cs, cons
   }
 }
 
+// v[r] *= w^r for r = 1..R-1, w = exp(S 2 pi i step / L).  Only w, w^2, w^4, w^8 come from
+// the (FP64-accurate) root table; the other powers are products of at most two of them.
+template <typename T, int R, int S>
+__device__ __forceinline__ void apply_twiddles(cpx<T>* v, const cpx<T>* __restrict__ tw, unsigned step) {
+  auto ld = [&](unsigned m) {
+    cpx<T> w = tw[m * step];
+    if (S > 0) w.y = -w.y;
+    return w;
+  };
+  const cpx<T> w1 = ld(1);
+  v[1] = c_mul(v[1], w1);
+  if constexpr (R >= 4) {
+    const cpx<T> w2 = ld(2);
+    const cpx<T> w3 = c_mul(w1, w2);
+    v[2] = c_mul(v[2], w2);
+    v[3] = c_mul(v[3], w3);
+    if constexpr (R >= 8) {
+      const cpx<T> w4 = ld(4);
+      v[4] = c_mul(v[4], w4);
+      v[5] = c_mul(v[5], c_mul(w4, w1));
+      v[6] = c_mul(v[6], c_mul(w4, w2));
+      v[7] = c_mul(v[7], c_mul(w4, w3));
+      if constexpr (R >= 16) {
+        const cpx<T> w8 = ld(8);
+        v[8] = c_mul(v[8], w8);
+        v[9] = c_mul(v[9], c_mul(w8, w1));
+        v[10] = c_mul(v[10], c_mul(w8, w2));
+        v[11] = c_mul(v[11], c_mul(w8, w3));
+        const cpx<T> w12 = c_mul(w8, w4);
+        v[12] = c_mul(v[12], w12);
+        v[13] = c_mul(v[13], c_mul(w12, w1));
+        v[14] = c_mul(v[14], c_mul(w12, w2));
+        v[15] = c_mul(v[15], c_mul(w12, w3));
+      }
+    }
+  }
+}
+
 // One in-place Stockham stage on an LDS line (Govindaraju et al. 2008 indexing):
 // butterfly j reads elements j + r L/R, twiddles by exp(S 2 pi i r (j mod Ns)/(Ns R)),
 // and writes (j/Ns) Ns R + (j mod Ns) + r Ns.  All reads precede all writes
@@ -241,15 +279,7 @@ __device__ __forceinline__ void stockham_stage(cpx<T>* line, int L, int Ns, int 
     const int j = lane + b * nlanes;
     if (active && j < nb) {
       const int k = j % Ns;
-      if (Ns > 1) {
-        const int step = k * (L / (Ns * R));
-#pragma unroll
-        for (int r = 1; r < R; ++r) {
-          cpx<T> w = tw[r * step];
-          if (S > 0) w.y = -w.y;
-          v[b][r] = c_mul(v[b][r], w);
-        }
-      }
+      if (Ns > 1) apply_twiddles<T, R, S>(v[b], tw, (unsigned)(k * (L / (Ns * R))));
       Pow2Dft<R, S, T>::run(v[b]);
       const int base = (j / Ns) * Ns * R + k;
 #pragma unroll
@@ -311,28 +341,59 @@ __device__ __forceinline__ void pingpong_stage(const cpx<T>* src, cpx<T>* dst, i
   __syncthreads();
 }
 
-// Full line FFT over the stages of f.rad.  Every thread of the workgroup must
-// call it (barriers inside); threads without a line pass active = false.
-// MIX = false: power-of-two radices, in place in buffer a, registers staged
-// across the barrier.  MIX = true: any radix, ping-pong between a and b.
+// Power-of-two lengths: the stage sequence is fixed at compile time (one
+// straight-line instantiation per length), which keeps the register
+// allocation to that of a single radix.  The radices match the host
+// factorisation: 2, 4, 8, 16, 8.4, 8.8, 16.8, 16.16, 16.8.4, 16.8.8, 16.16.8, 16.16.16.
+template <typename T, int S, int... Rs>
+struct StaticFft;
+template <typename T, int S>
+struct StaticFft<T, S> {
+  static __device__ __forceinline__ void run(cpx<T>*, int, int, int, int, bool, const cpx<T>*, int) {}
+};
+template <typename T, int S, int R, int... Rs>
+struct StaticFft<T, S, R, Rs...> {
+  static __device__ __forceinline__ void run(cpx<T>* a, int L, int Ns, int lane, int nlanes, bool active,
+                                             const cpx<T>* tw, int keep) {
+    stockham_stage<T, R, S>(a, L, Ns, lane, nlanes, active, tw, sizeof...(Rs) == 0 ? keep : L);
+    StaticFft<T, S, Rs...>::run(a, L, Ns * R, lane, nlanes, active, tw, keep);
+  }
+};
+
+template <typename T, int S>
+__device__ __forceinline__ void pow2_fft(cpx<T>* a, int L, int lane, int nlanes, bool active, const cpx<T>* tw,
+                                         int keep) {
+  switch (L) {
+    case 2: StaticFft<T, S, 2>::run(a, L, 1, lane, nlanes, active, tw, keep); break;
+    case 4: StaticFft<T, S, 4>::run(a, L, 1, lane, nlanes, active, tw, keep); break;
+    case 8: StaticFft<T, S, 8>::run(a, L, 1, lane, nlanes, active, tw, keep); break;
+    case 16: StaticFft<T, S, 16>::run(a, L, 1, lane, nlanes, active, tw, keep); break;
+    case 32: StaticFft<T, S, 8, 4>::run(a, L, 1, lane, nlanes, active, tw, keep); break;
+    case 64: StaticFft<T, S, 8, 8>::run(a, L, 1, lane, nlanes, active, tw, keep); break;
+    case 128: StaticFft<T, S, 16, 8>::run(a, L, 1, lane, nlanes, active, tw, keep); break;
+    case 256: StaticFft<T, S, 16, 16>::run(a, L, 1, lane, nlanes, active, tw, keep); break;
+    case 512: StaticFft<T, S, 16, 8, 4>::run(a, L, 1, lane, nlanes, active, tw, keep); break;
+    case 1024: StaticFft<T, S, 16, 8, 8>::run(a, L, 1, lane, nlanes, active, tw, keep); break;
+    case 2048: StaticFft<T, S, 16, 16, 8>::run(a, L, 1, lane, nlanes, active, tw, keep); break;
+    default: StaticFft<T, S, 16, 16, 16>::run(a, L, 1, lane, nlanes, active, tw, keep); break;
+  }
+}
+
+// Full line FFT.  Every thread of the workgroup must call it (barriers inside);
+// threads without a line pass active = false.  MIX = false: power-of-two
+// lengths, in place in buffer a, registers staged across each barrier.
+// MIX = true: any supported radix (f.rad), ping-pong between a and b.
 // Returns the buffer that holds the result.
 template <typename T, int S, bool MIX>
-__device__ cpx<T>* line_fft(cpx<T>* a, cpx<T>* b, const FftDesc& f, int lane, int nlanes, bool active, int keep) {
+__device__ __forceinline__ cpx<T>* line_fft(cpx<T>* a, cpx<T>* b, const FftDesc& f, int lane, int nlanes, bool active,
+                                           int keep) {
   const cpx<T>* __restrict__ tw = static_cast<const cpx<T>*>(f.tw);
   const int L = f.L;
   int Ns = 1;
   if constexpr (!MIX) {
-    for (int s = 0; s < f.nst; ++s) {
-      const int R = f.rad[s];
-      const int kp = (s == f.nst - 1) ? keep : L;
-      switch (R) {
-        case 2: stockham_stage<T, 2, S>(a, L, Ns, lane, nlanes, active, tw, kp); break;
-        case 4: stockham_stage<T, 4, S>(a, L, Ns, lane, nlanes, active, tw, kp); break;
-        case 8: stockham_stage<T, 8, S>(a, L, Ns, lane, nlanes, active, tw, kp); break;
-        default: stockham_stage<T, 16, S>(a, L, Ns, lane, nlanes, active, tw, kp); break;
-      }
-      Ns *= R;
-    }
+    (void)b;
+    (void)Ns;
+    pow2_fft<T, S>(a, L, lane, nlanes, active, tw, keep);
     return a;
   } else {
     cpx<T>* src = a;

@@ -169,7 +169,7 @@ template <typename T>
 __device__ __forceinline__ T lognormal_delta(T g, T s2half);
 template <>
 __device__ __forceinline__ float lognormal_delta<float>(float g, float s2half) {
-  return expf(g - s2half) - 1.0f;
+  return __expf(g - s2half) - 1.0f;
 }
 template <>
 __device__ __forceinline__ double lognormal_delta<double>(double g, double s2half) {
@@ -312,7 +312,7 @@ __device__ __forceinline__ T sq_at(const T* __restrict__ sq, const NoiseArgs& n,
 }
 
 template <typename T, bool MIX>
-__global__ void __launch_bounds__(512) k_noise_pass(LineGeom g, FftDesc f, NoiseArgs n, cpx<T>* __restrict__ out) {
+__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 4 : 2))) k_noise_pass(LineGeom g, FftDesc f, NoiseArgs n, cpx<T>* __restrict__ out) {
   cpx<T>* lds = lds_lines<T>();
   const PassPos pp = pass_pos(g);
   const int L = g.L;
@@ -346,7 +346,7 @@ __global__ void __launch_bounds__(512) k_noise_pass(LineGeom g, FftDesc f, Noise
 // Generic complex line pass (inner axes of 3-D transforms), pruned to K outputs.
 // In place is allowed: a group reads all its lines before writing them.
 template <typename T, int S, bool MIX>
-__global__ void __launch_bounds__(512) k_line_pass(LineGeom g, FftDesc f, const cpx<T>* in, cpx<T>* out) {
+__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 4 : 2))) k_line_pass(LineGeom g, FftDesc f, const cpx<T>* in, cpx<T>* out) {
   cpx<T>* lds = lds_lines<T>();
   const PassPos pp = pass_pos(g);
   load_lines(lds, in, g, pp);
@@ -386,7 +386,7 @@ __device__ __forceinline__ void forward_separate(cpx<T>* line, cpx<T>* other, co
 // crop epilogue (Sec. 2) and optionally the lognormal / Poisson step (Sec. 3.1)
 // and the first forward transform of the counts (Sec. 3.2).
 template <typename T, bool MIX>
-__global__ void __launch_bounds__(512) k_row_inverse(LineGeom g, FftDesc f, RowEpi e, const cpx<T>* in) {
+__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 4 : 2))) k_row_inverse(LineGeom g, FftDesc f, RowEpi e, const cpx<T>* in) {
   cpx<T>* lds = lds_lines<T>();
   __shared__ unsigned long long tot[2];
   const PassPos pp = pass_pos(g);
@@ -462,7 +462,7 @@ __global__ void __launch_bounds__(512) k_row_inverse(LineGeom g, FftDesc f, RowE
 // Standalone spectrum, first pass: rows of two maps packed as a + i b (the
 // contrast delta_g for counts, Sec. 3.2 eq. Estim), forward transform, separation.
 template <typename T, bool MIX>
-__global__ void __launch_bounds__(512) k_pair_forward(LineGeom g, FftDesc f, PairLoad p) {
+__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 4 : 2))) k_pair_forward(LineGeom g, FftDesc f, PairLoad p) {
   cpx<T>* lds = lds_lines<T>();
   const PassPos pp = pass_pos(g);
   const int K = f.L;
@@ -512,7 +512,7 @@ __device__ __forceinline__ int64_t isqrt64(int64_t v) {
 }
 
 template <typename T, bool MIX>
-__global__ void __launch_bounds__(512) k_bin_pass(LineGeom g, FftDesc f, BinArgs bn, const cpx<T>* in) {
+__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 4 : 2))) k_bin_pass(LineGeom g, FftDesc f, BinArgs bn, const cpx<T>* in) {
   cpx<T>* lds = lds_lines<T>();
   const PassPos pp = pass_pos(g);
   double* part = reinterpret_cast<double*>(lds + g.nbuf * g.R * g.lpitch);  // [R][nb]

@@ -381,10 +381,14 @@ def test_volume_3d_parity_and_full_size_properties(ce):
     b, ctx = ce
     from synth import workloads
     w = workloads.WORKLOADS["volume_3d"]
-    # parity at 64^3 in 128^3 with the same two-point function
+    # parity at 64^3 in 128^3; the 256^3 two-point function (r0 = 5) is not positive at this
+    # side (Sec. 2: positivity is only guaranteed for large embeddings), so use r0 = 2
     n = (64, 64, 64)
-    plan = b.plan_embedding(ctx, n, w["h"], w["xi"], b.F32)
-    ref_plan = embedding.plan(n, w["h"], w["xi"])
+    xi_small = dict(w["xi"], r0=2.0, rc=100.0)
+    with pytest.raises(b.NotPSDError):
+        b.plan_embedding(ctx, n, w["h"], w["xi"], b.F32)
+    plan = b.plan_embedding(ctx, n, w["h"], xi_small, b.F32)
+    ref_plan = embedding.plan(n, w["h"], xi_small)
     got = gpu_fields(b, ctx, plan, 0, 0, 0, 2).cpu().numpy().reshape((2,) + n)
     ref = ofields.generate_fields(ref_plan, 0, 0, 0, 2)
     assert max(rel(got[k], ref[k]) for k in range(2)) <= TOL_FIELD[0]
