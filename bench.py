@@ -26,6 +26,71 @@ sys.path.insert(0, ROOT)
 
 METRIC = "cropped realizations/s + % peak HBM GB/s vs plain FP64 path; p50/p99 latency"
 HBM_PEAK_GBS = 8000.0
+# VALU issue peak: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz lane-operations per second (FP32/INT32 and,
+# on CDNA4, FP64 arithmetic issue at one operation per lane per cycle; packed FP32 is not used).
+VALU_PEAK_GOPS = 256 * 64 * 2.4
+
+# Algorithmic VALU lane-operations per unit of work (op model, measurement).
+OPS_PHILOX = 60          # 10 rounds x (2 32x32->64 products + 4 XOR)
+OPS_BOX_MULLER = 23      # 2 uniforms (2 each), log2/sqrt/sin/cos (4 each, quarter rate), 3 mul
+OPS_SCALE = 2            # complex x real sqrt(lambda)
+OPS_LOGNORMAL = 7        # sub, mul log2e, exp2 (4), sub 1
+OPS_INTENSITY = 3        # FP64 convert, add, mul
+OPS_EXP64 = 20           # FP64 exp: range reduction + polynomial
+OPS_POIS_STEP = 4        # FP64 mul, mul, add, compare
+OPS_SEPARATE = 4         # Hermitian separation per output
+OPS_BIN = 5              # |F|^2 in FP64 and the shell sum
+
+
+def fft_ops(L):
+    """4 log2(L) lane-ops per complex element (5 log2 L flops with one FMA per radix-2 butterfly)."""
+    import math
+    return 4.0 * math.log2(L)
+
+
+def kernel_ops(name, n, pairs, nb, count, nbar):
+    """Algorithmic VALU lane-operations of one launch of a pipeline kernel over `pairs` pairs."""
+    d = len(n)
+    M = [2 * x for x in n]
+    cells = 1
+    emb = 1
+    for x in n:
+        cells *= x
+        emb *= 2 * x
+    Nl = n[-1]
+    W = 2 * (Nl // 2 + 1)
+    rows = cells // Nl
+    pois = OPS_PHILOX / 2 + 3 + OPS_EXP64 + OPS_POIS_STEP * (nbar + 1)   # per value, one chunk
+    if name == "noise_inverse_axis0":
+        return pairs * emb * (OPS_PHILOX / 2 + OPS_BOX_MULLER / 2 + OPS_SCALE + fft_ops(M[0]))
+    if name == "inverse_axis1":
+        return pairs * n[0] * M[1] * M[2] * fft_ops(M[1])
+    if name == "inverse_last_fused":
+        per_pair = (rows * M[-1] * fft_ops(M[-1]) + 2 * cells * (OPS_LOGNORMAL + OPS_INTENSITY + pois)
+                    + cells * fft_ops(Nl) + rows * W * OPS_SEPARATE)
+        return pairs * per_pair
+    if name == "forward_axis1":
+        return pairs * n[0] * n[1] * W * fft_ops(n[1])
+    if name == "forward_axis0_bins":
+        lines = (n[1] * W) if d == 3 else W
+        return pairs * lines * n[0] * (fft_ops(n[0]) + OPS_BIN)
+    return 0
+
+
+def traffic_for(kernel, workload):
+    """HBM bytes per launch from the committed counter summary, if the kernel sources are unchanged."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "traffic_%s.json" % workload)
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    h = hashlib.sha256()
+    for f in rec.get("sources", []):
+        h.update(open(os.path.join(ROOT, f), "rb").read())
+    if h.hexdigest() != rec.get("sources_sha256"):
+        return None
+    k = rec.get("kernels", {}).get(kernel)
+    return None if k is None else int(k["bytes_per_launch"])
 
 
 def parse():
@@ -38,6 +103,9 @@ def parse():
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--lines", default="",
+                    help="schedule: max lines per workgroup for noise,inner,last,bins (0 = automatic)")
+    ap.add_argument("--noise-order", type=int, default=-1, help="schedule: noise-pass tile order (0/1)")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="also run a plain device copy of this size (for counter calibration)")
     return ap.parse_args()
@@ -137,6 +205,12 @@ def main():
     ctx = b.ctx_create(0)
     stream = torch.cuda.current_stream()
 
+    if args.lines:
+        for opt, v in zip((b.OPT_LINES_NOISE, b.OPT_LINES_INNER, b.OPT_LINES_LAST, b.OPT_LINES_BINS),
+                          args.lines.split(",")):
+            b.ctx_set_option(ctx, opt, int(v))
+    if args.noise_order >= 0:
+        b.ctx_set_option(ctx, b.OPT_NOISE_ORDER, args.noise_order)
     t0 = time.perf_counter()
     plan = b.plan_embedding(ctx, n, h, w["xi"], prec)
     plan_ms = (time.perf_counter() - t0) * 1e3
@@ -186,9 +260,16 @@ def main():
                              share=round(ms / sum(v[0] for v in prof.values()), 3))
     dom = max(prof.items(), key=lambda kv: kv[1][0])[0]
     dk = kernels[dom]
-    achieved = dk["alg_GBs"]
-    roofline = dict(kernel=dom, bound="hbm", achieved=achieved, peak=HBM_PEAK_GBS, unit="GB/s",
-                    frac=round(achieved / HBM_PEAK_GBS, 4), traffic=None)
+    ops = kernel_ops(dom, n, pairs, nb, R, nbar)
+    achieved = ops / (dk["avg_ms"] * 1e-3) / 1e9
+    roofline = dict(kernel=dom, bound="alu", achieved=round(achieved, 1), peak=round(VALU_PEAK_GOPS, 1),
+                    unit="Gop/s", frac=round(achieved / VALU_PEAK_GOPS, 4),
+                    traffic=traffic_for(dom, args.workload), alg_bytes=dk["alg_bytes"],
+                    alg_GBs=dk["alg_GBs"], hbm_frac=round(dk["alg_GBs"] / HBM_PEAK_GBS, 4))
+    for name in kernels:
+        o = kernel_ops(name, n, pairs, nb, R, nbar)
+        if o:
+            kernels[name]["alg_Gops"] = round(o / (kernels[name]["avg_ms"] * 1e-3) / 1e9, 1)
     pipe_GBs = total_bytes / (np.median(step_ms) * 1e-3) / 1e9
 
     out = dict(metric=METRIC, value=round(value, 1), unit="realizations/s", n_gpus=1, steps=args.steps,
@@ -235,13 +316,18 @@ def main():
         p64.release()
 
     if args.copy_calibration_mib:
+        # known-size kernels for scaling the FETCH_SIZE / WRITE_SIZE counters: a fill (writes
+        # nbytes), a reduction (reads nbytes) and a device copy (reads and writes nbytes)
         nbytes = args.copy_calibration_mib << 20
-        src = torch.empty(nbytes // 4, dtype=torch.float32, device=dev).fill_(1.0)
-        dst = torch.empty_like(src)
+        src = torch.empty(nbytes // 4, dtype=torch.float32, device=dev)
+        src.fill_(1.0)
         torch.cuda.synchronize()
+        total = src.sum()
+        dst = torch.empty_like(src)
         dst.copy_(src)
         torch.cuda.synchronize()
-        out["copy_calibration_bytes"] = 2 * nbytes
+        out["calibration_bytes"] = dict(fill_write=nbytes, sum_read=nbytes, copy_each_way=nbytes,
+                                        check=float(total.item()))
 
     plan.release()
     b.ctx_destroy(ctx)

@@ -110,8 +110,22 @@ ce_status ce_ctx_check(ce_ctx* ctx, void* stream);
  * CE_OPT_UNPRUNED (default 0): when non-zero, ce_generate_fields computes every output of every
  * inverse pass on the full (2N)^d embedding and crops to the survey only when storing -- the
  * plain, unpruned form of the method, kept as a comparator.  Results are identical up to
- * rounding order.  Errors: CE_E_INVALID. */
-typedef enum { CE_OPT_UNPRUNED = 1 } ce_option;
+ * rounding order.  Schedule options change only the launch shape, never the results.
+ * Errors: CE_E_INVALID. */
+typedef enum {
+  CE_OPT_UNPRUNED = 1,
+  /* Schedule: maximum lines per workgroup (a power of two <= 64; 0 = automatic, the default)
+   * for the noise pass, the inner-axis passes, the last inverse pass and the binning pass.
+   * The library lowers a requested value to what the LDS and the 512-thread limit allow. */
+  CE_OPT_LINES_NOISE = 2,
+  CE_OPT_LINES_INNER = 3,
+  CE_OPT_LINES_LAST = 4,
+  CE_OPT_LINES_BINS = 5,
+  /* Schedule: tile order of the noise pass: 0 (default) = the line groups of one pair run
+   * together (their strided output segments merge in L2); 1 = the workgroups of one line group
+   * for consecutive pairs run together (the sqrt(lambda) lines they read stay in L2). */
+  CE_OPT_NOISE_ORDER = 6
+} ce_option;
 ce_status ce_ctx_set_option(ce_ctx* ctx, int32_t option, int64_t value);
 
 /* Profiling: with enable != 0 every kernel the ctx launches is bracketed by HIP events on its

@@ -189,6 +189,7 @@ def ctx_check(ctx, stream=None):
 
 
 OPT_UNPRUNED = 1
+OPT_LINES_NOISE, OPT_LINES_INNER, OPT_LINES_LAST, OPT_LINES_BINS, OPT_NOISE_ORDER = 2, 3, 4, 5, 6
 
 
 def ctx_set_option(ctx, option, value):

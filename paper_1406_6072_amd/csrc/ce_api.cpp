@@ -23,6 +23,7 @@ namespace {
 constexpr double kDefaultNegTol = 1e-13;
 constexpr size_t kLdsBudget = 80 * 1024;   // per workgroup: two workgroups fit one CU
 constexpr int kMaxSide = 4096;
+constexpr int kPoissonSteps = 4096;
 constexpr int kPrimes[] = {3, 5, 7, 11, 13, 17, 19, 23, 29, 31};
 
 #define CE_HIP(expr)                                   \
@@ -135,8 +136,10 @@ struct ce_ctx {
   hipStream_t own = nullptr;
   hipStream_t last = nullptr;
   uint32_t* flags = nullptr;
+  double* inv = nullptr;  // RN(1/k), k = 0..kPoissonSteps, for the Poisson recursion
   std::mutex mu;
   std::map<TwKey, void*> tw;
+  std::map<TwKey, void*> stw;
   std::map<std::tuple<int, int, int>, std::pair<int64_t*, std::vector<double>>> shells;
   struct Buf {
     void* p = nullptr;
@@ -151,6 +154,8 @@ struct ce_ctx {
   };
   bool prof = false;
   bool unpruned = false;  // inverse passes keep every embedding output (comparator form)
+  int lines_cap[4] = {0, 0, 0, 0};  // max lines per workgroup per pass kind (0 = automatic)
+  int noise_item_minor = 0;         // noise pass tile order (0: line groups of one pair adjacent; measured faster)
   std::vector<ProfRec> pending;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> pool;
   std::map<std::string, std::pair<double, int64_t>> agg;
@@ -239,6 +244,43 @@ struct ce_ctx {
     *out = p;
     return CE_OK;
   }
+  // Per-stage twiddles of a power-of-two length with stage radices rad: for each stage
+  // with span Ns > 1, Ns x (R-1) values exp(-2 pi i r k / (Ns R)), k < Ns, r = 1..R-1.
+  ce_status stage_twiddles(int L, int prec, const std::vector<int>& rad, const void** out) {
+    auto it = stw.find({L, prec});
+    if (it != stw.end()) {
+      *out = it->second;
+      return CE_OK;
+    }
+    std::vector<double> d;
+    int Ns = 1;
+    for (int R : rad) {
+      if (Ns > 1)
+        for (int k = 0; k < Ns; ++k)
+          for (int r = 1; r < R; ++r) {
+            const long double a = 2.0L * 3.14159265358979323846264338327950288L * (long double)(r * k) /
+                                  (long double)(Ns * R);
+            d.push_back((double)std::cos(a));
+            d.push_back((double)-std::sin(a));
+          }
+      Ns *= R;
+    }
+    if (d.empty()) d.assign(2, 0.0);
+    const size_t n = d.size() / 2;
+    const size_t elem = prec ? 16 : 8;
+    void* p = nullptr;
+    CE_TRY(alloc(&p, elem * n));
+    if (prec) {
+      CE_HIP(hipMemcpy(p, d.data(), elem * n, hipMemcpyHostToDevice));
+    } else {
+      std::vector<float> f(d.size());
+      for (size_t i = 0; i < f.size(); ++i) f[i] = (float)d[i];
+      CE_HIP(hipMemcpy(p, f.data(), elem * n, hipMemcpyHostToDevice));
+    }
+    stw[{L, prec}] = p;
+    *out = p;
+    return CE_OK;
+  }
 };
 
 struct ce_plan {
@@ -257,13 +299,20 @@ struct ce_plan {
 
 namespace {
 
+int cap_lines(const ce_ctx* ctx, int kind, int dflt) {
+  const int c = ctx->lines_cap[kind];
+  return c > 0 ? c : dflt;
+}
+
 ce_status build_fft(ce_ctx* ctx, int L, int prec, FftDesc& f) {
   std::vector<int> rad;
   if (!factor_length(L, rad)) return CE_E_UNSUPPORTED;
   f.L = L;
   f.nst = (int)rad.size();
   for (int i = 0; i < f.nst; ++i) f.rad[i] = rad[i];
-  return ctx->twiddles(L, prec, &f.tw);
+  CE_TRY(ctx->twiddles(L, prec, &f.tw));
+  if ((L & (L - 1)) == 0) CE_TRY(ctx->stage_twiddles(L, prec, rad, &f.stw));
+  return CE_OK;
 }
 
 ce_status check_geometry(const ce_geometry* g) {
@@ -376,6 +425,15 @@ ce_status ce_ctx_create(int device, size_t hbm_budget_bytes, ce_ctx** out) {
   CE_TRY(ctx->alloc(&f, 16));
   ctx->flags = static_cast<uint32_t*>(f);
   CE_HIP(hipMemset(ctx->flags, 0, 16));
+  {
+    std::vector<double> inv(kPoissonSteps + 1);
+    inv[0] = 0.0;
+    for (int k = 1; k <= kPoissonSteps; ++k) inv[k] = 1.0 / (double)k;  // IEEE: correctly rounded
+    void* p = nullptr;
+    CE_TRY(ctx->alloc(&p, sizeof(double) * inv.size()));
+    ctx->inv = static_cast<double*>(p);
+    CE_HIP(hipMemcpy(ctx->inv, inv.data(), sizeof(double) * inv.size(), hipMemcpyHostToDevice));
+  }
   *out = ctx.release();
   return CE_OK;
 }
@@ -387,6 +445,7 @@ void ce_ctx_destroy(ce_ctx* ctx) {
   for (auto& b : ctx->ws)
     if (b.p) (void)hipFree(b.p);
   for (auto& kv : ctx->tw) (void)hipFree(kv.second);
+  for (auto& kv : ctx->stw) (void)hipFree(kv.second);
   for (auto& kv : ctx->shells) (void)hipFree(kv.second.first);
   ctx->prof_resolve();
   for (auto& ev : ctx->pool) {
@@ -394,6 +453,7 @@ void ce_ctx_destroy(ce_ctx* ctx) {
     (void)hipEventDestroy(ev.second);
   }
   if (ctx->flags) (void)hipFree(ctx->flags);
+  if (ctx->inv) (void)hipFree(ctx->inv);
   if (ctx->own) (void)hipStreamDestroy(ctx->own);
   delete ctx;
 }
@@ -430,6 +490,17 @@ ce_status ce_ctx_set_option(ce_ctx* ctx, int32_t option, int64_t value) {
   std::lock_guard<std::mutex> lock(ctx->mu);
   switch (option) {
     case CE_OPT_UNPRUNED: ctx->unpruned = value != 0; return CE_OK;
+    case CE_OPT_LINES_NOISE:
+    case CE_OPT_LINES_INNER:
+    case CE_OPT_LINES_LAST:
+    case CE_OPT_LINES_BINS:
+      if (value < 0 || value > 64 || (value & (value - 1))) return CE_E_INVALID;
+      ctx->lines_cap[option - CE_OPT_LINES_NOISE] = (int)value;
+      return CE_OK;
+    case CE_OPT_NOISE_ORDER:
+      if (value != 0 && value != 1) return CE_E_INVALID;
+      ctx->noise_item_minor = (int)value;
+      return CE_OK;
     default: return CE_E_INVALID;
   }
 }
@@ -568,7 +639,7 @@ ce_status ce_plan_embedding(ce_ctx* ctx, const ce_geometry* geom, const ce_xi* x
   plan->bytes_sq = (plan->prec ? 8 : 4) * (size_t)noct;
   st = ctx->alloc(&plan->sq, plan->bytes_sq);
   if (st != CE_OK) return fail(st);
-  if (launch_sqrt_table(src, noct, 1.0 / cells, plan->prec, plan->sq, s) != hipSuccess ||
+  if (launch_sqrt_table(src, geom->ndim, O, 1.0 / cells, plan->prec, plan->sq, s) != hipSuccess ||
       hipStreamSynchronize(s) != hipSuccess) {
     ctx->release(plan->sq, plan->bytes_sq);
     return fail(CE_E_DEVICE);
@@ -656,7 +727,9 @@ ce_status run_inverse(ce_ctx* ctx, const ce_plan* p, const InverseSetup& fs, uin
   const int64_t y1_item = K0 * B1;
   void* y1 = nullptr;
   CE_TRY(ctx->scratch(0, elem * (size_t)(y1_item * npairs), &y1));
-  LineGeom g1 = make_geom((int)M0, (int)K0, 1, B1, npairs, 0, y1_item, elem, mixed_radix(fs.fM[0]), 2, 32);
+  LineGeom g1 = make_geom((int)M0, (int)K0, 1, B1, npairs, 0, y1_item, elem, mixed_radix(fs.fM[0]), 2,
+                          cap_lines(ctx, 0, 32));
+  g1.item_minor = ctx->noise_item_minor;
   CE_PROF(ctx, "noise_inverse_axis0", s, launch_noise_pass(p->prec, g1, fs.fM[0], na, y1, s));
   const void* last_in = y1;
   int64_t rows = K0;
@@ -665,7 +738,8 @@ ce_status run_inverse(ce_ctx* ctx, const ce_plan* p, const InverseSetup& fs, uin
     const int64_t y2_item = K0 * K1 * M2;
     void* y2 = nullptr;
     CE_TRY(ctx->scratch(1, elem * (size_t)(y2_item * npairs), &y2));
-    LineGeom g2 = make_geom((int)M1, (int)K1, K0, M2, npairs, y1_item, y2_item, elem, mixed_radix(fs.fM[1]), 1, 32);
+    LineGeom g2 = make_geom((int)M1, (int)K1, K0, M2, npairs, y1_item, y2_item, elem, mixed_radix(fs.fM[1]), 1,
+                            cap_lines(ctx, 1, 32));
     CE_PROF(ctx, "inverse_axis1", s, launch_line_pass(p->prec, +1, g2, fs.fM[1], y1, y2, s));
     last_in = y2;
     rows = K0 * K1;
@@ -677,7 +751,8 @@ ce_status run_inverse(ce_ctx* ctx, const ce_plan* p, const InverseSetup& fs, uin
   epi.keep1 = d == 3 ? p->n[1] : 1;
   epi.keep_last = p->n[last];
   LineGeom gl = make_geom((int)Ml, (int)Kl, rows, 1, npairs, rows * Ml, 0, elem,
-                          mixed_radix(fs.fM[last]) || (epi.mode == 2 && mixed_radix(epi.fwd)), 1, 1024);
+                          mixed_radix(fs.fM[last]) || (epi.mode == 2 && mixed_radix(epi.fwd)), 1,
+                          cap_lines(ctx, 2, 2));
   CE_PROF(ctx, epi.mode == 2 ? "inverse_last_fused" : "inverse_last_fields", s,
           launch_row_inverse(p->prec, gl, fs.fM[last], epi, last_in, s));
   return CE_OK;
@@ -695,13 +770,16 @@ ce_status run_forward_bins(ce_ctx* ctx, int ndim, const int* n, int prec, int64_
   if (ndim == 3) {
     FftDesc f1;
     CE_TRY(build_fft(ctx, n[1], prec, f1));
-    LineGeom g2 = make_geom(n[1], n[1], n[0], W, nitems, H_item, H_item, elem, mixed_radix(f1), 1, 32);
+    LineGeom g2 = make_geom(n[1], n[1], n[0], W, nitems, H_item, H_item, elem, mixed_radix(f1), 1,
+                            cap_lines(ctx, 1, 32));
     CE_PROF(ctx, "forward_axis1", s, launch_line_pass(prec, -1, g2, f1, H, H, s));
   }
   FftDesc f0;
   CE_TRY(build_fft(ctx, n[0], prec, f0));
   const int64_t Bb = ndim == 3 ? (int64_t)n[1] * W : W;
-  LineGeom gb = make_geom(n[0], n[0], 1, Bb, nitems, H_item, 0, elem, mixed_radix(f0), 1, 32, (size_t)nb * 8);
+  // per line: nb FP64 shell sums and one run record (24 B) per lane
+  LineGeom gb = make_geom(n[0], n[0], 1, Bb, nitems, H_item, 0, elem, mixed_radix(f0), 1, cap_lines(ctx, 3, 32),
+                          (size_t)nb * 8 + (size_t)((n[0] + kEPT - 1) / kEPT) * 32);
   void* part = nullptr;
   CE_TRY(ctx->scratch(3, sizeof(double) * (size_t)(nitems * gb.groups_per_item * 2 * nb), &part));
   BinArgs ba;
@@ -784,7 +862,7 @@ ce_status ce_lognormal_poisson(ce_ctx* ctx, const ce_plan* plan, const void* fie
   CE_HIP(launch_zero_u64(ntot, count, s));
   CE_PROF(ctx, "lognormal_poisson", s, launch_lognormal_poisson(plan->prec, fields, count, ncells, 0.5 * plan->info.sigma2, nbar, mask_f,
                                   (uint32_t)(seed & 0xFFFFFFFFu), (uint32_t)(seed >> 32), request_id,
-                                  first_realization, out_delta, out_counts, ntot, ctx->flags, s));
+                                  first_realization, out_delta, out_counts, ntot, ctx->inv, ctx->flags, s));
   if (out_ntot) CE_HIP(launch_copy_ntot(ntot, out_ntot, count, s));
   return CE_OK;
 }
@@ -950,6 +1028,7 @@ ce_status ce_pipeline_run(ce_ctx* ctx, const ce_plan* plan, uint64_t seed, uint3
       e.counts = out_counts ? out_counts + 2 * j * ncells : nullptr;
       e.ntot = ntot + 2 * j;
       e.flags = ctx->flags;
+      e.inv = ctx->inv;
       e.s2half = 0.5 * plan->info.sigma2;
       e.nbar = nbar;
       e.k0 = (uint32_t)(seed & 0xFFFFFFFFu);

@@ -216,76 +216,64 @@ __device__ __forceinline__ void odd_dft_store(const cpx<T>* v, const T* cs, cons
   }
 }
 
-// v[r] *= w^r for r = 1..R-1, w = exp(S 2 pi i step / L).  Only w, w^2, w^4, w^8 come from
-// the (FP64-accurate) root table; the other powers are products of at most two of them.
-template <typename T, int R, int S>
-__device__ __forceinline__ void apply_twiddles(cpx<T>* v, const cpx<T>* __restrict__ tw, unsigned step) {
-  auto ld = [&](unsigned m) {
-    cpx<T> w = tw[m * step];
-    if (S > 0) w.y = -w.y;
-    return w;
-  };
-  const cpx<T> w1 = ld(1);
-  v[1] = c_mul(v[1], w1);
-  if constexpr (R >= 4) {
-    const cpx<T> w2 = ld(2);
-    const cpx<T> w3 = c_mul(w1, w2);
-    v[2] = c_mul(v[2], w2);
-    v[3] = c_mul(v[3], w3);
-    if constexpr (R >= 8) {
-      const cpx<T> w4 = ld(4);
-      v[4] = c_mul(v[4], w4);
-      v[5] = c_mul(v[5], c_mul(w4, w1));
-      v[6] = c_mul(v[6], c_mul(w4, w2));
-      v[7] = c_mul(v[7], c_mul(w4, w3));
-      if constexpr (R >= 16) {
-        const cpx<T> w8 = ld(8);
-        v[8] = c_mul(v[8], w8);
-        v[9] = c_mul(v[9], c_mul(w8, w1));
-        v[10] = c_mul(v[10], c_mul(w8, w2));
-        v[11] = c_mul(v[11], c_mul(w8, w3));
-        const cpx<T> w12 = c_mul(w8, w4);
-        v[12] = c_mul(v[12], w12);
-        v[13] = c_mul(v[13], c_mul(w12, w1));
-        v[14] = c_mul(v[14], c_mul(w12, w2));
-        v[15] = c_mul(v[15], c_mul(w12, w3));
-      }
-    }
-  }
-}
-
-// One in-place Stockham stage on an LDS line (Govindaraju et al. 2008 indexing):
-// butterfly j reads elements j + r L/R, twiddles by exp(S 2 pi i r (j mod Ns)/(Ns R)),
-// and writes (j/Ns) Ns R + (j mod Ns) + r Ns.  All reads precede all writes
-// (workgroup barrier), so the stage is in place.  With keep < L only outputs below
-// keep are written (pruned last stage).  Power-of-two radices only.
-template <typename T, int R, int S>
-__device__ __forceinline__ void stockham_stage(cpx<T>* line, int L, int Ns, int lane, int nlanes, bool active,
-                                               const cpx<T>* __restrict__ tw, int keep) {
-  constexpr int NB = (kEPT + R - 1) / R;
-  const int nb = L / R;
+// One in-place Stockham stage of a power-of-two line FFT with every size known
+// at compile time (Govindaraju et al. 2008 indexing): butterfly j reads
+// elements j + r L/R, multiplies by exp(S 2 pi i r k/(Ns R)), k = j mod Ns, and
+// writes (j/Ns) Ns R + k + r Ns.  All reads precede all writes (workgroup
+// barrier), so the stage is in place.  Lane count NL = L/16 (one line per NL
+// threads, 16 elements each).  With HALF only outputs below L/2 are formed and
+// stored (the pruned last stage).  The twiddles of a stage are read as one
+// contiguous vector: stw[k (R-1) + r - 1] = exp(-2 pi i r k / (Ns R)).
+template <typename T, int S, int L, int R, int Ns, bool HALF>
+__device__ __forceinline__ void stage_ct(cpx<T>* line, int lane, bool active, const cpx<T>* __restrict__ stw) {
+  constexpr int NL = L / kEPT > 0 ? L / kEPT : 1;
+  constexpr int nb = L / R;
+  constexpr int NB = (nb + NL - 1) / NL;
+  constexpr bool kExact = NB * NL == nb;
   cpx<T> v[NB][R];
 #pragma unroll
   for (int b = 0; b < NB; ++b) {
-    const int j = lane + b * nlanes;
-    if (active && j < nb) {
+    const int j = lane + b * NL;
+    if (active && (kExact || j < nb)) {
+      if constexpr (nb % 16 == 0) {
+        const int base = pidx(j);
 #pragma unroll
-      for (int r = 0; r < R; ++r) v[b][r] = line[pidx(j + r * nb)];
+        for (int r = 0; r < R; ++r) v[b][r] = line[base + r * (nb + nb / 16)];
+      } else {
+#pragma unroll
+        for (int r = 0; r < R; ++r) v[b][r] = line[pidx(j + r * nb)];
+      }
     }
   }
   __syncthreads();
 #pragma unroll
   for (int b = 0; b < NB; ++b) {
-    const int j = lane + b * nlanes;
-    if (active && j < nb) {
-      const int k = j % Ns;
-      if (Ns > 1) apply_twiddles<T, R, S>(v[b], tw, (unsigned)(k * (L / (Ns * R))));
-      Pow2Dft<R, S, T>::run(v[b]);
-      const int base = (j / Ns) * Ns * R + k;
+    const int j = lane + b * NL;
+    if (active && (kExact || j < nb)) {
+      const int k = j & (Ns - 1);
+      if constexpr (Ns > 1) {
+        const cpx<T>* w = stw + k * (R - 1);
 #pragma unroll
-      for (int r = 0; r < R; ++r) {
-        const int o = base + r * Ns;
-        if (o < keep) line[pidx(o)] = v[b][r];
+        for (int r = 1; r < R; ++r) {
+          cpx<T> t = w[r - 1];
+          if (S > 0) t.y = -t.y;
+          v[b][r] = c_mul(v[b][r], t);
+        }
+      }
+      Pow2Dft<R, S, T>::run(v[b]);
+      constexpr int RK = HALF ? R / 2 : R;
+      const int base = (j / Ns) * Ns * R + k;
+      if constexpr (Ns % 16 == 0) {
+        const int pb = pidx(base);
+#pragma unroll
+        for (int r = 0; r < RK; ++r) line[pb + r * (Ns + Ns / 16)] = v[b][r];
+      } else if constexpr (Ns == 1) {
+        const int pb = pidx(base);
+#pragma unroll
+        for (int r = 0; r < RK; ++r) line[pb + r] = v[b][r];
+      } else {
+#pragma unroll
+        for (int r = 0; r < RK; ++r) line[pidx(base + r * Ns)] = v[b][r];
       }
     }
   }
@@ -343,40 +331,48 @@ __device__ __forceinline__ void pingpong_stage(const cpx<T>* src, cpx<T>* dst, i
 
 // Power-of-two lengths: the stage sequence is fixed at compile time (one
 // straight-line instantiation per length), which keeps the register
-// allocation to that of a single radix.  The radices match the host
-// factorisation: 2, 4, 8, 16, 8.4, 8.8, 16.8, 16.16, 16.8.4, 16.8.8, 16.16.8, 16.16.16.
-template <typename T, int S, int... Rs>
+// allocation to that of a single radix and turns every LDS offset into an
+// immediate.  The radices match the host factorisation: 2, 4, 8, 16, 8.4, 8.8,
+// 16.8, 16.16, 16.8.4, 16.8.8, 16.16.8, 16.16.16; the per-stage twiddle tables
+// follow one another in stage order in f.stw (stages with Ns > 1 only).
+template <typename T, int S, int L, int Ns, bool HALF, int... Rs>
 struct StaticFft;
-template <typename T, int S>
-struct StaticFft<T, S> {
-  static __device__ __forceinline__ void run(cpx<T>*, int, int, int, int, bool, const cpx<T>*, int) {}
+template <typename T, int S, int L, int Ns, bool HALF>
+struct StaticFft<T, S, L, Ns, HALF> {
+  static __device__ __forceinline__ void run(cpx<T>*, int, bool, const cpx<T>*) {}
 };
-template <typename T, int S, int R, int... Rs>
-struct StaticFft<T, S, R, Rs...> {
-  static __device__ __forceinline__ void run(cpx<T>* a, int L, int Ns, int lane, int nlanes, bool active,
-                                             const cpx<T>* tw, int keep) {
-    stockham_stage<T, R, S>(a, L, Ns, lane, nlanes, active, tw, sizeof...(Rs) == 0 ? keep : L);
-    StaticFft<T, S, Rs...>::run(a, L, Ns * R, lane, nlanes, active, tw, keep);
+template <typename T, int S, int L, int Ns, bool HALF, int R, int... Rs>
+struct StaticFft<T, S, L, Ns, HALF, R, Rs...> {
+  static __device__ __forceinline__ void run(cpx<T>* a, int lane, bool active, const cpx<T>* stw) {
+    stage_ct<T, S, L, R, Ns, HALF && sizeof...(Rs) == 0>(a, lane, active, stw);
+    StaticFft<T, S, L, Ns * R, HALF, Rs...>::run(a, lane, active, Ns > 1 ? stw + Ns * (R - 1) : stw);
   }
 };
 
-template <typename T, int S>
-__device__ __forceinline__ void pow2_fft(cpx<T>* a, int L, int lane, int nlanes, bool active, const cpx<T>* tw,
-                                         int keep) {
+template <typename T, int S, bool HALF>
+__device__ __forceinline__ void pow2_fft_h(cpx<T>* a, int L, int lane, bool active, const cpx<T>* stw) {
   switch (L) {
-    case 2: StaticFft<T, S, 2>::run(a, L, 1, lane, nlanes, active, tw, keep); break;
-    case 4: StaticFft<T, S, 4>::run(a, L, 1, lane, nlanes, active, tw, keep); break;
-    case 8: StaticFft<T, S, 8>::run(a, L, 1, lane, nlanes, active, tw, keep); break;
-    case 16: StaticFft<T, S, 16>::run(a, L, 1, lane, nlanes, active, tw, keep); break;
-    case 32: StaticFft<T, S, 8, 4>::run(a, L, 1, lane, nlanes, active, tw, keep); break;
-    case 64: StaticFft<T, S, 8, 8>::run(a, L, 1, lane, nlanes, active, tw, keep); break;
-    case 128: StaticFft<T, S, 16, 8>::run(a, L, 1, lane, nlanes, active, tw, keep); break;
-    case 256: StaticFft<T, S, 16, 16>::run(a, L, 1, lane, nlanes, active, tw, keep); break;
-    case 512: StaticFft<T, S, 16, 8, 4>::run(a, L, 1, lane, nlanes, active, tw, keep); break;
-    case 1024: StaticFft<T, S, 16, 8, 8>::run(a, L, 1, lane, nlanes, active, tw, keep); break;
-    case 2048: StaticFft<T, S, 16, 16, 8>::run(a, L, 1, lane, nlanes, active, tw, keep); break;
-    default: StaticFft<T, S, 16, 16, 16>::run(a, L, 1, lane, nlanes, active, tw, keep); break;
+    case 2: StaticFft<T, S, 2, 1, HALF, 2>::run(a, lane, active, stw); break;
+    case 4: StaticFft<T, S, 4, 1, HALF, 4>::run(a, lane, active, stw); break;
+    case 8: StaticFft<T, S, 8, 1, HALF, 8>::run(a, lane, active, stw); break;
+    case 16: StaticFft<T, S, 16, 1, HALF, 16>::run(a, lane, active, stw); break;
+    case 32: StaticFft<T, S, 32, 1, HALF, 8, 4>::run(a, lane, active, stw); break;
+    case 64: StaticFft<T, S, 64, 1, HALF, 8, 8>::run(a, lane, active, stw); break;
+    case 128: StaticFft<T, S, 128, 1, HALF, 16, 8>::run(a, lane, active, stw); break;
+    case 256: StaticFft<T, S, 256, 1, HALF, 16, 16>::run(a, lane, active, stw); break;
+    case 512: StaticFft<T, S, 512, 1, HALF, 16, 8, 4>::run(a, lane, active, stw); break;
+    case 1024: StaticFft<T, S, 1024, 1, HALF, 16, 8, 8>::run(a, lane, active, stw); break;
+    case 2048: StaticFft<T, S, 2048, 1, HALF, 16, 16, 8>::run(a, lane, active, stw); break;
+    default: StaticFft<T, S, 4096, 1, HALF, 16, 16, 16>::run(a, lane, active, stw); break;
   }
+}
+
+template <typename T, int S>
+__device__ __forceinline__ void pow2_fft(cpx<T>* a, int L, int lane, bool active, const cpx<T>* stw, int keep) {
+  if (keep == L)
+    pow2_fft_h<T, S, false>(a, L, lane, active, stw);
+  else
+    pow2_fft_h<T, S, true>(a, L, lane, active, stw);
 }
 
 // Full line FFT.  Every thread of the workgroup must call it (barriers inside);
@@ -393,7 +389,8 @@ __device__ __forceinline__ cpx<T>* line_fft(cpx<T>* a, cpx<T>* b, const FftDesc&
   if constexpr (!MIX) {
     (void)b;
     (void)Ns;
-    pow2_fft<T, S>(a, L, lane, nlanes, active, tw, keep);
+    (void)tw;
+    pow2_fft<T, S>(a, L, lane, active, static_cast<const cpx<T>*>(f.stw), keep);
     return a;
   } else {
     cpx<T>* src = a;

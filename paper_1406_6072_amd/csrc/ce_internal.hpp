@@ -18,7 +18,8 @@ struct FftDesc {
   int32_t L = 0;
   int32_t nst = 0;
   int32_t rad[kMaxStages] = {};
-  const void* tw = nullptr;
+  const void* tw = nullptr;    // roots exp(-2 pi i k / L), k < L
+  const void* stw = nullptr;   // power-of-two lengths: per-stage twiddles, see ce_device.hpp
 };
 
 // A batch of line transforms.  Lines are (a, b), a in [0, A), b in [0, B); line
@@ -34,6 +35,7 @@ struct LineGeom {
   int32_t R = 0, nlanes = 0;
   int32_t lpitch = 0;          // LDS elements per line buffer
   int32_t nbuf = 1;            // LDS buffers per line: 1 (in place) or 2 (ping-pong, mixed radix)
+  int32_t item_minor = 0;      // tile order: 0 = item-major (groups of one item adjacent), 1 = group-major
 };
 
 // Noise prologue of the first inverse pass (lines along axis 0 of the embedding).
@@ -43,7 +45,7 @@ struct NoiseArgs {
   int32_t ndim = 0;
   int32_t M[3] = {1, 1, 1};
   int32_t O[3] = {1, 1, 1};    // octant sides N_i + 1
-  const void* sq = nullptr;    // sqrt(lambda / M^d) on the octant (pass precision)
+  const void* sq = nullptr;    // sqrt(lambda / M^d) on the octant, axis 0 fastest (pass precision)
 };
 
 // Epilogue of the last inverse pass (rows along the last axis).
@@ -60,6 +62,7 @@ struct RowEpi {
   int32_t* counts = nullptr;   // nullable
   unsigned long long* ntot = nullptr;  // per local realization (zeroed by the host)
   uint32_t* flags = nullptr;
+  const double* inv = nullptr;  // RN(1/k), k = 0..4096, for the Poisson recursion
   double s2half = 0, nbar = 0;
   uint32_t k0 = 0, k1 = 0, rid = 0;
   uint64_t first_pair = 0;
@@ -100,7 +103,7 @@ hipError_t launch_lag_octant(int ndim, const int32_t* O, const double* h, int ki
 hipError_t launch_dct_axis(const LineGeom& g, const FftDesc& f, const DctArgs& a, hipStream_t s);
 hipError_t launch_lambda_stats(const double* lam, int ndim, const int32_t* O, int64_t n, double* stats,
                                unsigned long long* nneg, hipStream_t s);
-hipError_t launch_sqrt_table(const double* lam, int64_t n, double inv_cells, int prec, void* out,
+hipError_t launch_sqrt_table(const double* lam, int ndim, const int32_t* O, double inv_cells, int prec, void* out,
                              hipStream_t s);
 hipError_t launch_noise_pass(int prec, const LineGeom& g, const FftDesc& f, const NoiseArgs& n, void* out,
                              hipStream_t s);
@@ -117,7 +120,7 @@ hipError_t launch_bin_reduce(const double* partials, int64_t nitems, int64_t gro
 hipError_t launch_lognormal_poisson(int prec, const void* fields, int64_t count, int64_t ncells, double s2half,
                                     double nbar, const float* mask, uint32_t k0, uint32_t k1, uint32_t rid,
                                     uint64_t first_real, void* delta, int32_t* counts, unsigned long long* ntot,
-                                    uint32_t* flags, hipStream_t s);
+                                    const double* inv, uint32_t* flags, hipStream_t s);
 hipError_t launch_count_totals(const int32_t* counts, int64_t count, int64_t ncells, unsigned long long* ntot,
                                hipStream_t s);
 hipError_t launch_copy_ntot(const unsigned long long* src, int64_t* dst, int64_t n, hipStream_t s);

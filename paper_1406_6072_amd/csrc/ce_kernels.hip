@@ -27,8 +27,13 @@ struct PassPos {
 __device__ __forceinline__ PassPos pass_pos(const LineGeom& g) {
   const int64_t t = xcd_tile((int64_t)blockIdx.x, (int64_t)gridDim.x);
   PassPos p;
-  p.item = t / g.groups_per_item;
-  p.grp = t - p.item * g.groups_per_item;
+  if (g.item_minor) {
+    p.grp = t / g.nitems;
+    p.item = t - p.grp * g.nitems;
+  } else {
+    p.item = t / g.groups_per_item;
+    p.grp = t - p.item * g.groups_per_item;
+  }
   p.line0 = p.grp * g.R;
   const int64_t nlines = g.A * g.B;
   const int64_t left = nlines - p.line0;
@@ -119,18 +124,23 @@ constexpr int kMaxPoissonSteps = 4096;
 constexpr double kChunkMean = 64.0;
 constexpr double kMaxMu = 6.7108864e7;  // 2^20 chunks
 
-__device__ __forceinline__ int poisson_chunk(double u, double m, uint32_t* flags) {
+// inv[k] = RN(1/k), k = 0..kMaxPoissonSteps (inv[0] unused); the first kInvLds entries are
+// also read from an LDS copy (inv_lds, nullable) to keep the recursion off global-memory latency.
+constexpr int kInvLds = 256;
+__device__ __forceinline__ int poisson_chunk(double u, double m, const double* __restrict__ inv,
+                                             const double* inv_lds, uint32_t* flags) {
   double p = exp(-m);
   double F = p;
   int k = 0;
   while (u > F && p > 0.0) {
     ++k;
-    p = __ddiv_rn(__dmul_rn(p, m), (double)k);
-    F = __dadd_rn(F, p);
-    if (k >= kMaxPoissonSteps) {
+    if (k > kMaxPoissonSteps) {
       atomicOr(flags, 1u);
       break;
     }
+    const double ik = (inv_lds && k <= kInvLds) ? inv_lds[k] : inv[k];
+    p = __dmul_rn(__dmul_rn(p, m), ik);
+    F = __dadd_rn(F, p);
   }
   return k;
 }
@@ -145,8 +155,8 @@ __device__ __forceinline__ double chunk_mean(double mu, int c, int K) {
 
 // Counts of the two realizations of a pair at one cell; counter (cell, pair, rid, 1 + chunk).
 __device__ __forceinline__ void poisson_pair(double mua, double mub, bool has_b, uint32_t cell, uint32_t pair,
-                                             uint32_t rid, uint32_t k0, uint32_t k1, uint32_t* flags, int& na,
-                                             int& nb) {
+                                             uint32_t rid, uint32_t k0, uint32_t k1, const double* __restrict__ inv,
+                                             const double* inv_lds, uint32_t* flags, int& na, int& nb) {
   na = 0;
   nb = 0;
   if (!(mua <= kMaxMu) || (has_b && !(mub <= kMaxMu))) {
@@ -160,8 +170,8 @@ __device__ __forceinline__ void poisson_pair(double mua, double mub, bool has_b,
   const int Kmax = Ka > Kb ? Ka : Kb;
   for (int c = 0; c < Kmax; ++c) {
     const Words4 w = philox4x32_10(cell, pair, rid, 1u + (uint32_t)c, k0, k1);
-    if (c < Ka) na += poisson_chunk(unit52(w.x0, w.x1), chunk_mean(mua, c, Ka), flags);
-    if (c < Kb) nb += poisson_chunk(unit52(w.x2, w.x3), chunk_mean(mub, c, Kb), flags);
+    if (c < Ka) na += poisson_chunk(unit52(w.x0, w.x1), chunk_mean(mua, c, Ka), inv, inv_lds, flags);
+    if (c < Kb) nb += poisson_chunk(unit52(w.x2, w.x3), chunk_mean(mub, c, Kb), inv, inv_lds, flags);
   }
 }
 
@@ -229,7 +239,7 @@ __global__ void __launch_bounds__(512) k_dct_axis(LineGeom g, FftDesc f, DctArgs
   __syncthreads();
   const int r = tid / g.nlanes, lane = tid - r * g.nlanes;
   const bool active = r < pp.nl;
-  line_fft<double, -1, MIX>(buf_a(lds, g, r), buf_b(lds, g, r), f, lane, g.nlanes, active, Od);
+  line_fft<double, -1, MIX>(buf_a(lds, g, r), buf_b(lds, g, r), f, lane, g.nlanes, active, d.M);
   const cpx<double>* res = result_base<double, MIX>(lds, g, f);
   {
     const int R = g.R;
@@ -286,10 +296,15 @@ __global__ void k_lambda_stats(const double* __restrict__ lam, int ndim, int32_t
   }
 }
 
+// sqrt(max(lambda, 0) / M^d), stored with axis 0 fastest: out[(o1 O2 + o2) O0 + o0] (the noise
+// pass reads one embedding line -- fixed (o1, o2), all o0 -- contiguously).
 template <typename T>
-__global__ void k_sqrt_table(const double* __restrict__ lam, int64_t n, double inv_cells, T* __restrict__ out) {
+__global__ void k_sqrt_table(const double* __restrict__ lam, int32_t O0, int32_t O1, int32_t O2, double inv_cells,
+                             T* __restrict__ out) {
+  const int64_t n = (int64_t)O0 * O1 * O2;
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-    const double v = lam[i];
+    const int64_t o0 = i % O0, rest = i / O0;  // rest = o1 O2 + o2
+    const double v = lam[o0 * ((int64_t)O1 * O2) + rest];
     out[i] = (T)sqrt((v > 0.0 ? v : 0.0) * inv_cells);
   }
 }
@@ -299,16 +314,12 @@ __global__ void k_sqrt_table(const double* __restrict__ lam, int64_t n, double i
 // lines along axis 0 of the embedding; cells 2p and 2p+1 share one Philox call
 // and lie on adjacent lines.
 
-template <typename T>
-__device__ __forceinline__ T sq_at(const T* __restrict__ sq, const NoiseArgs& n, int q0, int64_t b) {
-  int64_t o = mirror(q0, n.M[0]);
-  if (n.ndim == 2) {
-    o = o * n.O[1] + mirror((int)b, n.M[1]);
-  } else {
-    const int q1 = (int)(b / n.M[2]), q2 = (int)(b - (int64_t)q1 * n.M[2]);
-    o = (o * n.O[1] + mirror(q1, n.M[1])) * n.O[2] + mirror(q2, n.M[2]);
-  }
-  return sq[o];
+// Offset of embedding line b (the flattened axes 1..d-1) in the sqrt(lambda) octant (axis 0 fastest).
+__device__ __forceinline__ uint32_t sq_line_offset(const NoiseArgs& n, uint32_t b) {
+  if (n.ndim == 2) return (uint32_t)mirror((int)b, n.M[1]) * (uint32_t)n.O[0];
+  const uint32_t q1 = b / (uint32_t)n.M[2], q2 = b - q1 * (uint32_t)n.M[2];
+  return ((uint32_t)mirror((int)q1, n.M[1]) * (uint32_t)n.O[2] + (uint32_t)mirror((int)q2, n.M[2])) *
+         (uint32_t)n.O[0];
 }
 
 template <typename T, bool MIX>
@@ -323,17 +334,21 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(sizeof
     const int H = g.R / 2;  // line pairs
     const int rp = tid % H, c0 = tid / H, step = nthr / H;
     if (2 * rp < pp.nl) {
-      const int64_t b = pp.line0 + 2 * rp;  // even line id = flattened index over axes 1..d-1
+      // even line id b = flattened index over axes 1..d-1; cells 2p, 2p+1 = (i, b), (i, b+1)
+      const uint32_t b = (uint32_t)(pp.line0 + 2 * rp);
+      const uint32_t half_b = (uint32_t)(g.B >> 1);
+      const T* __restrict__ sq0 = sq + sq_line_offset(n, b);
+      const T* __restrict__ sq1 = sq + sq_line_offset(n, b + 1);
       cpx<T>* d0 = lds + (2 * rp) * g.lpitch;
       cpx<T>* d1 = d0 + g.lpitch;
       for (int i = c0; i < L; i += step) {
-        const uint64_t cell = (uint64_t)i * (uint64_t)g.B + (uint64_t)b;
-        const Words4 w = philox4x32_10((uint32_t)(cell >> 1), pair, n.rid, 0u, n.k0, n.k1);
+        const uint32_t p = (uint32_t)i * half_b + (b >> 1);
+        const Words4 w = philox4x32_10(p, pair, n.rid, 0u, n.k0, n.k1);
         const cpx<T> e0 = normal_pair<T>(w.x0, w.x1);
         const cpx<T> e1 = normal_pair<T>(w.x2, w.x3);
-        const T s0 = sq_at(sq, n, i, b), s1 = sq_at(sq, n, i, b + 1);
-        d0[pidx(i)] = c_scale(e0, s0);
-        d1[pidx(i)] = c_scale(e1, s1);
+        const uint32_t o0 = (uint32_t)mirror(i, n.M[0]);
+        d0[pidx(i)] = c_scale(e0, sq0[o0]);
+        d1[pidx(i)] = c_scale(e1, sq1[o0]);
       }
     }
   }
@@ -389,8 +404,11 @@ template <typename T, bool MIX>
 __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 4 : 2))) k_row_inverse(LineGeom g, FftDesc f, RowEpi e, const cpx<T>* in) {
   cpx<T>* lds = lds_lines<T>();
   __shared__ unsigned long long tot[2];
+  __shared__ double inv_s[kInvLds + 1];
   const PassPos pp = pass_pos(g);
   if (threadIdx.x < 2) tot[threadIdx.x] = 0;
+  if (e.mode == 2)
+    for (int i = threadIdx.x; i <= kInvLds; i += blockDim.x) inv_s[i] = e.inv[i];
   load_lines(lds, in, g, pp);
   __syncthreads();
   const int r = threadIdx.x / g.nlanes, lane = threadIdx.x - r * g.nlanes;
@@ -432,7 +450,8 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(sizeof
       const double mua = intensity(e.nbar, 1.0, (double)dla);
       const double mub = intensity(e.nbar, 1.0, (double)dlb);
       int na, nb;
-      poisson_pair(mua, mub, has_b, (uint32_t)(row * K + i), pair, e.rid, e.k0, e.k1, e.flags, na, nb);
+      poisson_pair(mua, mub, has_b, (uint32_t)(row * K + i), pair, e.rid, e.k0, e.k1, e.inv, inv_s, e.flags, na,
+                   nb);
       if (fa) {
         fa[i] = z.x;
         if (has_b) fa[i + e.ncells] = z.y;
@@ -499,36 +518,50 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(sizeof
 // ---------------------------------------------------------------------------
 // Last forward pass with the shell sums of eq. Def spec.  Line b of the
 // separated spectra holds (k_1 [3-D], s, k_last) with k_last in [0, N/2]; after
-// the transform along axis 0 each (line, shell) task sums |F|^2 over the k_0
-// range of that shell (exact integer bounds), and the lines are combined per
-// (realization, shell) in a fixed order: the sums are bitwise reproducible.
+// the transform along axis 0, mode a = |k_0| in [0, N/2] of a line has the power
+// v(a) = |F(a)|^2 + |F(N-a)|^2 (one term at a = 0, N/2) times the line weight
+// (2 unless k_last is 0 or N/2: the half-space stands for both signs).  The
+// shell of a mode is nondecreasing in a, so each thread sums a contiguous chunk
+// of a into runs of equal shell; runs inside a chunk are complete, runs that
+// cross chunk boundaries are merged by their first chunk in chunk order, and
+// lines are combined per (realization, shell) in line order: all sums are in a
+// fixed order, hence bitwise reproducible.
 
-__device__ __forceinline__ int64_t isqrt64(int64_t v) {
-  if (v <= 0) return 0;
-  int64_t s = (int64_t)sqrt((double)v);
-  while (s * s > v) --s;
-  while ((s + 1) * (s + 1) <= v) ++s;
-  return s;
+// shell b in [0, nb) of |q|^2 = q2 (exact integers): b + 1 = smallest s with s^2 N^2 >= T q2
+__device__ __forceinline__ int shell_of(int64_t q2, int64_t T, int64_t NN) {
+  const int64_t t = T * q2;
+  int64_t s = (int64_t)sqrt((double)t / (double)NN);
+  while (s > 0 && (s - 1) * (s - 1) * NN >= t) --s;
+  while (s * s * NN < t) ++s;
+  return (int)(s - 1);
 }
+
+struct RunEnds {
+  int first_bin, last_bin;
+  double first_sum, last_sum;
+  int single, nonempty;
+};
 
 template <typename T, bool MIX>
 __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 4 : 2))) k_bin_pass(LineGeom g, FftDesc f, BinArgs bn, const cpx<T>* in) {
   cpx<T>* lds = lds_lines<T>();
   const PassPos pp = pass_pos(g);
-  double* part = reinterpret_cast<double*>(lds + g.nbuf * g.R * g.lpitch);  // [R][nb]
+  double* acc = reinterpret_cast<double*>(lds + g.nbuf * g.R * g.lpitch);  // [R][nb]
+  RunEnds* ends = reinterpret_cast<RunEnds*>(acc + g.R * bn.nb);             // [R][nlanes]
   load_lines(lds, in, g, pp);
+  for (int t = threadIdx.x; t < g.R * bn.nb; t += blockDim.x) acc[t] = 0.0;
   __syncthreads();
   const int r = threadIdx.x / g.nlanes, lane = threadIdx.x - r * g.nlanes;
-  line_fft<T, -1, MIX>(buf_a(lds, g, r), buf_b(lds, g, r), f, lane, g.nlanes, r < pp.nl, f.L);
+  const bool active = r < pp.nl;
+  line_fft<T, -1, MIX>(buf_a(lds, g, r), buf_b(lds, g, r), f, lane, g.nlanes, active, f.L);
   const cpx<T>* res = result_base<T, MIX>(lds, g, f);
 
   const int N = bn.N, Nh = N / 2, nb = bn.nb, W = bn.W, Kh = Nh + 1;
-  const int64_t Tq = 4ll * nb * nb;
-  for (int task = threadIdx.x; task < g.R * nb; task += blockDim.x) {
-    const int lr = task / nb, b = task - lr * nb;
-    double acc = 0.0;
-    if (lr < pp.nl) {
-      const int64_t ln = pp.line0 + lr;
+  const int64_t Tq = 4ll * nb * nb, NN = (int64_t)N * N;
+  if (r < g.R) {
+    RunEnds e{-1, -1, 0.0, 0.0, 1, 0};
+    if (active) {
+      const int64_t ln = pp.line0 + r;
       const int kl = (int)(ln % W);
       const int s = kl >= Kh;
       const int kz = kl - s * Kh;
@@ -538,37 +571,85 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(sizeof
         if (k1 > Nh) k1 -= N;
         p2 += (int64_t)k1 * k1;
       }
-      const int64_t D0 = (int64_t)b * N * ((int64_t)b * N);
-      const int64_t D1 = (int64_t)(b + 1) * N * ((int64_t)(b + 1) * N);
-      const int64_t top = D1 - Tq * p2;
-      if (top >= 0) {
-        int64_t hi = isqrt64(top / Tq);
-        if (hi > Nh) hi = Nh;
-        const int64_t low = D0 - Tq * p2;
-        const int64_t lo = low >= 0 ? isqrt64(low / Tq) + 1 : 0;
-        const cpx<T>* line = res + lr * g.lpitch;
-        for (int64_t a = lo; a <= hi; ++a) {
-          const cpx<T> v = line[pidx((int)a)];
-          acc += (double)v.x * (double)v.x + (double)v.y * (double)v.y;
-          if (a != 0 && a != Nh) {
-            const cpx<T> u = line[pidx(N - (int)a)];
-            acc += (double)u.x * (double)u.x + (double)u.y * (double)u.y;
+      const double wgt = (kz != 0 && kz != Nh) ? 2.0 : 1.0;
+      const int chunk = (Kh + g.nlanes - 1) / g.nlanes;
+      const int a0 = lane * chunk, a1 = min(a0 + chunk, Kh);
+      const cpx<T>* line = res + r * g.lpitch;
+      if (a0 < a1) {
+        e.nonempty = 1;
+        int bin = shell_of((int64_t)a0 * a0 + p2, Tq, NN);
+        int64_t edge = (int64_t)(bin + 1) * N;
+        edge *= edge;  // (bin+1)^2 N^2: the mode stays in `bin` while T q2 <= edge
+        double run = 0.0;
+        e.first_bin = bin;
+        for (int a = a0; a < a1; ++a) {
+          const int64_t t = Tq * ((int64_t)a * a + p2);
+          if (t > edge) {
+            // close the current run
+            if (bin == e.first_bin && e.single) {
+              e.first_sum = run;
+            } else if (bin >= 0 && bin < nb) {
+              acc[r * nb + bin] = run;  // interior run: complete within this chunk
+            }
+            e.single = 0;
+            bin = shell_of((int64_t)a * a + p2, Tq, NN);
+            edge = (int64_t)(bin + 1) * N;
+            edge *= edge;
+            run = 0.0;
           }
+          const cpx<T> v = line[pidx(a)];
+          double pw = (double)v.x * (double)v.x + (double)v.y * (double)v.y;
+          if (a != 0 && a != Nh) {
+            const cpx<T> u = line[pidx(N - a)];
+            pw += (double)u.x * (double)u.x + (double)u.y * (double)u.y;
+          }
+          run += wgt * pw;
         }
-        if (kz != 0 && kz != Nh) acc *= 2.0;
+        if (e.single) {
+          e.first_sum = run;
+          e.last_bin = bin;
+        } else {
+          e.last_bin = bin;
+          e.last_sum = run;
+        }
       }
     }
-    part[task] = acc;
+    ends[r * g.nlanes + lane] = e;
+  }
+  __syncthreads();
+  // merge runs that cross chunk boundaries: each run is owned by the chunk it starts in
+  if (r < pp.nl) {
+    const RunEnds* le = ends + r * g.nlanes;
+    const RunEnds e = le[lane];
+    if (e.nonempty) {
+      auto extend = [&](int bin, double total, int from) {
+        for (int m = from; m < g.nlanes; ++m) {
+          const RunEnds& x = le[m];
+          if (!x.nonempty || x.first_bin != bin) break;
+          total += x.first_sum;
+          if (!x.single) break;
+        }
+        if (bin >= 0 && bin < nb) acc[r * nb + bin] = total;
+      };
+      const bool continues = lane > 0 && le[lane - 1].nonempty && le[lane - 1].last_bin == e.first_bin;
+      if (!continues) {
+        if (e.single)
+          extend(e.first_bin, e.first_sum, lane + 1);
+        else if (e.first_bin >= 0 && e.first_bin < nb)
+          acc[r * nb + e.first_bin] = e.first_sum;
+      }
+      if (!e.single) extend(e.last_bin, e.last_sum, lane + 1);
+    }
   }
   __syncthreads();
   for (int t = threadIdx.x; t < 2 * nb; t += blockDim.x) {
     const int s = t / nb, b = t - s * nb;
-    double acc = 0.0;
+    double sum = 0.0;
     for (int lr = 0; lr < pp.nl; ++lr) {
       const int kl = (int)((pp.line0 + lr) % W);
-      if ((kl >= Kh) == s) acc += part[lr * nb + b];
+      if ((kl >= Kh) == s) sum += acc[lr * nb + b];
     }
-    bn.partials[((pp.item * g.groups_per_item + pp.grp) * 2 + s) * nb + b] = acc;
+    bn.partials[((pp.item * g.groups_per_item + pp.grp) * 2 + s) * nb + b] = sum;
   }
 }
 
@@ -624,7 +705,7 @@ __global__ void k_lognormal_poisson(const T* __restrict__ fields, int64_t count,
                                     double nbar, const float* __restrict__ mask, uint32_t k0, uint32_t k1,
                                     uint32_t rid, uint64_t first_real, T* __restrict__ delta,
                                     int32_t* __restrict__ counts, unsigned long long* __restrict__ ntot,
-                                    uint32_t* flags) {
+                                    const double* __restrict__ inv, uint32_t* flags) {
   __shared__ unsigned long long acc;
   const int64_t blocks_per_map = (ncells + blockDim.x - 1) / blockDim.x;
   const int64_t k = blockIdx.x / blocks_per_map;
@@ -646,7 +727,7 @@ __global__ void k_lognormal_poisson(const T* __restrict__ fields, int64_t count,
       for (int c = 0; c < K; ++c) {
         const Words4 w = philox4x32_10((uint32_t)cell, (uint32_t)(rr >> 1), rid, 1u + (uint32_t)c, k0, k1);
         const double u = (rr & 1) ? unit52(w.x2, w.x3) : unit52(w.x0, w.x1);
-        n += poisson_chunk(u, chunk_mean(mu, c, K), flags);
+        n += poisson_chunk(u, chunk_mean(mu, c, K), inv, nullptr, flags);
       }
     }
     if (delta) delta[k * ncells + cell] = d;
@@ -751,13 +832,16 @@ hipError_t launch_lambda_stats(const double* lam, int ndim, const int32_t* O, in
   return hipGetLastError();
 }
 
-hipError_t launch_sqrt_table(const double* lam, int64_t n, double inv_cells, int prec, void* out, hipStream_t s) {
+hipError_t launch_sqrt_table(const double* lam, int ndim, const int32_t* O, double inv_cells, int prec, void* out,
+                             hipStream_t s) {
+  (void)ndim;
+  const int64_t n = (int64_t)O[0] * O[1] * O[2];
   const int blocks = (int)((n + 255) / 256 < 65536 ? (n + 255) / 256 : 65536);
   if (prec == 0)
-    hipLaunchKernelGGL(k_sqrt_table<float>, dim3(blocks), dim3(256), 0, s, lam, n, inv_cells,
+    hipLaunchKernelGGL(k_sqrt_table<float>, dim3(blocks), dim3(256), 0, s, lam, O[0], O[1], O[2], inv_cells,
                        static_cast<float*>(out));
   else
-    hipLaunchKernelGGL(k_sqrt_table<double>, dim3(blocks), dim3(256), 0, s, lam, n, inv_cells,
+    hipLaunchKernelGGL(k_sqrt_table<double>, dim3(blocks), dim3(256), 0, s, lam, O[0], O[1], O[2], inv_cells,
                        static_cast<double*>(out));
   return hipGetLastError();
 }
@@ -867,7 +951,8 @@ hipError_t launch_pair_forward(int prec, const LineGeom& g, const FftDesc& f, co
 template <typename T>
 static void bin_pass_t(bool mix, const LineGeom& g, const FftDesc& f, const BinArgs& b, const void* in,
                        hipStream_t s) {
-  const size_t lds = lines_lds_bytes(g, sizeof(cpx<T>)) + (size_t)g.R * b.nb * sizeof(double);
+  const size_t lds = lines_lds_bytes(g, sizeof(cpx<T>)) + (size_t)g.R * b.nb * sizeof(double) +
+                     (size_t)g.R * g.nlanes * sizeof(RunEnds);
   const cpx<T>* i = static_cast<const cpx<T>*>(in);
   if (mix)
     CE_LAUNCH((k_bin_pass<T, true>), pass_grid(g), pass_block(g), lds, s, g, f, b, i);
@@ -898,17 +983,17 @@ hipError_t launch_bin_reduce(const double* partials, int64_t nitems, int64_t gro
 hipError_t launch_lognormal_poisson(int prec, const void* fields, int64_t count, int64_t ncells, double s2half,
                                     double nbar, const float* mask, uint32_t k0, uint32_t k1, uint32_t rid,
                                     uint64_t first_real, void* delta, int32_t* counts, unsigned long long* ntot,
-                                    uint32_t* flags, hipStream_t s) {
+                                    const double* inv, uint32_t* flags, hipStream_t s) {
   const int64_t bpm = (ncells + 255) / 256;
   const dim3 grid((unsigned)(bpm * count));
   if (prec == 0)
     hipLaunchKernelGGL(k_lognormal_poisson<float>, grid, dim3(256), 0, s, static_cast<const float*>(fields), count,
                        ncells, s2half, nbar, mask, k0, k1, rid, first_real, static_cast<float*>(delta), counts, ntot,
-                       flags);
+                       inv, flags);
   else
     hipLaunchKernelGGL(k_lognormal_poisson<double>, grid, dim3(256), 0, s, static_cast<const double*>(fields),
                        count, ncells, s2half, nbar, mask, k0, k1, rid, first_real, static_cast<double*>(delta),
-                       counts, ntot, flags);
+                       counts, ntot, inv, flags);
   return hipGetLastError();
 }
 
