@@ -106,6 +106,14 @@ def parse():
     ap.add_argument("--lines", default="",
                     help="schedule: max lines per workgroup for noise,inner,last,bins (0 = automatic)")
     ap.add_argument("--noise-order", type=int, default=-1, help="schedule: noise-pass tile order (0/1)")
+    ap.add_argument("--batch-requests", type=int, default=4096,
+                    help="requests of the uneven-batch leg (mixed 2-D sides 32..512); 0 to skip")
+    ap.add_argument("--batch-reps", type=int, default=5)
+    ap.add_argument("--serve-rates", default="500,1000,2000",
+                    help="offered request rates (1/s) of the open-loop serving leg; empty to skip")
+    ap.add_argument("--serve-seconds", type=float, default=4.0, help="arrival window per rate")
+    ap.add_argument("--serve-warmup", type=float, default=1.0, help="arrivals before the window (not counted)")
+    ap.add_argument("--serve-slots", type=int, default=4)
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="also run a plain device copy of this size (for counter calibration)")
     return ap.parse_args()
@@ -183,6 +191,131 @@ def cpu_oracle_sample(w, seconds):
                 sample="%d pairs (%d realizations) of the timed workload, full pipeline incl. covariance; "
                        "plan %.1f s excluded" % (pairs, 2 * pairs, t_plan),
                 seconds=dt)
+
+
+def uneven_batch_leg(b, torch, nreq, reps):
+    """The uneven batch (4096 requests of 2 realizations, 2-D sides 32..512 step 16, each with its
+    own two-point function) through ce_pipeline_run_batch, FP32 and FP64 on identical Philox
+    streams; plans are built before the timed region.  Also the same requests as one
+    ce_pipeline_run call each (FP32), for the batching gain."""
+    import numpy as np
+    from synth import workloads
+    reqs = workloads.uneven_batch(nreq)
+    ctx = b.ctx_create(0)
+    out = dict(requests=len(reqs), realizations=2 * len(reqs),
+               distinct_shapes=len({r["n"] for r in reqs}))
+    try:
+        for prec, tag, cb in ((b.F32, "f32", 28), (b.F64, "f64", 52)):
+            t0 = time.perf_counter()
+            plans = [b.plan_embedding(ctx, r["n"], r["h"], r["xi"], prec) for r in reqs]
+            plan_s = time.perf_counter() - t0
+            items, alg = [], 0
+            for r, p in zip(reqs, plans):
+                R, nb = r["realizations"], r["nbins"]
+                items.append(dict(plan=p, seed=r["seed"], request_id=r["request_id"], count=R, nbar=r["nbar"],
+                                  nbins=nb, out_pk=torch.empty(R * nb, dtype=torch.float64, device="cuda"),
+                                  out_counts=torch.empty(R * p.cells, dtype=torch.int32, device="cuda"),
+                                  out_ntot=torch.empty(R, dtype=torch.int64, device="cuda"),
+                                  out_cov=torch.empty(nb * nb, dtype=torch.float64, device="cuda")))
+                alg += cb * p.cells * R
+            b.pipeline_run_batch(ctx, items)
+            torch.cuda.synchronize()
+            if b.ctx_check(ctx) != 0:
+                raise RuntimeError("device flagged a sampler condition in the uneven batch")
+            times = []
+            for _ in range(reps):
+                t0 = time.perf_counter()
+                b.pipeline_run_batch(ctx, items)
+                torch.cuda.synchronize()
+                times.append(time.perf_counter() - t0)
+            ms = 1e3 * float(np.median(times))
+            leg = dict(value=round(2 * len(reqs) / (ms * 1e-3), 1), unit="realizations/s", ms_per_batch=round(ms, 3),
+                       alg_GB=round(alg / 1e9, 3), alg_GBs=round(alg / (ms * 1e-3) / 1e9, 1),
+                       hbm_frac=round(alg / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4), plan_s=round(plan_s, 2))
+            if prec == b.F32:
+                sub = items[:512]
+                for it in sub[:8]:
+                    b.pipeline_run(ctx, it["plan"], it["seed"], it["request_id"], 0, it["count"], it["nbar"],
+                                   it["nbins"], it["out_pk"], out_counts=it["out_counts"], out_ntot=it["out_ntot"],
+                                   out_cov=it["out_cov"])
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                for it in sub:
+                    b.pipeline_run(ctx, it["plan"], it["seed"], it["request_id"], 0, it["count"], it["nbar"],
+                                   it["nbins"], it["out_pk"], out_counts=it["out_counts"], out_ntot=it["out_ntot"],
+                                   out_cov=it["out_cov"])
+                torch.cuda.synchronize()
+                dt = time.perf_counter() - t0
+                leg["unbatched"] = dict(value=round(2 * len(sub) / dt, 1), unit="realizations/s",
+                                        sample="first %d requests, one ce_pipeline_run each" % len(sub))
+            out[tag] = leg
+            del items
+            for p in plans:
+                p.release()
+    finally:
+        b.ctx_destroy(ctx)
+    return out
+
+
+def serving_leg(b, torch, rate, seconds, warmup, slots):
+    """Open-loop replay of a Poisson arrival trace of mixed 2-D/3-D requests through the request
+    server (continuous batching, plan cache).  Requests arriving in the first `warmup` seconds
+    warm the plan cache and are not counted.  Latency = completion seen by the server's scheduler
+    minus submission; submissions lag the nominal arrival by `max_lateness_ms` at most."""
+    import numpy as np
+    from synth import workloads
+    trace = workloads.serving_trace(rate=rate, duration=warmup + seconds, seed=5)
+    nb = 32
+    offs, tot = [], 0
+    for r in trace:
+        offs.append(tot)
+        tot += r["realizations"] * nb + r["realizations"] + (nb * nb if r["realizations"] >= 2 else 0)
+    pool = torch.empty(max(tot, 1), dtype=torch.float64, device="cuda")
+    server = b.server_create(0, slots=slots)
+    pending = {}
+    lat, real_done, failed, lateness = [], 0, 0, 0.0
+    t_start = time.perf_counter()
+    i = 0
+    backlog_at_end = None
+    try:
+        while i < len(trace) or pending:
+            now = time.perf_counter() - t_start
+            while i < len(trace) and trace[i]["arrival"] <= now:
+                r = trace[i]
+                R = r["realizations"]
+                o = offs[i]
+                pk = pool[o:o + R * nb]
+                ntot = pool[o + R * nb:o + R * nb + R].view(torch.int64)
+                cov = pool[o + R * nb + R:o + R * nb + R + nb * nb] if R >= 2 else None
+                t = b.server_submit(server, r["n"], r["h"], r["xi"], b.F32, r["seed"], r["request_id"], R,
+                                    r["nbar"], nb, pk, out_ntot=ntot, out_cov=cov)
+                lateness = max(lateness, now - r["arrival"])
+                pending[t] = (r["arrival"] >= warmup, R)
+                i += 1
+            if backlog_at_end is None and i == len(trace):
+                backlog_at_end = len(pending)
+            for t, st, status, ms in b.server_drain(server):
+                counted, R = pending.pop(t)
+                if counted:
+                    if st == 2:
+                        lat.append(ms)
+                        real_done += R
+                    else:
+                        failed += 1
+            time.sleep(0.0002)
+        wall = time.perf_counter() - t_start
+        stats = b.server_stats(server)
+    finally:
+        b.server_destroy(server)
+    counted = [r for r in trace if r["arrival"] >= warmup]
+    span = max(wall - warmup, 1e-9)
+    return dict(offered_rate=rate, requests=len(counted), completed=len(lat), failed=failed,
+                realizations_per_s=round(real_done / span, 1), requests_per_s=round(len(lat) / span, 1),
+                p50_ms=round(float(np.percentile(lat, 50)), 3) if lat else None,
+                p99_ms=round(float(np.percentile(lat, 99)), 3) if lat else None,
+                drain_s=round(wall - (warmup + seconds), 3), backlog_at_last_arrival=backlog_at_end,
+                max_lateness_ms=round(1e3 * lateness, 3), plan_cache_hits=stats["cache_hits"],
+                plan_cache_misses=stats["cache_misses"], admission_stalls=stats["admission_stalls"])
 
 
 def main():
@@ -331,6 +464,27 @@ def main():
 
     plan.release()
     b.ctx_destroy(ctx)
+
+    if args.batch_requests:
+        out["uneven_batch"] = uneven_batch_leg(b, torch, args.batch_requests, args.batch_reps)
+        print("uneven batch %s" % json.dumps(out["uneven_batch"]), file=sys.stderr, flush=True)
+
+    if args.serve_rates:
+        legs = []
+        for rate in [float(x) for x in args.serve_rates.split(",")]:
+            leg = serving_leg(b, torch, rate, args.serve_seconds, args.serve_warmup, args.serve_slots)
+            legs.append(leg)
+            print("serving leg %s" % json.dumps(leg), file=sys.stderr, flush=True)
+        # sustainable: the backlog when the last request arrives stays within the slots and the
+        # queue drains within 0.5 s of it
+        ok = [g["offered_rate"] for g in legs
+              if g["backlog_at_last_arrival"] is not None and g["backlog_at_last_arrival"] <= 2 * args.serve_slots
+              and g["drain_s"] <= 0.5 and g["failed"] == 0]
+        out["serving"] = dict(trace="open-loop Poisson arrivals, 50/50 2-D (sides 64..2048) / 3-D (32..256), "
+                                    "sides 16 x 7-smooth log-uniform, 1..64 realizations log-uniform, 16 two-point "
+                                    "functions, nbar in {0.1,0.3,1,5}, 32 shells, FP32; seed 5",
+                              window_s=args.serve_seconds, warmup_s=args.serve_warmup, slots=args.serve_slots,
+                              legs=legs, max_sustainable_rate_tested=max(ok) if ok else None)
 
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_oracle_sample(w, args.cpu_seconds)

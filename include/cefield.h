@@ -106,6 +106,10 @@ void ce_ctx_destroy(ce_ctx* ctx);
  * draw exceeded its step bound or a counts map had N_tot = 0 since the last check. */
 ce_status ce_ctx_check(ce_ctx* ctx, void* stream);
 
+/* Free the ctx's cached pipeline scratch (it is allocated again on the next call that needs
+ * it).  Waits for the device first.  Errors: CE_E_INVALID, CE_E_DEVICE. */
+ce_status ce_ctx_trim(ce_ctx* ctx);
+
 /* Context options.
  * CE_OPT_UNPRUNED (default 0): when non-zero, ce_generate_fields computes every output of every
  * inverse pass on the full (2N)^d embedding and crops to the survey only when storing -- the
@@ -219,6 +223,101 @@ ce_status ce_pipeline_run(ce_ctx* ctx, const ce_plan* plan, uint64_t seed, uint3
                           void* out_fields, void* out_delta, int32_t* out_counts,
                           int64_t* out_ntot, double* out_pk, double* out_cov, double* out_cnorm,
                           void* stream);
+
+/* Batched form of ce_pipeline_run: many requests, each with its own plan (geometry, xi,
+ * precision), seed, request id, realizations, nbar and outputs.  Requests that share
+ * (ndim, N, h, precision, nbins) form a group that runs each pass of the pipeline as one launch
+ * over all the group's pairs, every pair reading its own sqrt(lambda) octant, Philox key and
+ * counter words, sigma^2 and nbar from a descriptor table; so a batch of many small requests
+ * costs a few launches per distinct shape instead of a few per request.  Every item's results
+ * equal, bit for bit, those of ce_pipeline_run called for that item alone with the same ctx
+ * options.  Fields and delta are not returned in this form.  All items must be valid for
+ * ce_pipeline_run (nothing is launched otherwise).  Errors: as ce_pipeline_run. */
+typedef struct {
+  const ce_plan* plan;
+  uint64_t seed;
+  uint32_t request_id;
+  uint64_t first_realization;  /* even */
+  int64_t count;
+  double nbar;
+  int32_t nbins;
+  double* out_pk;       /* device, count x nbins */
+  int32_t* out_counts;  /* device, nullable, count x N^d */
+  int64_t* out_ntot;    /* device, nullable, count */
+  double* out_cov;      /* device, nullable, nbins^2 (written when count >= 2) */
+  double* out_cnorm;    /* device, nullable, nbins^2 (written when count >= 2) */
+} ce_batch_item;
+ce_status ce_pipeline_run_batch(ce_ctx* ctx, const ce_batch_item* items, int64_t n, void* stream);
+
+/* Captured form of ce_pipeline_run (HIP graph).  Creation runs the pipeline once (sizing a
+ * private scratch area owned by the graph, so nothing is allocated while replaying), then
+ * captures it with the given output buffers.  Each ce_pipeline_graph_launch replays it on
+ * `stream` and then advances the realizations by `count`: launch k (k = 0, 1, ...) produces
+ * realizations first_realization + k*count .. + count - 1 into the same output buffers (read them
+ * before the next launch).  count must be even.  The outputs and the plan must stay valid while
+ * the graph exists; replays of one graph must not overlap.  Errors: as ce_pipeline_run,
+ * CE_E_DEVICE if capture fails. */
+typedef struct ce_graph ce_graph;
+ce_status ce_pipeline_graph_create(ce_ctx* ctx, const ce_plan* plan, uint64_t seed, uint32_t request_id,
+                                   uint64_t first_realization, int64_t count, double nbar, int32_t nbins,
+                                   void* out_fields, void* out_delta, int32_t* out_counts, int64_t* out_ntot,
+                                   double* out_pk, double* out_cov, double* out_cnorm, ce_graph** out);
+ce_status ce_pipeline_graph_launch(ce_graph* graph, void* stream);
+void ce_pipeline_graph_destroy(ce_graph* graph);
+
+/* Request loop (continuous batching).  A server owns `slots` contexts with one stream each,
+ * a plan context and an LRU cache of plans (sqrt(lambda) octants) keyed by (geometry, xi,
+ * precision).  ce_server_submit queues a request and returns at once; a scheduler thread
+ * admits the queue head (FIFO) as soon as a slot is free and its device footprint -- pipeline
+ * scratch, plus the plan if it is not cached -- fits hbm_budget_bytes (evicting unused plans
+ * first); admitted requests run ce_pipeline_run concurrently on their slots' streams.  Every
+ * request's results equal those of the same ce_pipeline_run issued alone (the computation of
+ * a request does not depend on what else runs).  A failing request (for example CE_E_NOT_PSD
+ * at plan time) fails alone.  The output buffers of a request must stay valid until it is done.
+ * Latency = completion observed by the scheduler minus the submit time (host steady clock). */
+typedef struct ce_server ce_server;
+typedef struct {
+  int32_t slots;            /* requests in flight at once (default 4, at most 32) */
+  size_t hbm_budget_bytes;  /* bound on slot scratch + cached plans (0: 64 GiB) */
+  size_t plan_cache_bytes;  /* bound on cached plans (0: 8 GiB) */
+} ce_server_config;
+typedef struct {
+  ce_geometry geom;
+  ce_xi xi;                 /* a table is copied at submit time */
+  ce_precision precision;
+  uint64_t seed;
+  uint32_t request_id;
+  int64_t realizations;     /* realizations 0 .. realizations-1 of this (seed, request_id) */
+  double nbar;
+  int32_t nbins;
+  double* out_pk;           /* device, realizations x nbins */
+  int32_t* out_counts;      /* device, nullable, realizations x N^d */
+  int64_t* out_ntot;        /* device, nullable, realizations */
+  double* out_cov;          /* device, nullable, nbins^2 (used when realizations >= 2) */
+} ce_request;
+typedef struct {
+  int64_t submitted, completed, failed, cache_hits, cache_misses, admission_stalls, queued;
+  double p50_ms, p99_ms;    /* over completed requests */
+  double elapsed_s;         /* since the server was created */
+  size_t held_bytes;        /* slot scratch + cached plans accounted by the admission */
+} ce_server_stats;
+ce_status ce_server_create(int device, const ce_server_config* cfg, ce_server** out);
+ce_status ce_server_submit(ce_server* server, const ce_request* request, uint64_t* ticket);
+/* Non-blocking.  *state: 0 queued, 1 running, 2 done, 3 failed, 4 cancelled; once a finished
+ * state (>= 2) has been returned the ticket is forgotten. */
+ce_status ce_server_poll(ce_server* server, uint64_t ticket, int32_t* state, ce_status* status,
+                         double* latency_ms);
+/* Non-blocking.  Returns in completion order up to `max` requests that reached a final state
+ * (done, failed, cancelled) and were not yet returned by ce_server_poll or an earlier drain:
+ * their tickets (required), states, statuses and latencies (nullable arrays of `max`), and
+ * their number in *n.  Drained tickets are forgotten. */
+ce_status ce_server_drain(ce_server* server, int32_t max, uint64_t* tickets, int32_t* states, ce_status* statuses,
+                          double* latency_ms, int32_t* n);
+/* Cancel a request that is still queued (CE_E_INVALID otherwise). */
+ce_status ce_server_cancel(ce_server* server, uint64_t ticket);
+ce_status ce_server_stats_read(ce_server* server, ce_server_stats* out);
+/* Stops admitting, cancels queued requests, waits for running ones, frees everything. */
+void ce_server_destroy(ce_server* server);
 
 /* Shell table of a cubic grid on the host: N_b and mean |k| per shell (same rule as
  * ce_estimate_pk).  nmodes, kmean: host arrays of nbins.  Errors: CE_E_INVALID, CE_E_UNSUPPORTED. */

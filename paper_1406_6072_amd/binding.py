@@ -44,6 +44,28 @@ class PlanInfo(ctypes.Structure):
                 ("n_negative", c_i64), ("n_clamped", c_i64), ("device_bytes", c_size)]
 
 
+class BatchItem(ctypes.Structure):
+    _fields_ = [("plan", c_void_p), ("seed", c_u64), ("request_id", c_u32), ("first_realization", c_u64),
+                ("count", c_i64), ("nbar", c_f64), ("nbins", c_i32), ("out_pk", c_void_p),
+                ("out_counts", c_void_p), ("out_ntot", c_void_p), ("out_cov", c_void_p), ("out_cnorm", c_void_p)]
+
+
+class ServerConfig(ctypes.Structure):
+    _fields_ = [("slots", c_i32), ("hbm_budget_bytes", c_size), ("plan_cache_bytes", c_size)]
+
+
+class Request(ctypes.Structure):
+    _fields_ = [("geom", Geometry), ("xi", Xi), ("precision", c_i32), ("seed", c_u64), ("request_id", c_u32),
+                ("realizations", c_i64), ("nbar", c_f64), ("nbins", c_i32), ("out_pk", c_void_p),
+                ("out_counts", c_void_p), ("out_ntot", c_void_p), ("out_cov", c_void_p)]
+
+
+class ServerStats(ctypes.Structure):
+    _fields_ = [("submitted", c_i64), ("completed", c_i64), ("failed", c_i64), ("cache_hits", c_i64),
+                ("cache_misses", c_i64), ("admission_stalls", c_i64), ("queued", c_i64), ("p50_ms", c_f64),
+                ("p99_ms", c_f64), ("elapsed_s", c_f64), ("held_bytes", c_size)]
+
+
 def _sig(name, res, *args):
     f = getattr(_lib, name)
     f.restype = res
@@ -56,6 +78,7 @@ _version = _sig("ce_version", ctypes.c_char_p)
 _ctx_create = _sig("ce_ctx_create", c_i32, c_i32, c_size, ctypes.POINTER(c_void_p))
 _ctx_destroy = _sig("ce_ctx_destroy", None, c_void_p)
 _ctx_check = _sig("ce_ctx_check", c_i32, c_void_p, c_void_p)
+_ctx_trim = _sig("ce_ctx_trim", c_i32, c_void_p)
 _ctx_set_option = _sig("ce_ctx_set_option", c_i32, c_void_p, c_i32, c_i64)
 _ctx_set_profiling = _sig("ce_ctx_set_profiling", c_i32, c_void_p, c_i32)
 _ctx_profile_read = _sig("ce_ctx_profile_read", c_i32, c_void_p, c_i32, c_void_p, c_void_p, c_void_p,
@@ -74,16 +97,33 @@ _estimate_pk = _sig("ce_estimate_pk", c_i32, c_void_p, ctypes.POINTER(Geometry),
 _pk_covariance = _sig("ce_pk_covariance", c_i32, c_void_p, c_void_p, c_i64, c_i32, c_void_p, c_void_p, c_void_p)
 _pipeline_run = _sig("ce_pipeline_run", c_i32, c_void_p, c_void_p, c_u64, c_u32, c_u64, c_i64, c_f64, c_i32,
                      c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p)
+_graph_create = _sig("ce_pipeline_graph_create", c_i32, c_void_p, c_void_p, c_u64, c_u32, c_u64, c_i64, c_f64, c_i32,
+                     c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, ctypes.POINTER(c_void_p))
+_graph_launch = _sig("ce_pipeline_graph_launch", c_i32, c_void_p, c_void_p)
+_graph_destroy = _sig("ce_pipeline_graph_destroy", None, c_void_p)
+_pipeline_batch = _sig("ce_pipeline_run_batch", c_i32, c_void_p, ctypes.POINTER(BatchItem), c_i64, c_void_p)
+_server_create = _sig("ce_server_create", c_i32, c_i32, ctypes.POINTER(ServerConfig), ctypes.POINTER(c_void_p))
+_server_submit = _sig("ce_server_submit", c_i32, c_void_p, ctypes.POINTER(Request), ctypes.POINTER(c_u64))
+_server_poll = _sig("ce_server_poll", c_i32, c_void_p, c_u64, ctypes.POINTER(c_i32), ctypes.POINTER(c_i32),
+                    ctypes.POINTER(c_f64))
+_server_cancel = _sig("ce_server_cancel", c_i32, c_void_p, c_u64)
+_server_drain = _sig("ce_server_drain", c_i32, c_void_p, c_i32, c_void_p, c_void_p, c_void_p, c_void_p,
+                     ctypes.POINTER(c_i32))
+_server_stats = _sig("ce_server_stats_read", c_i32, c_void_p, ctypes.POINTER(ServerStats))
+_server_destroy = _sig("ce_server_destroy", None, c_void_p)
 _shell_table = _sig("ce_shell_table", c_i32, ctypes.POINTER(Geometry), c_i32, c_void_p, c_void_p)
 _fft_factors = _sig("ce_fft_factors", c_i32, c_i32, c_void_p, c_void_p)
 _debug_philox = _sig("ce_debug_philox", c_i32, c_u64, c_void_p, c_i64, c_void_p, c_void_p)
 _debug_noise = _sig("ce_debug_noise", c_i32, c_void_p, c_u64, c_u32, c_u64, c_void_p, c_void_p)
 
-EXPORTED = ["ce_status_string", "ce_version", "ce_ctx_create", "ce_ctx_destroy", "ce_ctx_check",
+EXPORTED = ["ce_status_string", "ce_version", "ce_ctx_create", "ce_ctx_destroy", "ce_ctx_check", "ce_ctx_trim",
             "ce_ctx_set_option", "ce_ctx_set_profiling", "ce_ctx_profile_read",
             "ce_plan_embedding", "ce_plan_release", "ce_plan_get_info", "ce_plan_eigenvalues",
             "ce_generate_fields", "ce_lognormal_poisson", "ce_estimate_pk", "ce_pk_covariance",
-            "ce_pipeline_run", "ce_shell_table", "ce_fft_factors", "ce_debug_philox", "ce_debug_noise"]
+            "ce_pipeline_run", "ce_pipeline_run_batch", "ce_pipeline_graph_create", "ce_pipeline_graph_launch",
+            "ce_pipeline_graph_destroy",
+            "ce_server_create", "ce_server_submit", "ce_server_poll", "ce_server_drain", "ce_server_cancel",
+            "ce_server_stats_read", "ce_server_destroy", "ce_shell_table", "ce_fft_factors", "ce_debug_philox", "ce_debug_noise"]
 
 
 class CeError(RuntimeError):
@@ -186,6 +226,10 @@ def ctx_destroy(ctx):
 
 def ctx_check(ctx, stream=None):
     return _ctx_check(ctx, None if stream is None else _stream(stream))
+
+
+def ctx_trim(ctx):
+    _check(_ctx_trim(ctx), "ce_ctx_trim")
 
 
 OPT_UNPRUNED = 1
@@ -324,6 +368,113 @@ def pipeline_run(ctx, plan, seed, request_id, first_realization, count, nbar, nb
                          _ptr(out_cov, torch.float64, nbins * nbins, "out_cov"),
                          _ptr(out_cnorm, torch.float64, nbins * nbins, "out_cnorm"), _stream(stream)),
            "ce_pipeline_run")
+
+
+def pipeline_run_batch(ctx, items, stream=None):
+    """items: dicts with plan, seed, request_id, first_realization, count, nbar, nbins, out_pk and
+    optional out_counts, out_ntot, out_cov, out_cnorm (device tensors)."""
+    arr = (BatchItem * max(len(items), 1))()
+    for k, it in enumerate(items):
+        plan, count, nb = it["plan"], int(it["count"]), int(it["nbins"])
+        a = arr[k]
+        a.plan = plan.handle
+        a.seed, a.request_id = int(it.get("seed", 0)), int(it.get("request_id", 0))
+        a.first_realization, a.count, a.nbar, a.nbins = int(it.get("first_realization", 0)), count, \
+            float(it["nbar"]), nb
+        a.out_pk = _ptr(it["out_pk"], torch.float64, count * nb, "out_pk")
+        a.out_counts = _ptr(it.get("out_counts"), torch.int32, count * plan.cells, "out_counts")
+        a.out_ntot = _ptr(it.get("out_ntot"), torch.int64, count, "out_ntot")
+        a.out_cov = _ptr(it.get("out_cov"), torch.float64, nb * nb, "out_cov")
+        a.out_cnorm = _ptr(it.get("out_cnorm"), torch.float64, nb * nb, "out_cnorm")
+    _check(_pipeline_batch(ctx, arr, len(items), _stream(stream)), "ce_pipeline_run_batch")
+
+
+def pipeline_graph_create(ctx, plan, seed, request_id, first_realization, count, nbar, nbins, out_pk,
+                          out_fields=None, out_delta=None, out_counts=None, out_ntot=None, out_cov=None,
+                          out_cnorm=None):
+    cells = plan.cells
+    g = c_void_p()
+    _check(_graph_create(ctx, plan.handle, int(seed), int(request_id), int(first_realization), int(count),
+                         float(nbar), int(nbins), _ptr(out_fields, plan.dtype, count * cells, "out_fields"),
+                         _ptr(out_delta, plan.dtype, count * cells, "out_delta"),
+                         _ptr(out_counts, torch.int32, count * cells, "out_counts"),
+                         _ptr(out_ntot, torch.int64, count, "out_ntot"),
+                         _ptr(out_pk, torch.float64, count * nbins, "out_pk"),
+                         _ptr(out_cov, torch.float64, nbins * nbins, "out_cov"),
+                         _ptr(out_cnorm, torch.float64, nbins * nbins, "out_cnorm"), ctypes.byref(g)),
+           "ce_pipeline_graph_create")
+    return g
+
+
+def pipeline_graph_launch(graph, stream=None):
+    _check(_graph_launch(graph, _stream(stream)), "ce_pipeline_graph_launch")
+
+
+def pipeline_graph_destroy(graph):
+    _graph_destroy(graph)
+
+
+def server_create(device=0, slots=4, hbm_budget_bytes=0, plan_cache_bytes=0):
+    cfg = ServerConfig(int(slots), int(hbm_budget_bytes), int(plan_cache_bytes))
+    s = c_void_p()
+    _check(_server_create(int(device), ctypes.byref(cfg), ctypes.byref(s)), "ce_server_create")
+    return s
+
+
+def server_submit(server, n, h, xi, precision, seed, request_id, realizations, nbar, nbins, out_pk,
+                  out_counts=None, out_ntot=None, out_cov=None):
+    """Queue one request; returns its ticket.  Output tensors must outlive the request."""
+    cells = 1
+    for x in n:
+        cells *= int(x)
+    r = Request()
+    r.geom = geometry(n, h)
+    x, keep = xi_spec(xi)
+    r.xi = x
+    r.precision = int(precision)
+    r.seed, r.request_id, r.realizations, r.nbar, r.nbins = int(seed), int(request_id), int(realizations), \
+        float(nbar), int(nbins)
+    r.out_pk = _ptr(out_pk, torch.float64, realizations * nbins, "out_pk")
+    r.out_counts = _ptr(out_counts, torch.int32, realizations * cells, "out_counts")
+    r.out_ntot = _ptr(out_ntot, torch.int64, realizations, "out_ntot")
+    r.out_cov = _ptr(out_cov, torch.float64, nbins * nbins, "out_cov")
+    t = c_u64()
+    _check(_server_submit(server, ctypes.byref(r), ctypes.byref(t)), "ce_server_submit")
+    del keep
+    return t.value
+
+
+def server_poll(server, ticket):
+    """(state, status, latency_ms); state 0 queued, 1 running, 2 done, 3 failed, 4 cancelled."""
+    st, status, lat = c_i32(), c_i32(), c_f64()
+    _check(_server_poll(server, int(ticket), ctypes.byref(st), ctypes.byref(status), ctypes.byref(lat)),
+           "ce_server_poll")
+    return st.value, status.value, lat.value
+
+
+def server_drain(server, max_n=4096):
+    """Finished requests in completion order: list of (ticket, state, status, latency_ms)."""
+    t = (c_u64 * max_n)()
+    st = (c_i32 * max_n)()
+    status = (c_i32 * max_n)()
+    lat = (c_f64 * max_n)()
+    n = c_i32()
+    _check(_server_drain(server, max_n, t, st, status, lat, ctypes.byref(n)), "ce_server_drain")
+    return [(t[i], st[i], status[i], lat[i]) for i in range(n.value)]
+
+
+def server_cancel(server, ticket):
+    return _server_cancel(server, int(ticket))
+
+
+def server_stats(server):
+    st = ServerStats()
+    _check(_server_stats(server, ctypes.byref(st)), "ce_server_stats_read")
+    return {k: getattr(st, k) for k, _ in ServerStats._fields_}
+
+
+def server_destroy(server):
+    _server_destroy(server)
 
 
 def shell_table(n, h, nbins):

@@ -65,6 +65,22 @@ bool factor_length(int L, std::vector<int>& rad) {
   int e = 0;
   while ((1 << e) < n) ++e;
   std::vector<int> p2;
+  if (!odd.empty()) {
+    // mixed lengths run one butterfly at a time with the radix in registers: the power of two
+    // goes in radices of at most 8 (a radix-16 butterfly next to the odd ones spills)
+    int k = e;
+    if (k % 3 == 1 && k >= 4) {
+      p2.push_back(4);
+      p2.push_back(4);
+      k -= 4;
+    }
+    for (; k >= 3; k -= 3) p2.push_back(8);
+    if (k == 2) p2.push_back(4);
+    if (k == 1) p2.push_back(2);
+    for (int p : odd) rad.push_back(p);
+    for (int p : p2) rad.push_back(p);
+    return rad.size() <= (size_t)kMaxStages;
+  }
   int n4 = e / 4, rem = e % 4;
   if (rem == 1 && n4 >= 1) {
     for (int i = 0; i < n4 - 1; ++i) p2.push_back(16);
@@ -146,6 +162,10 @@ struct ce_ctx {
     size_t n = 0;
   };
   Buf ws[8];
+  // pinned host staging of batch tables; `staged` is recorded after the copy that reads it
+  void* pin = nullptr;
+  size_t pin_n = 0;
+  hipEvent_t staged = nullptr;
 
   // per-kernel timing with HIP events on the launch stream
   struct ProfRec {
@@ -193,6 +213,13 @@ struct ce_ctx {
     held += bytes;
     return CE_OK;
   }
+  // host -> device copy of a constant table on the context's own non-blocking stream (does
+  // not wait for work that other streams have in flight)
+  ce_status upload(void* dst, const void* src, size_t bytes) {
+    CE_HIP(hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, own));
+    CE_HIP(hipStreamSynchronize(own));
+    return CE_OK;
+  }
   void release(void* p, size_t bytes) {
     if (p) {
       (void)hipFree(p);
@@ -234,11 +261,11 @@ struct ce_ctx {
     void* p = nullptr;
     CE_TRY(alloc(&p, elem * L));
     if (prec) {
-      CE_HIP(hipMemcpy(p, d.data(), elem * L, hipMemcpyHostToDevice));
+      CE_TRY(upload(p, d.data(), elem * L));
     } else {
       std::vector<float> f(2 * (size_t)L);
       for (size_t i = 0; i < f.size(); ++i) f[i] = (float)d[i];
-      CE_HIP(hipMemcpy(p, f.data(), elem * L, hipMemcpyHostToDevice));
+      CE_TRY(upload(p, f.data(), elem * L));
     }
     tw[{L, prec}] = p;
     *out = p;
@@ -271,11 +298,11 @@ struct ce_ctx {
     void* p = nullptr;
     CE_TRY(alloc(&p, elem * n));
     if (prec) {
-      CE_HIP(hipMemcpy(p, d.data(), elem * n, hipMemcpyHostToDevice));
+      CE_TRY(upload(p, d.data(), elem * n));
     } else {
       std::vector<float> f(d.size());
       for (size_t i = 0; i < f.size(); ++i) f[i] = (float)d[i];
-      CE_HIP(hipMemcpy(p, f.data(), elem * n, hipMemcpyHostToDevice));
+      CE_TRY(upload(p, f.data(), elem * n));
     }
     stw[{L, prec}] = p;
     *out = p;
@@ -378,7 +405,7 @@ ce_status device_shells(ce_ctx* ctx, int N, int ndim, double h, int nb, int64_t*
     shell_table_host(N, ndim, 1.0, nb, nm, km);
     void* p = nullptr;
     CE_TRY(ctx->alloc(&p, sizeof(int64_t) * nb));
-    CE_HIP(hipMemcpy(p, nm.data(), sizeof(int64_t) * nb, hipMemcpyHostToDevice));
+    CE_TRY(ctx->upload(p, nm.data(), sizeof(int64_t) * nb));
     it = ctx->shells.emplace(key, std::make_pair(static_cast<int64_t*>(p), km)).first;
   }
   *nm_dev = it->second.first;
@@ -420,11 +447,12 @@ ce_status ce_ctx_create(int device, size_t hbm_budget_bytes, ce_ctx** out) {
   auto ctx = std::make_unique<ce_ctx>();
   ctx->device = device;
   ctx->budget = hbm_budget_bytes;
-  CE_HIP(hipStreamCreate(&ctx->own));
+  CE_HIP(hipStreamCreateWithFlags(&ctx->own, hipStreamNonBlocking));
   void* f = nullptr;
   CE_TRY(ctx->alloc(&f, 16));
   ctx->flags = static_cast<uint32_t*>(f);
-  CE_HIP(hipMemset(ctx->flags, 0, 16));
+  CE_HIP(hipMemsetAsync(ctx->flags, 0, 16, ctx->own));
+  CE_HIP(hipStreamSynchronize(ctx->own));
   {
     std::vector<double> inv(kPoissonSteps + 1);
     inv[0] = 0.0;
@@ -432,7 +460,7 @@ ce_status ce_ctx_create(int device, size_t hbm_budget_bytes, ce_ctx** out) {
     void* p = nullptr;
     CE_TRY(ctx->alloc(&p, sizeof(double) * inv.size()));
     ctx->inv = static_cast<double*>(p);
-    CE_HIP(hipMemcpy(ctx->inv, inv.data(), sizeof(double) * inv.size(), hipMemcpyHostToDevice));
+    CE_TRY(ctx->upload(ctx->inv, inv.data(), sizeof(double) * inv.size()));
   }
   *out = ctx.release();
   return CE_OK;
@@ -454,8 +482,26 @@ void ce_ctx_destroy(ce_ctx* ctx) {
   }
   if (ctx->flags) (void)hipFree(ctx->flags);
   if (ctx->inv) (void)hipFree(ctx->inv);
+  if (ctx->pin) (void)hipHostFree(ctx->pin);
+  if (ctx->staged) (void)hipEventDestroy(ctx->staged);
   if (ctx->own) (void)hipStreamDestroy(ctx->own);
   delete ctx;
+}
+
+ce_status ce_ctx_trim(ce_ctx* ctx) {
+  if (!ctx) return CE_E_INVALID;
+  std::lock_guard<std::mutex> lock(ctx->mu);
+  CE_HIP(hipSetDevice(ctx->device));
+  bool any = false;
+  for (auto& b : ctx->ws) any |= b.p != nullptr;
+  if (!any) return CE_OK;
+  CE_HIP(hipDeviceSynchronize());
+  for (auto& b : ctx->ws) {
+    ctx->release(b.p, b.n);
+    b.p = nullptr;
+    b.n = 0;
+  }
+  return CE_OK;
 }
 
 ce_status ce_ctx_set_profiling(ce_ctx* ctx, int32_t enable) {
@@ -509,11 +555,12 @@ ce_status ce_ctx_check(ce_ctx* ctx, void* stream) {
   if (!ctx) return CE_E_INVALID;
   CE_HIP(hipSetDevice(ctx->device));
   hipStream_t s = stream ? as_stream(stream) : ctx->last;
-  CE_HIP(hipStreamSynchronize(s));
   uint32_t f = 0;
-  CE_HIP(hipMemcpy(&f, ctx->flags, sizeof(f), hipMemcpyDeviceToHost));
+  CE_HIP(hipMemcpyAsync(&f, ctx->flags, sizeof(f), hipMemcpyDeviceToHost, s));
+  CE_HIP(hipStreamSynchronize(s));
   if (f) {
-    CE_HIP(hipMemset(ctx->flags, 0, sizeof(uint32_t)));
+    CE_HIP(hipMemsetAsync(ctx->flags, 0, sizeof(uint32_t), s));
+    CE_HIP(hipStreamSynchronize(s));
     return CE_E_SAMPLER;
   }
   return CE_OK;
@@ -714,14 +761,19 @@ NoiseArgs noise_args(const ce_plan* p, uint64_t seed, uint32_t rid, uint64_t fir
 // Inverse passes for `npairs` pairs starting at pair index first_pair, through the
 // last pass whose epilogue is `epi` (rows along the last axis).
 ce_status run_inverse(ce_ctx* ctx, const ce_plan* p, const InverseSetup& fs, uint64_t seed, uint32_t rid,
-                      uint64_t first_pair, int64_t npairs, RowEpi epi, hipStream_t s) {
+                      uint64_t first_pair, int64_t npairs, RowEpi epi, hipStream_t s,
+                      const unsigned long long* pair_base = nullptr, const PairDesc* desc = nullptr) {
   const size_t elem = p->prec ? 16 : 8;
   const int d = p->ndim;
   // the unpruned comparator form keeps all M outputs of every axis and crops at the end
   const bool full = ctx->unpruned && epi.mode == 1;
   const int64_t M0 = p->M[0], M1 = p->M[1], M2 = d == 3 ? p->M[2] : 1;
   const int64_t K0 = full ? M0 : p->n[0], K1 = full ? M1 : p->n[1];
-  const NoiseArgs na = noise_args(p, seed, rid, first_pair);
+  NoiseArgs na = noise_args(p, seed, rid, first_pair);
+  na.pair_base = pair_base;
+  na.desc = desc;
+  epi.pair_base = pair_base;
+  epi.desc = desc;
   // pass 1: axis 0 with the noise prologue; lines b over the remaining axes
   const int64_t B1 = M1 * M2;
   const int64_t y1_item = K0 * B1;
@@ -813,9 +865,228 @@ int64_t chunk_pairs(const ce_plan* p, int64_t npairs, size_t cap) {
 
 constexpr size_t kScratchCap = size_t(8) << 30;
 
+// The fused pipeline on stream s (ctx locked by the caller).  pair_base (nullable) is a
+// device counter added to every pair index (graph replays advance it).
+ce_status pipeline_impl(ce_ctx* ctx, const ce_plan* plan, uint64_t seed, uint32_t request_id,
+                        uint64_t first_realization, int64_t count, double nbar, int32_t nbins, void* out_fields,
+                        void* out_delta, int32_t* out_counts, int64_t* out_ntot, double* out_pk, double* out_cov,
+                        double* out_cnorm, const unsigned long long* pair_base, hipStream_t s) {
+  InverseSetup fs;
+  CE_TRY(setup_ffts(ctx, plan, fs));
+  const int ndim = plan->ndim;
+  const int64_t ncells = survey_cells(plan);
+  const int Nl = plan->n[ndim - 1];
+  const int W = 2 * (Nl / 2 + 1);
+  const int64_t rows = ncells / Nl;
+  const size_t elem = plan->prec ? 16 : 8;
+  const size_t relem = plan->prec ? 8 : 4;
+  const int64_t npairs = (count + 1) / 2;
+  const int64_t cp = chunk_pairs(plan, npairs, kScratchCap);
+  void* acc = nullptr;
+  CE_TRY(ctx->scratch(4, sizeof(unsigned long long) * (size_t)(2 * npairs), &acc));
+  auto* ntot = static_cast<unsigned long long*>(acc);
+  CE_HIP(launch_zero_u64(ntot, 2 * npairs, s));
+  int64_t* nm = nullptr;
+  const std::vector<double>* km = nullptr;
+  CE_TRY(device_shells(ctx, plan->n[0], ndim, plan->h[0], nbins, &nm, &km));
+  const double norm = std::pow(plan->h[0], ndim) / (double)ncells;
+  for (int64_t j = 0; j < npairs; j += cp) {
+    const int64_t np = std::min(cp, npairs - j);
+    void* H = nullptr;
+    CE_TRY(ctx->scratch(2, elem * (size_t)(np * rows * W), &H));
+    RowEpi e;
+    e.mode = 2;
+    e.ncells = ncells;
+    e.count = std::min<int64_t>(count - 2 * j, 2 * np);
+    e.real_off = 0;
+    e.fields = out_fields ? static_cast<char*>(out_fields) + relem * (size_t)(2 * j * ncells) : nullptr;
+    e.delta = out_delta ? static_cast<char*>(out_delta) + relem * (size_t)(2 * j * ncells) : nullptr;
+    e.counts = out_counts ? out_counts + 2 * j * ncells : nullptr;
+    e.ntot = ntot + 2 * j;
+    e.flags = ctx->flags;
+    e.inv = ctx->inv;
+    e.s2half = 0.5 * plan->info.sigma2;
+    e.nbar = nbar;
+    e.k0 = (uint32_t)(seed & 0xFFFFFFFFu);
+    e.k1 = (uint32_t)(seed >> 32);
+    e.rid = request_id;
+    e.first_pair = first_realization / 2 + j;
+    e.fwd = fs.fN[ndim - 1];
+    e.H = H;
+    e.H_item = rows * W;
+    CE_TRY(run_inverse(ctx, plan, fs, seed, request_id, first_realization / 2 + j, np, e, s, pair_base));
+    double* partials = nullptr;
+    int64_t groups = 0;
+    CE_TRY(run_forward_bins(ctx, ndim, plan->n, plan->prec, np, H, nbins, &partials, &groups, s));
+    CE_PROF(ctx, "bin_reduce", s,
+            launch_bin_reduce(partials, np, groups, nbins, e.count, nm, norm, 1, ntot + 2 * j, nullptr,
+                              (double)ncells, out_pk + 2 * j * nbins, ctx->flags, s));
+  }
+  if (out_ntot) CE_HIP(launch_copy_ntot(ntot, out_ntot, count, s));
+  if (count >= 2 && (out_cov || out_cnorm))
+    CE_PROF(ctx, "covariance", s, launch_covariance(out_pk, count, nbins, out_cov, out_cnorm, s));
+  return CE_OK;
+}
+
+ce_status pipeline_check(ce_ctx* ctx, const ce_plan* plan, uint64_t first_realization, int64_t count, double nbar,
+                         int32_t nbins, const double* out_pk) {
+  if (!ctx || !plan || !out_pk || count <= 0 || nbins <= 0 || (first_realization & 1)) return CE_E_INVALID;
+  if (!(nbar >= 0) || !std::isfinite(nbar)) return CE_E_INVALID;
+  if (plan->ctx->device != ctx->device) return CE_E_INVALID;
+  if ((first_realization + (uint64_t)count + 1) / 2 > 0xFFFFFFFFull) return CE_E_INVALID;
+  for (int d = 1; d < plan->ndim; ++d)
+    if (plan->n[d] != plan->n[0] || plan->h[d] != plan->h[0]) return CE_E_UNSUPPORTED;
+  return CE_OK;
+}
+
+// The batched pipeline: items grouped by (ndim, N, h, precision, nbins); each group runs the
+// fused passes once over all its pairs with per-pair descriptors.
+ce_status pipeline_batch_impl(ce_ctx* ctx, const ce_batch_item* items, int64_t n, hipStream_t s) {
+  struct Group {
+    std::vector<int64_t> idx;
+    int64_t pairs = 0, covs = 0;
+    size_t off_desc = 0, off_slot = 0, off_cov = 0;
+  };
+  std::map<std::tuple<int, int, double, int, int>, Group> groups;
+  for (int64_t i = 0; i < n; ++i) {
+    const ce_batch_item& it = items[i];
+    if (!it.plan) return CE_E_INVALID;
+    CE_TRY(pipeline_check(ctx, it.plan, it.first_realization, it.count, it.nbar, it.nbins, it.out_pk));
+    Group& g = groups[std::make_tuple(it.plan->ndim, it.plan->n[0], it.plan->h[0], it.plan->prec, (int)it.nbins)];
+    g.idx.push_back(i);
+    g.pairs += (it.count + 1) / 2;
+    if (it.count >= 2 && (it.out_cov || it.out_cnorm)) g.covs++;
+  }
+  // one table area: per group [PairDesc x pairs][SlotOut x 2 pairs][CovItem x covs]
+  auto align = [](size_t x) { return (x + 255) & ~(size_t)255; };
+  size_t bytes = 0;
+  for (auto& kv : groups) {
+    Group& g = kv.second;
+    g.off_desc = bytes;
+    bytes = align(bytes + sizeof(PairDesc) * (size_t)g.pairs);
+    g.off_slot = bytes;
+    bytes = align(bytes + sizeof(SlotOut) * (size_t)(2 * g.pairs));
+    g.off_cov = bytes;
+    bytes = align(bytes + sizeof(CovItem) * (size_t)g.covs);
+  }
+  if (!ctx->staged) CE_HIP(hipEventCreateWithFlags(&ctx->staged, hipEventDisableTiming));
+  CE_HIP(hipEventSynchronize(ctx->staged));  // the previous batch's tables have been copied
+  if (ctx->pin_n < bytes) {
+    if (ctx->pin) CE_HIP(hipHostFree(ctx->pin));
+    ctx->pin = nullptr;
+    ctx->pin_n = 0;
+    if (hipHostMalloc(&ctx->pin, bytes) != hipSuccess) {
+      ctx->pin = nullptr;
+      return CE_E_OOM;
+    }
+    ctx->pin_n = bytes;
+  }
+  void* dtab = nullptr;
+  CE_TRY(ctx->scratch(5, bytes, &dtab));
+  char* h = static_cast<char*>(ctx->pin);
+  char* d = static_cast<char*>(dtab);
+  for (auto& kv : groups) {
+    Group& g = kv.second;
+    auto* desc = reinterpret_cast<PairDesc*>(h + g.off_desc);
+    auto* slot = reinterpret_cast<SlotOut*>(h + g.off_slot);
+    auto* cov = reinterpret_cast<CovItem*>(h + g.off_cov);
+    int64_t pi = 0, ci = 0;
+    for (int64_t i : g.idx) {
+      const ce_batch_item& it = items[i];
+      const ce_plan* p = it.plan;
+      const int64_t ncells = survey_cells(p);
+      for (int64_t j = 0; 2 * j < it.count; ++j, ++pi) {
+        PairDesc pd;
+        pd.sq = p->sq;
+        pd.counts = it.out_counts ? it.out_counts + 2 * j * ncells : nullptr;
+        pd.k0 = (uint32_t)(it.seed & 0xFFFFFFFFu);
+        pd.k1 = (uint32_t)(it.seed >> 32);
+        pd.rid = it.request_id;
+        pd.pair = (uint32_t)(it.first_realization / 2 + (uint64_t)j);
+        pd.s2half = 0.5 * p->info.sigma2;
+        pd.nbar = it.nbar;
+        pd.nreal = it.count - 2 * j >= 2 ? 2 : 1;
+        desc[pi] = pd;
+        for (int hh = 0; hh < 2; ++hh) {
+          SlotOut so;
+          if (hh < pd.nreal) {
+            so.pk = it.out_pk + (2 * j + hh) * it.nbins;
+            so.ntot = it.out_ntot ? it.out_ntot + 2 * j + hh : nullptr;
+          }
+          slot[2 * pi + hh] = so;
+        }
+      }
+      if (it.count >= 2 && (it.out_cov || it.out_cnorm)) cov[ci++] = CovItem{it.out_pk, it.count, it.out_cov, it.out_cnorm};
+    }
+  }
+  CE_HIP(hipMemcpyAsync(dtab, ctx->pin, bytes, hipMemcpyHostToDevice, s));
+  CE_HIP(hipEventRecord(ctx->staged, s));
+  for (auto& kv : groups) {
+    Group& g = kv.second;
+    const ce_plan* plan = items[g.idx[0]].plan;
+    const int nbins = std::get<4>(kv.first);
+    const auto* ddesc = reinterpret_cast<const PairDesc*>(d + g.off_desc);
+    const auto* dslot = reinterpret_cast<const SlotOut*>(d + g.off_slot);
+    InverseSetup fs;
+    CE_TRY(setup_ffts(ctx, plan, fs));
+    const int ndim = plan->ndim;
+    const int64_t ncells = survey_cells(plan);
+    const int Nl = plan->n[ndim - 1];
+    const int W = 2 * (Nl / 2 + 1);
+    const int64_t rows = ncells / Nl;
+    const size_t elem = plan->prec ? 16 : 8;
+    const int64_t npairs = g.pairs;
+    const int64_t cp = chunk_pairs(plan, npairs, kScratchCap);
+    void* acc = nullptr;
+    CE_TRY(ctx->scratch(4, sizeof(unsigned long long) * (size_t)(2 * npairs), &acc));
+    auto* ntot = static_cast<unsigned long long*>(acc);
+    CE_HIP(launch_zero_u64(ntot, 2 * npairs, s));
+    int64_t* nm = nullptr;
+    const std::vector<double>* km = nullptr;
+    CE_TRY(device_shells(ctx, plan->n[0], ndim, plan->h[0], nbins, &nm, &km));
+    const double norm = std::pow(plan->h[0], ndim) / (double)ncells;
+    for (int64_t j = 0; j < npairs; j += cp) {
+      const int64_t np = std::min(cp, npairs - j);
+      void* H = nullptr;
+      CE_TRY(ctx->scratch(2, elem * (size_t)(np * rows * W), &H));
+      RowEpi e;
+      e.mode = 2;
+      e.ncells = ncells;
+      e.count = 2 * np;
+      e.ntot = ntot + 2 * j;
+      e.flags = ctx->flags;
+      e.inv = ctx->inv;
+      e.fwd = fs.fN[ndim - 1];
+      e.H = H;
+      e.H_item = rows * W;
+      CE_TRY(run_inverse(ctx, plan, fs, 0, 0, 0, np, e, s, nullptr, ddesc + j));
+      double* partials = nullptr;
+      int64_t ngroups = 0;
+      CE_TRY(run_forward_bins(ctx, ndim, plan->n, plan->prec, np, H, nbins, &partials, &ngroups, s));
+      CE_PROF(ctx, "bin_reduce", s,
+              launch_bin_reduce(partials, np, ngroups, nbins, 2 * np, nm, norm, 1, ntot + 2 * j, dslot + 2 * j,
+                                (double)ncells, nullptr, ctx->flags, s));
+    }
+    if (g.covs)
+      CE_PROF(ctx, "covariance", s,
+              launch_covariance_batch(reinterpret_cast<const CovItem*>(d + g.off_cov), g.covs, nbins, s));
+  }
+  return CE_OK;
+}
+
 }  // namespace
 
 extern "C" {
+
+ce_status ce_pipeline_run_batch(ce_ctx* ctx, const ce_batch_item* items, int64_t n, void* stream) {
+  if (!ctx || (n > 0 && !items) || n < 0) return CE_E_INVALID;
+  if (n == 0) return CE_OK;
+  std::lock_guard<std::mutex> lock(ctx->mu);
+  CE_HIP(hipSetDevice(ctx->device));
+  hipStream_t s = as_stream(stream);
+  ctx->last = s;
+  return pipeline_batch_impl(ctx, items, n, s);
+}
 
 ce_status ce_generate_fields(ce_ctx* ctx, const ce_plan* plan, uint64_t seed, uint32_t request_id,
                              uint64_t first_realization, int64_t count, void* out_fields, void* stream) {
@@ -985,71 +1256,84 @@ ce_status ce_pipeline_run(ce_ctx* ctx, const ce_plan* plan, uint64_t seed, uint3
                           uint64_t first_realization, int64_t count, double nbar, int32_t nbins, void* out_fields,
                           void* out_delta, int32_t* out_counts, int64_t* out_ntot, double* out_pk, double* out_cov,
                           double* out_cnorm, void* stream) {
-  if (!ctx || !plan || !out_pk || count <= 0 || nbins <= 0 || (first_realization & 1)) return CE_E_INVALID;
-  if (!(nbar >= 0) || !std::isfinite(nbar)) return CE_E_INVALID;
-  if (plan->ctx != ctx) return CE_E_INVALID;
-  for (int d = 1; d < plan->ndim; ++d)
-    if (plan->n[d] != plan->n[0] || plan->h[d] != plan->h[0]) return CE_E_UNSUPPORTED;
-  {
-    std::lock_guard<std::mutex> lock(ctx->mu);
-    CE_HIP(hipSetDevice(ctx->device));
-    hipStream_t s = as_stream(stream);
-    ctx->last = s;
-    InverseSetup fs;
-    CE_TRY(setup_ffts(ctx, plan, fs));
-    const int ndim = plan->ndim;
-    const int64_t ncells = survey_cells(plan);
-    const int Nl = plan->n[ndim - 1];
-    const int W = 2 * (Nl / 2 + 1);
-    const int64_t rows = ncells / Nl;
-    const size_t elem = plan->prec ? 16 : 8;
-    const size_t relem = plan->prec ? 8 : 4;
-    const int64_t npairs = (count + 1) / 2;
-    const int64_t cp = chunk_pairs(plan, npairs, kScratchCap);
-    void* acc = nullptr;
-    CE_TRY(ctx->scratch(4, sizeof(unsigned long long) * (size_t)(2 * npairs), &acc));
-    auto* ntot = static_cast<unsigned long long*>(acc);
-    CE_HIP(launch_zero_u64(ntot, 2 * npairs, s));
-    int64_t* nm = nullptr;
-    const std::vector<double>* km = nullptr;
-    CE_TRY(device_shells(ctx, plan->n[0], ndim, plan->h[0], nbins, &nm, &km));
-    const double norm = std::pow(plan->h[0], ndim) / (double)ncells;
-    for (int64_t j = 0; j < npairs; j += cp) {
-      const int64_t np = std::min(cp, npairs - j);
-      void* H = nullptr;
-      CE_TRY(ctx->scratch(2, elem * (size_t)(np * rows * W), &H));
-      RowEpi e;
-      e.mode = 2;
-      e.ncells = ncells;
-      e.count = std::min<int64_t>(count - 2 * j, 2 * np);
-      e.real_off = 0;
-      e.fields = out_fields ? static_cast<char*>(out_fields) + relem * (size_t)(2 * j * ncells) : nullptr;
-      e.delta = out_delta ? static_cast<char*>(out_delta) + relem * (size_t)(2 * j * ncells) : nullptr;
-      e.counts = out_counts ? out_counts + 2 * j * ncells : nullptr;
-      e.ntot = ntot + 2 * j;
-      e.flags = ctx->flags;
-      e.inv = ctx->inv;
-      e.s2half = 0.5 * plan->info.sigma2;
-      e.nbar = nbar;
-      e.k0 = (uint32_t)(seed & 0xFFFFFFFFu);
-      e.k1 = (uint32_t)(seed >> 32);
-      e.rid = request_id;
-      e.first_pair = first_realization / 2 + j;
-      e.fwd = fs.fN[ndim - 1];
-      e.H = H;
-      e.H_item = rows * W;
-      CE_TRY(run_inverse(ctx, plan, fs, seed, request_id, first_realization / 2 + j, np, e, s));
-      double* partials = nullptr;
-      int64_t groups = 0;
-      CE_TRY(run_forward_bins(ctx, ndim, plan->n, plan->prec, np, H, nbins, &partials, &groups, s));
-      CE_PROF(ctx, "bin_reduce", s, launch_bin_reduce(partials, np, groups, nbins, e.count, nm, norm, 1, ntot + 2 * j, nullptr,
-                               (double)ncells, out_pk + 2 * j * nbins, ctx->flags, s));
-    }
-    if (out_ntot) CE_HIP(launch_copy_ntot(ntot, out_ntot, count, s));
-    if (count >= 2 && (out_cov || out_cnorm))
-      CE_PROF(ctx, "covariance", s, launch_covariance(out_pk, count, nbins, out_cov, out_cnorm, s));
-  }
+  CE_TRY(pipeline_check(ctx, plan, first_realization, count, nbar, nbins, out_pk));
+  std::lock_guard<std::mutex> lock(ctx->mu);
+  CE_HIP(hipSetDevice(ctx->device));
+  hipStream_t s = as_stream(stream);
+  ctx->last = s;
+  return pipeline_impl(ctx, plan, seed, request_id, first_realization, count, nbar, nbins, out_fields, out_delta,
+                       out_counts, out_ntot, out_pk, out_cov, out_cnorm, nullptr, s);
+}
+
+// ---- captured pipeline ------------------------------------------------------------
+
+struct ce_graph {
+  ce_ctx* ctx = nullptr;  // private context: the graph's kernels use its scratch
+  hipStream_t cap = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  unsigned long long* base = nullptr;
+};
+
+ce_status ce_pipeline_graph_create(ce_ctx* ctx, const ce_plan* plan, uint64_t seed, uint32_t request_id,
+                                   uint64_t first_realization, int64_t count, double nbar, int32_t nbins,
+                                   void* out_fields, void* out_delta, int32_t* out_counts, int64_t* out_ntot,
+                                   double* out_pk, double* out_cov, double* out_cnorm, ce_graph** out) {
+  if (!out) return CE_E_INVALID;
+  *out = nullptr;
+  CE_TRY(pipeline_check(ctx, plan, first_realization, count, nbar, nbins, out_pk));
+  if (count & 1) return CE_E_INVALID;
+  auto g = std::make_unique<ce_graph>();
+  CE_TRY(ce_ctx_create(ctx->device, ctx->budget, &g->ctx));
+  auto fail = [&](ce_status st) {
+    if (g->exec) (void)hipGraphExecDestroy(g->exec);
+    if (g->graph) (void)hipGraphDestroy(g->graph);
+    if (g->cap) (void)hipStreamDestroy(g->cap);
+    ce_ctx_destroy(g->ctx);
+    g->ctx = nullptr;
+    return st;
+  };
+  ce_ctx* c = g->ctx;
+  std::lock_guard<std::mutex> lock(c->mu);
+  if (hipStreamCreate(&g->cap) != hipSuccess) return fail(CE_E_DEVICE);
+  void* b = nullptr;
+  ce_status st = c->alloc(&b, 64);
+  if (st != CE_OK) return fail(st);
+  g->base = static_cast<unsigned long long*>(b);
+  if (hipMemset(g->base, 0, 8) != hipSuccess) return fail(CE_E_DEVICE);
+  // size the scratch (no allocation may happen inside the capture)
+  st = pipeline_impl(c, plan, seed, request_id, first_realization, count, nbar, nbins, out_fields, out_delta,
+                     out_counts, out_ntot, out_pk, out_cov, out_cnorm, g->base, g->cap);
+  if (st != CE_OK) return fail(st);
+  if (hipStreamSynchronize(g->cap) != hipSuccess) return fail(CE_E_DEVICE);
+  if (hipStreamBeginCapture(g->cap, hipStreamCaptureModeThreadLocal) != hipSuccess) return fail(CE_E_DEVICE);
+  st = pipeline_impl(c, plan, seed, request_id, first_realization, count, nbar, nbins, out_fields, out_delta,
+                     out_counts, out_ntot, out_pk, out_cov, out_cnorm, g->base, g->cap);
+  const hipError_t adv = launch_advance(g->base, (unsigned long long)(count / 2), g->cap);
+  const hipError_t end = hipStreamEndCapture(g->cap, &g->graph);
+  if (st != CE_OK) return fail(st);
+  if (adv != hipSuccess || end != hipSuccess) return fail(CE_E_DEVICE);
+  if (hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0) != hipSuccess) return fail(CE_E_DEVICE);
+  *out = g.release();
   return CE_OK;
+}
+
+ce_status ce_pipeline_graph_launch(ce_graph* g, void* stream) {
+  if (!g) return CE_E_INVALID;
+  CE_HIP(hipSetDevice(g->ctx->device));
+  CE_HIP(hipGraphLaunch(g->exec, as_stream(stream)));
+  return CE_OK;
+}
+
+void ce_pipeline_graph_destroy(ce_graph* g) {
+  if (!g) return;
+  (void)hipSetDevice(g->ctx->device);
+  (void)hipDeviceSynchronize();
+  if (g->exec) (void)hipGraphExecDestroy(g->exec);
+  if (g->graph) (void)hipGraphDestroy(g->graph);
+  if (g->cap) (void)hipStreamDestroy(g->cap);
+  ce_ctx_destroy(g->ctx);
+  delete g;
 }
 
 ce_status ce_debug_philox(uint64_t seed, const uint32_t ctr[4], int64_t n_calls, uint32_t* out_words, void* stream) {

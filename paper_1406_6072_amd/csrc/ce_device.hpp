@@ -186,12 +186,20 @@ struct Pow2Dft {
 // output pair X_k, X_{R-k} is stored as soon as it is formed.  The line's root
 // table gives tw[m L / R] = exp(-2 pi i m / R).
 template <int R, int S, typename T>
-__device__ __forceinline__ void odd_dft_store(const cpx<T>* v, const T* cs, const T* sn, cpx<T>* dst, int base,
-                                              int Ns, int keep) {
+__device__ __forceinline__ void odd_dft_store(cpx<T>* v, const T* cs, const T* sn, cpx<T>* dst, int base, int Ns,
+                                              int keep) {
   constexpr int H = (R - 1) / 2;
+  // sums and differences of the pairs n, R - n replace them in place, so the live set is
+  // the R inputs plus the (R - 1) / 2 cosines and sines
+#pragma unroll
+  for (int n = 1; n <= H; ++n) {
+    const cpx<T> p = v[n], q = v[R - n];
+    v[n] = c_add(p, q);
+    v[R - n] = c_sub(p, q);
+  }
   cpx<T> x0 = v[0];
 #pragma unroll
-  for (int n = 1; n <= H; ++n) x0 = c_add(x0, c_add(v[n], v[R - n]));
+  for (int n = 1; n <= H; ++n) x0 = c_add(x0, v[n]);
   if (base < keep) dst[pidx(base)] = x0;
 #pragma unroll
   for (int k = 1; k <= H; ++k) {
@@ -202,8 +210,8 @@ __device__ __forceinline__ void odd_dft_store(const cpx<T>* v, const T* cs, cons
       const int mm = m <= H ? m : R - m;
       const T c = cs[mm];
       const T s = m <= H ? sn[mm] : -sn[mm];
-      const cpx<T> sp = c_add(v[n], v[R - n]);
-      const cpx<T> dm = c_sub(v[n], v[R - n]);
+      const cpx<T> sp = v[n];
+      const cpx<T> dm = v[R - n];
       a.x += sp.x * c;
       a.y += sp.y * c;
       b.x += dm.x * s;
@@ -329,6 +337,79 @@ __device__ __forceinline__ void pingpong_stage(const cpx<T>* src, cpx<T>* dst, i
   __syncthreads();
 }
 
+// Out-of-place stage of a prime radix R >= 11 with the inputs kept in LDS instead of
+// registers: each butterfly owns its R source slots, so it overwrites them with the
+// twiddled pair sums v[n] + v[R-n] and differences v[n] - v[R-n], then forms each output
+// pair X_k, X_{R-k} by reading them back.  The register footprint is the (R - 1) / 2
+// cosines and sines plus a few accumulators, so no radix spills.
+template <typename T, int R, int S>
+__device__ __forceinline__ void pingpong_stage_lds(cpx<T>* src, cpx<T>* dst, int L, int Ns, int lane, int nlanes,
+                                                   bool active, const cpx<T>* __restrict__ tw, int keep) {
+  constexpr int H = (R - 1) / 2;
+  const int nb = L / R;
+  T cs[H + 1], sn[H + 1];
+  {
+    const int Lr = L / R;
+#pragma unroll
+    for (int m = 1; m <= H; ++m) {
+      const cpx<T> w = tw[m * Lr];
+      cs[m] = w.x;
+      sn[m] = -w.y;
+    }
+  }
+  if (active) {
+    for (int j = lane; j < nb; j += nlanes) {
+      const int k = j % Ns;
+      const int step = k * (L / (Ns * R));
+      auto twiddled = [&](int r) {
+        cpx<T> x = src[pidx(j + r * nb)];
+        if (Ns > 1 && r > 0) {
+          cpx<T> w = tw[r * step];
+          if (S > 0) w.y = -w.y;
+          x = c_mul(x, w);
+        }
+        return x;
+      };
+      const cpx<T> v0 = twiddled(0);
+      cpx<T> x0 = v0;
+#pragma unroll
+      for (int n = 1; n <= H; ++n) {
+        const cpx<T> p = twiddled(n), q = twiddled(R - n);
+        const cpx<T> sp = c_add(p, q);
+        x0 = c_add(x0, sp);
+        src[pidx(j + n * nb)] = sp;
+        src[pidx(j + (R - n) * nb)] = c_sub(p, q);
+      }
+      const int base = (j / Ns) * Ns * R + k;
+      if (base < keep) dst[pidx(base)] = x0;
+#pragma unroll
+      for (int kk = 1; kk <= H; ++kk) {
+        cpx<T> a = v0, b = {T(0), T(0)};
+#pragma unroll
+        for (int n = 1; n <= H; ++n) {
+          const int m = (n * kk) % R;  // compile-time after unrolling
+          const int mm = m <= H ? m : R - m;
+          const T c = cs[mm];
+          const T sg = m <= H ? sn[mm] : -sn[mm];
+          const cpx<T> sp = src[pidx(j + n * nb)];
+          const cpx<T> dm = src[pidx(j + (R - n) * nb)];
+          a.x += sp.x * c;
+          a.y += sp.y * c;
+          b.x += dm.x * sg;
+          b.y += dm.y * sg;
+        }
+        const cpx<T> ib = c_rot<S>(b);
+        const int o1 = base + kk * Ns, o2 = base + (R - kk) * Ns;
+        if (o1 < keep) dst[pidx(o1)] = c_add(a, ib);
+        if (o2 < keep) dst[pidx(o2)] = c_sub(a, ib);
+        // keep the sums in LDS: no hoisting of the reads above into registers
+        __asm__ volatile("" ::: "memory");
+      }
+    }
+  }
+  __syncthreads();
+}
+
 // Power-of-two lengths: the stage sequence is fixed at compile time (one
 // straight-line instantiation per length), which keeps the register
 // allocation to that of a single radix and turns every LDS offset into an
@@ -378,9 +459,10 @@ __device__ __forceinline__ void pow2_fft(cpx<T>* a, int L, int lane, bool active
 // Full line FFT.  Every thread of the workgroup must call it (barriers inside);
 // threads without a line pass active = false.  MIX = false: power-of-two
 // lengths, in place in buffer a, registers staged across each barrier.
-// MIX = true: any supported radix (f.rad), ping-pong between a and b.
+// MIX = 1 or 2: the stages of f.rad (radices 2, 4, 8 and odd primes up to 7, or up to
+// 31), ping-pong between a and b.
 // Returns the buffer that holds the result.
-template <typename T, int S, bool MIX>
+template <typename T, int S, int MIX>
 __device__ __forceinline__ cpx<T>* line_fft(cpx<T>* a, cpx<T>* b, const FftDesc& f, int lane, int nlanes, bool active,
                                            int keep) {
   const cpx<T>* __restrict__ tw = static_cast<const cpx<T>*>(f.tw);
@@ -398,21 +480,30 @@ __device__ __forceinline__ cpx<T>* line_fft(cpx<T>* a, cpx<T>* b, const FftDesc&
     for (int s = 0; s < f.nst; ++s) {
       const int R = f.rad[s];
       const int kp = (s == f.nst - 1) ? keep : L;
+      // MIX 1 instantiates only the small radices, so its register footprint is that of
+      // radix 8; MIX 2 adds the primes 11..31
       switch (R) {
         case 2: pingpong_stage<T, 2, S>(src, dst, L, Ns, lane, nlanes, active, tw, kp); break;
         case 4: pingpong_stage<T, 4, S>(src, dst, L, Ns, lane, nlanes, active, tw, kp); break;
         case 8: pingpong_stage<T, 8, S>(src, dst, L, Ns, lane, nlanes, active, tw, kp); break;
-        case 16: pingpong_stage<T, 16, S>(src, dst, L, Ns, lane, nlanes, active, tw, kp); break;
         case 3: pingpong_stage<T, 3, S>(src, dst, L, Ns, lane, nlanes, active, tw, kp); break;
         case 5: pingpong_stage<T, 5, S>(src, dst, L, Ns, lane, nlanes, active, tw, kp); break;
-        case 7: pingpong_stage<T, 7, S>(src, dst, L, Ns, lane, nlanes, active, tw, kp); break;
-        case 11: pingpong_stage<T, 11, S>(src, dst, L, Ns, lane, nlanes, active, tw, kp); break;
-        case 13: pingpong_stage<T, 13, S>(src, dst, L, Ns, lane, nlanes, active, tw, kp); break;
-        case 17: pingpong_stage<T, 17, S>(src, dst, L, Ns, lane, nlanes, active, tw, kp); break;
-        case 19: pingpong_stage<T, 19, S>(src, dst, L, Ns, lane, nlanes, active, tw, kp); break;
-        case 23: pingpong_stage<T, 23, S>(src, dst, L, Ns, lane, nlanes, active, tw, kp); break;
-        case 29: pingpong_stage<T, 29, S>(src, dst, L, Ns, lane, nlanes, active, tw, kp); break;
-        default: pingpong_stage<T, 31, S>(src, dst, L, Ns, lane, nlanes, active, tw, kp); break;
+        default:
+          if constexpr (MIX == 1) {
+            pingpong_stage<T, 7, S>(src, dst, L, Ns, lane, nlanes, active, tw, kp);
+          } else {
+            switch (R) {
+              case 7: pingpong_stage<T, 7, S>(src, dst, L, Ns, lane, nlanes, active, tw, kp); break;
+              case 11: pingpong_stage_lds<T, 11, S>(src, dst, L, Ns, lane, nlanes, active, tw, kp); break;
+              case 13: pingpong_stage_lds<T, 13, S>(src, dst, L, Ns, lane, nlanes, active, tw, kp); break;
+              case 17: pingpong_stage_lds<T, 17, S>(src, dst, L, Ns, lane, nlanes, active, tw, kp); break;
+              case 19: pingpong_stage_lds<T, 19, S>(src, dst, L, Ns, lane, nlanes, active, tw, kp); break;
+              case 23: pingpong_stage_lds<T, 23, S>(src, dst, L, Ns, lane, nlanes, active, tw, kp); break;
+              case 29: pingpong_stage_lds<T, 29, S>(src, dst, L, Ns, lane, nlanes, active, tw, kp); break;
+              default: pingpong_stage_lds<T, 31, S>(src, dst, L, Ns, lane, nlanes, active, tw, kp); break;
+            }
+          }
+          break;
       }
       cpx<T>* t = src;
       src = dst;

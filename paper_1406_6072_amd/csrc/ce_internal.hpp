@@ -39,13 +39,41 @@ struct LineGeom {
 };
 
 // Noise prologue of the first inverse pass (lines along axis 0 of the embedding).
+// Per-pair parameters when one launch covers pairs of several requests that share a
+// shape (batched pipeline): each pair brings its own plan, Philox key and counter words,
+// lognormal variance, density and counts destination.
+struct PairDesc {
+  const void* sq = nullptr;    // sqrt(lambda / M^d) octant of the request's plan (pass precision)
+  int32_t* counts = nullptr;   // nullable: counts of the pair's real part; imaginary part at + ncells
+  uint32_t k0 = 0, k1 = 0, rid = 0, pair = 0;
+  double s2half = 0, nbar = 0;
+  int32_t nreal = 2;           // realizations of the pair that were requested (1: real part only)
+  int32_t pad = 0;
+};
+
+// Destination of one realization slot (2 per pair) of a batched P(k) reduction.
+struct SlotOut {
+  double* pk = nullptr;        // nullable: slot not requested
+  int64_t* ntot = nullptr;     // nullable
+};
+
+// One request of a batched covariance: R spectra of nb shells at pk.
+struct CovItem {
+  const double* pk = nullptr;
+  int64_t R = 0;
+  double* cov = nullptr;
+  double* cnorm = nullptr;
+};
+
 struct NoiseArgs {
   uint32_t k0 = 0, k1 = 0, rid = 0;
   uint64_t first_pair = 0;
+  const unsigned long long* pair_base = nullptr;  // nullable: device offset added to first_pair (graph replays)
   int32_t ndim = 0;
   int32_t M[3] = {1, 1, 1};
   int32_t O[3] = {1, 1, 1};    // octant sides N_i + 1
   const void* sq = nullptr;    // sqrt(lambda / M^d) on the octant, axis 0 fastest (pass precision)
+  const PairDesc* desc = nullptr;  // nullable: per-pair parameters (override k0, k1, rid, pairs, sq)
 };
 
 // Epilogue of the last inverse pass (rows along the last axis).
@@ -66,6 +94,8 @@ struct RowEpi {
   double s2half = 0, nbar = 0;
   uint32_t k0 = 0, k1 = 0, rid = 0;
   uint64_t first_pair = 0;
+  const unsigned long long* pair_base = nullptr;  // nullable, as in NoiseArgs
+  const PairDesc* desc = nullptr;  // nullable: per-pair parameters (batched pipeline, mode 2)
   FftDesc fwd;                 // forward FFT of the packed counts row (length K)
   void* H = nullptr;           // separated spectra rows: W = 2 (K/2 + 1) complex per row
   int64_t H_item = 0;
@@ -116,7 +146,7 @@ hipError_t launch_bin_pass(int prec, const LineGeom& g, const FftDesc& f, const 
                            hipStream_t s);
 hipError_t launch_bin_reduce(const double* partials, int64_t nitems, int64_t groups, int nb, int64_t count,
                              const int64_t* nmodes, double norm, int scale_kind, const unsigned long long* ntot_u,
-                             const int64_t* ntot_s, double ncells, double* pk, uint32_t* flags, hipStream_t s);
+                             const SlotOut* slots, double ncells, double* pk, uint32_t* flags, hipStream_t s);
 hipError_t launch_lognormal_poisson(int prec, const void* fields, int64_t count, int64_t ncells, double s2half,
                                     double nbar, const float* mask, uint32_t k0, uint32_t k1, uint32_t rid,
                                     uint64_t first_real, void* delta, int32_t* counts, unsigned long long* ntot,
@@ -125,9 +155,11 @@ hipError_t launch_count_totals(const int32_t* counts, int64_t count, int64_t nce
                                hipStream_t s);
 hipError_t launch_copy_ntot(const unsigned long long* src, int64_t* dst, int64_t n, hipStream_t s);
 hipError_t launch_covariance(const double* pk, int64_t count, int nb, double* cov, double* cnorm, hipStream_t s);
+hipError_t launch_covariance_batch(const CovItem* items, int64_t nitems, int nb, hipStream_t s);
 hipError_t launch_debug_philox(uint32_t k0, uint32_t k1, const uint32_t* ctr, int64_t n, uint32_t* out,
                                hipStream_t s);
 hipError_t launch_debug_noise(int prec, const NoiseArgs& n, uint64_t pair, int64_t cells, void* out, hipStream_t s);
 hipError_t launch_zero_u64(unsigned long long* p, int64_t n, hipStream_t s);
+hipError_t launch_advance(unsigned long long* p, unsigned long long by, hipStream_t s);
 
 }  // namespace ce

@@ -9,6 +9,8 @@
 // the last pass crops / exponentiates / samples in its epilogue.
 #include <hip/hip_runtime.h>
 #include <math.h>
+
+#include <algorithm>
 #include <stdint.h>
 
 #include "ce_device.hpp"
@@ -110,10 +112,12 @@ template <typename T>
 __device__ __forceinline__ cpx<T>* buf_b(cpx<T>* lds, const LineGeom& g, int r) {
   return lds + (g.R + r) * g.lpitch;
 }
-// Base of the buffer set that holds the result after an FFT of f.
-template <typename T, bool MIX>
+// Base of the buffer set that holds the result after an FFT of f.  MIX: 0 power-of-two
+// lengths (compile-time stages, in place), 1 lengths whose factors are 2, 3, 4, 5, 7, 8
+// (ping-pong), 2 lengths with a prime factor 11..31 (ping-pong, larger register footprint).
+template <typename T, int MIX>
 __device__ __forceinline__ cpx<T>* result_base(cpx<T>* lds, const LineGeom& g, const FftDesc& f) {
-  return (MIX && (f.nst & 1)) ? lds + g.R * g.lpitch : lds;
+  return (MIX != 0 && (f.nst & 1)) ? lds + g.R * g.lpitch : lds;
 }
 
 // ---------------------------------------------------------------------------
@@ -219,7 +223,7 @@ __global__ void k_lag_octant(int ndim, int32_t O0, int32_t O1, int32_t O2, doubl
 
 // DCT-I along one axis of the lag octant via a length-M complex FFT of the even
 // extension e(m) = c(min(m, M - m)); keeps Re of outputs q in [0, M/2].
-template <bool MIX>
+template <int MIX>
 __global__ void __launch_bounds__(512) k_dct_axis(LineGeom g, FftDesc f, DctArgs d) {
   cpx<double>* lds = lds_lines<double>();
   const PassPos pp = pass_pos(g);
@@ -322,14 +326,17 @@ __device__ __forceinline__ uint32_t sq_line_offset(const NoiseArgs& n, uint32_t 
          (uint32_t)n.O[0];
 }
 
-template <typename T, bool MIX>
+template <typename T, int MIX>
 __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 4 : 2))) k_noise_pass(LineGeom g, FftDesc f, NoiseArgs n, cpx<T>* __restrict__ out) {
   cpx<T>* lds = lds_lines<T>();
   const PassPos pp = pass_pos(g);
   const int L = g.L;
   const int tid = threadIdx.x, nthr = blockDim.x;
-  const T* __restrict__ sq = static_cast<const T*>(n.sq);
-  const uint32_t pair = (uint32_t)(n.first_pair + pp.item);
+  const PairDesc* pd = n.desc ? n.desc + pp.item : nullptr;
+  const T* __restrict__ sq = static_cast<const T*>(pd ? pd->sq : n.sq);
+  const uint32_t pair =
+      pd ? pd->pair : (uint32_t)(n.first_pair + (n.pair_base ? *n.pair_base : 0ull) + pp.item);
+  const uint32_t rid = pd ? pd->rid : n.rid, k0 = pd ? pd->k0 : n.k0, k1 = pd ? pd->k1 : n.k1;
   {
     const int H = g.R / 2;  // line pairs
     const int rp = tid % H, c0 = tid / H, step = nthr / H;
@@ -343,7 +350,7 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(sizeof
       cpx<T>* d1 = d0 + g.lpitch;
       for (int i = c0; i < L; i += step) {
         const uint32_t p = (uint32_t)i * half_b + (b >> 1);
-        const Words4 w = philox4x32_10(p, pair, n.rid, 0u, n.k0, n.k1);
+        const Words4 w = philox4x32_10(p, pair, rid, 0u, k0, k1);
         const cpx<T> e0 = normal_pair<T>(w.x0, w.x1);
         const cpx<T> e1 = normal_pair<T>(w.x2, w.x3);
         const uint32_t o0 = (uint32_t)mirror(i, n.M[0]);
@@ -360,7 +367,7 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(sizeof
 
 // Generic complex line pass (inner axes of 3-D transforms), pruned to K outputs.
 // In place is allowed: a group reads all its lines before writing them.
-template <typename T, int S, bool MIX>
+template <typename T, int S, int MIX>
 __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 4 : 2))) k_line_pass(LineGeom g, FftDesc f, const cpx<T>* in, cpx<T>* out) {
   cpx<T>* lds = lds_lines<T>();
   const PassPos pp = pass_pos(g);
@@ -375,7 +382,7 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(sizeof
 // Forward transform of a packed pair row (a + i b) followed by the Hermitian
 // separation F_a(k) = (G(k) + conj G(-k))/2, F_b(k) = (G(k) - conj G(-k))/(2i)
 // for k in [0, K/2]; row written as [F_a(0..K/2) | F_b(0..K/2)].
-template <typename T, bool MIX>
+template <typename T, int MIX>
 __device__ __forceinline__ void forward_separate(cpx<T>* line, cpx<T>* other, const FftDesc& fwd, int lane,
                                                  int nlanes, bool active, cpx<T>* __restrict__ Hrow) {
   line = line_fft<T, -1, MIX>(line, other, fwd, lane, nlanes, active, fwd.L);
@@ -400,7 +407,7 @@ __device__ __forceinline__ void forward_separate(cpx<T>* line, cpx<T>* other, co
 // Last inverse pass: rows along the last axis, pruned to the survey, with the
 // crop epilogue (Sec. 2) and optionally the lognormal / Poisson step (Sec. 3.1)
 // and the first forward transform of the counts (Sec. 3.2).
-template <typename T, bool MIX>
+template <typename T, int MIX>
 __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 4 : 2))) k_row_inverse(LineGeom g, FftDesc f, RowEpi e, const cpx<T>* in) {
   cpx<T>* lds = lds_lines<T>();
   __shared__ unsigned long long tot[2];
@@ -419,7 +426,8 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(sizeof
   const int K = g.K;
   const int64_t row = pp.line0 + r;
   const int64_t ra = e.real_off + 2 * pp.item;  // local realization of the real part
-  const bool has_b = ra + 1 < e.count;
+  const PairDesc* pd = e.desc ? e.desc + pp.item : nullptr;
+  const bool has_b = pd ? pd->nreal > 1 : ra + 1 < e.count;
   if (e.mode == 1) {
     // rows outside the survey exist only in the unpruned form
     const int64_t m0 = row / e.rows_per_m0, m1 = row - m0 * e.rows_per_m0;
@@ -438,20 +446,23 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(sizeof
   // fused epilogue
   unsigned long long sa = 0, sb = 0;
   if (active) {
-    const uint32_t pair = (uint32_t)(e.first_pair + pp.item);
-    const T s2h = (T)e.s2half;
+    const uint32_t pair =
+        pd ? pd->pair : (uint32_t)(e.first_pair + (e.pair_base ? *e.pair_base : 0ull) + pp.item);
+    const uint32_t rid = pd ? pd->rid : e.rid, k0 = pd ? pd->k0 : e.k0, k1 = pd ? pd->k1 : e.k1;
+    const T s2h = (T)(pd ? pd->s2half : e.s2half);
+    const double nbar = pd ? pd->nbar : e.nbar;
     T* fa = e.fields ? static_cast<T*>(e.fields) + ra * e.ncells + row * K : nullptr;
     T* da = e.delta ? static_cast<T*>(e.delta) + ra * e.ncells + row * K : nullptr;
-    int32_t* ca = e.counts ? e.counts + ra * e.ncells + row * K : nullptr;
+    int32_t* ca = pd ? (pd->counts ? pd->counts + row * K : nullptr)
+                     : (e.counts ? e.counts + ra * e.ncells + row * K : nullptr);
     for (int i = lane; i < K; i += g.nlanes) {
       const cpx<T> z = line[pidx(i)];
       const T dla = lognormal_delta<T>(z.x, s2h);
       const T dlb = lognormal_delta<T>(z.y, s2h);
-      const double mua = intensity(e.nbar, 1.0, (double)dla);
-      const double mub = intensity(e.nbar, 1.0, (double)dlb);
+      const double mua = intensity(nbar, 1.0, (double)dla);
+      const double mub = intensity(nbar, 1.0, (double)dlb);
       int na, nb;
-      poisson_pair(mua, mub, has_b, (uint32_t)(row * K + i), pair, e.rid, e.k0, e.k1, e.inv, inv_s, e.flags, na,
-                   nb);
+      poisson_pair(mua, mub, has_b, (uint32_t)(row * K + i), pair, rid, k0, k1, e.inv, inv_s, e.flags, na, nb);
       if (fa) {
         fa[i] = z.x;
         if (has_b) fa[i + e.ncells] = z.y;
@@ -480,7 +491,7 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(sizeof
 
 // Standalone spectrum, first pass: rows of two maps packed as a + i b (the
 // contrast delta_g for counts, Sec. 3.2 eq. Estim), forward transform, separation.
-template <typename T, bool MIX>
+template <typename T, int MIX>
 __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 4 : 2))) k_pair_forward(LineGeom g, FftDesc f, PairLoad p) {
   cpx<T>* lds = lds_lines<T>();
   const PassPos pp = pass_pos(g);
@@ -528,8 +539,7 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(sizeof
 // fixed order, hence bitwise reproducible.
 
 // shell b in [0, nb) of |q|^2 = q2 (exact integers): b + 1 = smallest s with s^2 N^2 >= T q2
-__device__ __forceinline__ int shell_of(int64_t q2, int64_t T, int64_t NN) {
-  const int64_t t = T * q2;
+__device__ __forceinline__ int shell_of_t(int64_t t, int64_t NN) {
   int64_t s = (int64_t)sqrt((double)t / (double)NN);
   while (s > 0 && (s - 1) * (s - 1) * NN >= t) --s;
   while (s * s * NN < t) ++s;
@@ -542,7 +552,7 @@ struct RunEnds {
   int single, nonempty;
 };
 
-template <typename T, bool MIX>
+template <typename T, int MIX>
 __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 4 : 2))) k_bin_pass(LineGeom g, FftDesc f, BinArgs bn, const cpx<T>* in) {
   cpx<T>* lds = lds_lines<T>();
   const PassPos pp = pass_pos(g);
@@ -571,46 +581,53 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(sizeof
         if (k1 > Nh) k1 -= N;
         p2 += (int64_t)k1 * k1;
       }
+      // line weight (exact factor 1 or 2), applied when a run is stored
       const double wgt = (kz != 0 && kz != Nh) ? 2.0 : 1.0;
       const int chunk = (Kh + g.nlanes - 1) / g.nlanes;
       const int a0 = lane * chunk, a1 = min(a0 + chunk, Kh);
       const cpx<T>* line = res + r * g.lpitch;
       if (a0 < a1) {
         e.nonempty = 1;
-        int bin = shell_of((int64_t)a0 * a0 + p2, Tq, NN);
+        // t = T |q|^2 advanced by differences: t(a+1) - t(a) = T (2a + 1)
+        int64_t t = Tq * ((int64_t)a0 * a0 + p2);
+        int64_t dt = Tq * (2 * (int64_t)a0 + 1);
+        const int64_t ddt = 2 * Tq;
+        int bin = shell_of_t(t, NN);
         int64_t edge = (int64_t)(bin + 1) * N;
         edge *= edge;  // (bin+1)^2 N^2: the mode stays in `bin` while T q2 <= edge
         double run = 0.0;
         e.first_bin = bin;
         for (int a = a0; a < a1; ++a) {
-          const int64_t t = Tq * ((int64_t)a * a + p2);
           if (t > edge) {
             // close the current run
             if (bin == e.first_bin && e.single) {
-              e.first_sum = run;
+              e.first_sum = wgt * run;
             } else if (bin >= 0 && bin < nb) {
-              acc[r * nb + bin] = run;  // interior run: complete within this chunk
+              acc[r * nb + bin] = wgt * run;  // interior run: complete within this chunk
             }
             e.single = 0;
-            bin = shell_of((int64_t)a * a + p2, Tq, NN);
+            bin = shell_of_t(t, NN);
             edge = (int64_t)(bin + 1) * N;
             edge *= edge;
             run = 0.0;
           }
+          // power of the mode pair in the pass precision, summed in FP64
           const cpx<T> v = line[pidx(a)];
-          double pw = (double)v.x * (double)v.x + (double)v.y * (double)v.y;
+          T pw = v.x * v.x + v.y * v.y;
           if (a != 0 && a != Nh) {
             const cpx<T> u = line[pidx(N - a)];
-            pw += (double)u.x * (double)u.x + (double)u.y * (double)u.y;
+            pw += u.x * u.x + u.y * u.y;
           }
-          run += wgt * pw;
+          run += (double)pw;
+          t += dt;
+          dt += ddt;
         }
         if (e.single) {
-          e.first_sum = run;
+          e.first_sum = wgt * run;
           e.last_bin = bin;
         } else {
           e.last_bin = bin;
-          e.last_sum = run;
+          e.last_sum = wgt * run;
         }
       }
     }
@@ -656,13 +673,19 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(sizeof
 // pk[r][b] = norm * scale_r * sum_groups partial / N_b
 __global__ void k_bin_reduce(const double* __restrict__ partials, int64_t nitems, int64_t groups, int nb,
                              int64_t count, const int64_t* __restrict__ nmodes, double norm, int scale_kind,
-                             const unsigned long long* __restrict__ ntot, double ncells, double* __restrict__ pk,
-                             uint32_t* flags) {
+                             const unsigned long long* __restrict__ ntot, const SlotOut* __restrict__ slots,
+                             double ncells, double* __restrict__ pk, uint32_t* flags) {
   const int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (idx >= nitems * 2 * nb) return;
   const int b = (int)(idx % nb);
   const int64_t rs = idx / nb;  // 2 * item + s
   if (rs >= count) return;
+  double* dst = pk + rs * nb;
+  if (slots) {  // batched pipeline: per-slot destinations, unrequested slots skipped
+    dst = slots[rs].pk;
+    if (!dst) return;
+    if (b == 0 && slots[rs].ntot) *slots[rs].ntot = (int64_t)ntot[rs];
+  }
   const int64_t item = rs / 2, s = rs - 2 * item;
   double acc = 0.0;
   for (int64_t gidx = 0; gidx < groups; ++gidx) acc += partials[((item * groups + gidx) * 2 + s) * nb + b];
@@ -673,13 +696,11 @@ __global__ void k_bin_reduce(const double* __restrict__ partials, int64_t nitems
     const double nhat = nt / ncells;
     scale = 1.0 / (nhat * nhat);
   }
-  pk[rs * nb + b] = norm * scale * acc / (double)nmodes[b];
+  dst[b] = norm * scale * acc / (double)nmodes[b];
 }
 
-__global__ void k_covariance(const double* __restrict__ pk, int64_t R, int nb, double* __restrict__ cov,
-                             double* __restrict__ cnorm) {
-  const int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (idx >= (int64_t)nb * nb) return;
+__device__ __forceinline__ void covariance_entry(const double* __restrict__ pk, int64_t R, int nb, int64_t idx,
+                                                 double* __restrict__ cov, double* __restrict__ cnorm) {
   const int a = (int)(idx / nb), b = (int)(idx % nb);
   double ma = 0.0, mb = 0.0;
   for (int64_t r = 0; r < R; ++r) {
@@ -696,6 +717,19 @@ __global__ void k_covariance(const double* __restrict__ pk, int64_t R, int nb, d
   }
   if (cov) cov[idx] = c / (double)(R - 1);
   if (cnorm) cnorm[idx] = (s2 / (double)R) / (ma * mb) - 1.0;
+}
+
+__global__ void k_covariance(const double* __restrict__ pk, int64_t R, int nb, double* __restrict__ cov,
+                             double* __restrict__ cnorm) {
+  const int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (idx < (int64_t)nb * nb) covariance_entry(pk, R, nb, idx, cov, cnorm);
+}
+
+// one request per blockIdx.y
+__global__ void k_covariance_batch(const CovItem* __restrict__ items, int nb) {
+  const int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const CovItem it = items[blockIdx.y];
+  if (idx < (int64_t)nb * nb) covariance_entry(it.pk, it.R, nb, idx, it.cov, it.cnorm);
 }
 
 // ---------------------------------------------------------------------------
@@ -759,6 +793,10 @@ __global__ void k_copy_ntot(const unsigned long long* __restrict__ src, int64_t*
   if (i < n) dst[i] = (int64_t)src[i];
 }
 
+__global__ void k_advance(unsigned long long* p, unsigned long long by) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *p += by;
+}
+
 __global__ void k_zero_u64(unsigned long long* p, int64_t n) {
   const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (i < n) p[i] = 0;
@@ -814,15 +852,38 @@ hipError_t launch_lag_octant(int ndim, const int32_t* O, const double* h, int ki
   return hipGetLastError();
 }
 
+static bool nbuf_ok(const LineGeom& g, int mix) { return (mix != 0) == (g.nbuf == 2); }
+
+// kernel variant of a transform (the MIX template argument)
+static int fft_variant(const FftDesc& f) {
+  int v = 0;
+  for (int i = 0; i < f.nst; ++i) {
+    const int r = f.rad[i];
+    if (r & (r - 1)) v = std::max(v, r <= 7 ? 1 : 2);
+  }
+  return v;
+}
+
+template <int V>
+struct Variant {
+  static constexpr int value = V;
+};
+// calls fn(Variant<v>{}) for the run-time variant v
+template <typename F>
+static void with_variant(int v, F&& fn) {
+  if (v == 2)
+    fn(Variant<2>{});
+  else if (v == 1)
+    fn(Variant<1>{});
+  else
+    fn(Variant<0>{});
+}
+
 hipError_t launch_dct_axis(const LineGeom& g, const FftDesc& f, const DctArgs& a, hipStream_t s) {
   const size_t lds = lines_lds_bytes(g, sizeof(cpx<double>));
-  bool mix = false;
-  for (int i = 0; i < f.nst; ++i) mix |= (f.rad[i] & (f.rad[i] - 1)) != 0;
-  if (mix != (g.nbuf == 2)) return hipErrorInvalidValue;
-  if (mix)
-    CE_LAUNCH(k_dct_axis<true>, pass_grid(g), pass_block(g), lds, s, g, f, a);
-  else
-    CE_LAUNCH(k_dct_axis<false>, pass_grid(g), pass_block(g), lds, s, g, f, a);
+  const int mix = fft_variant(f);
+  if (!nbuf_ok(g, mix)) return hipErrorInvalidValue;
+  with_variant(mix, [&](auto v) { CE_LAUNCH((k_dct_axis<decltype(v)::value>), pass_grid(g), pass_block(g), lds, s, g, f, a); });
   return hipGetLastError();
 }
 
@@ -846,60 +907,40 @@ hipError_t launch_sqrt_table(const double* lam, int ndim, const int32_t* O, doub
   return hipGetLastError();
 }
 
-static bool nbuf_ok(const LineGeom& g, bool mix) { return mix == (g.nbuf == 2); }
-
-static bool is_mixed(const FftDesc& f) {
-  for (int i = 0; i < f.nst; ++i)
-    if (f.rad[i] & (f.rad[i] - 1)) return true;
-  return false;
-}
-
 hipError_t launch_noise_pass(int prec, const LineGeom& g, const FftDesc& f, const NoiseArgs& n, void* out,
                              hipStream_t s) {
-  const bool mix = is_mixed(f);
+  const int mix = fft_variant(f);
   if (!nbuf_ok(g, mix) || g.R < 2 || (g.R & 1) || (g.B & 1)) return hipErrorInvalidValue;
-  if (prec == 0) {
-    const size_t lds = lines_lds_bytes(g, sizeof(cpx<float>));
-    if (mix)
-      CE_LAUNCH((k_noise_pass<float, true>), pass_grid(g), pass_block(g), lds, s, g, f, n,
-                         static_cast<cpx<float>*>(out));
+  with_variant(mix, [&](auto v) {
+    constexpr int V = decltype(v)::value;
+    if (prec == 0)
+      CE_LAUNCH((k_noise_pass<float, V>), pass_grid(g), pass_block(g), lines_lds_bytes(g, sizeof(cpx<float>)), s, g,
+                f, n, static_cast<cpx<float>*>(out));
     else
-      CE_LAUNCH((k_noise_pass<float, false>), pass_grid(g), pass_block(g), lds, s, g, f, n,
-                         static_cast<cpx<float>*>(out));
-  } else {
-    const size_t lds = lines_lds_bytes(g, sizeof(cpx<double>));
-    if (mix)
-      CE_LAUNCH((k_noise_pass<double, true>), pass_grid(g), pass_block(g), lds, s, g, f, n,
-                         static_cast<cpx<double>*>(out));
-    else
-      CE_LAUNCH((k_noise_pass<double, false>), pass_grid(g), pass_block(g), lds, s, g, f, n,
-                         static_cast<cpx<double>*>(out));
-  }
+      CE_LAUNCH((k_noise_pass<double, V>), pass_grid(g), pass_block(g), lines_lds_bytes(g, sizeof(cpx<double>)), s,
+                g, f, n, static_cast<cpx<double>*>(out));
+  });
   return hipGetLastError();
 }
 
 template <typename T>
-static void line_pass_t(int dir, bool mix, const LineGeom& g, const FftDesc& f, const void* in, void* out,
+static void line_pass_t(int dir, int mix, const LineGeom& g, const FftDesc& f, const void* in, void* out,
                         hipStream_t s) {
   const size_t lds = lines_lds_bytes(g, sizeof(cpx<T>));
   const cpx<T>* i = static_cast<const cpx<T>*>(in);
   cpx<T>* o = static_cast<cpx<T>*>(out);
-  if (dir > 0) {
-    if (mix)
-      CE_LAUNCH((k_line_pass<T, 1, true>), pass_grid(g), pass_block(g), lds, s, g, f, i, o);
+  with_variant(mix, [&](auto v) {
+    constexpr int V = decltype(v)::value;
+    if (dir > 0)
+      CE_LAUNCH((k_line_pass<T, 1, V>), pass_grid(g), pass_block(g), lds, s, g, f, i, o);
     else
-      CE_LAUNCH((k_line_pass<T, 1, false>), pass_grid(g), pass_block(g), lds, s, g, f, i, o);
-  } else {
-    if (mix)
-      CE_LAUNCH((k_line_pass<T, -1, true>), pass_grid(g), pass_block(g), lds, s, g, f, i, o);
-    else
-      CE_LAUNCH((k_line_pass<T, -1, false>), pass_grid(g), pass_block(g), lds, s, g, f, i, o);
-  }
+      CE_LAUNCH((k_line_pass<T, -1, V>), pass_grid(g), pass_block(g), lds, s, g, f, i, o);
+  });
 }
 
 hipError_t launch_line_pass(int prec, int dir, const LineGeom& g, const FftDesc& f, const void* in, void* out,
                             hipStream_t s) {
-  const bool mix = is_mixed(f);
+  const int mix = fft_variant(f);
   if (!nbuf_ok(g, mix)) return hipErrorInvalidValue;
   if (prec == 0)
     line_pass_t<float>(dir, mix, g, f, in, out, s);
@@ -909,19 +950,18 @@ hipError_t launch_line_pass(int prec, int dir, const LineGeom& g, const FftDesc&
 }
 
 template <typename T>
-static void row_inverse_t(bool mix, const LineGeom& g, const FftDesc& f, const RowEpi& e, const void* in,
+static void row_inverse_t(int mix, const LineGeom& g, const FftDesc& f, const RowEpi& e, const void* in,
                           hipStream_t s) {
   const size_t lds = lines_lds_bytes(g, sizeof(cpx<T>));
   const cpx<T>* i = static_cast<const cpx<T>*>(in);
-  if (mix)
-    CE_LAUNCH((k_row_inverse<T, true>), pass_grid(g), pass_block(g), lds, s, g, f, e, i);
-  else
-    CE_LAUNCH((k_row_inverse<T, false>), pass_grid(g), pass_block(g), lds, s, g, f, e, i);
+  with_variant(mix, [&](auto v) {
+    CE_LAUNCH((k_row_inverse<T, decltype(v)::value>), pass_grid(g), pass_block(g), lds, s, g, f, e, i);
+  });
 }
 
 hipError_t launch_row_inverse(int prec, const LineGeom& g, const FftDesc& f, const RowEpi& e, const void* in,
                               hipStream_t s) {
-  const bool mix = is_mixed(f) || (e.mode == 2 && is_mixed(e.fwd));
+  const int mix = std::max(fft_variant(f), e.mode == 2 ? fft_variant(e.fwd) : 0);
   if (!nbuf_ok(g, mix)) return hipErrorInvalidValue;
   if (prec == 0)
     row_inverse_t<float>(mix, g, f, e, in, s);
@@ -931,52 +971,51 @@ hipError_t launch_row_inverse(int prec, const LineGeom& g, const FftDesc& f, con
 }
 
 template <typename T>
-static void pair_forward_t(bool mix, const LineGeom& g, const FftDesc& f, const PairLoad& p, hipStream_t s) {
+static void pair_forward_t(int mix, const LineGeom& g, const FftDesc& f, const PairLoad& p, hipStream_t s) {
   const size_t lds = lines_lds_bytes(g, sizeof(cpx<T>));
-  if (mix)
-    CE_LAUNCH((k_pair_forward<T, true>), pass_grid(g), pass_block(g), lds, s, g, f, p);
-  else
-    CE_LAUNCH((k_pair_forward<T, false>), pass_grid(g), pass_block(g), lds, s, g, f, p);
+  with_variant(mix, [&](auto v) {
+    CE_LAUNCH((k_pair_forward<T, decltype(v)::value>), pass_grid(g), pass_block(g), lds, s, g, f, p);
+  });
 }
 
 hipError_t launch_pair_forward(int prec, const LineGeom& g, const FftDesc& f, const PairLoad& p, hipStream_t s) {
-  if (!nbuf_ok(g, is_mixed(f))) return hipErrorInvalidValue;
+  const int mix = fft_variant(f);
+  if (!nbuf_ok(g, mix)) return hipErrorInvalidValue;
   if (prec == 0)
-    pair_forward_t<float>(is_mixed(f), g, f, p, s);
+    pair_forward_t<float>(mix, g, f, p, s);
   else
-    pair_forward_t<double>(is_mixed(f), g, f, p, s);
+    pair_forward_t<double>(mix, g, f, p, s);
   return hipGetLastError();
 }
 
 template <typename T>
-static void bin_pass_t(bool mix, const LineGeom& g, const FftDesc& f, const BinArgs& b, const void* in,
+static void bin_pass_t(int mix, const LineGeom& g, const FftDesc& f, const BinArgs& b, const void* in,
                        hipStream_t s) {
   const size_t lds = lines_lds_bytes(g, sizeof(cpx<T>)) + (size_t)g.R * b.nb * sizeof(double) +
                      (size_t)g.R * g.nlanes * sizeof(RunEnds);
   const cpx<T>* i = static_cast<const cpx<T>*>(in);
-  if (mix)
-    CE_LAUNCH((k_bin_pass<T, true>), pass_grid(g), pass_block(g), lds, s, g, f, b, i);
-  else
-    CE_LAUNCH((k_bin_pass<T, false>), pass_grid(g), pass_block(g), lds, s, g, f, b, i);
+  with_variant(mix, [&](auto v) {
+    CE_LAUNCH((k_bin_pass<T, decltype(v)::value>), pass_grid(g), pass_block(g), lds, s, g, f, b, i);
+  });
 }
 
 hipError_t launch_bin_pass(int prec, const LineGeom& g, const FftDesc& f, const BinArgs& b, const void* in,
                            hipStream_t s) {
-  if (!nbuf_ok(g, is_mixed(f))) return hipErrorInvalidValue;
+  const int mix = fft_variant(f);
+  if (!nbuf_ok(g, mix)) return hipErrorInvalidValue;
   if (prec == 0)
-    bin_pass_t<float>(is_mixed(f), g, f, b, in, s);
+    bin_pass_t<float>(mix, g, f, b, in, s);
   else
-    bin_pass_t<double>(is_mixed(f), g, f, b, in, s);
+    bin_pass_t<double>(mix, g, f, b, in, s);
   return hipGetLastError();
 }
 
 hipError_t launch_bin_reduce(const double* partials, int64_t nitems, int64_t groups, int nb, int64_t count,
                              const int64_t* nmodes, double norm, int scale_kind, const unsigned long long* ntot_u,
-                             const int64_t* ntot_s, double ncells, double* pk, uint32_t* flags, hipStream_t s) {
-  (void)ntot_s;
+                             const SlotOut* slots, double ncells, double* pk, uint32_t* flags, hipStream_t s) {
   const int64_t n = nitems * 2 * nb;
   hipLaunchKernelGGL(k_bin_reduce, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, partials, nitems, groups, nb,
-                     count, nmodes, norm, scale_kind, ntot_u, ncells, pk, flags);
+                     count, nmodes, norm, scale_kind, ntot_u, slots, ncells, pk, flags);
   return hipGetLastError();
 }
 
@@ -1015,6 +1054,15 @@ hipError_t launch_covariance(const double* pk, int64_t count, int nb, double* co
   return hipGetLastError();
 }
 
+hipError_t launch_covariance_batch(const CovItem* items, int64_t nitems, int nb, hipStream_t s) {
+  const int64_t n = (int64_t)nb * nb;
+  for (int64_t i = 0; i < nitems; i += 65535) {
+    const unsigned ny = (unsigned)std::min<int64_t>(65535, nitems - i);
+    hipLaunchKernelGGL(k_covariance_batch, dim3((unsigned)((n + 255) / 256), ny), dim3(256), 0, s, items + i, nb);
+  }
+  return hipGetLastError();
+}
+
 hipError_t launch_debug_philox(uint32_t k0, uint32_t k1, const uint32_t* ctr, int64_t n, uint32_t* out,
                                hipStream_t s) {
   hipLaunchKernelGGL(k_debug_philox, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, k0, k1, ctr[0], ctr[1],
@@ -1031,6 +1079,11 @@ hipError_t launch_debug_noise(int prec, const NoiseArgs& n, uint64_t pair, int64
   else
     hipLaunchKernelGGL(k_debug_noise<double>, grid, dim3(256), 0, s, n, (uint32_t)pair, cells,
                        static_cast<cpx<double>*>(out));
+  return hipGetLastError();
+}
+
+hipError_t launch_advance(unsigned long long* p, unsigned long long by, hipStream_t s) {
+  hipLaunchKernelGGL(k_advance, dim3(1), dim3(64), 0, s, p, by);
   return hipGetLastError();
 }
 

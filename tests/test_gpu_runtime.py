@@ -1,0 +1,284 @@
+"""GPU tests of the runtime around the pipeline, through the C ABI: the captured
+(HIP graph) pipeline and the request server.  Both must reproduce ce_pipeline_run
+bit for bit, so the references here are eager ce_pipeline_run calls (themselves
+checked against the oracle in test_gpu_parity.py); the server mix also has one
+case checked against the oracle directly.
+"""
+
+import time
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+from oracle import embedding, fields as ofields, lognormal_poisson as olp, pk as opk  # noqa: E402
+
+
+@pytest.fixture(scope="module")
+def ce():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1406_6072_amd import binding
+    ctx = binding.ctx_create(0)
+    yield binding, ctx
+    binding.ctx_destroy(ctx)
+
+
+def outputs(cells, count, nb, cov=True):
+    return dict(out_pk=torch.empty(count * nb, dtype=torch.float64, device="cuda"),
+                out_counts=torch.empty(count * cells, dtype=torch.int32, device="cuda"),
+                out_ntot=torch.empty(count, dtype=torch.int64, device="cuda"),
+                out_cov=torch.empty(nb * nb, dtype=torch.float64, device="cuda") if cov else None)
+
+
+def host(o):
+    return {k: v.cpu() for k, v in o.items() if v is not None}
+
+
+GRAPH_CASES = [((128, 128), dict(kind="exp", sigma2=1.0, a=5.0), 0, 8, 32),
+               ((24, 24, 24), dict(kind="exp", sigma2=0.8, a=1.5), 1, 4, 12)]
+
+
+@pytest.mark.parametrize("n,xi,prec,count,nb", GRAPH_CASES)
+def test_graph_replays_match_eager(ce, n, xi, prec, count, nb):
+    """Four replays with eager pipeline calls between them; replay k must equal the eager
+    call for realizations first + k*count .. (the graph advances by itself)."""
+    b, ctx = ce
+    print("graph case", n, prec, flush=True)
+    plan = b.plan_embedding(ctx, n, (1.0,) * len(n), xi, prec)
+    seed, rid, first, nbar = 77, 5, 6, 2.0
+    g_out = outputs(plan.cells, count, nb)
+    g = b.pipeline_graph_create(ctx, plan, seed, rid, first, count, nbar, nb, **g_out)
+    try:
+        for k in range(4):
+            b.pipeline_graph_launch(g)
+            torch.cuda.synchronize()
+            got = host(g_out)
+            ref = outputs(plan.cells, count, nb)
+            b.pipeline_run(ctx, plan, seed, rid, first + k * count, count, nbar, nb, **ref)
+            torch.cuda.synchronize()
+            assert b.ctx_check(ctx) == 0
+            ref = host(ref)
+            for key in ref:
+                assert torch.equal(got[key], ref[key]), (k, key)
+    finally:
+        b.pipeline_graph_destroy(g)
+    plan.release()
+
+
+def test_graph_rejects_odd_count(ce):
+    b, ctx = ce
+    plan = b.plan_embedding(ctx, (32, 32), (1.0, 1.0), dict(kind="exp", sigma2=1.0, a=3.0), 0)
+    o = outputs(plan.cells, 3, 8)
+    with pytest.raises(b.CeError):
+        b.pipeline_graph_create(ctx, plan, 1, 0, 0, 3, 1.0, 8, **o)
+    plan.release()
+
+
+def wait_all(b, server, tickets, timeout=90.0):
+    states = {}
+    t0 = time.time()
+    while len(states) < len(tickets):
+        for t in tickets:
+            if t in states:
+                continue
+            st, status, lat = b.server_poll(server, t)
+            if st >= 2:
+                states[t] = (st, status, lat)
+        assert time.time() - t0 < timeout, "server did not finish"
+        time.sleep(0.002)
+    return states
+
+
+MIX = [  # n, xi, prec, realizations, nbar, nbins
+    ((64, 64), dict(kind="exp", sigma2=0.5, a=8.0), 1, 6, 5.0, 16),
+    ((96, 96), dict(kind="powexp", sigma2=1.0, r0=4.0, gamma=1.8, rc=300.0), 0, 9, 0.3, 24),
+    ((32, 32, 32), dict(kind="powexp", sigma2=1.0, r0=10.0, gamma=1.8, rc=0.0), 0, 4, 1.0, 8),  # not PSD
+    ((20, 20, 20), dict(kind="exp", sigma2=0.8, a=1.5), 0, 5, 2.0, 10),
+    ((64, 64), dict(kind="exp", sigma2=0.5, a=8.0), 1, 4, 1.0, 16),  # same plan as the first
+    ((256, 256), dict(kind="exp", sigma2=1.0, a=5.0), 0, 32, 0.3, 64),
+    ((40, 40), dict(kind="exp", sigma2=1.0, a=3.0), 1, 1, 5.0, 12),
+    ((96, 96), dict(kind="powexp", sigma2=1.0, r0=4.0, gamma=1.8, rc=300.0), 0, 2, 0.3, 24),
+]
+
+
+@pytest.mark.parametrize("slots", [3, 1])
+def test_server_mix_matches_requests_alone(ce, slots):
+    b, ctx = ce
+    server = b.server_create(0, slots=slots)
+    try:
+        outs, tickets = [], []
+        for i, (n, xi, prec, R, nbar, nb) in enumerate(MIX):
+            cells = int(np.prod(n))
+            o = outputs(cells, R, nb)
+            outs.append(o)
+            tickets.append(b.server_submit(server, n, (1.0,) * len(n), xi, prec, 11, 100 + i, R, nbar, nb, **o))
+        states = wait_all(b, server, tickets)
+        stats = b.server_stats(server)
+    finally:
+        b.server_destroy(server)
+    for i, (n, xi, prec, R, nbar, nb) in enumerate(MIX):
+        st, status, lat = states[tickets[i]]
+        print("request", i, n, prec, R, "state", st, "status", status, "latency_ms %.2f" % lat, flush=True)
+        if i == 2:
+            assert st == 3 and status == 2  # CE_E_NOT_PSD, alone
+            continue
+        assert st == 2 and status == 0 and lat > 0
+        plan = b.plan_embedding(ctx, n, (1.0,) * len(n), xi, prec)
+        ref = outputs(plan.cells, R, nb)
+        if R < 2:
+            ref["out_cov"] = None
+        b.pipeline_run(ctx, plan, 11, 100 + i, 0, R, nbar, nb, **ref)
+        torch.cuda.synchronize()
+        assert b.ctx_check(ctx) == 0
+        got = host(outs[i])
+        for key, v in host(ref).items():
+            assert torch.equal(got[key], v), (i, key)
+        plan.release()
+    assert stats["submitted"] == len(MIX) and stats["completed"] == len(MIX) - 1 and stats["failed"] == 1
+    assert stats["cache_hits"] >= 2 and stats["cache_misses"] == 6
+    assert stats["p99_ms"] >= stats["p50_ms"] > 0
+
+
+def test_server_request_against_oracle(ce):
+    """One served request checked against the oracle end to end (fields are not returned by
+    the server, so counts are checked through their statistics: the oracle run on the same
+    Philox streams must give the same N_tot and P(k))."""
+    b, _ = ce
+    n, xi, prec, R, nbar, nb, seed, rid = (48, 48), dict(kind="exp", sigma2=0.5, a=6.0), 1, 4, 3.0, 12, 3, 9
+    server = b.server_create(0, slots=2)
+    try:
+        o = outputs(48 * 48, R, nb, cov=False)
+        t = b.server_submit(server, n, (1.0, 1.0), xi, prec, seed, rid, R, nbar, nb, **o)
+        st, status, _ = wait_all(b, server, [t])[t]
+    finally:
+        b.server_destroy(server)
+    assert st == 2 and status == 0
+    ref_plan = embedding.plan(n, (1.0, 1.0), xi)
+    g = ofields.generate_fields(ref_plan, seed, rid, 0, R)
+    _, rc, rn = olp.lognormal_poisson(g, ref_plan["sigma2"], nbar, seed, rid, 0)
+    counts = o["out_counts"].cpu().numpy().reshape((R,) + n)
+    # FP64 fields differ from the oracle's by ~1e-15 relative: a Poisson draw can flip only
+    # where a uniform lands within that distance of a CDF step, so nearly all cells agree
+    assert np.mean(counts == rc) > 0.9999
+    rp = opk.estimate_pk(counts, 1.0, nb, kind="counts", ntot=o["out_ntot"].cpu().numpy())
+    assert np.max(np.abs(o["out_pk"].cpu().numpy().reshape(R, nb) / rp - 1)) <= 1e-12
+    assert abs(int(o["out_ntot"].sum()) - int(rn.sum())) <= 2
+
+
+def test_server_rejects_what_never_fits(ce):
+    b, _ = ce
+    server = b.server_create(0, slots=2, hbm_budget_bytes=1 << 20)
+    try:
+        o = outputs(128 * 128, 8, 16)
+        t = b.server_submit(server, (128, 128), (1.0, 1.0), dict(kind="exp", sigma2=1.0, a=5.0), 0, 1, 0, 8,
+                            0.3, 16, **o)
+        st, status, _ = wait_all(b, server, [t])[t]
+    finally:
+        b.server_destroy(server)
+    assert st == 3 and status == 3  # CE_E_OOM
+
+
+def test_server_budget_serialises_but_stays_exact(ce):
+    """A budget that admits one 256^2 request at a time: later requests wait (admission
+    stalls) and still produce what they produce alone."""
+    b, ctx = ce
+    n, xi, R, nb = (256, 256), dict(kind="exp", sigma2=1.0, a=5.0), 16, 32
+    server = b.server_create(0, slots=4, hbm_budget_bytes=40 << 20)
+    try:
+        outs, tickets = [], []
+        for i in range(4):
+            o = outputs(256 * 256, R, nb)
+            outs.append(o)
+            tickets.append(b.server_submit(server, n, (1.0, 1.0), xi, 0, 4, i, R, 0.3, nb, **o))
+        states = wait_all(b, server, tickets)
+        stats = b.server_stats(server)
+    finally:
+        b.server_destroy(server)
+    assert all(states[t][0] == 2 for t in tickets)
+    assert stats["admission_stalls"] > 0 and stats["cache_hits"] == 3
+    plan = b.plan_embedding(ctx, n, (1.0, 1.0), xi, 0)
+    for i in range(4):
+        ref = outputs(plan.cells, R, nb)
+        b.pipeline_run(ctx, plan, 4, i, 0, R, 0.3, nb, **ref)
+        torch.cuda.synchronize()
+        got = host(outs[i])
+        for key, v in host(ref).items():
+            assert torch.equal(got[key], v), (i, key)
+    plan.release()
+
+
+def test_server_cancel_queued(ce):
+    b, _ = ce
+    server = b.server_create(0, slots=1)
+    try:
+        big = outputs(512 * 512, 64, 32)
+        t0 = b.server_submit(server, (512, 512), (1.0, 1.0), dict(kind="exp", sigma2=1.0, a=5.0), 0, 1, 0, 64,
+                             0.3, 32, **big)
+        small = outputs(64 * 64, 2, 8)
+        t1 = b.server_submit(server, (64, 64), (1.0, 1.0), dict(kind="exp", sigma2=1.0, a=5.0), 0, 1, 1, 2,
+                             0.3, 8, **small)
+        cancelled = b.server_cancel(server, t1) == 0
+        states = wait_all(b, server, [t0, t1])
+    finally:
+        b.server_destroy(server)
+    assert states[t0][0] == 2
+    # the cancel can lose the race against admission; either outcome must be consistent
+    assert states[t1][0] == (4 if cancelled else 2)
+
+
+def test_batch_matches_items_alone(ce):
+    """Ragged batch: several shapes, both precisions, odd counts, odd first realizations of
+    pairs, optional outputs; every item equals its own ce_pipeline_run bit for bit."""
+    b, ctx = ce
+    specs = [  # n, xi, prec, first, count, nbar, nb, with_counts, with_cov
+        ((32, 32), dict(kind="exp", sigma2=1.0, a=3.0), 0, 0, 2, 1.0, 8, True, True),
+        ((48, 48), dict(kind="exp", sigma2=0.4, a=5.0), 0, 4, 3, 0.5, 12, True, True),
+        ((32, 32), dict(kind="exp", sigma2=1.5, a=2.0), 0, 2, 5, 5.0, 8, False, True),
+        ((48, 48), dict(kind="exp", sigma2=0.4, a=5.0), 1, 0, 2, 0.5, 12, True, False),
+        ((16, 16, 16), dict(kind="exp", sigma2=0.8, a=1.5), 0, 0, 1, 2.0, 6, True, False),
+        ((32, 32), dict(kind="exp", sigma2=1.0, a=3.0), 0, 6, 2, 1.0, 16, True, True),  # other nbins
+        ((96, 96), dict(kind="powexp", sigma2=1.0, r0=4.0, gamma=1.8, rc=300.0), 0, 0, 4, 0.3, 24, True, True),
+        ((16, 16, 16), dict(kind="exp", sigma2=0.8, a=1.5), 0, 2, 4, 2.0, 6, True, True),
+    ]
+    plans, items = [], []
+    for k, (n, xi, prec, first, count, nbar, nb, wc, wv) in enumerate(specs):
+        plan = b.plan_embedding(ctx, n, (1.0,) * len(n), xi, prec)
+        plans.append(plan)
+        o = outputs(plan.cells, count, nb, cov=wv)
+        if not wc:
+            o["out_counts"] = None
+        items.append(dict(plan=plan, seed=3 + k, request_id=40 + k, first_realization=first, count=count,
+                          nbar=nbar, nbins=nb, **o))
+    for rep in range(2):  # the second call reuses the staging and scratch buffers
+        b.pipeline_run_batch(ctx, items)
+        torch.cuda.synchronize()
+        assert b.ctx_check(ctx) == 0
+        for k, it in enumerate(items):
+            ref = outputs(it["plan"].cells, it["count"], it["nbins"], cov=it["out_cov"] is not None)
+            if it["out_counts"] is None:
+                ref["out_counts"] = None
+            b.pipeline_run(ctx, it["plan"], it["seed"], it["request_id"], it["first_realization"], it["count"],
+                           it["nbar"], it["nbins"], **ref)
+            torch.cuda.synchronize()
+            got = host({key: it[key] for key in ("out_pk", "out_counts", "out_ntot", "out_cov")})
+            for key, v in host(ref).items():
+                assert torch.equal(got[key], v), (rep, k, key)
+    for p in plans:
+        p.release()
+
+
+def test_batch_rejects_bad_item_without_launching(ce):
+    b, ctx = ce
+    plan = b.plan_embedding(ctx, (32, 32), (1.0, 1.0), dict(kind="exp", sigma2=1.0, a=3.0), 0)
+    good = dict(plan=plan, count=2, nbar=1.0, nbins=8, **outputs(plan.cells, 2, 8))
+    bad = dict(good, first_realization=1)
+    sentinel = good["out_pk"].fill_(-7.0).clone()
+    with pytest.raises(b.CeError):
+        b.pipeline_run_batch(ctx, [good, bad])
+    torch.cuda.synchronize()
+    assert torch.equal(good["out_pk"], sentinel)
+    plan.release()
