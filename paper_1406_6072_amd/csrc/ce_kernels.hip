@@ -174,8 +174,46 @@ __device__ __forceinline__ void poisson_pair(double mua, double mub, bool has_b,
   const int Kmax = Ka > Kb ? Ka : Kb;
   for (int c = 0; c < Kmax; ++c) {
     const Words4 w = philox4x32_10(cell, pair, rid, 1u + (uint32_t)c, k0, k1);
-    if (c < Ka) na += poisson_chunk(unit52(w.x0, w.x1), chunk_mean(mua, c, Ka), inv, inv_lds, flags);
-    if (c < Kb) nb += poisson_chunk(unit52(w.x2, w.x3), chunk_mean(mub, c, Kb), inv, inv_lds, flags);
+    // the two inversions run in one loop, so a wave iterates max(steps a, steps b) times
+    // rather than their sum; each realization's sequence of operations is that of
+    // poisson_chunk
+    const bool da = c < Ka, db = c < Kb;
+    const double ua = unit52(w.x0, w.x1), ub = unit52(w.x2, w.x3);
+    const double ma = da ? chunk_mean(mua, c, Ka) : 0.0;
+    const double mb = db ? chunk_mean(mub, c, Kb) : 0.0;
+    double pa = exp(-ma), pb = exp(-mb);
+    double Fa = pa, Fb = pb;
+    int ka = 0, kb = 0;
+    bool ra = da && ua > Fa && pa > 0.0;
+    bool rb = db && ub > Fb && pb > 0.0;
+    while (ra || rb) {
+      if (ra) {
+        ++ka;
+        if (ka > kMaxPoissonSteps) {
+          atomicOr(flags, 1u);
+          ra = false;
+        } else {
+          const double ik = (inv_lds && ka <= kInvLds) ? inv_lds[ka] : inv[ka];
+          pa = __dmul_rn(__dmul_rn(pa, ma), ik);
+          Fa = __dadd_rn(Fa, pa);
+          ra = ua > Fa && pa > 0.0;
+        }
+      }
+      if (rb) {
+        ++kb;
+        if (kb > kMaxPoissonSteps) {
+          atomicOr(flags, 1u);
+          rb = false;
+        } else {
+          const double ik = (inv_lds && kb <= kInvLds) ? inv_lds[kb] : inv[kb];
+          pb = __dmul_rn(__dmul_rn(pb, mb), ik);
+          Fb = __dadd_rn(Fb, pb);
+          rb = ub > Fb && pb > 0.0;
+        }
+      }
+    }
+    na += ka;
+    nb += kb;
   }
 }
 
@@ -595,6 +633,7 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(sizeof
         int bin = shell_of_t(t, NN);
         int64_t edge = (int64_t)(bin + 1) * N;
         edge *= edge;  // (bin+1)^2 N^2: the mode stays in `bin` while T q2 <= edge
+        int64_t estep = (int64_t)(2 * bin + 3) * NN;  // edge(bin + 1) - edge(bin)
         double run = 0.0;
         e.first_bin = bin;
         for (int a = a0; a < a1; ++a) {
@@ -606,9 +645,12 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(sizeof
               acc[r * nb + bin] = wgt * run;  // interior run: complete within this chunk
             }
             e.single = 0;
-            bin = shell_of_t(t, NN);
-            edge = (int64_t)(bin + 1) * N;
-            edge *= edge;
+            // next shell that holds the mode (t grows slowly: usually one step)
+            do {
+              ++bin;
+              edge += estep;
+              estep += 2 * NN;
+            } while (t > edge);
             run = 0.0;
           }
           // power of the mode pair in the pass precision, summed in FP64
@@ -687,8 +729,12 @@ __global__ void k_bin_reduce(const double* __restrict__ partials, int64_t nitems
     if (b == 0 && slots[rs].ntot) *slots[rs].ntot = (int64_t)ntot[rs];
   }
   const int64_t item = rs / 2, s = rs - 2 * item;
+  // unrolled so that several loads are in flight; the sum stays in group order
+  const double* src = partials + (item * groups * 2 + s) * nb + b;
+  const int64_t stride = 2 * (int64_t)nb;
   double acc = 0.0;
-  for (int64_t gidx = 0; gidx < groups; ++gidx) acc += partials[((item * groups + gidx) * 2 + s) * nb + b];
+#pragma unroll 8
+  for (int64_t gidx = 0; gidx < groups; ++gidx) acc += src[gidx * stride];
   double scale = 1.0;
   if (scale_kind == 1) {
     const double nt = (double)ntot[rs];
@@ -703,6 +749,7 @@ __device__ __forceinline__ void covariance_entry(const double* __restrict__ pk, 
                                                  double* __restrict__ cov, double* __restrict__ cnorm) {
   const int a = (int)(idx / nb), b = (int)(idx % nb);
   double ma = 0.0, mb = 0.0;
+#pragma unroll 8
   for (int64_t r = 0; r < R; ++r) {
     ma += pk[r * nb + a];
     mb += pk[r * nb + b];
@@ -710,6 +757,7 @@ __device__ __forceinline__ void covariance_entry(const double* __restrict__ pk, 
   ma /= (double)R;
   mb /= (double)R;
   double c = 0.0, s2 = 0.0;
+#pragma unroll 8
   for (int64_t r = 0; r < R; ++r) {
     const double pa = pk[r * nb + a], pb = pk[r * nb + b];
     c += (pa - ma) * (pb - mb);

@@ -137,6 +137,8 @@ FIELD_CASES = [
      0, 6, 5),
     ("rect_2d_f32_mixed", (96, 80), (1.0, 0.5), dict(kind="exp", sigma2=1.0, a=3.0), 0, 0, 4),
     ("primes_2d_f64", (62, 34), (1.0, 1.0), dict(kind="exp", sigma2=1.0, a=2.0), 1, 2, 3),
+    ("primes_2d_f32", (46, 26), (1.0, 1.0), dict(kind="exp", sigma2=1.0, a=2.0), 0, 0, 3),
+    ("primes_3d_f32", (22, 22, 22), (1.0, 1.0, 1.0), dict(kind="exp", sigma2=0.8, a=1.5), 0, 0, 2),
     ("vol_3d_f64", (16, 12, 20), (1.0, 1.0, 1.0), dict(kind="exp", sigma2=0.8, a=1.5), 1, 0, 3),
     ("vol_3d_f32", (32, 32, 32), (1.0, 1.0, 1.0), dict(kind="powexp", sigma2=2.0, r0=1.5, gamma=1.8, rc=100.0),
      0, 0, 4),
@@ -190,7 +192,8 @@ def test_lognormal_poisson_parity(ce, prec, first, masked):
 
 
 @pytest.mark.parametrize("prec", [1, 0])
-@pytest.mark.parametrize("n,nb", [((64, 64), 32), ((16, 16, 16), 8), ((48, 48), 12)])
+@pytest.mark.parametrize("n,nb", [((64, 64), 32), ((16, 16, 16), 8), ((48, 48), 12), ((58, 58), 14),
+                                  ((26, 26, 26), 6)])
 def test_pk_field_parity(ce, prec, n, nb):
     b, ctx = ce
     xi = dict(kind="exp", sigma2=1.0, a=2.0)
@@ -258,7 +261,9 @@ def test_covariance_parity(ce):
 PIPE_CASES = [((64, 64), dict(kind="exp", sigma2=0.5, a=8.0), 1, 32, 7),
               ((128, 128), dict(kind="powexp", sigma2=1.0, r0=4.0, gamma=1.8, rc=300.0), 0, 32, 6),
               ((16, 16, 16), dict(kind="exp", sigma2=0.8, a=1.5), 0, 8, 3),
-              ((48, 48), dict(kind="exp", sigma2=1.0, a=3.0), 1, 12, 4)]
+              ((48, 48), dict(kind="exp", sigma2=1.0, a=3.0), 1, 12, 4),
+              ((38, 38), dict(kind="exp", sigma2=1.0, a=3.0), 0, 10, 4),
+              ((22, 22, 22), dict(kind="exp", sigma2=0.8, a=1.5), 1, 6, 2)]
 
 
 @pytest.mark.parametrize("n,xi,prec,nb,count", PIPE_CASES)
