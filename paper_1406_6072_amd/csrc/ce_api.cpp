@@ -804,7 +804,7 @@ ce_status run_inverse(ce_ctx* ctx, const ce_plan* p, const InverseSetup& fs, uin
   epi.keep_last = p->n[last];
   LineGeom gl = make_geom((int)Ml, (int)Kl, rows, 1, npairs, rows * Ml, 0, elem,
                           mixed_radix(fs.fM[last]) || (epi.mode == 2 && mixed_radix(epi.fwd)), 1,
-                          cap_lines(ctx, 2, 2));
+                          cap_lines(ctx, 2, std::max(2, 256 / std::max(1, (int)Ml / kEPT))));
   CE_PROF(ctx, epi.mode == 2 ? "inverse_last_fused" : "inverse_last_fields", s,
           launch_row_inverse(p->prec, gl, fs.fM[last], epi, last_in, s));
   return CE_OK;

@@ -144,7 +144,7 @@ hipError_t launch_row_inverse(int prec, const LineGeom& g, const FftDesc& f, con
 hipError_t launch_pair_forward(int prec, const LineGeom& g, const FftDesc& f, const PairLoad& p, hipStream_t s);
 hipError_t launch_bin_pass(int prec, const LineGeom& g, const FftDesc& f, const BinArgs& b, const void* in,
                            hipStream_t s);
-hipError_t launch_bin_reduce(const double* partials, int64_t nitems, int64_t groups, int nb, int64_t count,
+hipError_t launch_bin_reduce(double* partials, int64_t nitems, int64_t groups, int nb, int64_t count,
                              const int64_t* nmodes, double norm, int scale_kind, const unsigned long long* ntot_u,
                              const SlotOut* slots, double ncells, double* pk, uint32_t* flags, hipStream_t s);
 hipError_t launch_lognormal_poisson(int prec, const void* fields, int64_t count, int64_t ncells, double s2half,

@@ -712,9 +712,28 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(sizeof
   }
 }
 
-// pk[r][b] = norm * scale_r * sum_groups partial / N_b
-__global__ void k_bin_reduce(const double* __restrict__ partials, int64_t nitems, int64_t groups, int nb,
-                             int64_t count, const int64_t* __restrict__ nmodes, double norm, int scale_kind,
+// Many line groups per item: the partials of each run of kGroupChunk groups are summed in
+// group order and the sum replaces the run's first entry (in place: a thread reads and
+// writes only its own run); k_bin_reduce then adds the runs in order.
+constexpr int kGroupChunk = 64;
+__global__ void k_bin_chunk_sum(double* __restrict__ partials, int64_t nitems, int64_t groups, int nb) {
+  const int64_t nchunks = (groups + kGroupChunk - 1) / kGroupChunk;
+  const int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (idx >= nitems * nchunks * 2 * nb) return;
+  const int64_t sb = idx % (2 * nb), t = idx / (2 * nb);
+  const int64_t c = t % nchunks, item = t / nchunks;
+  const int64_t g0 = c * kGroupChunk, g1 = g0 + kGroupChunk < groups ? g0 + kGroupChunk : groups;
+  double* p = partials + (item * groups + g0) * 2 * nb + sb;
+  const int64_t stride = 2 * (int64_t)nb;
+  double acc = 0.0;
+#pragma unroll 8
+  for (int64_t g = 0; g < g1 - g0; ++g) acc += p[g * stride];
+  p[0] = acc;
+}
+
+// pk[r][b] = norm * scale_r * sum_groups partial / N_b (groups taken gstep apart)
+__global__ void k_bin_reduce(const double* __restrict__ partials, int64_t nitems, int64_t groups, int64_t gstep,
+                             int nb, int64_t count, const int64_t* __restrict__ nmodes, double norm, int scale_kind,
                              const unsigned long long* __restrict__ ntot, const SlotOut* __restrict__ slots,
                              double ncells, double* __restrict__ pk, uint32_t* flags) {
   const int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
@@ -731,10 +750,10 @@ __global__ void k_bin_reduce(const double* __restrict__ partials, int64_t nitems
   const int64_t item = rs / 2, s = rs - 2 * item;
   // unrolled so that several loads are in flight; the sum stays in group order
   const double* src = partials + (item * groups * 2 + s) * nb + b;
-  const int64_t stride = 2 * (int64_t)nb;
+  const int64_t stride = 2 * (int64_t)nb * gstep;
   double acc = 0.0;
 #pragma unroll 8
-  for (int64_t gidx = 0; gidx < groups; ++gidx) acc += src[gidx * stride];
+  for (int64_t gidx = 0; gidx < (groups + gstep - 1) / gstep; ++gidx) acc += src[gidx * stride];
   double scale = 1.0;
   if (scale_kind == 1) {
     const double nt = (double)ntot[rs];
@@ -1058,12 +1077,19 @@ hipError_t launch_bin_pass(int prec, const LineGeom& g, const FftDesc& f, const 
   return hipGetLastError();
 }
 
-hipError_t launch_bin_reduce(const double* partials, int64_t nitems, int64_t groups, int nb, int64_t count,
+hipError_t launch_bin_reduce(double* partials, int64_t nitems, int64_t groups, int nb, int64_t count,
                              const int64_t* nmodes, double norm, int scale_kind, const unsigned long long* ntot_u,
                              const SlotOut* slots, double ncells, double* pk, uint32_t* flags, hipStream_t s) {
+  int64_t gstep = 1;
+  if (groups > kGroupChunk) {
+    const int64_t m = nitems * ((groups + kGroupChunk - 1) / kGroupChunk) * 2 * nb;
+    hipLaunchKernelGGL(k_bin_chunk_sum, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, s, partials, nitems, groups,
+                       nb);
+    gstep = kGroupChunk;
+  }
   const int64_t n = nitems * 2 * nb;
-  hipLaunchKernelGGL(k_bin_reduce, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, partials, nitems, groups, nb,
-                     count, nmodes, norm, scale_kind, ntot_u, slots, ncells, pk, flags);
+  hipLaunchKernelGGL(k_bin_reduce, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, partials, nitems, groups,
+                     gstep, nb, count, nmodes, norm, scale_kind, ntot_u, slots, ncells, pk, flags);
   return hipGetLastError();
 }
 
