@@ -109,11 +109,11 @@ def parse():
     ap.add_argument("--batch-requests", type=int, default=4096,
                     help="requests of the uneven-batch leg (mixed 2-D sides 32..512); 0 to skip")
     ap.add_argument("--batch-reps", type=int, default=5)
-    ap.add_argument("--serve-rates", default="500,1000,2000",
+    ap.add_argument("--serve-rates", default="250,500,1000,2000",
                     help="offered request rates (1/s) of the open-loop serving leg; empty to skip")
     ap.add_argument("--serve-seconds", type=float, default=4.0, help="arrival window per rate")
     ap.add_argument("--serve-warmup", type=float, default=1.0, help="arrivals before the window (not counted)")
-    ap.add_argument("--serve-slots", type=int, default=4)
+    ap.add_argument("--serve-slots", type=int, default=8)
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="also run a plain device copy of this size (for counter calibration)")
     return ap.parse_args()
@@ -257,21 +257,49 @@ def uneven_batch_leg(b, torch, nreq, reps):
     return out
 
 
-def serving_leg(b, torch, rate, seconds, warmup, slots):
-    """Open-loop replay of a Poisson arrival trace of mixed 2-D/3-D requests through the request
-    server (continuous batching, plan cache).  Requests arriving in the first `warmup` seconds
-    warm the plan cache and are not counted.  Latency = completion seen by the server's scheduler
-    minus submission; submissions lag the nominal arrival by `max_lateness_ms` at most."""
-    import numpy as np
-    from synth import workloads
-    trace = workloads.serving_trace(rate=rate, duration=warmup + seconds, seed=5)
-    nb = 32
+def serving_outputs(torch, trace, nb):
     offs, tot = [], 0
     for r in trace:
         offs.append(tot)
         tot += r["realizations"] * nb + r["realizations"] + (nb * nb if r["realizations"] >= 2 else 0)
-    pool = torch.empty(max(tot, 1), dtype=torch.float64, device="cuda")
-    server = b.server_create(0, slots=slots)
+    return offs, torch.empty(max(tot, 1), dtype=torch.float64, device="cuda")
+
+
+def submit_traced(b, torch, server, r, pool, o, nb, request_id):
+    R = r["realizations"]
+    pk = pool[o:o + R * nb]
+    ntot = pool[o + R * nb:o + R * nb + R].view(torch.int64)
+    cov = pool[o + R * nb + R:o + R * nb + R + nb * nb] if R >= 2 else None
+    return b.server_submit(server, r["n"], r["h"], r["xi"], b.F32, r["seed"], request_id, R, r["nbar"], nb, pk,
+                           out_ntot=ntot, out_cov=cov)
+
+
+def serving_warm(b, torch, server, trace, nb=32):
+    """Closed loop: submit every request of the trace at once and wait for all; returns
+    (seconds, requests per second).  Builds the plans and grows the slots' scratch as a
+    long-running server would have."""
+    offs, pool = serving_outputs(torch, trace, nb)
+    t0 = time.perf_counter()
+    left = {submit_traced(b, torch, server, r, pool, offs[i], nb, r["request_id"]) for i, r in enumerate(trace)}
+    while left:
+        for t, st, status, ms in b.server_drain(server):
+            left.discard(t)
+        time.sleep(0.0005)
+    dt = time.perf_counter() - t0
+    return dt, len(trace) / dt
+
+
+def serving_leg(b, torch, server, rate, seconds, warmup):
+    """Open-loop replay of a Poisson arrival trace of mixed 2-D/3-D requests through the request
+    server (continuous batching, plan cache), already warm.  Requests arriving in the first
+    `warmup` seconds are not counted.  Latency = completion seen by the server's scheduler minus
+    submission; submissions lag the nominal arrival by `max_lateness_ms` at most."""
+    import numpy as np
+    from synth import workloads
+    trace = workloads.serving_trace(rate=rate, duration=warmup + seconds, seed=5)
+    nb = 32
+    offs, pool = serving_outputs(torch, trace, nb)
+    stats0 = b.server_stats(server)
     pending = {}
     lat, real_done, failed, lateness = [], 0, 0, 0.0
     t_start = time.perf_counter()
@@ -283,12 +311,7 @@ def serving_leg(b, torch, rate, seconds, warmup, slots):
             while i < len(trace) and trace[i]["arrival"] <= now:
                 r = trace[i]
                 R = r["realizations"]
-                o = offs[i]
-                pk = pool[o:o + R * nb]
-                ntot = pool[o + R * nb:o + R * nb + R].view(torch.int64)
-                cov = pool[o + R * nb + R:o + R * nb + R + nb * nb] if R >= 2 else None
-                t = b.server_submit(server, r["n"], r["h"], r["xi"], b.F32, r["seed"], r["request_id"], R,
-                                    r["nbar"], nb, pk, out_ntot=ntot, out_cov=cov)
+                t = submit_traced(b, torch, server, r, pool, offs[i], nb, r["request_id"])
                 lateness = max(lateness, now - r["arrival"])
                 pending[t] = (r["arrival"] >= warmup, R)
                 i += 1
@@ -306,7 +329,7 @@ def serving_leg(b, torch, rate, seconds, warmup, slots):
         wall = time.perf_counter() - t_start
         stats = b.server_stats(server)
     finally:
-        b.server_destroy(server)
+        pass
     counted = [r for r in trace if r["arrival"] >= warmup]
     span = max(wall - warmup, 1e-9)
     return dict(offered_rate=rate, requests=len(counted), completed=len(lat), failed=failed,
@@ -314,8 +337,9 @@ def serving_leg(b, torch, rate, seconds, warmup, slots):
                 p50_ms=round(float(np.percentile(lat, 50)), 3) if lat else None,
                 p99_ms=round(float(np.percentile(lat, 99)), 3) if lat else None,
                 drain_s=round(wall - (warmup + seconds), 3), backlog_at_last_arrival=backlog_at_end,
-                max_lateness_ms=round(1e3 * lateness, 3), plan_cache_hits=stats["cache_hits"],
-                plan_cache_misses=stats["cache_misses"], admission_stalls=stats["admission_stalls"])
+                max_lateness_ms=round(1e3 * lateness, 3), plan_cache_hits=stats["cache_hits"] - stats0["cache_hits"],
+                plan_cache_misses=stats["cache_misses"] - stats0["cache_misses"],
+                admission_stalls=stats["admission_stalls"] - stats0["admission_stalls"])
 
 
 def main():
@@ -470,11 +494,24 @@ def main():
         print("uneven batch %s" % json.dumps(out["uneven_batch"]), file=sys.stderr, flush=True)
 
     if args.serve_rates:
-        legs = []
-        for rate in [float(x) for x in args.serve_rates.split(",")]:
-            leg = serving_leg(b, torch, rate, args.serve_seconds, args.serve_warmup, args.serve_slots)
-            legs.append(leg)
-            print("serving leg %s" % json.dumps(leg), file=sys.stderr, flush=True)
+        from synth import workloads
+        rates = [float(x) for x in args.serve_rates.split(",")]
+        server = b.server_create(0, slots=args.serve_slots)
+        try:
+            # a long-running server: every plan of the traces cached, slot scratch grown by one
+            # closed-loop pass; a second pass gives the saturation throughput
+            warm_trace = workloads.serving_trace(rate=min(max(rates), 1000.0),
+                                                 duration=args.serve_warmup + args.serve_seconds, seed=5)
+            warm_s, _ = serving_warm(b, torch, server, warm_trace)
+            sat_trace = workloads.serving_trace(rate=500.0, duration=args.serve_warmup + args.serve_seconds, seed=6)
+            sat_s, sat_rps = serving_warm(b, torch, server, sat_trace)
+            legs = []
+            for rate in rates:
+                leg = serving_leg(b, torch, server, rate, args.serve_seconds, args.serve_warmup)
+                legs.append(leg)
+                print("serving leg %s" % json.dumps(leg), file=sys.stderr, flush=True)
+        finally:
+            b.server_destroy(server)
         # sustainable: the backlog when the last request arrives stays within the slots and the
         # queue drains within 0.5 s of it
         ok = [g["offered_rate"] for g in legs
@@ -484,6 +521,11 @@ def main():
                                     "sides 16 x 7-smooth log-uniform, 1..64 realizations log-uniform, 16 two-point "
                                     "functions, nbar in {0.1,0.3,1,5}, 32 shells, FP32; seed 5",
                               window_s=args.serve_seconds, warmup_s=args.serve_warmup, slots=args.serve_slots,
+                              warm_pass=dict(requests=len(warm_trace), seconds=round(warm_s, 2)),
+                              closed_loop=dict(requests=len(sat_trace), seconds=round(sat_s, 3),
+                                               requests_per_s=round(sat_rps, 1),
+                                               realizations_per_s=round(sum(r["realizations"] for r in sat_trace)
+                                                                        / sat_s, 1)),
                               legs=legs, max_sustainable_rate_tested=max(ok) if ok else None)
 
     if not args.no_cpu_baseline:

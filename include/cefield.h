@@ -278,8 +278,8 @@ void ce_pipeline_graph_destroy(ce_graph* graph);
 typedef struct ce_server ce_server;
 typedef struct {
   int32_t slots;            /* requests in flight at once (default 4, at most 32) */
-  size_t hbm_budget_bytes;  /* bound on slot scratch + cached plans (0: 64 GiB) */
-  size_t plan_cache_bytes;  /* bound on cached plans (0: 8 GiB) */
+  size_t hbm_budget_bytes;  /* bound on slot scratch + cached plans (0: 3/4 of the free device memory) */
+  size_t plan_cache_bytes;  /* bound on cached plans (0: 32 GiB or a quarter of the budget if less) */
 } ce_server_config;
 typedef struct {
   ce_geometry geom;

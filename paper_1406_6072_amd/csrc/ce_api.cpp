@@ -135,15 +135,23 @@ LineGeom make_geom(int L, int K, int64_t A, int64_t B, int64_t nitems, int64_t i
   return g;
 }
 
-// Twiddle tables: tw[k] = exp(-2 pi i k / L), FP64 accurate, stored in the pass precision.
-struct TwKey {
-  int L, prec;
-  bool operator<(const TwKey& o) const { return std::tie(L, prec) < std::tie(o.L, o.prec); }
-};
 
 }  // namespace
 
 // ---- context -----------------------------------------------------------------
+
+// Constant tables shared by every context of the process, one set per device: twiddles,
+// per-stage twiddles and shell mode counts.  Built on first use, never freed (they are
+// small), so contexts created later (request-server slots, graphs) find them ready.
+struct SharedTables {
+  std::mutex mu;
+  std::map<std::tuple<int, int, int>, void*> tw, stw;  // (device, L, precision)
+  std::map<std::tuple<int, int, int, int>, std::pair<int64_t*, std::vector<double>>> shells;  // (device, N, d, nb)
+};
+SharedTables& shared_tables() {
+  static SharedTables* t = new SharedTables();
+  return *t;
+}
 
 struct ce_ctx {
   int device = 0;
@@ -154,12 +162,10 @@ struct ce_ctx {
   uint32_t* flags = nullptr;
   double* inv = nullptr;  // RN(1/k), k = 0..kPoissonSteps, for the Poisson recursion
   std::mutex mu;
-  std::map<TwKey, void*> tw;
-  std::map<TwKey, void*> stw;
-  std::map<std::tuple<int, int, int>, std::pair<int64_t*, std::vector<double>>> shells;
   struct Buf {
     void* p = nullptr;
     size_t n = 0;
+    hipStream_t used = nullptr;  // stream of the last call that used the buffer
   };
   Buf ws[8];
   // pinned host staging of batch tables; `staged` is recorded after the copy that reads it
@@ -226,26 +232,44 @@ struct ce_ctx {
       held -= bytes;
     }
   }
-  // scratch slot i with at least `bytes`
+  // Scratch slot i with at least `bytes`, for work on the stream of the current call
+  // (`last`).  Growth is stream-ordered (hipFreeAsync / hipMallocAsync on that stream), so
+  // it waits for nothing but this context's earlier work; if that work ran on another
+  // stream, that stream is drained first.
   ce_status scratch(int i, size_t bytes, void** out) {
     Buf& b = ws[i];
+    const hipStream_t s = last;
     if (b.n < bytes) {
       if (b.p) {
-        (void)hipDeviceSynchronize();
-        release(b.p, b.n);
+        if (b.used != s) CE_HIP(hipStreamSynchronize(b.used));
+        CE_HIP(hipFreeAsync(b.p, s));
+        held -= b.n;
         b.p = nullptr;
         b.n = 0;
       }
+      if (budget && held + bytes > budget) return CE_E_OOM;
       void* p = nullptr;
-      CE_TRY(alloc(&p, bytes));
+      const hipError_t e = hipMallocAsync(&p, bytes, s);
+      if (e != hipSuccess) return hip_status(e);
+      held += bytes;
       b.p = p;
       b.n = bytes;
     }
+    b.used = s;
     *out = b.p;
     return CE_OK;
   }
+  // table memory is the process's (shared_tables), not charged to the context budget
+  ce_status table_alloc(void** p, size_t bytes) {
+    const hipError_t e = hipMalloc(p, bytes ? bytes : 1);
+    return e == hipSuccess ? CE_OK : hip_status(e);
+  }
   ce_status twiddles(int L, int prec, const void** out) {
-    auto it = tw.find({L, prec});
+    SharedTables& st = shared_tables();
+    std::lock_guard<std::mutex> lock(st.mu);
+    auto& tw = st.tw;
+    const auto key = std::make_tuple(device, L, prec);
+    auto it = tw.find(key);
     if (it != tw.end()) {
       *out = it->second;
       return CE_OK;
@@ -259,7 +283,7 @@ struct ce_ctx {
       d[2 * k + 1] = (double)-std::sin(a);
     }
     void* p = nullptr;
-    CE_TRY(alloc(&p, elem * L));
+    CE_TRY(table_alloc(&p, elem * L));
     if (prec) {
       CE_TRY(upload(p, d.data(), elem * L));
     } else {
@@ -267,14 +291,18 @@ struct ce_ctx {
       for (size_t i = 0; i < f.size(); ++i) f[i] = (float)d[i];
       CE_TRY(upload(p, f.data(), elem * L));
     }
-    tw[{L, prec}] = p;
+    tw[key] = p;
     *out = p;
     return CE_OK;
   }
   // Per-stage twiddles of a power-of-two length with stage radices rad: for each stage
   // with span Ns > 1, Ns x (R-1) values exp(-2 pi i r k / (Ns R)), k < Ns, r = 1..R-1.
   ce_status stage_twiddles(int L, int prec, const std::vector<int>& rad, const void** out) {
-    auto it = stw.find({L, prec});
+    SharedTables& st = shared_tables();
+    std::lock_guard<std::mutex> lock(st.mu);
+    auto& stw = st.stw;
+    const auto key = std::make_tuple(device, L, prec);
+    auto it = stw.find(key);
     if (it != stw.end()) {
       *out = it->second;
       return CE_OK;
@@ -296,7 +324,7 @@ struct ce_ctx {
     const size_t n = d.size() / 2;
     const size_t elem = prec ? 16 : 8;
     void* p = nullptr;
-    CE_TRY(alloc(&p, elem * n));
+    CE_TRY(table_alloc(&p, elem * n));
     if (prec) {
       CE_TRY(upload(p, d.data(), elem * n));
     } else {
@@ -304,7 +332,7 @@ struct ce_ctx {
       for (size_t i = 0; i < f.size(); ++i) f[i] = (float)d[i];
       CE_TRY(upload(p, f.data(), elem * n));
     }
-    stw[{L, prec}] = p;
+    stw[key] = p;
     *out = p;
     return CE_OK;
   }
@@ -397,16 +425,18 @@ void shell_table_host(int N, int ndim, double h, int nb, std::vector<int64_t>& n
 
 ce_status device_shells(ce_ctx* ctx, int N, int ndim, double h, int nb, int64_t** nm_dev,
                         const std::vector<double>** km_host) {
-  auto key = std::make_tuple(N, ndim, nb);
-  auto it = ctx->shells.find(key);
-  if (it == ctx->shells.end()) {
+  SharedTables& st = shared_tables();
+  std::lock_guard<std::mutex> lock(st.mu);
+  auto key = std::make_tuple(ctx->device, N, ndim, nb);
+  auto it = st.shells.find(key);
+  if (it == st.shells.end()) {
     std::vector<int64_t> nm;
     std::vector<double> km;
     shell_table_host(N, ndim, 1.0, nb, nm, km);
     void* p = nullptr;
-    CE_TRY(ctx->alloc(&p, sizeof(int64_t) * nb));
+    CE_TRY(ctx->table_alloc(&p, sizeof(int64_t) * nb));
     CE_TRY(ctx->upload(p, nm.data(), sizeof(int64_t) * nb));
-    it = ctx->shells.emplace(key, std::make_pair(static_cast<int64_t*>(p), km)).first;
+    it = st.shells.emplace(key, std::make_pair(static_cast<int64_t*>(p), km)).first;
   }
   *nm_dev = it->second.first;
   *km_host = &it->second.second;
@@ -448,6 +478,13 @@ ce_status ce_ctx_create(int device, size_t hbm_budget_bytes, ce_ctx** out) {
   ctx->device = device;
   ctx->budget = hbm_budget_bytes;
   CE_HIP(hipStreamCreateWithFlags(&ctx->own, hipStreamNonBlocking));
+  {
+    // keep memory freed by the stream-ordered scratch growth in the device's default pool
+    hipMemPool_t pool = nullptr;
+    CE_HIP(hipDeviceGetDefaultMemPool(&pool, device));
+    uint64_t keep = UINT64_MAX;
+    CE_HIP(hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &keep));
+  }
   void* f = nullptr;
   CE_TRY(ctx->alloc(&f, 16));
   ctx->flags = static_cast<uint32_t*>(f);
@@ -471,10 +508,8 @@ void ce_ctx_destroy(ce_ctx* ctx) {
   (void)hipSetDevice(ctx->device);
   (void)hipDeviceSynchronize();
   for (auto& b : ctx->ws)
-    if (b.p) (void)hipFree(b.p);
-  for (auto& kv : ctx->tw) (void)hipFree(kv.second);
-  for (auto& kv : ctx->stw) (void)hipFree(kv.second);
-  for (auto& kv : ctx->shells) (void)hipFree(kv.second.first);
+    if (b.p) (void)hipFreeAsync(b.p, nullptr);
+  (void)hipDeviceSynchronize();
   ctx->prof_resolve();
   for (auto& ev : ctx->pool) {
     (void)hipEventDestroy(ev.first);
@@ -497,10 +532,14 @@ ce_status ce_ctx_trim(ce_ctx* ctx) {
   if (!any) return CE_OK;
   CE_HIP(hipDeviceSynchronize());
   for (auto& b : ctx->ws) {
-    ctx->release(b.p, b.n);
+    if (b.p) {
+      CE_HIP(hipFreeAsync(b.p, nullptr));
+      ctx->held -= b.n;
+    }
     b.p = nullptr;
     b.n = 0;
   }
+  CE_HIP(hipDeviceSynchronize());
   return CE_OK;
 }
 

@@ -124,9 +124,10 @@ struct ce_server {
     cache.splice(cache.begin(), cache, it->second);
     return &cache.front();
   }
-  // drop least-recently-used plans nobody runs until `need` more bytes fit
-  bool make_room(size_t need) {
-    while (held + need > cfg.hbm_budget_bytes || cache_bytes + need > cfg.plan_cache_bytes) {
+  // drop least-recently-used plans nobody runs until `need` more bytes fit the budget (and,
+  // for a plan, the plan cache)
+  bool make_room(size_t need, bool plan) {
+    while (held + need > cfg.hbm_budget_bytes || (plan && cache_bytes + need > cfg.plan_cache_bytes)) {
       auto it = cache.end();
       bool found = false;
       while (it != cache.begin()) {
@@ -184,7 +185,7 @@ struct ce_server {
     *never = false;
     const size_t extra = q->scratch > s.scratch_held ? q->scratch - s.scratch_held : 0;
     pe->users++;  // pinned while making room
-    bool room = make_room(extra);
+    bool room = make_room(extra, false);
     if (!room) {
       // give back the scratch that idle slots keep cached, then try again
       for (auto& o : slots)
@@ -192,7 +193,7 @@ struct ce_server {
           held -= o.scratch_held;
           o.scratch_held = 0;
         }
-      room = make_room(extra);
+      room = make_room(extra, false);
     }
     if (!room) {
       pe->users--;
@@ -331,7 +332,7 @@ struct ce_server {
       lock.lock();
       planning.erase(q->key);
       if (ps == CE_OK) {
-        (void)make_room(info.device_bytes);  // best effort: plans in use are never dropped
+        (void)make_room(info.device_bytes, true);  // best effort: plans in use are never dropped
         cache.push_front(PlanEntry{q->key, p, info.device_bytes, 0});
         index[q->key] = cache.begin();
         cache_bytes += info.device_bytes;
@@ -355,8 +356,13 @@ ce_status ce_server_create(int device, const ce_server_config* cfg, ce_server** 
   s->cfg = cfg ? *cfg : ce_server_config{};
   if (s->cfg.slots <= 0) s->cfg.slots = 4;
   if (s->cfg.slots > 32) return CE_E_INVALID;
-  if (s->cfg.hbm_budget_bytes == 0) s->cfg.hbm_budget_bytes = (size_t)64 << 30;
-  if (s->cfg.plan_cache_bytes == 0) s->cfg.plan_cache_bytes = (size_t)8 << 30;
+  if (s->cfg.hbm_budget_bytes == 0) {
+    // three quarters of the device memory free at creation
+    size_t free_b = 0, total_b = 0;
+    if (hipSetDevice(device) != hipSuccess || hipMemGetInfo(&free_b, &total_b) != hipSuccess) return CE_E_DEVICE;
+    s->cfg.hbm_budget_bytes = free_b / 4 * 3;
+  }
+  if (s->cfg.plan_cache_bytes == 0) s->cfg.plan_cache_bytes = std::min((size_t)32 << 30, s->cfg.hbm_budget_bytes / 4);
   ce_status st = ce_ctx_create(device, 0, &s->plan_ctx);
   if (st != CE_OK) return st;
   s->slots.resize(s->cfg.slots);
