@@ -43,6 +43,12 @@ struct Words4 {
 
 __device__ __forceinline__ Words4 philox4x32_10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
                                                 uint32_t k0, uint32_t k1) {
+  // The key is uniform over the wave.  The empty asm makes the compiler derive the ten
+  // round keys here (scalar adds) rather than keep all twenty live across the caller's
+  // loops, which overflows the scalar registers into VGPR lanes in the larger kernels.
+  k0 = __builtin_amdgcn_readfirstlane(k0);
+  k1 = __builtin_amdgcn_readfirstlane(k1);
+  __asm__ volatile("" : "+s"(k0), "+s"(k1));
 #pragma unroll
   for (int r = 0; r < 10; ++r) {
     if (r) {

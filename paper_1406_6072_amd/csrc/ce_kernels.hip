@@ -387,13 +387,16 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(sizeof
       cpx<T>* d0 = lds + (2 * rp) * g.lpitch;
       cpx<T>* d1 = d0 + g.lpitch;
       for (int i = c0; i < L; i += step) {
+        // both octant values are loaded before the generator runs (and before any LDS
+        // store, which the compiler could not move them across), so their latency is hidden
+        const uint32_t o0 = (uint32_t)mirror(i, n.M[0]);
+        const T s0 = sq0[o0], s1 = sq1[o0];
         const uint32_t p = (uint32_t)i * half_b + (b >> 1);
         const Words4 w = philox4x32_10(p, pair, rid, 0u, k0, k1);
         const cpx<T> e0 = normal_pair<T>(w.x0, w.x1);
         const cpx<T> e1 = normal_pair<T>(w.x2, w.x3);
-        const uint32_t o0 = (uint32_t)mirror(i, n.M[0]);
-        d0[pidx(i)] = c_scale(e0, sq0[o0]);
-        d1[pidx(i)] = c_scale(e1, sq1[o0]);
+        d0[pidx(i)] = c_scale(e0, s0);
+        d1[pidx(i)] = c_scale(e1, s1);
       }
     }
   }
