@@ -114,8 +114,9 @@ ce_status ce_ctx_trim(ce_ctx* ctx);
  * CE_OPT_UNPRUNED (default 0): when non-zero, ce_generate_fields computes every output of every
  * inverse pass on the full (2N)^d embedding and crops to the survey only when storing -- the
  * plain, unpruned form of the method, kept as a comparator.  Results are identical up to
- * rounding order.  Schedule options change only the launch shape, never the results.
- * Errors: CE_E_INVALID. */
+ * rounding order.  Schedule options change only the launch shape: fields, delta, counts and
+ * N_tot stay bitwise identical, P(k) may change in the last bits (the grouping of its FP64
+ * shell sums follows the lines per workgroup).  Errors: CE_E_INVALID. */
 typedef enum {
   CE_OPT_UNPRUNED = 1,
   /* Schedule: maximum lines per workgroup (a power of two <= 64; 0 = automatic, the default)
@@ -128,7 +129,10 @@ typedef enum {
   /* Schedule: tile order of the noise pass: 0 (default) = the line groups of one pair run
    * together (their strided output segments merge in L2); 1 = the workgroups of one line group
    * for consecutive pairs run together (the sqrt(lambda) lines they read stay in L2). */
-  CE_OPT_NOISE_ORDER = 6
+  CE_OPT_NOISE_ORDER = 6,
+  /* Schedule: LDS bytes a binning-pass workgroup may use (16384 .. 163840; default 81920,
+   * two workgroups per CU).  More LDS allows more lines per workgroup. */
+  CE_OPT_BIN_LDS = 7
 } ce_option;
 ce_status ce_ctx_set_option(ce_ctx* ctx, int32_t option, int64_t value);
 

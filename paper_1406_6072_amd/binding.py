@@ -233,7 +233,7 @@ def ctx_trim(ctx):
 
 
 OPT_UNPRUNED = 1
-OPT_LINES_NOISE, OPT_LINES_INNER, OPT_LINES_LAST, OPT_LINES_BINS, OPT_NOISE_ORDER = 2, 3, 4, 5, 6
+OPT_LINES_NOISE, OPT_LINES_INNER, OPT_LINES_LAST, OPT_LINES_BINS, OPT_NOISE_ORDER, OPT_BIN_LDS = 2, 3, 4, 5, 6, 7
 
 
 def ctx_set_option(ctx, option, value):

@@ -113,7 +113,8 @@ bool mixed_radix(const FftDesc& f) {
 }
 
 LineGeom make_geom(int L, int K, int64_t A, int64_t B, int64_t nitems, int64_t in_item, int64_t out_item,
-                   size_t elem, bool mix, int rmin, int rmax, size_t extra_per_line = 0) {
+                   size_t elem, bool mix, int rmin, int rmax, size_t extra_per_line = 0,
+                   size_t lds_budget = kLdsBudget) {
   LineGeom g;
   g.nbuf = mix ? 2 : 1;
   g.L = L;
@@ -127,7 +128,7 @@ LineGeom make_geom(int L, int K, int64_t A, int64_t B, int64_t nitems, int64_t i
   g.lpitch = line_pitch_host(L);
   const size_t per_line = (size_t)g.lpitch * elem * g.nbuf + extra_per_line;
   int R = 1;
-  while (R * 2 <= rmax && (size_t)(R * 2) * per_line <= kLdsBudget && R * 2 * g.nlanes <= kMaxWG) R *= 2;
+  while (R * 2 <= rmax && (size_t)(R * 2) * per_line <= lds_budget && R * 2 * g.nlanes <= kMaxWG) R *= 2;
   if (R < rmin) R = rmin;
   g.R = R;
   const int64_t nlines = A * B;
@@ -182,6 +183,7 @@ struct ce_ctx {
   bool unpruned = false;  // inverse passes keep every embedding output (comparator form)
   int lines_cap[4] = {0, 0, 0, 0};  // max lines per workgroup per pass kind (0 = automatic)
   int noise_item_minor = 0;         // noise pass tile order (0: line groups of one pair adjacent; measured faster)
+  size_t bin_lds = kLdsBudget;      // LDS budget of a binning-pass workgroup
   std::vector<ProfRec> pending;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> pool;
   std::map<std::string, std::pair<double, int64_t>> agg;
@@ -586,6 +588,10 @@ ce_status ce_ctx_set_option(ce_ctx* ctx, int32_t option, int64_t value) {
       if (value != 0 && value != 1) return CE_E_INVALID;
       ctx->noise_item_minor = (int)value;
       return CE_OK;
+    case CE_OPT_BIN_LDS:
+      if (value < 16384 || value > 163840) return CE_E_INVALID;
+      ctx->bin_lds = (size_t)value;
+      return CE_OK;
     default: return CE_E_INVALID;
   }
 }
@@ -870,7 +876,7 @@ ce_status run_forward_bins(ce_ctx* ctx, int ndim, const int* n, int prec, int64_
   const int64_t Bb = ndim == 3 ? (int64_t)n[1] * W : W;
   // per line: nb FP64 shell sums and one run record (24 B) per lane
   LineGeom gb = make_geom(n[0], n[0], 1, Bb, nitems, H_item, 0, elem, mixed_radix(f0), 1, cap_lines(ctx, 3, 32),
-                          (size_t)nb * 8 + (size_t)((n[0] + kEPT - 1) / kEPT) * 32);
+                          (size_t)nb * 8 + (size_t)((n[0] + kEPT - 1) / kEPT) * 32, ctx->bin_lds);
   void* part = nullptr;
   CE_TRY(ctx->scratch(3, sizeof(double) * (size_t)(nitems * gb.groups_per_item * 2 * nb), &part));
   BinArgs ba;

@@ -49,30 +49,97 @@ __device__ __forceinline__ cpx<T>* lds_lines() {
   return reinterpret_cast<cpx<T>*>(ce_smem);
 }
 
-// Load nl lines of length L (complex) into LDS.
+// Part of the lines of one group held in registers: elements k0 .. k0 + kPre - 1 of the
+// thread (row lines: element lane + k nlanes; strided lines: c0 + k (blockDim / R)); at
+// most kEPT per thread in all.  kPre keeps the array at 32 registers, which the compiler
+// keeps in VGPRs (a larger private array would go to scratch memory).
 template <typename T>
-__device__ __forceinline__ void load_lines(cpx<T>* lds, const cpx<T>* __restrict__ in, const LineGeom& g,
-                                           const PassPos& pp) {
-  const cpx<T>* base = in + pp.item * g.in_item;
+struct LinePrefetch {
+  static constexpr int kPre = sizeof(T) == 4 ? kEPT : kEPT / 2;
+  T x[kPre], y[kPre];  // separate scalar arrays: a struct array of doubles stays in scratch
+};
+
+template <typename T>
+__device__ __forceinline__ void fetch_lines(LinePrefetch<T>& pf, const cpx<T>* __restrict__ in, const LineGeom& g,
+                                            int64_t item, int64_t line0, int nl, int k0) {
+  constexpr int P = LinePrefetch<T>::kPre;
+  const cpx<T>* base = in + item * g.in_item;
   const int L = g.L;
-  const int tid = threadIdx.x, nthr = blockDim.x;
+  const int tid = threadIdx.x;
   if (g.B == 1) {
     const int r = tid / g.nlanes, lane = tid - r * g.nlanes;
-    if (r < pp.nl) {
-      const cpx<T>* src = base + (pp.line0 + r) * (int64_t)L;
-      cpx<T>* dst = lds + r * g.lpitch;
-      for (int i = lane; i < L; i += g.nlanes) dst[pidx(i)] = src[i];
+    if (r < nl) {
+      const cpx<T>* src = base + (line0 + r) * (int64_t)L;
+#pragma unroll
+      for (int k = 0; k < P; ++k) {
+        const int i = lane + (k0 + k) * g.nlanes;
+        if (i < L) {
+          const cpx<T> v = src[i];
+          pf.x[k] = v.x;
+          pf.y[k] = v.y;
+        }
+      }
     }
   } else {
     const int R = g.R;
-    const int r = tid % R, c0 = tid / R, step = nthr / R;
-    if (r < pp.nl) {
-      const int64_t ln = pp.line0 + r;
+    const int r = tid % R, c0 = tid / R, step = (int)blockDim.x / R;
+    if (r < nl) {
+      const int64_t ln = line0 + r;
       const int64_t a = ln / g.B, b = ln - a * g.B;
       const cpx<T>* src = base + a * (int64_t)L * g.B + b;
-      cpx<T>* dst = lds + r * g.lpitch;
-      for (int i = c0; i < L; i += step) dst[pidx(i)] = src[(int64_t)i * g.B];
+#pragma unroll
+      for (int k = 0; k < P; ++k) {
+        const int i = c0 + (k0 + k) * step;
+        if (i < L) {
+          const cpx<T> v = src[(int64_t)i * g.B];
+          pf.x[k] = v.x;
+          pf.y[k] = v.y;
+        }
+      }
     }
+  }
+}
+
+template <typename T>
+__device__ __forceinline__ void put_lines(cpx<T>* lds, const LinePrefetch<T>& pf, const LineGeom& g, int nl,
+                                          int k0) {
+  constexpr int P = LinePrefetch<T>::kPre;
+  const int L = g.L;
+  const int tid = threadIdx.x;
+  if (g.B == 1) {
+    const int r = tid / g.nlanes, lane = tid - r * g.nlanes;
+    if (r < nl) {
+      cpx<T>* dst = lds + r * g.lpitch;
+#pragma unroll
+      for (int k = 0; k < P; ++k) {
+        const int i = lane + (k0 + k) * g.nlanes;
+        if (i < L) dst[pidx(i)] = {pf.x[k], pf.y[k]};
+      }
+    }
+  } else {
+    const int R = g.R;
+    const int r = tid % R, c0 = tid / R, step = (int)blockDim.x / R;
+    if (r < nl) {
+      cpx<T>* dst = lds + r * g.lpitch;
+#pragma unroll
+      for (int k = 0; k < P; ++k) {
+        const int i = c0 + (k0 + k) * step;
+        if (i < L) dst[pidx(i)] = {pf.x[k], pf.y[k]};
+      }
+    }
+  }
+}
+
+// Load nl lines of length L (complex) into LDS: every element of the thread is requested
+// before the first one is stored, so up to kEPT loads per thread are in flight.
+template <typename T>
+__device__ __forceinline__ void load_lines(cpx<T>* lds, const cpx<T>* __restrict__ in, const LineGeom& g,
+                                           const PassPos& pp) {
+  LinePrefetch<T> pf;
+#pragma unroll
+  for (int k0 = 0; k0 < kEPT; k0 += LinePrefetch<T>::kPre) {
+    fetch_lines(pf, in, g, pp.item, pp.line0, pp.nl, k0);
+    put_lines(lds, pf, g, pp.nl, k0);
   }
 }
 
@@ -593,26 +660,20 @@ struct RunEnds {
   int single, nonempty;
 };
 
-template <typename T, int MIX>
-__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 4 : 2))) k_bin_pass(LineGeom g, FftDesc f, BinArgs bn, const cpx<T>* in) {
-  cpx<T>* lds = lds_lines<T>();
-  const PassPos pp = pass_pos(g);
-  double* acc = reinterpret_cast<double*>(lds + g.nbuf * g.R * g.lpitch);  // [R][nb]
-  RunEnds* ends = reinterpret_cast<RunEnds*>(acc + g.R * bn.nb);             // [R][nlanes]
-  load_lines(lds, in, g, pp);
-  for (int t = threadIdx.x; t < g.R * bn.nb; t += blockDim.x) acc[t] = 0.0;
-  __syncthreads();
+// Binning of one line group already transformed in LDS (lines r < nl of the group that
+// starts at line0); adds the group's per-shell sums, lines in order, to tot[2][nb]
+// (entry t is read and written by thread t only).
+template <typename T>
+__device__ __forceinline__ void bin_group(const cpx<T>* res, const LineGeom& g, const BinArgs& bn, int64_t line0,
+                                          int nl, double* acc, RunEnds* ends, double* tot) {
   const int r = threadIdx.x / g.nlanes, lane = threadIdx.x - r * g.nlanes;
-  const bool active = r < pp.nl;
-  line_fft<T, -1, MIX>(buf_a(lds, g, r), buf_b(lds, g, r), f, lane, g.nlanes, active, f.L);
-  const cpx<T>* res = result_base<T, MIX>(lds, g, f);
-
+  const bool active = r < nl;
   const int N = bn.N, Nh = N / 2, nb = bn.nb, W = bn.W, Kh = Nh + 1;
   const int64_t Tq = 4ll * nb * nb, NN = (int64_t)N * N;
   if (r < g.R) {
     RunEnds e{-1, -1, 0.0, 0.0, 1, 0};
     if (active) {
-      const int64_t ln = pp.line0 + r;
+      const int64_t ln = line0 + r;
       const int kl = (int)(ln % W);
       const int s = kl >= Kh;
       const int kz = kl - s * Kh;
@@ -680,7 +741,7 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(sizeof
   }
   __syncthreads();
   // merge runs that cross chunk boundaries: each run is owned by the chunk it starts in
-  if (r < pp.nl) {
+  if (active) {
     const RunEnds* le = ends + r * g.nlanes;
     const RunEnds e = le[lane];
     if (e.nonempty) {
@@ -706,13 +767,31 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(sizeof
   __syncthreads();
   for (int t = threadIdx.x; t < 2 * nb; t += blockDim.x) {
     const int s = t / nb, b = t - s * nb;
-    double sum = 0.0;
-    for (int lr = 0; lr < pp.nl; ++lr) {
-      const int kl = (int)((pp.line0 + lr) % W);
+    double sum = tot[t];
+    for (int lr = 0; lr < nl; ++lr) {
+      const int kl = (int)((line0 + lr) % W);
       if ((kl >= Kh) == s) sum += acc[lr * nb + b];
     }
-    bn.partials[((pp.item * g.groups_per_item + pp.grp) * 2 + s) * nb + b] = sum;
+    tot[t] = sum;
   }
+}
+
+template <typename T, int MIX>
+__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 4 : 2))) k_bin_pass(LineGeom g, FftDesc f, BinArgs bn, const cpx<T>* in) {
+  cpx<T>* lds = lds_lines<T>();
+  const PassPos pp = pass_pos(g);
+  double* acc = reinterpret_cast<double*>(lds + g.nbuf * g.R * g.lpitch);  // [R][nb]
+  RunEnds* ends = reinterpret_cast<RunEnds*>(acc + g.R * bn.nb);             // [R][nlanes]
+  double* tot = reinterpret_cast<double*>(ends + g.R * g.nlanes);            // [2][nb]
+  load_lines(lds, in, g, pp);
+  for (int t = threadIdx.x; t < g.R * bn.nb; t += blockDim.x) acc[t] = 0.0;
+  for (int t = threadIdx.x; t < 2 * bn.nb; t += blockDim.x) tot[t] = 0.0;
+  __syncthreads();
+  const int r = threadIdx.x / g.nlanes, lane = threadIdx.x - r * g.nlanes;
+  line_fft<T, -1, MIX>(buf_a(lds, g, r), buf_b(lds, g, r), f, lane, g.nlanes, r < pp.nl, f.L);
+  bin_group<T>(result_base<T, MIX>(lds, g, f), g, bn, pp.line0, pp.nl, acc, ends, tot);
+  for (int t = threadIdx.x; t < 2 * bn.nb; t += blockDim.x)
+    bn.partials[(pp.item * g.groups_per_item + pp.grp) * 2 * bn.nb + t] = tot[t];
 }
 
 // Many line groups per item: the partials of each run of kGroupChunk groups are summed in
@@ -1062,7 +1141,7 @@ template <typename T>
 static void bin_pass_t(int mix, const LineGeom& g, const FftDesc& f, const BinArgs& b, const void* in,
                        hipStream_t s) {
   const size_t lds = lines_lds_bytes(g, sizeof(cpx<T>)) + (size_t)g.R * b.nb * sizeof(double) +
-                     (size_t)g.R * g.nlanes * sizeof(RunEnds);
+                     (size_t)g.R * g.nlanes * sizeof(RunEnds) + 2 * (size_t)b.nb * sizeof(double);
   const cpx<T>* i = static_cast<const cpx<T>*>(in);
   with_variant(mix, [&](auto v) {
     CE_LAUNCH((k_bin_pass<T, decltype(v)::value>), pass_grid(g), pass_block(g), lds, s, g, f, b, i);
