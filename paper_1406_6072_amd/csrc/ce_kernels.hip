@@ -195,11 +195,17 @@ constexpr int kMaxPoissonSteps = 4096;
 constexpr double kChunkMean = 64.0;
 constexpr double kMaxMu = 6.7108864e7;  // 2^20 chunks
 
-// inv[k] = RN(1/k), k = 0..kMaxPoissonSteps (inv[0] unused); the first kInvLds entries are
-// also read from an LDS copy (inv_lds, nullable) to keep the recursion off global-memory latency.
+// RN(1/k): entries k <= kInvLds come from a copy of the host table RN(1/k) that the kernel
+// keeps in LDS (inv_lds); beyond it (never reached with chunk means of 64) the correctly
+// rounded quotient, which equals the table entry.
 constexpr int kInvLds = 256;
-__device__ __forceinline__ int poisson_chunk(double u, double m, const double* __restrict__ inv,
-                                             const double* inv_lds, uint32_t* flags) {
+__device__ __forceinline__ double inv_k(const double* inv_lds, int k) {
+  return k <= kInvLds ? inv_lds[k] : 1.0 / (double)k;
+}
+
+__device__ __forceinline__ int poisson_chunk(double u, double m, const double* inv_lds, uint32_t* flags) {
+  // every step separately rounded: no contraction of the products into the sums
+#pragma clang fp contract(off)
   double p = exp(-m);
   double F = p;
   int k = 0;
@@ -209,9 +215,8 @@ __device__ __forceinline__ int poisson_chunk(double u, double m, const double* _
       atomicOr(flags, 1u);
       break;
     }
-    const double ik = (inv_lds && k <= kInvLds) ? inv_lds[k] : inv[k];
-    p = __dmul_rn(__dmul_rn(p, m), ik);
-    F = __dadd_rn(F, p);
+    p = (p * m) * inv_k(inv_lds, k);
+    F = F + p;
   }
   return k;
 }
@@ -221,13 +226,16 @@ __device__ __forceinline__ int chunk_count(double mu) {
 }
 
 __device__ __forceinline__ double chunk_mean(double mu, int c, int K) {
-  return c == K - 1 ? __dsub_rn(mu, kChunkMean * (double)(K - 1)) : kChunkMean;
+#pragma clang fp contract(off)
+  return c == K - 1 ? mu - kChunkMean * (double)(K - 1) : kChunkMean;
 }
 
 // Counts of the two realizations of a pair at one cell; counter (cell, pair, rid, 1 + chunk).
+constexpr int kStraight = 3;  // steps of the inversion taken without branches (1/j folds to RN(1/j))
 __device__ __forceinline__ void poisson_pair(double mua, double mub, bool has_b, uint32_t cell, uint32_t pair,
-                                             uint32_t rid, uint32_t k0, uint32_t k1, const double* __restrict__ inv,
-                                             const double* inv_lds, uint32_t* flags, int& na, int& nb) {
+                                             uint32_t rid, uint32_t k0, uint32_t k1, const double* inv_lds,
+                                             uint32_t* flags, int& na, int& nb) {
+#pragma clang fp contract(off)
   na = 0;
   nb = 0;
   if (!(mua <= kMaxMu) || (has_b && !(mub <= kMaxMu))) {
@@ -253,6 +261,27 @@ __device__ __forceinline__ void poisson_pair(double mua, double mub, bool has_b,
     int ka = 0, kb = 0;
     bool ra = da && ua > Fa && pa > 0.0;
     bool rb = db && ub > Fb && pb > 0.0;
+    // the first kStraight steps run for every lane without branches (a lane that has
+    // stopped keeps its values), which is where nearly all draws at small means end;
+    // only lanes still going enter the loop.  The values each lane keeps are those of
+    // the step-by-step recursion.
+#pragma unroll
+    for (int j = 1; j <= kStraight; ++j) {
+      const double qa = (pa * ma) * (1.0 / (double)j), qb = (pb * mb) * (1.0 / (double)j);
+      const double Ga = Fa + qa, Gb = Fb + qb;
+      if (ra) {
+        ka = j;
+        pa = qa;
+        Fa = Ga;
+        ra = ua > Ga && qa > 0.0;
+      }
+      if (rb) {
+        kb = j;
+        pb = qb;
+        Fb = Gb;
+        rb = ub > Gb && qb > 0.0;
+      }
+    }
     while (ra || rb) {
       if (ra) {
         ++ka;
@@ -260,9 +289,8 @@ __device__ __forceinline__ void poisson_pair(double mua, double mub, bool has_b,
           atomicOr(flags, 1u);
           ra = false;
         } else {
-          const double ik = (inv_lds && ka <= kInvLds) ? inv_lds[ka] : inv[ka];
-          pa = __dmul_rn(__dmul_rn(pa, ma), ik);
-          Fa = __dadd_rn(Fa, pa);
+          pa = (pa * ma) * inv_k(inv_lds, ka);
+          Fa = Fa + pa;
           ra = ua > Fa && pa > 0.0;
         }
       }
@@ -272,9 +300,8 @@ __device__ __forceinline__ void poisson_pair(double mua, double mub, bool has_b,
           atomicOr(flags, 1u);
           rb = false;
         } else {
-          const double ik = (inv_lds && kb <= kInvLds) ? inv_lds[kb] : inv[kb];
-          pb = __dmul_rn(__dmul_rn(pb, mb), ik);
-          Fb = __dadd_rn(Fb, pb);
+          pb = (pb * mb) * inv_k(inv_lds, kb);
+          Fb = Fb + pb;
           rb = ub > Fb && pb > 0.0;
         }
       }
@@ -297,7 +324,8 @@ __device__ __forceinline__ double lognormal_delta<double>(double g, double s2hal
 
 // mu = (nbar f) (1 + delta) from delta as stored
 __device__ __forceinline__ double intensity(double nbar, double f, double delta) {
-  return __dmul_rn(__dmul_rn(nbar, f), __dadd_rn(1.0, delta));
+#pragma clang fp contract(off)
+  return (nbar * f) * (1.0 + delta);
 }
 
 // ---------------------------------------------------------------------------
@@ -570,7 +598,7 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(sizeof
       const double mua = intensity(nbar, 1.0, (double)dla);
       const double mub = intensity(nbar, 1.0, (double)dlb);
       int na, nb;
-      poisson_pair(mua, mub, has_b, (uint32_t)(row * K + i), pair, rid, k0, k1, e.inv, inv_s, e.flags, na, nb);
+      poisson_pair(mua, mub, has_b, (uint32_t)(row * K + i), pair, rid, k0, k1, inv_s, e.flags, na, nb);
       if (fa) {
         fa[i] = z.x;
         if (has_b) fa[i + e.ncells] = z.y;
@@ -890,10 +918,12 @@ __global__ void k_lognormal_poisson(const T* __restrict__ fields, int64_t count,
                                     int32_t* __restrict__ counts, unsigned long long* __restrict__ ntot,
                                     const double* __restrict__ inv, uint32_t* flags) {
   __shared__ unsigned long long acc;
+  __shared__ double inv_s[kInvLds + 1];
   const int64_t blocks_per_map = (ncells + blockDim.x - 1) / blockDim.x;
   const int64_t k = blockIdx.x / blocks_per_map;
   const int64_t cell = (blockIdx.x - k * blocks_per_map) * blockDim.x + threadIdx.x;
   if (threadIdx.x == 0) acc = 0;
+  for (int i = threadIdx.x; i <= kInvLds; i += blockDim.x) inv_s[i] = inv[i];
   __syncthreads();
   if (k < count && cell < ncells) {
     const uint64_t rr = first_real + (uint64_t)k;
@@ -910,7 +940,7 @@ __global__ void k_lognormal_poisson(const T* __restrict__ fields, int64_t count,
       for (int c = 0; c < K; ++c) {
         const Words4 w = philox4x32_10((uint32_t)cell, (uint32_t)(rr >> 1), rid, 1u + (uint32_t)c, k0, k1);
         const double u = (rr & 1) ? unit52(w.x2, w.x3) : unit52(w.x0, w.x1);
-        n += poisson_chunk(u, chunk_mean(mu, c, K), inv, nullptr, flags);
+        n += poisson_chunk(u, chunk_mean(mu, c, K), inv_s, flags);
       }
     }
     if (delta) delta[k * ncells + cell] = d;
