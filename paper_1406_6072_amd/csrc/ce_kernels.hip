@@ -231,7 +231,7 @@ __device__ __forceinline__ double chunk_mean(double mu, int c, int K) {
 }
 
 // Counts of the two realizations of a pair at one cell; counter (cell, pair, rid, 1 + chunk).
-constexpr int kStraight = 3;  // steps of the inversion taken without branches (1/j folds to RN(1/j))
+constexpr int kStraight = 4;  // steps of the inversion taken without branches (1/j folds to RN(1/j))
 __device__ __forceinline__ void poisson_pair(double mua, double mub, bool has_b, uint32_t cell, uint32_t pair,
                                              uint32_t rid, uint32_t k0, uint32_t k1, const double* inv_lds,
                                              uint32_t* flags, int& na, int& nb) {
