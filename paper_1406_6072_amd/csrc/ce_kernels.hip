@@ -793,12 +793,14 @@ __device__ __forceinline__ void bin_group(const cpx<T>* res, const LineGeom& g, 
     }
   }
   __syncthreads();
+  const int kl0 = (int)(line0 % W);
   for (int t = threadIdx.x; t < 2 * nb; t += blockDim.x) {
     const int s = t / nb, b = t - s * nb;
     double sum = tot[t];
+    int kl = kl0;
     for (int lr = 0; lr < nl; ++lr) {
-      const int kl = (int)((line0 + lr) % W);
       if ((kl >= Kh) == s) sum += acc[lr * nb + b];
+      if (++kl == W) kl = 0;
     }
     tot[t] = sum;
   }
