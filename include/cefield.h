@@ -228,6 +228,19 @@ ce_status ce_pipeline_run(ce_ctx* ctx, const ce_plan* plan, uint64_t seed, uint3
                           int64_t* out_ntot, double* out_pk, double* out_cov, double* out_cnorm,
                           void* stream);
 
+/* ce_pipeline_run on a masked survey (Sec. 3.1, eq. sampling; Sec. 3.2, eq. Estim): mask_f
+ * (device, N^d floats in [0, 1], row-major, caller-owned) is the surface fraction f of each
+ * survey cell.  Counts are drawn with rate nbar f rho; the spectra are those of
+ * delta_g = (N/f - N^)/N^ on cells with f != 0 (0 elsewhere), N^ = N_tot / sum f, the contrast
+ * ce_estimate_pk forms for counts with a mask.  Counts are always produced (into out_counts
+ * when given, else into context scratch) and transformed in a second pass, so a masked run
+ * moves 8 N^d more bytes per realization than the unmasked fused path.  mask_f = NULL is
+ * ce_pipeline_run.  Errors: as ce_pipeline_run. */
+ce_status ce_pipeline_run_masked(ce_ctx* ctx, const ce_plan* plan, const float* mask_f, uint64_t seed,
+                                 uint32_t request_id, uint64_t first_realization, int64_t count, double nbar,
+                                 int32_t nbins, void* out_fields, void* out_delta, int32_t* out_counts,
+                                 int64_t* out_ntot, double* out_pk, double* out_cov, double* out_cnorm, void* stream);
+
 /* Batched form of ce_pipeline_run: many requests, each with its own plan (geometry, xi,
  * precision), seed, request id, realizations, nbar and outputs.  Requests that share
  * (ndim, N, h, precision, nbins) form a group that runs each pass of the pipeline as one launch

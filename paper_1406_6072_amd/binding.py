@@ -101,6 +101,8 @@ _graph_create = _sig("ce_pipeline_graph_create", c_i32, c_void_p, c_void_p, c_u6
                      c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, ctypes.POINTER(c_void_p))
 _graph_launch = _sig("ce_pipeline_graph_launch", c_i32, c_void_p, c_void_p)
 _graph_destroy = _sig("ce_pipeline_graph_destroy", None, c_void_p)
+_pipeline_masked = _sig("ce_pipeline_run_masked", c_i32, c_void_p, c_void_p, c_void_p, c_u64, c_u32, c_u64, c_i64,
+                        c_f64, c_i32, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p)
 _pipeline_batch = _sig("ce_pipeline_run_batch", c_i32, c_void_p, ctypes.POINTER(BatchItem), c_i64, c_void_p)
 _server_create = _sig("ce_server_create", c_i32, c_i32, ctypes.POINTER(ServerConfig), ctypes.POINTER(c_void_p))
 _server_submit = _sig("ce_server_submit", c_i32, c_void_p, ctypes.POINTER(Request), ctypes.POINTER(c_u64))
@@ -120,7 +122,7 @@ EXPORTED = ["ce_status_string", "ce_version", "ce_ctx_create", "ce_ctx_destroy",
             "ce_ctx_set_option", "ce_ctx_set_profiling", "ce_ctx_profile_read",
             "ce_plan_embedding", "ce_plan_release", "ce_plan_get_info", "ce_plan_eigenvalues",
             "ce_generate_fields", "ce_lognormal_poisson", "ce_estimate_pk", "ce_pk_covariance",
-            "ce_pipeline_run", "ce_pipeline_run_batch", "ce_pipeline_graph_create", "ce_pipeline_graph_launch",
+            "ce_pipeline_run", "ce_pipeline_run_masked", "ce_pipeline_run_batch", "ce_pipeline_graph_create", "ce_pipeline_graph_launch",
             "ce_pipeline_graph_destroy",
             "ce_server_create", "ce_server_submit", "ce_server_poll", "ce_server_drain", "ce_server_cancel",
             "ce_server_stats_read", "ce_server_destroy", "ce_shell_table", "ce_fft_factors", "ce_debug_philox", "ce_debug_noise"]
@@ -368,6 +370,23 @@ def pipeline_run(ctx, plan, seed, request_id, first_realization, count, nbar, nb
                          _ptr(out_cov, torch.float64, nbins * nbins, "out_cov"),
                          _ptr(out_cnorm, torch.float64, nbins * nbins, "out_cnorm"), _stream(stream)),
            "ce_pipeline_run")
+
+
+def pipeline_run_masked(ctx, plan, mask, seed, request_id, first_realization, count, nbar, nbins, out_pk,
+                        out_fields=None, out_delta=None, out_counts=None, out_ntot=None, out_cov=None, out_cnorm=None,
+                        stream=None):
+    """The fused path on a masked survey; mask: float32 CUDA tensor of N^d surface fractions."""
+    cells = plan.cells
+    _check(_pipeline_masked(ctx, plan.handle, _ptr(mask, torch.float32, cells, "mask"), int(seed), int(request_id),
+                            int(first_realization), int(count), float(nbar), int(nbins),
+                            _ptr(out_fields, plan.dtype, count * cells, "out_fields"),
+                            _ptr(out_delta, plan.dtype, count * cells, "out_delta"),
+                            _ptr(out_counts, torch.int32, count * cells, "out_counts"),
+                            _ptr(out_ntot, torch.int64, count, "out_ntot"),
+                            _ptr(out_pk, torch.float64, count * nbins, "out_pk"),
+                            _ptr(out_cov, torch.float64, nbins * nbins, "out_cov"),
+                            _ptr(out_cnorm, torch.float64, nbins * nbins, "out_cnorm"), _stream(stream)),
+           "ce_pipeline_run_masked")
 
 
 def pipeline_run_batch(ctx, items, stream=None):

@@ -973,6 +973,119 @@ ce_status pipeline_impl(ce_ctx* ctx, const ce_plan* plan, uint64_t seed, uint32_
   return CE_OK;
 }
 
+// Spectra of a stack of maps described by pl (first forward pass with the contrast or field
+// load, remaining forward passes, shell sums, reduction): the standalone estimator and the
+// spectrum stage of the masked pipeline.
+ce_status spectrum_impl(ce_ctx* ctx, int ndim, const int* n, double h, int prec, PairLoad pl, int64_t count,
+                        int32_t nbins, double* out_pk, int64_t* out_nmodes, double* out_kmean, hipStream_t s) {
+  int64_t ncells = 1;
+  for (int d = 0; d < ndim; ++d) ncells *= n[d];
+  const int64_t nitems = (count + 1) / 2;
+  const int Nl = n[ndim - 1];
+  const int W = 2 * (Nl / 2 + 1);
+  const int64_t rows = ncells / Nl;
+  const size_t elem = prec ? 16 : 8;
+  void* H = nullptr;
+  CE_TRY(ctx->scratch(2, elem * (size_t)(nitems * rows * W), &H));
+  pl.H = H;
+  pl.H_item = rows * W;
+  FftDesc fl;
+  CE_TRY(build_fft(ctx, Nl, prec, fl));
+  LineGeom g1 = make_geom(Nl, Nl, rows, 1, nitems, 0, 0, elem, mixed_radix(fl), 1, 1024);
+  CE_PROF(ctx, "forward_rows_pair", s, launch_pair_forward(prec, g1, fl, pl, s));
+  double* partials = nullptr;
+  int64_t groups = 0;
+  CE_TRY(run_forward_bins(ctx, ndim, n, prec, nitems, H, nbins, &partials, &groups, s));
+  int64_t* nm = nullptr;
+  const std::vector<double>* km = nullptr;
+  CE_TRY(device_shells(ctx, n[0], ndim, h, nbins, &nm, &km));
+  const double norm = std::pow(h, ndim) / (double)ncells;
+  CE_PROF(ctx, "bin_reduce", s, launch_bin_reduce(partials, nitems, groups, nbins, count, nm, norm, 0, nullptr, nullptr, (double)ncells,
+                           out_pk, ctx->flags, s));
+  if (out_nmodes) CE_HIP(hipMemcpyAsync(out_nmodes, nm, sizeof(int64_t) * nbins, hipMemcpyDeviceToDevice, s));
+  if (out_kmean) {
+    std::vector<double> k(*km);
+    for (double& v : k) v /= h;
+    CE_HIP(hipMemcpyAsync(out_kmean, k.data(), sizeof(double) * nbins, hipMemcpyHostToDevice, s));
+    CE_HIP(hipStreamSynchronize(s));
+  }
+  return CE_OK;
+}
+
+// The pipeline on a masked survey: the fused pass samples counts with rate nbar f rho and
+// stores them (no forward transform); the spectrum stage then forms delta_g = (N/f - N^)/N^ on
+// f != 0 with N^ = N_tot / sum f (eq. Estim) as the standalone estimator does.
+ce_status pipeline_masked_impl(ce_ctx* ctx, const ce_plan* plan, const float* mask, uint64_t seed,
+                               uint32_t request_id, uint64_t first_realization, int64_t count, double nbar,
+                               int32_t nbins, void* out_fields, void* out_delta, int32_t* out_counts,
+                               int64_t* out_ntot, double* out_pk, double* out_cov, double* out_cnorm, hipStream_t s) {
+  InverseSetup fs;
+  CE_TRY(setup_ffts(ctx, plan, fs));
+  const int ndim = plan->ndim;
+  const int64_t ncells = survey_cells(plan);
+  const size_t relem = plan->prec ? 8 : 4;
+  const int64_t npairs = (count + 1) / 2;
+  const int64_t cp = chunk_pairs(plan, npairs, kScratchCap);
+  int32_t* counts = out_counts;
+  if (!counts) {
+    void* c = nullptr;
+    CE_TRY(ctx->scratch(7, sizeof(int32_t) * (size_t)(count * ncells), &c));
+    counts = static_cast<int32_t*>(c);
+  }
+  void* acc = nullptr;
+  CE_TRY(ctx->scratch(4, sizeof(unsigned long long) * (size_t)(2 * npairs), &acc));
+  auto* ntot = static_cast<unsigned long long*>(acc);
+  CE_HIP(launch_zero_u64(ntot, 2 * npairs, s));
+  for (int64_t j = 0; j < npairs; j += cp) {
+    const int64_t np = std::min(cp, npairs - j);
+    RowEpi e;
+    e.mode = 2;
+    e.ncells = ncells;
+    e.count = std::min<int64_t>(count - 2 * j, 2 * np);
+    e.real_off = 0;
+    e.fields = out_fields ? static_cast<char*>(out_fields) + relem * (size_t)(2 * j * ncells) : nullptr;
+    e.delta = out_delta ? static_cast<char*>(out_delta) + relem * (size_t)(2 * j * ncells) : nullptr;
+    e.counts = counts + 2 * j * ncells;
+    e.mask = mask;
+    e.ntot = ntot + 2 * j;
+    e.flags = ctx->flags;
+    e.inv = ctx->inv;
+    e.s2half = 0.5 * plan->info.sigma2;
+    e.nbar = nbar;
+    e.k0 = (uint32_t)(seed & 0xFFFFFFFFu);
+    e.k1 = (uint32_t)(seed >> 32);
+    e.rid = request_id;
+    e.first_pair = first_realization / 2 + j;
+    e.fwd = fs.fN[ndim - 1];
+    e.H = nullptr;
+    CE_TRY(run_inverse(ctx, plan, fs, seed, request_id, first_realization / 2 + j, np, e, s));
+  }
+  int64_t* sn = out_ntot;
+  if (!sn) {
+    void* t = nullptr;
+    CE_TRY(ctx->scratch(6, sizeof(int64_t) * (size_t)count, &t));
+    sn = static_cast<int64_t*>(t);
+  }
+  CE_HIP(launch_copy_ntot(ntot, sn, count, s));
+  std::vector<float> hm(ncells);
+  CE_HIP(hipMemcpyAsync(hm.data(), mask, sizeof(float) * ncells, hipMemcpyDeviceToHost, s));
+  CE_HIP(hipStreamSynchronize(s));
+  double fsum = 0;
+  for (float v : hm) fsum += (double)v;
+  PairLoad pl;
+  pl.kind = 1;
+  pl.maps = counts;
+  pl.count = count;
+  pl.ncells = ncells;
+  pl.ntot = sn;
+  pl.mask = mask;
+  pl.fsum = fsum;
+  CE_TRY(spectrum_impl(ctx, ndim, plan->n, plan->h[0], plan->prec, pl, count, nbins, out_pk, nullptr, nullptr, s));
+  if (count >= 2 && (out_cov || out_cnorm))
+    CE_PROF(ctx, "covariance", s, launch_covariance(out_pk, count, nbins, out_cov, out_cnorm, s));
+  return CE_OK;
+}
+
 ce_status pipeline_check(ce_ctx* ctx, const ce_plan* plan, uint64_t first_realization, int64_t count, double nbar,
                          int32_t nbins, const double* out_pk) {
   if (!ctx || !plan || !out_pk || count <= 0 || nbins <= 0 || (first_realization & 1)) return CE_E_INVALID;
@@ -1226,11 +1339,6 @@ ce_status ce_estimate_pk(ce_ctx* ctx, const ce_geometry* geom, ce_precision prec
     n[d] = (int)geom->n[d];
     ncells *= n[d];
   }
-  const int64_t nitems = (count + 1) / 2;
-  const int Nl = n[ndim - 1];
-  const int W = 2 * (Nl / 2 + 1);
-  const int64_t rows = ncells / Nl;
-  const size_t elem = prec ? 16 : 8;
 
   PairLoad pl;
   pl.kind = kind == CE_MAP_FIELD ? 0 : 1;
@@ -1261,31 +1369,7 @@ ce_status ce_estimate_pk(ce_ctx* ctx, const ce_geometry* geom, ce_precision prec
       pl.ntot = sgn;
     }
   }
-  void* H = nullptr;
-  CE_TRY(ctx->scratch(2, elem * (size_t)(nitems * rows * W), &H));
-  pl.H = H;
-  pl.H_item = rows * W;
-  FftDesc fl;
-  CE_TRY(build_fft(ctx, Nl, prec, fl));
-  LineGeom g1 = make_geom(Nl, Nl, rows, 1, nitems, 0, 0, elem, mixed_radix(fl), 1, 1024);
-  CE_PROF(ctx, "forward_rows_pair", s, launch_pair_forward(prec, g1, fl, pl, s));
-  double* partials = nullptr;
-  int64_t groups = 0;
-  CE_TRY(run_forward_bins(ctx, ndim, n, prec, nitems, H, nbins, &partials, &groups, s));
-  int64_t* nm = nullptr;
-  const std::vector<double>* km = nullptr;
-  CE_TRY(device_shells(ctx, n[0], ndim, geom->h[0], nbins, &nm, &km));
-  const double norm = std::pow(geom->h[0], ndim) / (double)ncells;
-  CE_PROF(ctx, "bin_reduce", s, launch_bin_reduce(partials, nitems, groups, nbins, count, nm, norm, 0, nullptr, nullptr, (double)ncells,
-                           out_pk, ctx->flags, s));
-  if (out_nmodes) CE_HIP(hipMemcpyAsync(out_nmodes, nm, sizeof(int64_t) * nbins, hipMemcpyDeviceToDevice, s));
-  if (out_kmean) {
-    std::vector<double> k(*km);
-    for (double& v : k) v /= geom->h[0];
-    CE_HIP(hipMemcpyAsync(out_kmean, k.data(), sizeof(double) * nbins, hipMemcpyHostToDevice, s));
-    CE_HIP(hipStreamSynchronize(s));
-  }
-  return CE_OK;
+  return spectrum_impl(ctx, ndim, n, geom->h[0], prec, pl, count, nbins, out_pk, out_nmodes, out_kmean, s);
 }
 
 ce_status ce_pk_covariance(ce_ctx* ctx, const double* pk, int64_t count, int32_t nbins, double* out_cov,
@@ -1308,6 +1392,22 @@ ce_status ce_pipeline_run(ce_ctx* ctx, const ce_plan* plan, uint64_t seed, uint3
   ctx->last = s;
   return pipeline_impl(ctx, plan, seed, request_id, first_realization, count, nbar, nbins, out_fields, out_delta,
                        out_counts, out_ntot, out_pk, out_cov, out_cnorm, nullptr, s);
+}
+
+ce_status ce_pipeline_run_masked(ce_ctx* ctx, const ce_plan* plan, const float* mask_f, uint64_t seed,
+                                 uint32_t request_id, uint64_t first_realization, int64_t count, double nbar,
+                                 int32_t nbins, void* out_fields, void* out_delta, int32_t* out_counts,
+                                 int64_t* out_ntot, double* out_pk, double* out_cov, double* out_cnorm, void* stream) {
+  if (!mask_f)
+    return ce_pipeline_run(ctx, plan, seed, request_id, first_realization, count, nbar, nbins, out_fields, out_delta,
+                           out_counts, out_ntot, out_pk, out_cov, out_cnorm, stream);
+  CE_TRY(pipeline_check(ctx, plan, first_realization, count, nbar, nbins, out_pk));
+  std::lock_guard<std::mutex> lock(ctx->mu);
+  CE_HIP(hipSetDevice(ctx->device));
+  hipStream_t s = as_stream(stream);
+  ctx->last = s;
+  return pipeline_masked_impl(ctx, plan, mask_f, seed, request_id, first_realization, count, nbar, nbins, out_fields,
+                              out_delta, out_counts, out_ntot, out_pk, out_cov, out_cnorm, s);
 }
 
 // ---- captured pipeline ------------------------------------------------------------

@@ -88,6 +88,7 @@ struct RowEpi {
   void* fields = nullptr;      // nullable (pass precision)
   void* delta = nullptr;       // nullable (pass precision)
   int32_t* counts = nullptr;   // nullable
+  const float* mask = nullptr; // nullable: surface fraction f per survey cell (rate nbar f rho)
   unsigned long long* ntot = nullptr;  // per local realization (zeroed by the host)
   uint32_t* flags = nullptr;
   const double* inv = nullptr;  // RN(1/k), k = 0..4096, for the Poisson recursion
@@ -97,7 +98,7 @@ struct RowEpi {
   const unsigned long long* pair_base = nullptr;  // nullable, as in NoiseArgs
   const PairDesc* desc = nullptr;  // nullable: per-pair parameters (batched pipeline, mode 2)
   FftDesc fwd;                 // forward FFT of the packed counts row (length K)
-  void* H = nullptr;           // separated spectra rows: W = 2 (K/2 + 1) complex per row
+  void* H = nullptr;           // separated spectra rows: W = 2 (K/2 + 1) complex per row (null: counts only)
   int64_t H_item = 0;
 };
 

@@ -591,12 +591,14 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(sizeof
     T* da = e.delta ? static_cast<T*>(e.delta) + ra * e.ncells + row * K : nullptr;
     int32_t* ca = pd ? (pd->counts ? pd->counts + row * K : nullptr)
                      : (e.counts ? e.counts + ra * e.ncells + row * K : nullptr);
+    const float* fr = e.mask ? e.mask + row * K : nullptr;
     for (int i = lane; i < K; i += g.nlanes) {
       const cpx<T> z = line[pidx(i)];
       const T dla = lognormal_delta<T>(z.x, s2h);
       const T dlb = lognormal_delta<T>(z.y, s2h);
-      const double mua = intensity(nbar, 1.0, (double)dla);
-      const double mub = intensity(nbar, 1.0, (double)dlb);
+      const double f = fr ? (double)fr[i] : 1.0;
+      const double mua = intensity(nbar, f, (double)dla);
+      const double mub = intensity(nbar, f, (double)dlb);
       int na, nb;
       poisson_pair(mua, mub, has_b, (uint32_t)(row * K + i), pair, rid, k0, k1, inv_s, e.flags, na, nb);
       if (fa) {
@@ -621,6 +623,7 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(sizeof
   __syncthreads();
   if (threadIdx.x == 0 && tot[0]) atomicAdd(&e.ntot[ra], tot[0]);
   if (threadIdx.x == 1 && tot[1] && has_b) atomicAdd(&e.ntot[ra + 1], tot[1]);
+  if (!e.H) return;  // counts only (masked survey: the spectrum is taken from the stored counts)
   cpx<T>* Hrow = static_cast<cpx<T>*>(e.H) + pp.item * e.H_item + row * (int64_t)(2 * (K / 2 + 1));
   forward_separate<T, MIX>(line, other, e.fwd, lane, g.nlanes, active, Hrow);
 }

@@ -88,3 +88,25 @@ def serving_trace(rate=2000.0, duration=20.0, seed=5, max_side_2d=2048, max_side
                          nbar=float(rng.choice([0.1, 0.3, 1.0, 5.0])), nbins=32, seed=0))
         i += 1
     return reqs
+
+
+def survey_mask(n, seed=7, holes_per_cell=1.0 / 400.0, edge=0.06):
+    """Synthetic surface-fraction map f in [0, 1] shaped like a masked survey: bright-star
+    holes (disks of radius 1..4 cells, f = 0), a partially covered border strip (f = 0.85)
+    and full coverage elsewhere; cells below 0.7 are fully masked (f = 0)."""
+    rng = np.random.default_rng(seed)
+    n = tuple(int(x) for x in n)
+    f = np.ones(n, dtype=np.float64)
+    w = max(1, int(round(edge * min(n))))
+    for ax in range(len(n)):
+        sl = [slice(None)] * len(n)
+        sl[ax] = slice(0, w)
+        f[tuple(sl)] = np.minimum(f[tuple(sl)], 0.85)
+    grids = np.meshgrid(*[np.arange(x) for x in n], indexing="ij")
+    for _ in range(max(1, int(np.prod(n) * holes_per_cell))):
+        c = [rng.integers(0, x) for x in n]
+        r = rng.uniform(1.0, 4.0)
+        d2 = sum((g - ci) ** 2 for g, ci in zip(grids, c))
+        f[d2 <= r * r] = 0.0
+    f[f < 0.7] = 0.0
+    return f.astype(np.float32)

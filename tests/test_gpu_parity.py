@@ -423,3 +423,50 @@ def test_volume_3d_parity_and_full_size_properties(ce):
     # P_counts >= h^3 / nbar (Poisson) at every shell on average
     assert pk.reshape(R, nb).mean(axis=0).min() > 0.5 / nbar
     plan.release()
+
+
+@pytest.mark.parametrize("n,prec,nb", [((64, 64), 1, 16), ((96, 96), 0, 24), ((16, 16, 16), 0, 6)])
+def test_masked_pipeline_matches_unfused_and_oracle(ce, n, prec, nb):
+    """Masked survey (Sec. 3.1 rate nbar f rho; Sec. 3.2 contrast on f != 0): the masked
+    pipeline equals the unfused calls with the same mask, and the oracle fed the GPU's delta
+    and counts."""
+    from synth import workloads
+    b, ctx = ce
+    print("masked case", n, prec, flush=True)
+    xi = dict(kind="exp", sigma2=0.8, a=3.0) if len(n) == 2 else dict(kind="exp", sigma2=0.8, a=1.5)
+    mask_np = workloads.survey_mask(n, seed=3)
+    mask = torch.from_numpy(mask_np.ravel()).cuda()
+    nbar, seed, rid, first, count = 4.0, 8, 6, 2, 5
+    plan = b.plan_embedding(ctx, n, (1.0,) * len(n), xi, prec)
+    cells = plan.cells
+    f = torch.empty(count * cells, dtype=plan.dtype, device="cuda")
+    d = torch.empty_like(f)
+    c = torch.empty(count * cells, dtype=torch.int32, device="cuda")
+    nt = torch.empty(count, dtype=torch.int64, device="cuda")
+    p = torch.empty(count * nb, dtype=torch.float64, device="cuda")
+    cov = torch.empty(nb * nb, dtype=torch.float64, device="cuda")
+    b.pipeline_run_masked(ctx, plan, mask, seed, rid, first, count, nbar, nb, p, f, d, c, nt, cov)
+    torch.cuda.synchronize()
+    assert b.ctx_check(ctx) == 0
+    ch = c.cpu().numpy().reshape((count,) + n)
+    assert np.all(ch[:, mask_np == 0] == 0)
+    # unfused calls
+    f2 = gpu_fields(b, ctx, plan, seed, rid, first, count)
+    assert torch.equal(f, f2)
+    d2, c2, nt2 = torch.empty_like(d), torch.empty_like(c), torch.empty_like(nt)
+    b.lognormal_poisson(ctx, plan, f2, count, nbar, mask, seed, rid, first, d2, c2, nt2)
+    p2 = torch.empty_like(p)
+    b.estimate_pk(ctx, n, (1.0,) * len(n), prec, b.MAP_COUNTS_DELTAG, c2, count, nt2, mask, nb, p2)
+    torch.cuda.synchronize()
+    assert torch.equal(d, d2) and torch.equal(c, c2) and torch.equal(nt, nt2)
+    assert torch.equal(p, p2)
+    # oracle
+    dh = d.cpu().numpy().reshape((count,) + n)
+    fh = f.cpu().numpy().astype(np.float64).reshape((count,) + n)
+    _, rc, rn = olp.lognormal_poisson(fh, plan.info["sigma2"], nbar, seed, rid, first, mask=mask_np, delta=dh)
+    assert np.array_equal(ch, rc) and np.array_equal(nt.cpu().numpy(), rn)
+    rp = opk.estimate_pk(rc, 1.0, nb, kind="counts", ntot=rn, mask=mask_np)
+    assert np.max(np.abs(p.cpu().numpy().reshape(count, nb) / rp - 1)) <= TOL_PK[prec]
+    rcov, _ = opk.covariance(p.cpu().numpy().reshape(count, nb))
+    assert rel(cov.cpu().numpy().reshape(nb, nb), rcov) <= 1e-12
+    plan.release()
