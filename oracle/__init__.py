@@ -18,10 +18,12 @@ Every function follows the definition in Carron, Wolk & Szapudi (2014),
 * ``pk``         -- Sec. 3.2: power-spectrum estimator (eq. Def spec) on the
   galaxy contrast with the estimated intensity (eq. Estim); spectrum
   covariance and the normalised matrix of eq. cuminfo.
+* ``cic``        -- Sec. 3.4: counts-in-cells histogram, its Poisson-lognormal
+  prediction, and the A* map (eq. As).
 * ``philox``     -- the counter-based generator that supplies the noise
   (Salmon et al. 2011, Philox4x32-10) and the uniform / Box-Muller maps.
 
 Parity status of each function is listed in its module header.
 """
 
-from . import philox, embedding, fields, lognormal_poisson, pk  # noqa: F401
+from . import philox, embedding, fields, lognormal_poisson, pk, cic  # noqa: F401
