@@ -106,6 +106,7 @@ def parse():
     ap.add_argument("--lines", default="",
                     help="schedule: max lines per workgroup for noise,inner,last,bins (0 = automatic)")
     ap.add_argument("--noise-order", type=int, default=-1, help="schedule: noise-pass tile order (0/1)")
+    ap.add_argument("--no-masked", action="store_true", help="skip the masked-survey leg")
     ap.add_argument("--batch-requests", type=int, default=4096,
                     help="requests of the uneven-batch leg (mixed 2-D sides 32..512); 0 to skip")
     ap.add_argument("--batch-reps", type=int, default=5)
@@ -488,6 +489,31 @@ def main():
 
     plan.release()
     b.ctx_destroy(ctx)
+
+    if not args.no_masked:
+        # the same workload on a masked survey (star holes and a partial border, 7% of cells out)
+        mask = torch.from_numpy(workloads.survey_mask(n, seed=3).ravel()).to(dev)
+        ctx = b.ctx_create(0)
+        plan = b.plan_embedding(ctx, n, h, w["xi"], prec)
+        mc = torch.empty(R * plan.cells, dtype=torch.int32, device=dev)
+
+        def mstep(i):
+            b.pipeline_run_masked(ctx, plan, mask, w["seed"], w["request_id"], i * R * 2, R, nbar, nb, pk_out,
+                                  out_counts=mc, out_ntot=ntot, out_cov=cov, out_cnorm=cnorm, stream=stream)
+
+        mstep(0)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        msteps = max(3, args.steps // 4)
+        for i in range(msteps):
+            mstep(1 + i)
+        torch.cuda.synchronize()
+        mdt = (time.perf_counter() - t0) / msteps
+        out["masked"] = dict(value=round(R / mdt, 1), unit="realizations/s", ms_per_step=round(1e3 * mdt, 3),
+                             steps=msteps, masked_fraction=round(float((mask == 0).float().mean()), 4),
+                             form="fused pass with the mask's rate, counts stored, contrast on f != 0 from them")
+        plan.release()
+        b.ctx_destroy(ctx)
 
     if args.batch_requests:
         out["uneven_batch"] = uneven_batch_leg(b, torch, args.batch_requests, args.batch_reps)
