@@ -214,6 +214,31 @@ ce_status ce_estimate_pk(ce_ctx* ctx, const ce_geometry* geom, ce_precision prec
 ce_status ce_pk_covariance(ce_ctx* ctx, const double* pk, int64_t count, int32_t nbins,
                            double* out_cov, double* out_cnorm, void* stream);
 
+/* Largest histogram length of ce_cic_histogram. */
+#define CE_CIC_MAX_BINS 4096
+
+/* Counts-in-cells histogram (Sec. 3.4): out_hist[r * nhist + N] = the number of cells i of map r
+ * with f_i != 0 and count N, N = 0 .. nhist-1; counts outside that range are in no bin and fully
+ * masked cells are ignored.  counts: count x cells int32 (device); mask_f (nullable: f = 1):
+ * cells floats in [0, 1] (device); out_hist: count x nhist int64 (device), overwritten.  Exact in
+ * integers.  1 <= nhist <= CE_CIC_MAX_BINS.  Errors: CE_E_INVALID, CE_E_DEVICE. */
+ce_status ce_cic_histogram(ce_ctx* ctx, const int32_t* counts, int64_t cells, int64_t count,
+                           const float* mask_f, int32_t nhist, int64_t* out_hist, void* stream);
+
+/* A* map (Sec. 3.4, eq. As): in each cell with f_i != 0, the root A* of
+ * e^{A*} N_bar_i sigma2_A + A* = sigma2_A (N_i - 1/2) with N_bar_i = nbar f_i, solved in FP64
+ * (unique: the left side increases strictly with A*); cells with f_i = 0 hold 0.
+ * subtract_mean != 0: A* minus its mean over the unmasked cells of the map, 0 on masked cells
+ * (the map whose spectrum ce_estimate_pk estimates as CE_MAP_FIELD).  counts: count x cells
+ * int32 (device); mask_f (nullable: f = 1): cells floats in [0, 1]; out_map: count x cells of
+ * float (CE_F32) or double (CE_F64), rounded once from FP64; out_mean (nullable, device): count
+ * doubles, the mean of A* over the unmasked cells of each map (0 when all are masked), summed
+ * in a fixed order.  nbar > 0 and sigma2_A > 0 (the variance of the log-density, ln(1 +
+ * sigma_delta^2)), both finite.  Errors: CE_E_INVALID, CE_E_DEVICE. */
+ce_status ce_astar_map(ce_ctx* ctx, const int32_t* counts, int64_t cells, int64_t count,
+                       const float* mask_f, double nbar, double sigma2_A, int32_t subtract_mean,
+                       ce_precision precision, void* out_map, double* out_mean, void* stream);
+
 /* The whole hot path fused: generate `count` realizations (as ce_generate_fields), lognormal +
  * Poisson counts (as ce_lognormal_poisson, f = 1, the same seed for fields and counts), the
  * counts spectrum (as ce_estimate_pk with CE_MAP_COUNTS_DELTAG) and, when out_cov or out_cnorm

@@ -95,6 +95,9 @@ _lognormal_poisson = _sig("ce_lognormal_poisson", c_i32, c_void_p, c_void_p, c_v
 _estimate_pk = _sig("ce_estimate_pk", c_i32, c_void_p, ctypes.POINTER(Geometry), c_i32, c_i32, c_void_p, c_i64,
                     c_void_p, c_void_p, c_i32, c_void_p, c_void_p, c_void_p, c_void_p)
 _pk_covariance = _sig("ce_pk_covariance", c_i32, c_void_p, c_void_p, c_i64, c_i32, c_void_p, c_void_p, c_void_p)
+_cic_histogram = _sig("ce_cic_histogram", c_i32, c_void_p, c_void_p, c_i64, c_i64, c_void_p, c_i32, c_void_p, c_void_p)
+_astar_map = _sig("ce_astar_map", c_i32, c_void_p, c_void_p, c_i64, c_i64, c_void_p, c_f64, c_f64, c_i32, c_i32,
+                  c_void_p, c_void_p, c_void_p)
 _pipeline_run = _sig("ce_pipeline_run", c_i32, c_void_p, c_void_p, c_u64, c_u32, c_u64, c_i64, c_f64, c_i32,
                      c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p)
 _graph_create = _sig("ce_pipeline_graph_create", c_i32, c_void_p, c_void_p, c_u64, c_u32, c_u64, c_i64, c_f64, c_i32,
@@ -122,6 +125,7 @@ EXPORTED = ["ce_status_string", "ce_version", "ce_ctx_create", "ce_ctx_destroy",
             "ce_ctx_set_option", "ce_ctx_set_profiling", "ce_ctx_profile_read",
             "ce_plan_embedding", "ce_plan_release", "ce_plan_get_info", "ce_plan_eigenvalues",
             "ce_generate_fields", "ce_lognormal_poisson", "ce_estimate_pk", "ce_pk_covariance",
+            "ce_cic_histogram", "ce_astar_map",
             "ce_pipeline_run", "ce_pipeline_run_masked", "ce_pipeline_run_batch", "ce_pipeline_graph_create", "ce_pipeline_graph_launch",
             "ce_pipeline_graph_destroy",
             "ce_server_create", "ce_server_submit", "ce_server_poll", "ce_server_drain", "ce_server_cancel",
@@ -235,6 +239,7 @@ def ctx_trim(ctx):
 
 
 OPT_UNPRUNED = 1
+CIC_MAX_BINS = 4096
 OPT_LINES_NOISE, OPT_LINES_INNER, OPT_LINES_LAST, OPT_LINES_BINS, OPT_NOISE_ORDER, OPT_BIN_LDS = 2, 3, 4, 5, 6, 7
 
 
@@ -356,6 +361,23 @@ def pk_covariance(ctx, pk, count, nbins, out_cov, out_cnorm, stream=None):
                           _ptr(out_cov, torch.float64, nbins * nbins, "out_cov"),
                           _ptr(out_cnorm, torch.float64, nbins * nbins, "out_cnorm"), _stream(stream)),
            "ce_pk_covariance")
+
+
+def cic_histogram(ctx, counts, cells, count, mask_f, nhist, out_hist, stream=None):
+    _check(_cic_histogram(ctx, _ptr(counts, torch.int32, count * cells, "counts"), int(cells), int(count),
+                          _ptr(mask_f, torch.float32, cells, "mask_f"), int(nhist),
+                          _ptr(out_hist, torch.int64, count * nhist, "out_hist"), _stream(stream)),
+           "ce_cic_histogram")
+
+
+def astar_map(ctx, counts, cells, count, mask_f, nbar, sigma2_A, subtract_mean, precision, out_map,
+              out_mean=None, stream=None):
+    mdt = torch.float64 if precision == F64 else torch.float32
+    _check(_astar_map(ctx, _ptr(counts, torch.int32, count * cells, "counts"), int(cells), int(count),
+                      _ptr(mask_f, torch.float32, cells, "mask_f"), float(nbar), float(sigma2_A),
+                      1 if subtract_mean else 0, int(precision), _ptr(out_map, mdt, count * cells, "out_map"),
+                      _ptr(out_mean, torch.float64, count, "out_mean"), _stream(stream)),
+           "ce_astar_map")
 
 
 def pipeline_run(ctx, plan, seed, request_id, first_realization, count, nbar, nbins, out_pk, out_fields=None,

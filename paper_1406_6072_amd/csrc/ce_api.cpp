@@ -168,7 +168,7 @@ struct ce_ctx {
     size_t n = 0;
     hipStream_t used = nullptr;  // stream of the last call that used the buffer
   };
-  Buf ws[8];
+  Buf ws[10];
   // pinned host staging of batch tables; `staged` is recorded after the copy that reads it
   void* pin = nullptr;
   size_t pin_n = 0;
@@ -1378,6 +1378,47 @@ ce_status ce_pk_covariance(ce_ctx* ctx, const double* pk, int64_t count, int32_t
   if (!out_cov && !out_cnorm) return CE_OK;
   CE_HIP(hipSetDevice(ctx->device));
   CE_HIP(launch_covariance(pk, count, nbins, out_cov, out_cnorm, as_stream(stream)));
+  return CE_OK;
+}
+
+ce_status ce_cic_histogram(ce_ctx* ctx, const int32_t* counts, int64_t cells, int64_t count, const float* mask_f,
+                           int32_t nhist, int64_t* out_hist, void* stream) {
+  if (!ctx || !counts || !out_hist || cells <= 0 || count <= 0) return CE_E_INVALID;
+  if (nhist < 1 || nhist > CE_CIC_MAX_BINS) return CE_E_INVALID;
+  std::lock_guard<std::mutex> lock(ctx->mu);
+  CE_HIP(hipSetDevice(ctx->device));
+  hipStream_t s = as_stream(stream);
+  ctx->last = s;
+  CE_PROF(ctx, "cic_histogram", s,
+          launch_cic_histogram(counts, mask_f, cells, count, nhist, reinterpret_cast<unsigned long long*>(out_hist),
+                               s));
+  return CE_OK;
+}
+
+ce_status ce_astar_map(ce_ctx* ctx, const int32_t* counts, int64_t cells, int64_t count, const float* mask_f,
+                       double nbar, double sigma2_A, int32_t subtract_mean, ce_precision precision, void* out_map,
+                       double* out_mean, void* stream) {
+  if (!ctx || !counts || !out_map || cells <= 0 || count <= 0) return CE_E_INVALID;
+  if (precision != CE_F32 && precision != CE_F64) return CE_E_INVALID;
+  if (!(nbar > 0) || !std::isfinite(nbar) || !(sigma2_A > 0) || !std::isfinite(sigma2_A)) return CE_E_INVALID;
+  std::lock_guard<std::mutex> lock(ctx->mu);
+  CE_HIP(hipSetDevice(ctx->device));
+  hipStream_t s = as_stream(stream);
+  ctx->last = s;
+  double* mean = out_mean;
+  double* part = nullptr;
+  if (subtract_mean || out_mean) {
+    void* p = nullptr;
+    CE_TRY(ctx->scratch(8, sizeof(double) * (size_t)astar_partials(cells, count), &p));
+    part = static_cast<double*>(p);
+    if (!mean) {
+      CE_TRY(ctx->scratch(9, sizeof(double) * (size_t)count, &p));
+      mean = static_cast<double*>(p);
+    }
+  }
+  CE_PROF(ctx, "astar_map", s,
+          launch_astar(precision == CE_F64 ? 1 : 0, counts, mask_f, cells, count, nbar, sigma2_A, subtract_mean != 0,
+                       out_map, part, mean, s));
   return CE_OK;
 }
 

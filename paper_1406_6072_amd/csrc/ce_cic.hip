@@ -1,0 +1,224 @@
+// Counts-in-cells statistics of Poisson maps (Sec. 3.4): the histogram of the counts over
+// unmasked cells, and the A* map, the per-cell root of eq. As, whose spectrum is estimated
+// like that of the galaxy contrast.
+//
+// Both read the counts once (int32) and the survey mask (float, optional).  The histogram
+// is exact in integers (LDS counters, one copy per wave, flushed with 64-bit atomics); the
+// A* map is solved in FP64 in registers and its per-map mean is reduced in a fixed order,
+// so every output is bitwise reproducible for a given launch shape.
+
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+
+#include "ce_internal.hpp"
+
+namespace ce {
+
+namespace {
+
+constexpr int kCicThreads = 256;
+constexpr int kCicWaves = kCicThreads / 64;
+constexpr int kGridY = 65535;  // realizations per launch (grid y)
+
+// Workgroups per map: enough to fill the chip for one map, about 8 cells per thread.
+int64_t blocks_per_map(int64_t cells) {
+  int64_t b = (cells + kCicThreads * 8 - 1) / (kCicThreads * 8);
+  return b < 1 ? 1 : (b > 2048 ? 2048 : b);
+}
+
+// Up to this many bins each wave counts into its own LDS copy (fewer collisions between
+// the waves of a workgroup); longer histograms share one copy.
+constexpr int kWaveCopyBins = 1024;
+
+__global__ void __launch_bounds__(kCicThreads) k_cic_histogram(const int32_t* __restrict__ counts,
+                                                               const float* __restrict__ mask, int64_t cells,
+                                                               int nhist, unsigned long long* __restrict__ hist) {
+  extern __shared__ uint32_t bins[];  // ncopy copies of nhist counters
+  const int ncopy = nhist <= kWaveCopyBins ? kCicWaves : 1;
+  const int r = blockIdx.y;
+  for (int i = threadIdx.x; i < ncopy * nhist; i += kCicThreads) bins[i] = 0;
+  __syncthreads();
+  uint32_t* mine = bins + (ncopy == 1 ? 0 : (threadIdx.x >> 6) * nhist);
+  const int32_t* c = counts + (int64_t)r * cells;
+  const int64_t stride = (int64_t)gridDim.x * kCicThreads;
+  for (int64_t i = blockIdx.x * (int64_t)kCicThreads + threadIdx.x; i < cells; i += stride) {
+    const int32_t n = c[i];
+    const bool keep = mask == nullptr || mask[i] != 0.0f;
+    if (keep && (uint32_t)n < (uint32_t)nhist) atomicAdd(&mine[n], 1u);
+  }
+  __syncthreads();
+  unsigned long long* h = hist + (int64_t)r * nhist;
+  for (int i = threadIdx.x; i < nhist; i += kCicThreads) {
+    uint32_t t = 0;
+    for (int w = 0; w < ncopy; ++w) t += bins[w * nhist + i];
+    if (t) atomicAdd(&h[i], (unsigned long long)t);
+  }
+}
+
+__global__ void k_zero_i64(unsigned long long* p, int64_t n) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0;
+}
+
+// Root of c e^A + A = d (eq. As with c = N_bar f sigma_A^2, d = sigma_A^2 (N - 1/2)).
+// With A = d - w the equation becomes w e^w = c e^d, so w is the principal Lambert
+// function of x = c e^d; it is found from y = ln x by Newton's method on w + ln w = y
+// (concave and increasing in w), which stays positive and converges quadratically from
+// the starting points used: x / (1 + x) for y <= 1, the asymptotic y - ln y + ln y / y
+// above.  For y < -36, W(x) = x to FP64 precision.
+__device__ __forceinline__ double astar_solve(int32_t n, double c, double s2) {
+  const double d = s2 * ((double)n - 0.5);
+  const double y = log(c) + d;
+  double w;
+  if (y < -36.0) {
+    w = exp(y);
+  } else {
+    if (y <= 1.0) {
+      const double x = exp(y);
+      w = x / (1.0 + x);
+    } else {
+      const double ly = log(y);
+      w = y - ly + ly / y;
+    }
+    for (int it = 0; it < 16; ++it) {
+      const double wn = w * (1.0 + y - log(w)) / (1.0 + w);
+      const bool done = fabs(wn - w) <= 0x1p-50 * wn;
+      w = wn;
+      if (done) break;
+    }
+  }
+  return d - w;
+}
+
+// MODE 0: write A* (0 on masked cells).  MODE 1: per-workgroup sums of A* and of the
+// number of unmasked cells into partials[(r * gridDim.x + block) * 2 + {0, 1}], no map
+// written.  MODE 2: write A* - mean[r] on unmasked cells, 0 on masked cells.
+template <typename T, int MODE>
+__global__ void __launch_bounds__(kCicThreads) k_astar(const int32_t* __restrict__ counts,
+                                                       const float* __restrict__ mask, int64_t cells,
+                                                       double nbar, double s2, T* __restrict__ out,
+                                                       double* __restrict__ partials,
+                                                       const double* __restrict__ mean) {
+  const int r = blockIdx.y;
+  const int32_t* c = counts + (int64_t)r * cells;
+  const double m = MODE == 2 ? mean[r] : 0.0;
+  double acc = 0.0, nk = 0.0;
+  const int64_t stride = (int64_t)gridDim.x * kCicThreads;
+  for (int64_t i = blockIdx.x * (int64_t)kCicThreads + threadIdx.x; i < cells; i += stride) {
+    const float f = mask ? mask[i] : 1.0f;
+    double a = 0.0;
+    if (f != 0.0f) {
+      a = astar_solve(c[i], (nbar * (double)f) * s2, s2);
+      acc += a;
+      nk += 1.0;
+      a -= m;
+    }
+    if (MODE != 1) out[(int64_t)r * cells + i] = (T)a;
+  }
+  if (MODE == 1) {
+    __shared__ double sa[kCicThreads], sn[kCicThreads];
+    sa[threadIdx.x] = acc;
+    sn[threadIdx.x] = nk;
+    __syncthreads();
+    for (int h = kCicThreads / 2; h > 0; h >>= 1) {
+      if ((int)threadIdx.x < h) {
+        sa[threadIdx.x] += sa[threadIdx.x + h];
+        sn[threadIdx.x] += sn[threadIdx.x + h];
+      }
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+      double* p = partials + ((int64_t)r * gridDim.x + blockIdx.x) * 2;
+      p[0] = sa[0];
+      p[1] = sn[0];
+    }
+  }
+}
+
+// mean[r] = (sum of A*) / (unmasked cells) from the partials of one map, in a fixed order;
+// 0 when every cell is masked.
+__global__ void __launch_bounds__(kCicThreads) k_astar_mean(const double* __restrict__ partials, int64_t blocks,
+                                                            double* __restrict__ mean) {
+  const int r = blockIdx.x;
+  __shared__ double sa[kCicThreads], sn[kCicThreads];
+  double a = 0.0, n = 0.0;
+  for (int64_t b = threadIdx.x; b < blocks; b += kCicThreads) {
+    a += partials[((int64_t)r * blocks + b) * 2];
+    n += partials[((int64_t)r * blocks + b) * 2 + 1];
+  }
+  sa[threadIdx.x] = a;
+  sn[threadIdx.x] = n;
+  __syncthreads();
+  for (int h = kCicThreads / 2; h > 0; h >>= 1) {
+    if ((int)threadIdx.x < h) {
+      sa[threadIdx.x] += sa[threadIdx.x + h];
+      sn[threadIdx.x] += sn[threadIdx.x + h];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) mean[r] = sn[0] > 0.0 ? sa[0] / sn[0] : 0.0;
+}
+
+template <typename T, int MODE>
+hipError_t astar_launch(const int32_t* counts, const float* mask, int64_t cells, int64_t count, double nbar,
+                        double s2, T* out, double* partials, const double* mean, hipStream_t s) {
+  const int64_t bx = blocks_per_map(cells);
+  for (int64_t r0 = 0; r0 < count; r0 += kGridY) {
+    const int64_t nr = count - r0 < kGridY ? count - r0 : kGridY;
+    hipLaunchKernelGGL((k_astar<T, MODE>), dim3((unsigned)bx, (unsigned)nr), dim3(kCicThreads), 0, s,
+                       counts + r0 * cells, mask, cells, nbar, s2, MODE == 1 ? nullptr : out + r0 * cells,
+                       MODE == 1 ? partials + r0 * bx * 2 : nullptr, MODE == 2 ? mean + r0 : nullptr);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+template <typename T>
+hipError_t astar_all(const int32_t* counts, const float* mask, int64_t cells, int64_t count, double nbar,
+                     double s2, bool subtract, T* out, double* partials, double* mean, hipStream_t s) {
+  if (mean) {
+    hipError_t e = astar_launch<T, 1>(counts, mask, cells, count, nbar, s2, out, partials, nullptr, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_astar_mean, dim3((unsigned)count), dim3(kCicThreads), 0, s, partials,
+                       blocks_per_map(cells), mean);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  if (subtract) return astar_launch<T, 2>(counts, mask, cells, count, nbar, s2, out, partials, mean, s);
+  return astar_launch<T, 0>(counts, mask, cells, count, nbar, s2, out, partials, mean, s);
+}
+
+}  // namespace
+
+int64_t astar_partials(int64_t cells, int64_t count) { return blocks_per_map(cells) * count * 2; }
+
+hipError_t launch_cic_histogram(const int32_t* counts, const float* mask, int64_t cells, int64_t count, int nhist,
+                                unsigned long long* hist, hipStream_t s) {
+  const int64_t n = count * nhist;
+  hipLaunchKernelGGL(k_zero_i64, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, hist, n);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const int64_t bx = blocks_per_map(cells);
+  const size_t lds = sizeof(uint32_t) * (nhist <= kWaveCopyBins ? kCicWaves : 1) * (size_t)nhist;
+  for (int64_t r0 = 0; r0 < count; r0 += kGridY) {
+    const int64_t nr = count - r0 < kGridY ? count - r0 : kGridY;
+    hipLaunchKernelGGL(k_cic_histogram, dim3((unsigned)bx, (unsigned)nr), dim3(kCicThreads), lds, s,
+                       counts + r0 * cells, mask, cells, nhist, hist + r0 * nhist);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+hipError_t launch_astar(int prec, const int32_t* counts, const float* mask, int64_t cells, int64_t count,
+                        double nbar, double s2, bool subtract, void* out, double* partials, double* mean,
+                        hipStream_t s) {
+  if (prec) return astar_all<double>(counts, mask, cells, count, nbar, s2, subtract, static_cast<double*>(out),
+                                     partials, mean, s);
+  return astar_all<float>(counts, mask, cells, count, nbar, s2, subtract, static_cast<float*>(out), partials,
+                          mean, s);
+}
+
+}  // namespace ce

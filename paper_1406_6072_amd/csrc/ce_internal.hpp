@@ -161,6 +161,13 @@ hipError_t launch_debug_philox(uint32_t k0, uint32_t k1, const uint32_t* ctr, in
                                hipStream_t s);
 hipError_t launch_debug_noise(int prec, const NoiseArgs& n, uint64_t pair, int64_t cells, void* out, hipStream_t s);
 hipError_t launch_zero_u64(unsigned long long* p, int64_t n, hipStream_t s);
+// counts-in-cells (ce_cic.hip)
+hipError_t launch_cic_histogram(const int32_t* counts, const float* mask, int64_t cells, int64_t count, int nhist,
+                                unsigned long long* hist, hipStream_t s);
+int64_t astar_partials(int64_t cells, int64_t count);  // doubles of partial sums for the mean
+hipError_t launch_astar(int prec, const int32_t* counts, const float* mask, int64_t cells, int64_t count,
+                        double nbar, double s2, bool subtract, void* out, double* partials, double* mean,
+                        hipStream_t s);
 hipError_t launch_advance(unsigned long long* p, unsigned long long by, hipStream_t s);
 
 }  // namespace ce
