@@ -97,12 +97,15 @@ def astar_root(N, nbar_i, sigma2_A):
     log1p_x = y + math.log1p(math.exp(-y)) if y > 0 else math.log1p(math.exp(y))
     lo, hi = d - log1p_x - 1.0, d
 
-    def g(A):
-        if A + math.log(c) > 700.0:  # c e^A beyond FP64 range: far above the root
-            return math.inf
-        return c * math.exp(A) + A - d
+    lnc = math.log(c)
 
-    assert g(lo) < 0 < g(hi)
+    def g(A):
+        if A + lnc > 700.0:  # c e^A beyond FP64 range: far above the root
+            return math.inf
+        e = c * math.exp(A) if A < 700.0 else math.exp(A + lnc)
+        return e + (A - d)
+
+    assert g(lo) < 0 <= g(hi)
     while True:
         mid = 0.5 * (lo + hi)
         if mid <= lo or mid >= hi:
