@@ -93,6 +93,41 @@ def traffic_for(kernel, workload):
     return None if k is None else int(k["bytes_per_launch"])
 
 
+def cic_leg(b, torch, ctx, plan, mask, counts, R, nb, nbar, n, h, stream, steps):
+    """Counts-in-cells statistics of the masked maps (Sec. 3.4): the 42-bin histogram, the
+    mean-subtracted A* map (FP32) and its P(k), per step of R maps."""
+    cells = plan.cells
+    nh = 42
+    s2 = plan.info["sigma2"]
+    hist = torch.empty(R * nh, dtype=torch.int64, device=counts.device)
+    amap = torch.empty(R * cells, dtype=torch.float32, device=counts.device)
+    apk = torch.empty(R * nb, dtype=torch.float64, device=counts.device)
+
+    def cstep():
+        b.cic_histogram(ctx, counts, cells, R, mask, nh, hist, stream)
+        b.astar_map(ctx, counts, cells, R, mask, nbar, s2, True, b.F32, amap, None, stream)
+        b.estimate_pk(ctx, n, h, b.F32, b.MAP_FIELD, amap, R, None, None, nb, apk, stream=stream)
+
+    cstep()
+    torch.cuda.synchronize()
+    b.ctx_profile_read(ctx)
+    b.ctx_set_profiling(ctx, True)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        cstep()
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    b.ctx_set_profiling(ctx, False)
+    prof = b.ctx_profile_read(ctx)
+    kern = {k: round(v[0] / steps, 4) for k, v in prof.items()}
+    hist_ms = kern.get("cic_histogram", 0.0)
+    hist_bytes = 4 * cells * R + 4 * cells  # the counts of every map (int32); the mask (float) once
+    return dict(value=round(R / dt, 1), unit="maps/s", ms_per_step=round(1e3 * dt, 3), steps=steps,
+                kernels_ms=kern, histogram_GBs=round(hist_bytes / (hist_ms * 1e-3) / 1e9, 1) if hist_ms else None,
+                form="42-bin histogram over f != 0, A* (FP64 solve, mean over f != 0 subtracted, stored FP32), "
+                     "P(k) of the A* map through the spectrum estimator")
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -107,6 +142,7 @@ def parse():
                     help="schedule: max lines per workgroup for noise,inner,last,bins (0 = automatic)")
     ap.add_argument("--noise-order", type=int, default=-1, help="schedule: noise-pass tile order (0/1)")
     ap.add_argument("--no-masked", action="store_true", help="skip the masked-survey leg")
+    ap.add_argument("--no-cic", action="store_true", help="skip the counts-in-cells leg (histogram, A* and its P(k))")
     ap.add_argument("--batch-requests", type=int, default=4096,
                     help="requests of the uneven-batch leg (mixed 2-D sides 32..512); 0 to skip")
     ap.add_argument("--batch-reps", type=int, default=5)
@@ -512,6 +548,8 @@ def main():
         out["masked"] = dict(value=round(R / mdt, 1), unit="realizations/s", ms_per_step=round(1e3 * mdt, 3),
                              steps=msteps, masked_fraction=round(float((mask == 0).float().mean()), 4),
                              form="fused pass with the mask's rate, counts stored, contrast on f != 0 from them")
+        if not args.no_cic:
+            out["cic"] = cic_leg(b, torch, ctx, plan, mask, mc, R, nb, nbar, n, h, stream, msteps)
         plan.release()
         b.ctx_destroy(ctx)
 

@@ -3,7 +3,7 @@
 // like that of the galaxy contrast.
 //
 // Both read the counts once (int32) and the survey mask (float, optional).  The histogram
-// is exact in integers (LDS counters, one copy per wave, flushed with 64-bit atomics); the
+// is exact in integers (LDS counters in several copies, flushed with 64-bit atomics); the
 // A* map is solved in FP64 in registers and its per-map mean is reduced in a fixed order,
 // so every output is bitwise reproducible for a given launch shape.
 
@@ -18,7 +18,6 @@ namespace ce {
 namespace {
 
 constexpr int kCicThreads = 256;
-constexpr int kCicWaves = kCicThreads / 64;
 constexpr int kGridY = 65535;  // realizations per launch (grid y)
 
 // Workgroups per map: enough to fill the chip for one map, about 8 cells per thread.
@@ -27,31 +26,59 @@ int64_t blocks_per_map(int64_t cells) {
   return b < 1 ? 1 : (b > 2048 ? 2048 : b);
 }
 
-// Up to this many bins each wave counts into its own LDS copy (fewer collisions between
-// the waves of a workgroup); longer histograms share one copy.
-constexpr int kWaveCopyBins = 1024;
+// LDS counters: the workgroup holds ncopy copies of the histogram and thread t counts into
+// copy t % ncopy, so lanes of a wave that see the same count (most of them, at low
+// intensity) hit different words; the copies are an odd number of words apart, so equal
+// counts also fall in different banks.  ncopy is the largest power of two <= 64 whose copies
+// fit kHistLds.
+constexpr int kHistLds = 48 * 1024;
 
+__host__ __device__ inline int hist_stride(int nhist) { return nhist | 1; }
+__host__ __device__ inline int hist_copies(int nhist) {
+  int c = 64;
+  while (c > 1 && (size_t)c * hist_stride(nhist) * 4 > (size_t)kHistLds) c >>= 1;
+  return c;
+}
+
+__device__ __forceinline__ void hist_count(uint32_t* mine, int32_t n, bool keep, int nhist) {
+  if (keep && (uint32_t)n < (uint32_t)nhist) atomicAdd(&mine[n], 1u);
+}
+
+// VEC: counts and mask read four cells at a time (cells % 4 == 0, 16-byte aligned maps).
+template <bool VEC>
 __global__ void __launch_bounds__(kCicThreads) k_cic_histogram(const int32_t* __restrict__ counts,
                                                                const float* __restrict__ mask, int64_t cells,
                                                                int nhist, unsigned long long* __restrict__ hist) {
-  extern __shared__ uint32_t bins[];  // ncopy copies of nhist counters
-  const int ncopy = nhist <= kWaveCopyBins ? kCicWaves : 1;
+  extern __shared__ uint32_t bins[];
+  const int ncopy = hist_copies(nhist), stride_b = hist_stride(nhist);
+  const int total = ncopy * stride_b;
   const int r = blockIdx.y;
-  for (int i = threadIdx.x; i < ncopy * nhist; i += kCicThreads) bins[i] = 0;
+  for (int i = threadIdx.x; i < total; i += kCicThreads) bins[i] = 0;
   __syncthreads();
-  uint32_t* mine = bins + (ncopy == 1 ? 0 : (threadIdx.x >> 6) * nhist);
+  uint32_t* mine = bins + (threadIdx.x & (ncopy - 1)) * stride_b;
   const int32_t* c = counts + (int64_t)r * cells;
   const int64_t stride = (int64_t)gridDim.x * kCicThreads;
-  for (int64_t i = blockIdx.x * (int64_t)kCicThreads + threadIdx.x; i < cells; i += stride) {
-    const int32_t n = c[i];
-    const bool keep = mask == nullptr || mask[i] != 0.0f;
-    if (keep && (uint32_t)n < (uint32_t)nhist) atomicAdd(&mine[n], 1u);
+  if (VEC) {
+    const int64_t q = cells >> 2;
+    const int4* c4 = reinterpret_cast<const int4*>(c);
+    const float4* m4 = reinterpret_cast<const float4*>(mask);
+    for (int64_t i = blockIdx.x * (int64_t)kCicThreads + threadIdx.x; i < q; i += stride) {
+      const int4 n = c4[i];
+      const float4 f = mask ? m4[i] : make_float4(1.0f, 1.0f, 1.0f, 1.0f);
+      hist_count(mine, n.x, f.x != 0.0f, nhist);
+      hist_count(mine, n.y, f.y != 0.0f, nhist);
+      hist_count(mine, n.z, f.z != 0.0f, nhist);
+      hist_count(mine, n.w, f.w != 0.0f, nhist);
+    }
+  } else {
+    for (int64_t i = blockIdx.x * (int64_t)kCicThreads + threadIdx.x; i < cells; i += stride)
+      hist_count(mine, c[i], mask == nullptr || mask[i] != 0.0f, nhist);
   }
   __syncthreads();
   unsigned long long* h = hist + (int64_t)r * nhist;
   for (int i = threadIdx.x; i < nhist; i += kCicThreads) {
     uint32_t t = 0;
-    for (int w = 0; w < ncopy; ++w) t += bins[w * nhist + i];
+    for (int k = 0; k < ncopy; ++k) t += bins[k * stride_b + i];
     if (t) atomicAdd(&h[i], (unsigned long long)t);
   }
 }
@@ -61,34 +88,52 @@ __global__ void k_zero_i64(unsigned long long* p, int64_t n) {
   if (i < n) p[i] = 0;
 }
 
-// Root of c e^A + A = d (eq. As with c = N_bar f sigma_A^2, d = sigma_A^2 (N - 1/2)).
-// With A = d - w the equation becomes w e^w = c e^d, so w is the principal Lambert
-// function of x = c e^d; it is found from y = ln x by Newton's method on w + ln w = y
-// (concave and increasing in w), which stays positive and converges quadratically from
-// the starting points used: x / (1 + x) for y <= 1, the asymptotic y - ln y + ln y / y
-// above.  For y < -36, W(x) = x to FP64 precision.
-__device__ __forceinline__ double astar_solve(int32_t n, double c, double s2) {
+// Root of g(A) = c e^A + A - d = 0 (eq. As with c = N_bar f sigma_A^2, d = sigma_A^2 (N - 1/2)).
+// With A = d - w the equation becomes w e^w = c e^d, so w is the principal Lambert function
+// of x = c e^d.  An FP32 estimate of w comes from Newton's method on w + ln w = y, y = ln x
+// (concave and increasing in w, so the iterates stay positive), started at x / (1 + x) for
+// y <= 1 and at the asymptotic y - ln y + ln y / y above, with hardware log / exp.  The root
+// is then refined in FP64 by Halley's method on g itself (g' = c e^A + 1, g'' = c e^A), whose
+// error contracts as e -> K e^3 with |K| <= 1/4, until a step falls below 2^-20 max(1, |A|).
+// For large d the FP32 estimate of A = d - w loses digits to cancellation, so it is first
+// replaced by two steps of A = ln(d - A) - ln c, a contraction by 1 / (d - A) there.
+// lnb = ln(N_bar sigma_A^2) in FP64; the FP32 estimate takes ln c = lnb + ln f.
+__device__ __forceinline__ double astar_solve(int32_t n, float f, double lnb, double c, double s2) {
   const double d = s2 * ((double)n - 0.5);
-  const double y = log(c) + d;
-  double w;
-  if (y < -36.0) {
-    w = exp(y);
+  // (a denormal f is scaled by 2^64 first: the hardware log may flush denormals to zero)
+  const float lf = f < 0x1p-126f ? __logf(f * 0x1p64f) - 44.3614196f : __logf(f);
+  const float y = (float)lnb + lf + (float)d;
+  float w;
+  if (y < -20.0f) {
+    w = __expf(y);  // W(x) = x (1 - x + ...) with x below 2e-9
   } else {
-    if (y <= 1.0) {
-      const double x = exp(y);
-      w = x / (1.0 + x);
+    if (y <= 1.0f) {
+      const float x = __expf(y);
+      w = x * __builtin_amdgcn_rcpf(1.0f + x);
     } else {
-      const double ly = log(y);
-      w = y - ly + ly / y;
+      const float ly = __logf(y);
+      w = y - ly + ly * __builtin_amdgcn_rcpf(y);
     }
-    for (int it = 0; it < 16; ++it) {
-      const double wn = w * (1.0 + y - log(w)) / (1.0 + w);
-      const bool done = fabs(wn - w) <= 0x1p-50 * wn;
-      w = wn;
-      if (done) break;
-    }
+    // the starting error is below 0.3 and contracts as e -> e^2 / 4 (or faster): three steps
+    // reach FP32 rounding
+#pragma unroll
+    for (int it = 0; it < 3; ++it) w = w * (1.0f + y - __logf(w)) * __builtin_amdgcn_rcpf(1.0f + w);
   }
-  return d - w;
+  double a = d - (double)w;
+  if (d > 256.0 && w > 0.0f) {
+    const double lc = log(c);
+    a = log(d - a) - lc;
+    a = log(d - a) - lc;
+  }
+  for (int it = 0; it < 12; ++it) {
+    const double e = c * exp(a);
+    const double g = e + a - d;
+    const double g1 = e + 1.0;
+    const double step = 2.0 * g * g1 / (2.0 * g1 * g1 - g * e);
+    a -= step;
+    if (fabs(step) <= 0x1p-20 * fmax(1.0, fabs(a))) break;
+  }
+  return a;
 }
 
 // MODE 0: write A* (0 on masked cells).  MODE 1: per-workgroup sums of A* and of the
@@ -97,7 +142,7 @@ __device__ __forceinline__ double astar_solve(int32_t n, double c, double s2) {
 template <typename T, int MODE>
 __global__ void __launch_bounds__(kCicThreads) k_astar(const int32_t* __restrict__ counts,
                                                        const float* __restrict__ mask, int64_t cells,
-                                                       double nbar, double s2, T* __restrict__ out,
+                                                       double nbar, double lnb, double s2, T* __restrict__ out,
                                                        double* __restrict__ partials,
                                                        const double* __restrict__ mean) {
   const int r = blockIdx.y;
@@ -109,7 +154,7 @@ __global__ void __launch_bounds__(kCicThreads) k_astar(const int32_t* __restrict
     const float f = mask ? mask[i] : 1.0f;
     double a = 0.0;
     if (f != 0.0f) {
-      a = astar_solve(c[i], (nbar * (double)f) * s2, s2);
+      a = astar_solve(c[i], f, lnb, (nbar * (double)f) * s2, s2);
       acc += a;
       nk += 1.0;
       a -= m;
@@ -167,7 +212,8 @@ hipError_t astar_launch(const int32_t* counts, const float* mask, int64_t cells,
   for (int64_t r0 = 0; r0 < count; r0 += kGridY) {
     const int64_t nr = count - r0 < kGridY ? count - r0 : kGridY;
     hipLaunchKernelGGL((k_astar<T, MODE>), dim3((unsigned)bx, (unsigned)nr), dim3(kCicThreads), 0, s,
-                       counts + r0 * cells, mask, cells, nbar, s2, MODE == 1 ? nullptr : out + r0 * cells,
+                       counts + r0 * cells, mask, cells, nbar, log(nbar * s2), s2,
+                       MODE == 1 ? nullptr : out + r0 * cells,
                        MODE == 1 ? partials + r0 * bx * 2 : nullptr, MODE == 2 ? mean + r0 : nullptr);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
@@ -200,12 +246,18 @@ hipError_t launch_cic_histogram(const int32_t* counts, const float* mask, int64_
   hipLaunchKernelGGL(k_zero_i64, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, hist, n);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  const int64_t bx = blocks_per_map(cells);
-  const size_t lds = sizeof(uint32_t) * (nhist <= kWaveCopyBins ? kCicWaves : 1) * (size_t)nhist;
+  const size_t lds = sizeof(uint32_t) * (size_t)hist_copies(nhist) * (size_t)hist_stride(nhist);
+  const bool vec = (cells & 3) == 0 && (reinterpret_cast<uintptr_t>(counts) & 15) == 0 &&
+                   (reinterpret_cast<uintptr_t>(mask) & 15) == 0;
+  const int64_t bx = blocks_per_map(vec ? cells / 4 : cells);
   for (int64_t r0 = 0; r0 < count; r0 += kGridY) {
     const int64_t nr = count - r0 < kGridY ? count - r0 : kGridY;
-    hipLaunchKernelGGL(k_cic_histogram, dim3((unsigned)bx, (unsigned)nr), dim3(kCicThreads), lds, s,
-                       counts + r0 * cells, mask, cells, nhist, hist + r0 * nhist);
+    if (vec)
+      hipLaunchKernelGGL(k_cic_histogram<true>, dim3((unsigned)bx, (unsigned)nr), dim3(kCicThreads), lds, s,
+                         counts + r0 * cells, mask, cells, nhist, hist + r0 * nhist);
+    else
+      hipLaunchKernelGGL(k_cic_histogram<false>, dim3((unsigned)bx, (unsigned)nr), dim3(kCicThreads), lds, s,
+                         counts + r0 * cells, mask, cells, nhist, hist + r0 * nhist);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
   }

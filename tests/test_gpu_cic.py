@@ -78,9 +78,15 @@ def test_astar_matches_oracle(ce, n, masked, prec, subtract):
     print("astar", n, masked, prec, subtract, flush=True)
     count = 3
     mask = workloads.survey_mask(n, seed=2) if masked else None
-    # a large count and N = 0 everywhere in the first row of the first map
-    c = seeded_counts(count, n, 4, mask=mask, extra=[(5, 5000)] + [(i, 0) for i in range(n[-1])])
     cells = int(np.prod(n))
+    if masked:
+        # tiny surface fractions, down to an FP32 denormal
+        flat = mask.reshape(-1)
+        for i, v in zip((cells // 3, cells // 3 + 1, cells // 3 + 2, cells // 3 + 3), (1e-20, 1e-38, 1.4e-45, 1e-3)):
+            flat[i] = v
+    # large counts (up to the int32 maximum) and N = 0 everywhere in the first row of the first map
+    big = [(cells // 3 + k, v) for k, v in enumerate((5000, 10 ** 6, 2 ** 31 - 1, 77))]
+    c = seeded_counts(count, n, 4, mask=mask, extra=big + [(5, 5000)] + [(i, 0) for i in range(n[-1])])
     dt = torch.float64 if prec == 1 else torch.float32
     out = torch.full((count * cells,), 7.0, dtype=dt, device="cuda")
     mean = torch.empty(count, dtype=torch.float64, device="cuda")
