@@ -11,6 +11,9 @@ Every function follows the definition in Carron, Wolk & Szapudi (2014),
 
 * ``embedding``  -- Sec. 2: lag table on the doubled grid, the discrete
   ad-hoc spectrum (eq. Specd) and its non-negativity condition (eq. condition).
+* ``filtered``   -- Sec. 3.1 and App. A: the square top-hat cell average of a
+  two-point function (eqs. exactformula, xibar, CoolEq) and the lognormal
+  target ln(1 + omega) (eq. Lncov), applied to the lag table by ``embedding``.
 * ``fields``     -- Sec. 2: independent Gaussian modes with variance set by the
   ad-hoc spectrum (eq. Papos2), inverse DFT, restriction to the survey grid.
 * ``lognormal_poisson`` -- Sec. 3.1: lognormal density (eq. Lncov, step i) and
@@ -26,4 +29,4 @@ Every function follows the definition in Carron, Wolk & Szapudi (2014),
 Parity status of each function is listed in its module header.
 """
 
-from . import philox, embedding, fields, lognormal_poisson, pk, cic  # noqa: F401
+from . import philox, embedding, filtered, fields, lognormal_poisson, pk, cic  # noqa: F401

@@ -80,17 +80,32 @@ def embedding_shape(n):
 
 
 def lag_octant(n, h, xi):
-    """xi on the lag octant l_i in [0, N_i] (shape (N_0+1, ..., N_{d-1}+1))."""
+    """xi on the lag octant l_i in [0, N_i] (shape (N_0+1, ..., N_{d-1}+1)).
+
+    Optional flags of the spec: ``cell_average`` (xi is the unfiltered omega; the table holds
+    its square top-hat cell average, App. A) and ``lognormal`` (the table holds
+    ln(1 + value), eq. Lncov), applied in that order.
+    """
     n = tuple(int(x) for x in n)
     if xi["kind"] == "table":
+        if xi.get("cell_average"):
+            raise ValueError("the cell average needs an analytic two-point function")
         tab = np.asarray(xi["table"], dtype=np.float64)
         if tab.shape != tuple(x + 1 for x in n):
             raise ValueError("table must have shape (N_i + 1)")
-        return tab.copy()
-    axes = np.meshgrid(*[h[i] * np.arange(n[i] + 1, dtype=np.float64) for i in range(len(n))],
-                       indexing="ij")
-    r = np.sqrt(sum(a * a for a in axes))
-    return eval_xi(xi, r)
+        out = tab.copy()
+    elif xi.get("cell_average"):
+        from . import filtered
+        out = filtered.cell_averaged_octant(n, h, lambda r: float(eval_xi(xi, r)))
+    else:
+        axes = np.meshgrid(*[h[i] * np.arange(n[i] + 1, dtype=np.float64) for i in range(len(n))],
+                           indexing="ij")
+        r = np.sqrt(sum(a * a for a in axes))
+        out = eval_xi(xi, r)
+    if xi.get("lognormal"):
+        from . import filtered
+        out = filtered.lognormal_target(out)
+    return out
 
 
 def lag_table(n, h, xi):
