@@ -64,20 +64,38 @@ typedef struct {
   double h[3];
 } ce_geometry;
 
-/* Two-point function xi of the Gaussian field (isotropic kinds use r = |x| in units of h).
+/* Transforms applied to xi when its lag table is built (flags, combinable; applied in this order).
+ * CE_XI_CELL_AVERAGE: xi is the unfiltered isotropic two-point function omega of the density
+ *   contrast and the table holds its average over pairs of cells, the square top-hat filtered
+ *   function of App. A: the overlap integral eq. exactformula (Gauss-Legendre, ~1e-14 relative)
+ *   for lags shorter than 15 max(h_0, h_1), the derivative expansion eq. CoolEq (second order,
+ *   5-point differences in ln r of step 2e-3, written for rectangular cells) beyond.  2-D maps
+ *   and the EXP / POWEXP kinds only (CE_E_UNSUPPORTED otherwise).
+ * CE_XI_LOGNORMAL: the table holds ln(1 + value) (eq. Lncov): the Gaussian field is the
+ *   log-density A, and rho = exp(A - sigma_A^2/2) has covariance `value` (sigma_A^2 is the
+ *   plan's sigma2).  A value <= -1 has no logarithm: the plan is rejected (CE_E_NOT_PSD). */
+typedef enum {
+  CE_XI_CELL_AVERAGE = 1,
+  CE_XI_LOGNORMAL = 2
+} ce_xi_transform;
+
+/* Two-point function xi of the Gaussian field; isotropic kinds take the distance r = |x|,
+ * x = (l_0 h_0, ..., l_{d-1} h_{d-1}).
  * CE_XI_TABLE: host FP64 array of xi at lags (l_0 h_0, ..., l_{d-1} h_{d-1}) for
  * l_i in [0, N_i], row-major, shape (N_0+1) x ... ; it must describe a function that is
- * even in every axis.  The table is copied during ce_plan_embedding. */
+ * even in every axis.  The table is copied during ce_plan_embedding.
+ * transform: 0 or a combination of ce_xi_transform flags. */
 typedef struct {
   int32_t kind;
   double p[4];
   const double* table;
+  int32_t transform;
 } ce_xi;
 
 typedef struct {
   double lambda_min;     /* smallest circulant eigenvalue before clamping (DFT of the lag table) */
   double lambda_max;     /* largest */
-  double sigma2;         /* xi(0): variance of each cell */
+  double sigma2;         /* the lag table at 0 (xi(0) after its transforms): variance of each cell */
   int64_t n_negative;    /* eigenvalues below zero (full embedding grid, before clamping) */
   int64_t n_clamped;     /* eigenvalues set to zero (= n_negative when the plan is accepted) */
   size_t device_bytes;   /* device memory held by the plan */
@@ -152,12 +170,20 @@ ce_status ce_ctx_profile_read(ce_ctx* ctx, int32_t max, char* names, double* tot
  * lambda_max the plan is rejected with CE_E_NOT_PSD and *out is left NULL; otherwise negative
  * values are clamped to 0.  neg_tol < 0 selects the default 1e-13.  The plan keeps
  * sqrt(lambda / M^d) on the eigenvalue octant in `precision` on the device; `info` (nullable)
- * is filled in both cases.  Synchronous.  Errors: CE_E_INVALID, CE_E_UNSUPPORTED, CE_E_OOM,
+ * is filled in both cases; a non-finite eigenvalue (a table value <= -1 under CE_XI_LOGNORMAL, an
+ * infinite xi) is reported as lambda_min = -inf and rejects the plan.  Synchronous.  Errors: CE_E_INVALID, CE_E_UNSUPPORTED, CE_E_OOM,
  * CE_E_NOT_PSD, CE_E_DEVICE. */
 ce_status ce_plan_embedding(ce_ctx* ctx, const ce_geometry* geom, const ce_xi* xi,
                             ce_precision precision, double neg_tol, ce_plan** out,
                             ce_plan_info* info);
 void ce_plan_release(ce_plan* plan);
+
+/* The lag octant a plan for (geom, xi) starts from: xi, transformed as xi->transform asks, at
+ * lags l_i in [0, N_i] (row-major (N_0+1) x ... doubles, device buffer `out`, caller owns).
+ * Asynchronous on `stream` (a CE_XI_TABLE is read before the call returns).
+ * Errors: CE_E_INVALID, CE_E_UNSUPPORTED, CE_E_DEVICE. */
+ce_status ce_xi_lag_octant(ce_ctx* ctx, const ce_geometry* geom, const ce_xi* xi, double* out,
+                           void* stream);
 ce_status ce_plan_get_info(const ce_plan* plan, ce_plan_info* info);
 
 /* Copy the FP64 eigenvalue octant lambda(q), q_i in [0, N_i] (before clamping), row-major

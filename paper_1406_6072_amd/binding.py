@@ -24,6 +24,7 @@ _lib = ctypes.CDLL(LIB_PATH)
 OK, E_INVALID, E_NOT_PSD, E_OOM, E_UNSUPPORTED, E_DEVICE, E_SAMPLER = range(7)
 F32, F64 = 0, 1
 XI_TABLE, XI_EXP, XI_POWEXP = 0, 1, 2
+XI_CELL_AVERAGE, XI_LOGNORMAL = 1, 2
 MAP_FIELD, MAP_COUNTS_DELTAG = 0, 1
 
 c_void_p = ctypes.c_void_p
@@ -36,7 +37,7 @@ class Geometry(ctypes.Structure):
 
 
 class Xi(ctypes.Structure):
-    _fields_ = [("kind", c_i32), ("p", c_f64 * 4), ("table", ctypes.POINTER(c_f64))]
+    _fields_ = [("kind", c_i32), ("p", c_f64 * 4), ("table", ctypes.POINTER(c_f64)), ("transform", c_i32)]
 
 
 class PlanInfo(ctypes.Structure):
@@ -86,6 +87,8 @@ _ctx_profile_read = _sig("ce_ctx_profile_read", c_i32, c_void_p, c_i32, c_void_p
 _plan_embedding = _sig("ce_plan_embedding", c_i32, c_void_p, ctypes.POINTER(Geometry), ctypes.POINTER(Xi), c_i32,
                        c_f64, ctypes.POINTER(c_void_p), ctypes.POINTER(PlanInfo))
 _plan_release = _sig("ce_plan_release", None, c_void_p)
+_xi_lag_octant = _sig("ce_xi_lag_octant", c_i32, c_void_p, ctypes.POINTER(Geometry), ctypes.POINTER(Xi), c_void_p,
+                      c_void_p)
 _plan_get_info = _sig("ce_plan_get_info", c_i32, c_void_p, ctypes.POINTER(PlanInfo))
 _plan_eigenvalues = _sig("ce_plan_eigenvalues", c_i32, c_void_p, c_void_p, c_void_p)
 _generate_fields = _sig("ce_generate_fields", c_i32, c_void_p, c_void_p, c_u64, c_u32, c_u64, c_i64, c_void_p,
@@ -123,7 +126,7 @@ _debug_noise = _sig("ce_debug_noise", c_i32, c_void_p, c_u64, c_u32, c_u64, c_vo
 
 EXPORTED = ["ce_status_string", "ce_version", "ce_ctx_create", "ce_ctx_destroy", "ce_ctx_check", "ce_ctx_trim",
             "ce_ctx_set_option", "ce_ctx_set_profiling", "ce_ctx_profile_read",
-            "ce_plan_embedding", "ce_plan_release", "ce_plan_get_info", "ce_plan_eigenvalues",
+            "ce_plan_embedding", "ce_plan_release", "ce_plan_get_info", "ce_plan_eigenvalues", "ce_xi_lag_octant",
             "ce_generate_fields", "ce_lognormal_poisson", "ce_estimate_pk", "ce_pk_covariance",
             "ce_cic_histogram", "ce_astar_map",
             "ce_pipeline_run", "ce_pipeline_run_masked", "ce_pipeline_run_batch", "ce_pipeline_graph_create", "ce_pipeline_graph_launch",
@@ -210,6 +213,7 @@ def xi_spec(xi):
         x.table = keep.ctypes.data_as(ctypes.POINTER(c_f64))
     else:
         raise ValueError("unknown xi kind %r" % kind)
+    x.transform = (XI_CELL_AVERAGE if xi.get("cell_average") else 0) | (XI_LOGNORMAL if xi.get("lognormal") else 0)
     return x, keep
 
 
@@ -304,6 +308,18 @@ def plan_embedding(ctx, n, h, xi, precision, neg_tol=-1.0):
         raise NotPSDError(st, "ce_plan_embedding", _info_dict(pi))
     _check(st, "ce_plan_embedding")
     return Plan(out, g.n[:g.ndim], g.h[:g.ndim], int(precision), _info_dict(pi))
+
+
+def xi_lag_octant(ctx, n, h, xi, out, stream=None):
+    """The (transformed) lag octant of xi on the grid (n, h) into a float64 CUDA tensor."""
+    g = geometry(n, h)
+    x, keep = xi_spec(xi)
+    noct = 1
+    for v in n:
+        noct *= int(v) + 1
+    _check(_xi_lag_octant(ctx, ctypes.byref(g), ctypes.byref(x), _ptr(out, torch.float64, noct, "out"),
+                          _stream(stream)), "ce_xi_lag_octant")
+    del keep
 
 
 def plan_release(plan):

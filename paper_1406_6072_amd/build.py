@@ -11,7 +11,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libcefield.so")
-SOURCES = ["ce_kernels.hip", "ce_cic.hip", "ce_api.cpp", "ce_serve.cpp"]
+SOURCES = ["ce_kernels.hip", "ce_cic.hip", "ce_xi.hip", "ce_api.cpp", "ce_serve.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-result",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

@@ -388,6 +388,79 @@ ce_status check_geometry(const ce_geometry* g) {
   return CE_OK;
 }
 
+ce_status check_xi(const ce_geometry* g, const ce_xi* xi) {
+  if (xi->kind == CE_XI_TABLE) {
+    if (!xi->table) return CE_E_INVALID;
+  } else if (xi->kind == CE_XI_EXP || xi->kind == CE_XI_POWEXP) {
+    if (!(xi->p[1] > 0) || !std::isfinite(xi->p[0])) return CE_E_INVALID;
+  } else {
+    return CE_E_INVALID;
+  }
+  if (xi->transform & ~(CE_XI_CELL_AVERAGE | CE_XI_LOGNORMAL)) return CE_E_INVALID;
+  if ((xi->transform & CE_XI_CELL_AVERAGE) && (g->ndim != 2 || xi->kind == CE_XI_TABLE)) return CE_E_UNSUPPORTED;
+  return CE_OK;
+}
+
+// Gauss-Legendre rule of kCellQuadNodes nodes on [0, 1] mapped by u = (1 - cos(pi t)) / 2 (nodes
+// clustered at both ends), with the cell-overlap weight folded in: a = w (pi/2) sin(pi t) (1 - u).
+// Nodes by Newton's method on the Legendre recurrence in long double.
+const CellQuad& cell_quad() {
+  static const CellQuad q = [] {
+    CellQuad c{};
+    const int n = kCellQuadNodes;
+    const long double pi = 3.14159265358979323846264338327950288L;
+    for (int i = 0; i < n; ++i) {
+      long double x = std::cos(pi * (i + 0.75L) / (n + 0.5L));
+      long double dp = 1;
+      for (int it = 0; it < 100; ++it) {
+        long double p0 = 1, p1 = x;
+        for (int k = 2; k <= n; ++k) {
+          const long double p2 = ((2 * k - 1) * x * p1 - (k - 1) * p0) / k;
+          p0 = p1;
+          p1 = p2;
+        }
+        dp = n * (x * p1 - p0) / (x * x - 1);
+        const long double dx = p1 / dp;
+        x -= dx;
+        if (std::fabs(dx) < 1e-19L) break;
+      }
+      const long double w = 2 / ((1 - x * x) * dp * dp);  // weight on [-1, 1]
+      const long double t = (x + 1) / 2;
+      const long double u = (1 - std::cos(pi * t)) / 2;
+      c.u[i] = (double)u;
+      c.a[i] = (double)((w / 2) * (pi / 2) * std::sin(pi * t) * (1 - u));
+    }
+    return c;
+  }();
+  return q;
+}
+
+constexpr double kNearCells = 15.0;   // direct overlap integral below this many cell sides
+constexpr double kLogStep = 2e-3;     // step in ln r of the finite differences of eq. CoolEq
+
+// The (transformed) lag octant of xi on the device buffer `out`, asynchronously on s.
+hipError_t build_lag_octant(const ce_geometry* geom, const ce_xi* xi, double* out, hipStream_t s) {
+  int32_t O[3] = {1, 1, 1};
+  double h[3] = {1, 1, 1};
+  int64_t noct = 1;
+  for (int i = 0; i < geom->ndim; ++i) {
+    O[i] = (int32_t)geom->n[i] + 1;
+    h[i] = geom->h[i];
+    noct *= O[i];
+  }
+  const double p[4] = {xi->p[0], xi->p[1], xi->p[2], xi->p[3]};
+  hipError_t e;
+  if (xi->kind == CE_XI_TABLE)
+    e = hipMemcpyAsync(out, xi->table, sizeof(double) * (size_t)noct, hipMemcpyHostToDevice, s);
+  else if (xi->transform & CE_XI_CELL_AVERAGE)
+    e = launch_lag_cell_average(O, h, xi->kind, p, cell_quad(), kNearCells, kLogStep, out, s);
+  else
+    e = launch_lag_octant(geom->ndim, O, h, xi->kind, p, out, s);
+  if (e != hipSuccess) return e;
+  if (xi->transform & CE_XI_LOGNORMAL) e = launch_log1p(out, noct, s);
+  return e;
+}
+
 bool is_cubic(const ce_geometry* g) {
   for (int i = 1; i < g->ndim; ++i)
     if (g->n[i] != g->n[0] || g->h[i] != g->h[0]) return false;
@@ -617,15 +690,7 @@ ce_status ce_plan_embedding(ce_ctx* ctx, const ce_geometry* geom, const ce_xi* x
   *out = nullptr;
   if (precision != CE_F32 && precision != CE_F64) return CE_E_INVALID;
   CE_TRY(check_geometry(geom));
-  if (xi->kind == CE_XI_TABLE) {
-    if (!xi->table) return CE_E_INVALID;
-  } else if (xi->kind == CE_XI_EXP) {
-    if (!(xi->p[1] > 0)) return CE_E_INVALID;
-  } else if (xi->kind == CE_XI_POWEXP) {
-    if (!(xi->p[1] > 0)) return CE_E_INVALID;
-  } else {
-    return CE_E_INVALID;
-  }
+  CE_TRY(check_xi(geom, xi));
   if (neg_tol < 0) neg_tol = kDefaultNegTol;
   std::lock_guard<std::mutex> lock(ctx->mu);
   CE_HIP(hipSetDevice(ctx->device));
@@ -664,14 +729,11 @@ ce_status ce_plan_embedding(ce_ctx* ctx, const ce_geometry* geom, const ce_xi* x
     return e;
   };
 
-  // lag octant c(l) = xi(h l)  (eq. grid: lags -N..N-1, minimum image)
-  if (xi->kind == CE_XI_TABLE) {
-    if (hipMemcpyAsync(bufA, xi->table, plan->bytes_lam, hipMemcpyHostToDevice, s) != hipSuccess)
-      return fail(CE_E_DEVICE);
-  } else {
-    double p[4] = {xi->p[0], xi->p[1], xi->p[2], xi->p[3]};
-    if (launch_lag_octant(geom->ndim, O, h, xi->kind, p, bufA, s) != hipSuccess) return fail(CE_E_DEVICE);
-  }
+  // lag octant c(l) = xi(h l)  (eq. grid: lags -N..N-1, minimum image), transformed
+  double sigma2 = 0;
+  if (build_lag_octant(geom, xi, bufA, s) != hipSuccess ||
+      hipMemcpyAsync(&sigma2, bufA, sizeof(double), hipMemcpyDeviceToHost, s) != hipSuccess)
+    return fail(CE_E_DEVICE);
   // eq. Specd: DFT over the doubled grid, separable; the lag table is even in each
   // axis so each axis is a DCT-I of the octant (length-M FFT of the even extension).
   double* src = bufA;
@@ -712,8 +774,7 @@ ce_status ce_plan_embedding(ce_ctx* ctx, const ce_geometry* geom, const ce_xi* x
     lmin = std::min(lmin, hs[2 * i]);
     lmax = std::max(lmax, hs[2 * i + 1]);
   }
-  // xi(0): the first element of the lag octant
-  const double sigma2 = xi->kind == CE_XI_TABLE ? xi->table[0] : xi->p[0];
+  // sigma2: the first element of the lag octant (copied above, before the synchronisation)
   ce_plan_info pi{};
   pi.lambda_min = lmin;
   pi.lambda_max = lmax;
@@ -742,6 +803,18 @@ ce_status ce_plan_embedding(ce_ctx* ctx, const ce_geometry* geom, const ce_xi* x
   plan->info = pi;
   if (info) *info = pi;
   *out = plan.release();
+  return CE_OK;
+}
+
+ce_status ce_xi_lag_octant(ce_ctx* ctx, const ce_geometry* geom, const ce_xi* xi, double* out, void* stream) {
+  if (!ctx || !geom || !xi || !out) return CE_E_INVALID;
+  CE_TRY(check_geometry(geom));
+  CE_TRY(check_xi(geom, xi));
+  std::lock_guard<std::mutex> lock(ctx->mu);
+  CE_HIP(hipSetDevice(ctx->device));
+  const hipStream_t s = as_stream(stream);
+  CE_HIP(build_lag_octant(geom, xi, out, s));
+  if (xi->kind == CE_XI_TABLE) CE_HIP(hipStreamSynchronize(s));  // the host table is read before returning
   return CE_OK;
 }
 

@@ -161,6 +161,16 @@ hipError_t launch_debug_philox(uint32_t k0, uint32_t k1, const uint32_t* ctr, in
                                hipStream_t s);
 hipError_t launch_debug_noise(int prec, const NoiseArgs& n, uint64_t pair, int64_t cells, void* out, hipStream_t s);
 hipError_t launch_zero_u64(unsigned long long* p, int64_t n, hipStream_t s);
+// transformed lag tables (ce_xi.hip).  Quadrature of one axis of a quadrant of the cell-overlap
+// integral: nodes u in (0, 1) and weights a = (Gauss-Legendre weight x du/dt) (1 - u).
+constexpr int kCellQuadNodes = 48;
+struct CellQuad {
+  double u[kCellQuadNodes];
+  double a[kCellQuadNodes];
+};
+hipError_t launch_lag_cell_average(const int32_t* O, const double* h, int kind, const double* p, const CellQuad& q,
+                                   double near_cells, double log_step, double* out, hipStream_t s);
+hipError_t launch_log1p(double* p, int64_t n, hipStream_t s);
 // counts-in-cells (ce_cic.hip)
 hipError_t launch_cic_histogram(const int32_t* counts, const float* mask, int64_t cells, int64_t count, int nhist,
                                 unsigned long long* hist, hipStream_t s);

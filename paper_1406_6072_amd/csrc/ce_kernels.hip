@@ -404,6 +404,10 @@ __global__ void k_lambda_stats(const double* __restrict__ lam, int ndim, int32_t
   for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < n;
        idx += (int64_t)gridDim.x * blockDim.x) {
     const double v = lam[idx];
+    if (!isfinite(v)) {  // a NaN or infinite eigenvalue: report the bounds as -inf / +inf
+      mn = -INFINITY;
+      mx = INFINITY;
+    }
     mn = fmin(mn, v);
     mx = fmax(mx, v);
     if (v < 0) {

@@ -71,6 +71,7 @@ std::string plan_key(const ce_request& r, const std::vector<double>& table) {
   }
   put(&r.xi.kind, sizeof(r.xi.kind));
   put(r.xi.p, sizeof(r.xi.p));
+  put(&r.xi.transform, sizeof(r.xi.transform));
   put(&r.precision, sizeof(r.precision));
   if (!table.empty()) put(table.data(), table.size() * sizeof(double));
   return k;

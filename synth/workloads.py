@@ -27,6 +27,12 @@ WORKLOADS = {
     # 3-D 256^3 survey in a 512^3 embedding, FP32 fields, 8 realizations
     "volume_3d": dict(n=(256, 256, 256), h=(1.0, 1.0, 1.0), xi=_powexp(2.0, 5.0, 200.0),
                       precision="f32", realizations=8, nbar=0.1, nbins=64, seed=0, request_id=0),
+    # the paper's model input: the unfiltered angular omega (slope -0.7, cell units), averaged
+    # over the cells and taken through ln(1 + omega) (cell variance 0.14, sigma_A^2 = 0.131)
+    "paper_128_omega": dict(n=(128, 128), h=(1.0, 1.0),
+                            xi=dict(kind="powexp", sigma2=0.185, r0=1.0, gamma=0.7, rc=300.0,
+                                    cell_average=True, lognormal=True),
+                            precision="f32", realizations=64, nbar=9.68, nbins=20, seed=0, request_id=0),
     # the paper's own geometry: 128^2 cells in a 256^2 embedding
     "paper_128": dict(n=(128, 128), h=(1.0, 1.0), xi=_powexp(0.131, 2.0, 300.0),
                       precision="f32", realizations=64, nbar=9.68, nbins=20, seed=0, request_id=0),
