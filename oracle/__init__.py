@@ -20,7 +20,9 @@ Every function follows the definition in Carron, Wolk & Szapudi (2014),
   Poisson sampling of counts (eq. sampling).
 * ``pk``         -- Sec. 3.2: power-spectrum estimator (eq. Def spec) on the
   galaxy contrast with the estimated intensity (eq. Estim); spectrum
-  covariance and the normalised matrix of eq. cuminfo.
+  covariance, the normalised matrix of eq. cuminfo and the cumulative information.
+* ``kspace``     -- Sec. 3.3: the k-space sampling comparator, a periodic box with the
+  modes of the continuous spectrum (eq. Periodicboxmodes), DC zeroed.
 * ``cic``        -- Sec. 3.4: counts-in-cells histogram, its Poisson-lognormal
   prediction, and the A* map (eq. As).
 * ``philox``     -- the counter-based generator that supplies the noise
@@ -29,4 +31,4 @@ Every function follows the definition in Carron, Wolk & Szapudi (2014),
 Parity status of each function is listed in its module header.
 """
 
-from . import philox, embedding, filtered, fields, lognormal_poisson, pk, cic  # noqa: F401
+from . import philox, embedding, filtered, fields, lognormal_poisson, pk, cic, kspace  # noqa: F401

@@ -28,8 +28,9 @@ Readings taken here:
 
 Parity: pinned by Parseval's identity, the single-plane-wave closed form, the
 white-noise level, a brute-force shell enumeration in Python integers, the
-closed-form expected survey power of a Gaussian field, and numpy.cov.  See
-``tests/test_oracle_pk.py``.
+closed-form expected survey power of a Gaussian field, and numpy.cov; the cumulative
+information by its diagonal closed form (half the number of modes for Gaussian shells), a
+2x2 closed form and its scaling.  See ``tests/test_oracle_pk.py``.
 """
 
 import numpy as np
@@ -125,3 +126,10 @@ def covariance(pk):
     second = (pk.T @ pk) / R
     cpaper = second / np.outer(mean, mean) - 1.0
     return cov, cpaper
+
+
+def cumulative_information(C):
+    """I(<= l_k) = sum of the elements of the inverse of the leading k x k block of the
+    normalised covariance C, for k = 1 .. nb (eq. cuminfo)."""
+    C = np.asarray(C, dtype=np.float64)
+    return np.array([np.linalg.inv(C[:k, :k]).sum() for k in range(1, C.shape[0] + 1)])
