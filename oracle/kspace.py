@@ -24,13 +24,14 @@ Readings taken here:
   (ln(1 + omega)); the cell average of App. A does not enter (the k-space method samples
   the continuous field at the cell centres).
 * lambda(0) = 0 (the DC mode is zeroed, as stated).
-* The 2-D transform is integrated between consecutive zeros of J0 (scipy) until the
-  exponential cut-off of xi has made the remainder negligible; the 3-D one by quadpack's
-  Fourier-integral routine (weight sin(k r)).
+* Both transforms are integrated between consecutive zeros of the oscillating factor (J0 from
+  scipy in 2-D, sin(k r) in 3-D) up to the radius where the exponential cut-off of xi has
+  reached e^-40.
 
 Parity: pinned by the closed forms of the exponential two-point function in 2-D,
 2 pi s a^2 / (1 + k^2 a^2)^(3/2), and 3-D, 8 pi s a^3 / (1 + k^2 a^2)^2, and of a 2-D
-Gaussian; the box plan by its DC mode and its variance sum rule.  See
+Gaussian; the box plan by those closed forms on chosen modes (signed frequencies, the
+Nyquist corner), its zeroed DC mode and its cell variance.  See
 ``tests/test_oracle_kspace.py``.
 """
 
@@ -61,16 +62,26 @@ def hankel_2d(xi_fn, k, rmax):
     return 2.0 * math.pi * tot
 
 
-def hankel_3d(xi_fn, k):
-    """4 pi int_0^inf r^2 sinc(k r) xi(r) dr = (4 pi / k) int_0^inf r xi(r) sin(k r) dr."""
+def hankel_3d(xi_fn, k, rmax):
+    """4 pi int_0^inf r^2 sinc(k r) xi(r) dr = (4 pi / k) int_0^inf r xi(r) sin(k r) dr, integrated
+    between consecutive zeros of sin(k r) up to rmax."""
+    if k == 0:
+        edges = np.linspace(0.0, rmax, 2001)
+    else:
+        nz = int(k * rmax / math.pi) + 1
+        zeros = math.pi * np.arange(1, nz + 1) / k
+        edges = np.concatenate([[0.0], zeros[zeros < rmax], [rmax]])
+    tot = 0.0
     with warnings.catch_warnings():
         warnings.simplefilter("ignore", integrate.IntegrationWarning)
-        if k == 0:
-            v, _ = integrate.quad(lambda r: r * r * xi_fn(r), 0.0, np.inf, epsabs=0.0, epsrel=1e-13, limit=400)
-            return 4.0 * math.pi * v
-        v, _ = integrate.quad(lambda r: r * xi_fn(r), 0.0, np.inf, weight="sin", wvar=k, epsabs=1e-300,
-                              epsrel=1e-13, limlst=200)
-    return 4.0 * math.pi * v / k
+        for a, b in zip(edges[:-1], edges[1:]):
+            if k == 0:
+                f = lambda r: r * r * xi_fn(r)  # noqa: E731
+            else:
+                f = lambda r: r * math.sin(k * r) * xi_fn(r) / k  # noqa: E731
+            v, _ = integrate.quad(f, a, b, epsabs=0.0, epsrel=1e-13, limit=200)
+            tot += v
+    return 4.0 * math.pi * tot
 
 
 def xi_of(xi):
@@ -108,7 +119,7 @@ def box_plan(n, M, h, xi):
         if val == 0:
             continue
         k = 2.0 * math.pi * math.sqrt(float(val)) / (M * h)
-        cache[int(val)] = (hankel_2d(fn, k, rmax) if d == 2 else hankel_3d(fn, k)) / h ** d
+        cache[int(val)] = (hankel_2d(fn, k, rmax) if d == 2 else hankel_3d(fn, k, rmax)) / h ** d
     for val, p in cache.items():
         lam[s == val] = p
     return dict(lam=lam, M=(M,) * d, n=tuple(int(x) for x in n), h=(float(h),) * d,

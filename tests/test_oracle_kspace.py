@@ -32,11 +32,11 @@ def test_hankel_2d_gaussian(k):
     assert abs(got - want) < 1e-10 * 2 * math.pi * sg * sg
 
 
-@pytest.mark.parametrize("k", [0.0, 0.3, 1.1, 3.0])
+@pytest.mark.parametrize("k", [0.0, 0.3, 2 * math.pi * 2 / 16, 2 * math.pi * math.sqrt(5) / 16, 1.1, 3.0])
 def test_hankel_3d_exponential(k):
     s, a = 0.8, 1.5
-    got = kspace.hankel_3d(lambda r: s * math.exp(-r / a), k)
-    assert abs(got / exp_3d(k, s, a) - 1) < 1e-9
+    got = kspace.hankel_3d(lambda r: s * math.exp(-r / a), k, 40 * a)
+    assert abs(got / exp_3d(k, s, a) - 1) < 1e-11
 
 
 @pytest.mark.parametrize("d,M,h", [(2, 16, 0.5), (3, 8, 2.0)])
