@@ -176,6 +176,20 @@ ce_status ce_ctx_profile_read(ce_ctx* ctx, int32_t max, char* names, double* tot
 ce_status ce_plan_embedding(ce_ctx* ctx, const ce_geometry* geom, const ce_xi* xi,
                             ce_precision precision, double neg_tol, ce_plan** out,
                             ce_plan_info* info);
+/* k-space sampling comparator (Sec. 3.3, eq. Periodicboxmodes): a plan on a periodic box of
+ * `box` cells per axis (square / cubic, box >= N_i, even, the cell side h equal on every axis)
+ * whose survey is cells [0, N_i) of the box.  The mode variances follow the continuous Fourier
+ * transform of the isotropic xi (after CE_XI_LOGNORMAL, if set): lambda(q) = P(|k_q|) / h^d with
+ * P(k) = 2 pi int r J0(k r) xi(r) dr (2-D) or 4 pi int r^2 sinc(k r) xi(r) dr (3-D), k_q =
+ * 2 pi q~ / (box h), evaluated on the device by Gauss-Legendre panels up to the radius where the
+ * exponential cut-off of xi reaches e^-40; lambda(0) = 0 (the DC mode is zeroed).  Kinds
+ * CE_XI_EXP and CE_XI_POWEXP with a cut-off (p[3] > 0); CE_XI_CELL_AVERAGE and tables are
+ * CE_E_UNSUPPORTED.  The plan's sigma2 is the cell variance of the box field, sum(lambda) / box^d.
+ * The plan runs through every generator and pipeline entry point like an embedding plan (which
+ * is the case box = 2N with the discrete spectrum).  Synchronous.  Errors: CE_E_INVALID,
+ * CE_E_UNSUPPORTED, CE_E_OOM, CE_E_NOT_PSD, CE_E_DEVICE. */
+ce_status ce_plan_periodic(ce_ctx* ctx, const ce_geometry* geom, int64_t box, const ce_xi* xi,
+                           ce_precision precision, double neg_tol, ce_plan** out, ce_plan_info* info);
 void ce_plan_release(ce_plan* plan);
 
 /* The lag octant a plan for (geom, xi) starts from: xi, transformed as xi->transform asks, at
@@ -186,8 +200,9 @@ ce_status ce_xi_lag_octant(ce_ctx* ctx, const ce_geometry* geom, const ce_xi* xi
                            void* stream);
 ce_status ce_plan_get_info(const ce_plan* plan, ce_plan_info* info);
 
-/* Copy the FP64 eigenvalue octant lambda(q), q_i in [0, N_i] (before clamping), row-major
- * (N_0+1) x ..., into device buffer out (caller owns, (N_0+1)...(N_{d-1}+1) doubles). */
+/* Copy the FP64 eigenvalue octant lambda(q), q_i in [0, M_i / 2] (before clamping), row-major
+ * (M_0/2+1) x ..., into device buffer out (caller owns, prod (M_i/2+1) doubles; M_i = 2 N_i for
+ * an embedding plan, the box side for a periodic plan). */
 ce_status ce_plan_eigenvalues(const ce_plan* plan, double* out, void* stream);
 
 /* Gaussian realizations (Sec. 2, eq. Papos2 and the discrete construction after eq. Specd).
@@ -239,6 +254,20 @@ ce_status ce_estimate_pk(ce_ctx* ctx, const ce_geometry* geom, ce_precision prec
  * Errors: CE_E_INVALID (count < 2), CE_E_DEVICE. */
 ce_status ce_pk_covariance(ce_ctx* ctx, const double* pk, int64_t count, int32_t nbins,
                            double* out_cov, double* out_cnorm, void* stream);
+
+/* Largest number of shells of ce_cumulative_information. */
+#define CE_INFO_MAX_BINS 2048
+
+/* Cumulative information (Sec. 3.3, eq. cuminfo): out_info[b] = I(<= shell b) = the sum of the
+ * elements of the inverse of the leading (b+1) x (b+1) block of the normalised spectrum
+ * covariance C_ab = <P_a P_b> / (<P_a><P_b>) - 1 (the out_cnorm of ce_pk_covariance).  One
+ * Cholesky factorisation of C in FP64 gives every prefix (the leading block of the factor is the
+ * factor of the leading block).  cnorm: nbins x nbins doubles (device, row-major, symmetric; the
+ * lower triangle is read); out_info: nbins doubles (device).  Entries from the first shell whose
+ * block is not positive definite on are NaN (e.g. fewer realizations than shells).
+ * 1 <= nbins <= CE_INFO_MAX_BINS.  Errors: CE_E_INVALID, CE_E_DEVICE. */
+ce_status ce_cumulative_information(ce_ctx* ctx, const double* cnorm, int32_t nbins, double* out_info,
+                                    void* stream);
 
 /* Largest histogram length of ce_cic_histogram. */
 #define CE_CIC_MAX_BINS 4096

@@ -87,6 +87,8 @@ _ctx_profile_read = _sig("ce_ctx_profile_read", c_i32, c_void_p, c_i32, c_void_p
 _plan_embedding = _sig("ce_plan_embedding", c_i32, c_void_p, ctypes.POINTER(Geometry), ctypes.POINTER(Xi), c_i32,
                        c_f64, ctypes.POINTER(c_void_p), ctypes.POINTER(PlanInfo))
 _plan_release = _sig("ce_plan_release", None, c_void_p)
+_plan_periodic = _sig("ce_plan_periodic", c_i32, c_void_p, ctypes.POINTER(Geometry), c_i64, ctypes.POINTER(Xi), c_i32,
+                      c_f64, ctypes.POINTER(c_void_p), ctypes.POINTER(PlanInfo))
 _xi_lag_octant = _sig("ce_xi_lag_octant", c_i32, c_void_p, ctypes.POINTER(Geometry), ctypes.POINTER(Xi), c_void_p,
                       c_void_p)
 _plan_get_info = _sig("ce_plan_get_info", c_i32, c_void_p, ctypes.POINTER(PlanInfo))
@@ -98,6 +100,7 @@ _lognormal_poisson = _sig("ce_lognormal_poisson", c_i32, c_void_p, c_void_p, c_v
 _estimate_pk = _sig("ce_estimate_pk", c_i32, c_void_p, ctypes.POINTER(Geometry), c_i32, c_i32, c_void_p, c_i64,
                     c_void_p, c_void_p, c_i32, c_void_p, c_void_p, c_void_p, c_void_p)
 _pk_covariance = _sig("ce_pk_covariance", c_i32, c_void_p, c_void_p, c_i64, c_i32, c_void_p, c_void_p, c_void_p)
+_cumulative_information = _sig("ce_cumulative_information", c_i32, c_void_p, c_void_p, c_i32, c_void_p, c_void_p)
 _cic_histogram = _sig("ce_cic_histogram", c_i32, c_void_p, c_void_p, c_i64, c_i64, c_void_p, c_i32, c_void_p, c_void_p)
 _astar_map = _sig("ce_astar_map", c_i32, c_void_p, c_void_p, c_i64, c_i64, c_void_p, c_f64, c_f64, c_i32, c_i32,
                   c_void_p, c_void_p, c_void_p)
@@ -127,8 +130,9 @@ _debug_noise = _sig("ce_debug_noise", c_i32, c_void_p, c_u64, c_u32, c_u64, c_vo
 EXPORTED = ["ce_status_string", "ce_version", "ce_ctx_create", "ce_ctx_destroy", "ce_ctx_check", "ce_ctx_trim",
             "ce_ctx_set_option", "ce_ctx_set_profiling", "ce_ctx_profile_read",
             "ce_plan_embedding", "ce_plan_release", "ce_plan_get_info", "ce_plan_eigenvalues", "ce_xi_lag_octant",
+            "ce_plan_periodic",
             "ce_generate_fields", "ce_lognormal_poisson", "ce_estimate_pk", "ce_pk_covariance",
-            "ce_cic_histogram", "ce_astar_map",
+            "ce_cic_histogram", "ce_astar_map", "ce_cumulative_information",
             "ce_pipeline_run", "ce_pipeline_run_masked", "ce_pipeline_run_batch", "ce_pipeline_graph_create", "ce_pipeline_graph_launch",
             "ce_pipeline_graph_destroy",
             "ce_server_create", "ce_server_submit", "ce_server_poll", "ce_server_drain", "ce_server_cancel",
@@ -272,8 +276,10 @@ def ctx_profile_read(ctx, max_entries=64):
 class Plan:
     """Owning handle of a ce_plan with the geometry it was built for."""
 
-    def __init__(self, handle, n, h, precision, info):
+    def __init__(self, handle, n, h, precision, info, M=None):
         self.handle, self.n, self.h, self.precision, self.info = handle, tuple(n), tuple(h), precision, info
+        # periodic side per axis: 2N (embedding) or the box side (k-space comparator)
+        self.M = tuple(2 * x for x in self.n) if M is None else tuple(M)
 
     @property
     def cells(self):
@@ -284,7 +290,15 @@ class Plan:
 
     @property
     def embedding_cells(self):
-        return self.cells * 2 ** len(self.n)
+        c = 1
+        for x in self.M:
+            c *= x
+        return c
+
+    @property
+    def octant(self):
+        """Shape of the eigenvalue octant, (M_i / 2 + 1) per axis."""
+        return tuple(m // 2 + 1 for m in self.M)
 
     @property
     def dtype(self):
@@ -308,6 +322,21 @@ def plan_embedding(ctx, n, h, xi, precision, neg_tol=-1.0):
         raise NotPSDError(st, "ce_plan_embedding", _info_dict(pi))
     _check(st, "ce_plan_embedding")
     return Plan(out, g.n[:g.ndim], g.h[:g.ndim], int(precision), _info_dict(pi))
+
+
+def plan_periodic(ctx, n, h, box, xi, precision, neg_tol=-1.0):
+    """k-space comparator plan: survey n in the corner of a periodic box of `box` cells per axis."""
+    g = geometry(n, h)
+    x, keep = xi_spec(xi)
+    out = c_void_p()
+    pi = PlanInfo()
+    st = _plan_periodic(ctx, ctypes.byref(g), int(box), ctypes.byref(x), int(precision), float(neg_tol),
+                        ctypes.byref(out), ctypes.byref(pi))
+    del keep
+    if st == E_NOT_PSD:
+        raise NotPSDError(st, "ce_plan_periodic", _info_dict(pi))
+    _check(st, "ce_plan_periodic")
+    return Plan(out, g.n[:g.ndim], g.h[:g.ndim], int(precision), _info_dict(pi), M=(int(box),) * g.ndim)
 
 
 def xi_lag_octant(ctx, n, h, xi, out, stream=None):
@@ -334,8 +363,8 @@ def plan_get_info(plan):
 
 def plan_eigenvalues(plan, out, stream=None):
     noct = 1
-    for x in plan.n:
-        noct *= x + 1
+    for x in plan.octant:
+        noct *= x
     _check(_plan_eigenvalues(plan.handle, _ptr(out, torch.float64, noct, "out"), _stream(stream)),
            "ce_plan_eigenvalues")
 
@@ -377,6 +406,12 @@ def pk_covariance(ctx, pk, count, nbins, out_cov, out_cnorm, stream=None):
                           _ptr(out_cov, torch.float64, nbins * nbins, "out_cov"),
                           _ptr(out_cnorm, torch.float64, nbins * nbins, "out_cnorm"), _stream(stream)),
            "ce_pk_covariance")
+
+
+def cumulative_information(ctx, cnorm, nbins, out_info, stream=None):
+    _check(_cumulative_information(ctx, _ptr(cnorm, torch.float64, nbins * nbins, "cnorm"), int(nbins),
+                                   _ptr(out_info, torch.float64, nbins, "out_info"), _stream(stream)),
+           "ce_cumulative_information")
 
 
 def cic_histogram(ctx, counts, cells, count, mask_f, nhist, out_hist, stream=None):

@@ -168,7 +168,7 @@ struct ce_ctx {
     size_t n = 0;
     hipStream_t used = nullptr;  // stream of the last call that used the buffer
   };
-  Buf ws[10];
+  Buf ws[11];
   // pinned host staging of batch tables; `staged` is recorded after the copy that reads it
   void* pin = nullptr;
   size_t pin_n = 0;
@@ -401,38 +401,63 @@ ce_status check_xi(const ce_geometry* g, const ce_xi* xi) {
   return CE_OK;
 }
 
-// Gauss-Legendre rule of kCellQuadNodes nodes on [0, 1] mapped by u = (1 - cos(pi t)) / 2 (nodes
-// clustered at both ends), with the cell-overlap weight folded in: a = w (pi/2) sin(pi t) (1 - u).
-// Nodes by Newton's method on the Legendre recurrence in long double.
+// Gauss-Legendre nodes x and weights w on [-1, 1] (n <= 64) by Newton's method on the Legendre
+// three-term recurrence, in long double.
+void gauss_legendre(int n, long double* xs, long double* ws) {
+  const long double pi = 3.14159265358979323846264338327950288L;
+  for (int i = 0; i < n; ++i) {
+    long double x = std::cos(pi * (i + 0.75L) / (n + 0.5L));
+    long double dp = 1;
+    for (int it = 0; it < 100; ++it) {
+      long double p0 = 1, p1 = x;
+      for (int k = 2; k <= n; ++k) {
+        const long double p2 = ((2 * k - 1) * x * p1 - (k - 1) * p0) / k;
+        p0 = p1;
+        p1 = p2;
+      }
+      dp = n * (x * p1 - p0) / (x * x - 1);
+      const long double dx = p1 / dp;
+      x -= dx;
+      if (std::fabs(dx) < 1e-19L) break;
+    }
+    xs[i] = x;
+    ws[i] = 2 / ((1 - x * x) * dp * dp);
+  }
+}
+
+// Cell-overlap rule: kCellQuadNodes Gauss-Legendre nodes on [0, 1] mapped by
+// u = (1 - cos(pi t)) / 2 (nodes clustered at both ends), with the overlap weight folded in:
+// a = w (pi/2) sin(pi t) (1 - u).
 const CellQuad& cell_quad() {
   static const CellQuad q = [] {
     CellQuad c{};
-    const int n = kCellQuadNodes;
     const long double pi = 3.14159265358979323846264338327950288L;
-    for (int i = 0; i < n; ++i) {
-      long double x = std::cos(pi * (i + 0.75L) / (n + 0.5L));
-      long double dp = 1;
-      for (int it = 0; it < 100; ++it) {
-        long double p0 = 1, p1 = x;
-        for (int k = 2; k <= n; ++k) {
-          const long double p2 = ((2 * k - 1) * x * p1 - (k - 1) * p0) / k;
-          p0 = p1;
-          p1 = p2;
-        }
-        dp = n * (x * p1 - p0) / (x * x - 1);
-        const long double dx = p1 / dp;
-        x -= dx;
-        if (std::fabs(dx) < 1e-19L) break;
-      }
-      const long double w = 2 / ((1 - x * x) * dp * dp);  // weight on [-1, 1]
-      const long double t = (x + 1) / 2;
+    long double xs[kCellQuadNodes], ws[kCellQuadNodes];
+    gauss_legendre(kCellQuadNodes, xs, ws);
+    for (int i = 0; i < kCellQuadNodes; ++i) {
+      const long double t = (xs[i] + 1) / 2;
       const long double u = (1 - std::cos(pi * t)) / 2;
       c.u[i] = (double)u;
-      c.a[i] = (double)((w / 2) * (pi / 2) * std::sin(pi * t) * (1 - u));
+      c.a[i] = (double)((ws[i] / 2) * (pi / 2) * std::sin(pi * t) * (1 - u));
     }
     return c;
   }();
   return q;
+}
+
+// Gauss-Legendre rule on the unit panel [0, 1] for the Hankel transforms.
+const HankelRule& hankel_rule() {
+  static const HankelRule g = [] {
+    HankelRule r{};
+    long double xs[kHankelNodes], ws[kHankelNodes];
+    gauss_legendre(kHankelNodes, xs, ws);
+    for (int i = 0; i < kHankelNodes; ++i) {
+      r.x[i] = (double)((xs[i] + 1) / 2);
+      r.w[i] = (double)(ws[i] / 2);
+    }
+    return r;
+  }();
+  return g;
 }
 
 constexpr double kNearCells = 15.0;   // direct overlap integral below this many cell sides
@@ -524,6 +549,73 @@ hipStream_t as_stream(void* s) { return static_cast<hipStream_t>(s); }
 }  // namespace
 
 // ---- entry points ---------------------------------------------------------------
+
+namespace {
+
+// Shared end of plan construction: the non-negativity check of eq. condition on the FP64
+// eigenvalue octant `lam` (dims O), then sqrt(lambda / M^d) in the plan precision.  Takes
+// ownership of lam and of spare (nullable, released here); on success the plan keeps lam.
+ce_status finish_plan(ce_ctx* ctx, std::unique_ptr<ce_plan>& plan, double* lam, double* spare, const int32_t* O,
+                      double neg_tol, double sigma2, ce_plan_info* info, ce_plan** out, hipStream_t s) {
+  auto fail = [&](ce_status e) {
+    (void)hipStreamSynchronize(s);
+    ctx->release(lam, plan->bytes_lam);
+    if (spare) ctx->release(spare, plan->bytes_lam);
+    return e;
+  };
+  const int64_t noct = plan->noct;
+  double* stats = nullptr;
+  unsigned long long* nneg = nullptr;
+  const size_t stat_bytes = sizeof(double) * 512 + 64;
+  ce_status st = ctx->alloc((void**)&stats, stat_bytes);
+  if (st != CE_OK) return fail(st);
+  nneg = reinterpret_cast<unsigned long long*>(stats + 512);
+  std::vector<double> hs(512);
+  unsigned long long hneg = 0;
+  bool ok = hipMemsetAsync(nneg, 0, 8, s) == hipSuccess &&
+            launch_lambda_stats(lam, plan->ndim, O, noct, stats, nneg, s) == hipSuccess &&
+            hipMemcpyAsync(hs.data(), stats, sizeof(double) * 512, hipMemcpyDeviceToHost, s) == hipSuccess &&
+            hipMemcpyAsync(&hneg, nneg, 8, hipMemcpyDeviceToHost, s) == hipSuccess &&
+            hipStreamSynchronize(s) == hipSuccess;
+  ctx->release(stats, stat_bytes);
+  if (!ok) return fail(CE_E_DEVICE);
+  double lmin = INFINITY, lmax = -INFINITY;
+  for (int i = 0; i < 256; ++i) {
+    lmin = std::min(lmin, hs[2 * i]);
+    lmax = std::max(lmax, hs[2 * i + 1]);
+  }
+  ce_plan_info pi{};
+  pi.lambda_min = lmin;
+  pi.lambda_max = lmax;
+  pi.sigma2 = sigma2;
+  pi.n_negative = (int64_t)hneg;
+  pi.n_clamped = 0;
+  if (!(lmax > 0) || lmin < -neg_tol * lmax || !std::isfinite(lmin) || !std::isfinite(lmax)) {
+    if (info) *info = pi;
+    return fail(CE_E_NOT_PSD);
+  }
+  pi.n_clamped = pi.n_negative;
+  // sqrt(lambda / M^d) in the plan precision (Papos2 scale folded with the 1/M^d of the inverse DFT)
+  double cells = 1;
+  for (int d = 0; d < plan->ndim; ++d) cells *= plan->M[d];
+  plan->bytes_sq = (plan->prec ? 8 : 4) * (size_t)noct;
+  st = ctx->alloc(&plan->sq, plan->bytes_sq);
+  if (st != CE_OK) return fail(st);
+  if (launch_sqrt_table(lam, plan->ndim, O, 1.0 / cells, plan->prec, plan->sq, s) != hipSuccess ||
+      hipStreamSynchronize(s) != hipSuccess) {
+    ctx->release(plan->sq, plan->bytes_sq);
+    return fail(CE_E_DEVICE);
+  }
+  plan->lam = lam;
+  if (spare) ctx->release(spare, plan->bytes_lam);
+  pi.device_bytes = plan->bytes_lam + plan->bytes_sq;
+  plan->info = pi;
+  if (info) *info = pi;
+  *out = plan.release();
+  return CE_OK;
+}
+
+}  // namespace
 
 extern "C" {
 
@@ -753,57 +845,121 @@ ce_status ce_plan_embedding(ce_ctx* ctx, const ce_geometry* geom, const ce_xi* x
     if (launch_dct_axis(g, f, a, s) != hipSuccess) return fail(CE_E_DEVICE);
     std::swap(src, dst);
   }
-  // eq. condition: lambda >= 0
-  double* stats = nullptr;
-  unsigned long long* nneg = nullptr;
-  const size_t stat_bytes = sizeof(double) * 512 + 64;
-  st = ctx->alloc((void**)&stats, stat_bytes);
-  if (st != CE_OK) return fail(st);
-  nneg = reinterpret_cast<unsigned long long*>(stats + 512);
-  std::vector<double> hs(512);
-  unsigned long long hneg = 0;
-  bool ok = hipMemsetAsync(nneg, 0, 8, s) == hipSuccess &&
-            launch_lambda_stats(src, geom->ndim, O, noct, stats, nneg, s) == hipSuccess &&
-            hipMemcpyAsync(hs.data(), stats, sizeof(double) * 512, hipMemcpyDeviceToHost, s) == hipSuccess &&
-            hipMemcpyAsync(&hneg, nneg, 8, hipMemcpyDeviceToHost, s) == hipSuccess &&
+  if (hipStreamSynchronize(s) != hipSuccess) return fail(CE_E_DEVICE);  // sigma2 has arrived
+  return finish_plan(ctx, plan, src, src == bufA ? bufB : bufA, O, neg_tol, sigma2, info, out, s);
+}
+
+ce_status ce_plan_periodic(ce_ctx* ctx, const ce_geometry* geom, int64_t box, const ce_xi* xi,
+                           ce_precision precision, double neg_tol, ce_plan** out, ce_plan_info* info) {
+  if (!ctx || !geom || !xi || !out) return CE_E_INVALID;
+  *out = nullptr;
+  if (precision != CE_F32 && precision != CE_F64) return CE_E_INVALID;
+  CE_TRY(check_geometry(geom));
+  CE_TRY(check_xi(geom, xi));
+  const int nd = geom->ndim;
+  if (box < 2 || (box & 1)) return CE_E_INVALID;
+  for (int i = 0; i < nd; ++i) {
+    if (geom->n[i] > box) return CE_E_INVALID;
+    if (geom->h[i] != geom->h[0]) return CE_E_UNSUPPORTED;
+  }
+  if (box > kMaxSide) return CE_E_UNSUPPORTED;
+  {
+    std::vector<int> r;
+    if (!factor_length((int)box, r)) return CE_E_UNSUPPORTED;
+  }
+  if (std::pow((double)box, nd) >= 4294967296.0) return CE_E_UNSUPPORTED;
+  if (xi->kind == CE_XI_TABLE || (xi->transform & CE_XI_CELL_AVERAGE)) return CE_E_UNSUPPORTED;
+  if (xi->kind == CE_XI_POWEXP && !(xi->p[3] > 0)) return CE_E_UNSUPPORTED;  // needs the cut-off
+  if (neg_tol < 0) neg_tol = kDefaultNegTol;
+  const double h = geom->h[0];
+  const double scale = xi->kind == CE_XI_EXP ? xi->p[1] : std::min(xi->p[1], xi->p[3]);
+  const double R = 40.0 * (xi->kind == CE_XI_EXP ? xi->p[1] : xi->p[3]);
+  const double kscale = 2.0 * M_PI / ((double)box * h);
+  const int32_t half = (int32_t)(box / 2);
+  // distinct squared frequencies s = sum q_i^2 on the octant and their multiplicity on the box
+  const int64_t smax = (int64_t)nd * half * half;
+  std::vector<double> mult(smax + 1, 0.0);
+  {
+    const int64_t O = half + 1;
+    int64_t q[3] = {0, 0, 0};
+    int64_t n = 1;
+    for (int d = 0; d < nd; ++d) n *= O;
+    for (int64_t idx = 0; idx < n; ++idx) {
+      int64_t rest = idx, s2 = 0;
+      double w = 1;
+      for (int d = 0; d < nd; ++d) {
+        q[d] = rest % O;
+        rest /= O;
+        s2 += q[d] * q[d];
+        if (q[d] != 0 && q[d] != half) w *= 2;
+      }
+      mult[s2] += w;
+    }
+  }
+  std::vector<int64_t> svals;
+  std::vector<int32_t> sidx(smax + 1, 0);
+  for (int64_t v = 1; v <= smax; ++v)
+    if (mult[v] > 0) {
+      sidx[v] = (int32_t)svals.size();
+      svals.push_back(v);
+    }
+  // bound the quadrature work: panels of the largest frequency times distinct values
+  const double kmax = std::sqrt((double)smax) * kscale;
+  const double npan_max = std::ceil(R / std::min(M_PI / (2 * kmax), 0.5 * scale));
+  if (npan_max * (double)svals.size() > 2e10) return CE_E_UNSUPPORTED;
+
+  std::lock_guard<std::mutex> lock(ctx->mu);
+  CE_HIP(hipSetDevice(ctx->device));
+  hipStream_t s = ctx->own;
+  auto plan = std::make_unique<ce_plan>();
+  plan->ctx = ctx;
+  plan->ndim = nd;
+  plan->prec = precision == CE_F64 ? 1 : 0;
+  int32_t O[3] = {1, 1, 1};
+  int64_t noct = 1;
+  for (int i = 0; i < nd; ++i) {
+    plan->n[i] = (int)geom->n[i];
+    plan->M[i] = (int)box;
+    plan->h[i] = h;
+    O[i] = half + 1;
+    noct *= O[i];
+  }
+  plan->noct = noct;
+  plan->bytes_lam = sizeof(double) * noct;
+  double* lam = nullptr;
+  CE_TRY(ctx->alloc((void**)&lam, plan->bytes_lam));
+  // tables for the transform: svals, sidx, pvals
+  const size_t b_s = sizeof(int64_t) * svals.size(), b_i = sizeof(int32_t) * sidx.size(),
+               b_p = sizeof(double) * svals.size();
+  void* tab = nullptr;
+  ce_status st = ctx->alloc(&tab, b_s + b_i + b_p + 64);
+  if (st != CE_OK) {
+    ctx->release(lam, plan->bytes_lam);
+    return st;
+  }
+  auto* d_s = static_cast<int64_t*>(tab);
+  auto* d_p = reinterpret_cast<double*>(static_cast<char*>(tab) + b_s);
+  auto* d_i = reinterpret_cast<int32_t*>(static_cast<char*>(tab) + b_s + b_p);
+  std::vector<double> pv(svals.size());
+  double inv_hd = 1;
+  for (int d = 0; d < nd; ++d) inv_hd /= h;
+  const double p[4] = {xi->p[0], xi->p[1], xi->p[2], xi->p[3]};
+  bool ok = ctx->upload(d_s, svals.data(), b_s) == CE_OK && ctx->upload(d_i, sidx.data(), b_i) == CE_OK &&
+            launch_box_spectrum(nd, half, d_s, (int64_t)svals.size(), d_i, kscale, inv_hd, xi->kind, p,
+                                (xi->transform & CE_XI_LOGNORMAL) ? 1 : 0, scale, R, hankel_rule(), d_p, lam,
+                                s) == hipSuccess &&
+            hipMemcpyAsync(pv.data(), d_p, b_p, hipMemcpyDeviceToHost, s) == hipSuccess &&
             hipStreamSynchronize(s) == hipSuccess;
-  ctx->release(stats, stat_bytes);
-  if (!ok) return fail(CE_E_DEVICE);
-  double lmin = INFINITY, lmax = -INFINITY;
-  for (int i = 0; i < 256; ++i) {
-    lmin = std::min(lmin, hs[2 * i]);
-    lmax = std::max(lmax, hs[2 * i + 1]);
+  ctx->release(tab, b_s + b_i + b_p + 64);
+  if (!ok) {
+    ctx->release(lam, plan->bytes_lam);
+    return CE_E_DEVICE;
   }
-  // sigma2: the first element of the lag octant (copied above, before the synchronisation)
-  ce_plan_info pi{};
-  pi.lambda_min = lmin;
-  pi.lambda_max = lmax;
-  pi.sigma2 = sigma2;
-  pi.n_negative = (int64_t)hneg;
-  pi.n_clamped = 0;
-  if (!(lmax > 0) || lmin < -neg_tol * lmax || !std::isfinite(lmin) || !std::isfinite(lmax)) {
-    if (info) *info = pi;
-    return fail(CE_E_NOT_PSD);
-  }
-  pi.n_clamped = pi.n_negative;
-  // sqrt(lambda / M^d) in the plan precision (Papos2 scale folded with the 1/M^d of the inverse DFT)
-  double cells = 1;
-  for (int d = 0; d < geom->ndim; ++d) cells *= plan->M[d];
-  plan->bytes_sq = (plan->prec ? 8 : 4) * (size_t)noct;
-  st = ctx->alloc(&plan->sq, plan->bytes_sq);
-  if (st != CE_OK) return fail(st);
-  if (launch_sqrt_table(src, geom->ndim, O, 1.0 / cells, plan->prec, plan->sq, s) != hipSuccess ||
-      hipStreamSynchronize(s) != hipSuccess) {
-    ctx->release(plan->sq, plan->bytes_sq);
-    return fail(CE_E_DEVICE);
-  }
-  plan->lam = src;
-  ctx->release(src == bufA ? bufB : bufA, plan->bytes_lam);
-  pi.device_bytes = plan->bytes_lam + plan->bytes_sq;
-  plan->info = pi;
-  if (info) *info = pi;
-  *out = plan.release();
-  return CE_OK;
+  // cell variance of the box field: sum over the box of lambda / M^d, in a fixed order
+  double sigma2 = 0;
+  for (size_t j = 0; j < svals.size(); ++j) sigma2 += mult[svals[j]] * pv[j] * inv_hd;
+  sigma2 /= std::pow((double)box, nd);
+  return finish_plan(ctx, plan, lam, nullptr, O, neg_tol, sigma2, info, out, s);
 }
 
 ce_status ce_xi_lag_octant(ce_ctx* ctx, const ce_geometry* geom, const ce_xi* xi, double* out, void* stream) {
@@ -870,7 +1026,7 @@ NoiseArgs noise_args(const ce_plan* p, uint64_t seed, uint32_t rid, uint64_t fir
   n.ndim = p->ndim;
   for (int d = 0; d < 3; ++d) {
     n.M[d] = d < p->ndim ? p->M[d] : 1;
-    n.O[d] = d < p->ndim ? p->n[d] + 1 : 1;
+    n.O[d] = d < p->ndim ? p->M[d] / 2 + 1 : 1;
   }
   n.sq = p->sq;
   return n;
@@ -1178,12 +1334,13 @@ ce_status pipeline_batch_impl(ce_ctx* ctx, const ce_batch_item* items, int64_t n
     int64_t pairs = 0, covs = 0;
     size_t off_desc = 0, off_slot = 0, off_cov = 0;
   };
-  std::map<std::tuple<int, int, double, int, int>, Group> groups;
+  std::map<std::tuple<int, int, int, double, int, int>, Group> groups;
   for (int64_t i = 0; i < n; ++i) {
     const ce_batch_item& it = items[i];
     if (!it.plan) return CE_E_INVALID;
     CE_TRY(pipeline_check(ctx, it.plan, it.first_realization, it.count, it.nbar, it.nbins, it.out_pk));
-    Group& g = groups[std::make_tuple(it.plan->ndim, it.plan->n[0], it.plan->h[0], it.plan->prec, (int)it.nbins)];
+    Group& g = groups[std::make_tuple(it.plan->ndim, it.plan->n[0], it.plan->M[0], it.plan->h[0], it.plan->prec,
+                                      (int)it.nbins)];
     g.idx.push_back(i);
     g.pairs += (it.count + 1) / 2;
     if (it.count >= 2 && (it.out_cov || it.out_cnorm)) g.covs++;
@@ -1255,7 +1412,7 @@ ce_status pipeline_batch_impl(ce_ctx* ctx, const ce_batch_item* items, int64_t n
   for (auto& kv : groups) {
     Group& g = kv.second;
     const ce_plan* plan = items[g.idx[0]].plan;
-    const int nbins = std::get<4>(kv.first);
+    const int nbins = std::get<5>(kv.first);
     const auto* ddesc = reinterpret_cast<const PairDesc*>(d + g.off_desc);
     const auto* dslot = reinterpret_cast<const SlotOut*>(d + g.off_slot);
     InverseSetup fs;
@@ -1451,6 +1608,20 @@ ce_status ce_pk_covariance(ce_ctx* ctx, const double* pk, int64_t count, int32_t
   if (!out_cov && !out_cnorm) return CE_OK;
   CE_HIP(hipSetDevice(ctx->device));
   CE_HIP(launch_covariance(pk, count, nbins, out_cov, out_cnorm, as_stream(stream)));
+  return CE_OK;
+}
+
+ce_status ce_cumulative_information(ce_ctx* ctx, const double* cnorm, int32_t nbins, double* out_info,
+                                    void* stream) {
+  if (!ctx || !cnorm || !out_info || nbins < 1 || nbins > CE_INFO_MAX_BINS) return CE_E_INVALID;
+  std::lock_guard<std::mutex> lock(ctx->mu);
+  CE_HIP(hipSetDevice(ctx->device));
+  hipStream_t s = as_stream(stream);
+  ctx->last = s;
+  void* work = nullptr;
+  CE_TRY(ctx->scratch(10, sizeof(double) * (size_t)nbins * (size_t)nbins, &work));
+  CE_PROF(ctx, "cumulative_information", s,
+          launch_cumulative_information(cnorm, nbins, static_cast<double*>(work), out_info, s));
   return CE_OK;
 }
 

@@ -1,6 +1,7 @@
-// Counts-in-cells statistics of Poisson maps (Sec. 3.4): the histogram of the counts over
-// unmasked cells, and the A* map, the per-cell root of eq. As, whose spectrum is estimated
-// like that of the galaxy contrast.
+// Statistics beyond the spectrum.  Counts-in-cells statistics of Poisson maps (Sec. 3.4): the
+// histogram of the counts over unmasked cells, and the A* map, the per-cell root of eq. As,
+// whose spectrum is estimated like that of the galaxy contrast.  The cumulative information
+// of the spectrum covariance (eq. cuminfo).
 //
 // Both read the counts once (int32) and the survey mask (float, optional).  The histogram
 // is exact in integers (LDS counters in several copies, flushed with 64-bit atomics); the
@@ -236,9 +237,74 @@ hipError_t astar_all(const int32_t* counts, const float* mask, int64_t cells, in
   return astar_launch<T, 0>(counts, mask, cells, count, nbar, s2, out, partials, mean, s);
 }
 
+// Cumulative information (eq. cuminfo): I(<= b) = 1^T C_b^-1 1 for the leading b x b blocks C_b of
+// the normalised spectrum covariance.  With the Cholesky factor C = L L^T, the leading block of L
+// is the factor of C_b, so I(<= b) = sum_{i <= b} z_i^2 with z = L^-1 1 (forward substitution):
+// one factorisation gives every prefix.  One workgroup; L overwrites the lower triangle of a copy
+// of C in `work` (nb x nb); z and the right-hand side live in LDS.  A pivot that is not positive
+// (C_b not positive definite) makes I NaN from that shell on.
+constexpr int kInfoThreads = 1024;
+
+__global__ void __launch_bounds__(kInfoThreads) k_cumulative_information(const double* __restrict__ C, int nb,
+                                                                        double* __restrict__ work,
+                                                                        double* __restrict__ out) {
+  extern __shared__ double sh[];  // rhs[nb], z[nb]
+  double* rhs = sh;
+  double* z = sh + nb;
+  __shared__ int nok;
+  const int tid = threadIdx.x;
+  for (int64_t i = tid; i < (int64_t)nb * nb; i += kInfoThreads) work[i] = C[i];
+  for (int i = tid; i < nb; i += kInfoThreads) rhs[i] = 1.0;
+  if (tid == 0) nok = nb;
+  __syncthreads();
+  for (int j = 0; j < nb; ++j) {
+    if (tid == 0) {
+      const double d = work[(int64_t)j * nb + j];
+      if (d > 0.0)
+        work[(int64_t)j * nb + j] = sqrt(d);
+      else
+        nok = j;
+    }
+    __syncthreads();
+    if (nok == j) break;
+    const double ljj = work[(int64_t)j * nb + j];
+    for (int i = j + 1 + tid; i < nb; i += kInfoThreads) work[(int64_t)i * nb + j] /= ljj;
+    __syncthreads();
+    const int m = nb - j - 1;
+    for (int64_t t = tid; t < (int64_t)m * m; t += kInfoThreads) {
+      const int ii = (int)(t / m), kk = (int)(t - (int64_t)ii * m);
+      if (kk <= ii) {
+        const int i = j + 1 + ii, k = j + 1 + kk;
+        work[(int64_t)i * nb + k] -= work[(int64_t)i * nb + j] * work[(int64_t)k * nb + j];
+      }
+    }
+    __syncthreads();
+  }
+  const int np = nok;
+  for (int j = 0; j < np; ++j) {
+    if (tid == 0) z[j] = rhs[j] / work[(int64_t)j * nb + j];
+    __syncthreads();
+    for (int i = j + 1 + tid; i < np; i += kInfoThreads) rhs[i] -= work[(int64_t)i * nb + j] * z[j];
+    __syncthreads();
+  }
+  if (tid == 0) {
+    double acc = 0.0;
+    for (int b = 0; b < nb; ++b) {
+      if (b < np) acc += z[b] * z[b];
+      out[b] = b < np ? acc : NAN;
+    }
+  }
+}
+
 }  // namespace
 
 int64_t astar_partials(int64_t cells, int64_t count) { return blocks_per_map(cells) * count * 2; }
+
+hipError_t launch_cumulative_information(const double* C, int nb, double* work, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_cumulative_information, dim3(1), dim3(kInfoThreads), sizeof(double) * 2 * (size_t)nb, s, C,
+                     nb, work, out);
+  return hipGetLastError();
+}
 
 hipError_t launch_cic_histogram(const int32_t* counts, const float* mask, int64_t cells, int64_t count, int nhist,
                                 unsigned long long* hist, hipStream_t s) {

@@ -171,10 +171,22 @@ struct CellQuad {
 hipError_t launch_lag_cell_average(const int32_t* O, const double* h, int kind, const double* p, const CellQuad& q,
                                    double near_cells, double log_step, double* out, hipStream_t s);
 hipError_t launch_log1p(double* p, int64_t n, hipStream_t s);
+// Gauss-Legendre rule on a unit panel: nodes x in (0, 1), weights w summing to 1.
+constexpr int kHankelNodes = 8;
+struct HankelRule {
+  double x[kHankelNodes];
+  double w[kHankelNodes];
+};
+// lambda on the box octant (half + 1)^ndim: P(sqrt(s) kscale) inv_hd via the distinct values svals
+// (nvals of them; sidx maps s to its index), pvals receives P per distinct value.
+hipError_t launch_box_spectrum(int ndim, int32_t half, const int64_t* svals, int64_t nvals, const int32_t* sidx,
+                               double kscale, double inv_hd, int kind, const double* p, int lognormal, double scale,
+                               double R, const HankelRule& g, double* pvals, double* lam, hipStream_t s);
 // counts-in-cells (ce_cic.hip)
 hipError_t launch_cic_histogram(const int32_t* counts, const float* mask, int64_t cells, int64_t count, int nhist,
                                 unsigned long long* hist, hipStream_t s);
 int64_t astar_partials(int64_t cells, int64_t count);  // doubles of partial sums for the mean
+hipError_t launch_cumulative_information(const double* C, int nb, double* work, double* out, hipStream_t s);
 hipError_t launch_astar(int prec, const int32_t* counts, const float* mask, int64_t cells, int64_t count,
                         double nbar, double s2, bool subtract, void* out, double* partials, double* mean,
                         hipStream_t s);

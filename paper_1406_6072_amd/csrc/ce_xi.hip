@@ -2,7 +2,9 @@
 //  * the cell average of an isotropic omega over pairs of cells of a 2-D map, i.e. the square
 //    top-hat filtered two-point function of App. A: the overlap integral eq. exactformula
 //    for lags shorter than 15 cell sides, the derivative expansion eq. CoolEq beyond;
-//  * the lognormal target ln(1 + value) (eq. Lncov), applied in place to a finished table.
+//  * the lognormal target ln(1 + value) (eq. Lncov), applied in place to a finished table;
+//  * the spectrum of the k-space comparator: the continuous Fourier transform of an isotropic
+//    xi on the modes of a periodic box (eq. Periodicboxmodes).
 //
 // The overlap integral is split into the four quadrants of [-1, 1]^2 (the weights
 // (1 - |e_0|)(1 - |e_1|) have a kink at e_i = 0) and each axis of a quadrant is mapped with
@@ -90,6 +92,60 @@ __global__ void k_lag_far(int32_t O0, int32_t O1, double h0, double h1, double r
   }
 }
 
+// Continuous Fourier transform of an isotropic xi (eq. Periodicboxmodes), one workgroup per
+// distinct squared frequency s of the box:
+//   2-D: P(k) = 2 pi int_0^R r J0(k r) xi(r) dr,  3-D: P(k) = (4 pi / k) int_0^R r sin(k r) xi(r) dr,
+// k = sqrt(s) kscale, over uniform panels of width min(pi / (2k), scale / 2) (a quarter of the
+// oscillation and half the length scale of xi) with kHankelNodes Gauss-Legendre nodes each.
+// R puts the exponential cut-off of xi at e^-40.  xi is ln(1 + omega) when lognormal != 0.
+__global__ void __launch_bounds__(kQThreads) k_hankel(const int64_t* __restrict__ svals, double kscale, int ndim,
+                                                       int kind, double p0, double p1, double p2, double p3,
+                                                       int lognormal, double scale, double R, HankelRule g,
+                                                       double* __restrict__ pvals) {
+  const int64_t j = blockIdx.x;
+  const double k = sqrt((double)svals[j]) * kscale;
+  const double dl = fmin(M_PI / (2.0 * k), 0.5 * scale);
+  const int64_t npan = (int64_t)ceil(R / dl);
+  double acc = 0.0;
+  for (int64_t p = threadIdx.x; p < npan; p += kQThreads) {
+    const double a = (double)p * dl;
+    double part = 0.0;
+    for (int i = 0; i < kHankelNodes; ++i) {
+      const double r = a + g.x[i] * dl;
+      double xi = omega_iso(kind, p0, p1, p2, p3, r);
+      if (lognormal) xi = log1p(xi);
+      part += g.w[i] * r * (ndim == 2 ? j0(k * r) : sin(k * r)) * xi;
+    }
+    acc += part;
+  }
+  __shared__ double red[kQThreads];
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int t = kQThreads / 2; t > 0; t >>= 1) {
+    if ((int)threadIdx.x < t) red[threadIdx.x] += red[threadIdx.x + t];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) pvals[j] = red[0] * dl * (ndim == 2 ? 2.0 * M_PI : 4.0 * M_PI / k);
+}
+
+// lambda on the box octant q_i in [0, half] (row-major): P(s) / h^d for s = sum q_i^2 > 0, and 0
+// for the DC mode.
+__global__ void k_fill_box_octant(int ndim, int32_t O, const int32_t* __restrict__ sidx,
+                                  const double* __restrict__ pvals, double inv_hd, double* __restrict__ lam) {
+  int64_t n = O;
+  for (int d = 1; d < ndim; ++d) n *= O;
+  for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < n;
+       idx += (int64_t)gridDim.x * blockDim.x) {
+    int64_t rest = idx, s = 0;
+    for (int d = 0; d < ndim; ++d) {
+      const int64_t q = rest % O;
+      rest /= O;
+      s += q * q;
+    }
+    lam[idx] = s == 0 ? 0.0 : pvals[sidx[s]] * inv_hd;
+  }
+}
+
 __global__ void k_log1p(double* __restrict__ p, int64_t n) {
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
     p[i] = log1p(p[i]);
@@ -113,6 +169,20 @@ hipError_t launch_lag_cell_average(const int32_t* O, const double* h, int kind, 
   const int blocks = (int)((nl + 255) / 256 < 65536 ? (nl + 255) / 256 : 65536);
   hipLaunchKernelGGL(k_lag_far, dim3(blocks), dim3(256), 0, s, O[0], O[1], h[0], h[1], rn2, kind, p[0], p[1], p[2],
                      p[3], log_step, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_box_spectrum(int ndim, int32_t half, const int64_t* svals, int64_t nvals, const int32_t* sidx,
+                               double kscale, double inv_hd, int kind, const double* p, int lognormal, double scale,
+                               double R, const HankelRule& g, double* pvals, double* lam, hipStream_t s) {
+  hipLaunchKernelGGL(k_hankel, dim3((unsigned)nvals), dim3(kQThreads), 0, s, svals, kscale, ndim, kind, p[0], p[1],
+                     p[2], p[3], lognormal, scale, R, g, pvals);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  int64_t n = half + 1;
+  for (int d = 1; d < ndim; ++d) n *= half + 1;
+  const int blocks = (int)((n + 255) / 256 < 65536 ? (n + 255) / 256 : 65536);
+  hipLaunchKernelGGL(k_fill_box_octant, dim3(blocks), dim3(256), 0, s, ndim, half + 1, sidx, pvals, inv_hd, lam);
   return hipGetLastError();
 }
 
