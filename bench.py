@@ -121,11 +121,59 @@ def cic_leg(b, torch, ctx, plan, mask, counts, R, nb, nbar, n, h, stream, steps)
     prof = b.ctx_profile_read(ctx)
     kern = {k: round(v[0] / steps, 4) for k, v in prof.items()}
     hist_ms = kern.get("cic_histogram", 0.0)
+    # the model's mean histogram for this mask (once per survey, not per step)
+    pred = torch.empty(nh, dtype=torch.float64, device=counts.device)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    b.cic_predict(ctx, mask, cells, nbar, s2, nh, pred, stream)
+    torch.cuda.synchronize()
+    predict_ms = (time.perf_counter() - t0) * 1e3
     hist_bytes = 4 * cells * R + 4 * cells  # the counts of every map (int32); the mask (float) once
     return dict(value=round(R / dt, 1), unit="maps/s", ms_per_step=round(1e3 * dt, 3), steps=steps,
                 kernels_ms=kern, histogram_GBs=round(hist_bytes / (hist_ms * 1e-3) / 1e9, 1) if hist_ms else None,
+                predict_ms=round(predict_ms, 3),
                 form="42-bin histogram over f != 0, A* (FP64 solve, mean over f != 0 subtracted, stored FP32), "
                      "P(k) of the A* map through the spectrum estimator")
+
+
+def information_leg(b, torch, R):
+    """The comparison of Sec. 3.3 on the paper's model (128^2 map, cell-averaged omega through
+    ln(1 + omega)): cumulative information of the density spectrum from R realizations of the
+    exact method and of 128^2, 256^2, 512^2 periodic boxes (k-space sampling, DC zeroed)."""
+    from synth import workloads
+    w = workloads.WORKLOADS["paper_128_omega"]
+    n, h, nb = w["n"], w["h"], 16
+    ctx = b.ctx_create(0)
+    dev = torch.device("cuda:0")
+    cells = n[0] * n[1]
+    d = torch.empty(R * cells, dtype=torch.float32, device=dev)
+    pkv = torch.empty(R * nb, dtype=torch.float64, device=dev)
+    cn = torch.empty(nb * nb, dtype=torch.float64, device=dev)
+    info = torch.empty(nb, dtype=torch.float64, device=dev)
+    out = dict(map=list(n), shells=nb, realizations=R, model="paper_128_omega")
+    kxi = {k: v for k, v in w["xi"].items() if k != "cell_average"}
+    for name in ("exact", 128, 256, 512):
+        t0 = time.perf_counter()
+        plan = (b.plan_embedding(ctx, n, h, w["xi"], b.F32) if name == "exact"
+                else b.plan_periodic(ctx, n, h, name, kxi, b.F32))
+        torch.cuda.synchronize()
+        plan_s = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        b.pipeline_run(ctx, plan, 9, 1, 0, R, w["nbar"], nb, pkv, out_delta=d)
+        b.estimate_pk(ctx, n, h, b.F32, b.MAP_FIELD, d, R, None, None, nb, pkv)
+        b.pk_covariance(ctx, pkv, R, nb, None, cn)
+        b.cumulative_information(ctx, cn, nb, info)
+        torch.cuda.synchronize()
+        run_s = time.perf_counter() - t0
+        curve = info.cpu().numpy()
+        out["exact" if name == "exact" else "box_%d" % name] = dict(
+            info_last=round(float(curve[-1]), 2), info_mid=round(float(curve[nb // 2 - 1]), 2),
+            plan_s=round(plan_s, 3), run_s=round(run_s, 3), periodic_side=2 * n[0] if name == "exact" else name)
+        plan.release()
+    nm, _ = b.shell_table(n, h, nb)
+    out["gaussian_half_modes"] = float(nm.sum() / 2)
+    b.ctx_destroy(ctx)
+    return out
 
 
 def parse():
@@ -143,6 +191,8 @@ def parse():
     ap.add_argument("--noise-order", type=int, default=-1, help="schedule: noise-pass tile order (0/1)")
     ap.add_argument("--no-masked", action="store_true", help="skip the masked-survey leg")
     ap.add_argument("--no-cic", action="store_true", help="skip the counts-in-cells leg (histogram, A* and its P(k))")
+    ap.add_argument("--info-realizations", type=int, default=4096,
+                    help="realizations per method of the information experiment (0: skip it)")
     ap.add_argument("--batch-requests", type=int, default=4096,
                     help="requests of the uneven-batch leg (mixed 2-D sides 32..512); 0 to skip")
     ap.add_argument("--batch-reps", type=int, default=5)
@@ -552,6 +602,10 @@ def main():
             out["cic"] = cic_leg(b, torch, ctx, plan, mask, mc, R, nb, nbar, n, h, stream, msteps)
         plan.release()
         b.ctx_destroy(ctx)
+
+    if args.info_realizations:
+        out["information"] = information_leg(b, torch, args.info_realizations)
+        print("information %s" % json.dumps(out["information"]), file=sys.stderr, flush=True)
 
     if args.batch_requests:
         out["uneven_batch"] = uneven_batch_leg(b, torch, args.batch_requests, args.batch_reps)

@@ -280,6 +280,17 @@ ce_status ce_cumulative_information(ce_ctx* ctx, const double* cnorm, int32_t nb
 ce_status ce_cic_histogram(ce_ctx* ctx, const int32_t* counts, int64_t cells, int64_t count,
                            const float* mask_f, int32_t nhist, int64_t* out_hist, void* stream);
 
+/* Mean counts-in-cells histogram of the model (Sec. 3.4): out_pred[N] = <P^(N)> =
+ * int dA G(A) sum_{f_i != 0} Pois(N; nbar f_i e^A), N = 0 .. nhist-1, G the normal law of the
+ * log-density with mean -sigma2_A/2 and variance sigma2_A (a Poisson-lognormal mixture over the
+ * cells' intensities).  The A integral is a Gauss-Legendre rule on mu +- 12 sigma (panels no
+ * wider than sigma/2 and 1/sqrt(nhist), 8 nodes each); the pmf is formed in FP64 from logs.
+ * mask_f (nullable: f = 1): cells floats in [0, 1] (device); out_pred: nhist doubles (device).
+ * Waits for the host side of its tables before returning.  nbar > 0 and sigma2_A > 0 finite,
+ * 1 <= nhist <= CE_CIC_MAX_BINS.  Errors: CE_E_INVALID, CE_E_DEVICE. */
+ce_status ce_cic_predict(ce_ctx* ctx, const float* mask_f, int64_t cells, double nbar, double sigma2_A,
+                         int32_t nhist, double* out_pred, void* stream);
+
 /* A* map (Sec. 3.4, eq. As): in each cell with f_i != 0, the root A* of
  * e^{A*} N_bar_i sigma2_A + A* = sigma2_A (N_i - 1/2) with N_bar_i = nbar f_i, solved in FP64
  * (unique: the left side increases strictly with A*); cells with f_i = 0 hold 0.

@@ -101,6 +101,7 @@ _estimate_pk = _sig("ce_estimate_pk", c_i32, c_void_p, ctypes.POINTER(Geometry),
                     c_void_p, c_void_p, c_i32, c_void_p, c_void_p, c_void_p, c_void_p)
 _pk_covariance = _sig("ce_pk_covariance", c_i32, c_void_p, c_void_p, c_i64, c_i32, c_void_p, c_void_p, c_void_p)
 _cumulative_information = _sig("ce_cumulative_information", c_i32, c_void_p, c_void_p, c_i32, c_void_p, c_void_p)
+_cic_predict = _sig("ce_cic_predict", c_i32, c_void_p, c_void_p, c_i64, c_f64, c_f64, c_i32, c_void_p, c_void_p)
 _cic_histogram = _sig("ce_cic_histogram", c_i32, c_void_p, c_void_p, c_i64, c_i64, c_void_p, c_i32, c_void_p, c_void_p)
 _astar_map = _sig("ce_astar_map", c_i32, c_void_p, c_void_p, c_i64, c_i64, c_void_p, c_f64, c_f64, c_i32, c_i32,
                   c_void_p, c_void_p, c_void_p)
@@ -132,7 +133,7 @@ EXPORTED = ["ce_status_string", "ce_version", "ce_ctx_create", "ce_ctx_destroy",
             "ce_plan_embedding", "ce_plan_release", "ce_plan_get_info", "ce_plan_eigenvalues", "ce_xi_lag_octant",
             "ce_plan_periodic",
             "ce_generate_fields", "ce_lognormal_poisson", "ce_estimate_pk", "ce_pk_covariance",
-            "ce_cic_histogram", "ce_astar_map", "ce_cumulative_information",
+            "ce_cic_histogram", "ce_cic_predict", "ce_astar_map", "ce_cumulative_information",
             "ce_pipeline_run", "ce_pipeline_run_masked", "ce_pipeline_run_batch", "ce_pipeline_graph_create", "ce_pipeline_graph_launch",
             "ce_pipeline_graph_destroy",
             "ce_server_create", "ce_server_submit", "ce_server_poll", "ce_server_drain", "ce_server_cancel",
@@ -412,6 +413,12 @@ def cumulative_information(ctx, cnorm, nbins, out_info, stream=None):
     _check(_cumulative_information(ctx, _ptr(cnorm, torch.float64, nbins * nbins, "cnorm"), int(nbins),
                                    _ptr(out_info, torch.float64, nbins, "out_info"), _stream(stream)),
            "ce_cumulative_information")
+
+
+def cic_predict(ctx, mask_f, cells, nbar, sigma2_A, nhist, out_pred, stream=None):
+    _check(_cic_predict(ctx, _ptr(mask_f, torch.float32, cells, "mask_f"), int(cells), float(nbar), float(sigma2_A),
+                        int(nhist), _ptr(out_pred, torch.float64, nhist, "out_pred"), _stream(stream)),
+           "ce_cic_predict")
 
 
 def cic_histogram(ctx, counts, cells, count, mask_f, nhist, out_hist, stream=None):

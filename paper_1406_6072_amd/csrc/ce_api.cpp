@@ -168,7 +168,7 @@ struct ce_ctx {
     size_t n = 0;
     hipStream_t used = nullptr;  // stream of the last call that used the buffer
   };
-  Buf ws[11];
+  Buf ws[12];
   // pinned host staging of batch tables; `staged` is recorded after the copy that reads it
   void* pin = nullptr;
   size_t pin_n = 0;
@@ -1608,6 +1608,45 @@ ce_status ce_pk_covariance(ce_ctx* ctx, const double* pk, int64_t count, int32_t
   if (!out_cov && !out_cnorm) return CE_OK;
   CE_HIP(hipSetDevice(ctx->device));
   CE_HIP(launch_covariance(pk, count, nbins, out_cov, out_cnorm, as_stream(stream)));
+  return CE_OK;
+}
+
+ce_status ce_cic_predict(ce_ctx* ctx, const float* mask_f, int64_t cells, double nbar, double sigma2_A,
+                         int32_t nhist, double* out_pred, void* stream) {
+  if (!ctx || !out_pred || cells <= 0 || nhist < 1 || nhist > CE_CIC_MAX_BINS) return CE_E_INVALID;
+  if (!(nbar > 0) || !std::isfinite(nbar) || !(sigma2_A > 0) || !std::isfinite(sigma2_A)) return CE_E_INVALID;
+  // the rule over the log-density A ~ N(-s2/2, s2): Gauss-Legendre panels on mu +- 12 sigma,
+  // of width at most sigma / 2 and 1 / sqrt(nhist) (the relative width of the Poisson pmf of the
+  // largest count), 8 nodes each, weights times the normal density
+  const double mu = -0.5 * sigma2_A, sg = std::sqrt(sigma2_A);
+  double wid = std::min(0.5 * sg, 1.0 / std::sqrt((double)nhist));
+  const int panels = (int)std::ceil(24.0 * sg / wid);
+  wid = 24.0 * sg / panels;
+  const HankelRule& g = hankel_rule();  // 8 Gauss-Legendre nodes on [0, 1]
+  const int nq = panels * kHankelNodes;
+  std::vector<double> host(2 * (size_t)nq + nhist);
+  for (int p = 0; p < panels; ++p)
+    for (int i = 0; i < kHankelNodes; ++i) {
+      const double a = mu - 12.0 * sg + wid * (p + g.x[i]);
+      const double z = (a - mu) / sg;
+      host[(size_t)p * kHankelNodes + i] = a;
+      host[(size_t)nq + (size_t)p * kHankelNodes + i] =
+          g.w[i] * wid * std::exp(-0.5 * z * z) / std::sqrt(2.0 * M_PI * sigma2_A);
+    }
+  for (int n = 0; n < nhist; ++n) host[2 * (size_t)nq + n] = std::lgamma((double)n + 1.0);
+  std::lock_guard<std::mutex> lock(ctx->mu);
+  CE_HIP(hipSetDevice(ctx->device));
+  hipStream_t s = as_stream(stream);
+  ctx->last = s;
+  const int64_t bx = cic_predict_blocks(cells);
+  void* p = nullptr;
+  CE_TRY(ctx->scratch(11, sizeof(double) * (host.size() + (size_t)nq * bx * nhist), &p));
+  double* tab = static_cast<double*>(p);
+  CE_HIP(hipMemcpyAsync(tab, host.data(), sizeof(double) * host.size(), hipMemcpyHostToDevice, s));
+  CE_HIP(hipStreamSynchronize(s));  // the host table goes out of scope
+  CE_PROF(ctx, "cic_predict", s,
+          launch_cic_predict(mask_f, cells, nbar, tab, tab + nq, nq, tab + 2 * nq, nhist, tab + host.size(), out_pred,
+                             s));
   return CE_OK;
 }
 

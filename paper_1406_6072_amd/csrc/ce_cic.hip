@@ -1,6 +1,7 @@
 // Statistics beyond the spectrum.  Counts-in-cells statistics of Poisson maps (Sec. 3.4): the
-// histogram of the counts over unmasked cells, and the A* map, the per-cell root of eq. As,
-// whose spectrum is estimated like that of the galaxy contrast.  The cumulative information
+// histogram of the counts over unmasked cells and its Poisson-lognormal prediction, and the A*
+// map, the per-cell root of eq. As, whose spectrum is estimated like that of the galaxy
+// contrast.  The cumulative information
 // of the spectrum covariance (eq. cuminfo).
 //
 // Both read the counts once (int32) and the survey mask (float, optional).  The histogram
@@ -237,6 +238,69 @@ hipError_t astar_all(const int32_t* counts, const float* mask, int64_t cells, in
   return astar_launch<T, 0>(counts, mask, cells, count, nbar, s2, out, partials, mean, s);
 }
 
+// Mean histogram under the model (Sec. 3.4): <P^(N)> = int dA G(A) sum_{f_i != 0} Pois(N; nbar
+// f_i e^A), G the normal law N(-s2/2, s2) of the log-density.  The A integral is a fixed rule
+// (nodes a_q, weights w_q summing to 1 over the law) applied by the host; this kernel forms, for
+// each node q, per-workgroup sums over its cells of the Poisson pmf, exp(N ln(lam) - lam -
+// lgamma(N + 1)) with lam = nbar f e^{a_q}, kPredChunk values of N at a time in registers, each
+// reduced over the workgroup in a fixed order into partials[(q * gridDim.x + block) * nhist + N].
+constexpr int kPredChunk = 16;
+
+__global__ void __launch_bounds__(kCicThreads) k_cic_predict(const float* __restrict__ mask, int64_t cells,
+                                                            double nbar, const double* __restrict__ nodes,
+                                                            const double* __restrict__ lgam, int nhist,
+                                                            double* __restrict__ partials) {
+  __shared__ double red[kCicThreads / 64][kPredChunk];
+  const int q = blockIdx.y;
+  const double ea = exp(nodes[q]);
+  const int64_t stride = (int64_t)gridDim.x * kCicThreads;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  for (int c0 = 0; c0 < nhist; c0 += kPredChunk) {
+    double acc[kPredChunk];
+#pragma unroll
+    for (int j = 0; j < kPredChunk; ++j) acc[j] = 0.0;
+    for (int64_t i = blockIdx.x * (int64_t)kCicThreads + threadIdx.x; i < cells; i += stride) {
+      const float f = mask ? mask[i] : 1.0f;
+      if (f == 0.0f) continue;
+      const double lam = nbar * (double)f * ea;
+      const double ll = log(lam);
+#pragma unroll
+      for (int j = 0; j < kPredChunk; ++j) {
+        const int N = c0 + j;
+        if (N < nhist) acc[j] += exp((double)N * ll - lam - lgam[N]);
+      }
+    }
+    // fixed-order reduction: within each wave by halving, then the waves in order
+#pragma unroll
+    for (int j = 0; j < kPredChunk; ++j) {
+      double v = acc[j];
+      for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+      if (lane == 0) red[wave][j] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x < kPredChunk && c0 + (int)threadIdx.x < nhist) {
+      double t = 0.0;
+      for (int w = 0; w < kCicThreads / 64; ++w) t += red[w][threadIdx.x];
+      partials[((int64_t)q * gridDim.x + blockIdx.x) * nhist + c0 + threadIdx.x] = t;
+    }
+    __syncthreads();
+  }
+}
+
+// out[N] = sum_q w_q sum_b partials[q][b][N], in a fixed order.
+__global__ void k_cic_predict_sum(const double* __restrict__ partials, int nq, int64_t blocks,
+                                  const double* __restrict__ weights, int nhist, double* __restrict__ out) {
+  const int N = blockIdx.x * blockDim.x + threadIdx.x;
+  if (N >= nhist) return;
+  double tot = 0.0;
+  for (int q = 0; q < nq; ++q) {
+    double s = 0.0;
+    for (int64_t b = 0; b < blocks; ++b) s += partials[((int64_t)q * blocks + b) * nhist + N];
+    tot += weights[q] * s;
+  }
+  out[N] = tot;
+}
+
 // Cumulative information (eq. cuminfo): I(<= b) = 1^T C_b^-1 1 for the leading b x b blocks C_b of
 // the normalised spectrum covariance.  With the Cholesky factor C = L L^T, the leading block of L
 // is the factor of C_b, so I(<= b) = sum_{i <= b} z_i^2 with z = L^-1 1 (forward substitution):
@@ -299,6 +363,24 @@ __global__ void __launch_bounds__(kInfoThreads) k_cumulative_information(const d
 }  // namespace
 
 int64_t astar_partials(int64_t cells, int64_t count) { return blocks_per_map(cells) * count * 2; }
+
+int64_t cic_predict_blocks(int64_t cells) {
+  int64_t b = (cells + kCicThreads * 16 - 1) / (kCicThreads * 16);
+  return b < 1 ? 1 : (b > 256 ? 256 : b);
+}
+
+hipError_t launch_cic_predict(const float* mask, int64_t cells, double nbar, const double* nodes,
+                              const double* weights, int nq, const double* lgam, int nhist, double* partials,
+                              double* out, hipStream_t s) {
+  const int64_t bx = cic_predict_blocks(cells);
+  hipLaunchKernelGGL(k_cic_predict, dim3((unsigned)bx, (unsigned)nq), dim3(kCicThreads), 0, s, mask, cells, nbar,
+                     nodes, lgam, nhist, partials);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_cic_predict_sum, dim3((unsigned)((nhist + 255) / 256)), dim3(256), 0, s, partials, nq, bx,
+                     weights, nhist, out);
+  return hipGetLastError();
+}
 
 hipError_t launch_cumulative_information(const double* C, int nb, double* work, double* out, hipStream_t s) {
   hipLaunchKernelGGL(k_cumulative_information, dim3(1), dim3(kInfoThreads), sizeof(double) * 2 * (size_t)nb, s, C,

@@ -151,6 +151,26 @@ def test_histogram_of_simulated_maps_matches_mixture(ce):
     assert np.all(np.abs(z) < 5), z
 
 
+@pytest.mark.parametrize("n,masked,nbar,s2,nhist", [((16, 16), False, 9.68, 0.131, 42), ((64, 64), True, 9.68, 0.131, 42),
+                                                    ((40, 30), True, 1.0, 1.0, 20), ((24, 24), True, 30.0, 0.5, 120)])
+def test_prediction_matches_oracle(ce, n, masked, nbar, s2, nhist):
+    """The Poisson-lognormal mixture on the GPU (fixed Gauss-Legendre rule in A) against the
+    oracle's adaptive quadrature."""
+    b, ctx = ce
+    cells = int(np.prod(n))
+    mask = workloads.survey_mask(n, seed=6) if masked else None
+    if masked:
+        mask.reshape(-1)[cells // 2] = 1e-3
+    out = torch.empty(nhist, dtype=torch.float64, device="cuda")
+    b.cic_predict(ctx, None if mask is None else torch.from_numpy(mask.ravel()).cuda(), cells, nbar, s2, nhist, out)
+    torch.cuda.synchronize()
+    got = out.cpu().numpy()
+    want = ocic.predicted_histogram(nbar, s2, mask, n=n, nhist=nhist)
+    big = want > 1e-6 * want.max()
+    assert np.max(np.abs(got[big] / want[big] - 1)) <= 1e-9
+    assert np.max(np.abs(got - want)) <= 1e-9 * want.max()
+
+
 def test_argument_errors(ce):
     b, ctx = ce
     c = torch.zeros(64, dtype=torch.int32, device="cuda")
@@ -163,6 +183,9 @@ def test_argument_errors(ce):
     assert status_of(b, b.astar_map, ctx, c, 64, 1, None, NBAR, -1.0, False, b.F64, a) == b.E_INVALID
     assert status_of(b, b.astar_map, ctx, c, 64, 1, None, NBAR, float("nan"), False, b.F64, a) == b.E_INVALID
     assert status_of(b, b.astar_map, ctx, c, 64, 1, None, float("inf"), S2A, False, b.F64, a) == b.E_INVALID
+    assert status_of(b, b.cic_predict, ctx, None, 64, 0.0, S2A, 8, a) == b.E_INVALID
+    assert status_of(b, b.cic_predict, ctx, None, 64, NBAR, 0.0, 8, a) == b.E_INVALID
+    assert status_of(b, b.cic_predict, ctx, None, 64, NBAR, S2A, 0, a) == b.E_INVALID
     torch.cuda.synchronize()
     assert b.ctx_check(ctx) == b.OK
 
