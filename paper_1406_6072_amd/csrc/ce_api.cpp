@@ -1624,7 +1624,7 @@ ce_status ce_cic_predict(ce_ctx* ctx, const float* mask_f, int64_t cells, double
   wid = 24.0 * sg / panels;
   const HankelRule& g = hankel_rule();  // 8 Gauss-Legendre nodes on [0, 1]
   const int nq = panels * kHankelNodes;
-  std::vector<double> host(2 * (size_t)nq + nhist);
+  std::vector<double> host(2 * (size_t)nq + 2 * (size_t)nhist);
   for (int p = 0; p < panels; ++p)
     for (int i = 0; i < kHankelNodes; ++i) {
       const double a = mu - 12.0 * sg + wid * (p + g.x[i]);
@@ -1633,12 +1633,15 @@ ce_status ce_cic_predict(ce_ctx* ctx, const float* mask_f, int64_t cells, double
       host[(size_t)nq + (size_t)p * kHankelNodes + i] =
           g.w[i] * wid * std::exp(-0.5 * z * z) / std::sqrt(2.0 * M_PI * sigma2_A);
     }
-  for (int n = 0; n < nhist; ++n) host[2 * (size_t)nq + n] = std::lgamma((double)n + 1.0);
+  for (int n = 0; n < nhist; ++n) {
+    host[2 * (size_t)nq + n] = std::lgamma((double)n + 1.0);
+    host[2 * (size_t)nq + nhist + n] = 1.0 / (double)(n + 1);  // 1 / N for N = n + 1
+  }
   std::lock_guard<std::mutex> lock(ctx->mu);
   CE_HIP(hipSetDevice(ctx->device));
   hipStream_t s = as_stream(stream);
   ctx->last = s;
-  const int64_t bx = cic_predict_blocks(cells);
+  const int64_t bx = cic_predict_blocks(cells, nq);
   void* p = nullptr;
   CE_TRY(ctx->scratch(11, sizeof(double) * (host.size() + (size_t)nq * bx * nhist), &p));
   double* tab = static_cast<double*>(p);

@@ -241,9 +241,11 @@ hipError_t astar_all(const int32_t* counts, const float* mask, int64_t cells, in
 // Mean histogram under the model (Sec. 3.4): <P^(N)> = int dA G(A) sum_{f_i != 0} Pois(N; nbar
 // f_i e^A), G the normal law N(-s2/2, s2) of the log-density.  The A integral is a fixed rule
 // (nodes a_q, weights w_q summing to 1 over the law) applied by the host; this kernel forms, for
-// each node q, per-workgroup sums over its cells of the Poisson pmf, exp(N ln(lam) - lam -
-// lgamma(N + 1)) with lam = nbar f e^{a_q}, kPredChunk values of N at a time in registers, each
+// each node q, per-workgroup sums over its cells of the Poisson pmf with lam = nbar f e^{a_q},
+// kPredChunk values of N at a time in registers: the first of a chunk from logs,
+// exp(N ln(lam) - lam - lgamma(N + 1)), the others by p_{N+1} = p_N lam / (N + 1).  Each is
 // reduced over the workgroup in a fixed order into partials[(q * gridDim.x + block) * nhist + N].
+// lgam holds lgamma(N + 1) for N < nhist, then 1 / N for N = 1 .. nhist (at lgam[nhist + N - 1]).
 constexpr int kPredChunk = 16;
 
 __global__ void __launch_bounds__(kCicThreads) k_cic_predict(const float* __restrict__ mask, int64_t cells,
@@ -263,11 +265,15 @@ __global__ void __launch_bounds__(kCicThreads) k_cic_predict(const float* __rest
       const float f = mask ? mask[i] : 1.0f;
       if (f == 0.0f) continue;
       const double lam = nbar * (double)f * ea;
-      const double ll = log(lam);
+      double p = exp((double)c0 * log(lam) - lam - lgam[c0]);
+      acc[0] += p;
 #pragma unroll
-      for (int j = 0; j < kPredChunk; ++j) {
+      for (int j = 1; j < kPredChunk; ++j) {
         const int N = c0 + j;
-        if (N < nhist) acc[j] += exp((double)N * ll - lam - lgam[N]);
+        if (N < nhist) {
+          p *= lam * lgam[nhist + N - 1];
+          acc[j] += p;
+        }
       }
     }
     // fixed-order reduction: within each wave by halving, then the waves in order
@@ -287,18 +293,26 @@ __global__ void __launch_bounds__(kCicThreads) k_cic_predict(const float* __rest
   }
 }
 
-// out[N] = sum_q w_q sum_b partials[q][b][N], in a fixed order.
-__global__ void k_cic_predict_sum(const double* __restrict__ partials, int nq, int64_t blocks,
-                                  const double* __restrict__ weights, int nhist, double* __restrict__ out) {
-  const int N = blockIdx.x * blockDim.x + threadIdx.x;
-  if (N >= nhist) return;
-  double tot = 0.0;
-  for (int q = 0; q < nq; ++q) {
+// out[N] = sum_q w_q sum_b partials[q][b][N]: one workgroup per N, each thread a fixed strided
+// set of nodes (blocks summed in order), then a tree over the workgroup.
+__global__ void __launch_bounds__(kCicThreads) k_cic_predict_sum(const double* __restrict__ partials, int nq,
+                                                                int64_t blocks, const double* __restrict__ weights,
+                                                                int nhist, double* __restrict__ out) {
+  __shared__ double red[kCicThreads];
+  const int N = blockIdx.x;
+  double acc = 0.0;
+  for (int q = threadIdx.x; q < nq; q += kCicThreads) {
     double s = 0.0;
     for (int64_t b = 0; b < blocks; ++b) s += partials[((int64_t)q * blocks + b) * nhist + N];
-    tot += weights[q] * s;
+    acc += weights[q] * s;
   }
-  out[N] = tot;
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int h = kCicThreads / 2; h > 0; h >>= 1) {
+    if ((int)threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[N] = red[0];
 }
 
 // Cumulative information (eq. cuminfo): I(<= b) = 1^T C_b^-1 1 for the leading b x b blocks C_b of
@@ -364,21 +378,24 @@ __global__ void __launch_bounds__(kInfoThreads) k_cumulative_information(const d
 
 int64_t astar_partials(int64_t cells, int64_t count) { return blocks_per_map(cells) * count * 2; }
 
-int64_t cic_predict_blocks(int64_t cells) {
-  int64_t b = (cells + kCicThreads * 16 - 1) / (kCicThreads * 16);
-  return b < 1 ? 1 : (b > 256 ? 256 : b);
+// workgroups per quadrature node: about 64 cells per thread, and a few thousand workgroups in all
+int64_t cic_predict_blocks(int64_t cells, int nq) {
+  int64_t b = (cells + kCicThreads * 64 - 1) / (kCicThreads * 64);
+  const int64_t cap = 4096 / (nq > 0 ? nq : 1);
+  if (b > cap) b = cap;
+  return b < 1 ? 1 : b;
 }
 
 hipError_t launch_cic_predict(const float* mask, int64_t cells, double nbar, const double* nodes,
                               const double* weights, int nq, const double* lgam, int nhist, double* partials,
                               double* out, hipStream_t s) {
-  const int64_t bx = cic_predict_blocks(cells);
+  const int64_t bx = cic_predict_blocks(cells, nq);
   hipLaunchKernelGGL(k_cic_predict, dim3((unsigned)bx, (unsigned)nq), dim3(kCicThreads), 0, s, mask, cells, nbar,
                      nodes, lgam, nhist, partials);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_cic_predict_sum, dim3((unsigned)((nhist + 255) / 256)), dim3(256), 0, s, partials, nq, bx,
-                     weights, nhist, out);
+  hipLaunchKernelGGL(k_cic_predict_sum, dim3((unsigned)nhist), dim3(kCicThreads), 0, s, partials, nq, bx, weights,
+                     nhist, out);
   return hipGetLastError();
 }
 

@@ -187,7 +187,7 @@ hipError_t launch_cic_histogram(const int32_t* counts, const float* mask, int64_
                                 unsigned long long* hist, hipStream_t s);
 int64_t astar_partials(int64_t cells, int64_t count);  // doubles of partial sums for the mean
 hipError_t launch_cumulative_information(const double* C, int nb, double* work, double* out, hipStream_t s);
-int64_t cic_predict_blocks(int64_t cells);  // workgroups per quadrature node of launch_cic_predict
+int64_t cic_predict_blocks(int64_t cells, int nq);  // workgroups per quadrature node of launch_cic_predict
 hipError_t launch_cic_predict(const float* mask, int64_t cells, double nbar, const double* nodes,
                               const double* weights, int nq, const double* lgam, int nhist, double* partials,
                               double* out, hipStream_t s);
