@@ -589,13 +589,18 @@ def main():
 
         mstep(0)
         torch.cuda.synchronize()
+        b.ctx_profile_read(ctx)
+        b.ctx_set_profiling(ctx, True)
         t0 = time.perf_counter()
         msteps = max(3, args.steps // 4)
         for i in range(msteps):
             mstep(1 + i)
         torch.cuda.synchronize()
         mdt = (time.perf_counter() - t0) / msteps
+        b.ctx_set_profiling(ctx, False)
+        mprof = b.ctx_profile_read(ctx)
         out["masked"] = dict(value=round(R / mdt, 1), unit="realizations/s", ms_per_step=round(1e3 * mdt, 3),
+                             kernels_ms={k: round(v[0] / msteps, 4) for k, v in mprof.items()},
                              steps=msteps, masked_fraction=round(float((mask == 0).float().mean()), 4),
                              form="fused pass with the mask's rate, counts stored, contrast on f != 0 from them")
         if not args.no_cic:

@@ -1296,11 +1296,9 @@ ce_status pipeline_masked_impl(ce_ctx* ctx, const ce_plan* plan, const float* ma
     sn = static_cast<int64_t*>(t);
   }
   CE_HIP(launch_copy_ntot(ntot, sn, count, s));
-  std::vector<float> hm(ncells);
-  CE_HIP(hipMemcpyAsync(hm.data(), mask, sizeof(float) * ncells, hipMemcpyDeviceToHost, s));
-  CE_HIP(hipStreamSynchronize(s));
-  double fsum = 0;
-  for (float v : hm) fsum += (double)v;
+  void* fsd = nullptr;
+  CE_TRY(ctx->scratch(9, sizeof(double), &fsd));
+  CE_HIP(launch_mask_sum(mask, ncells, static_cast<double*>(fsd), s));
   PairLoad pl;
   pl.kind = 1;
   pl.maps = counts;
@@ -1308,7 +1306,7 @@ ce_status pipeline_masked_impl(ce_ctx* ctx, const ce_plan* plan, const float* ma
   pl.ncells = ncells;
   pl.ntot = sn;
   pl.mask = mask;
-  pl.fsum = fsum;
+  pl.fsum = static_cast<const double*>(fsd);
   CE_TRY(spectrum_impl(ctx, ndim, plan->n, plan->h[0], plan->prec, pl, count, nbins, out_pk, nullptr, nullptr, s));
   if (count >= 2 && (out_cov || out_cnorm))
     CE_PROF(ctx, "covariance", s, launch_covariance(out_pk, count, nbins, out_cov, out_cnorm, s));
@@ -1576,15 +1574,12 @@ ce_status ce_estimate_pk(ce_ctx* ctx, const ce_geometry* geom, ce_precision prec
   pl.count = count;
   pl.ncells = ncells;
   pl.mask = mask_f;
-  pl.fsum = (double)ncells;
   if (pl.kind == 1) {
     if (mask_f) {
-      std::vector<float> hm(ncells);
-      CE_HIP(hipMemcpyAsync(hm.data(), mask_f, sizeof(float) * ncells, hipMemcpyDeviceToHost, s));
-      CE_HIP(hipStreamSynchronize(s));
-      double fs = 0;
-      for (float v : hm) fs += (double)v;
-      pl.fsum = fs;
+      void* fs = nullptr;
+      CE_TRY(ctx->scratch(9, sizeof(double), &fs));
+      CE_HIP(launch_mask_sum(mask_f, ncells, static_cast<double*>(fs), s));
+      pl.fsum = static_cast<const double*>(fs);
     }
     if (ntot) {
       pl.ntot = ntot;

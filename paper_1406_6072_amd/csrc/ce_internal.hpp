@@ -110,7 +110,7 @@ struct PairLoad {
   int64_t ncells = 0;
   const int64_t* ntot = nullptr;   // counts kind
   const float* mask = nullptr;     // counts kind, nullable
-  double fsum = 0;             // sum of mask (or ncells)
+  const double* fsum = nullptr;    // device: sum of the mask (null: ncells)
   void* H = nullptr;
   int64_t H_item = 0;
 };
@@ -161,6 +161,7 @@ hipError_t launch_debug_philox(uint32_t k0, uint32_t k1, const uint32_t* ctr, in
                                hipStream_t s);
 hipError_t launch_debug_noise(int prec, const NoiseArgs& n, uint64_t pair, int64_t cells, void* out, hipStream_t s);
 hipError_t launch_zero_u64(unsigned long long* p, int64_t n, hipStream_t s);
+hipError_t launch_mask_sum(const float* mask, int64_t n, double* out, hipStream_t s);
 // transformed lag tables (ce_xi.hip).  Quadrature of one axis of a quadrant of the cell-overlap
 // integral: nodes u in (0, 1) and weights a = (Gauss-Legendre weight x du/dt) (1 - u).
 constexpr int kCellQuadNodes = 48;

@@ -650,17 +650,23 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(sizeof
       const T* a = static_cast<const T*>(p.maps) + ma * p.ncells + row * K;
       for (int i = lane; i < K; i += g.nlanes) line[pidx(i)] = {a[i], has_b ? a[i + p.ncells] : T(0)};
     } else {
+      // delta_g = N / (f N^) - 1 on f != 0, 0 elsewhere, with 1 / N^ = fsum / N_tot formed once;
+      // the per-cell reciprocal of f is the pass precision's (FP32: the hardware reciprocal)
       const int32_t* a = static_cast<const int32_t*>(p.maps) + ma * p.ncells + row * K;
-      const double nha = (double)p.ntot[ma] / p.fsum;
-      const double nhb = has_b ? (double)p.ntot[ma + 1] / p.fsum : 1.0;
+      const double fsum = p.fsum ? *p.fsum : (double)p.ncells;
+      const T ia = (T)(fsum / (double)p.ntot[ma]);
+      const T ib = has_b ? (T)(fsum / (double)p.ntot[ma + 1]) : T(0);
+      const float* mrow = p.mask ? p.mask + row * K : nullptr;
+#pragma unroll 4
       for (int i = lane; i < K; i += g.nlanes) {
-        const double f = p.mask ? (double)p.mask[row * K + i] : 1.0;
-        double va = 0.0, vb = 0.0;
-        if (f != 0.0) {
-          va = ((double)a[i] / f - nha) / nha;
-          if (has_b) vb = ((double)a[i + p.ncells] / f - nhb) / nhb;
+        const T f = mrow ? (T)mrow[i] : T(1);
+        T va = T(0), vb = T(0);
+        if (f != T(0)) {
+          const T r = sizeof(T) == 4 ? (T)__builtin_amdgcn_rcpf((float)f) : T(1) / f;
+          va = (T)a[i] * r * ia - T(1);
+          if (has_b) vb = (T)a[i + p.ncells] * r * ib - T(1);
         }
-        line[pidx(i)] = {(T)va, (T)vb};
+        line[pidx(i)] = {va, vb};
       }
     }
   }
@@ -985,6 +991,21 @@ __global__ void k_advance(unsigned long long* p, unsigned long long by) {
   if (threadIdx.x == 0 && blockIdx.x == 0) *p += by;
 }
 
+// sum of the mask in FP64: thread t adds cells t, t + 1024, ... in order, then a fixed tree
+__global__ void __launch_bounds__(1024) k_mask_sum(const float* __restrict__ mask, int64_t n,
+                                                   double* __restrict__ out) {
+  __shared__ double red[1024];
+  double s = 0.0;
+  for (int64_t i = threadIdx.x; i < n; i += 1024) s += (double)mask[i];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int h = 512; h > 0; h >>= 1) {
+    if ((int)threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *out = red[0];
+}
+
 __global__ void k_zero_u64(unsigned long long* p, int64_t n) {
   const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (i < n) p[i] = 0;
@@ -1279,6 +1300,11 @@ hipError_t launch_debug_noise(int prec, const NoiseArgs& n, uint64_t pair, int64
 
 hipError_t launch_advance(unsigned long long* p, unsigned long long by, hipStream_t s) {
   hipLaunchKernelGGL(k_advance, dim3(1), dim3(64), 0, s, p, by);
+  return hipGetLastError();
+}
+
+hipError_t launch_mask_sum(const float* mask, int64_t n, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_mask_sum, dim3(1), dim3(1024), 0, s, mask, n, out);
   return hipGetLastError();
 }
 
