@@ -583,9 +583,9 @@ def main():
         plan = b.plan_embedding(ctx, n, h, w["xi"], prec)
         mc = torch.empty(R * plan.cells, dtype=torch.int32, device=dev)
 
-        def mstep(i):
+        def mstep(i, counts=None):
             b.pipeline_run_masked(ctx, plan, mask, w["seed"], w["request_id"], i * R * 2, R, nbar, nb, pk_out,
-                                  out_counts=mc, out_ntot=ntot, out_cov=cov, out_cnorm=cnorm, stream=stream)
+                                  out_counts=counts, out_ntot=ntot, out_cov=cov, out_cnorm=cnorm, stream=stream)
 
         mstep(0)
         torch.cuda.synchronize()
@@ -602,8 +602,10 @@ def main():
         out["masked"] = dict(value=round(R / mdt, 1), unit="realizations/s", ms_per_step=round(1e3 * mdt, 3),
                              kernels_ms={k: round(v[0] / msteps, 4) for k, v in mprof.items()},
                              steps=msteps, masked_fraction=round(float((mask == 0).float().mean()), 4),
-                             form="fused pass with the mask's rate, counts stored, contrast on f != 0 from them")
+                             form="fused pass with the mask's rate, transform of N / (f nbar) - 1, contrast completed in the "
+                                  "binning pass with the mask's window transform")
         if not args.no_cic:
+            mstep(1 + msteps, counts=mc)  # the counts of one step for the counts-in-cells leg
             out["cic"] = cic_leg(b, torch, ctx, plan, mask, mc, R, nb, nbar, n, h, stream, msteps)
         plan.release()
         b.ctx_destroy(ctx)

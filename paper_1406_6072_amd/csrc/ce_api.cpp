@@ -168,7 +168,7 @@ struct ce_ctx {
     size_t n = 0;
     hipStream_t used = nullptr;  // stream of the last call that used the buffer
   };
-  Buf ws[12];
+  Buf ws[13];
   // pinned host staging of batch tables; `staged` is recorded after the copy that reads it
   void* pin = nullptr;
   size_t pin_n = 0;
@@ -1087,7 +1087,8 @@ ce_status run_inverse(ce_ctx* ctx, const ce_plan* p, const InverseSetup& fs, uin
 // Forward passes after the separated first forward pass (H rows of W), ending in the
 // shell sums; partials per item.
 ce_status run_forward_bins(ce_ctx* ctx, int ndim, const int* n, int prec, int64_t nitems, void* H, int nb,
-                           double** partials_out, int64_t* groups_out, hipStream_t s) {
+                           double** partials_out, int64_t* groups_out, hipStream_t s,
+                           const BinArgs* window = nullptr) {
   const size_t elem = prec ? 16 : 8;
   const int N = n[0];
   const int W = 2 * (n[ndim - 1] / 2 + 1);
@@ -1114,6 +1115,12 @@ ce_status run_forward_bins(ce_ctx* ctx, int ndim, const int* n, int prec, int64_
   ba.nb = nb;
   ba.W = W;
   ba.partials = static_cast<double*>(part);
+  if (window) {
+    ba.win = window->win;
+    ba.ntot = window->ntot;
+    ba.fsum = window->fsum;
+    ba.nest = window->nest;
+  }
   CE_PROF(ctx, "forward_axis0_bins", s, launch_bin_pass(prec, gb, f0, ba, H, s));
   *partials_out = ba.partials;
   *groups_out = gb.groups_per_item;
@@ -1144,10 +1151,14 @@ constexpr size_t kScratchCap = size_t(8) << 30;
 ce_status pipeline_impl(ce_ctx* ctx, const ce_plan* plan, uint64_t seed, uint32_t request_id,
                         uint64_t first_realization, int64_t count, double nbar, int32_t nbins, void* out_fields,
                         void* out_delta, int32_t* out_counts, int64_t* out_ntot, double* out_pk, double* out_cov,
-                        double* out_cnorm, const unsigned long long* pair_base, hipStream_t s) {
+                        double* out_cnorm, const unsigned long long* pair_base, hipStream_t s,
+                        const float* mask = nullptr, const void* win = nullptr, const double* fsum = nullptr) {
   InverseSetup fs;
   CE_TRY(setup_ffts(ctx, plan, fs));
   const int ndim = plan->ndim;
+  // masked (2-D): the expected intensity nest scales the transformed rows; the binning pass
+  // forms the contrast with the window transform win and sum(f)
+  const double nest = nbar > 0 ? nbar : 1.0;
   const int64_t ncells = survey_cells(plan);
   const int Nl = plan->n[ndim - 1];
   const int W = 2 * (Nl / 2 + 1);
@@ -1188,12 +1199,20 @@ ce_status pipeline_impl(ce_ctx* ctx, const ce_plan* plan, uint64_t seed, uint32_
     e.fwd = fs.fN[ndim - 1];
     e.H = H;
     e.H_item = rows * W;
+    e.mask = mask;
+    e.inv_nest = 1.0 / nest;
     CE_TRY(run_inverse(ctx, plan, fs, seed, request_id, first_realization / 2 + j, np, e, s, pair_base));
     double* partials = nullptr;
     int64_t groups = 0;
-    CE_TRY(run_forward_bins(ctx, ndim, plan->n, plan->prec, np, H, nbins, &partials, &groups, s));
+    BinArgs window;
+    window.win = win;
+    window.ntot = ntot + 2 * j;
+    window.fsum = fsum;
+    window.nest = nest;
+    CE_TRY(run_forward_bins(ctx, ndim, plan->n, plan->prec, np, H, nbins, &partials, &groups, s,
+                            mask ? &window : nullptr));
     CE_PROF(ctx, "bin_reduce", s,
-            launch_bin_reduce(partials, np, groups, nbins, e.count, nm, norm, 1, ntot + 2 * j, nullptr,
+            launch_bin_reduce(partials, np, groups, nbins, e.count, nm, norm, mask ? 2 : 1, ntot + 2 * j, nullptr,
                               (double)ncells, out_pk + 2 * j * nbins, ctx->flags, s));
   }
   if (out_ntot) CE_HIP(launch_copy_ntot(ntot, out_ntot, count, s));
@@ -1244,10 +1263,51 @@ ce_status spectrum_impl(ce_ctx* ctx, int ndim, const int* n, double h, int prec,
 // The pipeline on a masked survey: the fused pass samples counts with rate nbar f rho and
 // stores them (no forward transform); the spectrum stage then forms delta_g = (N/f - N^)/N^ on
 // f != 0 with N^ = N_tot / sum f (eq. Estim) as the standalone estimator does.
+// Forward transform Wm of the indicator f != 0 of a 2-D mask (the spectra's row pass on the map
+// [f != 0] with an empty second map, then the axis-0 line transform), N_0 x W complex in the
+// plan precision in scratch slot 12, [q0][column] like the spectra.
+ce_status window_transform(ce_ctx* ctx, const ce_plan* plan, const float* mask, void** out, hipStream_t s) {
+  const int N0 = plan->n[0], N1 = plan->n[1];
+  const int W = 2 * (N1 / 2 + 1);
+  const size_t elem = plan->prec ? 16 : 8;
+  void* H = nullptr;
+  CE_TRY(ctx->scratch(2, elem * (size_t)N0 * W, &H));
+  void* Wm = nullptr;
+  CE_TRY(ctx->scratch(12, elem * (size_t)N0 * W, &Wm));
+  PairLoad pl;
+  pl.kind = 2;
+  pl.count = 1;
+  pl.ncells = (int64_t)N0 * N1;
+  pl.mask = mask;
+  pl.H = H;
+  pl.H_item = (int64_t)N0 * W;
+  FftDesc fl, f0;
+  CE_TRY(build_fft(ctx, N1, plan->prec, fl));
+  CE_TRY(build_fft(ctx, N0, plan->prec, f0));
+  LineGeom g1 = make_geom(N1, N1, N0, 1, 1, 0, 0, elem, mixed_radix(fl), 1, 1024);
+  CE_PROF(ctx, "window_rows", s, launch_pair_forward(plan->prec, g1, fl, pl, s));
+  LineGeom g0 = make_geom(N0, N0, 1, W, 1, (int64_t)N0 * W, (int64_t)N0 * W, elem, mixed_radix(f0), 1,
+                          cap_lines(ctx, 1, 32));
+  CE_PROF(ctx, "window_axis0", s, launch_line_pass(plan->prec, -1, g0, f0, H, Wm, s));
+  *out = Wm;
+  return CE_OK;
+}
+
 ce_status pipeline_masked_impl(ce_ctx* ctx, const ce_plan* plan, const float* mask, uint64_t seed,
                                uint32_t request_id, uint64_t first_realization, int64_t count, double nbar,
                                int32_t nbins, void* out_fields, void* out_delta, int32_t* out_counts,
                                int64_t* out_ntot, double* out_pk, double* out_cov, double* out_cnorm, hipStream_t s) {
+  if (plan->ndim == 2) {
+    // fused: the contrast is completed in the binning pass from the window transform
+    void* fsd = nullptr;
+    CE_TRY(ctx->scratch(9, sizeof(double), &fsd));
+    CE_HIP(launch_mask_sum(mask, survey_cells(plan), static_cast<double*>(fsd), s));
+    void* win = nullptr;
+    CE_TRY(window_transform(ctx, plan, mask, &win, s));
+    return pipeline_impl(ctx, plan, seed, request_id, first_realization, count, nbar, nbins, out_fields, out_delta,
+                         out_counts, out_ntot, out_pk, out_cov, out_cnorm, nullptr, s, mask, win,
+                         static_cast<const double*>(fsd));
+  }
   InverseSetup fs;
   CE_TRY(setup_ffts(ctx, plan, fs));
   const int ndim = plan->ndim;

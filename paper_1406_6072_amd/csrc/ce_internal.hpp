@@ -100,11 +100,15 @@ struct RowEpi {
   FftDesc fwd;                 // forward FFT of the packed counts row (length K)
   void* H = nullptr;           // separated spectra rows: W = 2 (K/2 + 1) complex per row (null: counts only)
   int64_t H_item = 0;
+  // with a mask and H: the row transformed is N / (f nest) - 1 on f != 0 (0 elsewhere), nest =
+  // 1 / inv_nest the expected intensity; the binning pass completes the contrast with the
+  // window transform (BinArgs.win)
+  double inv_nest = 1;
 };
 
 // Prologue of the standalone spectrum's first pass (rows of two real maps packed).
 struct PairLoad {
-  int32_t kind = 0;            // 0: real maps in pass precision, 1: int32 counts -> contrast
+  int32_t kind = 0;            // 0: real maps in pass precision, 1: int32 counts -> contrast, 2: mask indicator
   const void* maps = nullptr;
   int64_t count = 0;           // maps in the stack
   int64_t ncells = 0;
@@ -119,6 +123,14 @@ struct PairLoad {
 struct BinArgs {
   int32_t ndim = 0, N = 0, nb = 0, W = 0;
   double* partials = nullptr;  // [item][group][2][nb]
+  // Masked 2-D fused pipeline (nullable win): the lines hold the transform A of N / (f nest) - 1
+  // on f != 0; the contrast's transform is D = r A + (r - 1) Wm with r = nest sum(f) / N_tot of
+  // the line's realization and Wm the transform of the indicator f != 0, stored N x W complex in
+  // the pass precision, [q0][column] like the spectra (the first K/2 + 1 columns are used).
+  const void* win = nullptr;
+  const unsigned long long* ntot = nullptr;  // per local realization (2 item + s)
+  const double* fsum = nullptr;              // device: sum of the mask
+  double nest = 1;
 };
 
 // Plan-time DCT-I of the lag octant along one axis (FP64).

@@ -619,7 +619,19 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(sizeof
       }
       sa += (unsigned long long)na;
       sb += (unsigned long long)nb;
-      line[pidx(i)] = {(T)na, (T)nb};
+      if (fr) {
+        // masked: N / (f nest) - 1 on f != 0, 0 elsewhere (the binning pass adds the window term)
+        T va = T(0), vb = T(0);
+        const T ft = (T)f;
+        if (ft != T(0)) {
+          const T q = (sizeof(T) == 4 ? (T)__builtin_amdgcn_rcpf((float)ft) : T(1) / ft) * (T)e.inv_nest;
+          va = (T)na * q - T(1);
+          if (has_b) vb = (T)nb * q - T(1);
+        }
+        line[pidx(i)] = {va, vb};
+      } else {
+        line[pidx(i)] = {(T)na, (T)nb};
+      }
     }
   }
   if (sa) atomicAdd(&tot[0], sa);
@@ -649,6 +661,9 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(sizeof
     if (p.kind == 0) {
       const T* a = static_cast<const T*>(p.maps) + ma * p.ncells + row * K;
       for (int i = lane; i < K; i += g.nlanes) line[pidx(i)] = {a[i], has_b ? a[i + p.ncells] : T(0)};
+    } else if (p.kind == 2) {
+      const float* m = p.mask + row * K;
+      for (int i = lane; i < K; i += g.nlanes) line[pidx(i)] = {m[i] != 0.0f ? T(1) : T(0), T(0)};
     } else {
       // delta_g = N / (f N^) - 1 on f != 0, 0 elsewhere, with 1 / N^ = fsum / N_tot formed once;
       // the per-cell reciprocal of f is the pass precision's (FP32: the hardware reciprocal)
@@ -704,9 +719,9 @@ struct RunEnds {
 // Binning of one line group already transformed in LDS (lines r < nl of the group that
 // starts at line0); adds the group's per-shell sums, lines in order, to tot[2][nb]
 // (entry t is read and written by thread t only).
-template <typename T>
-__device__ __forceinline__ void bin_group(const cpx<T>* res, const LineGeom& g, const BinArgs& bn, int64_t line0,
-                                          int nl, double* acc, RunEnds* ends, double* tot) {
+template <typename T, int WIN>
+__device__ __forceinline__ void bin_group(const cpx<T>* res, const LineGeom& g, const BinArgs& bn, int64_t item,
+                                          int64_t line0, int nl, double* acc, RunEnds* ends, double* tot) {
   const int r = threadIdx.x / g.nlanes, lane = threadIdx.x - r * g.nlanes;
   const bool active = r < nl;
   const int N = bn.N, Nh = N / 2, nb = bn.nb, W = bn.W, Kh = Nh + 1;
@@ -729,6 +744,18 @@ __device__ __forceinline__ void bin_group(const cpx<T>* res, const LineGeom& g, 
       const int chunk = (Kh + g.nlanes - 1) / g.nlanes;
       const int a0 = lane * chunk, a1 = min(a0 + chunk, Kh);
       const cpx<T>* line = res + r * g.lpitch;
+      // masked 2-D pipeline (WIN): the line holds the transform A of N / (f nest) - 1; the
+      // contrast's is D = rr A + rm Wm with rr = nest sum(f) / N_tot of the line's realization,
+      // rm = rr - 1 and Wm the transform of the indicator f != 0 ([q0][column], as the spectra)
+      T rr = T(1), rm = T(0);
+      const cpx<T>* wcol = nullptr;
+      if (WIN) {
+        const double nt = (double)bn.ntot[2 * item + s];
+        const double rd = nt > 0.0 ? bn.nest * *bn.fsum / nt : 0.0;
+        rr = (T)rd;
+        rm = (T)(rd - 1.0);
+        wcol = static_cast<const cpx<T>*>(bn.win) + kz;
+      }
       if (a0 < a1) {
         e.nonempty = 1;
         // t = T |q|^2 advanced by differences: t(a+1) - t(a) = T (2a + 1)
@@ -759,10 +786,18 @@ __device__ __forceinline__ void bin_group(const cpx<T>* res, const LineGeom& g, 
             run = 0.0;
           }
           // power of the mode pair in the pass precision, summed in FP64
-          const cpx<T> v = line[pidx(a)];
+          cpx<T> v = line[pidx(a)];
+          if (WIN) {
+            const cpx<T> w = wcol[(int64_t)a * W];
+            v = {rr * v.x + rm * w.x, rr * v.y + rm * w.y};
+          }
           T pw = v.x * v.x + v.y * v.y;
           if (a != 0 && a != Nh) {
-            const cpx<T> u = line[pidx(N - a)];
+            cpx<T> u = line[pidx(N - a)];
+            if (WIN) {
+              const cpx<T> w = wcol[(int64_t)(N - a) * W];
+              u = {rr * u.x + rm * w.x, rr * u.y + rm * w.y};
+            }
             pw += u.x * u.x + u.y * u.y;
           }
           run += (double)pw;
@@ -819,7 +854,7 @@ __device__ __forceinline__ void bin_group(const cpx<T>* res, const LineGeom& g, 
   }
 }
 
-template <typename T, int MIX>
+template <typename T, int MIX, int WIN>
 __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 4 : 2))) k_bin_pass(LineGeom g, FftDesc f, BinArgs bn, const cpx<T>* in) {
   cpx<T>* lds = lds_lines<T>();
   const PassPos pp = pass_pos(g);
@@ -832,7 +867,7 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(sizeof
   __syncthreads();
   const int r = threadIdx.x / g.nlanes, lane = threadIdx.x - r * g.nlanes;
   line_fft<T, -1, MIX>(buf_a(lds, g, r), buf_b(lds, g, r), f, lane, g.nlanes, r < pp.nl, f.L);
-  bin_group<T>(result_base<T, MIX>(lds, g, f), g, bn, pp.line0, pp.nl, acc, ends, tot);
+  bin_group<T, WIN>(result_base<T, MIX>(lds, g, f), g, bn, pp.item, pp.line0, pp.nl, acc, ends, tot);
   for (int t = threadIdx.x; t < 2 * bn.nb; t += blockDim.x)
     bn.partials[(pp.item * g.groups_per_item + pp.grp) * 2 * bn.nb + t] = tot[t];
 }
@@ -885,6 +920,8 @@ __global__ void k_bin_reduce(const double* __restrict__ partials, int64_t nitems
     if (nt == 0.0) atomicOr(flags, 4u);
     const double nhat = nt / ncells;
     scale = 1.0 / (nhat * nhat);
+  } else if (scale_kind == 2 && ntot[rs] == 0) {  // contrast formed in the binning pass
+    atomicOr(flags, 4u);
   }
   dst[b] = norm * scale * acc / (double)nmodes[b];
 }
@@ -1204,7 +1241,10 @@ static void bin_pass_t(int mix, const LineGeom& g, const FftDesc& f, const BinAr
                      (size_t)g.R * g.nlanes * sizeof(RunEnds) + 2 * (size_t)b.nb * sizeof(double);
   const cpx<T>* i = static_cast<const cpx<T>*>(in);
   with_variant(mix, [&](auto v) {
-    CE_LAUNCH((k_bin_pass<T, decltype(v)::value>), pass_grid(g), pass_block(g), lds, s, g, f, b, i);
+    if (b.win)
+      CE_LAUNCH((k_bin_pass<T, decltype(v)::value, 1>), pass_grid(g), pass_block(g), lds, s, g, f, b, i);
+    else
+      CE_LAUNCH((k_bin_pass<T, decltype(v)::value, 0>), pass_grid(g), pass_block(g), lds, s, g, f, b, i);
   });
 }
 
