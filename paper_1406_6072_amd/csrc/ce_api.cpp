@@ -1300,7 +1300,7 @@ ce_status pipeline_masked_impl(ce_ctx* ctx, const ce_plan* plan, const float* ma
   if (plan->ndim == 2) {
     // fused: the contrast is completed in the binning pass from the window transform
     void* fsd = nullptr;
-    CE_TRY(ctx->scratch(9, sizeof(double), &fsd));
+    CE_TRY(ctx->scratch(9, sizeof(double) * 257, &fsd));
     CE_HIP(launch_mask_sum(mask, survey_cells(plan), static_cast<double*>(fsd), s));
     void* win = nullptr;
     CE_TRY(window_transform(ctx, plan, mask, &win, s));
@@ -1357,7 +1357,7 @@ ce_status pipeline_masked_impl(ce_ctx* ctx, const ce_plan* plan, const float* ma
   }
   CE_HIP(launch_copy_ntot(ntot, sn, count, s));
   void* fsd = nullptr;
-  CE_TRY(ctx->scratch(9, sizeof(double), &fsd));
+  CE_TRY(ctx->scratch(9, sizeof(double) * 257, &fsd));
   CE_HIP(launch_mask_sum(mask, ncells, static_cast<double*>(fsd), s));
   PairLoad pl;
   pl.kind = 1;
@@ -1637,7 +1637,7 @@ ce_status ce_estimate_pk(ce_ctx* ctx, const ce_geometry* geom, ce_precision prec
   if (pl.kind == 1) {
     if (mask_f) {
       void* fs = nullptr;
-      CE_TRY(ctx->scratch(9, sizeof(double), &fs));
+      CE_TRY(ctx->scratch(9, sizeof(double) * 257, &fs));
       CE_HIP(launch_mask_sum(mask_f, ncells, static_cast<double*>(fs), s));
       pl.fsum = static_cast<const double*>(fs);
     }

@@ -1028,15 +1028,29 @@ __global__ void k_advance(unsigned long long* p, unsigned long long by) {
   if (threadIdx.x == 0 && blockIdx.x == 0) *p += by;
 }
 
-// sum of the mask in FP64: thread t adds cells t, t + 1024, ... in order, then a fixed tree
-__global__ void __launch_bounds__(1024) k_mask_sum(const float* __restrict__ mask, int64_t n,
-                                                   double* __restrict__ out) {
-  __shared__ double red[1024];
+// sum of the mask in FP64, in a fixed order: workgroup b's thread t adds cells b 256 + t,
+// b 256 + t + 65536, ..., a tree gives the workgroup's partial, then one workgroup adds the 256
+// partials by a tree
+constexpr int kMaskSumBlocks = 256;
+__global__ void __launch_bounds__(256) k_mask_sum(const float* __restrict__ mask, int64_t n,
+                                                  double* __restrict__ part) {
+  __shared__ double red[256];
   double s = 0.0;
-  for (int64_t i = threadIdx.x; i < n; i += 1024) s += (double)mask[i];
+  for (int64_t i = blockIdx.x * 256ll + threadIdx.x; i < n; i += 256ll * kMaskSumBlocks) s += (double)mask[i];
   red[threadIdx.x] = s;
   __syncthreads();
-  for (int h = 512; h > 0; h >>= 1) {
+  for (int h = 128; h > 0; h >>= 1) {
+    if ((int)threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+
+__global__ void __launch_bounds__(256) k_mask_sum_final(double* __restrict__ part, double* __restrict__ out) {
+  __shared__ double red[256];
+  red[threadIdx.x] = part[threadIdx.x];
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
     if ((int)threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
     __syncthreads();
   }
@@ -1344,7 +1358,11 @@ hipError_t launch_advance(unsigned long long* p, unsigned long long by, hipStrea
 }
 
 hipError_t launch_mask_sum(const float* mask, int64_t n, double* out, hipStream_t s) {
-  hipLaunchKernelGGL(k_mask_sum, dim3(1), dim3(1024), 0, s, mask, n, out);
+  // out[0] receives the sum; out[1 .. 256] hold the workgroup partials
+  hipLaunchKernelGGL(k_mask_sum, dim3(kMaskSumBlocks), dim3(256), 0, s, mask, n, out + 1);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_mask_sum_final, dim3(1), dim3(256), 0, s, out + 1, out);
   return hipGetLastError();
 }
 
