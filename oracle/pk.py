@@ -16,12 +16,14 @@ V = N^d h^d this is P^_b = (h^d / N^d) mean_{q in b} |F(q)|^2.
 Readings taken here:
 
 * Shells are linear in |k| on (0, k_Ny], k_Ny = pi / h (the pixel scale of
-  Sec. 3.3), for a cubic grid: mode q (signed frequencies q~_i = q_i for
-  q_i <= N/2, else q_i - N) is in shell b when b < nb |k| / k_Ny <= b + 1,
-  i.e. |k| / k_Ny = 2 |q~| / N.  Evaluated exactly in integers: b + 1 is the
-  smallest s >= 0 with s^2 N^2 >= 4 nb^2 |q~|^2.  The DC mode and corner modes
-  beyond k_Ny are in no shell.  (The paper bins in ln l; the linear rule is
-  the configuration used here.)
+  Sec. 3.3): mode q (signed frequencies q~_i = q_i for q_i <= N_i/2, else
+  q_i - N_i) is in shell b when b < nb |k| / k_Ny <= b + 1, i.e. |k| / k_Ny =
+  2 sqrt(sum_i (q~_i / N_i)^2).  Evaluated exactly in integers: with L the
+  least common multiple of the N_i, b + 1 is the smallest s >= 0 with
+  s^2 L^2 >= sum_i 4 nb^2 (L / N_i)^2 q~_i^2 (for a cubic grid, s^2 N^2 >=
+  4 nb^2 |q~|^2).  Hyperrectangular grids keep square (cubic) cells.  The DC
+  mode and corner modes beyond k_Ny are in no shell.  (The paper bins in ln l;
+  the linear rule is the configuration used here.)
 * N_b counts every full-grid mode (q and -q separately).
 * Covariance across R realizations: the unbiased Cov_ab with 1/(R - 1), and
   the paper's normalised C_ab with 1/R sample means.
@@ -33,6 +35,8 @@ information by its diagonal closed form (half the number of modes for Gaussian s
 2x2 closed form and its scaling.  See ``tests/test_oracle_pk.py``.
 """
 
+import math
+
 import numpy as np
 
 
@@ -43,31 +47,35 @@ def signed_freq(n):
 
 
 def shell_index(n, nbins):
-    """Shell of every mode of a cubic grid (shape n), -1 where the mode is in no shell."""
+    """Shell of every mode of a grid of shape n with square / cubic cells, -1 where the mode is
+    in no shell.
+
+    |k| / k_Ny = 2 sqrt(sum_i (q~_i / N_i)^2); with L = lcm(N_i) the mode is in shell b = s - 1
+    for the smallest integer s >= 0 with (s L)^2 >= t, t = sum_i 4 nb^2 (L / N_i)^2 q~_i^2,
+    decided in integers (a cubic grid has L = N and t = 4 nb^2 |q~|^2)."""
     n = tuple(int(x) for x in n)
-    if len(set(n)) != 1:
-        raise ValueError("shell rule is defined for cubic grids")
-    N = n[0]
-    grids = np.meshgrid(*[signed_freq(N).astype(np.int64) for _ in n], indexing="ij")
-    q2 = sum(g * g for g in grids)
-    t = 4 * int(nbins) ** 2 * q2
+    L = 1
+    for x in n:
+        L = L * x // math.gcd(L, x)
+    grids = np.meshgrid(*[signed_freq(x).astype(np.int64) for x in n], indexing="ij")
+    nb2 = 4 * int(nbins) ** 2
+    t = sum(nb2 * (L // x) ** 2 * g * g for x, g in zip(n, grids))
     # r = smallest integer with r*r >= t (exact integer ceil-sqrt)
     r = np.floor(np.sqrt(t.astype(np.float64))).astype(np.int64)
     r = np.where(r * r < t, r + 1, r)
     r = np.where((r - 1) * (r - 1) >= t, r - 1, r)
     r = np.where(r * r < t, r + 1, r)
-    s = -(-r // N)  # ceil(r / N): smallest s with s*N >= r
+    s = -(-r // L)  # ceil(r / L): smallest s with s*L >= r
     b = s - 1
     return np.where((b >= 0) & (b < nbins), b, -1)
 
 
 def shell_stats(n, h, nbins):
-    """(N_b, mean |k| per shell) for a cubic grid with cell side h."""
+    """(N_b, mean |k| per shell) for a grid of shape n with cell side h."""
     n = tuple(int(x) for x in n)
     b = shell_index(n, nbins)
-    N = n[0]
-    grids = np.meshgrid(*[signed_freq(N).astype(np.float64) for _ in n], indexing="ij")
-    kmag = 2.0 * np.pi * np.sqrt(sum(g * g for g in grids)) / (N * h)
+    grids = np.meshgrid(*[signed_freq(x).astype(np.float64) / x for x in n], indexing="ij")
+    kmag = 2.0 * np.pi * np.sqrt(sum(g * g for g in grids)) / h
     sel = b >= 0
     nmodes = np.bincount(b[sel], minlength=nbins).astype(np.int64)
     ksum = np.bincount(b[sel], weights=kmag[sel], minlength=nbins)

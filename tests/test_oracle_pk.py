@@ -9,6 +9,38 @@ import pytest
 from oracle import embedding, fields, pk
 
 
+def brute_shell_rect(q, n, nbins):
+    """Smallest s >= 0 with s >= nb |k| / k_Ny, |k| / k_Ny = 2 sqrt(sum (q~_i / N_i)^2), compared
+    as exact rationals."""
+    from fractions import Fraction
+    u = sum(Fraction(x if x <= N // 2 else x - N, N) ** 2 for x, N in zip(q, n)) * 4 * nbins * nbins
+    s = 0
+    while s * s < u:
+        s += 1
+    b = s - 1
+    return b if 0 <= b < nbins else -1
+
+
+@pytest.mark.parametrize("n,nbins", [((12, 20), 7), ((16, 24), 8), ((6, 10, 8), 4), ((18, 12), 9)])
+def test_rectangular_shells_match_rational_enumeration(n, nbins):
+    b = pk.shell_index(n, nbins)
+    for q in itertools.product(*[range(x) for x in n]):
+        assert b[q] == brute_shell_rect(q, n, nbins), q
+
+
+def test_rectangular_shell_stats():
+    """Mean |k| of a shell lies inside it; the modes of all shells are those with |k| <= k_Ny."""
+    n, h, nb = (24, 40), 0.5, 10
+    nm, km = pk.shell_stats(n, h, nb)
+    kny = math.pi / h
+    for b in range(nb):
+        assert b * kny / nb < km[b] <= (b + 1) * kny / nb
+    q0 = np.minimum(np.arange(24), 24 - np.arange(24)) / 24.0
+    q1 = np.minimum(np.arange(40), 40 - np.arange(40)) / 40.0
+    kk = 2 * np.sqrt(q0[:, None] ** 2 + q1[None, :] ** 2)
+    assert nm.sum() == np.count_nonzero((kk > 0) & (kk <= 1 + 1e-12))
+
+
 def brute_shell(q, N, nbins):
     """Smallest s >= 0 with s^2 N^2 >= 4 nb^2 |q~|^2, by counting up in Python integers."""
     qt = [x if x <= N // 2 else x - N for x in q]
