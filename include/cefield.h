@@ -236,8 +236,10 @@ ce_status ce_lognormal_poisson(ce_ctx* ctx, const ce_plan* plan, const void* fie
  * P_b = (h^d / N^d) (1/N_b) sum_{q in b} |F(q)|^2, F the DFT of the map (CE_MAP_FIELD) or of
  * delta_g = (N/f - N^)/N^ on f != 0 and 0 elsewhere, N^ = N_tot / sum f (CE_MAP_COUNTS_DELTAG;
  * ntot nullable -> computed; mask_f nullable -> f = 1).  Shells are linear in |k| on
- * (0, pi/h]: mode q (signed frequencies q~) is in shell b when b < nbins 2|q~|/N <= b+1
- * (decided exactly in integers; cubic grids with equal h only).  maps: count x N^d of float /
+ * (0, pi/h]: mode q (signed frequencies q~_i) is in shell b when
+ * b < nbins 2 sqrt(sum_i (q~_i / N_i)^2) <= b+1, decided exactly in integers (with the least
+ * common multiple of the N_i).  The cells must be square / cubic (equal h); the sides N_i may
+ * differ (hyperrectangular surveys).  maps: count x N^d of float /
  * double (FIELD, per `precision`) or int32 (COUNTS).  out_pk: count x nbins doubles (device).
  * out_nmodes (nullable, device, nbins int64), out_kmean (nullable, device, nbins doubles: the
  * mean |k| = 2 pi |q~| / (N h) of each shell).  Bin sums are accumulated in FP64 in a fixed
@@ -429,8 +431,9 @@ ce_status ce_server_stats_read(ce_server* server, ce_server_stats* out);
 /* Stops admitting, cancels queued requests, waits for running ones, frees everything. */
 void ce_server_destroy(ce_server* server);
 
-/* Shell table of a cubic grid on the host: N_b and mean |k| per shell (same rule as
- * ce_estimate_pk).  nmodes, kmean: host arrays of nbins.  Errors: CE_E_INVALID, CE_E_UNSUPPORTED. */
+/* Shell table of a grid on the host: N_b and mean |k| per shell (same rule as ce_estimate_pk:
+ * square / cubic cells, any even sides).  nmodes, kmean: host arrays of nbins.
+ * Errors: CE_E_INVALID, CE_E_UNSUPPORTED (unequal cell sides). */
 ce_status ce_shell_table(const ce_geometry* geom, int32_t nbins, int64_t* nmodes, double* kmean);
 
 /* FFT factorisation chosen for a line length (host; for inspection).  Writes up to 16 radices

@@ -9,6 +9,7 @@
 #include <map>
 #include <memory>
 #include <mutex>
+#include <numeric>
 #include <string>
 #include <tuple>
 #include <vector>
@@ -147,7 +148,7 @@ LineGeom make_geom(int L, int K, int64_t A, int64_t B, int64_t nitems, int64_t i
 struct SharedTables {
   std::mutex mu;
   std::map<std::tuple<int, int, int>, void*> tw, stw;  // (device, L, precision)
-  std::map<std::tuple<int, int, int, int>, std::pair<int64_t*, std::vector<double>>> shells;  // (device, N, d, nb)
+  std::map<std::tuple<int, int, int, int, int, int>, std::pair<int64_t*, std::vector<double>>> shells;  // (device, n0, n1, n2, d, nb)
 };
 SharedTables& shared_tables() {
   static SharedTables* t = new SharedTables();
@@ -486,35 +487,60 @@ hipError_t build_lag_octant(const ce_geometry* geom, const ce_xi* xi, double* ou
   return e;
 }
 
-bool is_cubic(const ce_geometry* g) {
+// Shells need square (cubic) cells; the side counts may differ (hyperrectangular surveys).
+bool equal_cells(const ce_geometry* g) {
   for (int i = 1; i < g->ndim; ++i)
-    if (g->n[i] != g->n[0] || g->h[i] != g->h[0]) return false;
+    if (g->h[i] != g->h[0]) return false;
   return true;
 }
 
-// Shell table of a cubic grid: nmodes and mean |k| (host, exact integers).
-void shell_table_host(int N, int ndim, double h, int nb, std::vector<int64_t>& nm, std::vector<double>& km) {
+// Integer shell rule of a grid with sides n[0..ndim): mode q~ is in shell s - 1 for the smallest
+// s >= 0 with (s L)^2 >= t = sum_i T_i q~_i^2, L = lcm(n_i), T_i = 4 nb^2 (L / n_i)^2 (the cubic
+// rule has L = N, T = 4 nb^2).  False when the integers could overflow.
+struct ShellRule {
+  int64_t T[3] = {0, 0, 0};
+  int64_t LL = 1;
+};
+bool shell_rule(const int* n, int ndim, int nb, ShellRule& r) {
+  int64_t L = 1;
+  for (int i = 0; i < ndim; ++i) {
+    L = L / std::gcd(L, (int64_t)n[i]) * n[i];
+    if (L > (1ll << 24)) return false;
+  }
+  r.LL = L * L;
+  double tmax = 0;
+  for (int i = 0; i < ndim; ++i) {
+    const int64_t m = L / n[i];
+    r.T[i] = 4ll * nb * nb * m * m;
+    tmax += (double)r.T[i] * (double)(n[i] / 2) * (double)(n[i] / 2);
+  }
+  // t, the edges (s L)^2 for s <= nb + 1 and their differences stay far below 2^63
+  return tmax < 1e17 && (double)(nb + 2) * (nb + 2) * (double)r.LL < 1e17;
+}
+
+// Shell table (nmodes and mean |k| in units of 1 / h) of a grid, host, exact integers.
+void shell_table_host(const int* n, int ndim, int nb, std::vector<int64_t>& nm, std::vector<double>& km) {
+  ShellRule sr;
+  shell_rule(n, ndim, nb, sr);
   nm.assign(nb, 0);
   std::vector<double> ks(nb, 0.0);
-  const int64_t T = 4ll * nb * nb;
-  const int64_t NN = (int64_t)N * N;
-  const int n1 = ndim >= 2 ? N : 1, n2 = ndim >= 3 ? N : 1;
-  for (int a = 0; a < N; ++a) {
-    const int64_t qa = a <= N / 2 ? a : a - N;
+  const int n0 = n[0], n1 = ndim >= 2 ? n[1] : 1, n2 = ndim >= 3 ? n[2] : 1;
+  for (int a = 0; a < n0; ++a) {
+    const int64_t qa = a <= n0 / 2 ? a : a - n0;
     for (int b = 0; b < n1; ++b) {
-      const int64_t qb = b <= N / 2 ? b : b - N;
+      const int64_t qb = ndim >= 2 ? (b <= n1 / 2 ? b : b - n1) : 0;
       for (int c = 0; c < n2; ++c) {
-        const int64_t qc = ndim >= 3 ? (c <= N / 2 ? c : c - N) : 0;
-        const int64_t q2 = qa * qa + qb * qb + qc * qc;
-        const int64_t t = T * q2;
-        // smallest s >= 0 with s^2 N^2 >= t
-        int64_t s = (int64_t)std::sqrt((double)t / (double)NN);
-        while (s > 0 && (s - 1) * (s - 1) * NN >= t) --s;
-        while (s * s * NN < t) ++s;
+        const int64_t qc = ndim >= 3 ? (c <= n2 / 2 ? c : c - n2) : 0;
+        const int64_t t = sr.T[0] * qa * qa + sr.T[1] * qb * qb + sr.T[2] * qc * qc;
+        // smallest s >= 0 with s^2 L^2 >= t
+        int64_t s = (int64_t)std::sqrt((double)t / (double)sr.LL);
+        while (s > 0 && (s - 1) * (s - 1) * sr.LL >= t) --s;
+        while (s * s * sr.LL < t) ++s;
         const int64_t bin = s - 1;
         if (bin >= 0 && bin < nb) {
           nm[bin] += 1;
-          ks[bin] += 2.0 * M_PI * std::sqrt((double)q2) / ((double)N * h);
+          const double fa = (double)qa / n0, fb = (double)qb / n1, fc = (double)qc / n2;
+          ks[bin] += 2.0 * M_PI * std::sqrt(fa * fa + fb * fb + fc * fc);
         }
       }
     }
@@ -523,16 +549,16 @@ void shell_table_host(int N, int ndim, double h, int nb, std::vector<int64_t>& n
   for (int i = 0; i < nb; ++i) km[i] = nm[i] ? ks[i] / (double)nm[i] : NAN;
 }
 
-ce_status device_shells(ce_ctx* ctx, int N, int ndim, double h, int nb, int64_t** nm_dev,
+ce_status device_shells(ce_ctx* ctx, const int* n, int ndim, int nb, int64_t** nm_dev,
                         const std::vector<double>** km_host) {
   SharedTables& st = shared_tables();
   std::lock_guard<std::mutex> lock(st.mu);
-  auto key = std::make_tuple(ctx->device, N, ndim, nb);
+  auto key = std::make_tuple(ctx->device, n[0], ndim >= 2 ? n[1] : 1, ndim >= 3 ? n[2] : 1, ndim, nb);
   auto it = st.shells.find(key);
   if (it == st.shells.end()) {
     std::vector<int64_t> nm;
     std::vector<double> km;
-    shell_table_host(N, ndim, 1.0, nb, nm, km);
+    shell_table_host(n, ndim, nb, nm, km);
     void* p = nullptr;
     CE_TRY(ctx->table_alloc(&p, sizeof(int64_t) * nb));
     CE_TRY(ctx->upload(p, nm.data(), sizeof(int64_t) * nb));
@@ -540,7 +566,6 @@ ce_status device_shells(ce_ctx* ctx, int N, int ndim, double h, int nb, int64_t*
   }
   *nm_dev = it->second.first;
   *km_host = &it->second.second;
-  (void)h;
   return CE_OK;
 }
 
@@ -1112,8 +1137,15 @@ ce_status run_forward_bins(ce_ctx* ctx, int ndim, const int* n, int prec, int64_
   BinArgs ba;
   ba.ndim = ndim;
   ba.N = N;
+  ba.N1 = ndim == 3 ? n[1] : 1;
   ba.nb = nb;
   ba.W = W;
+  ShellRule sr;
+  if (!shell_rule(n, ndim, nb, sr)) return CE_E_UNSUPPORTED;
+  ba.T0 = sr.T[0];
+  ba.T1 = ndim == 3 ? sr.T[1] : 0;
+  ba.Tl = sr.T[ndim - 1];
+  ba.LL = sr.LL;
   ba.partials = static_cast<double*>(part);
   if (window) {
     ba.win = window->win;
@@ -1173,7 +1205,7 @@ ce_status pipeline_impl(ce_ctx* ctx, const ce_plan* plan, uint64_t seed, uint32_
   CE_HIP(launch_zero_u64(ntot, 2 * npairs, s));
   int64_t* nm = nullptr;
   const std::vector<double>* km = nullptr;
-  CE_TRY(device_shells(ctx, plan->n[0], ndim, plan->h[0], nbins, &nm, &km));
+  CE_TRY(device_shells(ctx, plan->n, ndim, nbins, &nm, &km));
   const double norm = std::pow(plan->h[0], ndim) / (double)ncells;
   for (int64_t j = 0; j < npairs; j += cp) {
     const int64_t np = std::min(cp, npairs - j);
@@ -1246,7 +1278,7 @@ ce_status spectrum_impl(ce_ctx* ctx, int ndim, const int* n, double h, int prec,
   CE_TRY(run_forward_bins(ctx, ndim, n, prec, nitems, H, nbins, &partials, &groups, s));
   int64_t* nm = nullptr;
   const std::vector<double>* km = nullptr;
-  CE_TRY(device_shells(ctx, n[0], ndim, h, nbins, &nm, &km));
+  CE_TRY(device_shells(ctx, n, ndim, nbins, &nm, &km));
   const double norm = std::pow(h, ndim) / (double)ncells;
   CE_PROF(ctx, "bin_reduce", s, launch_bin_reduce(partials, nitems, groups, nbins, count, nm, norm, 0, nullptr, nullptr, (double)ncells,
                            out_pk, ctx->flags, s));
@@ -1380,7 +1412,9 @@ ce_status pipeline_check(ce_ctx* ctx, const ce_plan* plan, uint64_t first_realiz
   if (plan->ctx->device != ctx->device) return CE_E_INVALID;
   if ((first_realization + (uint64_t)count + 1) / 2 > 0xFFFFFFFFull) return CE_E_INVALID;
   for (int d = 1; d < plan->ndim; ++d)
-    if (plan->n[d] != plan->n[0] || plan->h[d] != plan->h[0]) return CE_E_UNSUPPORTED;
+    if (plan->h[d] != plan->h[0]) return CE_E_UNSUPPORTED;  // shells need square / cubic cells
+  ShellRule sr;
+  if (!shell_rule(plan->n, plan->ndim, nbins, sr)) return CE_E_UNSUPPORTED;
   return CE_OK;
 }
 
@@ -1392,13 +1426,15 @@ ce_status pipeline_batch_impl(ce_ctx* ctx, const ce_batch_item* items, int64_t n
     int64_t pairs = 0, covs = 0;
     size_t off_desc = 0, off_slot = 0, off_cov = 0;
   };
-  std::map<std::tuple<int, int, int, double, int, int>, Group> groups;
+  // group key: (ndim, sides, periodic sides, cell side, precision, shells)
+  std::map<std::tuple<int, int, int, int, int, int, int, double, int, int>, Group> groups;
   for (int64_t i = 0; i < n; ++i) {
     const ce_batch_item& it = items[i];
     if (!it.plan) return CE_E_INVALID;
     CE_TRY(pipeline_check(ctx, it.plan, it.first_realization, it.count, it.nbar, it.nbins, it.out_pk));
-    Group& g = groups[std::make_tuple(it.plan->ndim, it.plan->n[0], it.plan->M[0], it.plan->h[0], it.plan->prec,
-                                      (int)it.nbins)];
+    const ce_plan* pl = it.plan;
+    Group& g = groups[std::make_tuple(pl->ndim, pl->n[0], pl->n[1], pl->n[2], pl->M[0], pl->M[1], pl->M[2], pl->h[0],
+                                      pl->prec, (int)it.nbins)];
     g.idx.push_back(i);
     g.pairs += (it.count + 1) / 2;
     if (it.count >= 2 && (it.out_cov || it.out_cnorm)) g.covs++;
@@ -1470,7 +1506,7 @@ ce_status pipeline_batch_impl(ce_ctx* ctx, const ce_batch_item* items, int64_t n
   for (auto& kv : groups) {
     Group& g = kv.second;
     const ce_plan* plan = items[g.idx[0]].plan;
-    const int nbins = std::get<5>(kv.first);
+    const int nbins = std::get<9>(kv.first);
     const auto* ddesc = reinterpret_cast<const PairDesc*>(d + g.off_desc);
     const auto* dslot = reinterpret_cast<const SlotOut*>(d + g.off_slot);
     InverseSetup fs;
@@ -1489,7 +1525,7 @@ ce_status pipeline_batch_impl(ce_ctx* ctx, const ce_batch_item* items, int64_t n
     CE_HIP(launch_zero_u64(ntot, 2 * npairs, s));
     int64_t* nm = nullptr;
     const std::vector<double>* km = nullptr;
-    CE_TRY(device_shells(ctx, plan->n[0], ndim, plan->h[0], nbins, &nm, &km));
+    CE_TRY(device_shells(ctx, plan->n, ndim, nbins, &nm, &km));
     const double norm = std::pow(plan->h[0], ndim) / (double)ncells;
     for (int64_t j = 0; j < npairs; j += cp) {
       const int64_t np = std::min(cp, npairs - j);
@@ -1589,10 +1625,14 @@ ce_status ce_shell_table(const ce_geometry* geom, int32_t nbins, int64_t* nmodes
   if (geom->ndim < 1 || geom->ndim > 3) return CE_E_INVALID;
   for (int i = 0; i < geom->ndim; ++i)
     if (geom->n[i] < 2 || (geom->n[i] & 1) || !(geom->h[i] > 0)) return CE_E_INVALID;
-  if (!is_cubic(geom)) return CE_E_UNSUPPORTED;
+  int n[3] = {1, 1, 1};
+  for (int i = 0; i < geom->ndim; ++i) n[i] = (int)geom->n[i];
+  ShellRule sr;
+  if (!equal_cells(geom) || !shell_rule(n, geom->ndim, nbins, sr)) return CE_E_UNSUPPORTED;
   std::vector<int64_t> nm;
   std::vector<double> km;
-  shell_table_host((int)geom->n[0], geom->ndim, geom->h[0], nbins, nm, km);
+  shell_table_host(n, geom->ndim, nbins, nm, km);
+  for (double& v : km) v /= geom->h[0];
   std::memcpy(nmodes, nm.data(), sizeof(int64_t) * nbins);
   std::memcpy(kmean, km.data(), sizeof(double) * nbins);
   return CE_OK;
@@ -1614,7 +1654,12 @@ ce_status ce_estimate_pk(ce_ctx* ctx, const ce_geometry* geom, ce_precision prec
   if (precision != CE_F32 && precision != CE_F64) return CE_E_INVALID;
   if (kind != CE_MAP_FIELD && kind != CE_MAP_COUNTS_DELTAG) return CE_E_INVALID;
   CE_TRY(check_geometry(geom));
-  if (!is_cubic(geom)) return CE_E_UNSUPPORTED;
+  {
+    int nn[3] = {1, 1, 1};
+    for (int i = 0; i < geom->ndim; ++i) nn[i] = (int)geom->n[i];
+    ShellRule sr;
+    if (!equal_cells(geom) || !shell_rule(nn, geom->ndim, nbins, sr)) return CE_E_UNSUPPORTED;
+  }
   std::lock_guard<std::mutex> lock(ctx->mu);
   CE_HIP(hipSetDevice(ctx->device));
   hipStream_t s = as_stream(stream);

@@ -121,7 +121,11 @@ struct PairLoad {
 
 // Binning epilogue of the last forward pass (lines along axis 0 of the spectra).
 struct BinArgs {
-  int32_t ndim = 0, N = 0, nb = 0, W = 0;
+  int32_t ndim = 0, N = 0, nb = 0, W = 0;   // N: side of axis 0 (the line length); W = 2 (N_last/2 + 1)
+  int32_t N1 = 1;                           // 3-D: side of axis 1
+  // shell rule: mode q~ is in shell s - 1 for the smallest s with s^2 LL >= T0 q~_0^2 + T1 q~_1^2
+  // + Tl q~_last^2 (LL = lcm(sides)^2, T_i = 4 nb^2 lcm^2 / N_i^2; cubic: LL = N^2, T = 4 nb^2)
+  int64_t T0 = 0, T1 = 0, Tl = 0, LL = 1;
   double* partials = nullptr;  // [item][group][2][nb]
   // Masked 2-D fused pipeline (nullable win): the lines hold the transform A of N / (f nest) - 1
   // on f != 0; the contrast's transform is D = r A + (r - 1) Wm with r = nest sum(f) / N_tot of

@@ -702,7 +702,8 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(sizeof
 // lines are combined per (realization, shell) in line order: all sums are in a
 // fixed order, hence bitwise reproducible.
 
-// shell b in [0, nb) of |q|^2 = q2 (exact integers): b + 1 = smallest s with s^2 N^2 >= T q2
+// shell b in [0, nb) of a mode with t = sum_i T_i q~_i^2 (exact integers): b + 1 = smallest s with
+// s^2 LL >= t
 __device__ __forceinline__ int shell_of_t(int64_t t, int64_t NN) {
   int64_t s = (int64_t)sqrt((double)t / (double)NN);
   while (s > 0 && (s - 1) * (s - 1) * NN >= t) --s;
@@ -724,8 +725,9 @@ __device__ __forceinline__ void bin_group(const cpx<T>* res, const LineGeom& g, 
                                           int64_t line0, int nl, double* acc, RunEnds* ends, double* tot) {
   const int r = threadIdx.x / g.nlanes, lane = threadIdx.x - r * g.nlanes;
   const bool active = r < nl;
-  const int N = bn.N, Nh = N / 2, nb = bn.nb, W = bn.W, Kh = Nh + 1;
-  const int64_t Tq = 4ll * nb * nb, NN = (int64_t)N * N;
+  // N, Nh: axis 0 (the line); Kh = N_last / 2 + 1 columns per realization of a pair
+  const int N = bn.N, Nh = N / 2, nb = bn.nb, W = bn.W, Kh = W / 2, Nlh = Kh - 1;
+  const int64_t Tq = bn.T0, NN = bn.LL;
   if (r < g.R) {
     RunEnds e{-1, -1, 0.0, 0.0, 1, 0};
     if (active) {
@@ -733,16 +735,16 @@ __device__ __forceinline__ void bin_group(const cpx<T>* res, const LineGeom& g, 
       const int kl = (int)(ln % W);
       const int s = kl >= Kh;
       const int kz = kl - s * Kh;
-      int64_t p2 = (int64_t)kz * kz;
+      int64_t p2 = bn.Tl * kz * kz;  // the line's fixed part of t
       if (bn.ndim == 3) {
         int k1 = (int)(ln / W);
-        if (k1 > Nh) k1 -= N;
-        p2 += (int64_t)k1 * k1;
+        if (k1 > bn.N1 / 2) k1 -= bn.N1;
+        p2 += bn.T1 * k1 * k1;
       }
       // line weight (exact factor 1 or 2), applied when a run is stored
-      const double wgt = (kz != 0 && kz != Nh) ? 2.0 : 1.0;
-      const int chunk = (Kh + g.nlanes - 1) / g.nlanes;
-      const int a0 = lane * chunk, a1 = min(a0 + chunk, Kh);
+      const double wgt = (kz != 0 && kz != Nlh) ? 2.0 : 1.0;
+      const int chunk = (Nh + 1 + g.nlanes - 1) / g.nlanes;
+      const int a0 = lane * chunk, a1 = min(a0 + chunk, Nh + 1);
       const cpx<T>* line = res + r * g.lpitch;
       // masked 2-D pipeline (WIN): the line holds the transform A of N / (f nest) - 1; the
       // contrast's is D = rr A + rm Wm with rr = nest sum(f) / N_tot of the line's realization,
@@ -758,13 +760,13 @@ __device__ __forceinline__ void bin_group(const cpx<T>* res, const LineGeom& g, 
       }
       if (a0 < a1) {
         e.nonempty = 1;
-        // t = T |q|^2 advanced by differences: t(a+1) - t(a) = T (2a + 1)
-        int64_t t = Tq * ((int64_t)a0 * a0 + p2);
+        // t = T0 a^2 + p2 advanced by differences: t(a+1) - t(a) = T0 (2a + 1)
+        int64_t t = Tq * (int64_t)a0 * a0 + p2;
         int64_t dt = Tq * (2 * (int64_t)a0 + 1);
         const int64_t ddt = 2 * Tq;
         int bin = shell_of_t(t, NN);
-        int64_t edge = (int64_t)(bin + 1) * N;
-        edge *= edge;  // (bin+1)^2 N^2: the mode stays in `bin` while T q2 <= edge
+        // (bin+1)^2 LL: the mode stays in `bin` while t <= edge
+        int64_t edge = (int64_t)(bin + 1) * (bin + 1) * NN;
         int64_t estep = (int64_t)(2 * bin + 3) * NN;  // edge(bin + 1) - edge(bin)
         double run = 0.0;
         e.first_bin = bin;

@@ -55,12 +55,20 @@ def test_fft_factors_reject_large_prime():
         binding.fft_factors(2 * 37)
 
 
-@pytest.mark.parametrize("N,d,nb", [(64, 2, 32), (16, 3, 8), (1024, 2, 128), (12, 2, 5)])
-def test_host_shell_table_matches_oracle(N, d, nb):
+@pytest.mark.parametrize("n,nb", [((64, 64), 32), ((16, 16, 16), 8), ((1024, 1024), 128), ((12, 12), 5),
+                                  ((48, 80), 12), ((40, 24, 32), 6), ((64, 26), 10), ((18, 12), 9)])
+def test_host_shell_table_matches_oracle(n, nb):
     from oracle import pk
     from paper_1406_6072_amd import binding
-    nm, km = binding.shell_table((N,) * d, (1.0,) * d, nb)
-    onm, okm = pk.shell_stats((N,) * d, 1.0, nb)
+    d = len(n)
+    nm, km = binding.shell_table(n, (0.5,) * d, nb)
+    onm, okm = pk.shell_stats(n, 0.5, nb)
     assert np.array_equal(nm, onm)
     ok = onm > 0
     assert np.allclose(km[ok], okm[ok], rtol=1e-13)
+
+
+def test_host_shell_table_rejects_unequal_cells():
+    from paper_1406_6072_amd import binding
+    with pytest.raises(binding.CeError):
+        binding.shell_table((16, 16), (1.0, 0.5), 4)

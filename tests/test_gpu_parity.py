@@ -193,7 +193,7 @@ def test_lognormal_poisson_parity(ce, prec, first, masked):
 
 @pytest.mark.parametrize("prec", [1, 0])
 @pytest.mark.parametrize("n,nb", [((64, 64), 32), ((16, 16, 16), 8), ((48, 48), 12), ((58, 58), 14),
-                                  ((26, 26, 26), 6)])
+                                  ((26, 26, 26), 6), ((48, 80), 12), ((40, 24, 32), 6), ((64, 26), 10)])
 def test_pk_field_parity(ce, prec, n, nb):
     b, ctx = ce
     xi = dict(kind="exp", sigma2=1.0, a=2.0)
@@ -263,7 +263,11 @@ PIPE_CASES = [((64, 64), dict(kind="exp", sigma2=0.5, a=8.0), 1, 32, 7),
               ((16, 16, 16), dict(kind="exp", sigma2=0.8, a=1.5), 0, 8, 3),
               ((48, 48), dict(kind="exp", sigma2=1.0, a=3.0), 1, 12, 4),
               ((38, 38), dict(kind="exp", sigma2=1.0, a=3.0), 0, 10, 4),
-              ((22, 22, 22), dict(kind="exp", sigma2=0.8, a=1.5), 1, 6, 2)]
+              ((22, 22, 22), dict(kind="exp", sigma2=0.8, a=1.5), 1, 6, 2),
+              # hyperrectangular surveys (square / cubic cells)
+              ((64, 96), dict(kind="exp", sigma2=0.8, a=3.0), 0, 16, 5),
+              ((48, 32), dict(kind="exp", sigma2=0.8, a=3.0), 1, 10, 4),
+              ((16, 24, 12), dict(kind="exp", sigma2=0.8, a=1.5), 0, 5, 3)]
 
 
 @pytest.mark.parametrize("n,xi,prec,nb,count", PIPE_CASES)
@@ -447,7 +451,7 @@ def test_masked_pipeline_without_counts(ce):
 
 
 @pytest.mark.parametrize("n,prec,nb", [((64, 64), 1, 16), ((96, 96), 0, 24), ((128, 128), 0, 20),
-                                       ((16, 16, 16), 0, 6)])
+                                       ((96, 64), 0, 12), ((16, 16, 16), 0, 6)])
 def test_masked_pipeline_matches_unfused_and_oracle(ce, n, prec, nb):
     """Masked survey (Sec. 3.1 rate nbar f rho; Sec. 3.2 contrast on f != 0): the masked
     pipeline equals the unfused calls with the same mask (fields, delta, counts, N_tot bitwise;
