@@ -22,8 +22,12 @@ Readings taken here:
   least common multiple of the N_i, b + 1 is the smallest s >= 0 with
   s^2 L^2 >= sum_i 4 nb^2 (L / N_i)^2 q~_i^2 (for a cubic grid, s^2 N^2 >=
   4 nb^2 |q~|^2).  Hyperrectangular grids keep square (cubic) cells.  The DC
-  mode and corner modes beyond k_Ny are in no shell.  (The paper bins in ln l;
-  the linear rule is the configuration used here.)
+  mode and corner modes beyond k_Ny are in no shell.  The paper bins in ln l:
+  any ascending shell edges e_b in |k| may be given instead; then, with t the
+  integer above (t = nb^2 L^2 (|k| / k_Ny)^2), a mode is in shell b when
+  TH_b < t <= TH_{b+1}, TH_b = nb^2 L^2 (e_b h / pi)^2 in FP64, snapped to an
+  integer within 1e-9 relative and rounded down otherwise (edges linear on
+  (0, k_Ny] give the integer rule back).
 * N_b counts every full-grid mode (q and -q separately).
 * Covariance across R realizations: the unbiased Cov_ab with 1/(R - 1), and
   the paper's normalised C_ab with 1/R sample means.
@@ -46,13 +50,35 @@ def signed_freq(n):
     return np.where(q <= n // 2, q, q - n)
 
 
-def shell_index(n, nbins):
+def shell_thresholds(n, h, nbins, edges):
+    """Integer thresholds of user shell edges (|k| values e_0 < ... < e_nb): a mode with the
+    integer t below is in shell b when TH_b < t <= TH_{b+1} (t = nb^2 L^2 (|k| / k_Ny)^2,
+    k_Ny = pi / h).  TH_b is v = nb^2 L^2 (e_b h / pi)^2 evaluated in FP64 in this order,
+    rounded to the nearest integer when it lies within 1e-9 v of one (an edge placed on a mode
+    by an FP64 formula, e.g. linear edges, keeps the mode in the lower shell as the integer rule
+    does) and rounded down otherwise."""
+    n = tuple(int(x) for x in n)
+    L = 1
+    for x in n:
+        L = L * x // math.gcd(L, x)
+    scale = float(int(nbins) ** 2 * L * L)
+    out = []
+    for e in edges:
+        x = float(e) * float(h) / math.pi
+        v = scale * (x * x)
+        r = math.floor(v + 0.5)
+        out.append(int(r) if abs(v - r) <= 1e-9 * v else int(math.floor(v)))
+    return np.array(out, dtype=np.int64)
+
+
+def shell_index(n, nbins, edges=None, h=1.0):
     """Shell of every mode of a grid of shape n with square / cubic cells, -1 where the mode is
     in no shell.
 
     |k| / k_Ny = 2 sqrt(sum_i (q~_i / N_i)^2); with L = lcm(N_i) the mode is in shell b = s - 1
     for the smallest integer s >= 0 with (s L)^2 >= t, t = sum_i 4 nb^2 (L / N_i)^2 q~_i^2,
-    decided in integers (a cubic grid has L = N and t = 4 nb^2 |q~|^2)."""
+    decided in integers (a cubic grid has L = N and t = 4 nb^2 |q~|^2).  With edges (|k| values,
+    nb + 1 ascending, cell side h) the shells are those of ``shell_thresholds``."""
     n = tuple(int(x) for x in n)
     L = 1
     for x in n:
@@ -60,6 +86,10 @@ def shell_index(n, nbins):
     grids = np.meshgrid(*[signed_freq(x).astype(np.int64) for x in n], indexing="ij")
     nb2 = 4 * int(nbins) ** 2
     t = sum(nb2 * (L // x) ** 2 * g * g for x, g in zip(n, grids))
+    if edges is not None:
+        th = shell_thresholds(n, h, nbins, edges)
+        b = np.searchsorted(th, t, side="left") - 1  # number of thresholds below t, minus one
+        return np.where((b >= 0) & (b < nbins), b, -1)
     # r = smallest integer with r*r >= t (exact integer ceil-sqrt)
     r = np.floor(np.sqrt(t.astype(np.float64))).astype(np.int64)
     r = np.where(r * r < t, r + 1, r)
@@ -70,10 +100,10 @@ def shell_index(n, nbins):
     return np.where((b >= 0) & (b < nbins), b, -1)
 
 
-def shell_stats(n, h, nbins):
+def shell_stats(n, h, nbins, edges=None):
     """(N_b, mean |k| per shell) for a grid of shape n with cell side h."""
     n = tuple(int(x) for x in n)
-    b = shell_index(n, nbins)
+    b = shell_index(n, nbins, edges, h)
     grids = np.meshgrid(*[signed_freq(x).astype(np.float64) / x for x in n], indexing="ij")
     kmag = 2.0 * np.pi * np.sqrt(sum(g * g for g in grids)) / h
     sel = b >= 0
@@ -96,13 +126,13 @@ def contrast_from_counts(counts, ntot=None, mask=None):
     return out
 
 
-def power_spectrum(phi, h, nbins):
+def power_spectrum(phi, h, nbins, edges=None):
     """P^_b = (h^d / N^d) mean_{q in b} |F(q)|^2 for one map phi (eq. Def spec)."""
     phi = np.asarray(phi, dtype=np.float64)
     n = phi.shape
     F = np.fft.fftn(phi)
     p2 = (F.real ** 2 + F.imag ** 2)
-    b = shell_index(n, nbins)
+    b = shell_index(n, nbins, edges, h)
     sel = b >= 0
     nmodes = np.bincount(b[sel], minlength=nbins)
     sums = np.bincount(b[sel], weights=p2[sel], minlength=nbins)
@@ -111,8 +141,9 @@ def power_spectrum(phi, h, nbins):
     return (h ** phi.ndim / float(np.prod(n))) * mean
 
 
-def estimate_pk(maps, h, nbins, kind="field", ntot=None, mask=None):
-    """Spectra of a stack of maps (count, *N).  kind: 'field' or 'counts'."""
+def estimate_pk(maps, h, nbins, kind="field", ntot=None, mask=None, edges=None):
+    """Spectra of a stack of maps (count, *N).  kind: 'field' or 'counts'; edges: optional shell
+    edges in |k| (nb + 1 ascending), e.g. logarithmic as in the paper."""
     maps = np.asarray(maps)
     out = np.empty((maps.shape[0], nbins), dtype=np.float64)
     for k in range(maps.shape[0]):
@@ -120,7 +151,7 @@ def estimate_pk(maps, h, nbins, kind="field", ntot=None, mask=None):
             phi = contrast_from_counts(maps[k], None if ntot is None else ntot[k], mask)
         else:
             phi = maps[k]
-        out[k] = power_spectrum(phi, h, nbins)
+        out[k] = power_spectrum(phi, h, nbins, edges)
     return out
 
 

@@ -136,3 +136,35 @@ def test_covariance_matches_numpy_and_paper_form():
     assert np.allclose(cov, np.cov(P, rowvar=False), rtol=1e-13, atol=1e-14)
     m = P.mean(axis=0)
     assert np.allclose(cp, np.mean(P[:, :, None] * P[:, None, :], axis=0) / np.outer(m, m) - 1, rtol=1e-12)
+
+
+@pytest.mark.parametrize("n,nb,h", [((64, 64), 32, 1.0), ((48, 80), 12, 0.7), ((16, 24, 12), 5, 2.0)])
+def test_linear_edges_reproduce_integer_rule(n, nb, h):
+    e = np.linspace(0.0, math.pi / h, nb + 1)
+    assert np.array_equal(pk.shell_index(n, nb, e, h), pk.shell_index(n, nb))
+
+
+@pytest.mark.parametrize("n,h", [((128, 128), 1.0), ((96, 64), 0.5), ((20, 16, 24), 1.0)])
+def test_log_edges_match_direct_classification(n, h):
+    """Shells equally spaced in ln k (the paper's binning): every mode not within 1e-9 of an
+    edge is in the shell with e_b < |k| <= e_{b+1}, |k| from its signed frequencies."""
+    nb = 20
+    kny = math.pi / h
+    e = np.exp(np.linspace(math.log(kny / 40.0), math.log(kny), nb + 1))
+    b = pk.shell_index(n, nb, e, h)
+    grids = np.meshgrid(*[pk.signed_freq(x).astype(np.float64) / x for x in n], indexing="ij")
+    k = 2 * math.pi * np.sqrt(sum(g * g for g in grids)) / h
+    direct = np.searchsorted(e, k, side="left") - 1
+    direct = np.where((direct >= 0) & (direct < nb), direct, -1)
+    far = np.min(np.abs(k[..., None] - e), axis=-1) > 1e-9 * k.max()
+    assert np.array_equal(b[far], direct[far])
+    assert (b >= 0).sum() > 0
+
+
+def test_kmax_edges_take_the_corners():
+    """Edges on (0, pi sqrt(2) / h] (the variant that includes the corners) bin every mode
+    but DC."""
+    n, nb, h = (32, 32), 10, 1.0
+    e = np.linspace(0.0, math.pi * math.sqrt(2.0) / h, nb + 1)
+    nm, km = pk.shell_stats(n, h, nb, e)
+    assert nm.sum() == 32 * 32 - 1
