@@ -249,6 +249,20 @@ ce_status ce_estimate_pk(ce_ctx* ctx, const ce_geometry* geom, ce_precision prec
                          const float* mask_f, int32_t nbins, double* out_pk, int64_t* out_nmodes,
                          double* out_kmean, void* stream);
 
+/* ce_estimate_pk with user shells (the paper bins in ln l; or linear shells up to a kmax that
+ * takes the corners): kedges is a host array of nbins + 1 strictly ascending |k| values >= 0
+ * (units 1 / length, as h).  Mode q with t = nbins^2 L^2 (|k| h / pi)^2 (an exact integer, L the
+ * least common multiple of the N_i) is in shell b when TH_b < t <= TH_{b+1}, TH_b =
+ * nbins^2 L^2 (kedges[b] h / pi)^2 evaluated in FP64 in this order, rounded to the nearest
+ * integer when within 1e-9 relative of one and down otherwise (so edges placed on modes by an
+ * FP64 formula keep them in the lower shell, and linear edges on (0, pi/h] reproduce
+ * ce_estimate_pk bitwise).  out_nmodes and out_kmean are those of these shells.  Errors: as
+ * ce_estimate_pk; CE_E_INVALID for edges that are not finite, negative or ascending. */
+ce_status ce_estimate_pk_edges(ce_ctx* ctx, const ce_geometry* geom, ce_precision precision,
+                               ce_map_kind kind, const void* maps, int64_t count, const int64_t* ntot,
+                               const float* mask_f, int32_t nbins, const double* kedges, double* out_pk,
+                               int64_t* out_nmodes, double* out_kmean, void* stream);
+
 /* Spectrum covariance across realizations (Sec. 3.2: covariance from many simulations; the
  * normalised matrix of eq. cuminfo).  pk: count x nbins doubles (device).  out_cov (nullable):
  * nbins^2, Cov_ab = 1/(count-1) sum_r (P_ra - mean_a)(P_rb - mean_b).  out_cnorm (nullable):

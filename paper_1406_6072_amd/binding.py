@@ -99,6 +99,8 @@ _lognormal_poisson = _sig("ce_lognormal_poisson", c_i32, c_void_p, c_void_p, c_v
                           c_u32, c_u64, c_void_p, c_void_p, c_void_p, c_void_p)
 _estimate_pk = _sig("ce_estimate_pk", c_i32, c_void_p, ctypes.POINTER(Geometry), c_i32, c_i32, c_void_p, c_i64,
                     c_void_p, c_void_p, c_i32, c_void_p, c_void_p, c_void_p, c_void_p)
+_estimate_pk_edges = _sig("ce_estimate_pk_edges", c_i32, c_void_p, ctypes.POINTER(Geometry), c_i32, c_i32, c_void_p,
+                          c_i64, c_void_p, c_void_p, c_i32, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p)
 _pk_covariance = _sig("ce_pk_covariance", c_i32, c_void_p, c_void_p, c_i64, c_i32, c_void_p, c_void_p, c_void_p)
 _cumulative_information = _sig("ce_cumulative_information", c_i32, c_void_p, c_void_p, c_i32, c_void_p, c_void_p)
 _cic_predict = _sig("ce_cic_predict", c_i32, c_void_p, c_void_p, c_i64, c_f64, c_f64, c_i32, c_void_p, c_void_p)
@@ -132,7 +134,7 @@ EXPORTED = ["ce_status_string", "ce_version", "ce_ctx_create", "ce_ctx_destroy",
             "ce_ctx_set_option", "ce_ctx_set_profiling", "ce_ctx_profile_read",
             "ce_plan_embedding", "ce_plan_release", "ce_plan_get_info", "ce_plan_eigenvalues", "ce_xi_lag_octant",
             "ce_plan_periodic",
-            "ce_generate_fields", "ce_lognormal_poisson", "ce_estimate_pk", "ce_pk_covariance",
+            "ce_generate_fields", "ce_lognormal_poisson", "ce_estimate_pk", "ce_estimate_pk_edges", "ce_pk_covariance",
             "ce_cic_histogram", "ce_cic_predict", "ce_astar_map", "ce_cumulative_information",
             "ce_pipeline_run", "ce_pipeline_run_masked", "ce_pipeline_run_batch", "ce_pipeline_graph_create", "ce_pipeline_graph_launch",
             "ce_pipeline_graph_destroy",
@@ -388,18 +390,26 @@ def lognormal_poisson(ctx, plan, fields, count, nbar, mask_f, seed, request_id, 
 
 
 def estimate_pk(ctx, n, h, precision, kind, maps, count, ntot, mask_f, nbins, out_pk, out_nmodes=None,
-                out_kmean=None, stream=None):
+                out_kmean=None, stream=None, edges=None):
+    """edges: optional host sequence of nbins + 1 ascending |k| shell edges (ce_estimate_pk_edges)."""
     g = geometry(n, h)
     cells = 1
     for x in n:
         cells *= int(x)
     mdt = torch.int32 if kind == MAP_COUNTS_DELTAG else (torch.float64 if precision == F64 else torch.float32)
-    _check(_estimate_pk(ctx, ctypes.byref(g), int(precision), int(kind), _ptr(maps, mdt, count * cells, "maps"),
-                        int(count), _ptr(ntot, torch.int64, count, "ntot"), _ptr(mask_f, torch.float32, cells, "mask"),
-                        int(nbins), _ptr(out_pk, torch.float64, count * nbins, "out_pk"),
-                        _ptr(out_nmodes, torch.int64, nbins, "out_nmodes"),
-                        _ptr(out_kmean, torch.float64, nbins, "out_kmean"), _stream(stream)),
-           "ce_estimate_pk")
+    args = (_ptr(maps, mdt, count * cells, "maps"), int(count), _ptr(ntot, torch.int64, count, "ntot"),
+            _ptr(mask_f, torch.float32, cells, "mask"), int(nbins))
+    outs = (_ptr(out_pk, torch.float64, count * nbins, "out_pk"), _ptr(out_nmodes, torch.int64, nbins, "out_nmodes"),
+            _ptr(out_kmean, torch.float64, nbins, "out_kmean"), _stream(stream))
+    if edges is None:
+        _check(_estimate_pk(ctx, ctypes.byref(g), int(precision), int(kind), *args, *outs), "ce_estimate_pk")
+        return
+    import numpy as np
+    e = np.ascontiguousarray(edges, dtype=np.float64)
+    if e.size != nbins + 1:
+        raise ValueError("edges must hold nbins + 1 values")
+    _check(_estimate_pk_edges(ctx, ctypes.byref(g), int(precision), int(kind), *args,
+                              e.ctypes.data_as(c_void_p), *outs), "ce_estimate_pk_edges")
 
 
 def pk_covariance(ctx, pk, count, nbins, out_cov, out_cnorm, stream=None):

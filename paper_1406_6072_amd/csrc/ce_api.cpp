@@ -169,7 +169,7 @@ struct ce_ctx {
     size_t n = 0;
     hipStream_t used = nullptr;  // stream of the last call that used the buffer
   };
-  Buf ws[13];
+  Buf ws[14];
   // pinned host staging of batch tables; `staged` is recorded after the copy that reads it
   void* pin = nullptr;
   size_t pin_n = 0;
@@ -518,8 +518,27 @@ bool shell_rule(const int* n, int ndim, int nb, ShellRule& r) {
   return tmax < 1e17 && (double)(nb + 2) * (nb + 2) * (double)r.LL < 1e17;
 }
 
-// Shell table (nmodes and mean |k| in units of 1 / h) of a grid, host, exact integers.
-void shell_table_host(const int* n, int ndim, int nb, std::vector<int64_t>& nm, std::vector<double>& km) {
+// Integer thresholds of user shell edges e_0 < ... < e_nb (|k|, cell side h): TH_b is
+// v = nb^2 L^2 (e_b h / pi)^2 in FP64 (in this order), the nearest integer when v lies within
+// 1e-9 v of one, else floor(v); a mode with t is in shell b when TH_b < t <= TH_{b+1}.
+void shell_thresholds(const int* n, int ndim, double h, int nb, const double* edges, std::vector<int64_t>& th) {
+  int64_t L = 1;
+  for (int i = 0; i < ndim; ++i) L = L / std::gcd(L, (int64_t)n[i]) * n[i];
+  const double scale = (double)((int64_t)nb * nb * L * L);
+  th.resize(nb + 1);
+  for (int b = 0; b <= nb; ++b) {
+    const double x = edges[b] * h / M_PI;
+    const double v = scale * (x * x);
+    const double r = std::floor(v + 0.5);
+    const double c = std::fabs(v - r) <= 1e-9 * v ? r : std::floor(v);
+    th[b] = c >= 4.0e18 ? (int64_t)4e18 : (int64_t)c;
+  }
+}
+
+// Shell table (nmodes and mean |k| in units of 1 / h) of a grid, host, exact integers; th
+// (nullable): user shells as thresholds of t.
+void shell_table_host(const int* n, int ndim, int nb, std::vector<int64_t>& nm, std::vector<double>& km,
+                      const std::vector<int64_t>* th = nullptr) {
   ShellRule sr;
   shell_rule(n, ndim, nb, sr);
   nm.assign(nb, 0);
@@ -532,11 +551,15 @@ void shell_table_host(const int* n, int ndim, int nb, std::vector<int64_t>& nm, 
       for (int c = 0; c < n2; ++c) {
         const int64_t qc = ndim >= 3 ? (c <= n2 / 2 ? c : c - n2) : 0;
         const int64_t t = sr.T[0] * qa * qa + sr.T[1] * qb * qb + sr.T[2] * qc * qc;
-        // smallest s >= 0 with s^2 L^2 >= t
-        int64_t s = (int64_t)std::sqrt((double)t / (double)sr.LL);
-        while (s > 0 && (s - 1) * (s - 1) * sr.LL >= t) --s;
-        while (s * s * sr.LL < t) ++s;
-        const int64_t bin = s - 1;
+        int64_t bin;
+        if (th) {  // number of thresholds below t, minus one
+          bin = (int64_t)(std::lower_bound(th->begin(), th->end(), t) - th->begin()) - 1;
+        } else {   // smallest s >= 0 with s^2 L^2 >= t
+          int64_t s = (int64_t)std::sqrt((double)t / (double)sr.LL);
+          while (s > 0 && (s - 1) * (s - 1) * sr.LL >= t) --s;
+          while (s * s * sr.LL < t) ++s;
+          bin = s - 1;
+        }
         if (bin >= 0 && bin < nb) {
           nm[bin] += 1;
           const double fa = (double)qa / n0, fb = (double)qb / n1, fc = (double)qc / n2;
@@ -1113,7 +1136,7 @@ ce_status run_inverse(ce_ctx* ctx, const ce_plan* p, const InverseSetup& fs, uin
 // shell sums; partials per item.
 ce_status run_forward_bins(ce_ctx* ctx, int ndim, const int* n, int prec, int64_t nitems, void* H, int nb,
                            double** partials_out, int64_t* groups_out, hipStream_t s,
-                           const BinArgs* window = nullptr) {
+                           const BinArgs* window = nullptr, const int64_t* th = nullptr) {
   const size_t elem = prec ? 16 : 8;
   const int N = n[0];
   const int W = 2 * (n[ndim - 1] / 2 + 1);
@@ -1146,6 +1169,7 @@ ce_status run_forward_bins(ce_ctx* ctx, int ndim, const int* n, int prec, int64_
   ba.T1 = ndim == 3 ? sr.T[1] : 0;
   ba.Tl = sr.T[ndim - 1];
   ba.LL = sr.LL;
+  ba.th = th;
   ba.partials = static_cast<double*>(part);
   if (window) {
     ba.win = window->win;
@@ -1257,7 +1281,8 @@ ce_status pipeline_impl(ce_ctx* ctx, const ce_plan* plan, uint64_t seed, uint32_
 // load, remaining forward passes, shell sums, reduction): the standalone estimator and the
 // spectrum stage of the masked pipeline.
 ce_status spectrum_impl(ce_ctx* ctx, int ndim, const int* n, double h, int prec, PairLoad pl, int64_t count,
-                        int32_t nbins, double* out_pk, int64_t* out_nmodes, double* out_kmean, hipStream_t s) {
+                        int32_t nbins, double* out_pk, int64_t* out_nmodes, double* out_kmean, hipStream_t s,
+                        const double* edges = nullptr) {
   int64_t ncells = 1;
   for (int d = 0; d < ndim; ++d) ncells *= n[d];
   const int64_t nitems = (count + 1) / 2;
@@ -1273,12 +1298,29 @@ ce_status spectrum_impl(ce_ctx* ctx, int ndim, const int* n, double h, int prec,
   CE_TRY(build_fft(ctx, Nl, prec, fl));
   LineGeom g1 = make_geom(Nl, Nl, rows, 1, nitems, 0, 0, elem, mixed_radix(fl), 1, 1024);
   CE_PROF(ctx, "forward_rows_pair", s, launch_pair_forward(prec, g1, fl, pl, s));
-  double* partials = nullptr;
-  int64_t groups = 0;
-  CE_TRY(run_forward_bins(ctx, ndim, n, prec, nitems, H, nbins, &partials, &groups, s));
+  // user shell edges: thresholds and shell table for this call (scratch slot 13: [th | nmodes])
+  const int64_t* th_dev = nullptr;
   int64_t* nm = nullptr;
   const std::vector<double>* km = nullptr;
-  CE_TRY(device_shells(ctx, n, ndim, nbins, &nm, &km));
+  std::vector<double> km_user;
+  if (edges) {
+    std::vector<int64_t> th, nmu;
+    shell_thresholds(n, ndim, h, nbins, edges, th);
+    shell_table_host(n, ndim, nbins, nmu, km_user, &th);
+    std::vector<int64_t> tab(th);
+    tab.insert(tab.end(), nmu.begin(), nmu.end());
+    void* p = nullptr;
+    CE_TRY(ctx->scratch(13, sizeof(int64_t) * tab.size(), &p));
+    CE_HIP(hipMemcpyAsync(p, tab.data(), sizeof(int64_t) * tab.size(), hipMemcpyHostToDevice, s));
+    CE_HIP(hipStreamSynchronize(s));  // the host table goes out of scope
+    th_dev = static_cast<const int64_t*>(p);
+    nm = static_cast<int64_t*>(p) + (nbins + 1);
+    km = &km_user;
+  }
+  double* partials = nullptr;
+  int64_t groups = 0;
+  CE_TRY(run_forward_bins(ctx, ndim, n, prec, nitems, H, nbins, &partials, &groups, s, nullptr, th_dev));
+  if (!edges) CE_TRY(device_shells(ctx, n, ndim, nbins, &nm, &km));
   const double norm = std::pow(h, ndim) / (double)ncells;
   CE_PROF(ctx, "bin_reduce", s, launch_bin_reduce(partials, nitems, groups, nbins, count, nm, norm, 0, nullptr, nullptr, (double)ncells,
                            out_pk, ctx->flags, s));
@@ -1292,9 +1334,6 @@ ce_status spectrum_impl(ce_ctx* ctx, int ndim, const int* n, double h, int prec,
   return CE_OK;
 }
 
-// The pipeline on a masked survey: the fused pass samples counts with rate nbar f rho and
-// stores them (no forward transform); the spectrum stage then forms delta_g = (N/f - N^)/N^ on
-// f != 0 with N^ = N_tot / sum f (eq. Estim) as the standalone estimator does.
 // Forward transform Wm of the indicator f != 0 of a 2-D mask (the spectra's row pass on the map
 // [f != 0] with an empty second map, then the axis-0 line transform), N_0 x W complex in the
 // plan precision in scratch slot 12, [q0][column] like the spectra.
@@ -1325,6 +1364,10 @@ ce_status window_transform(ce_ctx* ctx, const ce_plan* plan, const float* mask, 
   return CE_OK;
 }
 
+// The pipeline on a masked survey (rate nbar f rho; delta_g = (N/f - N^)/N^ on f != 0 with
+// N^ = N_tot / sum f, eq. Estim).  2-D: fused, the contrast completed in the binning pass with
+// the window transform.  3-D: the fused pass stores the counts (no forward transform) and the
+// spectrum stage forms delta_g from them as the standalone estimator does.
 ce_status pipeline_masked_impl(ce_ctx* ctx, const ce_plan* plan, const float* mask, uint64_t seed,
                                uint32_t request_id, uint64_t first_realization, int64_t count, double nbar,
                                int32_t nbins, void* out_fields, void* out_delta, int32_t* out_counts,
@@ -1647,9 +1690,10 @@ ce_status ce_fft_factors(int32_t length, int32_t* radices, int32_t* nstages) {
   return CE_OK;
 }
 
-ce_status ce_estimate_pk(ce_ctx* ctx, const ce_geometry* geom, ce_precision precision, ce_map_kind kind,
-                         const void* maps, int64_t count, const int64_t* ntot, const float* mask_f, int32_t nbins,
-                         double* out_pk, int64_t* out_nmodes, double* out_kmean, void* stream) {
+static ce_status estimate_common(ce_ctx* ctx, const ce_geometry* geom, ce_precision precision, ce_map_kind kind,
+                                 const void* maps, int64_t count, const int64_t* ntot, const float* mask_f,
+                                 int32_t nbins, const double* edges, double* out_pk, int64_t* out_nmodes,
+                                 double* out_kmean, void* stream) {
   if (!ctx || !geom || !maps || !out_pk || count <= 0 || nbins <= 0) return CE_E_INVALID;
   if (precision != CE_F32 && precision != CE_F64) return CE_E_INVALID;
   if (kind != CE_MAP_FIELD && kind != CE_MAP_COUNTS_DELTAG) return CE_E_INVALID;
@@ -1699,7 +1743,25 @@ ce_status ce_estimate_pk(ce_ctx* ctx, const ce_geometry* geom, ce_precision prec
       pl.ntot = sgn;
     }
   }
-  return spectrum_impl(ctx, ndim, n, geom->h[0], prec, pl, count, nbins, out_pk, out_nmodes, out_kmean, s);
+  return spectrum_impl(ctx, ndim, n, geom->h[0], prec, pl, count, nbins, out_pk, out_nmodes, out_kmean, s, edges);
+}
+
+ce_status ce_estimate_pk(ce_ctx* ctx, const ce_geometry* geom, ce_precision precision, ce_map_kind kind,
+                         const void* maps, int64_t count, const int64_t* ntot, const float* mask_f, int32_t nbins,
+                         double* out_pk, int64_t* out_nmodes, double* out_kmean, void* stream) {
+  return estimate_common(ctx, geom, precision, kind, maps, count, ntot, mask_f, nbins, nullptr, out_pk, out_nmodes,
+                         out_kmean, stream);
+}
+
+ce_status ce_estimate_pk_edges(ce_ctx* ctx, const ce_geometry* geom, ce_precision precision, ce_map_kind kind,
+                               const void* maps, int64_t count, const int64_t* ntot, const float* mask_f,
+                               int32_t nbins, const double* kedges, double* out_pk, int64_t* out_nmodes,
+                               double* out_kmean, void* stream) {
+  if (!kedges || nbins <= 0) return CE_E_INVALID;
+  for (int b = 0; b <= nbins; ++b)
+    if (!std::isfinite(kedges[b]) || kedges[b] < 0 || (b > 0 && !(kedges[b] > kedges[b - 1]))) return CE_E_INVALID;
+  return estimate_common(ctx, geom, precision, kind, maps, count, ntot, mask_f, nbins, kedges, out_pk, out_nmodes,
+                         out_kmean, stream);
 }
 
 ce_status ce_pk_covariance(ce_ctx* ctx, const double* pk, int64_t count, int32_t nbins, double* out_cov,

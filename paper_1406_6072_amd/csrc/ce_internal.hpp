@@ -126,6 +126,9 @@ struct BinArgs {
   // shell rule: mode q~ is in shell s - 1 for the smallest s with s^2 LL >= T0 q~_0^2 + T1 q~_1^2
   // + Tl q~_last^2 (LL = lcm(sides)^2, T_i = 4 nb^2 lcm^2 / N_i^2; cubic: LL = N^2, T = 4 nb^2)
   int64_t T0 = 0, T1 = 0, Tl = 0, LL = 1;
+  // nullable: user shell edges as integer thresholds of t (nb + 1, device): shell b holds
+  // TH_b < t <= TH_{b+1} instead of the linear rule
+  const int64_t* th = nullptr;
   double* partials = nullptr;  // [item][group][2][nb]
   // Masked 2-D fused pipeline (nullable win): the lines hold the transform A of N / (f nest) - 1
   // on f != 0; the contrast's transform is D = r A + (r - 1) Wm with r = nest sum(f) / N_tot of

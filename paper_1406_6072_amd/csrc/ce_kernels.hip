@@ -711,6 +711,20 @@ __device__ __forceinline__ int shell_of_t(int64_t t, int64_t NN) {
   return (int)(s - 1);
 }
 
+// shell of t under user thresholds th[0..nb]: b with th[b] < t <= th[b+1]; -1 below th[0], nb
+// above th[nb] (binary search)
+__device__ __forceinline__ int shell_of_tab(int64_t t, const int64_t* th, int nb) {
+  int lo = 0, hi = nb + 1;  // count of thresholds below t lies in [lo, hi]
+  while (lo < hi) {
+    const int mid = (lo + hi) >> 1;
+    if (th[mid] < t)
+      lo = mid + 1;
+    else
+      hi = mid;
+  }
+  return lo - 1;
+}
+
 struct RunEnds {
   int first_bin, last_bin;
   double first_sum, last_sum;
@@ -720,7 +734,7 @@ struct RunEnds {
 // Binning of one line group already transformed in LDS (lines r < nl of the group that
 // starts at line0); adds the group's per-shell sums, lines in order, to tot[2][nb]
 // (entry t is read and written by thread t only).
-template <typename T, int WIN>
+template <typename T, int WIN, int TAB>
 __device__ __forceinline__ void bin_group(const cpx<T>* res, const LineGeom& g, const BinArgs& bn, int64_t item,
                                           int64_t line0, int nl, double* acc, RunEnds* ends, double* tot) {
   const int r = threadIdx.x / g.nlanes, lane = threadIdx.x - r * g.nlanes;
@@ -764,9 +778,9 @@ __device__ __forceinline__ void bin_group(const cpx<T>* res, const LineGeom& g, 
         int64_t t = Tq * (int64_t)a0 * a0 + p2;
         int64_t dt = Tq * (2 * (int64_t)a0 + 1);
         const int64_t ddt = 2 * Tq;
-        int bin = shell_of_t(t, NN);
-        // (bin+1)^2 LL: the mode stays in `bin` while t <= edge
-        int64_t edge = (int64_t)(bin + 1) * (bin + 1) * NN;
+        int bin = TAB ? shell_of_tab(t, bn.th, nb) : shell_of_t(t, NN);
+        // the mode stays in `bin` while t <= edge: (bin+1)^2 LL (linear shells) or th[bin+1]
+        int64_t edge = TAB ? (bin < nb ? bn.th[bin + 1] : INT64_MAX) : (int64_t)(bin + 1) * (bin + 1) * NN;
         int64_t estep = (int64_t)(2 * bin + 3) * NN;  // edge(bin + 1) - edge(bin)
         double run = 0.0;
         e.first_bin = bin;
@@ -782,8 +796,12 @@ __device__ __forceinline__ void bin_group(const cpx<T>* res, const LineGeom& g, 
             // next shell that holds the mode (t grows slowly: usually one step)
             do {
               ++bin;
-              edge += estep;
-              estep += 2 * NN;
+              if (TAB) {
+                edge = bin < nb ? bn.th[bin + 1] : INT64_MAX;
+              } else {
+                edge += estep;
+                estep += 2 * NN;
+              }
             } while (t > edge);
             run = 0.0;
           }
@@ -856,7 +874,7 @@ __device__ __forceinline__ void bin_group(const cpx<T>* res, const LineGeom& g, 
   }
 }
 
-template <typename T, int MIX, int WIN>
+template <typename T, int MIX, int WIN, int TAB>
 __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 4 : 2))) k_bin_pass(LineGeom g, FftDesc f, BinArgs bn, const cpx<T>* in) {
   cpx<T>* lds = lds_lines<T>();
   const PassPos pp = pass_pos(g);
@@ -869,7 +887,7 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(sizeof
   __syncthreads();
   const int r = threadIdx.x / g.nlanes, lane = threadIdx.x - r * g.nlanes;
   line_fft<T, -1, MIX>(buf_a(lds, g, r), buf_b(lds, g, r), f, lane, g.nlanes, r < pp.nl, f.L);
-  bin_group<T, WIN>(result_base<T, MIX>(lds, g, f), g, bn, pp.item, pp.line0, pp.nl, acc, ends, tot);
+  bin_group<T, WIN, TAB>(result_base<T, MIX>(lds, g, f), g, bn, pp.item, pp.line0, pp.nl, acc, ends, tot);
   for (int t = threadIdx.x; t < 2 * bn.nb; t += blockDim.x)
     bn.partials[(pp.item * g.groups_per_item + pp.grp) * 2 * bn.nb + t] = tot[t];
 }
@@ -1258,9 +1276,11 @@ static void bin_pass_t(int mix, const LineGeom& g, const FftDesc& f, const BinAr
   const cpx<T>* i = static_cast<const cpx<T>*>(in);
   with_variant(mix, [&](auto v) {
     if (b.win)
-      CE_LAUNCH((k_bin_pass<T, decltype(v)::value, 1>), pass_grid(g), pass_block(g), lds, s, g, f, b, i);
+      CE_LAUNCH((k_bin_pass<T, decltype(v)::value, 1, 0>), pass_grid(g), pass_block(g), lds, s, g, f, b, i);
+    else if (b.th)
+      CE_LAUNCH((k_bin_pass<T, decltype(v)::value, 0, 1>), pass_grid(g), pass_block(g), lds, s, g, f, b, i);
     else
-      CE_LAUNCH((k_bin_pass<T, decltype(v)::value, 0>), pass_grid(g), pass_block(g), lds, s, g, f, b, i);
+      CE_LAUNCH((k_bin_pass<T, decltype(v)::value, 0, 0>), pass_grid(g), pass_block(g), lds, s, g, f, b, i);
   });
 }
 

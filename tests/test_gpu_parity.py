@@ -501,3 +501,85 @@ def test_masked_pipeline_matches_unfused_and_oracle(ce, n, prec, nb):
     rcov, _ = opk.covariance(p.cpu().numpy().reshape(count, nb))
     assert rel(cov.cpu().numpy().reshape(nb, nb), rcov) <= 1e-12
     plan.release()
+
+
+@pytest.mark.parametrize("n,prec", [((64, 64), 1), ((48, 80), 0), ((16, 24, 12), 1)])
+def test_linear_edges_equal_default_shells(ce, n, prec):
+    """Linear shell edges on (0, pi/h] through ce_estimate_pk_edges give ce_estimate_pk bitwise."""
+    import math
+    b, ctx = ce
+    nb, count = 9, 3
+    plan = b.plan_embedding(ctx, n, (1.0,) * len(n), dict(kind="exp", sigma2=1.0, a=2.0), prec)
+    g = gpu_fields(b, ctx, plan, 5, 0, 0, count)
+    p1 = torch.empty(count * nb, dtype=torch.float64, device="cuda")
+    p2 = torch.empty_like(p1)
+    m1 = torch.empty(nb, dtype=torch.int64, device="cuda")
+    m2 = torch.empty_like(m1)
+    b.estimate_pk(ctx, n, (1.0,) * len(n), prec, b.MAP_FIELD, g, count, None, None, nb, p1, m1)
+    b.estimate_pk(ctx, n, (1.0,) * len(n), prec, b.MAP_FIELD, g, count, None, None, nb, p2, m2,
+                  edges=np.linspace(0.0, math.pi, nb + 1))
+    torch.cuda.synchronize()
+    assert torch.equal(p1, p2) and torch.equal(m1, m2)
+    plan.release()
+
+
+@pytest.mark.parametrize("n,prec,masked", [((128, 128), 1, False), ((96, 64), 0, True), ((20, 16, 24), 0, False)])
+def test_log_edges_match_oracle(ce, n, prec, masked):
+    """The paper's binning, 20 shells equally spaced in ln k up to the pixel scale, against the
+    oracle (field maps; counts with a mask)."""
+    import math
+    from synth import workloads
+    b, ctx = ce
+    nb, count = 20, 4
+    h = 0.5
+    edges = np.exp(np.linspace(math.log(math.pi / h / 30.0), math.log(math.pi / h), nb + 1))
+    # a shorter range in 3-D keeps the small embedding positive definite
+    plan = b.plan_embedding(ctx, n, (h,) * len(n), dict(kind="exp", sigma2=1.0, a=2.0 if len(n) == 2 else 0.6), prec)
+    cells = plan.cells
+    p = torch.empty(count * nb, dtype=torch.float64, device="cuda")
+    nm = torch.empty(nb, dtype=torch.int64, device="cuda")
+    km = torch.empty(nb, dtype=torch.float64, device="cuda")
+    if masked:
+        mask_np = workloads.survey_mask(n, seed=2)
+        mask = torch.from_numpy(mask_np.ravel()).cuda()
+        c = torch.empty(count * cells, dtype=torch.int32, device="cuda")
+        nt = torch.empty(count, dtype=torch.int64, device="cuda")
+        pk0 = torch.empty(count * 8, dtype=torch.float64, device="cuda")
+        b.pipeline_run_masked(ctx, plan, mask, 4, 2, 0, count, 3.0, 8, pk0, out_counts=c, out_ntot=nt)
+        b.estimate_pk(ctx, n, (h,) * len(n), prec, b.MAP_COUNTS_DELTAG, c, count, nt, mask, nb, p, nm, km,
+                      edges=edges)
+        torch.cuda.synchronize()
+        ref = opk.estimate_pk(c.cpu().numpy().reshape((count,) + n), h, nb, kind="counts",
+                              ntot=nt.cpu().numpy(), mask=mask_np, edges=edges)
+    else:
+        g = gpu_fields(b, ctx, plan, 6, 0, 0, count)
+        b.estimate_pk(ctx, n, (h,) * len(n), prec, b.MAP_FIELD, g, count, None, None, nb, p, nm, km, edges=edges)
+        torch.cuda.synchronize()
+        ref = opk.estimate_pk(g.cpu().numpy().astype(np.float64).reshape((count,) + n), h, nb, edges=edges)
+    got = p.cpu().numpy().reshape(count, nb)
+    onm, okm = opk.shell_stats(n, h, nb, edges)
+    assert np.array_equal(nm.cpu().numpy(), onm)
+    ok = onm > 0
+    assert np.allclose(km.cpu().numpy()[ok], okm[ok], rtol=1e-13)
+    assert np.max(np.abs(got[:, ok] / ref[:, ok] - 1)) <= TOL_PK[prec]
+    plan.release()
+
+
+def test_shell_edge_errors_and_corners(ce):
+    import math
+    b, ctx = ce
+    n, nb = (32, 32), 10
+    plan = b.plan_embedding(ctx, n, (1.0, 1.0), dict(kind="exp", sigma2=1.0, a=2.0), b.F32)
+    g = gpu_fields(b, ctx, plan, 5, 0, 0, 2)
+    p = torch.empty(2 * nb, dtype=torch.float64, device="cuda")
+    nm = torch.empty(nb, dtype=torch.int64, device="cuda")
+    # edges up to pi sqrt(2) / h take the corners: every mode but DC is binned
+    b.estimate_pk(ctx, n, (1.0, 1.0), b.F32, b.MAP_FIELD, g, 2, None, None, nb, p, nm,
+                  edges=np.linspace(0.0, math.pi * math.sqrt(2.0), nb + 1))
+    torch.cuda.synchronize()
+    assert int(nm.sum()) == 32 * 32 - 1
+    for bad in (np.linspace(1.0, 0.0, nb + 1), np.full(nb + 1, 1.0), np.r_[-1.0, np.linspace(0, 3, nb)]):
+        with pytest.raises(b.CeError) as e:
+            b.estimate_pk(ctx, n, (1.0, 1.0), b.F32, b.MAP_FIELD, g, 2, None, None, nb, p, edges=bad)
+        assert e.value.status == b.E_INVALID
+    plan.release()
