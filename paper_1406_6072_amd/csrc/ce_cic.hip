@@ -138,18 +138,18 @@ __device__ __forceinline__ double astar_solve(int32_t n, float f, double lnb, do
   return a;
 }
 
-// MODE 0: write A* (0 on masked cells).  MODE 1: per-workgroup sums of A* and of the
-// number of unmasked cells into partials[(r * gridDim.x + block) * 2 + {0, 1}], no map
-// written.  MODE 2: write A* - mean[r] on unmasked cells, 0 on masked cells.
+// MODE 0: write A* (0 on masked cells).  MODE 1: write A* - off (0 on masked cells) and the
+// per-workgroup sums of A* and of the number of unmasked cells into
+// partials[(r * gridDim.x + block) * 2 + {0, 1}].  The map minus its mean is then written by
+// k_astar_shift from the stored values (one solve per cell); off, an estimate of the mean (the
+// prior mean of the log-density), keeps the stored values centred so an FP32 map loses no digits.
 template <typename T, int MODE>
 __global__ void __launch_bounds__(kCicThreads) k_astar(const int32_t* __restrict__ counts,
                                                        const float* __restrict__ mask, int64_t cells,
-                                                       double nbar, double lnb, double s2, T* __restrict__ out,
-                                                       double* __restrict__ partials,
-                                                       const double* __restrict__ mean) {
+                                                       double nbar, double lnb, double s2, double off,
+                                                       T* __restrict__ out, double* __restrict__ partials) {
   const int r = blockIdx.y;
   const int32_t* c = counts + (int64_t)r * cells;
-  const double m = MODE == 2 ? mean[r] : 0.0;
   double acc = 0.0, nk = 0.0;
   const int64_t stride = (int64_t)gridDim.x * kCicThreads;
   for (int64_t i = blockIdx.x * (int64_t)kCicThreads + threadIdx.x; i < cells; i += stride) {
@@ -159,9 +159,9 @@ __global__ void __launch_bounds__(kCicThreads) k_astar(const int32_t* __restrict
       a = astar_solve(c[i], f, lnb, (nbar * (double)f) * s2, s2);
       acc += a;
       nk += 1.0;
-      a -= m;
+      a -= off;
     }
-    if (MODE != 1) out[(int64_t)r * cells + i] = (T)a;
+    out[(int64_t)r * cells + i] = (T)a;
   }
   if (MODE == 1) {
     __shared__ double sa[kCicThreads], sn[kCicThreads];
@@ -181,6 +181,19 @@ __global__ void __launch_bounds__(kCicThreads) k_astar(const int32_t* __restrict
       p[1] = sn[0];
     }
   }
+}
+
+// A* - mean[r] on unmasked cells from the stored A* - off (masked cells stay 0).
+template <typename T>
+__global__ void __launch_bounds__(kCicThreads) k_astar_shift(const float* __restrict__ mask, int64_t cells,
+                                                             double off, const double* __restrict__ mean,
+                                                             T* __restrict__ out) {
+  const int r = blockIdx.y;
+  const double d = mean[r] - off;
+  T* o = out + (int64_t)r * cells;
+  const int64_t stride = (int64_t)gridDim.x * kCicThreads;
+  for (int64_t i = blockIdx.x * (int64_t)kCicThreads + threadIdx.x; i < cells; i += stride)
+    if (mask == nullptr || mask[i] != 0.0f) o[i] = (T)((double)o[i] - d);
 }
 
 // mean[r] = (sum of A*) / (unmasked cells) from the partials of one map, in a fixed order;
@@ -209,14 +222,13 @@ __global__ void __launch_bounds__(kCicThreads) k_astar_mean(const double* __rest
 
 template <typename T, int MODE>
 hipError_t astar_launch(const int32_t* counts, const float* mask, int64_t cells, int64_t count, double nbar,
-                        double s2, T* out, double* partials, const double* mean, hipStream_t s) {
+                        double s2, double off, T* out, double* partials, hipStream_t s) {
   const int64_t bx = blocks_per_map(cells);
   for (int64_t r0 = 0; r0 < count; r0 += kGridY) {
     const int64_t nr = count - r0 < kGridY ? count - r0 : kGridY;
     hipLaunchKernelGGL((k_astar<T, MODE>), dim3((unsigned)bx, (unsigned)nr), dim3(kCicThreads), 0, s,
-                       counts + r0 * cells, mask, cells, nbar, log(nbar * s2), s2,
-                       MODE == 1 ? nullptr : out + r0 * cells,
-                       MODE == 1 ? partials + r0 * bx * 2 : nullptr, MODE == 2 ? mean + r0 : nullptr);
+                       counts + r0 * cells, mask, cells, nbar, log(nbar * s2), s2, off, out + r0 * cells,
+                       MODE == 1 ? partials + r0 * bx * 2 : nullptr);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
@@ -226,16 +238,23 @@ hipError_t astar_launch(const int32_t* counts, const float* mask, int64_t cells,
 template <typename T>
 hipError_t astar_all(const int32_t* counts, const float* mask, int64_t cells, int64_t count, double nbar,
                      double s2, bool subtract, T* out, double* partials, double* mean, hipStream_t s) {
-  if (mean) {
-    hipError_t e = astar_launch<T, 1>(counts, mask, cells, count, nbar, s2, out, partials, nullptr, s);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_astar_mean, dim3((unsigned)count), dim3(kCicThreads), 0, s, partials,
-                       blocks_per_map(cells), mean);
+  if (!mean) return astar_launch<T, 0>(counts, mask, cells, count, nbar, s2, 0.0, out, nullptr, s);
+  const double off = subtract ? -0.5 * s2 : 0.0;
+  hipError_t e = astar_launch<T, 1>(counts, mask, cells, count, nbar, s2, off, out, partials, s);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_astar_mean, dim3((unsigned)count), dim3(kCicThreads), 0, s, partials, blocks_per_map(cells),
+                     mean);
+  e = hipGetLastError();
+  if (e != hipSuccess || !subtract) return e;
+  const int64_t bx = blocks_per_map(cells);
+  for (int64_t r0 = 0; r0 < count; r0 += kGridY) {
+    const int64_t nr = count - r0 < kGridY ? count - r0 : kGridY;
+    hipLaunchKernelGGL((k_astar_shift<T>), dim3((unsigned)bx, (unsigned)nr), dim3(kCicThreads), 0, s, mask, cells,
+                       off, mean + r0, out + r0 * cells);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
-  if (subtract) return astar_launch<T, 2>(counts, mask, cells, count, nbar, s2, out, partials, mean, s);
-  return astar_launch<T, 0>(counts, mask, cells, count, nbar, s2, out, partials, mean, s);
+  return hipSuccess;
 }
 
 // Mean histogram under the model (Sec. 3.4): <P^(N)> = int dA G(A) sum_{f_i != 0} Pois(N; nbar
