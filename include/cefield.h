@@ -335,6 +335,16 @@ ce_status ce_pipeline_run(ce_ctx* ctx, const ce_plan* plan, uint64_t seed, uint3
                           int64_t* out_ntot, double* out_pk, double* out_cov, double* out_cnorm,
                           void* stream);
 
+/* ce_pipeline_run with the user shells of ce_estimate_pk_edges (kedges: host, nbins + 1 strictly
+ * ascending |k| values >= 0; the paper bins in ln l).  Everything else as ce_pipeline_run; linear
+ * edges on (0, pi/h] give its results bitwise.  Errors: as ce_pipeline_run; CE_E_INVALID for bad
+ * edges. */
+ce_status ce_pipeline_run_edges(ce_ctx* ctx, const ce_plan* plan, uint64_t seed, uint32_t request_id,
+                                uint64_t first_realization, int64_t count, double nbar, int32_t nbins,
+                                const double* kedges, void* out_fields, void* out_delta, int32_t* out_counts,
+                                int64_t* out_ntot, double* out_pk, double* out_cov, double* out_cnorm,
+                                void* stream);
+
 /* ce_pipeline_run on a masked survey (Sec. 3.1, eq. sampling; Sec. 3.2, eq. Estim): mask_f
  * (device, N^d floats in [0, 1], row-major, caller-owned) is the surface fraction f of each
  * survey cell.  Counts are drawn with rate nbar f rho; the spectra are those of

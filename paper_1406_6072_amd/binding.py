@@ -115,6 +115,8 @@ _graph_launch = _sig("ce_pipeline_graph_launch", c_i32, c_void_p, c_void_p)
 _graph_destroy = _sig("ce_pipeline_graph_destroy", None, c_void_p)
 _pipeline_masked = _sig("ce_pipeline_run_masked", c_i32, c_void_p, c_void_p, c_void_p, c_u64, c_u32, c_u64, c_i64,
                         c_f64, c_i32, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p)
+_pipeline_edges = _sig("ce_pipeline_run_edges", c_i32, c_void_p, c_void_p, c_u64, c_u32, c_u64, c_i64, c_f64, c_i32,
+                       c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p)
 _pipeline_batch = _sig("ce_pipeline_run_batch", c_i32, c_void_p, ctypes.POINTER(BatchItem), c_i64, c_void_p)
 _server_create = _sig("ce_server_create", c_i32, c_i32, ctypes.POINTER(ServerConfig), ctypes.POINTER(c_void_p))
 _server_submit = _sig("ce_server_submit", c_i32, c_void_p, ctypes.POINTER(Request), ctypes.POINTER(c_u64))
@@ -136,7 +138,7 @@ EXPORTED = ["ce_status_string", "ce_version", "ce_ctx_create", "ce_ctx_destroy",
             "ce_plan_periodic",
             "ce_generate_fields", "ce_lognormal_poisson", "ce_estimate_pk", "ce_estimate_pk_edges", "ce_pk_covariance",
             "ce_cic_histogram", "ce_cic_predict", "ce_astar_map", "ce_cumulative_information",
-            "ce_pipeline_run", "ce_pipeline_run_masked", "ce_pipeline_run_batch", "ce_pipeline_graph_create", "ce_pipeline_graph_launch",
+            "ce_pipeline_run", "ce_pipeline_run_edges", "ce_pipeline_run_masked", "ce_pipeline_run_batch", "ce_pipeline_graph_create", "ce_pipeline_graph_launch",
             "ce_pipeline_graph_destroy",
             "ce_server_create", "ce_server_submit", "ce_server_poll", "ce_server_drain", "ce_server_cancel",
             "ce_server_stats_read", "ce_server_destroy", "ce_shell_table", "ce_fft_factors", "ce_debug_philox", "ce_debug_noise"]
@@ -460,6 +462,27 @@ def pipeline_run(ctx, plan, seed, request_id, first_realization, count, nbar, nb
                          _ptr(out_cov, torch.float64, nbins * nbins, "out_cov"),
                          _ptr(out_cnorm, torch.float64, nbins * nbins, "out_cnorm"), _stream(stream)),
            "ce_pipeline_run")
+
+
+def pipeline_run_edges(ctx, plan, seed, request_id, first_realization, count, nbar, nbins, edges, out_pk,
+                       out_fields=None, out_delta=None, out_counts=None, out_ntot=None, out_cov=None, out_cnorm=None,
+                       stream=None):
+    """The fused path with user shell edges (host sequence of nbins + 1 ascending |k| values)."""
+    import numpy as np
+    e = np.ascontiguousarray(edges, dtype=np.float64)
+    if e.size != nbins + 1:
+        raise ValueError("edges must hold nbins + 1 values")
+    cells = plan.cells
+    _check(_pipeline_edges(ctx, plan.handle, int(seed), int(request_id), int(first_realization), int(count),
+                           float(nbar), int(nbins), e.ctypes.data_as(c_void_p),
+                           _ptr(out_fields, plan.dtype, count * cells, "out_fields"),
+                           _ptr(out_delta, plan.dtype, count * cells, "out_delta"),
+                           _ptr(out_counts, torch.int32, count * cells, "out_counts"),
+                           _ptr(out_ntot, torch.int64, count, "out_ntot"),
+                           _ptr(out_pk, torch.float64, count * nbins, "out_pk"),
+                           _ptr(out_cov, torch.float64, nbins * nbins, "out_cov"),
+                           _ptr(out_cnorm, torch.float64, nbins * nbins, "out_cnorm"), _stream(stream)),
+           "ce_pipeline_run_edges")
 
 
 def pipeline_run_masked(ctx, plan, mask, seed, request_id, first_realization, count, nbar, nbins, out_pk,

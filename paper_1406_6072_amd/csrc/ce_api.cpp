@@ -1208,7 +1208,8 @@ ce_status pipeline_impl(ce_ctx* ctx, const ce_plan* plan, uint64_t seed, uint32_
                         uint64_t first_realization, int64_t count, double nbar, int32_t nbins, void* out_fields,
                         void* out_delta, int32_t* out_counts, int64_t* out_ntot, double* out_pk, double* out_cov,
                         double* out_cnorm, const unsigned long long* pair_base, hipStream_t s,
-                        const float* mask = nullptr, const void* win = nullptr, const double* fsum = nullptr) {
+                        const float* mask = nullptr, const void* win = nullptr, const double* fsum = nullptr,
+                        const double* edges = nullptr) {
   InverseSetup fs;
   CE_TRY(setup_ffts(ctx, plan, fs));
   const int ndim = plan->ndim;
@@ -1229,7 +1230,23 @@ ce_status pipeline_impl(ce_ctx* ctx, const ce_plan* plan, uint64_t seed, uint32_
   CE_HIP(launch_zero_u64(ntot, 2 * npairs, s));
   int64_t* nm = nullptr;
   const std::vector<double>* km = nullptr;
-  CE_TRY(device_shells(ctx, plan->n, ndim, nbins, &nm, &km));
+  // user shell edges: thresholds and shell table for this call (scratch slot 13: [th | nmodes])
+  const int64_t* th_dev = nullptr;
+  if (edges) {
+    std::vector<int64_t> th, nmu;
+    std::vector<double> kmu;
+    shell_thresholds(plan->n, ndim, plan->h[0], nbins, edges, th);
+    shell_table_host(plan->n, ndim, nbins, nmu, kmu, &th);
+    th.insert(th.end(), nmu.begin(), nmu.end());
+    void* p = nullptr;
+    CE_TRY(ctx->scratch(13, sizeof(int64_t) * th.size(), &p));
+    CE_HIP(hipMemcpyAsync(p, th.data(), sizeof(int64_t) * th.size(), hipMemcpyHostToDevice, s));
+    CE_HIP(hipStreamSynchronize(s));  // the host table goes out of scope
+    th_dev = static_cast<const int64_t*>(p);
+    nm = static_cast<int64_t*>(p) + (nbins + 1);
+  } else {
+    CE_TRY(device_shells(ctx, plan->n, ndim, nbins, &nm, &km));
+  }
   const double norm = std::pow(plan->h[0], ndim) / (double)ncells;
   for (int64_t j = 0; j < npairs; j += cp) {
     const int64_t np = std::min(cp, npairs - j);
@@ -1266,7 +1283,7 @@ ce_status pipeline_impl(ce_ctx* ctx, const ce_plan* plan, uint64_t seed, uint32_
     window.fsum = fsum;
     window.nest = nest;
     CE_TRY(run_forward_bins(ctx, ndim, plan->n, plan->prec, np, H, nbins, &partials, &groups, s,
-                            mask ? &window : nullptr));
+                            mask ? &window : nullptr, th_dev));
     CE_PROF(ctx, "bin_reduce", s,
             launch_bin_reduce(partials, np, groups, nbins, e.count, nm, norm, mask ? 2 : 1, ntot + 2 * j, nullptr,
                               (double)ncells, out_pk + 2 * j * nbins, ctx->flags, s));
@@ -1881,6 +1898,23 @@ ce_status ce_pipeline_run(ce_ctx* ctx, const ce_plan* plan, uint64_t seed, uint3
   ctx->last = s;
   return pipeline_impl(ctx, plan, seed, request_id, first_realization, count, nbar, nbins, out_fields, out_delta,
                        out_counts, out_ntot, out_pk, out_cov, out_cnorm, nullptr, s);
+}
+
+ce_status ce_pipeline_run_edges(ce_ctx* ctx, const ce_plan* plan, uint64_t seed, uint32_t request_id,
+                                uint64_t first_realization, int64_t count, double nbar, int32_t nbins,
+                                const double* kedges, void* out_fields, void* out_delta, int32_t* out_counts,
+                                int64_t* out_ntot, double* out_pk, double* out_cov, double* out_cnorm, void* stream) {
+  CE_TRY(pipeline_check(ctx, plan, first_realization, count, nbar, nbins, out_pk));
+  if (!kedges) return CE_E_INVALID;
+  for (int b = 0; b <= nbins; ++b)
+    if (!std::isfinite(kedges[b]) || kedges[b] < 0 || (b > 0 && !(kedges[b] > kedges[b - 1]))) return CE_E_INVALID;
+  std::lock_guard<std::mutex> lock(ctx->mu);
+  CE_HIP(hipSetDevice(ctx->device));
+  hipStream_t s = as_stream(stream);
+  ctx->last = s;
+  return pipeline_impl(ctx, plan, seed, request_id, first_realization, count, nbar, nbins, out_fields, out_delta,
+                       out_counts, out_ntot, out_pk, out_cov, out_cnorm, nullptr, s, nullptr, nullptr, nullptr,
+                       kedges);
 }
 
 ce_status ce_pipeline_run_masked(ce_ctx* ctx, const ce_plan* plan, const float* mask_f, uint64_t seed,

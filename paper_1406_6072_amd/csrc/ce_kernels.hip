@@ -811,14 +811,15 @@ __device__ __forceinline__ void bin_group(const cpx<T>* res, const LineGeom& g, 
             const cpx<T> w = wcol[(int64_t)a * W];
             v = {rr * v.x + rm * w.x, rr * v.y + rm * w.y};
           }
-          T pw = v.x * v.x + v.y * v.y;
+          // explicit fused multiply-adds: the same rounding in every instantiation of the pass
+          T pw = fma(v.x, v.x, v.y * v.y);
           if (a != 0 && a != Nh) {
             cpx<T> u = line[pidx(N - a)];
             if (WIN) {
               const cpx<T> w = wcol[(int64_t)(N - a) * W];
               u = {rr * u.x + rm * w.x, rr * u.y + rm * w.y};
             }
-            pw += u.x * u.x + u.y * u.y;
+            pw += fma(u.x, u.x, u.y * u.y);
           }
           run += (double)pw;
           t += dt;

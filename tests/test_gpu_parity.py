@@ -583,3 +583,35 @@ def test_shell_edge_errors_and_corners(ce):
             b.estimate_pk(ctx, n, (1.0, 1.0), b.F32, b.MAP_FIELD, g, 2, None, None, nb, p, edges=bad)
         assert e.value.status == b.E_INVALID
     plan.release()
+
+
+@pytest.mark.parametrize("n,prec", [((128, 128), 0), ((48, 32), 1), ((16, 16, 16), 0)])
+def test_pipeline_with_edges(ce, n, prec):
+    """The fused path with the paper's log-spaced shells against the oracle fed the GPU's counts,
+    and with linear edges equal to ce_pipeline_run bitwise."""
+    import math
+    b, ctx = ce
+    nb, count, nbar = 12, 4, 5.0
+    xi = dict(kind="exp", sigma2=0.8, a=3.0 if len(n) == 2 else 1.5)
+    plan = b.plan_embedding(ctx, n, (1.0,) * len(n), xi, prec)
+    c = torch.empty(count * plan.cells, dtype=torch.int32, device="cuda")
+    nt = torch.empty(count, dtype=torch.int64, device="cuda")
+    p = torch.empty(count * nb, dtype=torch.float64, device="cuda")
+    edges = np.exp(np.linspace(math.log(math.pi / 20.0), math.log(math.pi), nb + 1))
+    b.pipeline_run_edges(ctx, plan, 9, 2, 0, count, nbar, nb, edges, p, out_counts=c, out_ntot=nt)
+    p1 = torch.empty_like(p)
+    p2 = torch.empty_like(p)
+    b.pipeline_run(ctx, plan, 9, 2, 0, count, nbar, nb, p1)
+    b.pipeline_run_edges(ctx, plan, 9, 2, 0, count, nbar, nb, np.linspace(0.0, math.pi, nb + 1), p2)
+    torch.cuda.synchronize()
+    assert b.ctx_check(ctx) == 0
+    # (an empty shell is 0/0 = NaN on both sides)
+    assert np.array_equal(p1.cpu().numpy(), p2.cpu().numpy(), equal_nan=True)
+    ref = opk.estimate_pk(c.cpu().numpy().reshape((count,) + n), 1.0, nb, kind="counts", ntot=nt.cpu().numpy(),
+                          edges=edges)
+    got = p.cpu().numpy().reshape(count, nb)
+    ok = np.isfinite(ref[0])  # the lowest log shells of a small grid hold no mode
+    assert ok.sum() >= nb // 2
+    assert np.array_equal(np.isfinite(got[0]), ok)
+    assert np.max(np.abs(got[:, ok] / ref[:, ok] - 1)) <= TOL_PK[prec]
+    plan.release()
