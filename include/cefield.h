@@ -336,11 +336,14 @@ ce_status ce_pipeline_run(ce_ctx* ctx, const ce_plan* plan, uint64_t seed, uint3
                           void* stream);
 
 /* ce_pipeline_run with the user shells of ce_estimate_pk_edges (kedges: host, nbins + 1 strictly
- * ascending |k| values >= 0; the paper bins in ln l).  Everything else as ce_pipeline_run; linear
- * edges on (0, pi/h] give its results bitwise.  Errors: as ce_pipeline_run; CE_E_INVALID for bad
+ * ascending |k| values >= 0; the paper bins in ln l) and, when mask_f is not NULL, on a masked
+ * survey as ce_pipeline_run_masked (the paper's setting: a masked field binned in ln l).
+ * Everything else as ce_pipeline_run (ce_pipeline_run_masked with a mask); linear edges on
+ * (0, pi/h] give those results bitwise.  Errors: as ce_pipeline_run; CE_E_INVALID for bad
  * edges. */
-ce_status ce_pipeline_run_edges(ce_ctx* ctx, const ce_plan* plan, uint64_t seed, uint32_t request_id,
-                                uint64_t first_realization, int64_t count, double nbar, int32_t nbins,
+ce_status ce_pipeline_run_edges(ce_ctx* ctx, const ce_plan* plan, const float* mask_f, uint64_t seed,
+                                uint32_t request_id, uint64_t first_realization, int64_t count, double nbar,
+                                int32_t nbins,
                                 const double* kedges, void* out_fields, void* out_delta, int32_t* out_counts,
                                 int64_t* out_ntot, double* out_pk, double* out_cov, double* out_cnorm,
                                 void* stream);

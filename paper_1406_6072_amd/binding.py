@@ -115,8 +115,9 @@ _graph_launch = _sig("ce_pipeline_graph_launch", c_i32, c_void_p, c_void_p)
 _graph_destroy = _sig("ce_pipeline_graph_destroy", None, c_void_p)
 _pipeline_masked = _sig("ce_pipeline_run_masked", c_i32, c_void_p, c_void_p, c_void_p, c_u64, c_u32, c_u64, c_i64,
                         c_f64, c_i32, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p)
-_pipeline_edges = _sig("ce_pipeline_run_edges", c_i32, c_void_p, c_void_p, c_u64, c_u32, c_u64, c_i64, c_f64, c_i32,
-                       c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p)
+_pipeline_edges = _sig("ce_pipeline_run_edges", c_i32, c_void_p, c_void_p, c_void_p, c_u64, c_u32, c_u64, c_i64,
+                       c_f64, c_i32, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
+                       c_void_p)
 _pipeline_batch = _sig("ce_pipeline_run_batch", c_i32, c_void_p, ctypes.POINTER(BatchItem), c_i64, c_void_p)
 _server_create = _sig("ce_server_create", c_i32, c_i32, ctypes.POINTER(ServerConfig), ctypes.POINTER(c_void_p))
 _server_submit = _sig("ce_server_submit", c_i32, c_void_p, ctypes.POINTER(Request), ctypes.POINTER(c_u64))
@@ -466,14 +467,15 @@ def pipeline_run(ctx, plan, seed, request_id, first_realization, count, nbar, nb
 
 def pipeline_run_edges(ctx, plan, seed, request_id, first_realization, count, nbar, nbins, edges, out_pk,
                        out_fields=None, out_delta=None, out_counts=None, out_ntot=None, out_cov=None, out_cnorm=None,
-                       stream=None):
-    """The fused path with user shell edges (host sequence of nbins + 1 ascending |k| values)."""
+                       stream=None, mask=None):
+    """The fused path with user shell edges (host sequence of nbins + 1 ascending |k| values),
+    on a masked survey when mask (float32 CUDA tensor of N^d surface fractions) is given."""
     import numpy as np
     e = np.ascontiguousarray(edges, dtype=np.float64)
     if e.size != nbins + 1:
         raise ValueError("edges must hold nbins + 1 values")
     cells = plan.cells
-    _check(_pipeline_edges(ctx, plan.handle, int(seed), int(request_id), int(first_realization), int(count),
+    _check(_pipeline_edges(ctx, plan.handle, _ptr(mask, torch.float32, cells, "mask"), int(seed), int(request_id), int(first_realization), int(count),
                            float(nbar), int(nbins), e.ctypes.data_as(c_void_p),
                            _ptr(out_fields, plan.dtype, count * cells, "out_fields"),
                            _ptr(out_delta, plan.dtype, count * cells, "out_delta"),

@@ -1388,7 +1388,8 @@ ce_status window_transform(ce_ctx* ctx, const ce_plan* plan, const float* mask, 
 ce_status pipeline_masked_impl(ce_ctx* ctx, const ce_plan* plan, const float* mask, uint64_t seed,
                                uint32_t request_id, uint64_t first_realization, int64_t count, double nbar,
                                int32_t nbins, void* out_fields, void* out_delta, int32_t* out_counts,
-                               int64_t* out_ntot, double* out_pk, double* out_cov, double* out_cnorm, hipStream_t s) {
+                               int64_t* out_ntot, double* out_pk, double* out_cov, double* out_cnorm, hipStream_t s,
+                               const double* edges = nullptr) {
   if (plan->ndim == 2) {
     // fused: the contrast is completed in the binning pass from the window transform
     void* fsd = nullptr;
@@ -1398,7 +1399,7 @@ ce_status pipeline_masked_impl(ce_ctx* ctx, const ce_plan* plan, const float* ma
     CE_TRY(window_transform(ctx, plan, mask, &win, s));
     return pipeline_impl(ctx, plan, seed, request_id, first_realization, count, nbar, nbins, out_fields, out_delta,
                          out_counts, out_ntot, out_pk, out_cov, out_cnorm, nullptr, s, mask, win,
-                         static_cast<const double*>(fsd));
+                         static_cast<const double*>(fsd), edges);
   }
   InverseSetup fs;
   CE_TRY(setup_ffts(ctx, plan, fs));
@@ -1459,7 +1460,8 @@ ce_status pipeline_masked_impl(ce_ctx* ctx, const ce_plan* plan, const float* ma
   pl.ntot = sn;
   pl.mask = mask;
   pl.fsum = static_cast<const double*>(fsd);
-  CE_TRY(spectrum_impl(ctx, ndim, plan->n, plan->h[0], plan->prec, pl, count, nbins, out_pk, nullptr, nullptr, s));
+  CE_TRY(spectrum_impl(ctx, ndim, plan->n, plan->h[0], plan->prec, pl, count, nbins, out_pk, nullptr, nullptr, s,
+                       edges));
   if (count >= 2 && (out_cov || out_cnorm))
     CE_PROF(ctx, "covariance", s, launch_covariance(out_pk, count, nbins, out_cov, out_cnorm, s));
   return CE_OK;
@@ -1900,8 +1902,8 @@ ce_status ce_pipeline_run(ce_ctx* ctx, const ce_plan* plan, uint64_t seed, uint3
                        out_counts, out_ntot, out_pk, out_cov, out_cnorm, nullptr, s);
 }
 
-ce_status ce_pipeline_run_edges(ce_ctx* ctx, const ce_plan* plan, uint64_t seed, uint32_t request_id,
-                                uint64_t first_realization, int64_t count, double nbar, int32_t nbins,
+ce_status ce_pipeline_run_edges(ce_ctx* ctx, const ce_plan* plan, const float* mask_f, uint64_t seed,
+                                uint32_t request_id, uint64_t first_realization, int64_t count, double nbar, int32_t nbins,
                                 const double* kedges, void* out_fields, void* out_delta, int32_t* out_counts,
                                 int64_t* out_ntot, double* out_pk, double* out_cov, double* out_cnorm, void* stream) {
   CE_TRY(pipeline_check(ctx, plan, first_realization, count, nbar, nbins, out_pk));
@@ -1912,6 +1914,9 @@ ce_status ce_pipeline_run_edges(ce_ctx* ctx, const ce_plan* plan, uint64_t seed,
   CE_HIP(hipSetDevice(ctx->device));
   hipStream_t s = as_stream(stream);
   ctx->last = s;
+  if (mask_f)
+    return pipeline_masked_impl(ctx, plan, mask_f, seed, request_id, first_realization, count, nbar, nbins,
+                                out_fields, out_delta, out_counts, out_ntot, out_pk, out_cov, out_cnorm, s, kedges);
   return pipeline_impl(ctx, plan, seed, request_id, first_realization, count, nbar, nbins, out_fields, out_delta,
                        out_counts, out_ntot, out_pk, out_cov, out_cnorm, nullptr, s, nullptr, nullptr, nullptr,
                        kedges);

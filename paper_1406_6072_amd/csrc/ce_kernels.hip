@@ -1276,7 +1276,9 @@ static void bin_pass_t(int mix, const LineGeom& g, const FftDesc& f, const BinAr
                      (size_t)g.R * g.nlanes * sizeof(RunEnds) + 2 * (size_t)b.nb * sizeof(double);
   const cpx<T>* i = static_cast<const cpx<T>*>(in);
   with_variant(mix, [&](auto v) {
-    if (b.win)
+    if (b.win && b.th)
+      CE_LAUNCH((k_bin_pass<T, decltype(v)::value, 1, 1>), pass_grid(g), pass_block(g), lds, s, g, f, b, i);
+    else if (b.win)
       CE_LAUNCH((k_bin_pass<T, decltype(v)::value, 1, 0>), pass_grid(g), pass_block(g), lds, s, g, f, b, i);
     else if (b.th)
       CE_LAUNCH((k_bin_pass<T, decltype(v)::value, 0, 1>), pass_grid(g), pass_block(g), lds, s, g, f, b, i);
