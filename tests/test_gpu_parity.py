@@ -386,6 +386,47 @@ def test_batched_2d_full_size_sampled(ce):
     plan.release()
 
 
+def test_masked_full_size_log_shells_sampled(ce):
+    """The masked 1024^2 survey of the benchmark (256 realizations in one call, FP32) with 20
+    shells equally spaced in ln k: sampled realizations against the oracle (counts and N_tot
+    bitwise, P(k) to the spectrum tolerance), every realization against ce_estimate_pk_edges
+    on the stored counts."""
+    import math
+    b, ctx = ce
+    from synth import workloads
+    w = workloads.WORKLOADS["batched_2d"]
+    n, R, nbar, nb = w["n"], w["realizations"], w["nbar"], 20
+    mask_np = workloads.survey_mask(n, seed=3)
+    mask = torch.from_numpy(mask_np.ravel()).cuda()
+    edges = np.exp(np.linspace(math.log(math.pi / 256.0), math.log(math.pi), nb + 1))
+    plan = b.plan_embedding(ctx, n, w["h"], w["xi"], b.F32)
+    cells = plan.cells
+    d = torch.empty(R * cells, dtype=torch.float32, device="cuda")
+    c = torch.empty(R * cells, dtype=torch.int32, device="cuda")
+    nt = torch.empty(R, dtype=torch.int64, device="cuda")
+    p = torch.empty(R * nb, dtype=torch.float64, device="cuda")
+    b.pipeline_run_edges(ctx, plan, w["seed"], w["request_id"], 0, R, nbar, nb, edges, p, out_delta=d,
+                         out_counts=c, out_ntot=nt, mask=mask)
+    p2 = torch.empty_like(p)
+    b.estimate_pk(ctx, n, w["h"], b.F32, b.MAP_COUNTS_DELTAG, c, R, nt, mask, nb, p2, edges=edges)
+    torch.cuda.synchronize()
+    assert b.ctx_check(ctx) == 0
+    got, un = p.cpu().numpy().reshape(R, nb), p2.cpu().numpy().reshape(R, nb)
+    assert np.all(np.isfinite(got)) and np.max(np.abs(got / un - 1)) <= TOL_PK[0]
+    ref_plan = embedding.plan(n, w["h"], w["xi"])
+    for first in (0, R - 2):
+        print("sampled masked pair", first // 2, flush=True)
+        f = ofields.generate_fields(ref_plan, w["seed"], w["request_id"], first, 2)
+        dh = d[first * cells:(first + 2) * cells].cpu().numpy().reshape((2,) + n)
+        _, rc, rn = olp.lognormal_poisson(f, plan.info["sigma2"], nbar, w["seed"], w["request_id"], first,
+                                          mask=mask_np, delta=dh)
+        assert np.array_equal(c[first * cells:(first + 2) * cells].cpu().numpy().reshape((2,) + n), rc)
+        assert np.array_equal(nt[first:first + 2].cpu().numpy(), rn)
+        rp = opk.estimate_pk(rc, 1.0, nb, kind="counts", ntot=rn, mask=mask_np, edges=edges)
+        assert np.max(np.abs(got[first:first + 2] / rp - 1)) <= TOL_PK[0]
+    plan.release()
+
+
 def test_volume_3d_parity_and_full_size_properties(ce):
     b, ctx = ce
     from synth import workloads
