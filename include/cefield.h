@@ -352,12 +352,11 @@ ce_status ce_pipeline_run_edges(ce_ctx* ctx, const ce_plan* plan, const float* m
  * (device, N^d floats in [0, 1], row-major, caller-owned) is the surface fraction f of each
  * survey cell.  Counts are drawn with rate nbar f rho; the spectra are those of
  * delta_g = (N/f - N^)/N^ on cells with f != 0 (0 elsewhere), N^ = N_tot / sum f, the contrast
- * ce_estimate_pk forms for counts with a mask.  2-D: the fused pass transforms N / (f nbar) - 1
- * on f != 0 and the binning pass completes the contrast with the transform of the indicator
- * f != 0 (computed once per call), so counts are stored only into out_counts when given; P(k)
- * equals ce_estimate_pk's to rounding (not bitwise).  3-D: the counts are stored (out_counts or
- * context scratch) and transformed in a second pass, bitwise as ce_estimate_pk.  mask_f = NULL
- * is ce_pipeline_run.  Errors: as ce_pipeline_run. */
+ * ce_estimate_pk forms for counts with a mask.  The fused pass transforms N / (f nbar) - 1 on
+ * f != 0 and the binning pass completes the contrast with the transform of the indicator f != 0
+ * (computed once per call, held in context scratch: N^(d-1) x 2 (N_last/2 + 1) complex values), so
+ * counts are stored only into out_counts when given; P(k) equals ce_estimate_pk's to rounding
+ * (not bitwise).  mask_f = NULL is ce_pipeline_run.  Errors: as ce_pipeline_run. */
 ce_status ce_pipeline_run_masked(ce_ctx* ctx, const ce_plan* plan, const float* mask_f, uint64_t seed,
                                  uint32_t request_id, uint64_t first_realization, int64_t count, double nbar,
                                  int32_t nbins, void* out_fields, void* out_delta, int32_t* out_counts,

@@ -1351,120 +1351,63 @@ ce_status spectrum_impl(ce_ctx* ctx, int ndim, const int* n, double h, int prec,
   return CE_OK;
 }
 
-// Forward transform Wm of the indicator f != 0 of a 2-D mask (the spectra's row pass on the map
-// [f != 0] with an empty second map, then the axis-0 line transform), N_0 x W complex in the
-// plan precision in scratch slot 12, [q0][column] like the spectra.
+// Forward transform Wm of the indicator f != 0 of a mask (the spectra's row pass on the map
+// [f != 0] with an empty second map, then the remaining line transforms), rows x W complex in
+// the plan precision in scratch slot 12, laid out as one item of the spectra: [q0][column]
+// in 2-D, [q0][q1][column] in 3-D.
 ce_status window_transform(ce_ctx* ctx, const ce_plan* plan, const float* mask, void** out, hipStream_t s) {
-  const int N0 = plan->n[0], N1 = plan->n[1];
-  const int W = 2 * (N1 / 2 + 1);
+  const int ndim = plan->ndim;
+  const int N0 = plan->n[0], Nl = plan->n[ndim - 1];
+  const int W = 2 * (Nl / 2 + 1);
+  const int64_t rows = survey_cells(plan) / Nl;
+  const int64_t item = rows * W;
   const size_t elem = plan->prec ? 16 : 8;
   void* H = nullptr;
-  CE_TRY(ctx->scratch(2, elem * (size_t)N0 * W, &H));
+  CE_TRY(ctx->scratch(2, elem * (size_t)item, &H));
   void* Wm = nullptr;
-  CE_TRY(ctx->scratch(12, elem * (size_t)N0 * W, &Wm));
+  CE_TRY(ctx->scratch(12, elem * (size_t)item, &Wm));
   PairLoad pl;
   pl.kind = 2;
   pl.count = 1;
-  pl.ncells = (int64_t)N0 * N1;
+  pl.ncells = survey_cells(plan);
   pl.mask = mask;
   pl.H = H;
-  pl.H_item = (int64_t)N0 * W;
+  pl.H_item = item;
   FftDesc fl, f0;
-  CE_TRY(build_fft(ctx, N1, plan->prec, fl));
+  CE_TRY(build_fft(ctx, Nl, plan->prec, fl));
   CE_TRY(build_fft(ctx, N0, plan->prec, f0));
-  LineGeom g1 = make_geom(N1, N1, N0, 1, 1, 0, 0, elem, mixed_radix(fl), 1, 1024);
+  LineGeom g1 = make_geom(Nl, Nl, rows, 1, 1, 0, 0, elem, mixed_radix(fl), 1, 1024);
   CE_PROF(ctx, "window_rows", s, launch_pair_forward(plan->prec, g1, fl, pl, s));
-  LineGeom g0 = make_geom(N0, N0, 1, W, 1, (int64_t)N0 * W, (int64_t)N0 * W, elem, mixed_radix(f0), 1,
-                          cap_lines(ctx, 1, 32));
+  if (ndim == 3) {
+    FftDesc f1;
+    CE_TRY(build_fft(ctx, plan->n[1], plan->prec, f1));
+    LineGeom g2 = make_geom(plan->n[1], plan->n[1], N0, W, 1, item, item, elem, mixed_radix(f1), 1,
+                            cap_lines(ctx, 1, 32));
+    CE_PROF(ctx, "window_axis1", s, launch_line_pass(plan->prec, -1, g2, f1, H, H, s));
+  }
+  LineGeom g0 = make_geom(N0, N0, 1, item / N0, 1, item, item, elem, mixed_radix(f0), 1, cap_lines(ctx, 1, 32));
   CE_PROF(ctx, "window_axis0", s, launch_line_pass(plan->prec, -1, g0, f0, H, Wm, s));
   *out = Wm;
   return CE_OK;
 }
 
 // The pipeline on a masked survey (rate nbar f rho; delta_g = (N/f - N^)/N^ on f != 0 with
-// N^ = N_tot / sum f, eq. Estim).  2-D: fused, the contrast completed in the binning pass with
-// the window transform.  3-D: the fused pass stores the counts (no forward transform) and the
-// spectrum stage forms delta_g from them as the standalone estimator does.
+// N^ = N_tot / sum f, eq. Estim), fused: the last inverse pass transforms N / (f nest) - 1 on
+// f != 0 and the binning pass completes the contrast with the window transform.
 ce_status pipeline_masked_impl(ce_ctx* ctx, const ce_plan* plan, const float* mask, uint64_t seed,
                                uint32_t request_id, uint64_t first_realization, int64_t count, double nbar,
                                int32_t nbins, void* out_fields, void* out_delta, int32_t* out_counts,
                                int64_t* out_ntot, double* out_pk, double* out_cov, double* out_cnorm, hipStream_t s,
                                const double* edges = nullptr) {
-  if (plan->ndim == 2) {
-    // fused: the contrast is completed in the binning pass from the window transform
-    void* fsd = nullptr;
-    CE_TRY(ctx->scratch(9, sizeof(double) * 257, &fsd));
-    CE_HIP(launch_mask_sum(mask, survey_cells(plan), static_cast<double*>(fsd), s));
-    void* win = nullptr;
-    CE_TRY(window_transform(ctx, plan, mask, &win, s));
-    return pipeline_impl(ctx, plan, seed, request_id, first_realization, count, nbar, nbins, out_fields, out_delta,
-                         out_counts, out_ntot, out_pk, out_cov, out_cnorm, nullptr, s, mask, win,
-                         static_cast<const double*>(fsd), edges);
-  }
-  InverseSetup fs;
-  CE_TRY(setup_ffts(ctx, plan, fs));
-  const int ndim = plan->ndim;
-  const int64_t ncells = survey_cells(plan);
-  const size_t relem = plan->prec ? 8 : 4;
-  const int64_t npairs = (count + 1) / 2;
-  const int64_t cp = chunk_pairs(plan, npairs, kScratchCap);
-  int32_t* counts = out_counts;
-  if (!counts) {
-    void* c = nullptr;
-    CE_TRY(ctx->scratch(7, sizeof(int32_t) * (size_t)(count * ncells), &c));
-    counts = static_cast<int32_t*>(c);
-  }
-  void* acc = nullptr;
-  CE_TRY(ctx->scratch(4, sizeof(unsigned long long) * (size_t)(2 * npairs), &acc));
-  auto* ntot = static_cast<unsigned long long*>(acc);
-  CE_HIP(launch_zero_u64(ntot, 2 * npairs, s));
-  for (int64_t j = 0; j < npairs; j += cp) {
-    const int64_t np = std::min(cp, npairs - j);
-    RowEpi e;
-    e.mode = 2;
-    e.ncells = ncells;
-    e.count = std::min<int64_t>(count - 2 * j, 2 * np);
-    e.real_off = 0;
-    e.fields = out_fields ? static_cast<char*>(out_fields) + relem * (size_t)(2 * j * ncells) : nullptr;
-    e.delta = out_delta ? static_cast<char*>(out_delta) + relem * (size_t)(2 * j * ncells) : nullptr;
-    e.counts = counts + 2 * j * ncells;
-    e.mask = mask;
-    e.ntot = ntot + 2 * j;
-    e.flags = ctx->flags;
-    e.inv = ctx->inv;
-    e.s2half = 0.5 * plan->info.sigma2;
-    e.nbar = nbar;
-    e.k0 = (uint32_t)(seed & 0xFFFFFFFFu);
-    e.k1 = (uint32_t)(seed >> 32);
-    e.rid = request_id;
-    e.first_pair = first_realization / 2 + j;
-    e.fwd = fs.fN[ndim - 1];
-    e.H = nullptr;
-    CE_TRY(run_inverse(ctx, plan, fs, seed, request_id, first_realization / 2 + j, np, e, s));
-  }
-  int64_t* sn = out_ntot;
-  if (!sn) {
-    void* t = nullptr;
-    CE_TRY(ctx->scratch(6, sizeof(int64_t) * (size_t)count, &t));
-    sn = static_cast<int64_t*>(t);
-  }
-  CE_HIP(launch_copy_ntot(ntot, sn, count, s));
+  // fused: the contrast is completed in the binning pass from the window transform
   void* fsd = nullptr;
   CE_TRY(ctx->scratch(9, sizeof(double) * 257, &fsd));
-  CE_HIP(launch_mask_sum(mask, ncells, static_cast<double*>(fsd), s));
-  PairLoad pl;
-  pl.kind = 1;
-  pl.maps = counts;
-  pl.count = count;
-  pl.ncells = ncells;
-  pl.ntot = sn;
-  pl.mask = mask;
-  pl.fsum = static_cast<const double*>(fsd);
-  CE_TRY(spectrum_impl(ctx, ndim, plan->n, plan->h[0], plan->prec, pl, count, nbins, out_pk, nullptr, nullptr, s,
-                       edges));
-  if (count >= 2 && (out_cov || out_cnorm))
-    CE_PROF(ctx, "covariance", s, launch_covariance(out_pk, count, nbins, out_cov, out_cnorm, s));
-  return CE_OK;
+  CE_HIP(launch_mask_sum(mask, survey_cells(plan), static_cast<double*>(fsd), s));
+  void* win = nullptr;
+  CE_TRY(window_transform(ctx, plan, mask, &win, s));
+  return pipeline_impl(ctx, plan, seed, request_id, first_realization, count, nbar, nbins, out_fields, out_delta,
+                       out_counts, out_ntot, out_pk, out_cov, out_cnorm, nullptr, s, mask, win,
+                       static_cast<const double*>(fsd), edges);
 }
 
 ce_status pipeline_check(ce_ctx* ctx, const ce_plan* plan, uint64_t first_realization, int64_t count, double nbar,

@@ -760,17 +760,20 @@ __device__ __forceinline__ void bin_group(const cpx<T>* res, const LineGeom& g, 
       const int chunk = (Nh + 1 + g.nlanes - 1) / g.nlanes;
       const int a0 = lane * chunk, a1 = min(a0 + chunk, Nh + 1);
       const cpx<T>* line = res + r * g.lpitch;
-      // masked 2-D pipeline (WIN): the line holds the transform A of N / (f nest) - 1; the
+      // masked pipeline (WIN): the line holds the transform A of N / (f nest) - 1; the
       // contrast's is D = rr A + rm Wm with rr = nest sum(f) / N_tot of the line's realization,
-      // rm = rr - 1 and Wm the transform of the indicator f != 0 ([q0][column], as the spectra)
+      // rm = rr - 1 and Wm the transform of the indicator f != 0 (laid out as one item of the
+      // spectra: [q0][column] in 2-D, [q0][q1][column] in 3-D)
       T rr = T(1), rm = T(0);
       const cpx<T>* wcol = nullptr;
+      int64_t wstride = 0;
       if (WIN) {
         const double nt = (double)bn.ntot[2 * item + s];
         const double rd = nt > 0.0 ? bn.nest * *bn.fsum / nt : 0.0;
         rr = (T)rd;
         rm = (T)(rd - 1.0);
-        wcol = static_cast<const cpx<T>*>(bn.win) + kz;
+        wcol = static_cast<const cpx<T>*>(bn.win) + (ln - kl) + kz;
+        wstride = (int64_t)(bn.ndim == 3 ? bn.N1 : 1) * W;
       }
       if (a0 < a1) {
         e.nonempty = 1;
@@ -808,7 +811,7 @@ __device__ __forceinline__ void bin_group(const cpx<T>* res, const LineGeom& g, 
           // power of the mode pair in the pass precision, summed in FP64
           cpx<T> v = line[pidx(a)];
           if (WIN) {
-            const cpx<T> w = wcol[(int64_t)a * W];
+            const cpx<T> w = wcol[(int64_t)a * wstride];
             v = {rr * v.x + rm * w.x, rr * v.y + rm * w.y};
           }
           // explicit fused multiply-adds: the same rounding in every instantiation of the pass
@@ -816,7 +819,7 @@ __device__ __forceinline__ void bin_group(const cpx<T>* res, const LineGeom& g, 
           if (a != 0 && a != Nh) {
             cpx<T> u = line[pidx(N - a)];
             if (WIN) {
-              const cpx<T> w = wcol[(int64_t)(N - a) * W];
+              const cpx<T> w = wcol[(int64_t)(N - a) * wstride];
               u = {rr * u.x + rm * w.x, rr * u.y + rm * w.y};
             }
             pw += fma(u.x, u.x, u.y * u.y);

@@ -108,11 +108,14 @@ def survey_mask(n, seed=7, holes_per_cell=1.0 / 400.0, edge=0.06):
         sl = [slice(None)] * len(n)
         sl[ax] = slice(0, w)
         f[tuple(sl)] = np.minimum(f[tuple(sl)], 0.85)
-    grids = np.meshgrid(*[np.arange(x) for x in n], indexing="ij")
     for _ in range(max(1, int(np.prod(n) * holes_per_cell))):
-        c = [rng.integers(0, x) for x in n]
+        c = [int(rng.integers(0, x)) for x in n]
         r = rng.uniform(1.0, 4.0)
+        # the disk lies inside the box of half-side 4 around its centre (no wrap-around)
+        box = tuple(slice(max(0, ci - 4), min(x, ci + 5)) for ci, x in zip(c, n))
+        grids = np.meshgrid(*[np.arange(b.start, b.stop) for b in box], indexing="ij")
         d2 = sum((g - ci) ** 2 for g, ci in zip(grids, c))
-        f[d2 <= r * r] = 0.0
+        sub = f[box]
+        sub[d2 <= r * r] = 0.0
     f[f < 0.7] = 0.0
     return f.astype(np.float32)
