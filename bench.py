@@ -393,6 +393,51 @@ def serving_warm(b, torch, server, trace, nb=32):
     return dt, len(trace) / dt
 
 
+def small_request_leg(b, torch, slots):
+    """Closed-loop throughput of a burst of small requests (2-D sides 64..256, 3-D 32..64, 1..4
+    realizations) through the server with groups of up to 256 requests per launch and with one
+    request per launch."""
+    from synth import workloads
+    trace = workloads.serving_trace(rate=4000.0, duration=1.0, seed=7, max_side_2d=256, max_side_3d=64,
+                                    max_realizations=4)
+    out = dict(requests=len(trace), realizations=sum(r["realizations"] for r in trace))
+    nb = 32
+    offs, pool = serving_outputs(torch, trace, nb)
+    reqs = []
+    for i, r in enumerate(trace):
+        R, o = r["realizations"], offs[i]
+        reqs.append(dict(n=r["n"], h=r["h"], xi=r["xi"], precision=b.F32, seed=r["seed"], request_id=r["request_id"],
+                         realizations=R, nbar=r["nbar"], nbins=nb, out_pk=pool[o:o + R * nb],
+                         out_ntot=pool[o + R * nb:o + R * nb + R].view(torch.int64),
+                         out_cov=pool[o + R * nb + R:o + R * nb + R + nb * nb] if R >= 2 else None))
+
+    def burst(server):
+        # every request queued in one call, so the scheduler sees them at once
+        t0 = time.perf_counter()
+        left = set(b.server_submit_many(server, reqs))
+        while left:
+            for t, st, status, ms in b.server_drain(server):
+                left.discard(t)
+            time.sleep(0.0002)
+        dt = time.perf_counter() - t0
+        return dt, len(reqs) / dt
+
+    for tag, mg in (("grouped", 0), ("one_per_launch", 1)):
+        server = b.server_create(0, slots=slots, max_group=mg)
+        try:
+            burst(server)  # plans and scratch
+            st0 = b.server_stats(server)
+            dt, rps = burst(server)
+            st = b.server_stats(server)
+        finally:
+            b.server_destroy(server)
+        out[tag] = dict(seconds=round(dt, 4), requests_per_s=round(rps, 1),
+                        realizations_per_s=round(out["realizations"] / dt, 1),
+                        launches=int(st["launches"] - st0["launches"]),
+                        largest_group=int(st["largest_group"]))
+    return out
+
+
 def serving_leg(b, torch, server, rate, seconds, warmup):
     """Open-loop replay of a Poisson arrival trace of mixed 2-D/3-D requests through the request
     server (continuous batching, plan cache), already warm.  Requests arriving in the first
@@ -669,6 +714,8 @@ def main():
                                                realizations_per_s=round(sum(r["realizations"] for r in sat_trace)
                                                                         / sat_s, 1)),
                               legs=legs, max_sustainable_rate_tested=max(ok) if ok else None)
+        out["serving"]["small_requests"] = small_request_leg(b, torch, args.serve_slots)
+        print("small requests %s" % json.dumps(out["serving"]["small_requests"]), file=sys.stderr, flush=True)
 
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_oracle_sample(w, args.cpu_seconds)

@@ -408,16 +408,21 @@ void ce_pipeline_graph_destroy(ce_graph* graph);
  * precision).  ce_server_submit queues a request and returns at once; a scheduler thread
  * admits the queue head (FIFO) as soon as a slot is free and its device footprint -- pipeline
  * scratch, plus the plan if it is not cached -- fits hbm_budget_bytes (evicting unused plans
- * first); admitted requests run ce_pipeline_run concurrently on their slots' streams.  Every
- * request's results equal those of the same ce_pipeline_run issued alone (the computation of
- * a request does not depend on what else runs).  A failing request (for example CE_E_NOT_PSD
- * at plan time) fails alone.  The output buffers of a request must stay valid until it is done.
- * Latency = completion observed by the scheduler minus the submit time (host steady clock). */
+ * first), together with up to max_group - 1 more queued requests of at most 256 MiB of scratch
+ * each whose plans are cached and whose scratch still fits; a slot runs its group as one
+ * ce_pipeline_run_batch call (one request: ce_pipeline_run), slots concurrently on their
+ * streams.  Every request's results equal those of the same ce_pipeline_run issued alone (the
+ * computation of a request does not depend on what else runs).  A failing request (for
+ * example CE_E_NOT_PSD at plan time) fails alone; a device-side sampler flag (see
+ * ce_ctx_check) fails the group it ran in.  The output buffers of a request must stay valid
+ * until it is done.  Latency = completion observed by the scheduler minus the submit time
+ * (host steady clock). */
 typedef struct ce_server ce_server;
 typedef struct {
   int32_t slots;            /* requests in flight at once (default 4, at most 32) */
   size_t hbm_budget_bytes;  /* bound on slot scratch + cached plans (0: 3/4 of the free device memory) */
   size_t plan_cache_bytes;  /* bound on cached plans (0: 32 GiB or a quarter of the budget if less) */
+  int32_t max_group;        /* most requests admitted together (0: 256; 1: one request per launch) */
 } ce_server_config;
 typedef struct {
   ce_geometry geom;
@@ -438,9 +443,15 @@ typedef struct {
   double p50_ms, p99_ms;    /* over completed requests */
   double elapsed_s;         /* since the server was created */
   size_t held_bytes;        /* slot scratch + cached plans accounted by the admission */
+  int64_t launches;         /* slot launches (one per admitted group) */
+  int64_t largest_group;    /* most requests admitted together */
 } ce_server_stats;
 ce_status ce_server_create(int device, const ce_server_config* cfg, ce_server** out);
 ce_status ce_server_submit(ce_server* server, const ce_request* request, uint64_t* ticket);
+/* ce_server_submit for n requests (host array) queued together, in order, under one lock, so
+ * that the scheduler sees them at once (clients with many small requests: they are admitted in
+ * groups).  tickets: host array of n.  All or nothing: CE_E_INVALID queues none. */
+ce_status ce_server_submit_many(ce_server* server, const ce_request* requests, int64_t n, uint64_t* tickets);
 /* Non-blocking.  *state: 0 queued, 1 running, 2 done, 3 failed, 4 cancelled; once a finished
  * state (>= 2) has been returned the ticket is forgotten. */
 ce_status ce_server_poll(ce_server* server, uint64_t ticket, int32_t* state, ce_status* status,

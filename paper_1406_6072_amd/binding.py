@@ -52,7 +52,7 @@ class BatchItem(ctypes.Structure):
 
 
 class ServerConfig(ctypes.Structure):
-    _fields_ = [("slots", c_i32), ("hbm_budget_bytes", c_size), ("plan_cache_bytes", c_size)]
+    _fields_ = [("slots", c_i32), ("hbm_budget_bytes", c_size), ("plan_cache_bytes", c_size), ("max_group", c_i32)]
 
 
 class Request(ctypes.Structure):
@@ -64,7 +64,8 @@ class Request(ctypes.Structure):
 class ServerStats(ctypes.Structure):
     _fields_ = [("submitted", c_i64), ("completed", c_i64), ("failed", c_i64), ("cache_hits", c_i64),
                 ("cache_misses", c_i64), ("admission_stalls", c_i64), ("queued", c_i64), ("p50_ms", c_f64),
-                ("p99_ms", c_f64), ("elapsed_s", c_f64), ("held_bytes", c_size)]
+                ("p99_ms", c_f64), ("elapsed_s", c_f64), ("held_bytes", c_size), ("launches", c_i64),
+                ("largest_group", c_i64)]
 
 
 def _sig(name, res, *args):
@@ -121,6 +122,8 @@ _pipeline_edges = _sig("ce_pipeline_run_edges", c_i32, c_void_p, c_void_p, c_voi
 _pipeline_batch = _sig("ce_pipeline_run_batch", c_i32, c_void_p, ctypes.POINTER(BatchItem), c_i64, c_void_p)
 _server_create = _sig("ce_server_create", c_i32, c_i32, ctypes.POINTER(ServerConfig), ctypes.POINTER(c_void_p))
 _server_submit = _sig("ce_server_submit", c_i32, c_void_p, ctypes.POINTER(Request), ctypes.POINTER(c_u64))
+_server_submit_many = _sig("ce_server_submit_many", c_i32, c_void_p, ctypes.POINTER(Request), c_i64,
+                           ctypes.POINTER(c_u64))
 _server_poll = _sig("ce_server_poll", c_i32, c_void_p, c_u64, ctypes.POINTER(c_i32), ctypes.POINTER(c_i32),
                     ctypes.POINTER(c_f64))
 _server_cancel = _sig("ce_server_cancel", c_i32, c_void_p, c_u64)
@@ -141,7 +144,7 @@ EXPORTED = ["ce_status_string", "ce_version", "ce_ctx_create", "ce_ctx_destroy",
             "ce_cic_histogram", "ce_cic_predict", "ce_astar_map", "ce_cumulative_information",
             "ce_pipeline_run", "ce_pipeline_run_edges", "ce_pipeline_run_masked", "ce_pipeline_run_batch", "ce_pipeline_graph_create", "ce_pipeline_graph_launch",
             "ce_pipeline_graph_destroy",
-            "ce_server_create", "ce_server_submit", "ce_server_poll", "ce_server_drain", "ce_server_cancel",
+            "ce_server_create", "ce_server_submit", "ce_server_submit_many", "ce_server_poll", "ce_server_drain", "ce_server_cancel",
             "ce_server_stats_read", "ce_server_destroy", "ce_shell_table", "ce_fft_factors", "ce_debug_philox", "ce_debug_noise"]
 
 
@@ -548,20 +551,18 @@ def pipeline_graph_destroy(graph):
     _graph_destroy(graph)
 
 
-def server_create(device=0, slots=4, hbm_budget_bytes=0, plan_cache_bytes=0):
-    cfg = ServerConfig(int(slots), int(hbm_budget_bytes), int(plan_cache_bytes))
+def server_create(device=0, slots=4, hbm_budget_bytes=0, plan_cache_bytes=0, max_group=0):
+    cfg = ServerConfig(int(slots), int(hbm_budget_bytes), int(plan_cache_bytes), int(max_group))
     s = c_void_p()
     _check(_server_create(int(device), ctypes.byref(cfg), ctypes.byref(s)), "ce_server_create")
     return s
 
 
-def server_submit(server, n, h, xi, precision, seed, request_id, realizations, nbar, nbins, out_pk,
+def _fill_request(r, n, h, xi, precision, seed, request_id, realizations, nbar, nbins, out_pk,
                   out_counts=None, out_ntot=None, out_cov=None):
-    """Queue one request; returns its ticket.  Output tensors must outlive the request."""
     cells = 1
     for x in n:
         cells *= int(x)
-    r = Request()
     r.geom = geometry(n, h)
     x, keep = xi_spec(xi)
     r.xi = x
@@ -572,10 +573,30 @@ def server_submit(server, n, h, xi, precision, seed, request_id, realizations, n
     r.out_counts = _ptr(out_counts, torch.int32, realizations * cells, "out_counts")
     r.out_ntot = _ptr(out_ntot, torch.int64, realizations, "out_ntot")
     r.out_cov = _ptr(out_cov, torch.float64, nbins * nbins, "out_cov")
+    return keep
+
+
+def server_submit(server, n, h, xi, precision, seed, request_id, realizations, nbar, nbins, out_pk,
+                  out_counts=None, out_ntot=None, out_cov=None):
+    """Queue one request; returns its ticket.  Output tensors must outlive the request."""
+    r = Request()
+    keep = _fill_request(r, n, h, xi, precision, seed, request_id, realizations, nbar, nbins, out_pk,
+                         out_counts, out_ntot, out_cov)
     t = c_u64()
     _check(_server_submit(server, ctypes.byref(r), ctypes.byref(t)), "ce_server_submit")
     del keep
     return t.value
+
+
+def server_submit_many(server, requests):
+    """Queue several requests at once (dicts with the arguments of server_submit after
+    `server`); returns their tickets."""
+    arr = (Request * len(requests))()
+    keep = [_fill_request(arr[k], **q) for k, q in enumerate(requests)]
+    t = (c_u64 * len(requests))()
+    _check(_server_submit_many(server, arr, len(requests), t), "ce_server_submit_many")
+    del keep
+    return list(t)
 
 
 def server_poll(server, ticket):

@@ -1,9 +1,9 @@
 // Request loop of the generator (host C++): continuous batching of field
 // requests of different geometries.  Requests wait in a queue; a scheduler thread
-// admits a request whenever one of the slots (a context + stream each) is free, the
-// request's plan is in the cache and its scratch fits the HBM budget; admitted
-// requests run concurrently on their slots' streams, so work of requests that
-// arrive while others are on the GPU overlaps with them.  Plans (the sqrt(lambda)
+// admits a group of requests whenever one of the slots (a context + stream each) is
+// free, their plans are in the cache and their scratch fits the HBM budget; a group
+// runs as one batched pipeline call, groups run concurrently on their slots' streams,
+// so work of requests that arrive while others are on the GPU overlaps with them.  Plans (the sqrt(lambda)
 // octant of a (geometry, xi, precision) key) are built by a planner thread on a
 // stream of their own and kept in an LRU cache on the device shared by all slots;
 // a request whose plan is being built does not hold up the requests behind it
@@ -56,10 +56,17 @@ struct Slot {
   ce_ctx* ctx = nullptr;
   hipStream_t stream = nullptr;
   hipEvent_t done = nullptr;
-  std::shared_ptr<Req> req;
-  PlanEntry* plan = nullptr;
+  std::vector<std::shared_ptr<Req>> reqs;  // the group running on the slot (empty: free)
+  std::vector<PlanEntry*> plans;
   size_t scratch_held = 0;
+  bool busy() const { return !reqs.empty(); }
 };
+
+// A free slot takes the oldest admissible request and, behind it, up to max_group - 1 more
+// from the lookahead window whose scratch is at most kGroupScratch each, run as one batched
+// call (one launch per pass and shape for the whole group); larger requests run alone.
+constexpr int kMaxGroup = 256;
+constexpr size_t kGroupScratch = size_t(256) << 20;
 
 std::string plan_key(const ce_request& r, const std::vector<double>& table) {
   std::string k;
@@ -164,73 +171,123 @@ struct ce_server {
   }
 
   void complete(Slot& s) {
-    auto& q = *s.req;
-    q.status = ce_ctx_check(s.ctx, s.stream);
-    q.latency_ms = std::chrono::duration<double, std::milli>(Clock::now() - q.arrival).count();
-    q.state = q.status == CE_OK ? 2 : 3;
-    finished.push_back(q.ticket);
-    if (q.status == CE_OK) {
-      st.completed++;
-      record_latency(q.latency_ms);
-    } else {
-      st.failed++;
+    // one check of the slot's context covers the group (a device-side sampler flag fails
+    // every request of the group that ran with it)
+    const ce_status status = ce_ctx_check(s.ctx, s.stream);
+    for (auto& qp : s.reqs) {
+      auto& q = *qp;
+      if (q.state != 1) continue;  // failed at launch
+      q.status = status;
+      q.latency_ms = std::chrono::duration<double, std::milli>(Clock::now() - q.arrival).count();
+      q.state = status == CE_OK ? 2 : 3;
+      finished.push_back(q.ticket);
+      if (status == CE_OK) {
+        st.completed++;
+        record_latency(q.latency_ms);
+      } else {
+        st.failed++;
+      }
     }
-    s.plan->users--;
-    s.plan = nullptr;
-    s.req.reset();
+    for (PlanEntry* pe : s.plans) pe->users--;
+    s.plans.clear();
+    s.reqs.clear();
   }
 
-  // Start q (whose plan pe is cached) on slot s; false when its scratch does not fit yet,
-  // with *never set when it cannot fit even with nothing else running.
-  bool admit(Slot& s, const std::shared_ptr<Req>& q, PlanEntry* pe, bool* never) {
+  // Reserve q's scratch on slot s (on top of `want`, the scratch of the group so far); false
+  // when it does not fit, with *never set when it cannot fit even with nothing else running.
+  bool reserve(Slot& s, const Req& q, size_t want, bool first, bool* never) {
     *never = false;
-    const size_t extra = q->scratch > s.scratch_held ? q->scratch - s.scratch_held : 0;
-    pe->users++;  // pinned while making room
+    const size_t total = want + q.scratch;
+    const size_t extra = total > s.scratch_held ? total - s.scratch_held : 0;
     bool room = make_room(extra, false);
-    if (!room) {
+    if (!room && first) {
       // give back the scratch that idle slots keep cached, then try again
       for (auto& o : slots)
-        if (&o != &s && !o.req && o.scratch_held && ce_ctx_trim(o.ctx) == CE_OK) {
+        if (&o != &s && !o.busy() && o.scratch_held && ce_ctx_trim(o.ctx) == CE_OK) {
           held -= o.scratch_held;
           o.scratch_held = 0;
         }
       room = make_room(extra, false);
     }
     if (!room) {
-      pe->users--;
-      bool busy = false;
-      for (auto& o : slots) busy |= (bool)o.req;
-      *never = !busy;
+      if (first) {
+        bool busy = false;
+        for (auto& o : slots) busy |= o.busy();
+        *never = !busy;
+      }
       return false;
     }
-    if (q->planned)
-      st.cache_misses++;
-    else
-      st.cache_hits++;
-    s.plan = pe;
-    s.req = q;
-    if (q->scratch > s.scratch_held) {
-      held += q->scratch - s.scratch_held;
-      s.scratch_held = q->scratch;
-    }
-    q->state = 1;
-    const ce_request& r = q->r;
-    ce_status rs = ce_pipeline_run(s.ctx, pe->plan, r.seed, r.request_id, 0, r.realizations, r.nbar, r.nbins,
-                                   nullptr, nullptr, r.out_counts, r.out_ntot, r.out_pk,
-                                   r.realizations >= 2 ? r.out_cov : nullptr, nullptr, s.stream);
-    if (rs == CE_OK && hipEventRecord(s.done, s.stream) != hipSuccess) rs = CE_E_DEVICE;
-    if (rs != CE_OK) {
-      fail(*q, rs);
-      pe->users--;
-      s.plan = nullptr;
-      s.req.reset();
-    }
+    held += extra;
+    s.scratch_held += extra;
     return true;
   }
 
-  // At most one admission onto the free slot s, from the first kLookahead queued requests.
+  // Run the group picked for slot s on its stream.
+  void launch(Slot& s) {
+    st.launches++;
+    st.largest_group = std::max(st.largest_group, (int64_t)s.reqs.size());
+    for (size_t k = 0; k < s.reqs.size(); ++k) {
+      Req& q = *s.reqs[k];
+      if (q.planned)
+        st.cache_misses++;
+      else
+        st.cache_hits++;
+      q.state = 1;
+    }
+    auto run_alone = [&](Req& q, PlanEntry* pe) {
+      const ce_request& r = q.r;
+      return ce_pipeline_run(s.ctx, pe->plan, r.seed, r.request_id, 0, r.realizations, r.nbar, r.nbins, nullptr,
+                             nullptr, r.out_counts, r.out_ntot, r.out_pk, r.realizations >= 2 ? r.out_cov : nullptr,
+                             nullptr, s.stream);
+    };
+    std::vector<ce_status> rs(s.reqs.size(), CE_OK);
+    bool batched = false;
+    if (s.reqs.size() > 1) {
+      std::vector<ce_batch_item> items(s.reqs.size());
+      for (size_t k = 0; k < s.reqs.size(); ++k) {
+        const ce_request& r = s.reqs[k]->r;
+        ce_batch_item& it = items[k];
+        it.plan = s.plans[k]->plan;
+        it.seed = r.seed;
+        it.request_id = r.request_id;
+        it.first_realization = 0;
+        it.count = r.realizations;
+        it.nbar = r.nbar;
+        it.nbins = r.nbins;
+        it.out_pk = r.out_pk;
+        it.out_counts = r.out_counts;
+        it.out_ntot = r.out_ntot;
+        it.out_cov = r.realizations >= 2 ? r.out_cov : nullptr;
+        it.out_cnorm = nullptr;
+      }
+      // an invalid item makes the batch launch nothing: then every request runs alone, so a
+      // failing request fails alone
+      batched = ce_pipeline_run_batch(s.ctx, items.data(), (int64_t)items.size(), s.stream) == CE_OK;
+    }
+    if (!batched)
+      for (size_t k = 0; k < s.reqs.size(); ++k) rs[k] = run_alone(*s.reqs[k], s.plans[k]);
+    const bool recorded = hipEventRecord(s.done, s.stream) == hipSuccess;
+    size_t kept = 0;
+    for (size_t k = 0; k < s.reqs.size(); ++k) {
+      const ce_status why = rs[k] != CE_OK ? rs[k] : (recorded ? CE_OK : CE_E_DEVICE);
+      if (why != CE_OK) {
+        fail(*s.reqs[k], why);
+        s.plans[k]->users--;
+      } else {
+        s.reqs[kept] = s.reqs[k];
+        s.plans[kept] = s.plans[k];
+        ++kept;
+      }
+    }
+    s.reqs.resize(kept);
+    s.plans.resize(kept);
+  }
+
+  // At most one admission onto the free slot s (a group of requests), from the first
+  // kLookahead queued requests, oldest first.
   bool admit_one(Slot& s) {
     bool progress = false;
+    size_t want = 0;
     for (size_t i = 0; i < queue.size() && i < kLookahead;) {
       const std::shared_ptr<Req> q = queue[i];
       if (q->state == 4) {  // cancelled
@@ -257,11 +314,24 @@ struct ce_server {
         ++i;
         continue;
       }
-      bool never = false;
-      if (admit(s, q, pe, &never)) {
-        queue.erase(queue.begin() + (std::ptrdiff_t)i);
-        return true;
+      const bool first = s.reqs.empty();
+      if (!first && ((int)s.reqs.size() >= cfg.max_group || q->scratch > kGroupScratch)) {
+        ++i;
+        continue;
       }
+      pe->users++;  // pinned while making room
+      bool never = false;
+      if (reserve(s, *q, want, first, &never)) {
+        want += q->scratch;
+        s.reqs.push_back(q);
+        s.plans.push_back(pe);
+        queue.erase(queue.begin() + (std::ptrdiff_t)i);
+        progress = true;
+        if (q->scratch > kGroupScratch) break;  // a large request runs alone
+        continue;
+      }
+      pe->users--;
+      if (!first) break;  // the group is complete
       if (never) {  // nothing runs and it still does not fit: it can never be admitted
         queue.erase(queue.begin() + (std::ptrdiff_t)i);
         fail(*q, CE_E_OOM);
@@ -270,6 +340,7 @@ struct ce_server {
       st.admission_stalls++;  // the oldest request with a plan waits for memory; keep the order
       return progress;
     }
+    if (!s.reqs.empty()) launch(s);
     return progress;
   }
 
@@ -293,14 +364,14 @@ struct ce_server {
       bool progress = false;
       if (!queue.empty()) prefetch_plans();
       for (auto& s : slots)
-        if (s.req && hipEventQuery(s.done) != hipErrorNotReady) {  // done, or failed: complete() reports it
+        if (s.busy() && hipEventQuery(s.done) != hipErrorNotReady) {  // done, or failed: complete() reports it
           complete(s);
           progress = true;
         }
       for (auto& s : slots)
-        if (!s.req && !queue.empty()) progress |= admit_one(s);
+        if (!s.busy() && !queue.empty()) progress |= admit_one(s);
       bool busy = false;
-      for (auto& s : slots) busy |= (bool)s.req;
+      for (auto& s : slots) busy |= s.busy();
       if (stop && !busy && queue.empty()) break;
       if (!progress) {
         if (busy)
@@ -357,6 +428,8 @@ ce_status ce_server_create(int device, const ce_server_config* cfg, ce_server** 
   s->cfg = cfg ? *cfg : ce_server_config{};
   if (s->cfg.slots <= 0) s->cfg.slots = 4;
   if (s->cfg.slots > 32) return CE_E_INVALID;
+  if (s->cfg.max_group <= 0) s->cfg.max_group = kMaxGroup;
+  if (s->cfg.max_group > kMaxGroup) return CE_E_INVALID;
   if (s->cfg.hbm_budget_bytes == 0) {
     // three quarters of the device memory free at creation
     size_t free_b = 0, total_b = 0;
@@ -390,13 +463,15 @@ ce_status ce_server_create(int device, const ce_server_config* cfg, ce_server** 
   return CE_OK;
 }
 
-ce_status ce_server_submit(ce_server* s, const ce_request* r, uint64_t* ticket) {
-  if (!s || !r || !ticket || !r->out_pk || r->realizations <= 0 || r->nbins <= 0) return CE_E_INVALID;
+namespace {
+// A queued copy of *r (a tabulated xi copied), or nullptr when r is invalid.
+std::shared_ptr<Req> make_request(const ce_request* r) {
+  if (!r || !r->out_pk || r->realizations <= 0 || r->nbins <= 0) return nullptr;
   auto q = std::make_shared<Req>();
   q->arrival = Clock::now();
   q->r = *r;
   if (r->xi.kind == CE_XI_TABLE) {
-    if (!r->xi.table || r->geom.ndim < 1 || r->geom.ndim > 3) return CE_E_INVALID;
+    if (!r->xi.table || r->geom.ndim < 1 || r->geom.ndim > 3) return nullptr;
     double n = 1;
     for (int i = 0; i < r->geom.ndim; ++i) n *= (double)(r->geom.n[i] + 1);
     q->table.assign(r->xi.table, r->xi.table + (size_t)n);
@@ -404,13 +479,29 @@ ce_status ce_server_submit(ce_server* s, const ce_request* r, uint64_t* ticket) 
   }
   q->key = plan_key(q->r, q->table);
   q->scratch = scratch_bytes(q->r);
+  return q;
+}
+}  // namespace
+
+ce_status ce_server_submit(ce_server* s, const ce_request* r, uint64_t* ticket) {
+  return ce_server_submit_many(s, r, 1, ticket);
+}
+
+ce_status ce_server_submit_many(ce_server* s, const ce_request* r, int64_t n, uint64_t* tickets) {
+  if (!s || !r || !tickets || n <= 0) return CE_E_INVALID;
+  std::vector<std::shared_ptr<Req>> qs((size_t)n);
+  for (int64_t k = 0; k < n; ++k)
+    if (!(qs[(size_t)k] = make_request(r + k))) return CE_E_INVALID;
   std::lock_guard<std::mutex> lock(s->mu);
   if (s->stop) return CE_E_INVALID;
-  q->ticket = s->next_ticket++;
-  *ticket = q->ticket;
-  s->queue.push_back(q);
-  s->all[q->ticket] = q;
-  s->st.submitted++;
+  for (int64_t k = 0; k < n; ++k) {
+    auto& q = qs[(size_t)k];
+    q->ticket = s->next_ticket++;
+    tickets[k] = q->ticket;
+    s->queue.push_back(q);
+    s->all[q->ticket] = q;
+    s->st.submitted++;
+  }
   s->cv.notify_one();
   return CE_OK;
 }

@@ -69,9 +69,9 @@ def _log_uniform_smooth(rng, lo, hi):
             return j
 
 
-def serving_trace(rate=2000.0, duration=20.0, seed=5, max_side_2d=2048, max_side_3d=256):
+def serving_trace(rate=2000.0, duration=20.0, seed=5, max_side_2d=2048, max_side_3d=256, max_realizations=64):
     """Poisson arrivals mixing 2-D and 3-D requests from a menu of 16 two-point functions.
-    Sides are 16 j with j 7-smooth."""
+    Sides are 16 j with j 7-smooth; realizations log-uniform in 1 .. max_realizations."""
     rng = np.random.default_rng(seed)
     menu2 = [_powexp(s2, r0, 300.0) for s2, r0 in zip(np.linspace(0.2, 2.0, 8), np.linspace(2.0, 10.0, 8))]
     menu3 = [_powexp(s2, r0, rc) for s2, r0, rc in
@@ -89,7 +89,7 @@ def serving_trace(rate=2000.0, duration=20.0, seed=5, max_side_2d=2048, max_side
         else:
             N = 16 * _log_uniform_smooth(rng, 2, max_side_3d // 16)
             n, h, xi = (N, N, N), (1.0, 1.0, 1.0), menu3[int(rng.integers(8))]
-        R = int(np.round(np.exp(rng.uniform(0.0, np.log(64)))))
+        R = int(np.round(np.exp(rng.uniform(0.0, np.log(max_realizations)))))
         reqs.append(dict(request_id=i, arrival=t, n=n, h=h, xi=xi, realizations=max(R, 1),
                          nbar=float(rng.choice([0.1, 0.3, 1.0, 5.0])), nbins=32, seed=0))
         i += 1

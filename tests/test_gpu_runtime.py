@@ -143,6 +143,58 @@ def test_server_mix_matches_requests_alone(ce, slots):
     assert stats["p99_ms"] >= stats["p50_ms"] > 0
 
 
+def test_server_groups_small_requests(ce):
+    """A burst of small requests on one slot (ce_server_submit_many): the scheduler admits them
+    in groups (one batched call per group), each request still equals its ce_pipeline_run
+    alone, and a request that is invalid for the pipeline (negative nbar) fails alone inside
+    its group."""
+    b, ctx = ce
+    shapes = [((32, 32), dict(kind="exp", sigma2=0.5, a=3.0), 0), ((48, 64), dict(kind="exp", sigma2=0.8, a=4.0), 1),
+              ((16, 16, 16), dict(kind="exp", sigma2=0.6, a=1.2), 0), ((80, 80), dict(kind="exp", sigma2=1.0, a=5.0), 0)]
+    reqs = []
+    for i in range(40):
+        n, xi, prec = shapes[i % 4]
+        reqs.append((n, xi, prec, 1 + i % 5, -1.0 if i == 17 else 0.5 + 0.25 * (i % 3), 8 + (i % 2) * 4))
+    server = b.server_create(0, slots=1)
+    try:
+        outs, batch = [], []
+        for i, (n, xi, prec, R, nbar, nb) in enumerate(reqs):
+            o = outputs(int(np.prod(n)), R, nb)
+            outs.append(o)
+            batch.append(dict(n=n, h=(1.0,) * len(n), xi=xi, precision=prec, seed=21, request_id=300 + i,
+                              realizations=R, nbar=nbar, nbins=nb, **o))
+        # the first ten one by one, the rest queued in one call
+        tickets = [b.server_submit_many(server, [q])[0] for q in batch[:10]]
+        tickets += b.server_submit_many(server, batch[10:])
+        states = wait_all(b, server, tickets)
+        stats = b.server_stats(server)
+    finally:
+        b.server_destroy(server)
+    print("launches", stats["launches"], "largest group", stats["largest_group"], flush=True)
+    assert stats["largest_group"] >= 2 and stats["launches"] < len(reqs)
+    plans = {}
+    for i, (n, xi, prec, R, nbar, nb) in enumerate(reqs):
+        st, status, _ = states[tickets[i]]
+        if i == 17:
+            assert st == 3 and status == 1  # CE_E_INVALID, alone
+            continue
+        assert st == 2 and status == 0, (i, st, status)
+        key = (n, prec)
+        if key not in plans:
+            plans[key] = b.plan_embedding(ctx, n, (1.0,) * len(n), xi, prec)
+        ref = outputs(plans[key].cells, R, nb)
+        if R < 2:
+            ref["out_cov"] = None
+        b.pipeline_run(ctx, plans[key], 21, 300 + i, 0, R, nbar, nb, **ref)
+        torch.cuda.synchronize()
+        got = host(outs[i])
+        for k2, v in host(ref).items():
+            assert torch.equal(got[k2], v), (i, k2)
+    for p in plans.values():
+        p.release()
+    assert stats["completed"] == len(reqs) - 1 and stats["failed"] == 1
+
+
 def test_server_request_against_oracle(ce):
     """One served request checked against the oracle end to end (fields are not returned by
     the server, so counts are checked through their statistics: the oracle run on the same
