@@ -368,8 +368,9 @@ ce_status ce_pipeline_run_masked(ce_ctx* ctx, const ce_plan* plan, const float* 
  * over all the group's pairs, every pair reading its own sqrt(lambda) octant, Philox key and
  * counter words, sigma^2 and nbar from a descriptor table; so a batch of many small requests
  * costs a few launches per distinct shape instead of a few per request.  Every item's results
- * equal, bit for bit, those of ce_pipeline_run called for that item alone with the same ctx
- * options.  Fields and delta are not returned in this form.  All items must be valid for
+ * equal, bit for bit, those of ce_pipeline_run (ce_pipeline_run_edges for an item with
+ * kedges) called for that item alone with the same ctx options.  Fields and delta are not
+ * returned in this form.  All items must be valid for
  * ce_pipeline_run (nothing is launched otherwise).  Errors: as ce_pipeline_run. */
 typedef struct {
   const ce_plan* plan;
@@ -384,6 +385,8 @@ typedef struct {
   int64_t* out_ntot;    /* device, nullable, count */
   double* out_cov;      /* device, nullable, nbins^2 (written when count >= 2) */
   double* out_cnorm;    /* device, nullable, nbins^2 (written when count >= 2) */
+  const double* kedges; /* host, nullable: nbins + 1 shell edges in |k| as ce_pipeline_run_edges
+                           (read during the call); items with different edges form different groups */
 } ce_batch_item;
 ce_status ce_pipeline_run_batch(ce_ctx* ctx, const ce_batch_item* items, int64_t n, void* stream);
 
@@ -437,6 +440,7 @@ typedef struct {
   int32_t* out_counts;      /* device, nullable, realizations x N^d */
   int64_t* out_ntot;        /* device, nullable, realizations */
   double* out_cov;          /* device, nullable, nbins^2 (used when realizations >= 2) */
+  const double* kedges;     /* host, nullable: nbins + 1 shell edges in |k| (copied at submit) */
 } ce_request;
 typedef struct {
   int64_t submitted, completed, failed, cache_hits, cache_misses, admission_stalls, queued;

@@ -48,7 +48,8 @@ class PlanInfo(ctypes.Structure):
 class BatchItem(ctypes.Structure):
     _fields_ = [("plan", c_void_p), ("seed", c_u64), ("request_id", c_u32), ("first_realization", c_u64),
                 ("count", c_i64), ("nbar", c_f64), ("nbins", c_i32), ("out_pk", c_void_p),
-                ("out_counts", c_void_p), ("out_ntot", c_void_p), ("out_cov", c_void_p), ("out_cnorm", c_void_p)]
+                ("out_counts", c_void_p), ("out_ntot", c_void_p), ("out_cov", c_void_p), ("out_cnorm", c_void_p),
+                ("kedges", c_void_p)]
 
 
 class ServerConfig(ctypes.Structure):
@@ -58,7 +59,7 @@ class ServerConfig(ctypes.Structure):
 class Request(ctypes.Structure):
     _fields_ = [("geom", Geometry), ("xi", Xi), ("precision", c_i32), ("seed", c_u64), ("request_id", c_u32),
                 ("realizations", c_i64), ("nbar", c_f64), ("nbins", c_i32), ("out_pk", c_void_p),
-                ("out_counts", c_void_p), ("out_ntot", c_void_p), ("out_cov", c_void_p)]
+                ("out_counts", c_void_p), ("out_ntot", c_void_p), ("out_cov", c_void_p), ("kedges", c_void_p)]
 
 
 class ServerStats(ctypes.Structure):
@@ -509,8 +510,11 @@ def pipeline_run_masked(ctx, plan, mask, seed, request_id, first_realization, co
 
 def pipeline_run_batch(ctx, items, stream=None):
     """items: dicts with plan, seed, request_id, first_realization, count, nbar, nbins, out_pk and
-    optional out_counts, out_ntot, out_cov, out_cnorm (device tensors)."""
+    optional out_counts, out_ntot, out_cov, out_cnorm (device tensors) and edges (host sequence
+    of nbins + 1 shell edges)."""
+    import numpy as np
     arr = (BatchItem * max(len(items), 1))()
+    keep = []
     for k, it in enumerate(items):
         plan, count, nb = it["plan"], int(it["count"]), int(it["nbins"])
         a = arr[k]
@@ -523,6 +527,12 @@ def pipeline_run_batch(ctx, items, stream=None):
         a.out_ntot = _ptr(it.get("out_ntot"), torch.int64, count, "out_ntot")
         a.out_cov = _ptr(it.get("out_cov"), torch.float64, nb * nb, "out_cov")
         a.out_cnorm = _ptr(it.get("out_cnorm"), torch.float64, nb * nb, "out_cnorm")
+        if it.get("edges") is not None:
+            e = np.ascontiguousarray(it["edges"], dtype=np.float64)
+            if e.size != nb + 1:
+                raise ValueError("edges must hold nbins + 1 values")
+            keep.append(e)
+            a.kedges = e.ctypes.data
     _check(_pipeline_batch(ctx, arr, len(items), _stream(stream)), "ce_pipeline_run_batch")
 
 
@@ -559,7 +569,7 @@ def server_create(device=0, slots=4, hbm_budget_bytes=0, plan_cache_bytes=0, max
 
 
 def _fill_request(r, n, h, xi, precision, seed, request_id, realizations, nbar, nbins, out_pk,
-                  out_counts=None, out_ntot=None, out_cov=None):
+                  out_counts=None, out_ntot=None, out_cov=None, edges=None):
     cells = 1
     for x in n:
         cells *= int(x)
@@ -573,15 +583,23 @@ def _fill_request(r, n, h, xi, precision, seed, request_id, realizations, nbar, 
     r.out_counts = _ptr(out_counts, torch.int32, realizations * cells, "out_counts")
     r.out_ntot = _ptr(out_ntot, torch.int64, realizations, "out_ntot")
     r.out_cov = _ptr(out_cov, torch.float64, nbins * nbins, "out_cov")
+    if edges is not None:
+        import numpy as np
+        e = np.ascontiguousarray(edges, dtype=np.float64)
+        if e.size != nbins + 1:
+            raise ValueError("edges must hold nbins + 1 values")
+        r.kedges = e.ctypes.data
+        keep = (keep, e)
     return keep
 
 
 def server_submit(server, n, h, xi, precision, seed, request_id, realizations, nbar, nbins, out_pk,
-                  out_counts=None, out_ntot=None, out_cov=None):
-    """Queue one request; returns its ticket.  Output tensors must outlive the request."""
+                  out_counts=None, out_ntot=None, out_cov=None, edges=None):
+    """Queue one request; returns its ticket.  Output tensors must outlive the request; edges
+    (nbins + 1 shell edges in |k|, host) are copied."""
     r = Request()
     keep = _fill_request(r, n, h, xi, precision, seed, request_id, realizations, nbar, nbins, out_pk,
-                         out_counts, out_ntot, out_cov)
+                         out_counts, out_ntot, out_cov, edges)
     t = c_u64()
     _check(_server_submit(server, ctypes.byref(r), ctypes.byref(t)), "ce_server_submit")
     del keep

@@ -1429,17 +1429,25 @@ ce_status pipeline_batch_impl(ce_ctx* ctx, const ce_batch_item* items, int64_t n
   struct Group {
     std::vector<int64_t> idx;
     int64_t pairs = 0, covs = 0;
-    size_t off_desc = 0, off_slot = 0, off_cov = 0;
+    size_t off_desc = 0, off_slot = 0, off_cov = 0, off_th = 0;
+    std::vector<int64_t> tab;  // user shells: thresholds (nbins + 1) then N_b (nbins)
   };
-  // group key: (ndim, sides, periodic sides, cell side, precision, shells)
-  std::map<std::tuple<int, int, int, int, int, int, int, double, int, int>, Group> groups;
+  // group key: (ndim, sides, periodic sides, cell side, precision, shells, user edges)
+  std::map<std::tuple<int, int, int, int, int, int, int, double, int, int, std::vector<double>>, Group> groups;
   for (int64_t i = 0; i < n; ++i) {
     const ce_batch_item& it = items[i];
     if (!it.plan) return CE_E_INVALID;
     CE_TRY(pipeline_check(ctx, it.plan, it.first_realization, it.count, it.nbar, it.nbins, it.out_pk));
+    std::vector<double> ev;
+    if (it.kedges) {
+      for (int b = 0; b <= it.nbins; ++b)
+        if (!std::isfinite(it.kedges[b]) || it.kedges[b] < 0 || (b > 0 && !(it.kedges[b] > it.kedges[b - 1])))
+          return CE_E_INVALID;
+      ev.assign(it.kedges, it.kedges + it.nbins + 1);
+    }
     const ce_plan* pl = it.plan;
     Group& g = groups[std::make_tuple(pl->ndim, pl->n[0], pl->n[1], pl->n[2], pl->M[0], pl->M[1], pl->M[2], pl->h[0],
-                                      pl->prec, (int)it.nbins)];
+                                      pl->prec, (int)it.nbins, std::move(ev))];
     g.idx.push_back(i);
     g.pairs += (it.count + 1) / 2;
     if (it.count >= 2 && (it.out_cov || it.out_cnorm)) g.covs++;
@@ -1455,6 +1463,18 @@ ce_status pipeline_batch_impl(ce_ctx* ctx, const ce_batch_item* items, int64_t n
     bytes = align(bytes + sizeof(SlotOut) * (size_t)(2 * g.pairs));
     g.off_cov = bytes;
     bytes = align(bytes + sizeof(CovItem) * (size_t)g.covs);
+    const std::vector<double>& ev = std::get<10>(kv.first);
+    if (!ev.empty()) {
+      const ce_plan* p = items[g.idx[0]].plan;
+      const int nbins = std::get<9>(kv.first);
+      std::vector<int64_t> nmu;
+      std::vector<double> kmu;
+      shell_thresholds(p->n, p->ndim, p->h[0], nbins, ev.data(), g.tab);
+      shell_table_host(p->n, p->ndim, nbins, nmu, kmu, &g.tab);
+      g.tab.insert(g.tab.end(), nmu.begin(), nmu.end());
+      g.off_th = bytes;
+      bytes = align(bytes + sizeof(int64_t) * g.tab.size());
+    }
   }
   if (!ctx->staged) CE_HIP(hipEventCreateWithFlags(&ctx->staged, hipEventDisableTiming));
   CE_HIP(hipEventSynchronize(ctx->staged));  // the previous batch's tables have been copied
@@ -1505,6 +1525,7 @@ ce_status pipeline_batch_impl(ce_ctx* ctx, const ce_batch_item* items, int64_t n
       }
       if (it.count >= 2 && (it.out_cov || it.out_cnorm)) cov[ci++] = CovItem{it.out_pk, it.count, it.out_cov, it.out_cnorm};
     }
+    if (!g.tab.empty()) std::memcpy(h + g.off_th, g.tab.data(), sizeof(int64_t) * g.tab.size());
   }
   CE_HIP(hipMemcpyAsync(dtab, ctx->pin, bytes, hipMemcpyHostToDevice, s));
   CE_HIP(hipEventRecord(ctx->staged, s));
@@ -1529,8 +1550,14 @@ ce_status pipeline_batch_impl(ce_ctx* ctx, const ce_batch_item* items, int64_t n
     auto* ntot = static_cast<unsigned long long*>(acc);
     CE_HIP(launch_zero_u64(ntot, 2 * npairs, s));
     int64_t* nm = nullptr;
-    const std::vector<double>* km = nullptr;
-    CE_TRY(device_shells(ctx, plan->n, ndim, nbins, &nm, &km));
+    const int64_t* th = nullptr;
+    if (!g.tab.empty()) {
+      th = reinterpret_cast<const int64_t*>(d + g.off_th);
+      nm = reinterpret_cast<int64_t*>(d + g.off_th) + (nbins + 1);
+    } else {
+      const std::vector<double>* km = nullptr;
+      CE_TRY(device_shells(ctx, plan->n, ndim, nbins, &nm, &km));
+    }
     const double norm = std::pow(plan->h[0], ndim) / (double)ncells;
     for (int64_t j = 0; j < npairs; j += cp) {
       const int64_t np = std::min(cp, npairs - j);
@@ -1549,7 +1576,7 @@ ce_status pipeline_batch_impl(ce_ctx* ctx, const ce_batch_item* items, int64_t n
       CE_TRY(run_inverse(ctx, plan, fs, 0, 0, 0, np, e, s, nullptr, ddesc + j));
       double* partials = nullptr;
       int64_t ngroups = 0;
-      CE_TRY(run_forward_bins(ctx, ndim, plan->n, plan->prec, np, H, nbins, &partials, &ngroups, s));
+      CE_TRY(run_forward_bins(ctx, ndim, plan->n, plan->prec, np, H, nbins, &partials, &ngroups, s, nullptr, th));
       CE_PROF(ctx, "bin_reduce", s,
               launch_bin_reduce(partials, np, ngroups, nbins, 2 * np, nm, norm, 1, ntot + 2 * j, dslot + 2 * j,
                                 (double)ncells, nullptr, ctx->flags, s));

@@ -11,6 +11,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cmath>
 #include <chrono>
 #include <condition_variable>
 #include <cstring>
@@ -43,6 +44,7 @@ struct Req {
   uint64_t ticket = 0;
   ce_request r{};
   std::vector<double> table;  // copy of a tabulated xi
+  std::vector<double> edges;  // copy of the user shell edges (empty: the default shells)
   std::string key;
   Clock::time_point arrival;
   int state = 0;  // 0 queued, 1 running, 2 done, 3 failed, 4 cancelled
@@ -236,9 +238,13 @@ struct ce_server {
     }
     auto run_alone = [&](Req& q, PlanEntry* pe) {
       const ce_request& r = q.r;
+      double* cov = r.realizations >= 2 ? r.out_cov : nullptr;
+      if (!q.edges.empty())
+        return ce_pipeline_run_edges(s.ctx, pe->plan, nullptr, r.seed, r.request_id, 0, r.realizations, r.nbar,
+                                     r.nbins, q.edges.data(), nullptr, nullptr, r.out_counts, r.out_ntot, r.out_pk,
+                                     cov, nullptr, s.stream);
       return ce_pipeline_run(s.ctx, pe->plan, r.seed, r.request_id, 0, r.realizations, r.nbar, r.nbins, nullptr,
-                             nullptr, r.out_counts, r.out_ntot, r.out_pk, r.realizations >= 2 ? r.out_cov : nullptr,
-                             nullptr, s.stream);
+                             nullptr, r.out_counts, r.out_ntot, r.out_pk, cov, nullptr, s.stream);
     };
     std::vector<ce_status> rs(s.reqs.size(), CE_OK);
     bool batched = false;
@@ -259,6 +265,7 @@ struct ce_server {
         it.out_ntot = r.out_ntot;
         it.out_cov = r.realizations >= 2 ? r.out_cov : nullptr;
         it.out_cnorm = nullptr;
+        it.kedges = s.reqs[k]->edges.empty() ? nullptr : s.reqs[k]->edges.data();
       }
       // an invalid item makes the batch launch nothing: then every request runs alone, so a
       // failing request fails alone
@@ -477,6 +484,13 @@ std::shared_ptr<Req> make_request(const ce_request* r) {
     q->table.assign(r->xi.table, r->xi.table + (size_t)n);
     q->r.xi.table = nullptr;
   }
+  if (r->kedges) {
+    q->edges.assign(r->kedges, r->kedges + r->nbins + 1);
+    for (size_t b = 0; b < q->edges.size(); ++b)
+      if (!std::isfinite(q->edges[b]) || q->edges[b] < 0 || (b > 0 && !(q->edges[b] > q->edges[b - 1])))
+        return nullptr;
+  }
+  q->r.kedges = nullptr;
   q->key = plan_key(q->r, q->table);
   q->scratch = scratch_bytes(q->r);
   return q;

@@ -155,6 +155,8 @@ def test_server_groups_small_requests(ce):
     for i in range(40):
         n, xi, prec = shapes[i % 4]
         reqs.append((n, xi, prec, 1 + i % 5, -1.0 if i == 17 else 0.5 + 0.25 * (i % 3), 8 + (i % 2) * 4))
+    # every third request bins in ln k (log-spaced edges up to the pixel scale)
+    edges = {i: np.exp(np.linspace(np.log(0.3), np.log(np.pi), reqs[i][5] + 1)) for i in range(0, 40, 3)}
     server = b.server_create(0, slots=1)
     try:
         outs, batch = [], []
@@ -162,7 +164,7 @@ def test_server_groups_small_requests(ce):
             o = outputs(int(np.prod(n)), R, nb)
             outs.append(o)
             batch.append(dict(n=n, h=(1.0,) * len(n), xi=xi, precision=prec, seed=21, request_id=300 + i,
-                              realizations=R, nbar=nbar, nbins=nb, **o))
+                              realizations=R, nbar=nbar, nbins=nb, edges=edges.get(i), **o))
         # the first ten one by one, the rest queued in one call
         tickets = [b.server_submit_many(server, [q])[0] for q in batch[:10]]
         tickets += b.server_submit_many(server, batch[10:])
@@ -185,11 +187,14 @@ def test_server_groups_small_requests(ce):
         ref = outputs(plans[key].cells, R, nb)
         if R < 2:
             ref["out_cov"] = None
-        b.pipeline_run(ctx, plans[key], 21, 300 + i, 0, R, nbar, nb, **ref)
+        if i in edges:
+            b.pipeline_run_edges(ctx, plans[key], 21, 300 + i, 0, R, nbar, nb, edges[i], **ref)
+        else:
+            b.pipeline_run(ctx, plans[key], 21, 300 + i, 0, R, nbar, nb, **ref)
         torch.cuda.synchronize()
         got = host(outs[i])
         for k2, v in host(ref).items():
-            assert torch.equal(got[k2], v), (i, k2)
+            assert same(got[k2], v), (i, k2)
     for p in plans.values():
         p.release()
     assert stats["completed"] == len(reqs) - 1 and stats["failed"] == 1
@@ -319,6 +324,56 @@ def test_batch_matches_items_alone(ce):
             got = host({key: it[key] for key in ("out_pk", "out_counts", "out_ntot", "out_cov")})
             for key, v in host(ref).items():
                 assert torch.equal(got[key], v), (rep, k, key)
+    for p in plans:
+        p.release()
+
+
+def same(a, b):
+    """Bitwise equality of two tensors, an empty shell's NaN equal to itself."""
+    return np.array_equal(a.numpy(), b.numpy(), equal_nan=True)
+
+
+def test_batch_with_user_edges(ce):
+    """Items with the paper's log-spaced shells (and others with the default shells or other
+    edges, same shapes) in one batch: every item equals its own ce_pipeline_run_edges (or
+    ce_pipeline_run) bit for bit."""
+    import math
+    b, ctx = ce
+    log8 = np.exp(np.linspace(math.log(0.15), math.log(math.pi), 9))
+    log6 = np.exp(np.linspace(math.log(0.3), math.log(math.pi), 7))
+    specs = [  # n, xi, prec, count, nbar, nb, edges
+        ((32, 32), dict(kind="exp", sigma2=1.0, a=3.0), 0, 4, 1.0, 8, log8),
+        ((32, 32), dict(kind="exp", sigma2=1.0, a=3.0), 0, 3, 1.0, 8, None),
+        ((32, 32), dict(kind="exp", sigma2=0.5, a=2.0), 0, 2, 2.0, 8, np.linspace(0.0, math.pi, 9)),
+        ((48, 64), dict(kind="exp", sigma2=0.4, a=5.0), 1, 5, 0.5, 8, log8),
+        ((16, 16, 16), dict(kind="exp", sigma2=0.8, a=1.5), 0, 2, 2.0, 6, log6),
+        ((32, 32), dict(kind="exp", sigma2=0.7, a=3.0), 0, 2, 3.0, 8, log8),
+    ]
+    plans, items = [], []
+    for k, (n, xi, prec, count, nbar, nb, edges) in enumerate(specs):
+        plan = b.plan_embedding(ctx, n, (1.0,) * len(n), xi, prec)
+        plans.append(plan)
+        items.append(dict(plan=plan, seed=7 + k, request_id=60 + k, first_realization=0, count=count, nbar=nbar,
+                          nbins=nb, edges=edges, **outputs(plan.cells, count, nb)))
+    b.pipeline_run_batch(ctx, items)
+    torch.cuda.synchronize()
+    assert b.ctx_check(ctx) == 0
+    for k, it in enumerate(items):
+        ref = outputs(it["plan"].cells, it["count"], it["nbins"])
+        if it["edges"] is None:
+            b.pipeline_run(ctx, it["plan"], it["seed"], it["request_id"], 0, it["count"], it["nbar"], it["nbins"],
+                           **ref)
+        else:
+            b.pipeline_run_edges(ctx, it["plan"], it["seed"], it["request_id"], 0, it["count"], it["nbar"],
+                                 it["nbins"], it["edges"], **ref)
+        torch.cuda.synchronize()
+        got = host({key: it[key] for key in ("out_pk", "out_counts", "out_ntot", "out_cov")})
+        for key, v in host(ref).items():
+            assert same(got[key], v), (k, key)
+    # bad edges reject the whole batch before anything runs
+    bad = dict(items[0], edges=log8[::-1].copy())
+    with pytest.raises(b.CeError):
+        b.pipeline_run_batch(ctx, [items[1], bad])
     for p in plans:
         p.release()
 
