@@ -21,8 +21,13 @@ Readings taken here:
   2 sqrt(sum_i (q~_i / N_i)^2).  Evaluated exactly in integers: with L the
   least common multiple of the N_i, b + 1 is the smallest s >= 0 with
   s^2 L^2 >= sum_i 4 nb^2 (L / N_i)^2 q~_i^2 (for a cubic grid, s^2 N^2 >=
-  4 nb^2 |q~|^2).  Hyperrectangular grids keep square (cubic) cells.  The DC
-  mode and corner modes beyond k_Ny are in no shell.  The paper bins in ln l:
+  4 nb^2 |q~|^2).  The DC mode and corner modes beyond k_Ny are in no shell.
+* Rectangular cells (sides h_i): |k|^2 = sum_i (2 pi q~_i / (N_i h_i))^2, shells linear on
+  (0, pi / h_ref] with h_ref = max h_i (the largest |k| that every axis resolves).  With
+  h_i = h_ref a_i / c_i (a_i / c_i the fraction of smallest denominator c_i <= 64 equal to
+  h_i / h_ref within 1e-12; other ratios are not supported) and D = lcm(N_i a_i), the
+  integers are t = sum_i 4 nb^2 (c_i D / (N_i a_i))^2 q~_i^2 against (s D)^2; equal sides
+  give a_i = c_i = 1, D = L and the rule above.  The paper bins in ln l:
   any ascending shell edges e_b in |k| may be given instead; then, with t the
   integer above (t = nb^2 L^2 (|k| / k_Ny)^2), a mode is in shell b when
   TH_b < t <= TH_{b+1}, TH_b = nb^2 L^2 (e_b h / pi)^2 in FP64, snapped to an
@@ -50,21 +55,49 @@ def signed_freq(n):
     return np.where(q <= n // 2, q, q - n)
 
 
+def cell_ratios(h, d):
+    """(h_ref, a, c): h_ref = max h_i and h_i / h_ref = a_i / c_i, the fraction of smallest
+    denominator c_i <= 64 within 1e-12 relative (ValueError when there is none)."""
+    hs = tuple(float(x) for x in h) if np.ndim(h) else (float(h),) * d
+    href = max(hs)
+    a, c = [], []
+    for x in hs:
+        rho = x / href
+        for den in range(1, 65):
+            num = round(rho * den)
+            if num >= 1 and abs(num - rho * den) <= 1e-12 * rho * den:
+                a.append(num)
+                c.append(den)
+                break
+        else:
+            raise ValueError("cell sides %r: ratio %r is not a fraction with denominator <= 64" % (hs, rho))
+    return href, a, c
+
+
+def grid_weights(n, h):
+    """(D, w, h_ref): |k| / (pi / h_ref) = 2 sqrt(sum_i (w_i q~_i)^2) / D with integer weights
+    w_i = c_i D / (N_i a_i) and D = lcm(N_i a_i) (square cells: D = lcm(N_i), w_i = D / N_i)."""
+    n = tuple(int(x) for x in n)
+    href, a, c = cell_ratios(h, len(n))
+    D = 1
+    for x, ai in zip(n, a):
+        D = D * (x * ai) // math.gcd(D, x * ai)
+    return D, [ci * (D // (x * ai)) for x, ai, ci in zip(n, a, c)], href
+
+
 def shell_thresholds(n, h, nbins, edges):
     """Integer thresholds of user shell edges (|k| values e_0 < ... < e_nb): a mode with the
-    integer t below is in shell b when TH_b < t <= TH_{b+1} (t = nb^2 L^2 (|k| / k_Ny)^2,
-    k_Ny = pi / h).  TH_b is v = nb^2 L^2 (e_b h / pi)^2 evaluated in FP64 in this order,
-    rounded to the nearest integer when it lies within 1e-9 v of one (an edge placed on a mode
-    by an FP64 formula, e.g. linear edges, keeps the mode in the lower shell as the integer rule
-    does) and rounded down otherwise."""
+    integer t below is in shell b when TH_b < t <= TH_{b+1} (t = nb^2 D^2 (|k| / k_Ny)^2,
+    k_Ny = pi / h_ref).  TH_b is v = nb^2 D^2 (e_b h_ref / pi)^2 evaluated in FP64 in this
+    order, rounded to the nearest integer when it lies within 1e-9 v of one (an edge placed on
+    a mode by an FP64 formula, e.g. linear edges, keeps the mode in the lower shell as the
+    integer rule does) and rounded down otherwise."""
     n = tuple(int(x) for x in n)
-    L = 1
-    for x in n:
-        L = L * x // math.gcd(L, x)
+    L, _, href = grid_weights(n, h)
     scale = float(int(nbins) ** 2 * L * L)
     out = []
     for e in edges:
-        x = float(e) * float(h) / math.pi
+        x = float(e) * float(href) / math.pi
         v = scale * (x * x)
         r = math.floor(v + 0.5)
         out.append(int(r) if abs(v - r) <= 1e-9 * v else int(math.floor(v)))
@@ -72,20 +105,19 @@ def shell_thresholds(n, h, nbins, edges):
 
 
 def shell_index(n, nbins, edges=None, h=1.0):
-    """Shell of every mode of a grid of shape n with square / cubic cells, -1 where the mode is
-    in no shell.
+    """Shell of every mode of a grid of shape n with cell sides h (a number or one per axis),
+    -1 where the mode is in no shell.
 
-    |k| / k_Ny = 2 sqrt(sum_i (q~_i / N_i)^2); with L = lcm(N_i) the mode is in shell b = s - 1
-    for the smallest integer s >= 0 with (s L)^2 >= t, t = sum_i 4 nb^2 (L / N_i)^2 q~_i^2,
-    decided in integers (a cubic grid has L = N and t = 4 nb^2 |q~|^2).  With edges (|k| values,
-    nb + 1 ascending, cell side h) the shells are those of ``shell_thresholds``."""
+    Square cells: |k| / k_Ny = 2 sqrt(sum_i (q~_i / N_i)^2); with L = lcm(N_i) the mode is in
+    shell b = s - 1 for the smallest integer s >= 0 with (s L)^2 >= t,
+    t = sum_i 4 nb^2 (L / N_i)^2 q~_i^2, decided in integers (a cubic grid has L = N and
+    t = 4 nb^2 |q~|^2); rectangular cells use the weights of ``grid_weights`` and D for L.
+    With edges (|k| values, nb + 1 ascending) the shells are those of ``shell_thresholds``."""
     n = tuple(int(x) for x in n)
-    L = 1
-    for x in n:
-        L = L * x // math.gcd(L, x)
+    L, w, _ = grid_weights(n, h)
     grids = np.meshgrid(*[signed_freq(x).astype(np.int64) for x in n], indexing="ij")
     nb2 = 4 * int(nbins) ** 2
-    t = sum(nb2 * (L // x) ** 2 * g * g for x, g in zip(n, grids))
+    t = sum(nb2 * wi * wi * g * g for wi, g in zip(w, grids))
     if edges is not None:
         th = shell_thresholds(n, h, nbins, edges)
         b = np.searchsorted(th, t, side="left") - 1  # number of thresholds below t, minus one
@@ -101,11 +133,15 @@ def shell_index(n, nbins, edges=None, h=1.0):
 
 
 def shell_stats(n, h, nbins, edges=None):
-    """(N_b, mean |k| per shell) for a grid of shape n with cell side h."""
+    """(N_b, mean |k| per shell) for a grid of shape n with cell sides h."""
     n = tuple(int(x) for x in n)
     b = shell_index(n, nbins, edges, h)
-    grids = np.meshgrid(*[signed_freq(x).astype(np.float64) / x for x in n], indexing="ij")
-    kmag = 2.0 * np.pi * np.sqrt(sum(g * g for g in grids)) / h
+    hs = tuple(float(x) for x in h) if np.ndim(h) else (float(h),) * len(n)
+    href = max(hs)
+    # |k| h_ref = 2 pi sqrt(sum_i ((q~_i / N_i) / (h_i / h_ref))^2)
+    grids = np.meshgrid(*[(signed_freq(x).astype(np.float64) / x) / (hi / href) for x, hi in zip(n, hs)],
+                        indexing="ij")
+    kmag = 2.0 * np.pi * np.sqrt(sum(g * g for g in grids)) / href
     sel = b >= 0
     nmodes = np.bincount(b[sel], minlength=nbins).astype(np.int64)
     ksum = np.bincount(b[sel], weights=kmag[sel], minlength=nbins)
@@ -127,7 +163,8 @@ def contrast_from_counts(counts, ntot=None, mask=None):
 
 
 def power_spectrum(phi, h, nbins, edges=None):
-    """P^_b = (h^d / N^d) mean_{q in b} |F(q)|^2 for one map phi (eq. Def spec)."""
+    """P^_b = (prod_i h_i / N^d) mean_{q in b} |F(q)|^2 for one map phi (eq. Def spec; h a
+    number or one cell side per axis)."""
     phi = np.asarray(phi, dtype=np.float64)
     n = phi.shape
     F = np.fft.fftn(phi)
@@ -138,7 +175,8 @@ def power_spectrum(phi, h, nbins, edges=None):
     sums = np.bincount(b[sel], weights=p2[sel], minlength=nbins)
     with np.errstate(invalid="ignore", divide="ignore"):
         mean = sums / nmodes
-    return (h ** phi.ndim / float(np.prod(n))) * mean
+    cell = float(np.prod([float(x) for x in h])) if np.ndim(h) else float(h) ** phi.ndim
+    return (cell / float(np.prod(n))) * mean
 
 
 def estimate_pk(maps, h, nbins, kind="field", ntot=None, mask=None, edges=None):

@@ -168,3 +168,55 @@ def test_kmax_edges_take_the_corners():
     e = np.linspace(0.0, math.pi * math.sqrt(2.0) / h, nb + 1)
     nm, km = pk.shell_stats(n, h, nb, e)
     assert nm.sum() == 32 * 32 - 1
+
+
+# rectangular cells (h_i differ): shells in |k| = 2 pi sqrt(sum (q~_i / (N_i h_i))^2) up to
+# pi / max h_i
+
+@pytest.mark.parametrize("n,h,nb", [((16, 32), (2.0, 1.0), 10), ((24, 20), (0.5, 0.75), 12),
+                                    ((12, 16, 10), (1.0, 0.5, 1.5), 7), ((30, 18), (1.0, 1.0 / 3.0), 9)])
+def test_rectangular_cells_match_direct_classification(n, h, nb):
+    """Every mode away from an edge lands where the plain FP64 |k| puts it."""
+    b = pk.shell_index(n, nb, h=h)
+    grids = np.meshgrid(*[pk.signed_freq(x) for x in n], indexing="ij")
+    k = 2 * math.pi * np.sqrt(sum((g / (x * hi)) ** 2 for g, x, hi in zip(grids, n, h)))
+    u = nb * k / (math.pi / max(h))
+    clear = np.abs(u - np.round(u)) > 1e-9
+    want = np.where(u > 0, np.ceil(u) - 1, -1).astype(np.int64)
+    want = np.where(want < nb, want, -1)
+    assert clear.sum() > 0.5 * clear.size
+    assert np.array_equal(b[clear], want[clear])
+    nm, km = pk.shell_stats(n, h, nb)
+    ok = nm > 0
+    assert nm.sum() == np.count_nonzero((u > 0) & (u <= nb + 1e-12))
+    # mean |k| of every shell lies inside it
+    assert np.all(km[ok] > (np.arange(nb)[ok]) * math.pi / max(h) / nb - 1e-12)
+    assert np.all(km[ok] <= (np.arange(nb)[ok] + 1) * math.pi / max(h) / nb + 1e-12)
+
+
+def test_rectangular_cells_reduce_to_a_square_grid():
+    """16 x 32 cells of 2 x 1 have the same |k| as the 32 x 32 unit grid on the shared modes
+    and shells of the same width (pi / 2 over nb against pi over 2 nb): identical shells."""
+    nb = 8
+    rect = pk.shell_index((16, 32), nb, h=(2.0, 1.0))
+    sq = pk.shell_index((32, 32), 2 * nb)
+    for q0 in range(16):
+        s0 = q0 if q0 <= 8 else q0 - 16
+        for q1 in range(32):
+            want = sq[s0 % 32, q1]
+            assert rect[q0, q1] == (want if want < nb else -1)
+    with pytest.raises(ValueError):
+        pk.shell_index((16, 16), 4, h=(1.0, math.sqrt(0.5)))
+
+
+def test_rectangular_cells_parseval():
+    """Shells that take every nonzero mode: sum_b P_b N_b = (prod h_i)(sum phi^2 - (sum phi)^2 / N)."""
+    rng = np.random.default_rng(3)
+    n, h, nb = (24, 16), (0.5, 1.5), 5
+    phi = rng.normal(size=n)
+    edges = np.linspace(0.0, 2 * math.pi * math.sqrt(sum((0.5 / x) ** 2 for x in h)) * 1.01, nb + 1)
+    p = pk.power_spectrum(phi, h, nb, edges)
+    nm, _ = pk.shell_stats(n, h, nb, edges)
+    assert nm.sum() == phi.size - 1
+    want = h[0] * h[1] * (np.sum(phi ** 2) - phi.sum() ** 2 / phi.size)
+    assert abs(np.nansum(p * nm) / want - 1) < 1e-12
