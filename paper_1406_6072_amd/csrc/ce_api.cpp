@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -148,7 +149,8 @@ LineGeom make_geom(int L, int K, int64_t A, int64_t B, int64_t nitems, int64_t i
 struct SharedTables {
   std::mutex mu;
   std::map<std::tuple<int, int, int>, void*> tw, stw;  // (device, L, precision)
-  std::map<std::tuple<int, int, int, int, int, int>, std::pair<int64_t*, std::vector<double>>> shells;  // (device, n0, n1, n2, d, nb)
+  std::map<std::tuple<int, int, int, int, int, int, int64_t>, std::pair<int64_t*, std::vector<double>>>
+      shells;  // (device, n0, n1, n2, d, nb, cell-side ratios)
 };
 SharedTables& shared_tables() {
   static SharedTables* t = new SharedTables();
@@ -487,47 +489,91 @@ hipError_t build_lag_octant(const ce_geometry* geom, const ce_xi* xi, double* ou
   return e;
 }
 
-// Shells need square (cubic) cells; the side counts may differ (hyperrectangular surveys).
-bool equal_cells(const ce_geometry* g) {
-  for (int i = 1; i < g->ndim; ++i)
-    if (g->h[i] != g->h[0]) return false;
+// Cell sides of the shells: h_ref = max h_i and h_i / h_ref = a_i / c_i, the fraction of
+// smallest denominator c_i <= 64 within 1e-12 relative (square cells: a_i = c_i = 1).  False
+// when a ratio has no such fraction (the integer shell rule needs one).  h may be null (unit
+// cells).
+struct CellRatios {
+  double href = 1.0;
+  double rho[3] = {1.0, 1.0, 1.0};  // h_i / h_ref
+  int64_t a[3] = {1, 1, 1}, c[3] = {1, 1, 1};
+};
+bool cell_ratios(const double* h, int ndim, CellRatios& r) {
+  r = CellRatios();
+  if (!h) return true;
+  r.href = 0.0;
+  for (int i = 0; i < ndim; ++i) r.href = std::max(r.href, h[i]);
+  if (!(r.href > 0)) return false;
+  for (int i = 0; i < ndim; ++i) {
+    const double rho = h[i] / r.href;
+    r.rho[i] = rho;
+    bool found = false;
+    for (int den = 1; den <= 64 && !found; ++den) {
+      const double num = std::round(rho * den);
+      if (num >= 1 && std::fabs(num - rho * den) <= 1e-12 * rho * den) {
+        r.a[i] = (int64_t)num;
+        r.c[i] = den;
+        found = true;
+      }
+    }
+    if (!found) return false;
+  }
   return true;
 }
 
-// Integer shell rule of a grid with sides n[0..ndim): mode q~ is in shell s - 1 for the smallest
-// s >= 0 with (s L)^2 >= t = sum_i T_i q~_i^2, L = lcm(n_i), T_i = 4 nb^2 (L / n_i)^2 (the cubic
-// rule has L = N, T = 4 nb^2).  False when the integers could overflow.
+// h_0^d for square (cubic) cells, else the product of the sides
+double cell_volume(const double* h, int ndim) {
+  bool equal = true;
+  double v = 1.0;
+  for (int i = 0; i < ndim; ++i) {
+    equal = equal && h[i] == h[0];
+    v *= h[i];
+  }
+  return equal ? std::pow(h[0], ndim) : v;
+}
+
+// Integer shell rule of a grid with sides n[0..ndim) and cell sides h (nullable: unit cells):
+// mode q~ is in shell s - 1 for the smallest s >= 0 with (s D)^2 >= t = sum_i T_i q~_i^2, with
+// D = lcm(n_i a_i) and T_i = 4 nb^2 (c_i D / (n_i a_i))^2 (CellRatios; square cells: D = lcm(n_i),
+// T_i = 4 nb^2 (D / n_i)^2, the cubic rule D = N, T = 4 nb^2).  Shells are linear in |k| up to
+// pi / h_ref.  False when the cell sides have no small ratio or the integers could overflow.
 struct ShellRule {
   int64_t T[3] = {0, 0, 0};
   int64_t LL = 1;
+  int64_t D = 1;
+  CellRatios cr;
 };
-bool shell_rule(const int* n, int ndim, int nb, ShellRule& r) {
+bool shell_rule(const int* n, int ndim, int nb, ShellRule& r, const double* h = nullptr) {
+  if (!cell_ratios(h, ndim, r.cr)) return false;
   int64_t L = 1;
   for (int i = 0; i < ndim; ++i) {
-    L = L / std::gcd(L, (int64_t)n[i]) * n[i];
+    const int64_t x = (int64_t)n[i] * r.cr.a[i];
+    L = L / std::gcd(L, x) * x;
     if (L > (1ll << 24)) return false;
   }
+  r.D = L;
   r.LL = L * L;
   double tmax = 0;
   for (int i = 0; i < ndim; ++i) {
-    const int64_t m = L / n[i];
+    const int64_t m = r.cr.c[i] * (L / ((int64_t)n[i] * r.cr.a[i]));
     r.T[i] = 4ll * nb * nb * m * m;
     tmax += (double)r.T[i] * (double)(n[i] / 2) * (double)(n[i] / 2);
   }
-  // t, the edges (s L)^2 for s <= nb + 1 and their differences stay far below 2^63
+  // t, the edges (s D)^2 for s <= nb + 1 and their differences stay far below 2^63
   return tmax < 1e17 && (double)(nb + 2) * (nb + 2) * (double)r.LL < 1e17;
 }
 
-// Integer thresholds of user shell edges e_0 < ... < e_nb (|k|, cell side h): TH_b is
-// v = nb^2 L^2 (e_b h / pi)^2 in FP64 (in this order), the nearest integer when v lies within
-// 1e-9 v of one, else floor(v); a mode with t is in shell b when TH_b < t <= TH_{b+1}.
-void shell_thresholds(const int* n, int ndim, double h, int nb, const double* edges, std::vector<int64_t>& th) {
-  int64_t L = 1;
-  for (int i = 0; i < ndim; ++i) L = L / std::gcd(L, (int64_t)n[i]) * n[i];
-  const double scale = (double)((int64_t)nb * nb * L * L);
+// Integer thresholds of user shell edges e_0 < ... < e_nb (|k|): TH_b is
+// v = nb^2 D^2 (e_b h_ref / pi)^2 in FP64 (in this order), the nearest integer when v lies
+// within 1e-9 v of one, else floor(v); a mode with t is in shell b when TH_b < t <= TH_{b+1}.
+void shell_thresholds(const int* n, int ndim, const double* h, int nb, const double* edges,
+                      std::vector<int64_t>& th) {
+  ShellRule sr;
+  shell_rule(n, ndim, nb, sr, h);
+  const double scale = (double)((int64_t)nb * nb * sr.D * sr.D);
   th.resize(nb + 1);
   for (int b = 0; b <= nb; ++b) {
-    const double x = edges[b] * h / M_PI;
+    const double x = edges[b] * sr.cr.href / M_PI;
     const double v = scale * (x * x);
     const double r = std::floor(v + 0.5);
     const double c = std::fabs(v - r) <= 1e-9 * v ? r : std::floor(v);
@@ -535,12 +581,12 @@ void shell_thresholds(const int* n, int ndim, double h, int nb, const double* ed
   }
 }
 
-// Shell table (nmodes and mean |k| in units of 1 / h) of a grid, host, exact integers; th
-// (nullable): user shells as thresholds of t.
+// Shell table (nmodes and mean |k| in units of 1 / h_ref) of a grid, host, exact integers; th
+// (nullable): user shells as thresholds of t; h (nullable): cell sides.
 void shell_table_host(const int* n, int ndim, int nb, std::vector<int64_t>& nm, std::vector<double>& km,
-                      const std::vector<int64_t>* th = nullptr) {
+                      const std::vector<int64_t>* th = nullptr, const double* h = nullptr) {
   ShellRule sr;
-  shell_rule(n, ndim, nb, sr);
+  shell_rule(n, ndim, nb, sr, h);
   nm.assign(nb, 0);
   std::vector<double> ks(nb, 0.0);
   const int n0 = n[0], n1 = ndim >= 2 ? n[1] : 1, n2 = ndim >= 3 ? n[2] : 1;
@@ -554,7 +600,7 @@ void shell_table_host(const int* n, int ndim, int nb, std::vector<int64_t>& nm, 
         int64_t bin;
         if (th) {  // number of thresholds below t, minus one
           bin = (int64_t)(std::lower_bound(th->begin(), th->end(), t) - th->begin()) - 1;
-        } else {   // smallest s >= 0 with s^2 L^2 >= t
+        } else {   // smallest s >= 0 with s^2 D^2 >= t
           int64_t s = (int64_t)std::sqrt((double)t / (double)sr.LL);
           while (s > 0 && (s - 1) * (s - 1) * sr.LL >= t) --s;
           while (s * s * sr.LL < t) ++s;
@@ -562,7 +608,9 @@ void shell_table_host(const int* n, int ndim, int nb, std::vector<int64_t>& nm, 
         }
         if (bin >= 0 && bin < nb) {
           nm[bin] += 1;
-          const double fa = (double)qa / n0, fb = (double)qb / n1, fc = (double)qc / n2;
+          // |k| h_ref = 2 pi sqrt(sum_i ((q~_i / N_i) / (h_i / h_ref))^2)
+          const double fa = ((double)qa / n0) / sr.cr.rho[0], fb = ((double)qb / n1) / sr.cr.rho[1],
+                       fc = ((double)qc / n2) / sr.cr.rho[2];
           ks[bin] += 2.0 * M_PI * std::sqrt(fa * fa + fb * fb + fc * fc);
         }
       }
@@ -573,15 +621,19 @@ void shell_table_host(const int* n, int ndim, int nb, std::vector<int64_t>& nm, 
 }
 
 ce_status device_shells(ce_ctx* ctx, const int* n, int ndim, int nb, int64_t** nm_dev,
-                        const std::vector<double>** km_host) {
+                        const std::vector<double>** km_host, const double* h = nullptr) {
   SharedTables& st = shared_tables();
   std::lock_guard<std::mutex> lock(st.mu);
-  auto key = std::make_tuple(ctx->device, n[0], ndim >= 2 ? n[1] : 1, ndim >= 3 ? n[2] : 1, ndim, nb);
+  CellRatios cr;
+  cell_ratios(h, ndim, cr);
+  int64_t sig = 0;  // the cell-side ratios (7 bits per number)
+  for (int i = 0; i < 3; ++i) sig = (sig << 14) | (cr.a[i] << 7) | cr.c[i];
+  auto key = std::make_tuple(ctx->device, n[0], ndim >= 2 ? n[1] : 1, ndim >= 3 ? n[2] : 1, ndim, nb, sig);
   auto it = st.shells.find(key);
   if (it == st.shells.end()) {
     std::vector<int64_t> nm;
     std::vector<double> km;
-    shell_table_host(n, ndim, nb, nm, km);
+    shell_table_host(n, ndim, nb, nm, km, nullptr, h);
     void* p = nullptr;
     CE_TRY(ctx->table_alloc(&p, sizeof(int64_t) * nb));
     CE_TRY(ctx->upload(p, nm.data(), sizeof(int64_t) * nb));
@@ -1136,7 +1188,8 @@ ce_status run_inverse(ce_ctx* ctx, const ce_plan* p, const InverseSetup& fs, uin
 // shell sums; partials per item.
 ce_status run_forward_bins(ce_ctx* ctx, int ndim, const int* n, int prec, int64_t nitems, void* H, int nb,
                            double** partials_out, int64_t* groups_out, hipStream_t s,
-                           const BinArgs* window = nullptr, const int64_t* th = nullptr) {
+                           const BinArgs* window = nullptr, const int64_t* th = nullptr,
+                           const double* h = nullptr) {
   const size_t elem = prec ? 16 : 8;
   const int N = n[0];
   const int W = 2 * (n[ndim - 1] / 2 + 1);
@@ -1164,7 +1217,7 @@ ce_status run_forward_bins(ce_ctx* ctx, int ndim, const int* n, int prec, int64_
   ba.nb = nb;
   ba.W = W;
   ShellRule sr;
-  if (!shell_rule(n, ndim, nb, sr)) return CE_E_UNSUPPORTED;
+  if (!shell_rule(n, ndim, nb, sr, h)) return CE_E_UNSUPPORTED;
   ba.T0 = sr.T[0];
   ba.T1 = ndim == 3 ? sr.T[1] : 0;
   ba.Tl = sr.T[ndim - 1];
@@ -1235,8 +1288,8 @@ ce_status pipeline_impl(ce_ctx* ctx, const ce_plan* plan, uint64_t seed, uint32_
   if (edges) {
     std::vector<int64_t> th, nmu;
     std::vector<double> kmu;
-    shell_thresholds(plan->n, ndim, plan->h[0], nbins, edges, th);
-    shell_table_host(plan->n, ndim, nbins, nmu, kmu, &th);
+    shell_thresholds(plan->n, ndim, plan->h, nbins, edges, th);
+    shell_table_host(plan->n, ndim, nbins, nmu, kmu, &th, plan->h);
     th.insert(th.end(), nmu.begin(), nmu.end());
     void* p = nullptr;
     CE_TRY(ctx->scratch(13, sizeof(int64_t) * th.size(), &p));
@@ -1245,9 +1298,9 @@ ce_status pipeline_impl(ce_ctx* ctx, const ce_plan* plan, uint64_t seed, uint32_
     th_dev = static_cast<const int64_t*>(p);
     nm = static_cast<int64_t*>(p) + (nbins + 1);
   } else {
-    CE_TRY(device_shells(ctx, plan->n, ndim, nbins, &nm, &km));
+    CE_TRY(device_shells(ctx, plan->n, ndim, nbins, &nm, &km, plan->h));
   }
-  const double norm = std::pow(plan->h[0], ndim) / (double)ncells;
+  const double norm = cell_volume(plan->h, ndim) / (double)ncells;
   for (int64_t j = 0; j < npairs; j += cp) {
     const int64_t np = std::min(cp, npairs - j);
     void* H = nullptr;
@@ -1283,7 +1336,7 @@ ce_status pipeline_impl(ce_ctx* ctx, const ce_plan* plan, uint64_t seed, uint32_
     window.fsum = fsum;
     window.nest = nest;
     CE_TRY(run_forward_bins(ctx, ndim, plan->n, plan->prec, np, H, nbins, &partials, &groups, s,
-                            mask ? &window : nullptr, th_dev));
+                            mask ? &window : nullptr, th_dev, plan->h));
     CE_PROF(ctx, "bin_reduce", s,
             launch_bin_reduce(partials, np, groups, nbins, e.count, nm, norm, mask ? 2 : 1, ntot + 2 * j, nullptr,
                               (double)ncells, out_pk + 2 * j * nbins, ctx->flags, s));
@@ -1297,7 +1350,7 @@ ce_status pipeline_impl(ce_ctx* ctx, const ce_plan* plan, uint64_t seed, uint32_
 // Spectra of a stack of maps described by pl (first forward pass with the contrast or field
 // load, remaining forward passes, shell sums, reduction): the standalone estimator and the
 // spectrum stage of the masked pipeline.
-ce_status spectrum_impl(ce_ctx* ctx, int ndim, const int* n, double h, int prec, PairLoad pl, int64_t count,
+ce_status spectrum_impl(ce_ctx* ctx, int ndim, const int* n, const double* h, int prec, PairLoad pl, int64_t count,
                         int32_t nbins, double* out_pk, int64_t* out_nmodes, double* out_kmean, hipStream_t s,
                         const double* edges = nullptr) {
   int64_t ncells = 1;
@@ -1323,7 +1376,7 @@ ce_status spectrum_impl(ce_ctx* ctx, int ndim, const int* n, double h, int prec,
   if (edges) {
     std::vector<int64_t> th, nmu;
     shell_thresholds(n, ndim, h, nbins, edges, th);
-    shell_table_host(n, ndim, nbins, nmu, km_user, &th);
+    shell_table_host(n, ndim, nbins, nmu, km_user, &th, h);
     std::vector<int64_t> tab(th);
     tab.insert(tab.end(), nmu.begin(), nmu.end());
     void* p = nullptr;
@@ -1336,15 +1389,17 @@ ce_status spectrum_impl(ce_ctx* ctx, int ndim, const int* n, double h, int prec,
   }
   double* partials = nullptr;
   int64_t groups = 0;
-  CE_TRY(run_forward_bins(ctx, ndim, n, prec, nitems, H, nbins, &partials, &groups, s, nullptr, th_dev));
-  if (!edges) CE_TRY(device_shells(ctx, n, ndim, nbins, &nm, &km));
-  const double norm = std::pow(h, ndim) / (double)ncells;
+  CE_TRY(run_forward_bins(ctx, ndim, n, prec, nitems, H, nbins, &partials, &groups, s, nullptr, th_dev, h));
+  if (!edges) CE_TRY(device_shells(ctx, n, ndim, nbins, &nm, &km, h));
+  const double norm = cell_volume(h, ndim) / (double)ncells;
   CE_PROF(ctx, "bin_reduce", s, launch_bin_reduce(partials, nitems, groups, nbins, count, nm, norm, 0, nullptr, nullptr, (double)ncells,
                            out_pk, ctx->flags, s));
   if (out_nmodes) CE_HIP(hipMemcpyAsync(out_nmodes, nm, sizeof(int64_t) * nbins, hipMemcpyDeviceToDevice, s));
   if (out_kmean) {
     std::vector<double> k(*km);
-    for (double& v : k) v /= h;
+    CellRatios cr;
+    cell_ratios(h, ndim, cr);
+    for (double& v : k) v /= cr.href;
     CE_HIP(hipMemcpyAsync(out_kmean, k.data(), sizeof(double) * nbins, hipMemcpyHostToDevice, s));
     CE_HIP(hipStreamSynchronize(s));
   }
@@ -1416,10 +1471,8 @@ ce_status pipeline_check(ce_ctx* ctx, const ce_plan* plan, uint64_t first_realiz
   if (!(nbar >= 0) || !std::isfinite(nbar)) return CE_E_INVALID;
   if (plan->ctx->device != ctx->device) return CE_E_INVALID;
   if ((first_realization + (uint64_t)count + 1) / 2 > 0xFFFFFFFFull) return CE_E_INVALID;
-  for (int d = 1; d < plan->ndim; ++d)
-    if (plan->h[d] != plan->h[0]) return CE_E_UNSUPPORTED;  // shells need square / cubic cells
-  ShellRule sr;
-  if (!shell_rule(plan->n, plan->ndim, nbins, sr)) return CE_E_UNSUPPORTED;
+  ShellRule sr;  // cell sides with small ratios, integers within range
+  if (!shell_rule(plan->n, plan->ndim, nbins, sr, plan->h)) return CE_E_UNSUPPORTED;
   return CE_OK;
 }
 
@@ -1432,8 +1485,9 @@ ce_status pipeline_batch_impl(ce_ctx* ctx, const ce_batch_item* items, int64_t n
     size_t off_desc = 0, off_slot = 0, off_cov = 0, off_th = 0;
     std::vector<int64_t> tab;  // user shells: thresholds (nbins + 1) then N_b (nbins)
   };
-  // group key: (ndim, sides, periodic sides, cell side, precision, shells, user edges)
-  std::map<std::tuple<int, int, int, int, int, int, int, double, int, int, std::vector<double>>, Group> groups;
+  // group key: (ndim, sides, periodic sides, cell sides, precision, shells, user edges)
+  std::map<std::tuple<int, int, int, int, int, int, int, std::array<double, 3>, int, int, std::vector<double>>, Group>
+      groups;
   for (int64_t i = 0; i < n; ++i) {
     const ce_batch_item& it = items[i];
     if (!it.plan) return CE_E_INVALID;
@@ -1446,7 +1500,8 @@ ce_status pipeline_batch_impl(ce_ctx* ctx, const ce_batch_item* items, int64_t n
       ev.assign(it.kedges, it.kedges + it.nbins + 1);
     }
     const ce_plan* pl = it.plan;
-    Group& g = groups[std::make_tuple(pl->ndim, pl->n[0], pl->n[1], pl->n[2], pl->M[0], pl->M[1], pl->M[2], pl->h[0],
+    const std::array<double, 3> hs{pl->h[0], pl->ndim >= 2 ? pl->h[1] : 0.0, pl->ndim >= 3 ? pl->h[2] : 0.0};
+    Group& g = groups[std::make_tuple(pl->ndim, pl->n[0], pl->n[1], pl->n[2], pl->M[0], pl->M[1], pl->M[2], hs,
                                       pl->prec, (int)it.nbins, std::move(ev))];
     g.idx.push_back(i);
     g.pairs += (it.count + 1) / 2;
@@ -1469,8 +1524,8 @@ ce_status pipeline_batch_impl(ce_ctx* ctx, const ce_batch_item* items, int64_t n
       const int nbins = std::get<9>(kv.first);
       std::vector<int64_t> nmu;
       std::vector<double> kmu;
-      shell_thresholds(p->n, p->ndim, p->h[0], nbins, ev.data(), g.tab);
-      shell_table_host(p->n, p->ndim, nbins, nmu, kmu, &g.tab);
+      shell_thresholds(p->n, p->ndim, p->h, nbins, ev.data(), g.tab);
+      shell_table_host(p->n, p->ndim, nbins, nmu, kmu, &g.tab, p->h);
       g.tab.insert(g.tab.end(), nmu.begin(), nmu.end());
       g.off_th = bytes;
       bytes = align(bytes + sizeof(int64_t) * g.tab.size());
@@ -1556,9 +1611,9 @@ ce_status pipeline_batch_impl(ce_ctx* ctx, const ce_batch_item* items, int64_t n
       nm = reinterpret_cast<int64_t*>(d + g.off_th) + (nbins + 1);
     } else {
       const std::vector<double>* km = nullptr;
-      CE_TRY(device_shells(ctx, plan->n, ndim, nbins, &nm, &km));
+      CE_TRY(device_shells(ctx, plan->n, ndim, nbins, &nm, &km, plan->h));
     }
-    const double norm = std::pow(plan->h[0], ndim) / (double)ncells;
+    const double norm = cell_volume(plan->h, ndim) / (double)ncells;
     for (int64_t j = 0; j < npairs; j += cp) {
       const int64_t np = std::min(cp, npairs - j);
       void* H = nullptr;
@@ -1576,7 +1631,8 @@ ce_status pipeline_batch_impl(ce_ctx* ctx, const ce_batch_item* items, int64_t n
       CE_TRY(run_inverse(ctx, plan, fs, 0, 0, 0, np, e, s, nullptr, ddesc + j));
       double* partials = nullptr;
       int64_t ngroups = 0;
-      CE_TRY(run_forward_bins(ctx, ndim, plan->n, plan->prec, np, H, nbins, &partials, &ngroups, s, nullptr, th));
+      CE_TRY(run_forward_bins(ctx, ndim, plan->n, plan->prec, np, H, nbins, &partials, &ngroups, s, nullptr, th,
+                              plan->h));
       CE_PROF(ctx, "bin_reduce", s,
               launch_bin_reduce(partials, np, ngroups, nbins, 2 * np, nm, norm, 1, ntot + 2 * j, dslot + 2 * j,
                                 (double)ncells, nullptr, ctx->flags, s));
@@ -1660,11 +1716,11 @@ ce_status ce_shell_table(const ce_geometry* geom, int32_t nbins, int64_t* nmodes
   int n[3] = {1, 1, 1};
   for (int i = 0; i < geom->ndim; ++i) n[i] = (int)geom->n[i];
   ShellRule sr;
-  if (!equal_cells(geom) || !shell_rule(n, geom->ndim, nbins, sr)) return CE_E_UNSUPPORTED;
+  if (!shell_rule(n, geom->ndim, nbins, sr, geom->h)) return CE_E_UNSUPPORTED;
   std::vector<int64_t> nm;
   std::vector<double> km;
-  shell_table_host(n, geom->ndim, nbins, nm, km);
-  for (double& v : km) v /= geom->h[0];
+  shell_table_host(n, geom->ndim, nbins, nm, km, nullptr, geom->h);
+  for (double& v : km) v /= sr.cr.href;
   std::memcpy(nmodes, nm.data(), sizeof(int64_t) * nbins);
   std::memcpy(kmean, km.data(), sizeof(double) * nbins);
   return CE_OK;
@@ -1691,7 +1747,7 @@ static ce_status estimate_common(ce_ctx* ctx, const ce_geometry* geom, ce_precis
     int nn[3] = {1, 1, 1};
     for (int i = 0; i < geom->ndim; ++i) nn[i] = (int)geom->n[i];
     ShellRule sr;
-    if (!equal_cells(geom) || !shell_rule(nn, geom->ndim, nbins, sr)) return CE_E_UNSUPPORTED;
+    if (!shell_rule(nn, geom->ndim, nbins, sr, geom->h)) return CE_E_UNSUPPORTED;
   }
   std::lock_guard<std::mutex> lock(ctx->mu);
   CE_HIP(hipSetDevice(ctx->device));
@@ -1732,7 +1788,7 @@ static ce_status estimate_common(ce_ctx* ctx, const ce_geometry* geom, ce_precis
       pl.ntot = sgn;
     }
   }
-  return spectrum_impl(ctx, ndim, n, geom->h[0], prec, pl, count, nbins, out_pk, out_nmodes, out_kmean, s, edges);
+  return spectrum_impl(ctx, ndim, n, geom->h, prec, pl, count, nbins, out_pk, out_nmodes, out_kmean, s, edges);
 }
 
 ce_status ce_estimate_pk(ce_ctx* ctx, const ce_geometry* geom, ce_precision precision, ce_map_kind kind,

@@ -68,7 +68,22 @@ def test_host_shell_table_matches_oracle(n, nb):
     assert np.allclose(km[ok], okm[ok], rtol=1e-13)
 
 
-def test_host_shell_table_rejects_unequal_cells():
+@pytest.mark.parametrize("n,h,nb", [((16, 32), (2.0, 1.0), 10), ((24, 20), (0.5, 0.75), 12),
+                                    ((12, 16, 10), (1.0, 0.5, 1.5), 7), ((30, 18), (1.0, 1.0 / 3.0), 9),
+                                    ((64, 48), (0.25, 0.2), 16)])
+def test_host_shell_table_rectangular_cells(n, h, nb):
+    """Rectangular cells: the library's integer shell table equals the oracle's."""
+    from oracle import pk
     from paper_1406_6072_amd import binding
-    with pytest.raises(binding.CeError):
-        binding.shell_table((16, 16), (1.0, 0.5), 4)
+    nm, km = binding.shell_table(n, h, nb)
+    onm, okm = pk.shell_stats(n, h, nb)
+    assert np.array_equal(nm, onm)
+    ok = onm > 0
+    assert np.allclose(km[ok], okm[ok], rtol=1e-13)
+
+
+def test_host_shell_table_rejects_irrational_cell_ratio():
+    from paper_1406_6072_amd import binding
+    with pytest.raises(binding.CeError) as e:
+        binding.shell_table((16, 16), (1.0, 0.5 ** 0.5), 4)
+    assert e.value.status == binding.E_UNSUPPORTED

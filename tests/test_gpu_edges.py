@@ -59,8 +59,8 @@ def test_pipeline_argument_errors(ce):
     with pytest.raises(ValueError):  # the binding refuses an undersized output
         b.pipeline_run(ctx, plan, 1, 0, 0, 9, 1.0, 16, pk)
     plan.release()
-    rect = b.plan_embedding(ctx, (32, 16), (1.0, 0.5), XI, b.F32)
-    # shells need square cells (hyperrectangular sides are fine)
+    rect = b.plan_embedding(ctx, (32, 16), (1.0, 0.5 ** 0.5), XI, b.F32)
+    # the integer shells need cell sides in a ratio of small integers (1 : 0.5 is fine)
     assert status_of(b, b.pipeline_run, ctx, rect, 1, 0, 0, 2, 1.0, 8, pk) == b.E_UNSUPPORTED
     rect.release()
     torch.cuda.synchronize()

@@ -697,3 +697,54 @@ def test_masked_pipeline_with_edges(ce, n, prec):
     assert np.max(np.abs(got[:, ok] / un[:, ok] - 1)) <= TOL_PK[prec]
     assert np.max(np.abs(got[:, ok] / ref[:, ok] - 1)) <= TOL_PK[prec]
     plan.release()
+
+
+@pytest.mark.parametrize("n,h,prec,nb", [((64, 48), (1.0, 0.5), 1, 12), ((96, 80), (0.5, 0.75), 0, 16),
+                                         ((16, 24, 20), (1.0, 0.5, 1.0), 0, 8)])
+def test_rectangular_cells_match_oracle(ce, n, h, prec, nb):
+    """Rectangular cells (h_i differ): field spectra (default and log shells), N_b and mean |k|,
+    and the fused pipeline (plain and masked, against ce_estimate_pk on its own counts and the
+    oracle, to the P(k) tolerance) on the same shells as the oracle's."""
+    import math
+    from synth import workloads
+    b, ctx = ce
+    print("rect cells", n, h, prec, flush=True)
+    count, nbar = 4, 3.0
+    plan = b.plan_embedding(ctx, n, h, dict(kind="exp", sigma2=0.8, a=2.0 if len(n) == 2 else 0.8), prec)
+    cells = plan.cells
+    g = gpu_fields(b, ctx, plan, 5, 1, 0, count)
+    gh = g.cpu().numpy().astype(np.float64).reshape((count,) + n)
+    p = torch.empty(count * nb, dtype=torch.float64, device="cuda")
+    nm = torch.empty(nb, dtype=torch.int64, device="cuda")
+    km = torch.empty(nb, dtype=torch.float64, device="cuda")
+    edges = np.exp(np.linspace(math.log(math.pi / max(h) / 8.0), math.log(math.pi / max(h)), nb + 1))
+    for e in (None, edges):
+        b.estimate_pk(ctx, n, h, prec, b.MAP_FIELD, g, count, None, None, nb, p, nm, km, edges=e)
+        torch.cuda.synchronize()
+        onm, okm = opk.shell_stats(n, h, nb, e)
+        assert np.array_equal(nm.cpu().numpy(), onm)
+        ok = onm > 0
+        assert np.allclose(km.cpu().numpy()[ok], okm[ok], rtol=1e-13)
+        ref = opk.estimate_pk(gh, h, nb, edges=e)
+        assert np.max(np.abs(p.cpu().numpy().reshape(count, nb)[:, ok] / ref[:, ok] - 1)) <= TOL_PK[prec]
+    # fused pipeline, plain and masked
+    mask_np = workloads.survey_mask(n, seed=4)
+    for mask in (None, torch.from_numpy(mask_np.ravel()).cuda()):
+        c = torch.empty(count * cells, dtype=torch.int32, device="cuda")
+        nt = torch.empty(count, dtype=torch.int64, device="cuda")
+        if mask is None:
+            b.pipeline_run(ctx, plan, 5, 1, 0, count, nbar, nb, p, out_counts=c, out_ntot=nt)
+        else:
+            b.pipeline_run_masked(ctx, plan, mask, 5, 1, 0, count, nbar, nb, p, out_counts=c, out_ntot=nt)
+        p2 = torch.empty_like(p)
+        b.estimate_pk(ctx, n, h, prec, b.MAP_COUNTS_DELTAG, c, count, nt, mask, nb, p2)
+        torch.cuda.synchronize()
+        assert b.ctx_check(ctx) == 0
+        got, un = p.cpu().numpy().reshape(count, nb), p2.cpu().numpy().reshape(count, nb)
+        ref = opk.estimate_pk(c.cpu().numpy().reshape((count,) + n), h, nb, kind="counts", ntot=nt.cpu().numpy(),
+                              mask=None if mask is None else mask_np)
+        ok = np.isfinite(ref[0])
+        assert np.array_equal(np.isfinite(got[0]), ok)
+        assert np.max(np.abs(got[:, ok] / un[:, ok] - 1)) <= TOL_PK[prec]
+        assert np.max(np.abs(got[:, ok] / ref[:, ok] - 1)) <= TOL_PK[prec]
+    plan.release()
