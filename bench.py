@@ -202,6 +202,7 @@ def parse():
     ap.add_argument("--plain-realizations", type=int, default=8)
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-graph", action="store_true", help="skip the captured-step (HIP graph) leg")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--lines", default="",
                     help="schedule: max lines per workgroup for noise,inner,last,bins (0 = automatic)")
@@ -589,6 +590,26 @@ def main():
                pipeline_hbm=dict(alg_bytes_per_step=int(total_bytes), alg_GBs=round(pipe_GBs, 1),
                                  frac_of_peak=round(pipe_GBs / HBM_PEAK_GBS, 4)),
                roofline=roofline, kernels=kernels, plan_ms=round(plan_ms, 2))
+
+    if not args.no_graph:
+        # the same step captured once as a HIP graph and replayed (each replay advances the
+        # realizations): the host launch work of the passes is gone
+        g = b.pipeline_graph_create(ctx, plan, w["seed"], w["request_id"], 0, R, nbar, nb, pk_out, out_counts=counts,
+                                    out_ntot=ntot, out_cov=cov, out_cnorm=cnorm)
+        try:
+            for _ in range(args.warmup):
+                b.pipeline_graph_launch(g, stream)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(args.steps):
+                b.pipeline_graph_launch(g, stream)
+            torch.cuda.synchronize()
+            gwall = time.perf_counter() - t0
+        finally:
+            b.pipeline_graph_destroy(g)
+        out["graph"] = dict(value=round(R * args.steps / gwall, 1), unit="realizations/s",
+                            ms_per_step=round(1e3 * gwall / args.steps, 4),
+                            form="ce_pipeline_graph_create once, one ce_pipeline_graph_launch per step")
 
     if not args.no_plain:
         # plain FP64 comparator: FP64 plan, unpruned inverse FFT, unfused, one realization per chain

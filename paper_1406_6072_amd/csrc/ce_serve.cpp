@@ -322,7 +322,8 @@ struct ce_server {
         continue;
       }
       const bool first = s.reqs.empty();
-      if (!first && ((int)s.reqs.size() >= cfg.max_group || q->scratch > kGroupScratch)) {
+      if (!first && (int)s.reqs.size() >= cfg.max_group) break;  // the group is full
+      if (!first && q->scratch > kGroupScratch) {  // a large request waits for a slot of its own
         ++i;
         continue;
       }
