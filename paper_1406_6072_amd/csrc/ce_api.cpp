@@ -1179,6 +1179,15 @@ ce_status run_inverse(ce_ctx* ctx, const ce_plan* p, const InverseSetup& fs, uin
   LineGeom gl = make_geom((int)Ml, (int)Kl, rows, 1, npairs, rows * Ml, 0, elem,
                           mixed_radix(fs.fM[last]) || (epi.mode == 2 && mixed_radix(epi.fwd)), 1,
                           cap_lines(ctx, 2, std::max(2, 256 / std::max(1, (int)Ml / kEPT))));
+  if (epi.mode == 2) {
+    // short rows, few of them: fewer rows per workgroup until the grid has ~2048 workgroups,
+    // and the epilogue's cells spread over up to 256 threads (its FP64 sampler is
+    // latency-bound when a thread holds many cells)
+    const int64_t rows_total = rows * npairs;
+    while (gl.R > 1 && rows_total / gl.R < 2048) gl.R /= 2;
+    gl.groups_per_item = (rows + gl.R - 1) / gl.R;
+    gl.threads = (int)std::min<int64_t>(256, (int64_t)gl.R * Kl);
+  }
   CE_PROF(ctx, epi.mode == 2 ? "inverse_last_fused" : "inverse_last_fields", s,
           launch_row_inverse(p->prec, gl, fs.fM[last], epi, last_in, s));
   return CE_OK;

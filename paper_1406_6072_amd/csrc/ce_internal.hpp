@@ -36,6 +36,7 @@ struct LineGeom {
   int32_t lpitch = 0;          // LDS elements per line buffer
   int32_t nbuf = 1;            // LDS buffers per line: 1 (in place) or 2 (ping-pong, mixed radix)
   int32_t item_minor = 0;      // tile order: 0 = item-major (groups of one item adjacent), 1 = group-major
+  int32_t threads = 0;         // workgroup size when above R nlanes (the fused epilogue spreads its cells)
 };
 
 // Noise prologue of the first inverse pass (lines along axis 0 of the embedding).

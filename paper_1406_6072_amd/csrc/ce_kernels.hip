@@ -583,28 +583,37 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(sizeof
     }
     return;
   }
-  // fused epilogue
+  // fused epilogue: the cells of the group's rows spread over every thread of the workgroup
+  // (more threads per row than line lanes when rows are short)
   unsigned long long sa = 0, sb = 0;
-  if (active) {
+  {
     const uint32_t pair =
         pd ? pd->pair : (uint32_t)(e.first_pair + (e.pair_base ? *e.pair_base : 0ull) + pp.item);
     const uint32_t rid = pd ? pd->rid : e.rid, k0 = pd ? pd->k0 : e.k0, k1 = pd ? pd->k1 : e.k1;
     const T s2h = (T)(pd ? pd->s2half : e.s2half);
     const double nbar = pd ? pd->nbar : e.nbar;
-    T* fa = e.fields ? static_cast<T*>(e.fields) + ra * e.ncells + row * K : nullptr;
-    T* da = e.delta ? static_cast<T*>(e.delta) + ra * e.ncells + row * K : nullptr;
-    int32_t* ca = pd ? (pd->counts ? pd->counts + row * K : nullptr)
-                     : (e.counts ? e.counts + ra * e.ncells + row * K : nullptr);
-    const float* fr = e.mask ? e.mask + row * K : nullptr;
-    for (int i = lane; i < K; i += g.nlanes) {
-      const cpx<T> z = line[pidx(i)];
+    T* fbase = e.fields ? static_cast<T*>(e.fields) + ra * e.ncells : nullptr;
+    T* dbase = e.delta ? static_cast<T*>(e.delta) + ra * e.ncells : nullptr;
+    int32_t* cbase = pd ? pd->counts : (e.counts ? e.counts + ra * e.ncells : nullptr);
+    cpx<T>* set = line - r * g.lpitch;  // row 0 of the buffer set that holds the result
+    // tpr threads per row (the line lanes when the workgroup has no more threads than them)
+    const int tpr = (int)blockDim.x / g.R;
+    const int rr = (int)threadIdx.x / tpr, i0 = (int)threadIdx.x - rr * tpr;
+    const int64_t rowc = pp.line0 + rr;
+    cpx<T>* lr = set + rr * g.lpitch;
+    T* fa = fbase && rr < pp.nl ? fbase + rowc * K : nullptr;
+    T* da = dbase && rr < pp.nl ? dbase + rowc * K : nullptr;
+    int32_t* ca = cbase && rr < pp.nl ? cbase + rowc * K : nullptr;
+    const float* fr = e.mask && rr < pp.nl ? e.mask + rowc * K : nullptr;
+    for (int i = i0; rr < pp.nl && i < K; i += tpr) {
+      const cpx<T> z = lr[pidx(i)];
       const T dla = lognormal_delta<T>(z.x, s2h);
       const T dlb = lognormal_delta<T>(z.y, s2h);
       const double f = fr ? (double)fr[i] : 1.0;
       const double mua = intensity(nbar, f, (double)dla);
       const double mub = intensity(nbar, f, (double)dlb);
       int na, nb;
-      poisson_pair(mua, mub, has_b, (uint32_t)(row * K + i), pair, rid, k0, k1, inv_s, e.flags, na, nb);
+      poisson_pair(mua, mub, has_b, (uint32_t)(rowc * K + i), pair, rid, k0, k1, inv_s, e.flags, na, nb);
       if (fa) {
         fa[i] = z.x;
         if (has_b) fa[i + e.ncells] = z.y;
@@ -628,9 +637,9 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(sizeof
           va = (T)na * q - T(1);
           if (has_b) vb = (T)nb * q - T(1);
         }
-        line[pidx(i)] = {va, vb};
+        lr[pidx(i)] = {va, vb};
       } else {
-        line[pidx(i)] = {(T)na, (T)nb};
+        lr[pidx(i)] = {(T)na, (T)nb};
       }
     }
   }
@@ -1123,7 +1132,7 @@ static size_t lines_lds_bytes(const LineGeom& g, size_t elem) { return (size_t)g
 
 static dim3 pass_grid(const LineGeom& g) { return dim3((unsigned)(g.nitems * g.groups_per_item)); }
 static dim3 pass_block(const LineGeom& g) {
-  const int t = g.R * g.nlanes;
+  const int t = std::max(g.R * g.nlanes, g.threads);
   return dim3((unsigned)((t + 63) / 64 * 64));
 }
 
