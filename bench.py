@@ -30,7 +30,7 @@ HBM_PEAK_GBS = 8000.0
 # on CDNA4, FP64 arithmetic issue at one operation per lane per cycle; packed FP32 is not used).
 VALU_PEAK_GOPS = 256 * 64 * 2.4
 
-# Algorithmic VALU lane-operations per unit of work (op model, measurement).
+# Algorithmic VALU lane-operations per unit of work (the op model: transcendentals count 4).
 OPS_PHILOX = 60          # 10 rounds x (2 32x32->64 products + 4 XOR)
 OPS_BOX_MULLER = 23      # 2 uniforms (2 each), log2/sqrt/sin/cos (4 each, quarter rate), 3 mul
 OPS_SCALE = 2            # complex x real sqrt(lambda)
