@@ -1417,8 +1417,8 @@ ce_status spectrum_impl(ce_ctx* ctx, int ndim, const int* n, const double* h, in
 
 // Forward transform Wm of the indicator f != 0 of a mask (the spectra's row pass on the map
 // [f != 0] with an empty second map, then the remaining line transforms), rows x W complex in
-// the plan precision in scratch slot 12, laid out as one item of the spectra: [q0][column]
-// in 2-D, [q0][q1][column] in 3-D.
+// the plan precision in scratch slot 12, column-major for the binning pass: [column][q0] in
+// 2-D, [q1][column][q0] in 3-D (the spectra's item layout transposed over q0).
 ce_status window_transform(ce_ctx* ctx, const ce_plan* plan, const float* mask, void** out, hipStream_t s) {
   const int ndim = plan->ndim;
   const int N0 = plan->n[0], Nl = plan->n[ndim - 1];
@@ -1450,7 +1450,8 @@ ce_status window_transform(ce_ctx* ctx, const ce_plan* plan, const float* mask, 
     CE_PROF(ctx, "window_axis1", s, launch_line_pass(plan->prec, -1, g2, f1, H, H, s));
   }
   LineGeom g0 = make_geom(N0, N0, 1, item / N0, 1, item, item, elem, mixed_radix(f0), 1, cap_lines(ctx, 1, 32));
-  CE_PROF(ctx, "window_axis0", s, launch_line_pass(plan->prec, -1, g0, f0, H, Wm, s));
+  CE_PROF(ctx, "window_axis0", s, launch_line_pass(plan->prec, -1, g0, f0, H, H, s));
+  CE_PROF(ctx, "window_columns", s, launch_window_columns(plan->prec, H, Wm, N0, item / N0, s));
   *out = Wm;
   return CE_OK;
 }

@@ -182,6 +182,7 @@ hipError_t launch_debug_philox(uint32_t k0, uint32_t k1, const uint32_t* ctr, in
 hipError_t launch_debug_noise(int prec, const NoiseArgs& n, uint64_t pair, int64_t cells, void* out, hipStream_t s);
 hipError_t launch_zero_u64(unsigned long long* p, int64_t n, hipStream_t s);
 hipError_t launch_mask_sum(const float* mask, int64_t n, double* out, hipStream_t s);  // out: 257 doubles
+hipError_t launch_window_columns(int prec, const void* in, void* out, int64_t N0, int64_t C, hipStream_t s);
 // transformed lag tables (ce_xi.hip).  Quadrature of one axis of a quadrant of the cell-overlap
 // integral: nodes u in (0, 1) and weights a = (Gauss-Legendre weight x du/dt) (1 - u).
 constexpr int kCellQuadNodes = 48;

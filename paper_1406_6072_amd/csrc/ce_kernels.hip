@@ -771,8 +771,8 @@ __device__ __forceinline__ void bin_group(const cpx<T>* res, const LineGeom& g, 
       const cpx<T>* line = res + r * g.lpitch;
       // masked pipeline (WIN): the line holds the transform A of N / (f nest) - 1; the
       // contrast's is D = rr A + rm Wm with rr = nest sum(f) / N_tot of the line's realization,
-      // rm = rr - 1 and Wm the transform of the indicator f != 0 (laid out as one item of the
-      // spectra: [q0][column] in 2-D, [q0][q1][column] in 3-D)
+      // rm = rr - 1 and Wm the transform of the indicator f != 0, column-major ([column][q0] in
+      // 2-D, [q1][column][q0] in 3-D: the line's window values are contiguous in q0)
       T rr = T(1), rm = T(0);
       const cpx<T>* wcol = nullptr;
       int64_t wstride = 0;
@@ -781,8 +781,8 @@ __device__ __forceinline__ void bin_group(const cpx<T>* res, const LineGeom& g, 
         const double rd = nt > 0.0 ? bn.nest * *bn.fsum / nt : 0.0;
         rr = (T)rd;
         rm = (T)(rd - 1.0);
-        wcol = static_cast<const cpx<T>*>(bn.win) + (ln - kl) + kz;
-        wstride = (int64_t)(bn.ndim == 3 ? bn.N1 : 1) * W;
+        wcol = static_cast<const cpx<T>*>(bn.win) + ((ln - kl) + kz) * (int64_t)N;
+        wstride = 1;
       }
       if (a0 < a1) {
         e.nonempty = 1;
@@ -1391,6 +1391,34 @@ hipError_t launch_debug_noise(int prec, const NoiseArgs& n, uint64_t pair, int64
 
 hipError_t launch_advance(unsigned long long* p, unsigned long long by, hipStream_t s) {
   hipLaunchKernelGGL(k_advance, dim3(1), dim3(64), 0, s, p, by);
+  return hipGetLastError();
+}
+
+// Window transform to column-major: out[c][a] = in[a][c] for the first Kh columns of every
+// W-wide block (the columns the binning pass reads), so that the pass reads it along a.
+template <typename T>
+__global__ void k_window_columns(const cpx<T>* __restrict__ in, cpx<T>* __restrict__ out, int64_t N0, int64_t C) {
+  __shared__ cpx<T> tile[32][33];
+  const int64_t a0 = (int64_t)blockIdx.y * 32, c0 = (int64_t)blockIdx.x * 32;
+  for (int k = threadIdx.y; k < 32; k += blockDim.y) {
+    const int64_t a = a0 + k, c = c0 + threadIdx.x;
+    if (a < N0 && c < C) tile[k][threadIdx.x] = in[a * C + c];
+  }
+  __syncthreads();
+  for (int k = threadIdx.y; k < 32; k += blockDim.y) {
+    const int64_t c = c0 + k, a = a0 + threadIdx.x;
+    if (a < N0 && c < C) out[c * N0 + a] = tile[threadIdx.x][k];
+  }
+}
+
+hipError_t launch_window_columns(int prec, const void* in, void* out, int64_t N0, int64_t C, hipStream_t s) {
+  const dim3 grid((unsigned)((C + 31) / 32), (unsigned)((N0 + 31) / 32)), block(32, 8);
+  if (prec == 0)
+    hipLaunchKernelGGL(k_window_columns<float>, grid, block, 0, s, static_cast<const cpx<float>*>(in),
+                       static_cast<cpx<float>*>(out), N0, C);
+  else
+    hipLaunchKernelGGL(k_window_columns<double>, grid, block, 0, s, static_cast<const cpx<double>*>(in),
+                       static_cast<cpx<double>*>(out), N0, C);
   return hipGetLastError();
 }
 
