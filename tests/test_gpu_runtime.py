@@ -200,6 +200,27 @@ def test_server_groups_small_requests(ce):
     assert stats["completed"] == len(reqs) - 1 and stats["failed"] == 1
 
 
+def test_server_submit_many_is_all_or_nothing(ce):
+    """A batch submission with one invalid request (bad shell edges) queues nothing."""
+    import math
+    b, _ = ce
+    server = b.server_create(0, slots=1)
+    try:
+        good = dict(n=(32, 32), h=(1.0, 1.0), xi=dict(kind="exp", sigma2=1.0, a=3.0), precision=0, seed=1,
+                    request_id=0, realizations=2, nbar=1.0, nbins=8, **outputs(32 * 32, 2, 8))
+        bad = dict(good, request_id=1, edges=np.linspace(math.pi, 0.0, 9))  # descending
+        with pytest.raises(b.CeError) as e:
+            b.server_submit_many(server, [good, bad, dict(good, request_id=2)])
+        assert e.value.status == b.E_INVALID
+        stats = b.server_stats(server)
+        assert stats["submitted"] == 0 and stats["queued"] == 0
+        t = b.server_submit_many(server, [good])
+        states = wait_all(b, server, t)
+    finally:
+        b.server_destroy(server)
+    assert states[t[0]][0] == 2
+
+
 def test_server_request_against_oracle(ce):
     """One served request checked against the oracle end to end (fields are not returned by
     the server, so counts are checked through their statistics: the oracle run on the same
