@@ -104,7 +104,10 @@ bool factor_length(int L, std::vector<int>& rad) {
   return !rad.empty();
 }
 
-int line_pitch_host(int L) { return L + (L >> 4) + 1; }
+// LDS elements per line: the padded line (one pad per 16 elements) plus a shift that puts
+// the lines of a workgroup on different banks (FP32: 4 elements = 8 banks per line, so the
+// column loads of four lines at the same position do not collide; FP64: 1 element)
+int line_pitch_host(int L, size_t elem) { return L + (L >> 4) + (elem == 8 ? 4 : 1); }
 
 // Lines of length L (FFT), K kept; A x B lines per item.  Chooses R (power of two,
 // lines per workgroup) within the LDS budget and the 1024-thread limit.
@@ -127,7 +130,7 @@ LineGeom make_geom(int L, int K, int64_t A, int64_t B, int64_t nitems, int64_t i
   g.in_item = in_item;
   g.out_item = out_item;
   g.nlanes = (L + kEPT - 1) / kEPT;
-  g.lpitch = line_pitch_host(L);
+  g.lpitch = line_pitch_host(L, elem);
   const size_t per_line = (size_t)g.lpitch * elem * g.nbuf + extra_per_line;
   int R = 1;
   while (R * 2 <= rmax && (size_t)(R * 2) * per_line <= lds_budget && R * 2 * g.nlanes <= kMaxWG) R *= 2;
