@@ -261,40 +261,52 @@ hipError_t astar_all(const int32_t* counts, const float* mask, int64_t cells, in
 // f_i e^A), G the normal law N(-s2/2, s2) of the log-density.  The A integral is a fixed rule
 // (nodes a_q, weights w_q summing to 1 over the law) applied by the host; this kernel forms, for
 // each node q, per-workgroup sums over its cells of the Poisson pmf with lam = nbar f e^{a_q},
-// kPredChunk values of N at a time in registers: the first of a chunk from logs,
-// exp(N ln(lam) - lam - lgamma(N + 1)), the others by p_{N+1} = p_N lam / (N + 1).  Each is
-// reduced over the workgroup in a fixed order into partials[(q * gridDim.x + block) * nhist + N].
-// lgam holds lgamma(N + 1) for N < nhist, then 1 / N for N = 1 .. nhist (at lgam[nhist + N - 1]).
-constexpr int kPredChunk = 16;
-
+// CH values of N at a time in registers: the first of a chunk from logs,
+// exp(N ln(lam) - lam - lgamma(N + 1)) (exp(-lam) for the first chunk), the others by
+// p_{N+1} = p_N lam / (N + 1).  Each is reduced over the workgroup in a fixed order into
+// partials[(q * gridDim.x + block) * nhist + N].  lgam holds lgamma(N + 1) for N < nhist, then
+// 1 / N for N = 1 .. nhist (at lgam[nhist + N - 1]).
+template <int CH>
 __global__ void __launch_bounds__(kCicThreads) k_cic_predict(const float* __restrict__ mask, int64_t cells,
                                                             double nbar, const double* __restrict__ nodes,
                                                             const double* __restrict__ lgam, int nhist,
                                                             double* __restrict__ partials) {
+  constexpr int kPredChunk = CH;
   __shared__ double red[kCicThreads / 64][kPredChunk];
   const int q = blockIdx.y;
   const double ea = exp(nodes[q]);
   const int64_t stride = (int64_t)gridDim.x * kCicThreads;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   for (int c0 = 0; c0 < nhist; c0 += kPredChunk) {
-    double acc[kPredChunk];
+    double acc[kPredChunk], acc2[kPredChunk];
 #pragma unroll
-    for (int j = 0; j < kPredChunk; ++j) acc[j] = 0.0;
-    for (int64_t i = blockIdx.x * (int64_t)kCicThreads + threadIdx.x; i < cells; i += stride) {
+    for (int j = 0; j < kPredChunk; ++j) acc[j] = acc2[j] = 0.0;
+    // two cells per step (independent recursions side by side); a masked cell (f = 0) or a
+    // missing second cell contributes exactly 0 through its own accumulators
+    for (int64_t i = blockIdx.x * (int64_t)kCicThreads + threadIdx.x; i < cells; i += 2 * stride) {
+      const int64_t i2 = i + stride;
       const float f = mask ? mask[i] : 1.0f;
-      if (f == 0.0f) continue;
-      const double lam = nbar * (double)f * ea;
-      double p = exp((double)c0 * log(lam) - lam - lgam[c0]);
+      const float f2 = i2 < cells ? (mask ? mask[i2] : 1.0f) : 0.0f;
+      const double lam = nbar * (double)f * ea, lam2 = nbar * (double)f2 * ea;
+      double p = 0.0, p2 = 0.0;
+      if (f != 0.0f) p = c0 == 0 ? exp(-lam) : exp((double)c0 * log(lam) - lam - lgam[c0]);
+      if (f2 != 0.0f) p2 = c0 == 0 ? exp(-lam2) : exp((double)c0 * log(lam2) - lam2 - lgam[c0]);
       acc[0] += p;
+      acc2[0] += p2;
 #pragma unroll
       for (int j = 1; j < kPredChunk; ++j) {
         const int N = c0 + j;
         if (N < nhist) {
-          p *= lam * lgam[nhist + N - 1];
+          const double r = lgam[nhist + N - 1];
+          p *= lam * r;
+          p2 *= lam2 * r;
           acc[j] += p;
+          acc2[j] += p2;
         }
       }
     }
+#pragma unroll
+    for (int j = 0; j < kPredChunk; ++j) acc[j] += acc2[j];
     // fixed-order reduction: within each wave by halving, then the waves in order
 #pragma unroll
     for (int j = 0; j < kPredChunk; ++j) {
@@ -409,8 +421,11 @@ hipError_t launch_cic_predict(const float* mask, int64_t cells, double nbar, con
                               const double* weights, int nq, const double* lgam, int nhist, double* partials,
                               double* out, hipStream_t s) {
   const int64_t bx = cic_predict_blocks(cells, nq);
-  hipLaunchKernelGGL(k_cic_predict, dim3((unsigned)bx, (unsigned)nq), dim3(kCicThreads), 0, s, mask, cells, nbar,
-                     nodes, lgam, nhist, partials);
+  // 24 values of N per pass and two cells per step: wide enough for two independent FP64
+  // recursions per thread, narrow enough to keep several waves per SIMD to hide their latency
+  // (on a 2^20-cell mask with 42 bins, about half the time of 16 values and one cell)
+  hipLaunchKernelGGL(k_cic_predict<24>, dim3((unsigned)bx, (unsigned)nq), dim3(kCicThreads), 0, s, mask, cells,
+                     nbar, nodes, lgam, nhist, partials);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_cic_predict_sum, dim3((unsigned)nhist), dim3(kCicThreads), 0, s, partials, nq, bx, weights,
