@@ -196,6 +196,39 @@ __global__ void __launch_bounds__(kCicThreads) k_astar_shift(const float* __rest
     if (mask == nullptr || mask[i] != 0.0f) o[i] = (T)((double)o[i] - d);
 }
 
+// The same shift four cells at a time with 16-byte accesses (cells a multiple of 4, aligned
+// buffers): the pass is bound by HBM and the wide accesses halve its instruction count.
+template <typename T>
+__device__ __forceinline__ T shifted(T v, float m, double d) {
+  return m != 0.0f ? (T)((double)v - d) : v;
+}
+__device__ __forceinline__ void shift4(float* o, float4 m, double d) {
+  float4 x = *reinterpret_cast<float4*>(o);
+  x = make_float4(shifted(x.x, m.x, d), shifted(x.y, m.y, d), shifted(x.z, m.z, d), shifted(x.w, m.w, d));
+  *reinterpret_cast<float4*>(o) = x;
+}
+__device__ __forceinline__ void shift4(double* o, float4 m, double d) {
+  double2 x = reinterpret_cast<double2*>(o)[0], y = reinterpret_cast<double2*>(o)[1];
+  x = make_double2(shifted(x.x, m.x, d), shifted(x.y, m.y, d));
+  y = make_double2(shifted(y.x, m.z, d), shifted(y.y, m.w, d));
+  reinterpret_cast<double2*>(o)[0] = x;
+  reinterpret_cast<double2*>(o)[1] = y;
+}
+template <typename T>
+__global__ void __launch_bounds__(kCicThreads) k_astar_shift4(const float* __restrict__ mask, int64_t cells,
+                                                              double off, const double* __restrict__ mean,
+                                                              T* __restrict__ out) {
+  const int r = blockIdx.y;
+  const double d = mean[r] - off;
+  T* o = out + (int64_t)r * cells;
+  const int64_t n4 = cells / 4;
+  const int64_t stride = (int64_t)gridDim.x * kCicThreads;
+  for (int64_t i = blockIdx.x * (int64_t)kCicThreads + threadIdx.x; i < n4; i += stride) {
+    const float4 m = mask ? reinterpret_cast<const float4*>(mask)[i] : make_float4(1.0f, 1.0f, 1.0f, 1.0f);
+    shift4(o + 4 * i, m, d);
+  }
+}
+
 // mean[r] = (sum of A*) / (unmasked cells) from the partials of one map, in a fixed order;
 // 0 when every cell is masked.
 __global__ void __launch_bounds__(kCicThreads) k_astar_mean(const double* __restrict__ partials, int64_t blocks,
@@ -246,11 +279,17 @@ hipError_t astar_all(const int32_t* counts, const float* mask, int64_t cells, in
                      mean);
   e = hipGetLastError();
   if (e != hipSuccess || !subtract) return e;
-  const int64_t bx = blocks_per_map(cells);
+  const bool wide = cells % 4 == 0 && reinterpret_cast<uintptr_t>(out) % (4 * sizeof(T)) == 0 &&
+                    reinterpret_cast<uintptr_t>(mask) % 16 == 0;
+  const int64_t bx = blocks_per_map(wide ? cells / 4 : cells);
   for (int64_t r0 = 0; r0 < count; r0 += kGridY) {
     const int64_t nr = count - r0 < kGridY ? count - r0 : kGridY;
-    hipLaunchKernelGGL((k_astar_shift<T>), dim3((unsigned)bx, (unsigned)nr), dim3(kCicThreads), 0, s, mask, cells,
-                       off, mean + r0, out + r0 * cells);
+    if (wide)
+      hipLaunchKernelGGL((k_astar_shift4<T>), dim3((unsigned)bx, (unsigned)nr), dim3(kCicThreads), 0, s, mask,
+                         cells, off, mean + r0, out + r0 * cells);
+    else
+      hipLaunchKernelGGL((k_astar_shift<T>), dim3((unsigned)bx, (unsigned)nr), dim3(kCicThreads), 0, s, mask,
+                         cells, off, mean + r0, out + r0 * cells);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
