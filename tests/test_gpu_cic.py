@@ -71,7 +71,7 @@ def test_histogram_matches_oracle(ce, n, masked, nhist):
 
 
 @pytest.mark.parametrize("n,masked,prec", [((37, 41), False, 1), ((64, 64), True, 1), ((64, 64), True, 0),
-                                           ((12, 10, 14), True, 1)])
+                                           ((12, 10, 14), True, 1), ((48, 40), False, 0), ((33, 30), True, 0)])
 @pytest.mark.parametrize("subtract", [False, True])
 def test_astar_matches_oracle(ce, n, masked, prec, subtract):
     b, ctx = ce
