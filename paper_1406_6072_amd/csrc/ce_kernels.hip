@@ -668,8 +668,22 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(sizeof
   const bool has_b = ma + 1 < p.count;
   if (active) {
     if (p.kind == 0) {
+      // eight elements of the thread requested before any is stored
       const T* a = static_cast<const T*>(p.maps) + ma * p.ncells + row * K;
-      for (int i = lane; i < K; i += g.nlanes) line[pidx(i)] = {a[i], has_b ? a[i + p.ncells] : T(0)};
+      for (int i0 = lane; i0 < K; i0 += 8 * g.nlanes) {
+        T va[8], vb[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+          const int i = i0 + k * g.nlanes;
+          va[k] = i < K ? a[i] : T(0);
+          vb[k] = i < K && has_b ? a[i + p.ncells] : T(0);
+        }
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+          const int i = i0 + k * g.nlanes;
+          if (i < K) line[pidx(i)] = {va[k], vb[k]};
+        }
+      }
     } else if (p.kind == 2) {
       const float* m = p.mask + row * K;
       for (int i = lane; i < K; i += g.nlanes) line[pidx(i)] = {m[i] != 0.0f ? T(1) : T(0), T(0)};
@@ -681,16 +695,30 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(sizeof
       const T ia = (T)(fsum / (double)p.ntot[ma]);
       const T ib = has_b ? (T)(fsum / (double)p.ntot[ma + 1]) : T(0);
       const float* mrow = p.mask ? p.mask + row * K : nullptr;
-#pragma unroll 4
-      for (int i = lane; i < K; i += g.nlanes) {
-        const T f = mrow ? (T)mrow[i] : T(1);
-        T va = T(0), vb = T(0);
-        if (f != T(0)) {
-          const T r = sizeof(T) == 4 ? (T)__builtin_amdgcn_rcpf((float)f) : T(1) / f;
-          va = (T)a[i] * r * ia - T(1);
-          if (has_b) vb = (T)a[i + p.ncells] * r * ib - T(1);
+      for (int i0 = lane; i0 < K; i0 += 8 * g.nlanes) {
+        // eight elements of the thread requested before any is used
+        int32_t ca[8], cb[8];
+        float fm[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+          const int i = i0 + k * g.nlanes;
+          ca[k] = i < K ? a[i] : 0;
+          cb[k] = i < K && has_b ? a[i + p.ncells] : 0;
+          fm[k] = i < K && mrow ? mrow[i] : 1.0f;
         }
-        line[pidx(i)] = {va, vb};
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+          const int i = i0 + k * g.nlanes;
+          if (i >= K) continue;
+          const T f = (T)fm[k];
+          T va = T(0), vb = T(0);
+          if (f != T(0)) {
+            const T r = sizeof(T) == 4 ? (T)__builtin_amdgcn_rcpf((float)f) : T(1) / f;
+            va = (T)ca[k] * r * ia - T(1);
+            if (has_b) vb = (T)cb[k] * r * ib - T(1);
+          }
+          line[pidx(i)] = {va, vb};
+        }
       }
     }
   }
