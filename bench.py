@@ -687,6 +687,20 @@ def main():
                              steps=msteps, masked_fraction=round(float((mask == 0).float().mean()), 4),
                              form="fused pass with the mask's rate, transform of N / (f nbar) - 1, contrast completed in the "
                                   "binning pass with the mask's window transform")
+        # the same steps with the mask prepared once (ce_mask_prepare): no per-call window transform
+        prep = b.mask_prepare(ctx, plan, mask, stream)
+        try:
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for i in range(msteps):
+                b.pipeline_run_prepared(ctx, plan, mask, prep, w["seed"], w["request_id"], (1 + i) * R * 2, R, nbar,
+                                        nb, pk_out, out_ntot=ntot, out_cov=cov, out_cnorm=cnorm, stream=stream)
+            torch.cuda.synchronize()
+            pdt = (time.perf_counter() - t0) / msteps
+        finally:
+            b.mask_release(prep)
+        out["masked"]["prepared"] = dict(value=round(R / pdt, 1), ms_per_step=round(1e3 * pdt, 3),
+                                         form="ce_mask_prepare once, ce_pipeline_run_prepared per step")
         if not args.no_cic:
             mstep(1 + msteps, counts=mc)  # the counts of one step for the counts-in-cells leg
             out["cic"] = cic_leg(b, torch, ctx, plan, mask, mc, R, nb, nbar, n, h, stream, msteps)

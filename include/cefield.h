@@ -362,6 +362,28 @@ ce_status ce_pipeline_run_masked(ce_ctx* ctx, const ce_plan* plan, const float* 
                                  int32_t nbins, void* out_fields, void* out_delta, int32_t* out_counts,
                                  int64_t* out_ntot, double* out_pk, double* out_cov, double* out_cnorm, void* stream);
 
+/* The mask-dependent part of ce_pipeline_run_masked computed once for repeated calls on one
+ * survey (Sec. 3.1, eq. sampling; Sec. 3.2, eq. Estim): the sum of f and the transform of the
+ * indicator f != 0 for plan's grid and precision, held in device memory the handle owns
+ * (N^(d-1) x 2 (N_last/2 + 1) complex values plus 257 doubles, counted against ctx's budget).
+ * mask_f (device, N^d floats, caller-owned) is read on `stream` during the call only.
+ * ce_mask_release frees the handle (it waits for work that still reads it).  Errors:
+ * CE_E_INVALID (null arguments, plan on another device), CE_E_OOM, CE_E_DEVICE. */
+typedef struct ce_mask ce_mask;
+ce_status ce_mask_prepare(ce_ctx* ctx, const ce_plan* plan, const float* mask_f, void* stream, ce_mask** out);
+void ce_mask_release(ce_mask* mask);
+
+/* ce_pipeline_run_edges on a masked survey with a prepared mask: mask_f must hold the values
+ * the handle was prepared from (the fused pass reads the rates from it); kedges nullable
+ * (equal-width shells).  Results equal ce_pipeline_run_edges with mask_f bit for bit.
+ * Errors: as ce_pipeline_run_edges; CE_E_INVALID when the handle was prepared for another
+ * grid, precision or device. */
+ce_status ce_pipeline_run_prepared(ce_ctx* ctx, const ce_plan* plan, const float* mask_f, const ce_mask* mask,
+                                   uint64_t seed, uint32_t request_id, uint64_t first_realization, int64_t count,
+                                   double nbar, int32_t nbins, const double* kedges, void* out_fields,
+                                   void* out_delta, int32_t* out_counts, int64_t* out_ntot, double* out_pk,
+                                   double* out_cov, double* out_cnorm, void* stream);
+
 /* Batched form of ce_pipeline_run: many requests, each with its own plan (geometry, xi,
  * precision), seed, request id, realizations, nbar and outputs.  Requests that share
  * (ndim, N, h, precision, nbins) form a group that runs each pass of the pipeline as one launch

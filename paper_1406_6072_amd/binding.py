@@ -120,6 +120,11 @@ _pipeline_masked = _sig("ce_pipeline_run_masked", c_i32, c_void_p, c_void_p, c_v
 _pipeline_edges = _sig("ce_pipeline_run_edges", c_i32, c_void_p, c_void_p, c_void_p, c_u64, c_u32, c_u64, c_i64,
                        c_f64, c_i32, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
                        c_void_p)
+_mask_prepare = _sig("ce_mask_prepare", c_i32, c_void_p, c_void_p, c_void_p, c_void_p, ctypes.POINTER(c_void_p))
+_mask_release = _sig("ce_mask_release", None, c_void_p)
+_pipeline_prepared = _sig("ce_pipeline_run_prepared", c_i32, c_void_p, c_void_p, c_void_p, c_void_p, c_u64, c_u32,
+                          c_u64, c_i64, c_f64, c_i32, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
+                          c_void_p, c_void_p, c_void_p)
 _pipeline_batch = _sig("ce_pipeline_run_batch", c_i32, c_void_p, ctypes.POINTER(BatchItem), c_i64, c_void_p)
 _server_create = _sig("ce_server_create", c_i32, c_i32, ctypes.POINTER(ServerConfig), ctypes.POINTER(c_void_p))
 _server_submit = _sig("ce_server_submit", c_i32, c_void_p, ctypes.POINTER(Request), ctypes.POINTER(c_u64))
@@ -143,7 +148,8 @@ EXPORTED = ["ce_status_string", "ce_version", "ce_ctx_create", "ce_ctx_destroy",
             "ce_plan_periodic",
             "ce_generate_fields", "ce_lognormal_poisson", "ce_estimate_pk", "ce_estimate_pk_edges", "ce_pk_covariance",
             "ce_cic_histogram", "ce_cic_predict", "ce_astar_map", "ce_cumulative_information",
-            "ce_pipeline_run", "ce_pipeline_run_edges", "ce_pipeline_run_masked", "ce_pipeline_run_batch", "ce_pipeline_graph_create", "ce_pipeline_graph_launch",
+            "ce_pipeline_run", "ce_pipeline_run_edges", "ce_pipeline_run_masked", "ce_mask_prepare",
+            "ce_mask_release", "ce_pipeline_run_prepared", "ce_pipeline_run_batch", "ce_pipeline_graph_create", "ce_pipeline_graph_launch",
             "ce_pipeline_graph_destroy",
             "ce_server_create", "ce_server_submit", "ce_server_submit_many", "ce_server_poll", "ce_server_drain", "ce_server_cancel",
             "ce_server_stats_read", "ce_server_destroy", "ce_shell_table", "ce_fft_factors", "ce_debug_philox", "ce_debug_noise"]
@@ -506,6 +512,42 @@ def pipeline_run_masked(ctx, plan, mask, seed, request_id, first_realization, co
                             _ptr(out_cov, torch.float64, nbins * nbins, "out_cov"),
                             _ptr(out_cnorm, torch.float64, nbins * nbins, "out_cnorm"), _stream(stream)),
            "ce_pipeline_run_masked")
+
+
+def mask_prepare(ctx, plan, mask, stream=None):
+    """Handle holding sum(f) and the window transform of a mask (float32 CUDA tensor)."""
+    m = c_void_p()
+    _check(_mask_prepare(ctx, plan.handle, _ptr(mask, torch.float32, plan.cells, "mask"), _stream(stream),
+                         ctypes.byref(m)), "ce_mask_prepare")
+    return m
+
+
+def mask_release(m):
+    _mask_release(m)
+
+
+def pipeline_run_prepared(ctx, plan, mask, prepared, seed, request_id, first_realization, count, nbar, nbins, out_pk,
+                          edges=None, out_fields=None, out_delta=None, out_counts=None, out_ntot=None, out_cov=None,
+                          out_cnorm=None, stream=None):
+    """The masked fused path with a prepared mask (and optional shell edges)."""
+    import numpy as np
+    e = None
+    if edges is not None:
+        e = np.ascontiguousarray(edges, dtype=np.float64)
+        if e.size != nbins + 1:
+            raise ValueError("edges must hold nbins + 1 values")
+    cells = plan.cells
+    _check(_pipeline_prepared(ctx, plan.handle, _ptr(mask, torch.float32, cells, "mask"), prepared, int(seed),
+                              int(request_id), int(first_realization), int(count), float(nbar), int(nbins),
+                              None if e is None else e.ctypes.data_as(c_void_p),
+                              _ptr(out_fields, plan.dtype, count * cells, "out_fields"),
+                              _ptr(out_delta, plan.dtype, count * cells, "out_delta"),
+                              _ptr(out_counts, torch.int32, count * cells, "out_counts"),
+                              _ptr(out_ntot, torch.int64, count, "out_ntot"),
+                              _ptr(out_pk, torch.float64, count * nbins, "out_pk"),
+                              _ptr(out_cov, torch.float64, nbins * nbins, "out_cov"),
+                              _ptr(out_cnorm, torch.float64, nbins * nbins, "out_cnorm"), _stream(stream)),
+           "ce_pipeline_run_prepared")
 
 
 def pipeline_run_batch(ctx, items, stream=None):

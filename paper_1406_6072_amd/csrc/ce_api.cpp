@@ -1977,6 +1977,86 @@ ce_status ce_pipeline_run_masked(ce_ctx* ctx, const ce_plan* plan, const float* 
                               out_delta, out_counts, out_ntot, out_pk, out_cov, out_cnorm, s);
 }
 
+// ---- prepared masks ------------------------------------------------------------------
+
+struct ce_mask {
+  ce_ctx* ctx = nullptr;
+  int ndim = 0, prec = 0;
+  int n[3] = {1, 1, 1};
+  double* fsum = nullptr;  // sum of f, then the workgroup partials (257 doubles)
+  void* win = nullptr;     // window transform of [f != 0], column-major
+  size_t win_bytes = 0;
+};
+
+ce_status ce_mask_prepare(ce_ctx* ctx, const ce_plan* plan, const float* mask_f, void* stream, ce_mask** out) {
+  if (!ctx || !plan || !mask_f || !out) return CE_E_INVALID;
+  *out = nullptr;
+  if (plan->ctx->device != ctx->device) return CE_E_INVALID;
+  std::lock_guard<std::mutex> lock(ctx->mu);
+  CE_HIP(hipSetDevice(ctx->device));
+  hipStream_t s = as_stream(stream);
+  ctx->last = s;
+  auto m = std::make_unique<ce_mask>();
+  m->ctx = ctx;
+  m->ndim = plan->ndim;
+  m->prec = plan->prec;
+  for (int d = 0; d < plan->ndim; ++d) m->n[d] = plan->n[d];
+  const int Nl = plan->n[plan->ndim - 1];
+  m->win_bytes = (size_t)(plan->prec ? 16 : 8) * (size_t)(survey_cells(plan) / Nl) * (size_t)(2 * (Nl / 2 + 1));
+  CE_TRY(ctx->alloc(reinterpret_cast<void**>(&m->fsum), sizeof(double) * 257));
+  ce_status st = ctx->alloc(&m->win, m->win_bytes);
+  if (st != CE_OK) {
+    ctx->release(m->fsum, sizeof(double) * 257);
+    return st;
+  }
+  auto fail = [&](ce_status e) {
+    (void)hipStreamSynchronize(s);
+    ctx->release(m->win, m->win_bytes);
+    ctx->release(m->fsum, sizeof(double) * 257);
+    return e;
+  };
+  if (launch_mask_sum(mask_f, survey_cells(plan), m->fsum, s) != hipSuccess) return fail(CE_E_DEVICE);
+  void* w = nullptr;
+  st = window_transform(ctx, plan, mask_f, &w, s);
+  if (st != CE_OK) return fail(st);
+  if (hipMemcpyAsync(m->win, w, m->win_bytes, hipMemcpyDeviceToDevice, s) != hipSuccess) return fail(CE_E_DEVICE);
+  *out = m.release();
+  return CE_OK;
+}
+
+void ce_mask_release(ce_mask* m) {
+  if (!m) return;
+  {
+    std::lock_guard<std::mutex> lock(m->ctx->mu);
+    (void)hipSetDevice(m->ctx->device);
+    m->ctx->release(m->win, m->win_bytes);  // hipFree waits for the work that reads it
+    m->ctx->release(m->fsum, sizeof(double) * 257);
+  }
+  delete m;
+}
+
+ce_status ce_pipeline_run_prepared(ce_ctx* ctx, const ce_plan* plan, const float* mask_f, const ce_mask* mask,
+                                   uint64_t seed, uint32_t request_id, uint64_t first_realization, int64_t count,
+                                   double nbar, int32_t nbins, const double* kedges, void* out_fields,
+                                   void* out_delta, int32_t* out_counts, int64_t* out_ntot, double* out_pk,
+                                   double* out_cov, double* out_cnorm, void* stream) {
+  CE_TRY(pipeline_check(ctx, plan, first_realization, count, nbar, nbins, out_pk));
+  if (!mask_f || !mask || mask->ctx->device != ctx->device || mask->ndim != plan->ndim || mask->prec != plan->prec)
+    return CE_E_INVALID;
+  for (int d = 0; d < plan->ndim; ++d)
+    if (mask->n[d] != plan->n[d]) return CE_E_INVALID;
+  if (kedges)
+    for (int b = 0; b <= nbins; ++b)
+      if (!std::isfinite(kedges[b]) || kedges[b] < 0 || (b > 0 && !(kedges[b] > kedges[b - 1]))) return CE_E_INVALID;
+  std::lock_guard<std::mutex> lock(ctx->mu);
+  CE_HIP(hipSetDevice(ctx->device));
+  hipStream_t s = as_stream(stream);
+  ctx->last = s;
+  return pipeline_impl(ctx, plan, seed, request_id, first_realization, count, nbar, nbins, out_fields, out_delta,
+                       out_counts, out_ntot, out_pk, out_cov, out_cnorm, nullptr, s, mask_f, mask->win, mask->fsum,
+                       kedges);
+}
+
 // ---- captured pipeline ------------------------------------------------------------
 
 struct ce_graph {

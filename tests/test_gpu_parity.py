@@ -748,3 +748,43 @@ def test_rectangular_cells_match_oracle(ce, n, h, prec, nb):
         assert np.max(np.abs(got[:, ok] / un[:, ok] - 1)) <= TOL_PK[prec]
         assert np.max(np.abs(got[:, ok] / ref[:, ok] - 1)) <= TOL_PK[prec]
     plan.release()
+
+
+@pytest.mark.parametrize("n,prec,log", [((96, 64), 0, True), ((64, 64), 1, False), ((16, 20, 16), 0, True)])
+def test_prepared_mask_equals_per_call_window(ce, n, prec, log):
+    """A mask prepared once (sum f and window transform held by a handle) gives the masked
+    pipeline's results bit for bit, over two calls with different realizations; a handle
+    prepared for another grid or precision is rejected."""
+    import math
+    from synth import workloads
+    b, ctx = ce
+    nb, count, nbar = 12, 4, 2.5
+    mask = torch.from_numpy(workloads.survey_mask(n, seed=9).ravel()).cuda()
+    plan = b.plan_embedding(ctx, n, (1.0,) * len(n), dict(kind="exp", sigma2=0.7, a=2.5 if len(n) == 2 else 1.2),
+                            prec)
+    edges = np.exp(np.linspace(math.log(math.pi / 16.0), math.log(math.pi), nb + 1)) if log else None
+    prep = b.mask_prepare(ctx, plan, mask)
+    try:
+        for first in (0, 2 * count):
+            ref = dict(out_pk=torch.empty(count * nb, dtype=torch.float64, device="cuda"),
+                       out_counts=torch.empty(count * plan.cells, dtype=torch.int32, device="cuda"),
+                       out_ntot=torch.empty(count, dtype=torch.int64, device="cuda"))
+            got = {k: torch.empty_like(v) for k, v in ref.items()}
+            if log:
+                b.pipeline_run_edges(ctx, plan, 7, 5, first, count, nbar, nb, edges, mask=mask, **ref)
+            else:
+                b.pipeline_run_masked(ctx, plan, mask, 7, 5, first, count, nbar, nb, **ref)
+            b.pipeline_run_prepared(ctx, plan, mask, prep, 7, 5, first, count, nbar, nb, edges=edges, **got)
+            torch.cuda.synchronize()
+            assert b.ctx_check(ctx) == 0
+            for k in ref:
+                assert np.array_equal(got[k].cpu().numpy(), ref[k].cpu().numpy(), equal_nan=True), (first, k)
+        other = b.plan_embedding(ctx, n, (1.0,) * len(n), dict(kind="exp", sigma2=0.7, a=1.2), 1 - prec)
+        pk = torch.empty(count * nb, dtype=torch.float64, device="cuda")
+        with pytest.raises(b.CeError) as e:
+            b.pipeline_run_prepared(ctx, other, mask, prep, 7, 5, 0, count, nbar, nb, pk)
+        assert e.value.status == b.E_INVALID
+        other.release()
+    finally:
+        b.mask_release(prep)
+    plan.release()
