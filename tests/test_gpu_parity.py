@@ -747,6 +747,17 @@ def test_rectangular_cells_match_oracle(ce, n, h, prec, nb):
         assert np.array_equal(np.isfinite(got[0]), ok)
         assert np.max(np.abs(got[:, ok] / un[:, ok] - 1)) <= TOL_PK[prec]
         assert np.max(np.abs(got[:, ok] / ref[:, ok] - 1)) <= TOL_PK[prec]
+    # the fused path with the log shells on these cells
+    c = torch.empty(count * cells, dtype=torch.int32, device="cuda")
+    nt = torch.empty(count, dtype=torch.int64, device="cuda")
+    b.pipeline_run_edges(ctx, plan, 6, 2, 0, count, nbar, nb, edges, p, out_counts=c, out_ntot=nt)
+    torch.cuda.synchronize()
+    ref = opk.estimate_pk(c.cpu().numpy().reshape((count,) + n), h, nb, kind="counts", ntot=nt.cpu().numpy(),
+                          edges=edges)
+    got = p.cpu().numpy().reshape(count, nb)
+    ok = np.isfinite(ref[0])
+    assert ok.sum() >= nb // 2 and np.array_equal(np.isfinite(got[0]), ok)
+    assert np.max(np.abs(got[:, ok] / ref[:, ok] - 1)) <= TOL_PK[prec]
     plan.release()
 
 

@@ -309,7 +309,7 @@ def test_server_cancel_queued(ce):
 
 
 def test_batch_matches_items_alone(ce):
-    """Ragged batch: several shapes, both precisions, odd counts, odd first realizations of
+    """Ragged batch: several shapes and cell shapes, both precisions, odd counts, odd first realizations of
     pairs, optional outputs; every item equals its own ce_pipeline_run bit for bit."""
     b, ctx = ce
     specs = [  # n, xi, prec, first, count, nbar, nb, with_counts, with_cov
@@ -321,10 +321,12 @@ def test_batch_matches_items_alone(ce):
         ((32, 32), dict(kind="exp", sigma2=1.0, a=3.0), 0, 6, 2, 1.0, 16, True, True),  # other nbins
         ((96, 96), dict(kind="powexp", sigma2=1.0, r0=4.0, gamma=1.8, rc=300.0), 0, 0, 4, 0.3, 24, True, True),
         ((16, 16, 16), dict(kind="exp", sigma2=0.8, a=1.5), 0, 2, 4, 2.0, 6, True, True),
+        ((32, 32), dict(kind="exp", sigma2=1.0, a=3.0), 0, 0, 3, 1.0, 8, True, True),  # 1 x 0.5 cells
     ]
+    cells_h = {len(specs) - 1: (1.0, 0.5)}  # same sides as item 0, other cell shape: its own group
     plans, items = [], []
     for k, (n, xi, prec, first, count, nbar, nb, wc, wv) in enumerate(specs):
-        plan = b.plan_embedding(ctx, n, (1.0,) * len(n), xi, prec)
+        plan = b.plan_embedding(ctx, n, cells_h.get(k, (1.0,) * len(n)), xi, prec)
         plans.append(plan)
         o = outputs(plan.cells, count, nb, cov=wv)
         if not wc:
