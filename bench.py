@@ -77,8 +77,9 @@ def kernel_ops(name, n, pairs, nb, count, nbar):
     return 0
 
 
-def traffic_for(kernel, workload):
-    """HBM bytes per launch from the committed counter summary, if the kernel sources are unchanged."""
+def counters_for(kernel, workload):
+    """HBM bytes per launch (FETCH_SIZE + WRITE_SIZE, calibrated) and VALU busy of a kernel from the
+    committed counter summary, if the kernel sources are unchanged since it was taken; else None."""
     import hashlib
     path = os.path.join(ROOT, "profiles", "traffic_%s.json" % workload)
     if not os.path.exists(path):
@@ -89,8 +90,7 @@ def traffic_for(kernel, workload):
         h.update(open(os.path.join(ROOT, f), "rb").read())
     if h.hexdigest() != rec.get("sources_sha256"):
         return None
-    k = rec.get("kernels", {}).get(kernel)
-    return None if k is None else int(k["bytes_per_launch"])
+    return rec.get("kernels", {}).get(kernel)
 
 
 def cic_leg(b, torch, ctx, plan, mask, counts, R, nb, nbar, n, h, stream, steps):
@@ -202,6 +202,8 @@ def parse():
     ap.add_argument("--plain-realizations", type=int, default=8)
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-accuracy", action="store_true", help="skip the oracle comparison of one timed pair")
+    ap.add_argument("--volume-steps", type=int, default=10, help="steps of the 3-D workload leg (0: skip it)")
     ap.add_argument("--no-graph", action="store_true", help="skip the captured-step (HIP graph) leg")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--lines", default="",
@@ -271,6 +273,53 @@ def kernel_bytes(name, n, prec, pairs, nb, count):
     return 0
 
 
+def request_alg_bytes(n, realizations, prec="f32"):
+    """Algorithmic HBM bytes of the fused path for one request (2-D: 28 N^2 per realization in FP32,
+    52 N^2 in FP64; 3-D: 68 N^3 in FP32, 132 N^3 in FP64), plus nothing for the plan."""
+    cells = 1
+    for x in n:
+        cells *= x
+    per = {(2, "f32"): 28, (2, "f64"): 52, (3, "f32"): 68, (3, "f64"): 132}[(len(n), prec)]
+    return per * cells * realizations
+
+
+def accuracy_leg(b, torch, ctx, plan, w, pair=0):
+    """Error of the fused path against the FP64 oracle on identical Philox streams, for one pair of
+    the timed workload (realizations 2 pair, 2 pair + 1 of the same call geometry): fields (relative
+    L2, max |dg| / sqrt(xi(0))), delta from the GPU's fields, counts (mismatches with the oracle fed
+    the GPU's delta) and N_tot, P(k) per shell (oracle fed the same counts)."""
+    import numpy as np
+    from oracle import embedding, fields, lognormal_poisson, pk
+    n, nb, nbar = w["n"], w["nbins"], w["nbar"]
+    cells = plan.cells
+    f = torch.empty(2 * cells, dtype=plan.dtype, device="cuda")
+    d = torch.empty_like(f)
+    c = torch.empty(2 * cells, dtype=torch.int32, device="cuda")
+    nt = torch.empty(2, dtype=torch.int64, device="cuda")
+    p = torch.empty(2 * nb, dtype=torch.float64, device="cuda")
+    b.pipeline_run(ctx, plan, w["seed"], w["request_id"], 2 * pair, 2, nbar, nb, p, f, d, c, nt)
+    torch.cuda.synchronize()
+    ref_plan = embedding.plan(n, w["h"], w["xi"])
+    ref = fields.generate_fields(ref_plan, w["seed"], w["request_id"], 2 * pair, 2)
+    g = f.cpu().numpy().astype(np.float64).reshape(ref.shape)
+    dg = g - ref
+    sig = float(np.sqrt(ref_plan["sigma2"]))
+    dh = d.cpu().numpy().reshape(ref.shape)
+    rd = lognormal_poisson.lognormal_delta(g, ref_plan["sigma2"])
+    _, rc, rn = lognormal_poisson.lognormal_poisson(g, ref_plan["sigma2"], nbar, w["seed"], w["request_id"],
+                                                    2 * pair, delta=dh)
+    ch = c.cpu().numpy().reshape(ref.shape)
+    rp = pk.estimate_pk(rc, 1.0, nb, kind="counts", ntot=rn)
+    return dict(pair=pair, fields_rel_l2=float(np.linalg.norm(dg) / np.linalg.norm(ref)),
+                fields_max_abs_over_sigma=float(np.max(np.abs(dg)) / sig),
+                delta_max_rel=float(np.max(np.abs(dh - rd) / (1 + np.abs(rd)))),
+                counts_mismatches=int(np.count_nonzero(ch != rc)), cells=int(ch.size),
+                ntot_equal=bool(np.array_equal(nt.cpu().numpy(), rn)),
+                pk_max_rel=float(np.max(np.abs(p.cpu().numpy().reshape(2, nb) / rp - 1))),
+                tolerances=dict(fields=1e-5 if w["precision"] == "f32" else 1e-12, counts="bit-exact",
+                                pk=1e-5 if w["precision"] == "f32" else 1e-12))
+
+
 def cpu_oracle_sample(w, seconds):
     """The FP64 oracle (as it stands) on whole pairs of the same workload until `seconds` pass."""
     import numpy as np
@@ -298,31 +347,39 @@ def cpu_oracle_sample(w, seconds):
                 seconds=dt)
 
 
-def uneven_batch_leg(b, torch, nreq, reps):
+def uneven_batch_leg(b, torch, nreq, reps, sample_every=32):
     """The uneven batch (4096 requests of 2 realizations, 2-D sides 32..512 step 16, each with its
     own two-point function) through ce_pipeline_run_batch, FP32 and FP64 on identical Philox
     streams; plans are built before the timed region.  Also the same requests as one
-    ce_pipeline_run call each (FP32), for the batching gain."""
+    ce_pipeline_run call each (FP32), for the batching gain.  The FP32-vs-FP64 ladder: for every
+    request the relative L2 and largest relative shell error of the FP32 P(k) against the FP64
+    P(k), the fraction of counts that differ (a Poisson draw flips where the two precisions' delta
+    straddle a CDF step), and on every `sample_every`-th request the fields (relative L2 and
+    max |dg| / sqrt(xi(0)))."""
     import numpy as np
     from synth import workloads
     reqs = workloads.uneven_batch(nreq)
     ctx = b.ctx_create(0)
     out = dict(requests=len(reqs), realizations=2 * len(reqs),
                distinct_shapes=len({r["n"] for r in reqs}))
+    kept = {}
     try:
-        for prec, tag, cb in ((b.F32, "f32", 28), (b.F64, "f64", 52)):
+        for prec, tag in ((b.F32, "f32"), (b.F64, "f64")):
             t0 = time.perf_counter()
             plans = [b.plan_embedding(ctx, r["n"], r["h"], r["xi"], prec) for r in reqs]
             plan_s = time.perf_counter() - t0
             items, alg = [], 0
-            for r, p in zip(reqs, plans):
+            for i, (r, p) in enumerate(zip(reqs, plans)):
                 R, nb = r["realizations"], r["nbins"]
-                items.append(dict(plan=p, seed=r["seed"], request_id=r["request_id"], count=R, nbar=r["nbar"],
-                                  nbins=nb, out_pk=torch.empty(R * nb, dtype=torch.float64, device="cuda"),
-                                  out_counts=torch.empty(R * p.cells, dtype=torch.int32, device="cuda"),
-                                  out_ntot=torch.empty(R, dtype=torch.int64, device="cuda"),
-                                  out_cov=torch.empty(nb * nb, dtype=torch.float64, device="cuda")))
-                alg += cb * p.cells * R
+                it = dict(plan=p, seed=r["seed"], request_id=r["request_id"], count=R, nbar=r["nbar"],
+                          nbins=nb, out_pk=torch.empty(R * nb, dtype=torch.float64, device="cuda"),
+                          out_counts=torch.empty(R * p.cells, dtype=torch.int32, device="cuda"),
+                          out_ntot=torch.empty(R, dtype=torch.int64, device="cuda"),
+                          out_cov=torch.empty(nb * nb, dtype=torch.float64, device="cuda"))
+                if i % sample_every == 0:
+                    it["out_fields"] = torch.empty(R * p.cells, dtype=p.dtype, device="cuda")
+                items.append(it)
+                alg += request_alg_bytes(r["n"], R, tag) + (4 if tag == "f32" else 8) * (r["n"][0] + 1) ** 2
             b.pipeline_run_batch(ctx, items)
             torch.cuda.synchronize()
             if b.ctx_check(ctx) != 0:
@@ -337,6 +394,9 @@ def uneven_batch_leg(b, torch, nreq, reps):
             leg = dict(value=round(2 * len(reqs) / (ms * 1e-3), 1), unit="realizations/s", ms_per_batch=round(ms, 3),
                        alg_GB=round(alg / 1e9, 3), alg_GBs=round(alg / (ms * 1e-3) / 1e9, 1),
                        hbm_frac=round(alg / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4), plan_s=round(plan_s, 2))
+            kept[tag] = [dict(pk=it["out_pk"].cpu().numpy(), counts=it["out_counts"].cpu().numpy(),
+                              fields=it["out_fields"].cpu().numpy().astype(np.float64) if "out_fields" in it else None)
+                         for it in items]
             if prec == b.F32:
                 sub = items[:512]
                 for it in sub[:8]:
@@ -359,6 +419,26 @@ def uneven_batch_leg(b, torch, nreq, reps):
                 p.release()
     finally:
         b.ctx_destroy(ctx)
+    # the ladder: FP32 against FP64 on the same Philox streams
+    pk_l2, pk_max, flips, cells, f_l2, f_max = [], [], 0, 0, [], []
+    for r, a, d in zip(reqs, kept["f32"], kept["f64"]):
+        ok = np.isfinite(d["pk"]) & (d["pk"] != 0)   # shells without modes (small grids) hold NaN
+        pa, pd = a["pk"][ok], d["pk"][ok]
+        pk_l2.append(float(np.linalg.norm(pa - pd) / np.linalg.norm(pd)))
+        pk_max.append(float(np.max(np.abs(pa / pd - 1))))
+        flips += int(np.count_nonzero(a["counts"] != d["counts"]))
+        cells += a["counts"].size
+        if a["fields"] is not None:
+            df = a["fields"] - d["fields"]
+            f_l2.append(float(np.linalg.norm(df) / np.linalg.norm(d["fields"])))
+            f_max.append(float(np.max(np.abs(df)) / np.sqrt(r["xi"]["sigma2"])))
+    out["ladder_f32_vs_f64"] = dict(
+        pk_rel_l2=dict(median=float(np.median(pk_l2)), max=float(np.max(pk_l2))),
+        pk_max_rel_shell=dict(median=float(np.median(pk_max)), max=float(np.max(pk_max))),
+        counts_differing_fraction=flips / max(cells, 1),
+        fields_rel_l2=dict(requests=len(f_l2), median=float(np.median(f_l2)), max=float(np.max(f_l2))),
+        fields_max_abs_over_sigma=float(np.max(f_max)),
+        note="identical Philox streams; P(k) differences are dominated by the counts that flip")
     return out
 
 
@@ -391,7 +471,7 @@ def serving_warm(b, torch, server, trace, nb=32):
             left.discard(t)
         time.sleep(0.0005)
     dt = time.perf_counter() - t0
-    return dt, len(trace) / dt
+    return dt, len(trace) / dt, sum(request_alg_bytes(r["n"], r["realizations"]) for r in trace) / dt / 1e9
 
 
 def small_request_leg(b, torch, slots):
@@ -451,7 +531,7 @@ def serving_leg(b, torch, server, rate, seconds, warmup):
     offs, pool = serving_outputs(torch, trace, nb)
     stats0 = b.server_stats(server)
     pending = {}
-    lat, real_done, failed, lateness = [], 0, 0, 0.0
+    lat, real_done, failed, lateness, bytes_done = [], 0, 0, 0.0, 0
     t_start = time.perf_counter()
     i = 0
     backlog_at_end = None
@@ -463,16 +543,17 @@ def serving_leg(b, torch, server, rate, seconds, warmup):
                 R = r["realizations"]
                 t = submit_traced(b, torch, server, r, pool, offs[i], nb, r["request_id"])
                 lateness = max(lateness, now - r["arrival"])
-                pending[t] = (r["arrival"] >= warmup, R)
+                pending[t] = (r["arrival"] >= warmup, R, request_alg_bytes(r["n"], R))
                 i += 1
             if backlog_at_end is None and i == len(trace):
                 backlog_at_end = len(pending)
             for t, st, status, ms in b.server_drain(server):
-                counted, R = pending.pop(t)
+                counted, R, nbytes = pending.pop(t)
                 if counted:
                     if st == 2:
                         lat.append(ms)
                         real_done += R
+                        bytes_done += nbytes
                     else:
                         failed += 1
             time.sleep(0.0002)
@@ -480,16 +561,101 @@ def serving_leg(b, torch, server, rate, seconds, warmup):
         stats = b.server_stats(server)
     finally:
         pass
-    counted = [r for r in trace if r["arrival"] >= warmup]
+    counted_reqs = [r for r in trace if r["arrival"] >= warmup]
     span = max(wall - warmup, 1e-9)
-    return dict(offered_rate=rate, requests=len(counted), completed=len(lat), failed=failed,
+    return dict(offered_rate=rate, requests=len(counted_reqs), completed=len(lat), failed=failed,
                 realizations_per_s=round(real_done / span, 1), requests_per_s=round(len(lat) / span, 1),
+                alg_GBs=round(bytes_done / span / 1e9, 1),
+                offered_GBs=round(sum(request_alg_bytes(r["n"], r["realizations"]) for r in counted_reqs)
+                                  / seconds / 1e9, 1),
                 p50_ms=round(float(np.percentile(lat, 50)), 3) if lat else None,
                 p99_ms=round(float(np.percentile(lat, 99)), 3) if lat else None,
                 drain_s=round(wall - (warmup + seconds), 3), backlog_at_last_arrival=backlog_at_end,
                 max_lateness_ms=round(1e3 * lateness, 3), plan_cache_hits=stats["cache_hits"] - stats0["cache_hits"],
                 plan_cache_misses=stats["cache_misses"] - stats0["cache_misses"],
                 admission_stalls=stats["admission_stalls"] - stats0["admission_stalls"])
+
+
+def timed_workload(b, torch, ctx, w, name, steps, warmup, stream):
+    """Time `steps` fused steps (ce_pipeline_run of the workload's realizations, counts, N_tot,
+    P(k), covariance) after `warmup` untimed ones, with per-kernel HIP events recorded by the
+    library on the launch stream.  The roofline is that of the kernel with the largest share of
+    the step: its algorithmic bytes per launch over its average event duration, against the HBM
+    peak (the counter-measured traffic and VALU busy of the committed counter summary beside it,
+    when the kernel sources are unchanged; the VALU op model as an extra field)."""
+    import numpy as np
+    prec = b.F64 if w["precision"] == "f64" else b.F32
+    n, h, nb, R, nbar = w["n"], w["h"], w["nbins"], w["realizations"], w["nbar"]
+    dev = torch.device("cuda:0")
+    t0 = time.perf_counter()
+    plan = b.plan_embedding(ctx, n, h, w["xi"], prec)
+    plan_ms = (time.perf_counter() - t0) * 1e3
+    cells = plan.cells
+    pk_out = torch.empty(R * nb, dtype=torch.float64, device=dev)
+    counts = torch.empty(R * cells, dtype=torch.int32, device=dev)
+    ntot = torch.empty(R, dtype=torch.int64, device=dev)
+    cov = torch.empty(nb * nb, dtype=torch.float64, device=dev)
+    cnorm = torch.empty(nb * nb, dtype=torch.float64, device=dev)
+
+    def step(i):
+        b.pipeline_run(ctx, plan, w["seed"], w["request_id"], i * R * 2, R, nbar, nb, pk_out,
+                       out_counts=counts, out_ntot=ntot, out_cov=cov, out_cnorm=cnorm, stream=stream)
+
+    for i in range(warmup):
+        step(i)
+    torch.cuda.synchronize()
+    if b.ctx_check(ctx) != 0:
+        raise RuntimeError("device flagged a sampler condition during warm-up")
+    b.ctx_profile_read(ctx)
+    b.ctx_set_profiling(ctx, True)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ev[0].record(stream)
+    for i in range(steps):
+        step(warmup + i)
+        ev[i + 1].record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    b.ctx_set_profiling(ctx, False)
+    prof = b.ctx_profile_read(ctx)
+    step_ms = np.array([ev[i].elapsed_time(ev[i + 1]) for i in range(steps)])
+    gpu_ms = float(ev[0].elapsed_time(ev[-1]))
+
+    pairs = (R + 1) // 2
+    kernels = {}
+    total_bytes = 0
+    for kname, (ms, launches) in prof.items():
+        per = kernel_bytes(kname, n, w["precision"], pairs, nb, R)
+        avg = ms / launches
+        total_bytes += per * launches / steps
+        kernels[kname] = dict(avg_ms=round(avg, 4), launches=int(launches // steps),
+                              alg_bytes=per, alg_GBs=round(per / (avg * 1e-3) / 1e9, 1),
+                              share=round(ms / sum(v[0] for v in prof.values()), 3))
+        o = kernel_ops(kname, n, pairs, nb, R, nbar)
+        if o:
+            kernels[kname]["alg_Gops"] = round(o / (avg * 1e-3) / 1e9, 1)
+    dom = max(prof.items(), key=lambda kv: kv[1][0])[0]
+    dk = kernels[dom]
+    achieved = dk["alg_bytes"] / (dk["avg_ms"] * 1e-3) / 1e9
+    cnt = counters_for(dom, name)
+    ops = kernel_ops(dom, n, pairs, nb, R, nbar)
+    roofline = dict(kernel=dom, bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
+                    frac=round(achieved / HBM_PEAK_GBS, 4),
+                    traffic=None if cnt is None else int(cnt["bytes_per_launch"]),
+                    alg_bytes=dk["alg_bytes"], avg_ms=dk["avg_ms"],
+                    valu_busy=None if cnt is None else cnt.get("valu_busy"),
+                    valu_op_model=dict(achieved=round(ops / (dk["avg_ms"] * 1e-3) / 1e9, 1),
+                                       peak=round(VALU_PEAK_GOPS, 1), unit="Gop/s",
+                                       frac=round(ops / (dk["avg_ms"] * 1e-3) / 1e9 / VALU_PEAK_GOPS, 4)))
+    pipe_GBs = total_bytes / (np.median(step_ms) * 1e-3) / 1e9
+    return dict(value=round(R * steps / wall, 1), ms_per_step=round(1e3 * wall / steps, 4),
+                latency_ms=dict(p50=round(float(np.percentile(step_ms, 50)), 4),
+                                p99=round(float(np.percentile(step_ms, 99)), 4), gpu_total=round(gpu_ms, 3)),
+                pipeline_hbm=dict(alg_bytes_per_step=int(total_bytes), alg_GBs=round(pipe_GBs, 1),
+                                  frac_of_peak=round(pipe_GBs / HBM_PEAK_GBS, 4)),
+                roofline=roofline, kernels=kernels, plan_ms=round(plan_ms, 2),
+                _plan=plan, _bufs=(pk_out, counts, ntot, cov, cnorm))
 
 
 def main():
@@ -518,78 +684,23 @@ def main():
             b.ctx_set_option(ctx, opt, int(v))
     if args.noise_order >= 0:
         b.ctx_set_option(ctx, b.OPT_NOISE_ORDER, args.noise_order)
-    t0 = time.perf_counter()
-    plan = b.plan_embedding(ctx, n, h, w["xi"], prec)
-    plan_ms = (time.perf_counter() - t0) * 1e3
+    leg = timed_workload(b, torch, ctx, w, args.workload, args.steps, args.warmup, stream)
+    plan, bufs = leg.pop("_plan"), leg.pop("_bufs")
+    pk_out, counts, ntot, cov, cnorm = bufs
     cells = plan.cells
-    pk_out = torch.empty(R * nb, dtype=torch.float64, device=dev)
-    counts = torch.empty(R * cells, dtype=torch.int32, device=dev)
-    ntot = torch.empty(R, dtype=torch.int64, device=dev)
-    cov = torch.empty(nb * nb, dtype=torch.float64, device=dev)
-    cnorm = torch.empty(nb * nb, dtype=torch.float64, device=dev)
+    value = leg.pop("value")
 
-    def step(i):
-        b.pipeline_run(ctx, plan, w["seed"], w["request_id"], i * R * 2, R, nbar, nb, pk_out,
-                       out_counts=counts, out_ntot=ntot, out_cov=cov, out_cnorm=cnorm, stream=stream)
-
-    for i in range(args.warmup):
-        step(i)
-    torch.cuda.synchronize()
-    if b.ctx_check(ctx) != 0:
-        raise RuntimeError("device flagged a sampler condition during warm-up")
-    b.ctx_profile_read(ctx)
-    b.ctx_set_profiling(ctx, True)
-    ev = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    ev[0].record(stream)
-    for i in range(args.steps):
-        step(args.warmup + i)
-        ev[i + 1].record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    b.ctx_set_profiling(ctx, False)
-    prof = b.ctx_profile_read(ctx)
-    step_ms = np.array([ev[i].elapsed_time(ev[i + 1]) for i in range(args.steps)])
-    gpu_ms = float(ev[0].elapsed_time(ev[-1]))
-    ms_per_step = 1e3 * wall / args.steps
-    value = R * args.steps / wall
-
-    pairs = (R + 1) // 2
-    kernels = {}
-    total_bytes = 0
-    for name, (ms, launches) in prof.items():
-        per = kernel_bytes(name, n, w["precision"], pairs, nb, R)
-        avg = ms / launches
-        total_bytes += per * launches / args.steps
-        kernels[name] = dict(avg_ms=round(avg, 4), launches=int(launches // args.steps),
-                             alg_bytes=per, alg_GBs=round(per / (avg * 1e-3) / 1e9, 1),
-                             share=round(ms / sum(v[0] for v in prof.values()), 3))
-    dom = max(prof.items(), key=lambda kv: kv[1][0])[0]
-    dk = kernels[dom]
-    ops = kernel_ops(dom, n, pairs, nb, R, nbar)
-    achieved = ops / (dk["avg_ms"] * 1e-3) / 1e9
-    roofline = dict(kernel=dom, bound="alu", achieved=round(achieved, 1), peak=round(VALU_PEAK_GOPS, 1),
-                    unit="Gop/s", frac=round(achieved / VALU_PEAK_GOPS, 4),
-                    traffic=traffic_for(dom, args.workload), alg_bytes=dk["alg_bytes"],
-                    alg_GBs=dk["alg_GBs"], hbm_frac=round(dk["alg_GBs"] / HBM_PEAK_GBS, 4))
-    for name in kernels:
-        o = kernel_ops(name, n, pairs, nb, R, nbar)
-        if o:
-            kernels[name]["alg_Gops"] = round(o / (kernels[name]["avg_ms"] * 1e-3) / 1e9, 1)
-    pipe_GBs = total_bytes / (np.median(step_ms) * 1e-3) / 1e9
-
-    out = dict(metric=METRIC, value=round(value, 1), unit="realizations/s", n_gpus=1, steps=args.steps,
-               warmup=args.warmup, ms_per_step=round(ms_per_step, 4), higher_is_better=True, scaling="weak",
+    out = dict(metric=METRIC, value=value, unit="realizations/s", n_gpus=1, steps=args.steps,
+               warmup=args.warmup, ms_per_step=leg.pop("ms_per_step"), higher_is_better=True, scaling="weak",
                vs_baseline=None, dtype=w["precision"], data="synthetic",
                config=dict(workload=workload_description(w, args.workload), survey=list(n),
                            embedding=[2 * x for x in n], realizations_per_step=R, nbar=nbar, shells=nb,
                            precision=w["precision"]),
-               latency_ms=dict(p50=round(float(np.percentile(step_ms, 50)), 4),
-                               p99=round(float(np.percentile(step_ms, 99)), 4), gpu_total=round(gpu_ms, 3)),
-               pipeline_hbm=dict(alg_bytes_per_step=int(total_bytes), alg_GBs=round(pipe_GBs, 1),
-                                 frac_of_peak=round(pipe_GBs / HBM_PEAK_GBS, 4)),
-               roofline=roofline, kernels=kernels, plan_ms=round(plan_ms, 2))
+               roofline=leg.pop("roofline"))
+    out.update(leg)
+    if not args.no_accuracy:
+        out["accuracy"] = accuracy_leg(b, torch, ctx, plan, w)
+        print("accuracy %s" % json.dumps(out["accuracy"]), file=sys.stderr, flush=True)
 
     if not args.no_graph:
         # the same step captured once as a HIP graph and replayed (each replay advances the
@@ -659,6 +770,20 @@ def main():
     plan.release()
     b.ctx_destroy(ctx)
 
+    if args.volume_steps and args.workload != "volume_3d":
+        # the 3-D workload (256^3 survey in a 512^3 embedding, 8 realizations per step) timed the
+        # same way: per-kernel events, algorithmic bytes and the roofline of its largest kernel
+        vw = workloads.WORKLOADS["volume_3d"]
+        vctx = b.ctx_create(0)
+        vleg = timed_workload(b, torch, vctx, vw, "volume_3d", args.volume_steps, 2, stream)
+        vleg.pop("_plan").release()
+        vleg.pop("_bufs")
+        vleg["unit"] = "realizations/s"
+        vleg["workload"] = workload_description(vw, "volume_3d")
+        b.ctx_destroy(vctx)
+        out["volume_3d"] = vleg
+        print("volume_3d %s" % json.dumps(vleg), file=sys.stderr, flush=True)
+
     if not args.no_masked:
         # the same workload on a masked survey (star holes and a partial border, 7% of cells out)
         mask = torch.from_numpy(workloads.survey_mask(n, seed=3).ravel()).to(dev)
@@ -724,9 +849,9 @@ def main():
             # closed-loop pass; a second pass gives the saturation throughput
             warm_trace = workloads.serving_trace(rate=min(max(rates), 1000.0),
                                                  duration=args.serve_warmup + args.serve_seconds, seed=5)
-            warm_s, _ = serving_warm(b, torch, server, warm_trace)
+            warm_s, _, _ = serving_warm(b, torch, server, warm_trace)
             sat_trace = workloads.serving_trace(rate=500.0, duration=args.serve_warmup + args.serve_seconds, seed=6)
-            sat_s, sat_rps = serving_warm(b, torch, server, sat_trace)
+            sat_s, sat_rps, sat_gbs = serving_warm(b, torch, server, sat_trace)
             legs = []
             for rate in rates:
                 leg = serving_leg(b, torch, server, rate, args.serve_seconds, args.serve_warmup)
@@ -745,7 +870,7 @@ def main():
                               window_s=args.serve_seconds, warmup_s=args.serve_warmup, slots=args.serve_slots,
                               warm_pass=dict(requests=len(warm_trace), seconds=round(warm_s, 2)),
                               closed_loop=dict(requests=len(sat_trace), seconds=round(sat_s, 3),
-                                               requests_per_s=round(sat_rps, 1),
+                                               requests_per_s=round(sat_rps, 1), alg_GBs=round(sat_gbs, 1),
                                                realizations_per_s=round(sum(r["realizations"] for r in sat_trace)
                                                                         / sat_s, 1)),
                               legs=legs, max_sustainable_rate_tested=max(ok) if ok else None)

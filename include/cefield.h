@@ -132,9 +132,10 @@ ce_status ce_ctx_trim(ce_ctx* ctx);
  * CE_OPT_UNPRUNED (default 0): when non-zero, ce_generate_fields computes every output of every
  * inverse pass on the full (2N)^d embedding and crops to the survey only when storing -- the
  * plain, unpruned form of the method, kept as a comparator.  Results are identical up to
- * rounding order.  Schedule options change only the launch shape: fields, delta, counts and
- * N_tot stay bitwise identical, P(k) may change in the last bits (the grouping of its FP64
- * shell sums follows the lines per workgroup).  Errors: CE_E_INVALID. */
+ * rounding order.  Schedule options change only the launch shape: every output (fields, delta,
+ * counts, N_tot, P(k), covariance) stays bitwise identical (the FP64 shell sums are grouped in
+ * blocks of lines fixed by the grid, shells and precision, not by the schedule).
+ * Errors: CE_E_INVALID. */
 typedef enum {
   CE_OPT_UNPRUNED = 1,
   /* Schedule: maximum lines per workgroup (a power of two <= 64; 0 = automatic, the default)
@@ -150,7 +151,11 @@ typedef enum {
   CE_OPT_NOISE_ORDER = 6,
   /* Schedule: LDS bytes a binning-pass workgroup may use (16384 .. 163840; default 81920,
    * two workgroups per CU).  More LDS allows more lines per workgroup. */
-  CE_OPT_BIN_LDS = 7
+  CE_OPT_BIN_LDS = 7,
+  /* Schedule: with CE_OPT_NOISE_ORDER 0, the noise pass orders its workgroups in blocks of this
+   * many pairs (1 .. 65536, default 1): inside a block the workgroups of one line group for the
+   * block's pairs run together, so the sqrt(lambda) lines they read are fetched once per block. */
+  CE_OPT_NOISE_BLOCK = 8
 } ce_option;
 ce_status ce_ctx_set_option(ce_ctx* ctx, int32_t option, int64_t value);
 
@@ -366,8 +371,12 @@ ce_status ce_pipeline_run_masked(ce_ctx* ctx, const ce_plan* plan, const float* 
  * survey (Sec. 3.1, eq. sampling; Sec. 3.2, eq. Estim): the sum of f and the transform of the
  * indicator f != 0 for plan's grid and precision, held in device memory the handle owns
  * (N^(d-1) x 2 (N_last/2 + 1) complex values plus 257 doubles, counted against ctx's budget).
- * mask_f (device, N^d floats, caller-owned) is read on `stream` during the call only.
- * ce_mask_release frees the handle (it waits for work that still reads it).  Errors:
+ * mask_f (device, N^d floats, caller-owned) is read on `stream` by work enqueued there; the
+ * handle records an event after that work, and every ce_pipeline_run_prepared call (on any
+ * stream, with any ctx of the device) waits for it on its own stream before reading the handle,
+ * so no synchronisation is needed between preparing and using it.  ce_mask_release frees the
+ * handle (it waits for work that still reads it); release every handle before destroying the
+ * ctx it was prepared with (the handle's memory is accounted to that ctx).  Errors:
  * CE_E_INVALID (null arguments, plan on another device), CE_E_OOM, CE_E_DEVICE. */
 typedef struct ce_mask ce_mask;
 ce_status ce_mask_prepare(ce_ctx* ctx, const ce_plan* plan, const float* mask_f, void* stream, ce_mask** out);
@@ -390,10 +399,10 @@ ce_status ce_pipeline_run_prepared(ce_ctx* ctx, const ce_plan* plan, const float
  * over all the group's pairs, every pair reading its own sqrt(lambda) octant, Philox key and
  * counter words, sigma^2 and nbar from a descriptor table; so a batch of many small requests
  * costs a few launches per distinct shape instead of a few per request.  Every item's results
- * equal, bit for bit, those of ce_pipeline_run (ce_pipeline_run_edges for an item with
- * kedges) called for that item alone with the same ctx options.  Fields and delta are not
- * returned in this form.  All items must be valid for
- * ce_pipeline_run (nothing is launched otherwise).  Errors: as ce_pipeline_run. */
+ * (fields, delta, counts, N_tot, P(k), covariance) equal, bit for bit, those of ce_pipeline_run
+ * (ce_pipeline_run_edges for an item with kedges) called for that item alone with the same ctx
+ * options.  All items must be valid for ce_pipeline_run (nothing is launched otherwise).
+ * Errors: as ce_pipeline_run. */
 typedef struct {
   const ce_plan* plan;
   uint64_t seed;
@@ -409,6 +418,8 @@ typedef struct {
   double* out_cnorm;    /* device, nullable, nbins^2 (written when count >= 2) */
   const double* kedges; /* host, nullable: nbins + 1 shell edges in |k| as ce_pipeline_run_edges
                            (read during the call); items with different edges form different groups */
+  void* out_fields;     /* device, nullable, count x N^d in the plan precision (Gaussian fields) */
+  void* out_delta;      /* device, nullable, count x N^d in the plan precision (lognormal contrast) */
 } ce_batch_item;
 ce_status ce_pipeline_run_batch(ce_ctx* ctx, const ce_batch_item* items, int64_t n, void* stream);
 
@@ -463,6 +474,8 @@ typedef struct {
   int64_t* out_ntot;        /* device, nullable, realizations */
   double* out_cov;          /* device, nullable, nbins^2 (used when realizations >= 2) */
   const double* kedges;     /* host, nullable: nbins + 1 shell edges in |k| (copied at submit) */
+  void* out_fields;         /* device, nullable, realizations x N^d in `precision` (Gaussian fields) */
+  void* out_delta;          /* device, nullable, realizations x N^d in `precision` (lognormal contrast) */
 } ce_request;
 typedef struct {
   int64_t submitted, completed, failed, cache_hits, cache_misses, admission_stalls, queued;

@@ -49,7 +49,7 @@ class BatchItem(ctypes.Structure):
     _fields_ = [("plan", c_void_p), ("seed", c_u64), ("request_id", c_u32), ("first_realization", c_u64),
                 ("count", c_i64), ("nbar", c_f64), ("nbins", c_i32), ("out_pk", c_void_p),
                 ("out_counts", c_void_p), ("out_ntot", c_void_p), ("out_cov", c_void_p), ("out_cnorm", c_void_p),
-                ("kedges", c_void_p)]
+                ("kedges", c_void_p), ("out_fields", c_void_p), ("out_delta", c_void_p)]
 
 
 class ServerConfig(ctypes.Structure):
@@ -59,7 +59,8 @@ class ServerConfig(ctypes.Structure):
 class Request(ctypes.Structure):
     _fields_ = [("geom", Geometry), ("xi", Xi), ("precision", c_i32), ("seed", c_u64), ("request_id", c_u32),
                 ("realizations", c_i64), ("nbar", c_f64), ("nbins", c_i32), ("out_pk", c_void_p),
-                ("out_counts", c_void_p), ("out_ntot", c_void_p), ("out_cov", c_void_p), ("kedges", c_void_p)]
+                ("out_counts", c_void_p), ("out_ntot", c_void_p), ("out_cov", c_void_p), ("kedges", c_void_p),
+                ("out_fields", c_void_p), ("out_delta", c_void_p)]
 
 
 class ServerStats(ctypes.Structure):
@@ -265,6 +266,7 @@ def ctx_trim(ctx):
 OPT_UNPRUNED = 1
 CIC_MAX_BINS = 4096
 OPT_LINES_NOISE, OPT_LINES_INNER, OPT_LINES_LAST, OPT_LINES_BINS, OPT_NOISE_ORDER, OPT_BIN_LDS = 2, 3, 4, 5, 6, 7
+OPT_NOISE_BLOCK = 8
 
 
 def ctx_set_option(ctx, option, value):
@@ -552,8 +554,8 @@ def pipeline_run_prepared(ctx, plan, mask, prepared, seed, request_id, first_rea
 
 def pipeline_run_batch(ctx, items, stream=None):
     """items: dicts with plan, seed, request_id, first_realization, count, nbar, nbins, out_pk and
-    optional out_counts, out_ntot, out_cov, out_cnorm (device tensors) and edges (host sequence
-    of nbins + 1 shell edges)."""
+    optional out_counts, out_ntot, out_cov, out_cnorm, out_fields, out_delta (device tensors) and
+    edges (host sequence of nbins + 1 shell edges)."""
     import numpy as np
     arr = (BatchItem * max(len(items), 1))()
     keep = []
@@ -569,6 +571,8 @@ def pipeline_run_batch(ctx, items, stream=None):
         a.out_ntot = _ptr(it.get("out_ntot"), torch.int64, count, "out_ntot")
         a.out_cov = _ptr(it.get("out_cov"), torch.float64, nb * nb, "out_cov")
         a.out_cnorm = _ptr(it.get("out_cnorm"), torch.float64, nb * nb, "out_cnorm")
+        a.out_fields = _ptr(it.get("out_fields"), plan.dtype, count * plan.cells, "out_fields")
+        a.out_delta = _ptr(it.get("out_delta"), plan.dtype, count * plan.cells, "out_delta")
         if it.get("edges") is not None:
             e = np.ascontiguousarray(it["edges"], dtype=np.float64)
             if e.size != nb + 1:
@@ -611,7 +615,7 @@ def server_create(device=0, slots=4, hbm_budget_bytes=0, plan_cache_bytes=0, max
 
 
 def _fill_request(r, n, h, xi, precision, seed, request_id, realizations, nbar, nbins, out_pk,
-                  out_counts=None, out_ntot=None, out_cov=None, edges=None):
+                  out_counts=None, out_ntot=None, out_cov=None, edges=None, out_fields=None, out_delta=None):
     cells = 1
     for x in n:
         cells *= int(x)
@@ -625,6 +629,9 @@ def _fill_request(r, n, h, xi, precision, seed, request_id, realizations, nbar, 
     r.out_counts = _ptr(out_counts, torch.int32, realizations * cells, "out_counts")
     r.out_ntot = _ptr(out_ntot, torch.int64, realizations, "out_ntot")
     r.out_cov = _ptr(out_cov, torch.float64, nbins * nbins, "out_cov")
+    fdt = torch.float64 if int(precision) == F64 else torch.float32
+    r.out_fields = _ptr(out_fields, fdt, realizations * cells, "out_fields")
+    r.out_delta = _ptr(out_delta, fdt, realizations * cells, "out_delta")
     if edges is not None:
         import numpy as np
         e = np.ascontiguousarray(edges, dtype=np.float64)
@@ -636,12 +643,12 @@ def _fill_request(r, n, h, xi, precision, seed, request_id, realizations, nbar, 
 
 
 def server_submit(server, n, h, xi, precision, seed, request_id, realizations, nbar, nbins, out_pk,
-                  out_counts=None, out_ntot=None, out_cov=None, edges=None):
+                  out_counts=None, out_ntot=None, out_cov=None, edges=None, out_fields=None, out_delta=None):
     """Queue one request; returns its ticket.  Output tensors must outlive the request; edges
     (nbins + 1 shell edges in |k|, host) are copied."""
     r = Request()
     keep = _fill_request(r, n, h, xi, precision, seed, request_id, realizations, nbar, nbins, out_pk,
-                         out_counts, out_ntot, out_cov, edges)
+                         out_counts, out_ntot, out_cov, edges, out_fields, out_delta)
     t = c_u64()
     _check(_server_submit(server, ctypes.byref(r), ctypes.byref(t)), "ce_server_submit")
     del keep

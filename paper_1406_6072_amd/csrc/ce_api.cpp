@@ -189,6 +189,7 @@ struct ce_ctx {
   bool unpruned = false;  // inverse passes keep every embedding output (comparator form)
   int lines_cap[4] = {0, 0, 0, 0};  // max lines per workgroup per pass kind (0 = automatic)
   int noise_item_minor = 0;         // noise pass tile order (0: line groups of one pair adjacent; measured faster)
+  int noise_block = 1;              // noise pass: pairs per block of the item-major order
   size_t bin_lds = kLdsBudget;      // LDS budget of a binning-pass workgroup
   std::vector<ProfRec> pending;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> pool;
@@ -365,6 +366,43 @@ namespace {
 int cap_lines(const ce_ctx* ctx, int kind, int dflt) {
   const int c = ctx->lines_cap[kind];
   return c > 0 ? c : dflt;
+}
+
+// Geometry of the binning pass (lines of length N along axis 0 of the spectra, B of them per
+// item) and its record block G.  The shell sums are recorded per block of G consecutive lines,
+// G = the lines per workgroup of the default schedule (LDS budget kLdsBudget, at most 32 lines)
+// capped at 4: it depends only on (N, nb, precision), and every schedule uses a multiple of G
+// lines per workgroup, so the spectra do not depend on the schedule.
+LineGeom bin_geom(const ce_ctx* ctx, int N, int nb, int64_t B, int64_t nitems, int64_t in_item, size_t elem,
+                  bool mix, int* G_out) {
+  LineGeom g = make_geom(N, N, 1, B, nitems, in_item, 0, elem, mix, 1, 1);
+  auto fits = [&](int R, int G, size_t budget) {
+    LineGeom t = g;
+    t.R = R;
+    return R * t.nlanes <= kMaxWG && bin_pass_lds(t, N, nb, G, elem) <= budget;
+  };
+  int Rd = 1;
+  while (Rd * 2 <= 32 && fits(Rd * 2, std::min(4, Rd * 2), kLdsBudget)) Rd *= 2;
+  const int G = std::min(4, Rd);
+  int R = G;
+  const int cap = cap_lines(ctx, 3, 32);
+  while (R * 2 <= cap && fits(R * 2, G, ctx->bin_lds)) R *= 2;
+  g.R = R;
+  g.groups_per_item = (B + R - 1) / R;
+  *G_out = G;
+  return g;
+}
+
+// The binning pass of an N-line spectrum with nb shells fits one workgroup's LDS (one line at a time).
+bool bins_fit(int N, int nb, int prec) {
+  std::vector<int> rad;
+  if (!factor_length(N, rad)) return true;  // reported as unsupported elsewhere
+  FftDesc f;
+  f.nst = (int)rad.size();
+  for (int i = 0; i < f.nst; ++i) f.rad[i] = rad[i];
+  const size_t elem = prec ? 16 : 8;
+  LineGeom g = make_geom(N, N, 1, 1, 1, 0, 0, elem, mixed_radix(f), 1, 1);
+  return bin_pass_lds(g, N, nb, 1, elem) <= kMaxLdsBytes;
 }
 
 ce_status build_fft(ce_ctx* ctx, int L, int prec, FftDesc& f) {
@@ -860,6 +898,10 @@ ce_status ce_ctx_set_option(ce_ctx* ctx, int32_t option, int64_t value) {
       if (value < 16384 || value > 163840) return CE_E_INVALID;
       ctx->bin_lds = (size_t)value;
       return CE_OK;
+    case CE_OPT_NOISE_BLOCK:
+      if (value < 1 || value > 65536) return CE_E_INVALID;
+      ctx->noise_block = (int)value;
+      return CE_OK;
     default: return CE_E_INVALID;
   }
 }
@@ -1159,6 +1201,7 @@ ce_status run_inverse(ce_ctx* ctx, const ce_plan* p, const InverseSetup& fs, uin
   LineGeom g1 = make_geom((int)M0, (int)K0, 1, B1, npairs, 0, y1_item, elem, mixed_radix(fs.fM[0]), 2,
                           cap_lines(ctx, 0, 32));
   g1.item_minor = ctx->noise_item_minor;
+  g1.item_block = ctx->noise_block;
   CE_PROF(ctx, "noise_inverse_axis0", s, launch_noise_pass(p->prec, g1, fs.fM[0], na, y1, s));
   const void* last_in = y1;
   int64_t rows = K0;
@@ -1217,11 +1260,12 @@ ce_status run_forward_bins(ce_ctx* ctx, int ndim, const int* n, int prec, int64_
   FftDesc f0;
   CE_TRY(build_fft(ctx, n[0], prec, f0));
   const int64_t Bb = ndim == 3 ? (int64_t)n[1] * W : W;
-  // per line: nb FP64 shell sums and one run record (24 B) per lane
-  LineGeom gb = make_geom(n[0], n[0], 1, Bb, nitems, H_item, 0, elem, mixed_radix(f0), 1, cap_lines(ctx, 3, 32),
-                          (size_t)nb * 8 + (size_t)((n[0] + kEPT - 1) / kEPT) * 32, ctx->bin_lds);
+  int G = 1;
+  LineGeom gb = bin_geom(ctx, n[0], nb, Bb, nitems, H_item, elem, mixed_radix(f0), &G);
+  if (bin_pass_lds(gb, n[0], nb, G, elem) > kMaxLdsBytes) return CE_E_UNSUPPORTED;
+  const int64_t nblocks = (Bb + G - 1) / G;
   void* part = nullptr;
-  CE_TRY(ctx->scratch(3, sizeof(double) * (size_t)(nitems * gb.groups_per_item * 2 * nb), &part));
+  CE_TRY(ctx->scratch(3, sizeof(double) * (size_t)(nitems * nblocks * 2 * nb), &part));
   BinArgs ba;
   ba.ndim = ndim;
   ba.N = N;
@@ -1235,6 +1279,7 @@ ce_status run_forward_bins(ce_ctx* ctx, int ndim, const int* n, int prec, int64_
   ba.Tl = sr.T[ndim - 1];
   ba.LL = sr.LL;
   ba.th = th;
+  ba.G = G;
   ba.partials = static_cast<double*>(part);
   if (window) {
     ba.win = window->win;
@@ -1244,7 +1289,7 @@ ce_status run_forward_bins(ce_ctx* ctx, int ndim, const int* n, int prec, int64_
   }
   CE_PROF(ctx, "forward_axis0_bins", s, launch_bin_pass(prec, gb, f0, ba, H, s));
   *partials_out = ba.partials;
-  *groups_out = gb.groups_per_item;
+  *groups_out = nblocks;
   return CE_OK;
 }
 
@@ -1486,6 +1531,7 @@ ce_status pipeline_check(ce_ctx* ctx, const ce_plan* plan, uint64_t first_realiz
   if ((first_realization + (uint64_t)count + 1) / 2 > 0xFFFFFFFFull) return CE_E_INVALID;
   ShellRule sr;  // cell sides with small ratios, integers within range
   if (!shell_rule(plan->n, plan->ndim, nbins, sr, plan->h)) return CE_E_UNSUPPORTED;
+  if (!bins_fit(plan->n[0], nbins, plan->prec)) return CE_E_UNSUPPORTED;  // shells beyond one workgroup's LDS
   return CE_OK;
 }
 
@@ -1570,10 +1616,13 @@ ce_status pipeline_batch_impl(ce_ctx* ctx, const ce_batch_item* items, int64_t n
       const ce_batch_item& it = items[i];
       const ce_plan* p = it.plan;
       const int64_t ncells = survey_cells(p);
+      const size_t relem = p->prec ? 8 : 4;
       for (int64_t j = 0; 2 * j < it.count; ++j, ++pi) {
         PairDesc pd;
         pd.sq = p->sq;
         pd.counts = it.out_counts ? it.out_counts + 2 * j * ncells : nullptr;
+        pd.fields = it.out_fields ? static_cast<char*>(it.out_fields) + relem * (size_t)(2 * j * ncells) : nullptr;
+        pd.delta = it.out_delta ? static_cast<char*>(it.out_delta) + relem * (size_t)(2 * j * ncells) : nullptr;
         pd.k0 = (uint32_t)(it.seed & 0xFFFFFFFFu);
         pd.k1 = (uint32_t)(it.seed >> 32);
         pd.rid = it.request_id;
@@ -1761,6 +1810,7 @@ static ce_status estimate_common(ce_ctx* ctx, const ce_geometry* geom, ce_precis
     for (int i = 0; i < geom->ndim; ++i) nn[i] = (int)geom->n[i];
     ShellRule sr;
     if (!shell_rule(nn, geom->ndim, nbins, sr, geom->h)) return CE_E_UNSUPPORTED;
+    if (!bins_fit(nn[0], nbins, precision == CE_F64 ? 1 : 0)) return CE_E_UNSUPPORTED;
   }
   std::lock_guard<std::mutex> lock(ctx->mu);
   CE_HIP(hipSetDevice(ctx->device));
@@ -1986,6 +2036,7 @@ struct ce_mask {
   double* fsum = nullptr;  // sum of f, then the workgroup partials (257 doubles)
   void* win = nullptr;     // window transform of [f != 0], column-major
   size_t win_bytes = 0;
+  hipEvent_t ready = nullptr;  // recorded after the work that writes fsum and win
 };
 
 ce_status ce_mask_prepare(ce_ctx* ctx, const ce_plan* plan, const float* mask_f, void* stream, ce_mask** out) {
@@ -2011,15 +2062,19 @@ ce_status ce_mask_prepare(ce_ctx* ctx, const ce_plan* plan, const float* mask_f,
   }
   auto fail = [&](ce_status e) {
     (void)hipStreamSynchronize(s);
+    if (m->ready) (void)hipEventDestroy(m->ready);
     ctx->release(m->win, m->win_bytes);
     ctx->release(m->fsum, sizeof(double) * 257);
     return e;
   };
+  if (hipEventCreateWithFlags(&m->ready, hipEventDisableTiming) != hipSuccess) return fail(CE_E_DEVICE);
   if (launch_mask_sum(mask_f, survey_cells(plan), m->fsum, s) != hipSuccess) return fail(CE_E_DEVICE);
   void* w = nullptr;
   st = window_transform(ctx, plan, mask_f, &w, s);
   if (st != CE_OK) return fail(st);
   if (hipMemcpyAsync(m->win, w, m->win_bytes, hipMemcpyDeviceToDevice, s) != hipSuccess) return fail(CE_E_DEVICE);
+  // runs on any stream wait for this event before reading the handle
+  if (hipEventRecord(m->ready, s) != hipSuccess) return fail(CE_E_DEVICE);
   *out = m.release();
   return CE_OK;
 }
@@ -2029,8 +2084,10 @@ void ce_mask_release(ce_mask* m) {
   {
     std::lock_guard<std::mutex> lock(m->ctx->mu);
     (void)hipSetDevice(m->ctx->device);
+    (void)hipEventSynchronize(m->ready);
     m->ctx->release(m->win, m->win_bytes);  // hipFree waits for the work that reads it
     m->ctx->release(m->fsum, sizeof(double) * 257);
+    (void)hipEventDestroy(m->ready);
   }
   delete m;
 }
@@ -2052,6 +2109,8 @@ ce_status ce_pipeline_run_prepared(ce_ctx* ctx, const ce_plan* plan, const float
   CE_HIP(hipSetDevice(ctx->device));
   hipStream_t s = as_stream(stream);
   ctx->last = s;
+  // the handle may have been prepared on another stream: its window and sum must be complete
+  CE_HIP(hipStreamWaitEvent(s, mask->ready, 0));
   return pipeline_impl(ctx, plan, seed, request_id, first_realization, count, nbar, nbins, out_fields, out_delta,
                        out_counts, out_ntot, out_pk, out_cov, out_cnorm, nullptr, s, mask_f, mask->win, mask->fsum,
                        kedges);

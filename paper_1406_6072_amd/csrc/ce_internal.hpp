@@ -11,6 +11,7 @@ namespace ce {
 constexpr int kMaxStages = 16;
 constexpr int kEPT = 16;        // FFT elements held per thread
 constexpr int kMaxWG = 512;
+constexpr size_t kMaxLdsBytes = 160 * 1024;  // LDS of one gfx950 CU, the most one workgroup can use
 
 // One FFT line length: radices of the mixed-radix Stockham stages and the
 // device table of forward roots tw[k] = exp(-2 pi i k / L) in the pass precision.
@@ -36,6 +37,7 @@ struct LineGeom {
   int32_t lpitch = 0;          // LDS elements per line buffer
   int32_t nbuf = 1;            // LDS buffers per line: 1 (in place) or 2 (ping-pong, mixed radix)
   int32_t item_minor = 0;      // tile order: 0 = item-major (groups of one item adjacent), 1 = group-major
+  int32_t item_block = 1;      // item-major order over blocks of this many items (group-major inside a block)
   int32_t threads = 0;         // workgroup size when above R nlanes (the fused epilogue spreads its cells)
 };
 
@@ -46,6 +48,8 @@ struct LineGeom {
 struct PairDesc {
   const void* sq = nullptr;    // sqrt(lambda / M^d) octant of the request's plan (pass precision)
   int32_t* counts = nullptr;   // nullable: counts of the pair's real part; imaginary part at + ncells
+  void* fields = nullptr;      // nullable: field of the pair's real part (pass precision); imaginary at + ncells
+  void* delta = nullptr;       // nullable: lognormal contrast, laid out as fields
   uint32_t k0 = 0, k1 = 0, rid = 0, pair = 0;
   double s2half = 0, nbar = 0;
   int32_t nreal = 2;           // realizations of the pair that were requested (1: real part only)
@@ -130,7 +134,8 @@ struct BinArgs {
   // nullable: user shell edges as integer thresholds of t (nb + 1, device): shell b holds
   // TH_b < t <= TH_{b+1} instead of the linear rule
   const int64_t* th = nullptr;
-  double* partials = nullptr;  // [item][group][2][nb]
+  int32_t G = 1;               // lines per partial record (a divisor of the lines per workgroup)
+  double* partials = nullptr;  // [item][block of G lines][2][nb]
   // Masked 2-D fused pipeline (nullable win): the lines hold the transform A of N / (f nest) - 1
   // on f != 0; the contrast's transform is D = r A + (r - 1) Wm with r = nest sum(f) / N_tot of
   // the line's realization and Wm the transform of the indicator f != 0, stored N x W complex in
@@ -165,6 +170,7 @@ hipError_t launch_row_inverse(int prec, const LineGeom& g, const FftDesc& f, con
 hipError_t launch_pair_forward(int prec, const LineGeom& g, const FftDesc& f, const PairLoad& p, hipStream_t s);
 hipError_t launch_bin_pass(int prec, const LineGeom& g, const FftDesc& f, const BinArgs& b, const void* in,
                            hipStream_t s);
+size_t bin_pass_lds(const LineGeom& g, int N, int nb, int G, size_t elem);  // bytes of LDS per workgroup
 hipError_t launch_bin_reduce(double* partials, int64_t nitems, int64_t groups, int nb, int64_t count,
                              const int64_t* nmodes, double norm, int scale_kind, const unsigned long long* ntot_u,
                              const SlotOut* slots, double ncells, double* pk, uint32_t* flags, hipStream_t s);

@@ -32,6 +32,15 @@ __device__ __forceinline__ PassPos pass_pos(const LineGeom& g) {
   if (g.item_minor) {
     p.grp = t / g.nitems;
     p.item = t - p.grp * g.nitems;
+  } else if (g.item_block > 1) {
+    // blocks of item_block items: within a block, the items of one line group are adjacent
+    const int64_t per = g.groups_per_item * g.item_block;
+    const int64_t blk = t / per, rem = t - blk * per;
+    const int64_t i0 = blk * g.item_block;
+    const int64_t left = g.nitems - i0;
+    const int64_t kb = left < g.item_block ? left : g.item_block;
+    p.grp = rem / kb;
+    p.item = i0 + (rem - p.grp * kb);
   } else {
     p.item = t / g.groups_per_item;
     p.grp = t - p.item * g.groups_per_item;
@@ -592,8 +601,8 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(sizeof
     const uint32_t rid = pd ? pd->rid : e.rid, k0 = pd ? pd->k0 : e.k0, k1 = pd ? pd->k1 : e.k1;
     const T s2h = (T)(pd ? pd->s2half : e.s2half);
     const double nbar = pd ? pd->nbar : e.nbar;
-    T* fbase = e.fields ? static_cast<T*>(e.fields) + ra * e.ncells : nullptr;
-    T* dbase = e.delta ? static_cast<T*>(e.delta) + ra * e.ncells : nullptr;
+    T* fbase = pd ? static_cast<T*>(pd->fields) : (e.fields ? static_cast<T*>(e.fields) + ra * e.ncells : nullptr);
+    T* dbase = pd ? static_cast<T*>(pd->delta) : (e.delta ? static_cast<T*>(e.delta) + ra * e.ncells : nullptr);
     int32_t* cbase = pd ? pd->counts : (e.counts ? e.counts + ra * e.ncells : nullptr);
     cpx<T>* set = line - r * g.lpitch;  // row 0 of the buffer set that holds the result
     // tpr threads per row (the line lanes when the workgroup has no more threads than them)
@@ -733,185 +742,133 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(sizeof
 // the transform along axis 0, mode a = |k_0| in [0, N/2] of a line has the power
 // v(a) = |F(a)|^2 + |F(N-a)|^2 (one term at a = 0, N/2) times the line weight
 // (2 unless k_last is 0 or N/2: the half-space stands for both signs).  The
-// shell of a mode is nondecreasing in a, so each thread sums a contiguous chunk
-// of a into runs of equal shell; runs inside a chunk are complete, runs that
-// cross chunk boundaries are merged by their first chunk in chunk order, and
-// lines are combined per (realization, shell) in line order: all sums are in a
-// fixed order, hence bitwise reproducible.
+// shell integer t(a) = T0 a^2 + p (p the line's fixed part) grows with a, so the
+// modes of shell b on a line are one contiguous range of a, found from the shell
+// edges by an integer square root.  Each line's powers are first stored in its own
+// LDS slots (slot a <- v(a); lane-local, slot a and N - a are read only by the lane
+// of a), then one lane per shell adds the shell's range in increasing a; the lines
+// of a group are combined per (realization, shell) in line order.  Every sum has a
+// fixed order, so results are bitwise reproducible and independent of the number
+// of items in a launch.
 
-// shell b in [0, nb) of a mode with t = sum_i T_i q~_i^2 (exact integers): b + 1 = smallest s with
-// s^2 LL >= t
-__device__ __forceinline__ int shell_of_t(int64_t t, int64_t NN) {
-  int64_t s = (int64_t)sqrt((double)t / (double)NN);
-  while (s > 0 && (s - 1) * (s - 1) * NN >= t) --s;
-  while (s * s * NN < t) ++s;
-  return (int)(s - 1);
+// Edge e_b of shell b (b in [0, nb]): shell b holds the modes with e_b < t <= e_{b+1};
+// linear shells e_b = b^2 LL, user shells the thresholds th[b].
+template <int TAB>
+__device__ __forceinline__ int64_t shell_edge(const BinArgs& bn, int b) {
+  return TAB ? bn.th[b] : (int64_t)b * b * bn.LL;
 }
 
-// shell of t under user thresholds th[0..nb]: b with th[b] < t <= th[b+1]; -1 below th[0], nb
-// above th[nb] (binary search)
-__device__ __forceinline__ int shell_of_tab(int64_t t, const int64_t* th, int nb) {
-  int lo = 0, hi = nb + 1;  // count of thresholds below t lies in [lo, hi]
-  while (lo < hi) {
-    const int mid = (lo + hi) >> 1;
-    if (th[mid] < t)
-      lo = mid + 1;
-    else
-      hi = mid;
-  }
-  return lo - 1;
+// Number of a in [0, amax] with T a^2 <= y (y may be negative): the count of modes of a line
+// with t <= p + y.  FP32 square-root estimate, corrected exactly in integers (T a^2 < 2^63 for
+// a <= amax + 1, the shell-rule range).
+__device__ __forceinline__ int modes_upto(int64_t y, int64_t T, int amax) {
+  if (y < 0) return 0;
+  int a = (int)sqrtf((float)y / (float)T);
+  a = a > amax + 1 ? amax + 1 : a;
+  while (a > 0 && T * (int64_t)a * a > y) --a;
+  while (a <= amax && T * (int64_t)(a + 1) * (a + 1) <= y) ++a;
+  return a > amax ? amax + 1 : a + 1;
 }
 
-struct RunEnds {
-  int first_bin, last_bin;
-  double first_sum, last_sum;
-  int single, nonempty;
-};
-
-// Binning of one line group already transformed in LDS (lines r < nl of the group that
-// starts at line0); adds the group's per-shell sums, lines in order, to tot[2][nb]
-// (entry t is read and written by thread t only).
+// Per-line partial sums of the shells (acc of line r: nb doubles at accr(r)), lines r < nl of
+// the group that starts at line0; then, for every block of bn.G consecutive lines, the block's
+// per-shell totals (lines in order, from zero) into the record rec[j][2][nb] of block j of the
+// group.  The records depend only on the block, not on the lines per workgroup (a multiple of G),
+// so the spectra are bitwise independent of the launch shape.
 template <typename T, int WIN, int TAB>
-__device__ __forceinline__ void bin_group(const cpx<T>* res, const LineGeom& g, const BinArgs& bn, int64_t item,
-                                          int64_t line0, int nl, double* acc, RunEnds* ends, double* tot) {
+__device__ __forceinline__ void bin_group(cpx<T>* res, const LineGeom& g, const BinArgs& bn, int64_t item,
+                                          int64_t line0, int nl, double* acc_area, double* rec) {
   const int r = threadIdx.x / g.nlanes, lane = threadIdx.x - r * g.nlanes;
   const bool active = r < nl;
   // N, Nh: axis 0 (the line); Kh = N_last / 2 + 1 columns per realization of a pair
   const int N = bn.N, Nh = N / 2, nb = bn.nb, W = bn.W, Kh = W / 2, Nlh = Kh - 1;
-  const int64_t Tq = bn.T0, NN = bn.LL;
-  if (r < g.R) {
-    RunEnds e{-1, -1, 0.0, 0.0, 1, 0};
-    if (active) {
-      const int64_t ln = line0 + r;
-      const int kl = (int)(ln % W);
-      const int s = kl >= Kh;
-      const int kz = kl - s * Kh;
-      int64_t p2 = bn.Tl * kz * kz;  // the line's fixed part of t
-      if (bn.ndim == 3) {
-        int k1 = (int)(ln / W);
-        if (k1 > bn.N1 / 2) k1 -= bn.N1;
-        p2 += bn.T1 * k1 * k1;
-      }
-      // line weight (exact factor 1 or 2), applied when a run is stored
-      const double wgt = (kz != 0 && kz != Nlh) ? 2.0 : 1.0;
-      const int chunk = (Nh + 1 + g.nlanes - 1) / g.nlanes;
-      const int a0 = lane * chunk, a1 = min(a0 + chunk, Nh + 1);
-      const cpx<T>* line = res + r * g.lpitch;
-      // masked pipeline (WIN): the line holds the transform A of N / (f nest) - 1; the
-      // contrast's is D = rr A + rm Wm with rr = nest sum(f) / N_tot of the line's realization,
-      // rm = rr - 1 and Wm the transform of the indicator f != 0, column-major ([column][q0] in
-      // 2-D, [q1][column][q0] in 3-D: the line's window values are contiguous in q0)
-      T rr = T(1), rm = T(0);
-      const cpx<T>* wcol = nullptr;
-      int64_t wstride = 0;
-      if (WIN) {
-        const double nt = (double)bn.ntot[2 * item + s];
-        const double rd = nt > 0.0 ? bn.nest * *bn.fsum / nt : 0.0;
-        rr = (T)rd;
-        rm = (T)(rd - 1.0);
-        wcol = static_cast<const cpx<T>*>(bn.win) + ((ln - kl) + kz) * (int64_t)N;
-        wstride = 1;
-      }
-      if (a0 < a1) {
-        e.nonempty = 1;
-        // t = T0 a^2 + p2 advanced by differences: t(a+1) - t(a) = T0 (2a + 1)
-        int64_t t = Tq * (int64_t)a0 * a0 + p2;
-        int64_t dt = Tq * (2 * (int64_t)a0 + 1);
-        const int64_t ddt = 2 * Tq;
-        int bin = TAB ? shell_of_tab(t, bn.th, nb) : shell_of_t(t, NN);
-        // the mode stays in `bin` while t <= edge: (bin+1)^2 LL (linear shells) or th[bin+1]
-        int64_t edge = TAB ? (bin < nb ? bn.th[bin + 1] : INT64_MAX) : (int64_t)(bin + 1) * (bin + 1) * NN;
-        int64_t estep = (int64_t)(2 * bin + 3) * NN;  // edge(bin + 1) - edge(bin)
-        double run = 0.0;
-        e.first_bin = bin;
-        for (int a = a0; a < a1; ++a) {
-          if (t > edge) {
-            // close the current run
-            if (bin == e.first_bin && e.single) {
-              e.first_sum = wgt * run;
-            } else if (bin >= 0 && bin < nb) {
-              acc[r * nb + bin] = wgt * run;  // interior run: complete within this chunk
-            }
-            e.single = 0;
-            // next shell that holds the mode (t grows slowly: usually one step)
-            do {
-              ++bin;
-              if (TAB) {
-                edge = bin < nb ? bn.th[bin + 1] : INT64_MAX;
-              } else {
-                edge += estep;
-                estep += 2 * NN;
-              }
-            } while (t > edge);
-            run = 0.0;
-          }
-          // power of the mode pair in the pass precision, summed in FP64
-          cpx<T> v = line[pidx(a)];
-          if (WIN) {
-            const cpx<T> w = wcol[(int64_t)a * wstride];
-            v = {rr * v.x + rm * w.x, rr * v.y + rm * w.y};
-          }
-          // explicit fused multiply-adds: the same rounding in every instantiation of the pass
-          T pw = fma(v.x, v.x, v.y * v.y);
-          if (a != 0 && a != Nh) {
-            cpx<T> u = line[pidx(N - a)];
-            if (WIN) {
-              const cpx<T> w = wcol[(int64_t)(N - a) * wstride];
-              u = {rr * u.x + rm * w.x, rr * u.y + rm * w.y};
-            }
-            pw += fma(u.x, u.x, u.y * u.y);
-          }
-          run += (double)pw;
-          t += dt;
-          dt += ddt;
-        }
-        if (e.single) {
-          e.first_sum = wgt * run;
-          e.last_bin = bin;
-        } else {
-          e.last_bin = bin;
-          e.last_sum = wgt * run;
-        }
-      }
-    }
-    ends[r * g.nlanes + lane] = e;
-  }
-  __syncthreads();
-  // merge runs that cross chunk boundaries: each run is owned by the chunk it starts in
+  // shell sums of line r: in its own slots Nh + 1 .. N - 1 (free once the powers are formed)
+  // when they hold nb values, else in the separate area
+  const bool in_line = nb <= N - Nh - 1;
+  auto accr = [&](int rr) -> double* {
+    return in_line ? nullptr : acc_area + (int64_t)rr * nb;
+  };
+  cpx<T>* line = res + r * g.lpitch;
+  int64_t p2 = 0;
+  double wgt = 1.0;
   if (active) {
-    const RunEnds* le = ends + r * g.nlanes;
-    const RunEnds e = le[lane];
-    if (e.nonempty) {
-      auto extend = [&](int bin, double total, int from) {
-        for (int m = from; m < g.nlanes; ++m) {
-          const RunEnds& x = le[m];
-          if (!x.nonempty || x.first_bin != bin) break;
-          total += x.first_sum;
-          if (!x.single) break;
-        }
-        if (bin >= 0 && bin < nb) acc[r * nb + bin] = total;
-      };
-      const bool continues = lane > 0 && le[lane - 1].nonempty && le[lane - 1].last_bin == e.first_bin;
-      if (!continues) {
-        if (e.single)
-          extend(e.first_bin, e.first_sum, lane + 1);
-        else if (e.first_bin >= 0 && e.first_bin < nb)
-          acc[r * nb + e.first_bin] = e.first_sum;
+    const int64_t ln = line0 + r;
+    const int kl = (int)(ln % W);
+    const int s = kl >= Kh;
+    const int kz = kl - s * Kh;
+    p2 = bn.Tl * kz * kz;  // the line's fixed part of t
+    if (bn.ndim == 3) {
+      int k1 = (int)(ln / W);
+      if (k1 > bn.N1 / 2) k1 -= bn.N1;
+      p2 += bn.T1 * k1 * k1;
+    }
+    // line weight (exact factor 1 or 2)
+    wgt = (kz != 0 && kz != Nlh) ? 2.0 : 1.0;
+    // masked pipeline (WIN): the line holds the transform A of N / (f nest) - 1; the
+    // contrast's is D = rr A + rm Wm with rr = nest sum(f) / N_tot of the line's realization,
+    // rm = rr - 1 and Wm the transform of the indicator f != 0, column-major ([column][q0] in
+    // 2-D, [q1][column][q0] in 3-D: the line's window values are contiguous in q0)
+    T rr = T(1), rm = T(0);
+    const cpx<T>* wcol = nullptr;
+    if (WIN) {
+      const double nt = (double)bn.ntot[2 * item + s];
+      const double rd = nt > 0.0 ? bn.nest * *bn.fsum / nt : 0.0;
+      rr = (T)rd;
+      rm = (T)(rd - 1.0);
+      wcol = static_cast<const cpx<T>*>(bn.win) + ((ln - kl) + kz) * (int64_t)N;
+    }
+    // power of each mode pair in the pass precision (explicit fused multiply-adds: the same
+    // rounding in every instantiation), stored as a double in slot a
+    for (int a = lane; a <= Nh; a += g.nlanes) {
+      cpx<T> v = line[pidx(a)];
+      if (WIN) {
+        const cpx<T> w = wcol[a];
+        v = {rr * v.x + rm * w.x, rr * v.y + rm * w.y};
       }
-      if (!e.single) extend(e.last_bin, e.last_sum, lane + 1);
+      T pw = fma(v.x, v.x, v.y * v.y);
+      if (a != 0 && a != Nh) {
+        cpx<T> u = line[pidx(N - a)];
+        if (WIN) {
+          const cpx<T> w = wcol[N - a];
+          u = {rr * u.x + rm * w.x, rr * u.y + rm * w.y};
+        }
+        pw += fma(u.x, u.x, u.y * u.y);
+      }
+      *reinterpret_cast<double*>(&line[pidx(a)]) = (double)pw;
     }
   }
   __syncthreads();
-  const int kl0 = (int)(line0 % W);
-  for (int t = threadIdx.x; t < 2 * nb; t += blockDim.x) {
-    const int s = t / nb, b = t - s * nb;
-    double sum = tot[t];
-    int kl = kl0;
-    for (int lr = 0; lr < nl; ++lr) {
-      if ((kl >= Kh) == s) sum += acc[lr * nb + b];
+  if (active) {
+    // shell b holds a in [lo, hi): e_b < T0 a^2 + p2 <= e_{b+1}
+    double* ar = accr(r);
+    for (int b = lane; b < nb; b += g.nlanes) {
+      const int lo = modes_upto(shell_edge<TAB>(bn, b) - p2, bn.T0, Nh);
+      const int hi = modes_upto(shell_edge<TAB>(bn, b + 1) - p2, bn.T0, Nh);
+      double sum = 0.0;
+      for (int a = lo; a < hi; ++a) sum += *reinterpret_cast<const double*>(&line[pidx(a)]);
+      if (ar)
+        ar[b] = wgt * sum;
+      else
+        *reinterpret_cast<double*>(&line[pidx(Nh + 1 + b)]) = wgt * sum;
+    }
+  }
+  __syncthreads();
+  const int G = bn.G;
+  const int nrec = (nl + G - 1) / G;
+  for (int t = threadIdx.x; t < nrec * 2 * nb; t += blockDim.x) {
+    const int j = t / (2 * nb), sb = t - j * 2 * nb;
+    const int s = sb / nb, b = sb - s * nb;
+    double sum = 0.0;
+    const int l1 = min(nl, (j + 1) * G);
+    int kl = (int)((line0 + j * G) % W);
+    for (int lr = j * G; lr < l1; ++lr) {
+      if ((kl >= Kh) == s) {
+        const double* ar = accr(lr);
+        sum += ar ? ar[b] : *reinterpret_cast<const double*>(&res[lr * g.lpitch + pidx(Nh + 1 + b)]);
+      }
       if (++kl == W) kl = 0;
     }
-    tot[t] = sum;
+    rec[t] = sum;
   }
 }
 
@@ -919,18 +876,20 @@ template <typename T, int MIX, int WIN, int TAB>
 __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 4 : 2))) k_bin_pass(LineGeom g, FftDesc f, BinArgs bn, const cpx<T>* in) {
   cpx<T>* lds = lds_lines<T>();
   const PassPos pp = pass_pos(g);
-  double* acc = reinterpret_cast<double*>(lds + g.nbuf * g.R * g.lpitch);  // [R][nb]
-  RunEnds* ends = reinterpret_cast<RunEnds*>(acc + g.R * bn.nb);             // [R][nlanes]
-  double* tot = reinterpret_cast<double*>(ends + g.R * g.nlanes);            // [2][nb]
+  const int nrec_wg = g.R / bn.G;                                            // records per workgroup
+  double* rec = reinterpret_cast<double*>(lds + g.nbuf * g.R * g.lpitch);  // [R/G][2][nb]
+  double* acc = rec + nrec_wg * 2 * bn.nb;                                  // [R][nb] when not in the lines
   load_lines(lds, in, g, pp);
-  for (int t = threadIdx.x; t < g.R * bn.nb; t += blockDim.x) acc[t] = 0.0;
-  for (int t = threadIdx.x; t < 2 * bn.nb; t += blockDim.x) tot[t] = 0.0;
   __syncthreads();
   const int r = threadIdx.x / g.nlanes, lane = threadIdx.x - r * g.nlanes;
   line_fft<T, -1, MIX>(buf_a(lds, g, r), buf_b(lds, g, r), f, lane, g.nlanes, r < pp.nl, f.L);
-  bin_group<T, WIN, TAB>(result_base<T, MIX>(lds, g, f), g, bn, pp.item, pp.line0, pp.nl, acc, ends, tot);
-  for (int t = threadIdx.x; t < 2 * bn.nb; t += blockDim.x)
-    bn.partials[(pp.item * g.groups_per_item + pp.grp) * 2 * bn.nb + t] = tot[t];
+  bin_group<T, WIN, TAB>(result_base<T, MIX>(lds, g, f), g, bn, pp.item, pp.line0, pp.nl, acc, rec);
+  __syncthreads();
+  // the records of this group's blocks: block (line0 / G + j) of the item
+  const int nrec = (pp.nl + bn.G - 1) / bn.G;
+  const int64_t nblocks = (g.A * g.B + bn.G - 1) / bn.G;
+  double* dst = bn.partials + (pp.item * nblocks + pp.line0 / bn.G) * 2 * bn.nb;
+  for (int t = threadIdx.x; t < nrec * 2 * bn.nb; t += blockDim.x) dst[t] = rec[t];
 }
 
 // Many line groups per item: the partials of each run of kGroupChunk groups are summed in
@@ -1312,8 +1271,7 @@ hipError_t launch_pair_forward(int prec, const LineGeom& g, const FftDesc& f, co
 template <typename T>
 static void bin_pass_t(int mix, const LineGeom& g, const FftDesc& f, const BinArgs& b, const void* in,
                        hipStream_t s) {
-  const size_t lds = lines_lds_bytes(g, sizeof(cpx<T>)) + (size_t)g.R * b.nb * sizeof(double) +
-                     (size_t)g.R * g.nlanes * sizeof(RunEnds) + 2 * (size_t)b.nb * sizeof(double);
+  const size_t lds = bin_pass_lds(g, b.N, b.nb, b.G, sizeof(cpx<T>));
   const cpx<T>* i = static_cast<const cpx<T>*>(in);
   with_variant(mix, [&](auto v) {
     if (b.win && b.th)
@@ -1327,8 +1285,20 @@ static void bin_pass_t(int mix, const LineGeom& g, const FftDesc& f, const BinAr
   });
 }
 
+// LDS of a binning-pass workgroup of R lines: the line buffers, the records of its blocks of G
+// lines ([R/G][2][nb]) and, when a line's free slots (N/2 - 1 of them) cannot hold its nb shell
+// sums, a separate [R][nb] area.
+size_t bin_pass_lds(const LineGeom& g, int N, int nb, int G, size_t elem) {
+  const bool in_line = nb <= N - N / 2 - 1;
+  return lines_lds_bytes(g, elem) + (size_t)(g.R / G) * 2 * nb * sizeof(double) +
+         (in_line ? 0 : (size_t)g.R * nb * sizeof(double));
+}
+
 hipError_t launch_bin_pass(int prec, const LineGeom& g, const FftDesc& f, const BinArgs& b, const void* in,
                            hipStream_t s) {
+  if (b.G < 1 || g.R % b.G || bin_pass_lds(g, b.N, b.nb, b.G, prec ? sizeof(cpx<double>) : sizeof(cpx<float>)) >
+                                   kMaxLdsBytes)
+    return hipErrorInvalidValue;
   const int mix = fft_variant(f);
   if (!nbuf_ok(g, mix)) return hipErrorInvalidValue;
   if (prec == 0)

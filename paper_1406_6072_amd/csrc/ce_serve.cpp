@@ -241,10 +241,10 @@ struct ce_server {
       double* cov = r.realizations >= 2 ? r.out_cov : nullptr;
       if (!q.edges.empty())
         return ce_pipeline_run_edges(s.ctx, pe->plan, nullptr, r.seed, r.request_id, 0, r.realizations, r.nbar,
-                                     r.nbins, q.edges.data(), nullptr, nullptr, r.out_counts, r.out_ntot, r.out_pk,
-                                     cov, nullptr, s.stream);
-      return ce_pipeline_run(s.ctx, pe->plan, r.seed, r.request_id, 0, r.realizations, r.nbar, r.nbins, nullptr,
-                             nullptr, r.out_counts, r.out_ntot, r.out_pk, cov, nullptr, s.stream);
+                                     r.nbins, q.edges.data(), r.out_fields, r.out_delta, r.out_counts, r.out_ntot,
+                                     r.out_pk, cov, nullptr, s.stream);
+      return ce_pipeline_run(s.ctx, pe->plan, r.seed, r.request_id, 0, r.realizations, r.nbar, r.nbins,
+                             r.out_fields, r.out_delta, r.out_counts, r.out_ntot, r.out_pk, cov, nullptr, s.stream);
     };
     std::vector<ce_status> rs(s.reqs.size(), CE_OK);
     bool batched = false;
@@ -266,6 +266,8 @@ struct ce_server {
         it.out_cov = r.realizations >= 2 ? r.out_cov : nullptr;
         it.out_cnorm = nullptr;
         it.kedges = s.reqs[k]->edges.empty() ? nullptr : s.reqs[k]->edges.data();
+        it.out_fields = r.out_fields;
+        it.out_delta = r.out_delta;
       }
       // an invalid item makes the batch launch nothing: then every request runs alone, so a
       // failing request fails alone

@@ -14,6 +14,7 @@ pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
 
 from oracle import fields as ofields, kspace, pk as opk  # noqa: E402
+from parity_check import check_maps  # noqa: E402
 from synth import workloads  # noqa: E402
 
 
@@ -65,8 +66,7 @@ def test_box_fields_match_oracle(ce, prec):
     got = out.cpu().numpy().astype(np.float64).reshape((6,) + n)
     want = ofields.generate_fields(ref, 11, 5, 4, 6)
     tol = 1e-10 if prec == 1 else 1e-5
-    for k in range(6):
-        assert np.linalg.norm(got[k] - want[k]) <= tol * np.linalg.norm(want[k])
+    check_maps(got, want, tol, math.sqrt(ref["sigma2"]), "box fields")
     plan.release()
 
 

@@ -15,6 +15,7 @@ pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
 
 from oracle import embedding, fields as ofields, lognormal_poisson as olp, pk as opk  # noqa: E402
+from parity_check import check_delta, check_maps  # noqa: E402
 
 
 @pytest.fixture(scope="module")
@@ -222,29 +223,81 @@ def test_server_submit_many_is_all_or_nothing(ce):
 
 
 def test_server_request_against_oracle(ce):
-    """One served request checked against the oracle end to end (fields are not returned by
-    the server, so counts are checked through their statistics: the oracle run on the same
-    Philox streams must give the same N_tot and P(k))."""
+    """Served requests checked against the oracle end to end on identical Philox streams: fields
+    to the field tolerance (relative L2 and element-wise), delta from the GPU's fields, counts and
+    N_tot bit-exact with the oracle fed the GPU's delta, P(k) per shell from the oracle on those
+    counts.  Two requests of the same shape are submitted together, so they run as one group of
+    the batched pipeline; a third of another shape runs beside them."""
     b, _ = ce
-    n, xi, prec, R, nbar, nb, seed, rid = (48, 48), dict(kind="exp", sigma2=0.5, a=6.0), 1, 4, 3.0, 12, 3, 9
-    server = b.server_create(0, slots=2)
+    nb, nbar, seed = 12, 3.0, 3
+    cases = [((48, 48), dict(kind="exp", sigma2=0.5, a=6.0), 1, 4, 9),
+             ((48, 48), dict(kind="exp", sigma2=0.9, a=3.0), 1, 3, 10),
+             ((40, 24), dict(kind="exp", sigma2=0.7, a=4.0), 0, 2, 11)]
+    server = b.server_create(0, slots=1)
+    outs = []
     try:
-        o = outputs(48 * 48, R, nb, cov=False)
-        t = b.server_submit(server, n, (1.0, 1.0), xi, prec, seed, rid, R, nbar, nb, **o)
-        st, status, _ = wait_all(b, server, [t])[t]
+        reqs = []
+        for n, xi, prec, R, rid in cases:
+            cells = n[0] * n[1]
+            dt = torch.float64 if prec == 1 else torch.float32
+            o = outputs(cells, R, nb, cov=False)
+            o["out_fields"] = torch.empty(R * cells, dtype=dt, device="cuda")
+            o["out_delta"] = torch.empty(R * cells, dtype=dt, device="cuda")
+            outs.append(o)
+            reqs.append(dict(n=n, h=(1.0, 1.0), xi=xi, precision=prec, seed=seed, request_id=rid, realizations=R,
+                             nbar=nbar, nbins=nb, **o))
+        tickets = b.server_submit_many(server, reqs)
+        states = wait_all(b, server, tickets)
     finally:
         b.server_destroy(server)
-    assert st == 2 and status == 0
-    ref_plan = embedding.plan(n, (1.0, 1.0), xi)
-    g = ofields.generate_fields(ref_plan, seed, rid, 0, R)
-    _, rc, rn = olp.lognormal_poisson(g, ref_plan["sigma2"], nbar, seed, rid, 0)
-    counts = o["out_counts"].cpu().numpy().reshape((R,) + n)
-    # FP64 fields differ from the oracle's by ~1e-15 relative: a Poisson draw can flip only
-    # where a uniform lands within that distance of a CDF step, so nearly all cells agree
-    assert np.mean(counts == rc) > 0.9999
-    rp = opk.estimate_pk(counts, 1.0, nb, kind="counts", ntot=o["out_ntot"].cpu().numpy())
-    assert np.max(np.abs(o["out_pk"].cpu().numpy().reshape(R, nb) / rp - 1)) <= 1e-12
-    assert abs(int(o["out_ntot"].sum()) - int(rn.sum())) <= 2
+    for (n, xi, prec, R, rid), o, t in zip(cases, outs, tickets):
+        st, status, _ = states[t]
+        assert st == 2 and status == 0
+        ref_plan = embedding.plan(n, (1.0, 1.0), xi)
+        tol = 1e-12 if prec == 1 else 1e-5
+        g = o["out_fields"].cpu().numpy().reshape((R,) + n)
+        check_maps(g, ofields.generate_fields(ref_plan, seed, rid, 0, R), tol, np.sqrt(ref_plan["sigma2"]),
+                   "served fields %s" % (n,))
+        dh = o["out_delta"].cpu().numpy().reshape((R,) + n)
+        check_delta(dh, olp.lognormal_delta(g.astype(np.float64), ref_plan["sigma2"]), tol)
+        _, rc, rn = olp.lognormal_poisson(g.astype(np.float64), ref_plan["sigma2"], nbar, seed, rid, 0, delta=dh)
+        assert np.array_equal(o["out_counts"].cpu().numpy().reshape((R,) + n), rc)
+        assert np.array_equal(o["out_ntot"].cpu().numpy(), rn)
+        rp = opk.estimate_pk(rc, 1.0, nb, kind="counts", ntot=rn)
+        assert np.max(np.abs(o["out_pk"].cpu().numpy().reshape(R, nb) / rp - 1)) <= tol
+
+
+def test_batch_fields_and_delta_equal_single_calls(ce):
+    """Fields and delta requested from the batched pipeline equal those of ce_pipeline_run
+    for each item alone, bit for bit (odd counts, both precisions, one item without them)."""
+    b, ctx = ce
+    specs = [((32, 32), dict(kind="exp", sigma2=1.0, a=3.0), 0, 3, True),
+             ((32, 32), dict(kind="exp", sigma2=0.6, a=2.0), 0, 2, False),
+             ((32, 32), dict(kind="exp", sigma2=0.8, a=4.0), 0, 5, True),
+             ((20, 24), dict(kind="exp", sigma2=0.8, a=4.0), 1, 4, True)]
+    nb, nbar = 10, 2.0
+    items, refs, plans = [], [], []
+    for k, (n, xi, prec, R, want) in enumerate(specs):
+        plan = b.plan_embedding(ctx, n, (1.0, 1.0), xi, prec)
+        plans.append(plan)
+        o = outputs(plan.cells, R, nb)
+        r = outputs(plan.cells, R, nb)
+        if want:
+            for d in (o, r):
+                d["out_fields"] = torch.empty(R * plan.cells, dtype=plan.dtype, device="cuda")
+                d["out_delta"] = torch.empty(R * plan.cells, dtype=plan.dtype, device="cuda")
+        items.append(dict(plan=plan, seed=4, request_id=30 + k, count=R, nbar=nbar, nbins=nb, **o))
+        b.pipeline_run(ctx, plan, 4, 30 + k, 0, R, nbar, nb, **r)
+        refs.append(r)
+    b.pipeline_run_batch(ctx, items)
+    torch.cuda.synchronize()
+    assert b.ctx_check(ctx) == 0
+    for it, r in zip(items, refs):
+        for key in r:
+            if r[key] is not None:
+                assert torch.equal(it[key].cpu(), r[key].cpu()), key
+    for p in plans:
+        p.release()
 
 
 def test_server_rejects_what_never_fits(ce):

@@ -13,6 +13,7 @@ pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
 
 from oracle import embedding, fields as ofields, filtered  # noqa: E402
+from parity_check import check_maps  # noqa: E402
 from synth import workloads  # noqa: E402
 
 POWEXP = dict(kind="powexp", sigma2=0.185, r0=1.0, gamma=0.7, rc=300.0)
@@ -84,8 +85,7 @@ def test_plan_and_fields_in_omega_mode(ce, prec):
     got = out.cpu().numpy().astype(np.float64).reshape((4,) + n)
     want = ofields.generate_fields(ref, 7, 3, 2, 4)
     tol = 1e-10 if prec == 1 else 1e-5
-    for k in range(4):
-        assert np.linalg.norm(got[k] - want[k]) <= tol * np.linalg.norm(want[k])
+    check_maps(got, want, tol, math.sqrt(ref["sigma2"]), "omega-mode fields")
     plan.release()
 
 

@@ -84,3 +84,28 @@ def test_lognormal_variance_relation_matches_paper_numbers():
     rng = np.random.default_rng(3)
     g = rng.normal(0.0, math.sqrt(math.log(1 + s2d)), 1000000)
     assert abs(lp.lognormal_delta(g, math.log(1 + s2d)).var() - s2d) < 0.003
+
+
+def test_masked_rate_is_nbar_times_f():
+    """Eq. sampling: with the surface fraction f fixed per cell (and rho = 1), counts of every cell
+    have mean = variance = nbar f; cells with f = 0 draw nothing.  A rate that ignored f (nbar)
+    or applied it twice (nbar f^2) fails every partially covered group by tens of standard errors."""
+    nbar, R = 4.0, 120
+    fs = np.array([0.0, 0.25, 0.5, 0.85, 1.0])
+    mask = np.repeat(fs, 16 * 64).reshape(80, 64).astype(np.float32)   # stripes of 16 rows per value
+    delta = np.zeros((R,) + mask.shape)
+    _, counts, ntot = lp.lognormal_poisson(delta, 0.0, nbar, seed=8, request_id=3, first_realization=0,
+                                           mask=mask, delta=delta)
+    assert np.array_equal(ntot, counts.reshape(R, -1).sum(axis=1))
+    for f in fs:
+        c = counts[:, mask == np.float32(f)].astype(np.float64).ravel()
+        mu = nbar * float(np.float32(f))
+        if f == 0:
+            assert not c.any()
+            continue
+        n = c.size
+        assert abs(c.mean() - mu) < 5 * math.sqrt(mu / n), (f, c.mean(), mu)
+        assert abs(c.var() - mu) < 5 * math.sqrt((mu + 2 * mu * mu) / n), (f, c.var(), mu)
+        for wrong in (nbar, nbar * float(np.float32(f)) ** 2):
+            if abs(wrong - mu) > 1e-12:
+                assert abs(c.mean() - wrong) > 20 * math.sqrt(mu / n)
