@@ -340,6 +340,27 @@ ce_status ce_pipeline_run(ce_ctx* ctx, const ce_plan* plan, uint64_t seed, uint3
                           int64_t* out_ntot, double* out_pk, double* out_cov, double* out_cnorm,
                           void* stream);
 
+/* ce_pipeline_run for callers that cannot allocate device memory (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc): the same computation and results, bit for
+ * bit, as ce_pipeline_run with the same arguments, but every scratch buffer (the pass
+ * intermediates, the shell records, the N_tot accumulators and the shell table, counted on the
+ * device) is carved from one static device array of the library, 1 GiB per device (CE_NOALLOC_BYTES),
+ * held by every device the library runs on until the process ends.  The call allocates nothing:
+ * no hipMalloc, hipFree or allocating library routine (the twiddle tables of the plan's lengths
+ * are built when the plan is created).  Realizations are processed in chunks of as many pairs as
+ * the array holds; a geometry of which one pair does not fit (the noise-pass and inner-axis
+ * intermediates of one pair plus its spectra above 1 GiB, e.g. 3-D sides above ~300) returns
+ * CE_E_UNSUPPORTED before anything is enqueued.  Equal-width shells only (no user edges, no mask).
+ * All calls on one device share the array and it keeps the last call's contents (everything that
+ * must start at zero is cleared by a kernel in each call): calls that overlap in time on one
+ * device race, whatever their ctx or stream, so serialise them.  Profiling events are not
+ * recorded for this call.  Errors: as ce_pipeline_run; CE_E_UNSUPPORTED as above. */
+#define CE_NOALLOC_BYTES ((size_t)1 << 30)
+ce_status ce_pipeline_run_noalloc(ce_ctx* ctx, const ce_plan* plan, uint64_t seed, uint32_t request_id,
+                                  uint64_t first_realization, int64_t count, double nbar, int32_t nbins,
+                                  void* out_fields, void* out_delta, int32_t* out_counts, int64_t* out_ntot,
+                                  double* out_pk, double* out_cov, double* out_cnorm, void* stream);
+
 /* ce_pipeline_run with the user shells of ce_estimate_pk_edges (kedges: host, nbins + 1 strictly
  * ascending |k| values >= 0; the paper bins in ln l) and, when mask_f is not NULL, on a masked
  * survey as ce_pipeline_run_masked (the paper's setting: a masked field binned in ln l).

@@ -112,6 +112,8 @@ _astar_map = _sig("ce_astar_map", c_i32, c_void_p, c_void_p, c_i64, c_i64, c_voi
                   c_void_p, c_void_p, c_void_p)
 _pipeline_run = _sig("ce_pipeline_run", c_i32, c_void_p, c_void_p, c_u64, c_u32, c_u64, c_i64, c_f64, c_i32,
                      c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p)
+_pipeline_noalloc = _sig("ce_pipeline_run_noalloc", c_i32, c_void_p, c_void_p, c_u64, c_u32, c_u64, c_i64, c_f64,
+                         c_i32, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p)
 _graph_create = _sig("ce_pipeline_graph_create", c_i32, c_void_p, c_void_p, c_u64, c_u32, c_u64, c_i64, c_f64, c_i32,
                      c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, ctypes.POINTER(c_void_p))
 _graph_launch = _sig("ce_pipeline_graph_launch", c_i32, c_void_p, c_void_p)
@@ -149,7 +151,7 @@ EXPORTED = ["ce_status_string", "ce_version", "ce_ctx_create", "ce_ctx_destroy",
             "ce_plan_periodic",
             "ce_generate_fields", "ce_lognormal_poisson", "ce_estimate_pk", "ce_estimate_pk_edges", "ce_pk_covariance",
             "ce_cic_histogram", "ce_cic_predict", "ce_astar_map", "ce_cumulative_information",
-            "ce_pipeline_run", "ce_pipeline_run_edges", "ce_pipeline_run_masked", "ce_mask_prepare",
+            "ce_pipeline_run", "ce_pipeline_run_noalloc", "ce_pipeline_run_edges", "ce_pipeline_run_masked", "ce_mask_prepare",
             "ce_mask_release", "ce_pipeline_run_prepared", "ce_pipeline_run_batch", "ce_pipeline_graph_create", "ce_pipeline_graph_launch",
             "ce_pipeline_graph_destroy",
             "ce_server_create", "ce_server_submit", "ce_server_submit_many", "ce_server_poll", "ce_server_drain", "ce_server_cancel",
@@ -475,6 +477,21 @@ def pipeline_run(ctx, plan, seed, request_id, first_realization, count, nbar, nb
                          _ptr(out_cov, torch.float64, nbins * nbins, "out_cov"),
                          _ptr(out_cnorm, torch.float64, nbins * nbins, "out_cnorm"), _stream(stream)),
            "ce_pipeline_run")
+
+
+def pipeline_run_noalloc(ctx, plan, seed, request_id, first_realization, count, nbar, nbins, out_pk, out_fields=None,
+                         out_delta=None, out_counts=None, out_ntot=None, out_cov=None, out_cnorm=None, stream=None):
+    """ce_pipeline_run with every scratch buffer in the library's static device array (no allocation)."""
+    cells = plan.cells
+    _check(_pipeline_noalloc(ctx, plan.handle, int(seed), int(request_id), int(first_realization), int(count),
+                             float(nbar), int(nbins), _ptr(out_fields, plan.dtype, count * cells, "out_fields"),
+                             _ptr(out_delta, plan.dtype, count * cells, "out_delta"),
+                             _ptr(out_counts, torch.int32, count * cells, "out_counts"),
+                             _ptr(out_ntot, torch.int64, count, "out_ntot"),
+                             _ptr(out_pk, torch.float64, count * nbins, "out_pk"),
+                             _ptr(out_cov, torch.float64, nbins * nbins, "out_cov"),
+                             _ptr(out_cnorm, torch.float64, nbins * nbins, "out_cnorm"), _stream(stream)),
+           "ce_pipeline_run_noalloc")
 
 
 def pipeline_run_edges(ctx, plan, seed, request_id, first_realization, count, nbar, nbins, edges, out_pk,

@@ -46,7 +46,7 @@ ce_status hip_status(hipError_t e) { return e == hipErrorOutOfMemory ? CE_E_OOM 
 #define CE_PROF(ctx, name, s, expr)                        \
   do {                                                     \
     hipEvent_t b_ = nullptr;                               \
-    if ((ctx)->prof) (ctx)->prof_begin(name, s, &b_);      \
+    if ((ctx)->prof && !(ctx)->noalloc) (ctx)->prof_begin(name, s, &b_); \
     CE_HIP(expr);                                          \
     if (b_) (void)hipEventRecord(b_, s);                   \
   } while (0)
@@ -144,6 +144,35 @@ LineGeom make_geom(int L, int K, int64_t A, int64_t B, int64_t nitems, int64_t i
 
 }  // namespace
 
+// ---- static scratch of the allocation-free entry point ----------------------------
+
+// Device memory of ce_pipeline_run_noalloc: a file-scope device array, one copy on every device
+// the library runs on, held until the process ends.  Host code never passes the array's name to
+// a kernel or a copy (on the host it is only a stand-in): it uses the device address that
+// hipGetSymbolAddress returns, resolved once per device with that device current.
+constexpr size_t kFixedScratchBytes = size_t(1) << 30;
+static __device__ __align__(256) unsigned char scratch[kFixedScratchBytes];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_fixed_mu;
+void* g_fixed_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on `device` (which must be current).
+ce_status fixed_scratch(int device, void** out) {
+  if (device < 0 || device >= kMaxDevices) return CE_E_INVALID;
+  std::lock_guard<std::mutex> lock(g_fixed_mu);
+  if (!g_fixed_ptr[device]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) return CE_E_DEVICE;
+    g_fixed_ptr[device] = p;
+  }
+  *out = g_fixed_ptr[device];
+  return CE_OK;
+}
+}  // namespace
+
 // ---- context -----------------------------------------------------------------
 
 // Constant tables shared by every context of the process, one set per device: twiddles,
@@ -186,6 +215,16 @@ struct ce_ctx {
     hipEvent_t a, b;
   };
   bool prof = false;
+  // Allocation-free calls: scratch slots are carved from the library's static device array
+  // (base, size) instead of being allocated; noalloc_pairs is the chunk that fits it.
+  bool noalloc = false;
+  int64_t noalloc_pairs = 0;
+  struct Arena {
+    char* base = nullptr;
+    size_t size = 0, off = 0;
+    void* p[14] = {};
+    size_t n[14] = {};
+  } arena;
   bool unpruned = false;  // inverse passes keep every embedding output (comparator form)
   int lines_cap[4] = {0, 0, 0, 0};  // max lines per workgroup per pass kind (0 = automatic)
   int noise_item_minor = 0;         // noise pass tile order (0: line groups of one pair adjacent; measured faster)
@@ -246,6 +285,20 @@ struct ce_ctx {
   // it waits for nothing but this context's earlier work; if that work ran on another
   // stream, that stream is drained first.
   ce_status scratch(int i, size_t bytes, void** out) {
+    if (noalloc) {
+      // a slot keeps its region for the whole call (later chunks ask for no more)
+      if (arena.p[i] && arena.n[i] >= bytes) {
+        *out = arena.p[i];
+        return CE_OK;
+      }
+      const size_t need = (bytes + 255) & ~(size_t)255;
+      if (arena.off + need > arena.size) return CE_E_UNSUPPORTED;
+      arena.p[i] = arena.base + arena.off;
+      arena.n[i] = need;
+      arena.off += need;
+      *out = arena.p[i];
+      return CE_OK;
+    }
     Buf& b = ws[i];
     const hipStream_t s = last;
     if (b.n < bytes) {
@@ -283,6 +336,7 @@ struct ce_ctx {
       *out = it->second;
       return CE_OK;
     }
+    if (noalloc) return CE_E_UNSUPPORTED;  // built with the plan; never allocated here
     const size_t elem = prec ? 16 : 8;
     std::vector<double> d(2 * (size_t)L);
     for (int k = 0; k < L; ++k) {
@@ -316,6 +370,7 @@ struct ce_ctx {
       *out = it->second;
       return CE_OK;
     }
+    if (noalloc) return CE_E_UNSUPPORTED;
     std::vector<double> d;
     int Ns = 1;
     for (int R : rad) {
@@ -693,6 +748,23 @@ hipStream_t as_stream(void* s) { return static_cast<hipStream_t>(s); }
 
 namespace {
 
+ce_status prebuild_tables(ce_ctx* ctx, const ce_plan* p);
+
+// A new plan's FFT tables are built with it (twiddles of every length its passes use), so the
+// pipeline calls on it find them ready; on failure the plan is freed (ctx locked by the caller).
+ce_status with_tables(ce_ctx* ctx, ce_status st, ce_plan** out) {
+  if (st != CE_OK) return st;
+  st = prebuild_tables(ctx, *out);
+  if (st != CE_OK) {
+    ce_plan* p = *out;
+    ctx->release(p->lam, p->bytes_lam);
+    ctx->release(p->sq, p->bytes_sq);
+    delete p;
+    *out = nullptr;
+  }
+  return st;
+}
+
 // Shared end of plan construction: the non-negativity check of eq. condition on the FP64
 // eigenvalue octant `lam` (dims O), then sqrt(lambda / M^d) in the plan precision.  Takes
 // ownership of lam and of spare (nullable, released here); on success the plan keeps lam.
@@ -792,6 +864,11 @@ ce_status ce_ctx_create(int device, size_t hbm_budget_bytes, ce_ctx** out) {
     CE_HIP(hipDeviceGetDefaultMemPool(&pool, device));
     uint64_t keep = UINT64_MAX;
     CE_HIP(hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &keep));
+  }
+  {
+    // the static scratch's address on this device, resolved at set-up
+    void* fixed = nullptr;
+    CE_TRY(fixed_scratch(device, &fixed));
   }
   void* f = nullptr;
   CE_TRY(ctx->alloc(&f, 16));
@@ -991,7 +1068,8 @@ ce_status ce_plan_embedding(ce_ctx* ctx, const ce_geometry* geom, const ce_xi* x
     std::swap(src, dst);
   }
   if (hipStreamSynchronize(s) != hipSuccess) return fail(CE_E_DEVICE);  // sigma2 has arrived
-  return finish_plan(ctx, plan, src, src == bufA ? bufB : bufA, O, neg_tol, sigma2, info, out, s);
+  return with_tables(ctx, finish_plan(ctx, plan, src, src == bufA ? bufB : bufA, O, neg_tol, sigma2, info, out, s),
+                     out);
 }
 
 ce_status ce_plan_periodic(ce_ctx* ctx, const ce_geometry* geom, int64_t box, const ce_xi* xi,
@@ -1104,7 +1182,7 @@ ce_status ce_plan_periodic(ce_ctx* ctx, const ce_geometry* geom, int64_t box, co
   double sigma2 = 0;
   for (size_t j = 0; j < svals.size(); ++j) sigma2 += mult[svals[j]] * pv[j] * inv_hd;
   sigma2 /= std::pow((double)box, nd);
-  return finish_plan(ctx, plan, lam, nullptr, O, neg_tol, sigma2, info, out, s);
+  return with_tables(ctx, finish_plan(ctx, plan, lam, nullptr, O, neg_tol, sigma2, info, out, s), out);
 }
 
 ce_status ce_xi_lag_octant(ce_ctx* ctx, const ce_geometry* geom, const ce_xi* xi, double* out, void* stream) {
@@ -1160,6 +1238,11 @@ ce_status setup_ffts(ce_ctx* ctx, const ce_plan* p, InverseSetup& s) {
     CE_TRY(build_fft(ctx, p->n[d], p->prec, s.fN[d]));
   }
   return CE_OK;
+}
+
+ce_status prebuild_tables(ce_ctx* ctx, const ce_plan* p) {
+  InverseSetup fs;
+  return setup_ffts(ctx, p, fs);
 }
 
 NoiseArgs noise_args(const ce_plan* p, uint64_t seed, uint32_t rid, uint64_t first_pair) {
@@ -1333,7 +1416,7 @@ ce_status pipeline_impl(ce_ctx* ctx, const ce_plan* plan, uint64_t seed, uint32_
   const size_t elem = plan->prec ? 16 : 8;
   const size_t relem = plan->prec ? 8 : 4;
   const int64_t npairs = (count + 1) / 2;
-  const int64_t cp = chunk_pairs(plan, npairs, kScratchCap);
+  const int64_t cp = ctx->noalloc ? std::min(ctx->noalloc_pairs, npairs) : chunk_pairs(plan, npairs, kScratchCap);
   void* acc = nullptr;
   CE_TRY(ctx->scratch(4, sizeof(unsigned long long) * (size_t)(2 * npairs), &acc));
   auto* ntot = static_cast<unsigned long long*>(acc);
@@ -1354,6 +1437,16 @@ ce_status pipeline_impl(ce_ctx* ctx, const ce_plan* plan, uint64_t seed, uint32_
     CE_HIP(hipStreamSynchronize(s));  // the host table goes out of scope
     th_dev = static_cast<const int64_t*>(p);
     nm = static_cast<int64_t*>(p) + (nbins + 1);
+  } else if (ctx->noalloc) {
+    // the shell table counted on the device into the call's scratch (no table is allocated)
+    ShellRule sr;
+    if (!shell_rule(plan->n, ndim, nbins, sr, plan->h)) return CE_E_UNSUPPORTED;
+    void* p = nullptr;
+    CE_TRY(ctx->scratch(11, sizeof(int64_t) * (size_t)nbins, &p));
+    nm = static_cast<int64_t*>(p);
+    const int32_t nn[3] = {plan->n[0], ndim >= 2 ? plan->n[1] : 1, ndim >= 3 ? plan->n[2] : 1};
+    CE_HIP(launch_zero_u64(reinterpret_cast<unsigned long long*>(nm), nbins, s));
+    CE_HIP(launch_shell_counts(nn, sr.T, sr.LL, nbins, nm, s));
   } else {
     CE_TRY(device_shells(ctx, plan->n, ndim, nbins, &nm, &km, plan->h));
   }
@@ -1989,6 +2082,54 @@ ce_status ce_pipeline_run(ce_ctx* ctx, const ce_plan* plan, uint64_t seed, uint3
   ctx->last = s;
   return pipeline_impl(ctx, plan, seed, request_id, first_realization, count, nbar, nbins, out_fields, out_delta,
                        out_counts, out_ntot, out_pk, out_cov, out_cnorm, nullptr, s);
+}
+
+ce_status ce_pipeline_run_noalloc(ce_ctx* ctx, const ce_plan* plan, uint64_t seed, uint32_t request_id,
+                                  uint64_t first_realization, int64_t count, double nbar, int32_t nbins,
+                                  void* out_fields, void* out_delta, int32_t* out_counts, int64_t* out_ntot,
+                                  double* out_pk, double* out_cov, double* out_cnorm, void* stream) {
+  CE_TRY(pipeline_check(ctx, plan, first_realization, count, nbar, nbins, out_pk));
+  std::lock_guard<std::mutex> lock(ctx->mu);
+  CE_HIP(hipSetDevice(ctx->device));
+  void* base = nullptr;
+  CE_TRY(fixed_scratch(ctx->device, &base));
+  // the pairs per chunk that fit the array: per call the N_tot accumulators (2 per pair) and the
+  // shell table; per pair the pass intermediates and the shell records of the binning pass
+  const int ndim = plan->ndim;
+  const size_t elem = plan->prec ? 16 : 8;
+  auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
+  const int64_t npairs = (count + 1) / 2;
+  const int64_t M1 = plan->M[1], M2 = ndim == 3 ? plan->M[2] : 1;
+  const int64_t y1 = (int64_t)plan->n[0] * M1 * M2;
+  const int64_t y2 = ndim == 3 ? (int64_t)plan->n[0] * plan->n[1] * M2 : 0;
+  const int Nl = plan->n[ndim - 1];
+  const int64_t W = 2 * (Nl / 2 + 1);
+  const int64_t hrow = survey_cells(plan) / Nl * W;
+  const int64_t Bb = ndim == 3 ? (int64_t)plan->n[1] * W : W;
+  std::vector<int> rad;
+  FftDesc f0;
+  if (!factor_length(plan->n[0], rad)) return CE_E_UNSUPPORTED;
+  f0.nst = (int)rad.size();
+  for (int i = 0; i < f0.nst; ++i) f0.rad[i] = rad[i];
+  int G = 1;
+  (void)bin_geom(ctx, plan->n[0], nbins, Bb, 1, 0, elem, mixed_radix(f0), &G);
+  const int64_t rec = (Bb + G - 1) / G * 2 * nbins;  // shell records per pair (doubles)
+  const size_t fixed = al(sizeof(unsigned long long) * 2 * (size_t)npairs) + al(sizeof(int64_t) * (size_t)nbins);
+  const size_t per_pair = elem * (size_t)(y1 + y2 + hrow) + sizeof(double) * (size_t)rec;
+  if (fixed + per_pair + 4 * 256 > kFixedScratchBytes) return CE_E_UNSUPPORTED;  // one pair does not fit
+  int64_t cp = (int64_t)((kFixedScratchBytes - fixed - 4 * 256) / per_pair);
+  cp = std::max<int64_t>(1, std::min(cp, npairs));
+  hipStream_t s = as_stream(stream);
+  ctx->last = s;
+  ctx->noalloc = true;
+  ctx->noalloc_pairs = cp;
+  ctx->arena = ce_ctx::Arena();
+  ctx->arena.base = static_cast<char*>(base);
+  ctx->arena.size = kFixedScratchBytes;
+  const ce_status st = pipeline_impl(ctx, plan, seed, request_id, first_realization, count, nbar, nbins, out_fields,
+                                     out_delta, out_counts, out_ntot, out_pk, out_cov, out_cnorm, nullptr, s);
+  ctx->noalloc = false;
+  return st;
 }
 
 ce_status ce_pipeline_run_edges(ce_ctx* ctx, const ce_plan* plan, const float* mask_f, uint64_t seed,

@@ -187,6 +187,9 @@ hipError_t launch_debug_philox(uint32_t k0, uint32_t k1, const uint32_t* ctr, in
                                hipStream_t s);
 hipError_t launch_debug_noise(int prec, const NoiseArgs& n, uint64_t pair, int64_t cells, void* out, hipStream_t s);
 hipError_t launch_zero_u64(unsigned long long* p, int64_t n, hipStream_t s);
+// N_b of the linear shells on the device (n: three sides, 1 for missing axes; T: the shell weights)
+hipError_t launch_shell_counts(const int32_t* n, const int64_t* T, int64_t LL, int nb, int64_t* counts,
+                               hipStream_t s);
 hipError_t launch_mask_sum(const float* mask, int64_t n, double* out, hipStream_t s);  // out: 257 doubles
 hipError_t launch_window_columns(int prec, const void* in, void* out, int64_t N0, int64_t C, hipStream_t s);
 // transformed lag tables (ce_xi.hip).  Quadrature of one axis of a quadrant of the cell-overlap

@@ -1077,6 +1077,35 @@ __global__ void __launch_bounds__(256) k_mask_sum_final(double* __restrict__ par
   if (threadIdx.x == 0) *out = red[0];
 }
 
+// N_b of the linear shells of a grid (the binning pass's integer rule: mode q~ is in shell s - 1 for
+// the smallest s >= 0 with s^2 LL >= sum_i T_i q~_i^2) by visiting every mode; integer atomics, so
+// the counts are exact in any order.  counts (nb) must start at zero.
+__global__ void k_shell_counts(int32_t n0, int32_t n1, int32_t n2, int64_t T0, int64_t T1, int64_t T2, int64_t LL,
+                               int nb, unsigned long long* __restrict__ counts) {
+  const int64_t total = (int64_t)n0 * n1 * n2;
+  for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < total;
+       idx += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t i2 = idx % n2, rest = idx / n2;
+    const int64_t i1 = rest % n1, i0 = rest / n1;
+    const int64_t q0 = i0 <= n0 / 2 ? i0 : i0 - n0, q1 = i1 <= n1 / 2 ? i1 : i1 - n1,
+                  q2 = i2 <= n2 / 2 ? i2 : i2 - n2;
+    const int64_t t = T0 * q0 * q0 + T1 * q1 * q1 + T2 * q2 * q2;
+    int64_t s = (int64_t)sqrt((double)t / (double)LL);
+    while (s > 0 && (s - 1) * (s - 1) * LL >= t) --s;
+    while (s * s * LL < t) ++s;
+    if (s >= 1 && s <= nb) atomicAdd(&counts[s - 1], 1ull);
+  }
+}
+
+hipError_t launch_shell_counts(const int32_t* n, const int64_t* T, int64_t LL, int nb, int64_t* counts,
+                               hipStream_t s) {
+  const int64_t total = (int64_t)n[0] * n[1] * n[2];
+  const int blocks = (int)std::min<int64_t>((total + 255) / 256, 4096);
+  hipLaunchKernelGGL(k_shell_counts, dim3(blocks), dim3(256), 0, s, n[0], n[1], n[2], T[0], T[1], T[2], LL, nb,
+                     reinterpret_cast<unsigned long long*>(counts));
+  return hipGetLastError();
+}
+
 __global__ void k_zero_u64(unsigned long long* p, int64_t n) {
   const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (i < n) p[i] = 0;
