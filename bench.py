@@ -203,6 +203,8 @@ def parse():
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-accuracy", action="store_true", help="skip the oracle comparison of one timed pair")
+    ap.add_argument("--skip-main", action="store_true",
+                    help="skip the headline step and its comparators (profiling of the other legs only)")
     ap.add_argument("--volume-steps", type=int, default=10, help="steps of the 3-D workload leg (0: skip it)")
     ap.add_argument("--no-graph", action="store_true", help="skip the captured-step (HIP graph) leg")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
@@ -658,25 +660,14 @@ def timed_workload(b, torch, ctx, w, name, steps, warmup, stream):
                 _plan=plan, _bufs=(pk_out, counts, ntot, cov, cnorm))
 
 
-def main():
-    args = parse()
-    world = int(os.environ.get("WORLD_SIZE", "1"))
-    if args.gpus != 1 or world != 1:
-        print("bench.py measures one GPU: the library has no multi-GPU path (realizations would shard across "
-              "GPUs with no exchange but the final shell sums); run with --gpus 1", file=sys.stderr)
-        sys.exit(2)
-
+def main_leg(args, b, torch, w, stream):
+    """The headline step (ce_pipeline_run of the workload), its oracle accuracy, the captured-graph
+    replay, the plain FP64 comparator and the counter calibration copies."""
     import numpy as np
-    import torch
-    from paper_1406_6072_amd import binding as b
-    from synth import workloads
-
-    w = workloads.WORKLOADS[args.workload]
     prec = b.F64 if w["precision"] == "f64" else b.F32
     n, h, nb, R, nbar = w["n"], w["h"], w["nbins"], w["realizations"], w["nbar"]
     dev = torch.device("cuda:0")
     ctx = b.ctx_create(0)
-    stream = torch.cuda.current_stream()
 
     if args.lines:
         for opt, v in zip((b.OPT_LINES_NOISE, b.OPT_LINES_INNER, b.OPT_LINES_LAST, b.OPT_LINES_BINS),
@@ -769,6 +760,30 @@ def main():
 
     plan.release()
     b.ctx_destroy(ctx)
+    return out
+
+
+def main():
+    args = parse()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU: the library has no multi-GPU path (realizations would shard across "
+              "GPUs with no exchange but the final shell sums); run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_1406_6072_amd import binding as b
+    from synth import workloads
+
+    w = workloads.WORKLOADS[args.workload]
+    prec = b.F64 if w["precision"] == "f64" else b.F32
+    n, h, nb, R, nbar = w["n"], w["h"], w["nbins"], w["realizations"], w["nbar"]
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream()
+    out = dict(metric=METRIC)
+    if not args.skip_main:
+        out = main_leg(args, b, torch, w, stream)
 
     if args.volume_steps and args.workload != "volume_3d":
         # the 3-D workload (256^3 survey in a 512^3 embedding, 8 realizations per step) timed the
@@ -790,6 +805,10 @@ def main():
         ctx = b.ctx_create(0)
         plan = b.plan_embedding(ctx, n, h, w["xi"], prec)
         mc = torch.empty(R * plan.cells, dtype=torch.int32, device=dev)
+        pk_out = torch.empty(R * nb, dtype=torch.float64, device=dev)
+        ntot = torch.empty(R, dtype=torch.int64, device=dev)
+        cov = torch.empty(nb * nb, dtype=torch.float64, device=dev)
+        cnorm = torch.empty(nb * nb, dtype=torch.float64, device=dev)
 
         def mstep(i, counts=None):
             b.pipeline_run_masked(ctx, plan, mask, w["seed"], w["request_id"], i * R * 2, R, nbar, nb, pk_out,
@@ -879,7 +898,8 @@ def main():
 
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_oracle_sample(w, args.cpu_seconds)
-        out["speedup_vs_cpu_oracle"] = round(value / out["cpu_baseline"]["value"], 1)
+        if "value" in out:
+            out["speedup_vs_cpu_oracle"] = round(out["value"] / out["cpu_baseline"]["value"], 1)
     print(json.dumps(out), flush=True)
 
 

@@ -24,10 +24,12 @@
  *  - Layouts are row-major with the last axis fastest.  A stack of `count`
  *    maps is count x N_0 x ... x N_{d-1}.  Realization r = 2j + s comes from
  *    pair j: s = 0 is the real part, s = 1 the imaginary part.
- *  - Supported: d = 2 or 3, every N_i even and >= 4, M_i a product of the
- *    primes 2, 3, 5, 7, 11, 13, 17, 19, 23, 29, 31 and at most 4096, each
- *    embedding with fewer than 2^32 cells.  Other sizes return
- *    CE_E_UNSUPPORTED.
+ *  - Supported: d = 2 or 3, every N_i even and >= 4, M_i = 2 N_i at most 4096
+ *    (any factorisation: powers of two in radices up to 16, the primes up to 31
+ *    in dedicated butterflies, larger primes in a generic prime stage), each
+ *    embedding with fewer than 2^32 cells; in FP64, a first periodic side whose
+ *    length is not a power of two is at most ~2400 (two of its lines must fit
+ *    one workgroup's 160 KB of LDS).  Other sizes return CE_E_UNSUPPORTED.
  */
 #ifndef CEFIELD_H
 #define CEFIELD_H

@@ -26,7 +26,6 @@ constexpr double kDefaultNegTol = 1e-13;
 constexpr size_t kLdsBudget = 80 * 1024;   // per workgroup: two workgroups fit one CU
 constexpr int kMaxSide = 4096;
 constexpr int kPoissonSteps = 4096;
-constexpr int kPrimes[] = {3, 5, 7, 11, 13, 17, 19, 23, 29, 31};
 
 #define CE_HIP(expr)                                   \
   do {                                                 \
@@ -57,13 +56,16 @@ bool factor_length(int L, std::vector<int>& rad) {
   rad.clear();
   if (L < 2 || L > kMaxSide) return false;
   int n = L;
-  std::vector<int> odd;
-  for (int p : kPrimes)
+  std::vector<int> odd;  // odd prime factors, ascending (any prime: those above 31 use the generic radix)
+  while (n % 2 == 0 && n > 1) n /= 2;
+  for (int p = 3; p * p <= n; p += 2)
     while (n % p == 0) {
       odd.push_back(p);
       n /= p;
     }
-  if (n & (n - 1)) return false;
+  if (n > 1) odd.push_back(n);
+  n = L;
+  for (int p : odd) n /= p;  // the power of two that remains
   int e = 0;
   while ((1 << e) < n) ++e;
   std::vector<int> p2;
@@ -460,14 +462,27 @@ bool bins_fit(int N, int nb, int prec) {
   return bin_pass_lds(g, N, nb, 1, elem) <= kMaxLdsBytes;
 }
 
+// Stage tables of a factorisation: span, quotient multiplier and twiddle offset per stage.
+void stage_layout(FftDesc& f) {
+  int Ns = 1, off = 0;
+  for (int s = 0; s < f.nst; ++s) {
+    f.ns[s] = Ns;
+    f.nsm[s] = Ns > 1 ? (uint32_t)((((uint64_t)1 << 32) + (uint64_t)Ns - 1) / (uint64_t)Ns) : 0u;
+    f.soff[s] = off;
+    if (Ns > 1) off += Ns * (f.rad[s] - 1);
+    Ns *= f.rad[s];
+  }
+}
+
 ce_status build_fft(ce_ctx* ctx, int L, int prec, FftDesc& f) {
   std::vector<int> rad;
   if (!factor_length(L, rad)) return CE_E_UNSUPPORTED;
   f.L = L;
   f.nst = (int)rad.size();
   for (int i = 0; i < f.nst; ++i) f.rad[i] = rad[i];
+  stage_layout(f);
   CE_TRY(ctx->twiddles(L, prec, &f.tw));
-  if ((L & (L - 1)) == 0) CE_TRY(ctx->stage_twiddles(L, prec, rad, &f.stw));
+  CE_TRY(ctx->stage_twiddles(L, prec, rad, &f.stw));
   return CE_OK;
 }
 
@@ -485,6 +500,24 @@ ce_status check_geometry(const ce_geometry* g) {
   }
   if (cells >= 4294967296.0) return CE_E_UNSUPPORTED;
   return CE_OK;
+}
+
+// Every pass of a plan fits one workgroup's LDS at its smallest shape: the noise pass holds two
+// lines of the first periodic axis (cells 2p and 2p + 1 share a generator call), every other
+// pass one line; mixed lengths need two buffers per line.
+bool passes_fit(const int* M, const int* n, int ndim, int prec) {
+  const size_t elem = prec ? 16 : 8;
+  auto line_bytes = [&](int L) {
+    std::vector<int> rad;
+    if (!factor_length(L, rad)) return (size_t)0;
+    bool mix = false;
+    for (int r : rad) mix |= (r & (r - 1)) != 0;
+    return (size_t)line_pitch_host(L, elem) * elem * (mix ? 2 : 1);
+  };
+  if (2 * line_bytes(M[0]) > kMaxLdsBytes) return false;
+  for (int d = 0; d < ndim; ++d)
+    if (line_bytes(M[d]) > kMaxLdsBytes || line_bytes(n[d]) > kMaxLdsBytes) return false;
+  return true;
 }
 
 ce_status check_xi(const ce_geometry* g, const ce_xi* xi) {
@@ -1005,6 +1038,14 @@ ce_status ce_plan_embedding(ce_ctx* ctx, const ce_geometry* geom, const ce_xi* x
   if (precision != CE_F32 && precision != CE_F64) return CE_E_INVALID;
   CE_TRY(check_geometry(geom));
   CE_TRY(check_xi(geom, xi));
+  {
+    int M[3] = {1, 1, 1}, nn[3] = {1, 1, 1};
+    for (int i = 0; i < geom->ndim; ++i) {
+      nn[i] = (int)geom->n[i];
+      M[i] = 2 * nn[i];
+    }
+    if (!passes_fit(M, nn, geom->ndim, precision == CE_F64 ? 1 : 0)) return CE_E_UNSUPPORTED;
+  }
   if (neg_tol < 0) neg_tol = kDefaultNegTol;
   std::lock_guard<std::mutex> lock(ctx->mu);
   CE_HIP(hipSetDevice(ctx->device));
@@ -1081,6 +1122,14 @@ ce_status ce_plan_periodic(ce_ctx* ctx, const ce_geometry* geom, int64_t box, co
   CE_TRY(check_xi(geom, xi));
   const int nd = geom->ndim;
   if (box < 2 || (box & 1)) return CE_E_INVALID;
+  {
+    int M[3] = {1, 1, 1}, nn[3] = {1, 1, 1};
+    for (int i = 0; i < nd; ++i) {
+      nn[i] = (int)geom->n[i];
+      M[i] = (int)std::min<int64_t>(box, kMaxSide);
+    }
+    if (!passes_fit(M, nn, nd, precision == CE_F64 ? 1 : 0)) return CE_E_UNSUPPORTED;
+  }
   for (int i = 0; i < nd; ++i) {
     if (geom->n[i] > box) return CE_E_INVALID;
     if (geom->h[i] != geom->h[0]) return CE_E_UNSUPPORTED;

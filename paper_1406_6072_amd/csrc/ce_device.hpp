@@ -295,11 +295,22 @@ __device__ __forceinline__ void stage_ct(cpx<T>* line, int lane, bool active, co
   __syncthreads();
 }
 
+// Butterfly j of a mixed-radix stage with span Ns: k = j mod Ns (the twiddle index) and the
+// output base (j / Ns) Ns R + k.  The quotient is umulhi(j, nsm), exact for j < 4096.
+__device__ __forceinline__ void stage_index(int j, int Ns, uint32_t nsm, int R, int& k, int& base) {
+  const int q = Ns > 1 ? (int)__umulhi((uint32_t)j, nsm) : j;
+  k = j - q * Ns;
+  base = q * Ns * R + k;
+}
+
 // Out-of-place Stockham stage (src -> dst LDS lines), any supported radix; one
-// butterfly at a time, so the register footprint is one radix.
+// butterfly at a time, so the register footprint is one radix.  The twiddles of
+// butterfly j are read as one contiguous vector: stw[k (R-1) + r - 1] =
+// exp(-2 pi i r k / (Ns R)) (stages with Ns > 1).
 template <typename T, int R, int S>
-__device__ __forceinline__ void pingpong_stage(const cpx<T>* src, cpx<T>* dst, int L, int Ns, int lane, int nlanes,
-                                               bool active, const cpx<T>* __restrict__ tw, int keep) {
+__device__ __forceinline__ void pingpong_stage(const cpx<T>* src, cpx<T>* dst, int L, int Ns, uint32_t nsm, int lane,
+                                               int nlanes, bool active, const cpx<T>* __restrict__ tw,
+                                               const cpx<T>* __restrict__ stw, int keep) {
   constexpr bool kPow2 = (R & (R - 1)) == 0;
   constexpr int H = (R - 1) / 2;
   const int nb = L / R;
@@ -318,17 +329,17 @@ __device__ __forceinline__ void pingpong_stage(const cpx<T>* src, cpx<T>* dst, i
       cpx<T> v[R];
 #pragma unroll
       for (int r = 0; r < R; ++r) v[r] = src[pidx(j + r * nb)];
-      const int k = j % Ns;
+      int k, base;
+      stage_index(j, Ns, nsm, R, k, base);
       if (Ns > 1) {
-        const int step = k * (L / (Ns * R));
+        const cpx<T>* w = stw + k * (R - 1);
 #pragma unroll
         for (int r = 1; r < R; ++r) {
-          cpx<T> w = tw[r * step];
-          if (S > 0) w.y = -w.y;
-          v[r] = c_mul(v[r], w);
+          cpx<T> t = w[r - 1];
+          if (S > 0) t.y = -t.y;
+          v[r] = c_mul(v[r], t);
         }
       }
-      const int base = (j / Ns) * Ns * R + k;
       if constexpr (kPow2) {
         Pow2Dft<R, S, T>::run(v);
 #pragma unroll
@@ -350,8 +361,9 @@ __device__ __forceinline__ void pingpong_stage(const cpx<T>* src, cpx<T>* dst, i
 // pair X_k, X_{R-k} by reading them back.  The register footprint is the (R - 1) / 2
 // cosines and sines plus a few accumulators, so no radix spills.
 template <typename T, int R, int S>
-__device__ __forceinline__ void pingpong_stage_lds(cpx<T>* src, cpx<T>* dst, int L, int Ns, int lane, int nlanes,
-                                                   bool active, const cpx<T>* __restrict__ tw, int keep) {
+__device__ __forceinline__ void pingpong_stage_lds(cpx<T>* src, cpx<T>* dst, int L, int Ns, uint32_t nsm, int lane,
+                                                   int nlanes, bool active, const cpx<T>* __restrict__ tw,
+                                                   const cpx<T>* __restrict__ stw, int keep) {
   constexpr int H = (R - 1) / 2;
   const int nb = L / R;
   T cs[H + 1], sn[H + 1];
@@ -366,14 +378,15 @@ __device__ __forceinline__ void pingpong_stage_lds(cpx<T>* src, cpx<T>* dst, int
   }
   if (active) {
     for (int j = lane; j < nb; j += nlanes) {
-      const int k = j % Ns;
-      const int step = k * (L / (Ns * R));
+      int k, base;
+      stage_index(j, Ns, nsm, R, k, base);
+      const cpx<T>* w = stw + k * (R - 1);
       auto twiddled = [&](int r) {
         cpx<T> x = src[pidx(j + r * nb)];
         if (Ns > 1 && r > 0) {
-          cpx<T> w = tw[r * step];
-          if (S > 0) w.y = -w.y;
-          x = c_mul(x, w);
+          cpx<T> t = w[r - 1];
+          if (S > 0) t.y = -t.y;
+          x = c_mul(x, t);
         }
         return x;
       };
@@ -387,7 +400,6 @@ __device__ __forceinline__ void pingpong_stage_lds(cpx<T>* src, cpx<T>* dst, int
         src[pidx(j + n * nb)] = sp;
         src[pidx(j + (R - n) * nb)] = c_sub(p, q);
       }
-      const int base = (j / Ns) * Ns * R + k;
       if (base < keep) dst[pidx(base)] = x0;
 #pragma unroll
       for (int kk = 1; kk <= H; ++kk) {
@@ -411,6 +423,70 @@ __device__ __forceinline__ void pingpong_stage_lds(cpx<T>* src, cpx<T>* dst, int
         if (o2 < keep) dst[pidx(o2)] = c_sub(a, ib);
         // keep the sums in LDS: no hoisting of the reads above into registers
         __asm__ volatile("" ::: "memory");
+      }
+    }
+  }
+  __syncthreads();
+}
+
+// The same for any odd prime R known only at run time (the primes above 31): the direct
+// O(R^2) DFT of the pair sums and differences in the butterfly's own LDS slots; the angle
+// 2 pi m / R of each term comes from the line's root table, tw[m L / R], with m = n kk mod R
+// advanced incrementally (the index is uniform over the wave).
+template <typename T, int S>
+__device__ __forceinline__ void pingpong_stage_generic(cpx<T>* src, cpx<T>* dst, int L, int R, int Ns, uint32_t nsm,
+                                                       int lane, int nlanes, bool active,
+                                                       const cpx<T>* __restrict__ tw, const cpx<T>* __restrict__ stw,
+                                                       int keep) {
+  const int H = (R - 1) / 2;
+  const int nb = L / R;
+  const int Lr = L / R;
+  if (active) {
+    for (int j = lane; j < nb; j += nlanes) {
+      int k, base;
+      stage_index(j, Ns, nsm, R, k, base);
+      const cpx<T>* w = stw + k * (R - 1);
+      auto twiddled = [&](int r) {
+        cpx<T> x = src[pidx(j + r * nb)];
+        if (Ns > 1 && r > 0) {
+          cpx<T> t = w[r - 1];
+          if (S > 0) t.y = -t.y;
+          x = c_mul(x, t);
+        }
+        return x;
+      };
+      const cpx<T> v0 = twiddled(0);
+      cpx<T> x0 = v0;
+      for (int n = 1; n <= H; ++n) {
+        const cpx<T> p = twiddled(n), q = twiddled(R - n);
+        const cpx<T> sp = c_add(p, q);
+        x0 = c_add(x0, sp);
+        src[pidx(j + n * nb)] = sp;
+        src[pidx(j + (R - n) * nb)] = c_sub(p, q);
+      }
+      if (base < keep) dst[pidx(base)] = x0;
+      for (int kk = 1; kk <= H; ++kk) {
+        cpx<T> a = v0, b = {T(0), T(0)};
+        int m = 0;
+        for (int n = 1; n <= H; ++n) {
+          m += kk;
+          if (m >= R) m -= R;
+          // cos / sin (2 pi m / R) from the root exp(-2 pi i m' / R), m' = min(m, R - m)
+          const bool lo = m <= H;
+          const cpx<T> r = tw[(lo ? m : R - m) * Lr];
+          const T c = r.x;
+          const T sg = lo ? -r.y : r.y;
+          const cpx<T> sp = src[pidx(j + n * nb)];
+          const cpx<T> dm = src[pidx(j + (R - n) * nb)];
+          a.x += sp.x * c;
+          a.y += sp.y * c;
+          b.x += dm.x * sg;
+          b.y += dm.y * sg;
+        }
+        const cpx<T> ib = c_rot<S>(b);
+        const int o1 = base + kk * Ns, o2 = base + (R - kk) * Ns;
+        if (o1 < keep) dst[pidx(o1)] = c_add(a, ib);
+        if (o2 < keep) dst[pidx(o2)] = c_sub(a, ib);
       }
     }
   }
@@ -484,30 +560,36 @@ __device__ __forceinline__ cpx<T>* line_fft(cpx<T>* a, cpx<T>* b, const FftDesc&
   } else {
     cpx<T>* src = a;
     cpx<T>* dst = b;
+    const cpx<T>* __restrict__ stw0 = static_cast<const cpx<T>*>(f.stw);
     for (int s = 0; s < f.nst; ++s) {
       const int R = f.rad[s];
       const int kp = (s == f.nst - 1) ? keep : L;
+      const uint32_t nm = f.nsm[s];
+      const cpx<T>* sw = stw0 + f.soff[s];
       // MIX 1 instantiates only the small radices, so its register footprint is that of
-      // radix 8; MIX 2 adds the primes 11..31
+      // radix 8; MIX 2 adds the primes 11..31 and the generic prime stage
       switch (R) {
-        case 2: pingpong_stage<T, 2, S>(src, dst, L, Ns, lane, nlanes, active, tw, kp); break;
-        case 4: pingpong_stage<T, 4, S>(src, dst, L, Ns, lane, nlanes, active, tw, kp); break;
-        case 8: pingpong_stage<T, 8, S>(src, dst, L, Ns, lane, nlanes, active, tw, kp); break;
-        case 3: pingpong_stage<T, 3, S>(src, dst, L, Ns, lane, nlanes, active, tw, kp); break;
-        case 5: pingpong_stage<T, 5, S>(src, dst, L, Ns, lane, nlanes, active, tw, kp); break;
+        case 2: pingpong_stage<T, 2, S>(src, dst, L, Ns, nm, lane, nlanes, active, tw, sw, kp); break;
+        case 4: pingpong_stage<T, 4, S>(src, dst, L, Ns, nm, lane, nlanes, active, tw, sw, kp); break;
+        case 8: pingpong_stage<T, 8, S>(src, dst, L, Ns, nm, lane, nlanes, active, tw, sw, kp); break;
+        case 3: pingpong_stage<T, 3, S>(src, dst, L, Ns, nm, lane, nlanes, active, tw, sw, kp); break;
+        case 5: pingpong_stage<T, 5, S>(src, dst, L, Ns, nm, lane, nlanes, active, tw, sw, kp); break;
         default:
           if constexpr (MIX == 1) {
-            pingpong_stage<T, 7, S>(src, dst, L, Ns, lane, nlanes, active, tw, kp);
+            pingpong_stage<T, 7, S>(src, dst, L, Ns, nm, lane, nlanes, active, tw, sw, kp);
           } else {
             switch (R) {
-              case 7: pingpong_stage<T, 7, S>(src, dst, L, Ns, lane, nlanes, active, tw, kp); break;
-              case 11: pingpong_stage_lds<T, 11, S>(src, dst, L, Ns, lane, nlanes, active, tw, kp); break;
-              case 13: pingpong_stage_lds<T, 13, S>(src, dst, L, Ns, lane, nlanes, active, tw, kp); break;
-              case 17: pingpong_stage_lds<T, 17, S>(src, dst, L, Ns, lane, nlanes, active, tw, kp); break;
-              case 19: pingpong_stage_lds<T, 19, S>(src, dst, L, Ns, lane, nlanes, active, tw, kp); break;
-              case 23: pingpong_stage_lds<T, 23, S>(src, dst, L, Ns, lane, nlanes, active, tw, kp); break;
-              case 29: pingpong_stage_lds<T, 29, S>(src, dst, L, Ns, lane, nlanes, active, tw, kp); break;
-              default: pingpong_stage_lds<T, 31, S>(src, dst, L, Ns, lane, nlanes, active, tw, kp); break;
+              case 7: pingpong_stage<T, 7, S>(src, dst, L, Ns, nm, lane, nlanes, active, tw, sw, kp); break;
+              case 11: pingpong_stage_lds<T, 11, S>(src, dst, L, Ns, nm, lane, nlanes, active, tw, sw, kp); break;
+              case 13: pingpong_stage_lds<T, 13, S>(src, dst, L, Ns, nm, lane, nlanes, active, tw, sw, kp); break;
+              case 17: pingpong_stage_lds<T, 17, S>(src, dst, L, Ns, nm, lane, nlanes, active, tw, sw, kp); break;
+              case 19: pingpong_stage_lds<T, 19, S>(src, dst, L, Ns, nm, lane, nlanes, active, tw, sw, kp); break;
+              case 23: pingpong_stage_lds<T, 23, S>(src, dst, L, Ns, nm, lane, nlanes, active, tw, sw, kp); break;
+              case 29: pingpong_stage_lds<T, 29, S>(src, dst, L, Ns, nm, lane, nlanes, active, tw, sw, kp); break;
+              case 31: pingpong_stage_lds<T, 31, S>(src, dst, L, Ns, nm, lane, nlanes, active, tw, sw, kp); break;
+              default:
+                pingpong_stage_generic<T, S>(src, dst, L, R, Ns, nm, lane, nlanes, active, tw, sw, kp);
+                break;
             }
           }
           break;

@@ -19,8 +19,14 @@ struct FftDesc {
   int32_t L = 0;
   int32_t nst = 0;
   int32_t rad[kMaxStages] = {};
+  // per stage s: the span Ns (product of the radices before it), the multiplier of the exact
+  // quotient j / Ns = umulhi(j, nsm) for j < 4096 (nsm = ceil(2^32 / Ns); unused when Ns = 1), and
+  // the offset of the stage's twiddles in stw (complex elements; stages with Ns > 1)
+  int32_t ns[kMaxStages] = {};
+  uint32_t nsm[kMaxStages] = {};
+  int32_t soff[kMaxStages] = {};
   const void* tw = nullptr;    // roots exp(-2 pi i k / L), k < L
-  const void* stw = nullptr;   // power-of-two lengths: per-stage twiddles, see ce_device.hpp
+  const void* stw = nullptr;   // per-stage twiddles exp(-2 pi i r k / (Ns R)), see ce_device.hpp
 };
 
 // A batch of line transforms.  Lines are (a, b), a in [0, A), b in [0, B); line

@@ -41,18 +41,30 @@ def test_status_strings():
 
 
 @pytest.mark.parametrize("L,prod", [(2048, 2048), (1024, 1024), (512, 512), (96, 96), (992, 992), (160, 160),
-                                    (4096, 4096), (64, 64), (6, 6)])
+                                    (4096, 4096), (64, 64), (6, 6), (1184, 1184), (4064, 4064), (3998, 3998),
+                                    (74, 74), (2 * 2039, 4078)])
 def test_fft_factors_cover_length(L, prod):
+    """Every even length up to 4096 factors: powers of two in radices 2..16, primes up to 31 in their own
+    butterflies, larger primes (37 .. 2039) in the generic prime stage."""
     from paper_1406_6072_amd import binding
     r = binding.fft_factors(L)
     assert int(np.prod(r)) == prod
-    assert all(x in (2, 3, 4, 5, 7, 8, 11, 13, 16, 17, 19, 23, 29, 31) for x in r)
+    for x in r:
+        assert x in (2, 4, 8, 16) or all(x % p for p in range(2, int(x ** 0.5) + 1)), (L, r)
 
 
-def test_fft_factors_reject_large_prime():
+def test_every_even_side_is_a_supported_length():
     from paper_1406_6072_amd import binding
-    with pytest.raises(binding.CeError):
-        binding.fft_factors(2 * 37)
+    for L in range(2, 4097, 2):
+        r = binding.fft_factors(L)
+        assert int(np.prod(r)) == L
+
+
+def test_fft_factors_reject_out_of_range():
+    from paper_1406_6072_amd import binding
+    for L in (1, 4098, 8192):
+        with pytest.raises(binding.CeError):
+            binding.fft_factors(L)
 
 
 @pytest.mark.parametrize("n,nb", [((64, 64), 32), ((16, 16, 16), 8), ((1024, 1024), 128), ((12, 12), 5),

@@ -144,6 +144,11 @@ FIELD_CASES = [
     ("vol_3d_f64", (16, 12, 20), (1.0, 1.0, 1.0), dict(kind="exp", sigma2=0.8, a=1.5), 1, 0, 3),
     ("vol_3d_f32", (32, 32, 32), (1.0, 1.0, 1.0), dict(kind="powexp", sigma2=2.0, r0=1.5, gamma=1.8, rc=100.0),
      0, 0, 4),
+    # primes above 31 (the generic radix): 37 (592 = 16 x 37, 1184 = 32 x 37), 127 (2032, 4064)
+    ("prime37_2d_f32", (592, 74), (1.0, 1.0), dict(kind="exp", sigma2=1.0, a=4.0), 0, 2, 3),
+    ("prime37_2d_f64", (74, 54), (1.0, 1.0), dict(kind="exp", sigma2=1.0, a=3.0), 1, 0, 2),
+    ("prime127_2d_f32", (2032, 16), (1.0, 1.0), dict(kind="exp", sigma2=1.0, a=4.0), 0, 0, 2),
+    ("prime41_3d_f32", (82, 20, 24), (1.0, 1.0, 1.0), dict(kind="exp", sigma2=0.8, a=1.5), 0, 0, 2),
 ]
 
 
@@ -194,7 +199,8 @@ def test_lognormal_poisson_parity(ce, prec, first, masked):
 
 @pytest.mark.parametrize("prec", [1, 0])
 @pytest.mark.parametrize("n,nb", [((64, 64), 32), ((16, 16, 16), 8), ((48, 48), 12), ((58, 58), 14),
-                                  ((26, 26, 26), 6), ((48, 80), 12), ((40, 24, 32), 6), ((64, 26), 10)])
+                                  ((26, 26, 26), 6), ((48, 80), 12), ((40, 24, 32), 6), ((64, 26), 10),
+                                  ((74, 118), 12), ((254, 82), 16)])
 def test_pk_field_parity(ce, prec, n, nb):
     b, ctx = ce
     xi = dict(kind="exp", sigma2=1.0, a=2.0)
@@ -264,6 +270,8 @@ PIPE_CASES = [((64, 64), dict(kind="exp", sigma2=0.5, a=8.0), 1, 32, 7),
               ((16, 16, 16), dict(kind="exp", sigma2=0.8, a=1.5), 0, 8, 3),
               ((48, 48), dict(kind="exp", sigma2=1.0, a=3.0), 1, 12, 4),
               ((38, 38), dict(kind="exp", sigma2=1.0, a=3.0), 0, 10, 4),
+              ((74, 94), dict(kind="exp", sigma2=1.0, a=3.0), 0, 12, 4),     # primes 37, 47
+              ((106, 74), dict(kind="exp", sigma2=1.0, a=3.0), 1, 12, 3),    # primes 53, 37
               ((22, 22, 22), dict(kind="exp", sigma2=0.8, a=1.5), 1, 6, 2),
               # hyperrectangular surveys (square / cubic cells)
               ((64, 96), dict(kind="exp", sigma2=0.8, a=3.0), 0, 16, 5),
