@@ -157,7 +157,11 @@ typedef enum {
   /* Schedule: with CE_OPT_NOISE_ORDER 0, the noise pass orders its workgroups in blocks of this
    * many pairs (1 .. 65536, default 1): inside a block the workgroups of one line group for the
    * block's pairs run together, so the sqrt(lambda) lines they read are fetched once per block. */
-  CE_OPT_NOISE_BLOCK = 8
+  CE_OPT_NOISE_BLOCK = 8,
+  /* Schedule: ce_pipeline_run_batch runs its groups of different shapes concurrently on up to
+   * this many internal streams (1 .. 16, default 4), each with its own scratch, forked from and
+   * joined back into the call's stream. */
+  CE_OPT_BATCH_LANES = 9
 } ce_option;
 ce_status ce_ctx_set_option(ce_ctx* ctx, int32_t option, int64_t value);
 

@@ -269,6 +269,7 @@ OPT_UNPRUNED = 1
 CIC_MAX_BINS = 4096
 OPT_LINES_NOISE, OPT_LINES_INNER, OPT_LINES_LAST, OPT_LINES_BINS, OPT_NOISE_ORDER, OPT_BIN_LDS = 2, 3, 4, 5, 6, 7
 OPT_NOISE_BLOCK = 8
+OPT_BATCH_LANES = 9
 
 
 def ctx_set_option(ctx, option, value):
@@ -569,34 +570,48 @@ def pipeline_run_prepared(ctx, plan, mask, prepared, seed, request_id, first_rea
            "ce_pipeline_run_prepared")
 
 
+class PreparedBatch:
+    """The C item array of a batch, marshalled once (tensors are checked and their addresses
+    taken here); pipeline_run_batch accepts it in place of the item list, so repeated calls
+    on the same buffers cost one C call each.  The tensors must outlive the object."""
+
+    def __init__(self, items):
+        import numpy as np
+        self.n = len(items)
+        self.arr = (BatchItem * max(self.n, 1))()
+        self.keep = []
+        for k, it in enumerate(items):
+            plan, count, nb = it["plan"], int(it["count"]), int(it["nbins"])
+            a = self.arr[k]
+            a.plan = plan.handle
+            a.seed, a.request_id = int(it.get("seed", 0)), int(it.get("request_id", 0))
+            a.first_realization, a.count, a.nbar, a.nbins = int(it.get("first_realization", 0)), count, \
+                float(it["nbar"]), nb
+            a.out_pk = _ptr(it["out_pk"], torch.float64, count * nb, "out_pk")
+            a.out_counts = _ptr(it.get("out_counts"), torch.int32, count * plan.cells, "out_counts")
+            a.out_ntot = _ptr(it.get("out_ntot"), torch.int64, count, "out_ntot")
+            a.out_cov = _ptr(it.get("out_cov"), torch.float64, nb * nb, "out_cov")
+            a.out_cnorm = _ptr(it.get("out_cnorm"), torch.float64, nb * nb, "out_cnorm")
+            a.out_fields = _ptr(it.get("out_fields"), plan.dtype, count * plan.cells, "out_fields")
+            a.out_delta = _ptr(it.get("out_delta"), plan.dtype, count * plan.cells, "out_delta")
+            if it.get("edges") is not None:
+                e = np.ascontiguousarray(it["edges"], dtype=np.float64)
+                if e.size != nb + 1:
+                    raise ValueError("edges must hold nbins + 1 values")
+                self.keep.append(e)
+                a.kedges = e.ctypes.data
+
+
+def prepare_batch(items):
+    return PreparedBatch(items)
+
+
 def pipeline_run_batch(ctx, items, stream=None):
-    """items: dicts with plan, seed, request_id, first_realization, count, nbar, nbins, out_pk and
-    optional out_counts, out_ntot, out_cov, out_cnorm, out_fields, out_delta (device tensors) and
-    edges (host sequence of nbins + 1 shell edges)."""
-    import numpy as np
-    arr = (BatchItem * max(len(items), 1))()
-    keep = []
-    for k, it in enumerate(items):
-        plan, count, nb = it["plan"], int(it["count"]), int(it["nbins"])
-        a = arr[k]
-        a.plan = plan.handle
-        a.seed, a.request_id = int(it.get("seed", 0)), int(it.get("request_id", 0))
-        a.first_realization, a.count, a.nbar, a.nbins = int(it.get("first_realization", 0)), count, \
-            float(it["nbar"]), nb
-        a.out_pk = _ptr(it["out_pk"], torch.float64, count * nb, "out_pk")
-        a.out_counts = _ptr(it.get("out_counts"), torch.int32, count * plan.cells, "out_counts")
-        a.out_ntot = _ptr(it.get("out_ntot"), torch.int64, count, "out_ntot")
-        a.out_cov = _ptr(it.get("out_cov"), torch.float64, nb * nb, "out_cov")
-        a.out_cnorm = _ptr(it.get("out_cnorm"), torch.float64, nb * nb, "out_cnorm")
-        a.out_fields = _ptr(it.get("out_fields"), plan.dtype, count * plan.cells, "out_fields")
-        a.out_delta = _ptr(it.get("out_delta"), plan.dtype, count * plan.cells, "out_delta")
-        if it.get("edges") is not None:
-            e = np.ascontiguousarray(it["edges"], dtype=np.float64)
-            if e.size != nb + 1:
-                raise ValueError("edges must hold nbins + 1 values")
-            keep.append(e)
-            a.kedges = e.ctypes.data
-    _check(_pipeline_batch(ctx, arr, len(items), _stream(stream)), "ce_pipeline_run_batch")
+    """items: a PreparedBatch, or dicts with plan, seed, request_id, first_realization, count,
+    nbar, nbins, out_pk and optional out_counts, out_ntot, out_cov, out_cnorm, out_fields,
+    out_delta (device tensors) and edges (host sequence of nbins + 1 shell edges)."""
+    pb = items if isinstance(items, PreparedBatch) else PreparedBatch(items)
+    _check(_pipeline_batch(ctx, pb.arr, pb.n, _stream(stream)), "ce_pipeline_run_batch")
 
 
 def pipeline_graph_create(ctx, plan, seed, request_id, first_realization, count, nbar, nbins, out_pk,

@@ -231,6 +231,12 @@ struct ce_ctx {
   int lines_cap[4] = {0, 0, 0, 0};  // max lines per workgroup per pass kind (0 = automatic)
   int noise_item_minor = 0;         // noise pass tile order (0: line groups of one pair adjacent; measured faster)
   int noise_block = 1;              // noise pass: pairs per block of the item-major order
+  // batched pipeline: groups of different shapes run concurrently on up to batch_lanes
+  // sub-contexts (own scratch and stream), forked from and joined into the caller's stream
+  int batch_lanes = 4;
+  std::vector<ce_ctx*> lanes;
+  hipEvent_t fork = nullptr;    // recorded on the caller's stream once the batch tables are copied
+  hipEvent_t joined = nullptr;  // (lane sub-contexts) recorded after the lane's last group
   size_t bin_lds = kLdsBudget;      // LDS budget of a binning-pass workgroup
   std::vector<ProfRec> pending;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> pool;
@@ -925,6 +931,10 @@ void ce_ctx_destroy(ce_ctx* ctx) {
   if (!ctx) return;
   (void)hipSetDevice(ctx->device);
   (void)hipDeviceSynchronize();
+  for (ce_ctx* lc : ctx->lanes) ce_ctx_destroy(lc);
+  ctx->lanes.clear();
+  if (ctx->fork) (void)hipEventDestroy(ctx->fork);
+  if (ctx->joined) (void)hipEventDestroy(ctx->joined);
   for (auto& b : ctx->ws)
     if (b.p) (void)hipFreeAsync(b.p, nullptr);
   (void)hipDeviceSynchronize();
@@ -944,6 +954,7 @@ void ce_ctx_destroy(ce_ctx* ctx) {
 ce_status ce_ctx_trim(ce_ctx* ctx) {
   if (!ctx) return CE_E_INVALID;
   std::lock_guard<std::mutex> lock(ctx->mu);
+  for (ce_ctx* lc : ctx->lanes) CE_TRY(ce_ctx_trim(lc));
   CE_HIP(hipSetDevice(ctx->device));
   bool any = false;
   for (auto& b : ctx->ws) any |= b.p != nullptr;
@@ -974,6 +985,15 @@ ce_status ce_ctx_profile_read(ce_ctx* ctx, int32_t max, char* names, double* tot
   std::lock_guard<std::mutex> lock(ctx->mu);
   CE_HIP(hipSetDevice(ctx->device));
   ctx->prof_resolve();
+  for (ce_ctx* lc : ctx->lanes) {  // kernels the batch lanes ran for this context
+    lc->prof_resolve();
+    for (auto& kv : lc->agg) {
+      auto& e = ctx->agg[kv.first];
+      e.first += kv.second.first;
+      e.second += kv.second.second;
+    }
+    lc->agg.clear();
+  }
   int32_t i = 0;
   for (auto& kv : ctx->agg) {
     if (i >= max) break;
@@ -1012,6 +1032,10 @@ ce_status ce_ctx_set_option(ce_ctx* ctx, int32_t option, int64_t value) {
       if (value < 1 || value > 65536) return CE_E_INVALID;
       ctx->noise_block = (int)value;
       return CE_OK;
+    case CE_OPT_BATCH_LANES:
+      if (value < 1 || value > 16) return CE_E_INVALID;
+      ctx->batch_lanes = (int)value;
+      return CE_OK;
     default: return CE_E_INVALID;
   }
 }
@@ -1023,6 +1047,8 @@ ce_status ce_ctx_check(ce_ctx* ctx, void* stream) {
   uint32_t f = 0;
   CE_HIP(hipMemcpyAsync(&f, ctx->flags, sizeof(f), hipMemcpyDeviceToHost, s));
   CE_HIP(hipStreamSynchronize(s));
+  for (ce_ctx* lc : ctx->lanes)  // the batch lanes' flags (their work was joined into the caller's stream)
+    if (ce_ctx_check(lc, lc->own) == CE_E_SAMPLER) f |= 1u;
   if (f) {
     CE_HIP(hipMemsetAsync(ctx->flags, 0, sizeof(uint32_t), s));
     CE_HIP(hipStreamSynchronize(s));
@@ -1679,16 +1705,100 @@ ce_status pipeline_check(ce_ctx* ctx, const ce_plan* plan, uint64_t first_realiz
 
 // The batched pipeline: items grouped by (ndim, N, h, precision, nbins); each group runs the
 // fused passes once over all its pairs with per-pair descriptors.
+// A group of batch items sharing (ndim, sides, periodic sides, cell sides, precision, shells, user
+// edges): every pass runs as one launch over the group's pairs.
+struct Group {
+  std::vector<int64_t> idx;
+  int64_t pairs = 0, covs = 0;
+  size_t off_desc = 0, off_slot = 0, off_cov = 0, off_th = 0;
+  std::vector<int64_t> tab;  // user shells: thresholds (nbins + 1) then N_b (nbins)
+};
+using GroupKey = std::tuple<int, int, int, int, int, int, int, std::array<double, 3>, int, int, std::vector<double>>;
+
+// The sub-contexts of a context's batch lanes (created on first use, same device and schedule).
+ce_status ensure_lanes(ce_ctx* ctx, int nl) {
+  if (!ctx->fork) CE_HIP(hipEventCreateWithFlags(&ctx->fork, hipEventDisableTiming));
+  while ((int)ctx->lanes.size() < nl) {
+    ce_ctx* lc = nullptr;
+    CE_TRY(ce_ctx_create(ctx->device, 0, &lc));
+    if (hipEventCreateWithFlags(&lc->joined, hipEventDisableTiming) != hipSuccess) {
+      ce_ctx_destroy(lc);
+      return CE_E_DEVICE;
+    }
+    ctx->lanes.push_back(lc);
+  }
+  for (ce_ctx* lc : ctx->lanes) {
+    std::copy(std::begin(ctx->lines_cap), std::end(ctx->lines_cap), std::begin(lc->lines_cap));
+    lc->noise_item_minor = ctx->noise_item_minor;
+    lc->noise_block = ctx->noise_block;
+    lc->bin_lds = ctx->bin_lds;
+    lc->prof = ctx->prof;
+  }
+  return CE_OK;
+}
+
+// The fused passes of one group on context c and stream s; d is the device table area.
+ce_status run_batch_group(ce_ctx* c, const ce_batch_item* items, Group& g, const GroupKey& key, const char* d,
+                          hipStream_t s) {
+  const ce_plan* plan = items[g.idx[0]].plan;
+  const int nbins = std::get<9>(key);
+  const auto* ddesc = reinterpret_cast<const PairDesc*>(d + g.off_desc);
+  const auto* dslot = reinterpret_cast<const SlotOut*>(d + g.off_slot);
+  InverseSetup fs;
+  CE_TRY(setup_ffts(c, plan, fs));
+  const int ndim = plan->ndim;
+  const int64_t ncells = survey_cells(plan);
+  const int Nl = plan->n[ndim - 1];
+  const int W = 2 * (Nl / 2 + 1);
+  const int64_t rows = ncells / Nl;
+  const size_t elem = plan->prec ? 16 : 8;
+  const int64_t npairs = g.pairs;
+  const int64_t cp = chunk_pairs(plan, npairs, kScratchCap);
+  void* acc = nullptr;
+  CE_TRY(c->scratch(4, sizeof(unsigned long long) * (size_t)(2 * npairs), &acc));
+  auto* ntot = static_cast<unsigned long long*>(acc);
+  CE_HIP(launch_zero_u64(ntot, 2 * npairs, s));
+  int64_t* nm = nullptr;
+  const int64_t* th = nullptr;
+  if (!g.tab.empty()) {
+    th = reinterpret_cast<const int64_t*>(d + g.off_th);
+    nm = reinterpret_cast<int64_t*>(const_cast<char*>(d) + g.off_th) + (nbins + 1);
+  } else {
+    const std::vector<double>* km = nullptr;
+    CE_TRY(device_shells(c, plan->n, ndim, nbins, &nm, &km, plan->h));
+  }
+  const double norm = cell_volume(plan->h, ndim) / (double)ncells;
+  for (int64_t j = 0; j < npairs; j += cp) {
+    const int64_t np = std::min(cp, npairs - j);
+    void* H = nullptr;
+    CE_TRY(c->scratch(2, elem * (size_t)(np * rows * W), &H));
+    RowEpi e;
+    e.mode = 2;
+    e.ncells = ncells;
+    e.count = 2 * np;
+    e.ntot = ntot + 2 * j;
+    e.flags = c->flags;
+    e.inv = c->inv;
+    e.fwd = fs.fN[ndim - 1];
+    e.H = H;
+    e.H_item = rows * W;
+    CE_TRY(run_inverse(c, plan, fs, 0, 0, 0, np, e, s, nullptr, ddesc + j));
+    double* partials = nullptr;
+    int64_t ngroups = 0;
+    CE_TRY(run_forward_bins(c, ndim, plan->n, plan->prec, np, H, nbins, &partials, &ngroups, s, nullptr, th,
+                            plan->h));
+    CE_PROF(c, "bin_reduce", s,
+            launch_bin_reduce(partials, np, ngroups, nbins, 2 * np, nm, norm, 1, ntot + 2 * j, dslot + 2 * j,
+                              (double)ncells, nullptr, c->flags, s));
+  }
+  if (g.covs)
+    CE_PROF(c, "covariance", s,
+            launch_covariance_batch(reinterpret_cast<const CovItem*>(d + g.off_cov), g.covs, nbins, s));
+  return CE_OK;
+}
+
 ce_status pipeline_batch_impl(ce_ctx* ctx, const ce_batch_item* items, int64_t n, hipStream_t s) {
-  struct Group {
-    std::vector<int64_t> idx;
-    int64_t pairs = 0, covs = 0;
-    size_t off_desc = 0, off_slot = 0, off_cov = 0, off_th = 0;
-    std::vector<int64_t> tab;  // user shells: thresholds (nbins + 1) then N_b (nbins)
-  };
-  // group key: (ndim, sides, periodic sides, cell sides, precision, shells, user edges)
-  std::map<std::tuple<int, int, int, int, int, int, int, std::array<double, 3>, int, int, std::vector<double>>, Group>
-      groups;
+  std::map<GroupKey, Group> groups;
   for (int64_t i = 0; i < n; ++i) {
     const ce_batch_item& it = items[i];
     if (!it.plan) return CE_E_INVALID;
@@ -1788,64 +1898,57 @@ ce_status pipeline_batch_impl(ce_ctx* ctx, const ce_batch_item* items, int64_t n
   }
   CE_HIP(hipMemcpyAsync(dtab, ctx->pin, bytes, hipMemcpyHostToDevice, s));
   CE_HIP(hipEventRecord(ctx->staged, s));
-  for (auto& kv : groups) {
-    Group& g = kv.second;
-    const ce_plan* plan = items[g.idx[0]].plan;
-    const int nbins = std::get<9>(kv.first);
-    const auto* ddesc = reinterpret_cast<const PairDesc*>(d + g.off_desc);
-    const auto* dslot = reinterpret_cast<const SlotOut*>(d + g.off_slot);
-    InverseSetup fs;
-    CE_TRY(setup_ffts(ctx, plan, fs));
-    const int ndim = plan->ndim;
-    const int64_t ncells = survey_cells(plan);
-    const int Nl = plan->n[ndim - 1];
-    const int W = 2 * (Nl / 2 + 1);
-    const int64_t rows = ncells / Nl;
-    const size_t elem = plan->prec ? 16 : 8;
-    const int64_t npairs = g.pairs;
-    const int64_t cp = chunk_pairs(plan, npairs, kScratchCap);
-    void* acc = nullptr;
-    CE_TRY(ctx->scratch(4, sizeof(unsigned long long) * (size_t)(2 * npairs), &acc));
-    auto* ntot = static_cast<unsigned long long*>(acc);
-    CE_HIP(launch_zero_u64(ntot, 2 * npairs, s));
-    int64_t* nm = nullptr;
-    const int64_t* th = nullptr;
-    if (!g.tab.empty()) {
-      th = reinterpret_cast<const int64_t*>(d + g.off_th);
-      nm = reinterpret_cast<int64_t*>(d + g.off_th) + (nbins + 1);
-    } else {
-      const std::vector<double>* km = nullptr;
-      CE_TRY(device_shells(ctx, plan->n, ndim, nbins, &nm, &km, plan->h));
-    }
-    const double norm = cell_volume(plan->h, ndim) / (double)ncells;
-    for (int64_t j = 0; j < npairs; j += cp) {
-      const int64_t np = std::min(cp, npairs - j);
-      void* H = nullptr;
-      CE_TRY(ctx->scratch(2, elem * (size_t)(np * rows * W), &H));
-      RowEpi e;
-      e.mode = 2;
-      e.ncells = ncells;
-      e.count = 2 * np;
-      e.ntot = ntot + 2 * j;
-      e.flags = ctx->flags;
-      e.inv = ctx->inv;
-      e.fwd = fs.fN[ndim - 1];
-      e.H = H;
-      e.H_item = rows * W;
-      CE_TRY(run_inverse(ctx, plan, fs, 0, 0, 0, np, e, s, nullptr, ddesc + j));
-      double* partials = nullptr;
-      int64_t ngroups = 0;
-      CE_TRY(run_forward_bins(ctx, ndim, plan->n, plan->prec, np, H, nbins, &partials, &ngroups, s, nullptr, th,
-                              plan->h));
-      CE_PROF(ctx, "bin_reduce", s,
-              launch_bin_reduce(partials, np, ngroups, nbins, 2 * np, nm, norm, 1, ntot + 2 * j, dslot + 2 * j,
-                                (double)ncells, nullptr, ctx->flags, s));
-    }
-    if (g.covs)
-      CE_PROF(ctx, "covariance", s,
-              launch_covariance_batch(reinterpret_cast<const CovItem*>(d + g.off_cov), g.covs, nbins, s));
+  // Groups are independent: with several lanes they run concurrently, each lane a sub-context
+  // (its own scratch, flags and non-blocking stream) forked from s after the tables arrive and
+  // joined back into s; the largest groups are dealt first, each to the least-loaded lane.
+  // A group's results do not depend on the lane or the order, so they stay bitwise those of
+  // the per-item calls.
+  std::vector<Group*> order;
+  for (auto& kv : groups) order.push_back(&kv.second);
+  std::vector<double> work(order.size());
+  for (size_t i = 0; i < order.size(); ++i) {
+    const ce_plan* p = items[order[i]->idx[0]].plan;
+    double emb = 1;
+    for (int d = 0; d < p->ndim; ++d) emb *= p->M[d];
+    work[i] = emb * (double)order[i]->pairs;
   }
-  return CE_OK;
+  std::vector<size_t> byw(order.size());
+  for (size_t i = 0; i < byw.size(); ++i) byw[i] = i;
+  std::stable_sort(byw.begin(), byw.end(), [&](size_t a, size_t b) { return work[a] > work[b]; });
+  const int nl = (int)std::min<size_t>((size_t)ctx->batch_lanes, order.size());
+  if (nl <= 1) {
+    for (auto& kv : groups) CE_TRY(run_batch_group(ctx, items, kv.second, kv.first, d, s));
+    return CE_OK;
+  }
+  CE_TRY(ensure_lanes(ctx, nl));
+  std::vector<double> load(nl, 0.0);
+  std::vector<std::vector<size_t>> assign(nl);
+  for (size_t i : byw) {
+    const int l = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+    load[l] += work[i];
+    assign[l].push_back(i);
+  }
+  std::vector<const void*> keys(order.size());
+  {
+    size_t i = 0;
+    for (auto& kv : groups) keys[i++] = &kv.first;
+  }
+  CE_HIP(hipEventRecord(ctx->fork, s));
+  ce_status st = CE_OK;
+  for (int l = 0; l < nl; ++l) {
+    ce_ctx* lc = ctx->lanes[l];
+    hipStream_t ls = lc->own;
+    lc->last = ls;
+    if (st == CE_OK && hipStreamWaitEvent(ls, ctx->fork, 0) != hipSuccess) st = CE_E_DEVICE;
+    for (size_t i : assign[l]) {
+      if (st != CE_OK) break;
+      st = run_batch_group(lc, items, *order[i], *static_cast<const GroupKey*>(keys[i]), d, ls);
+    }
+    // the join is recorded even after a failure, so s never waits on an unrecorded event
+    if (hipEventRecord(lc->joined, ls) != hipSuccess || hipStreamWaitEvent(s, lc->joined, 0) != hipSuccess)
+      st = st == CE_OK ? CE_E_DEVICE : st;
+  }
+  return st;
 }
 
 }  // namespace
