@@ -203,6 +203,10 @@ def parse():
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-accuracy", action="store_true", help="skip the oracle comparison of one timed pair")
+    ap.add_argument("--no-tune", action="store_true",
+                    help="time the default launch schedules only (no ce_autotune before the timed steps)")
+    ap.add_argument("--schedules", default="", help="load tuned launch schedules (JSON) before timing")
+    ap.add_argument("--save-schedules", default="", help="write the tuned launch schedules (JSON) after tuning")
     ap.add_argument("--skip-main", action="store_true",
                     help="skip the headline step and its comparators (profiling of the other legs only)")
     ap.add_argument("--volume-steps", type=int, default=10, help="steps of the 3-D workload leg (0: skip it)")
@@ -349,7 +353,7 @@ def cpu_oracle_sample(w, seconds):
                 seconds=dt)
 
 
-def uneven_batch_leg(b, torch, nreq, reps, sample_every=32):
+def uneven_batch_leg(b, torch, nreq, reps, sample_every=32, tune=True):
     """The uneven batch (4096 requests of 2 realizations, 2-D sides 32..512 step 16, each with its
     own two-point function) through ce_pipeline_run_batch, FP32 and FP64 on identical Philox
     streams; plans are built before the timed region.  Also the same requests as one
@@ -405,6 +409,30 @@ def uneven_batch_leg(b, torch, nreq, reps, sample_every=32):
             kept[tag] = [dict(pk=it["out_pk"].cpu().numpy(), counts=it["out_counts"].cpu().numpy(),
                               fields=it["out_fields"].cpu().numpy().astype(np.float64) if "out_fields" in it else None)
                          for it in items]
+            if prec == b.F32 and tune:
+                # the launch schedule of every distinct shape tuned on that shape's requests, then
+                # the same batch again
+                t0 = time.perf_counter()
+                seen = {}
+                for r, p in zip(reqs, plans):
+                    seen.setdefault(r["n"], [p, 0])[1] += r["realizations"]
+                for p, R in seen.values():
+                    b.autotune(ctx, p, R, 1.0, 32, reps=2)
+                tune_s = time.perf_counter() - t0
+                b.pipeline_run_batch(ctx, prepared)
+                torch.cuda.synchronize()
+                tt = []
+                for _ in range(reps):
+                    t0 = time.perf_counter()
+                    b.pipeline_run_batch(ctx, prepared)
+                    torch.cuda.synchronize()
+                    tt.append(time.perf_counter() - t0)
+                tms = 1e3 * float(np.median(tt))
+                leg["default_schedule"] = dict(ms_per_batch=leg["ms_per_batch"], alg_GBs=leg["alg_GBs"])
+                leg.update(value=round(2 * len(reqs) / (tms * 1e-3), 1), ms_per_batch=round(tms, 3),
+                           alg_GBs=round(alg / (tms * 1e-3) / 1e9, 1),
+                           hbm_frac=round(alg / (tms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                           tuned=dict(shapes=len(seen), tune_s=round(tune_s, 2)))
             if prec == b.F32:
                 sub = items[:512]
                 for it in sub[:8]:
@@ -584,13 +612,15 @@ def serving_leg(b, torch, server, rate, seconds, warmup):
                 admission_stalls=stats["admission_stalls"] - stats0["admission_stalls"])
 
 
-def timed_workload(b, torch, ctx, w, name, steps, warmup, stream):
+def timed_workload(b, torch, ctx, w, name, steps, warmup, stream, tune=False):
     """Time `steps` fused steps (ce_pipeline_run of the workload's realizations, counts, N_tot,
     P(k), covariance) after `warmup` untimed ones, with per-kernel HIP events recorded by the
     library on the launch stream.  The roofline is that of the kernel with the largest share of
     the step: its algorithmic bytes per launch over its average event duration, against the HBM
     peak (the counter-measured traffic and VALU busy of the committed counter summary beside it,
-    when the kernel sources are unchanged; the VALU op model as an extra field)."""
+    when the kernel sources are unchanged; the VALU op model as an extra field).  With `tune`, the
+    step is first timed with the default schedule, then ce_autotune picks the launch schedule of
+    the workload's shape (installed in ctx) and the timed steps run with it."""
     import numpy as np
     prec = b.F64 if w["precision"] == "f64" else b.F32
     n, h, nb, R, nbar = w["n"], w["h"], w["nbins"], w["realizations"], w["nbar"]
@@ -614,6 +644,22 @@ def timed_workload(b, torch, ctx, w, name, steps, warmup, stream):
     torch.cuda.synchronize()
     if b.ctx_check(ctx) != 0:
         raise RuntimeError("device flagged a sampler condition during warm-up")
+    sched = None
+    if tune:
+        nd = max(3, steps // 2)
+        t0 = time.perf_counter()
+        for i in range(nd):
+            step(warmup + i)
+        torch.cuda.synchronize()
+        default_ms = 1e3 * (time.perf_counter() - t0) / nd
+        t0 = time.perf_counter()
+        sched = b.autotune(ctx, plan, R, nbar, nb, reps=2)
+        sched = dict(chosen={k: v for k, v in sched.items() if k not in ("ms", "default_ms")},
+                     tune_s=round(time.perf_counter() - t0, 2), default_ms_per_step=round(default_ms, 4),
+                     tuner_ms=dict(chosen=round(sched["ms"], 4), default=round(sched["default_ms"], 4)))
+        for i in range(warmup):
+            step(i)
+        torch.cuda.synchronize()
     b.ctx_profile_read(ctx)
     b.ctx_set_profiling(ctx, True)
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
@@ -663,6 +709,7 @@ def timed_workload(b, torch, ctx, w, name, steps, warmup, stream):
                 pipeline_hbm=dict(alg_bytes_per_step=int(total_bytes), alg_GBs=round(pipe_GBs, 1),
                                   frac_of_peak=round(pipe_GBs / HBM_PEAK_GBS, 4)),
                 roofline=roofline, kernels=kernels, plan_ms=round(plan_ms, 2),
+                **({} if sched is None else dict(schedule=sched)),
                 _plan=plan, _bufs=(pk_out, counts, ntot, cov, cnorm))
 
 
@@ -681,7 +728,11 @@ def main_leg(args, b, torch, w, stream):
             b.ctx_set_option(ctx, opt, int(v))
     if args.noise_order >= 0:
         b.ctx_set_option(ctx, b.OPT_NOISE_ORDER, args.noise_order)
-    leg = timed_workload(b, torch, ctx, w, args.workload, args.steps, args.warmup, stream)
+    if args.schedules:
+        b.schedule_load(ctx, args.schedules)
+    leg = timed_workload(b, torch, ctx, w, args.workload, args.steps, args.warmup, stream, tune=not args.no_tune)
+    if args.save_schedules:
+        b.schedule_save(ctx, args.save_schedules)
     plan, bufs = leg.pop("_plan"), leg.pop("_bufs")
     pk_out, counts, ntot, cov, cnorm = bufs
     cells = plan.cells
@@ -796,7 +847,7 @@ def main():
         # same way: per-kernel events, algorithmic bytes and the roofline of its largest kernel
         vw = workloads.WORKLOADS["volume_3d"]
         vctx = b.ctx_create(0)
-        vleg = timed_workload(b, torch, vctx, vw, "volume_3d", args.volume_steps, 2, stream)
+        vleg = timed_workload(b, torch, vctx, vw, "volume_3d", args.volume_steps, 2, stream, tune=not args.no_tune)
         vleg.pop("_plan").release()
         vleg.pop("_bufs")
         vleg["unit"] = "realizations/s"
@@ -862,7 +913,7 @@ def main():
         print("information %s" % json.dumps(out["information"]), file=sys.stderr, flush=True)
 
     if args.batch_requests:
-        out["uneven_batch"] = uneven_batch_leg(b, torch, args.batch_requests, args.batch_reps)
+        out["uneven_batch"] = uneven_batch_leg(b, torch, args.batch_requests, args.batch_reps, tune=not args.no_tune)
         print("uneven batch %s" % json.dumps(out["uneven_batch"]), file=sys.stderr, flush=True)
 
     if args.serve_rates:

@@ -534,6 +534,39 @@ ce_status ce_server_stats_read(ce_server* server, ce_server_stats* out);
 /* Stops admitting, cancels queued requests, waits for running ones, frees everything. */
 void ce_server_destroy(ce_server* server);
 
+/* Launch schedule of the pipeline passes for one shape (ndim, sides, precision): lines per workgroup
+ * of the noise pass (even, 2..32), the inner-axis passes (3-D), the last inverse pass and the
+ * binning pass (powers of two up to 64; 0 = automatic), the noise pass's tile order (0/1) and
+ * pair blocks (1..65536), and the binning pass's LDS budget (16384..163840 bytes).  Every schedule
+ * gives bitwise identical results (fields, delta, counts, N_tot, P(k), covariance); the radix
+ * plans of the line FFTs are fixed per length, since another order would change the rounding. */
+typedef struct {
+  int32_t lines_noise, lines_inner, lines_last, lines_bins;
+  int32_t noise_order, noise_block;
+  int64_t bin_lds;
+  double ms, default_ms;  /* ce_autotune: median step time of the chosen and of the default schedule */
+} ce_schedule;
+
+/* Autotuner: times ce_pipeline_run steps of `count` realizations of plan (counts, N_tot, P(k) in
+ * nbins shells and the covariance, into private buffers, seed 1) under candidate schedules --
+ * coordinate descent from the context's options over each knob, two sweeps, the median of `reps`
+ * HIP-event timed steps per candidate, a candidate kept when 1% faster -- and installs the fastest
+ * for the plan's shape in ctx; every later call on that shape (pipelines, fields, spectra, the
+ * batch groups) uses it.  out (nullable) receives it with both timings.  Synchronous; allocates
+ * its buffers.  Errors: as ce_pipeline_run, CE_E_INVALID for reps outside 1..100. */
+ce_status ce_autotune(ce_ctx* ctx, const ce_plan* plan, int64_t count, double nbar, int32_t nbins, int32_t reps,
+                      ce_schedule* out);
+/* Install (schedule non-NULL) or remove (NULL) the schedule of a shape; read it back.  Errors:
+ * CE_E_INVALID (bad values; ce_schedule_get: no schedule for the shape), CE_E_UNSUPPORTED. */
+ce_status ce_schedule_set(ce_ctx* ctx, const ce_geometry* geom, ce_precision precision, const ce_schedule* schedule);
+ce_status ce_schedule_get(ce_ctx* ctx, const ce_geometry* geom, ce_precision precision, ce_schedule* out);
+/* Persist the context's tuned schedules as JSON ({"format": "cefield-schedules", "version": 1,
+ * "arch": ..., "entries": [{"ndim", "n": [3], "precision": "f32"|"f64", "lines": [4], "noise_order",
+ * "noise_block", "bin_lds"}]}) and load such a file into a context (entries added or replaced; a
+ * malformed file or an invalid entry loads nothing).  path: host string.  Errors: CE_E_INVALID. */
+ce_status ce_schedule_save(ce_ctx* ctx, const char* path);
+ce_status ce_schedule_load(ce_ctx* ctx, const char* path);
+
 /* Shell table of a grid on the host: N_b and mean |k| per shell (same rule as ce_estimate_pk:
  * square / cubic cells, any even sides).  nmodes, kmean: host arrays of nbins.
  * Errors: CE_E_INVALID, CE_E_UNSUPPORTED (unequal cell sides). */

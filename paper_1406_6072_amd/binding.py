@@ -63,6 +63,12 @@ class Request(ctypes.Structure):
                 ("out_fields", c_void_p), ("out_delta", c_void_p)]
 
 
+class Schedule(ctypes.Structure):
+    _fields_ = [("lines_noise", c_i32), ("lines_inner", c_i32), ("lines_last", c_i32), ("lines_bins", c_i32),
+                ("noise_order", c_i32), ("noise_block", c_i32), ("bin_lds", c_i64), ("ms", c_f64),
+                ("default_ms", c_f64)]
+
+
 class ServerStats(ctypes.Structure):
     _fields_ = [("submitted", c_i64), ("completed", c_i64), ("failed", c_i64), ("cache_hits", c_i64),
                 ("cache_misses", c_i64), ("admission_stalls", c_i64), ("queued", c_i64), ("p50_ms", c_f64),
@@ -140,6 +146,11 @@ _server_drain = _sig("ce_server_drain", c_i32, c_void_p, c_i32, c_void_p, c_void
                      ctypes.POINTER(c_i32))
 _server_stats = _sig("ce_server_stats_read", c_i32, c_void_p, ctypes.POINTER(ServerStats))
 _server_destroy = _sig("ce_server_destroy", None, c_void_p)
+_autotune = _sig("ce_autotune", c_i32, c_void_p, c_void_p, c_i64, c_f64, c_i32, c_i32, ctypes.POINTER(Schedule))
+_schedule_set = _sig("ce_schedule_set", c_i32, c_void_p, ctypes.POINTER(Geometry), c_i32, ctypes.POINTER(Schedule))
+_schedule_get = _sig("ce_schedule_get", c_i32, c_void_p, ctypes.POINTER(Geometry), c_i32, ctypes.POINTER(Schedule))
+_schedule_save = _sig("ce_schedule_save", c_i32, c_void_p, ctypes.c_char_p)
+_schedule_load = _sig("ce_schedule_load", c_i32, c_void_p, ctypes.c_char_p)
 _shell_table = _sig("ce_shell_table", c_i32, ctypes.POINTER(Geometry), c_i32, c_void_p, c_void_p)
 _fft_factors = _sig("ce_fft_factors", c_i32, c_i32, c_void_p, c_void_p)
 _debug_philox = _sig("ce_debug_philox", c_i32, c_u64, c_void_p, c_i64, c_void_p, c_void_p)
@@ -155,7 +166,8 @@ EXPORTED = ["ce_status_string", "ce_version", "ce_ctx_create", "ce_ctx_destroy",
             "ce_mask_release", "ce_pipeline_run_prepared", "ce_pipeline_run_batch", "ce_pipeline_graph_create", "ce_pipeline_graph_launch",
             "ce_pipeline_graph_destroy",
             "ce_server_create", "ce_server_submit", "ce_server_submit_many", "ce_server_poll", "ce_server_drain", "ce_server_cancel",
-            "ce_server_stats_read", "ce_server_destroy", "ce_shell_table", "ce_fft_factors", "ce_debug_philox", "ce_debug_noise"]
+            "ce_server_stats_read", "ce_server_destroy", "ce_autotune", "ce_schedule_set", "ce_schedule_get",
+            "ce_schedule_save", "ce_schedule_load", "ce_shell_table", "ce_fft_factors", "ce_debug_philox", "ce_debug_noise"]
 
 
 class CeError(RuntimeError):
@@ -729,6 +741,51 @@ def server_stats(server):
 
 def server_destroy(server):
     _server_destroy(server)
+
+
+def _sched_dict(s):
+    return {k: getattr(s, k) for k, _ in Schedule._fields_}
+
+
+def autotune(ctx, plan, count, nbar, nbins, reps=3):
+    """Tune the launch schedule of plan's shape (installed in ctx); returns it with the timings."""
+    s = Schedule()
+    _check(_autotune(ctx, plan.handle, int(count), float(nbar), int(nbins), int(reps), ctypes.byref(s)),
+           "ce_autotune")
+    return _sched_dict(s)
+
+
+def schedule_set(ctx, n, h, precision, schedule):
+    """Install a schedule (dict with the Schedule fields; None removes it) for a shape."""
+    g = geometry(n, h)
+    if schedule is None:
+        _check(_schedule_set(ctx, ctypes.byref(g), int(precision), None), "ce_schedule_set")
+        return
+    s = Schedule()
+    s.noise_block, s.bin_lds = 1, 81920
+    for k, v in schedule.items():
+        if k in ("ms", "default_ms"):
+            continue
+        setattr(s, k, int(v))
+    _check(_schedule_set(ctx, ctypes.byref(g), int(precision), ctypes.byref(s)), "ce_schedule_set")
+
+
+def schedule_get(ctx, n, h, precision):
+    g = geometry(n, h)
+    s = Schedule()
+    st = _schedule_get(ctx, ctypes.byref(g), int(precision), ctypes.byref(s))
+    if st == E_INVALID:
+        return None
+    _check(st, "ce_schedule_get")
+    return _sched_dict(s)
+
+
+def schedule_save(ctx, path):
+    _check(_schedule_save(ctx, str(path).encode()), "ce_schedule_save")
+
+
+def schedule_load(ctx, path):
+    _check(_schedule_load(ctx, str(path).encode()), "ce_schedule_load")
 
 
 def shell_table(n, h, nbins):

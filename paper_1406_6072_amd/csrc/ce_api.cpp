@@ -4,7 +4,9 @@
 
 #include <algorithm>
 #include <array>
+#include <cctype>
 #include <cmath>
+#include <cstdlib>
 #include <cstdio>
 #include <cstring>
 #include <map>
@@ -146,6 +148,20 @@ LineGeom make_geom(int L, int K, int64_t A, int64_t B, int64_t nitems, int64_t i
 
 }  // namespace
 
+// ---- launch schedules ---------------------------------------------------------------
+
+// Launch-shape knobs of the pipeline passes (all keep the results bitwise identical): lines per
+// workgroup of the noise, inner-axis, last inverse and binning passes (0 = automatic), the noise
+// pass's tile order and pair blocks, and the binning pass's LDS budget.
+struct Schedule {
+  int lines[4] = {0, 0, 0, 0};
+  int noise_order = 0;
+  int noise_block = 1;
+  size_t bin_lds = kLdsBudget;
+};
+// Shape a schedule is tuned for: (ndim, N_0, N_1, N_2, precision).
+using ScheduleKey = std::tuple<int, int, int, int, int>;
+
 // ---- static scratch of the allocation-free entry point ----------------------------
 
 // Device memory of ce_pipeline_run_noalloc: a file-scope device array, one copy on every device
@@ -228,16 +244,19 @@ struct ce_ctx {
     size_t n[14] = {};
   } arena;
   bool unpruned = false;  // inverse passes keep every embedding output (comparator form)
-  int lines_cap[4] = {0, 0, 0, 0};  // max lines per workgroup per pass kind (0 = automatic)
-  int noise_item_minor = 0;         // noise pass tile order (0: line groups of one pair adjacent; measured faster)
-  int noise_block = 1;              // noise pass: pairs per block of the item-major order
+  // Launch schedule: the context-wide options, the schedules tuned per shape, and the one in
+  // force during a call (the tuned schedule of the call's shape, else the options).  Every
+  // schedule gives bitwise identical results; only the launch shape changes.
+  Schedule opts;
+  std::map<ScheduleKey, Schedule> tuned;
+  const Schedule* active = nullptr;
+  const Schedule& sch() const { return active ? *active : opts; }
   // batched pipeline: groups of different shapes run concurrently on up to batch_lanes
   // sub-contexts (own scratch and stream), forked from and joined into the caller's stream
   int batch_lanes = 4;
   std::vector<ce_ctx*> lanes;
   hipEvent_t fork = nullptr;    // recorded on the caller's stream once the batch tables are copied
   hipEvent_t joined = nullptr;  // (lane sub-contexts) recorded after the lane's last group
-  size_t bin_lds = kLdsBudget;      // LDS budget of a binning-pass workgroup
   std::vector<ProfRec> pending;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> pool;
   std::map<std::string, std::pair<double, int64_t>> agg;
@@ -426,8 +445,19 @@ struct ce_plan {
 
 namespace {
 
+// The tuned schedule of a shape, if any, is in force for the duration of a call on it.
+struct ScheduleScope {
+  ce_ctx* c;
+  const Schedule* prev;
+  ScheduleScope(ce_ctx* ctx, int ndim, const int* n, int prec) : c(ctx), prev(ctx->active) {
+    const auto it = c->tuned.find(ScheduleKey(ndim, n[0], ndim >= 2 ? n[1] : 1, ndim >= 3 ? n[2] : 1, prec));
+    c->active = it != c->tuned.end() ? &it->second : nullptr;
+  }
+  ~ScheduleScope() { c->active = prev; }
+};
+
 int cap_lines(const ce_ctx* ctx, int kind, int dflt) {
-  const int c = ctx->lines_cap[kind];
+  const int c = ctx->sch().lines[kind];
   return c > 0 ? c : dflt;
 }
 
@@ -449,7 +479,7 @@ LineGeom bin_geom(const ce_ctx* ctx, int N, int nb, int64_t B, int64_t nitems, i
   const int G = std::min(4, Rd);
   int R = G;
   const int cap = cap_lines(ctx, 3, 32);
-  while (R * 2 <= cap && fits(R * 2, G, ctx->bin_lds)) R *= 2;
+  while (R * 2 <= cap && fits(R * 2, G, ctx->sch().bin_lds)) R *= 2;
   g.R = R;
   g.groups_per_item = (B + R - 1) / R;
   *G_out = G;
@@ -1018,19 +1048,19 @@ ce_status ce_ctx_set_option(ce_ctx* ctx, int32_t option, int64_t value) {
     case CE_OPT_LINES_LAST:
     case CE_OPT_LINES_BINS:
       if (value < 0 || value > 64 || (value & (value - 1))) return CE_E_INVALID;
-      ctx->lines_cap[option - CE_OPT_LINES_NOISE] = (int)value;
+      ctx->opts.lines[option - CE_OPT_LINES_NOISE] = (int)value;
       return CE_OK;
     case CE_OPT_NOISE_ORDER:
       if (value != 0 && value != 1) return CE_E_INVALID;
-      ctx->noise_item_minor = (int)value;
+      ctx->opts.noise_order = (int)value;
       return CE_OK;
     case CE_OPT_BIN_LDS:
       if (value < 16384 || value > 163840) return CE_E_INVALID;
-      ctx->bin_lds = (size_t)value;
+      ctx->opts.bin_lds = (size_t)value;
       return CE_OK;
     case CE_OPT_NOISE_BLOCK:
       if (value < 1 || value > 65536) return CE_E_INVALID;
-      ctx->noise_block = (int)value;
+      ctx->opts.noise_block = (int)value;
       return CE_OK;
     case CE_OPT_BATCH_LANES:
       if (value < 1 || value > 16) return CE_E_INVALID;
@@ -1358,8 +1388,8 @@ ce_status run_inverse(ce_ctx* ctx, const ce_plan* p, const InverseSetup& fs, uin
   CE_TRY(ctx->scratch(0, elem * (size_t)(y1_item * npairs), &y1));
   LineGeom g1 = make_geom((int)M0, (int)K0, 1, B1, npairs, 0, y1_item, elem, mixed_radix(fs.fM[0]), 2,
                           cap_lines(ctx, 0, 32));
-  g1.item_minor = ctx->noise_item_minor;
-  g1.item_block = ctx->noise_block;
+  g1.item_minor = ctx->sch().noise_order;
+  g1.item_block = ctx->sch().noise_block;
   CE_PROF(ctx, "noise_inverse_axis0", s, launch_noise_pass(p->prec, g1, fs.fM[0], na, y1, s));
   const void* last_in = y1;
   int64_t rows = K0;
@@ -1478,6 +1508,7 @@ ce_status pipeline_impl(ce_ctx* ctx, const ce_plan* plan, uint64_t seed, uint32_
                         double* out_cnorm, const unsigned long long* pair_base, hipStream_t s,
                         const float* mask = nullptr, const void* win = nullptr, const double* fsum = nullptr,
                         const double* edges = nullptr) {
+  ScheduleScope scope(ctx, plan->ndim, plan->n, plan->prec);
   InverseSetup fs;
   CE_TRY(setup_ffts(ctx, plan, fs));
   const int ndim = plan->ndim;
@@ -1578,6 +1609,7 @@ ce_status pipeline_impl(ce_ctx* ctx, const ce_plan* plan, uint64_t seed, uint32_
 ce_status spectrum_impl(ce_ctx* ctx, int ndim, const int* n, const double* h, int prec, PairLoad pl, int64_t count,
                         int32_t nbins, double* out_pk, int64_t* out_nmodes, double* out_kmean, hipStream_t s,
                         const double* edges = nullptr) {
+  ScheduleScope scope(ctx, ndim, n, prec);
   int64_t ncells = 1;
   for (int d = 0; d < ndim; ++d) ncells *= n[d];
   const int64_t nitems = (count + 1) / 2;
@@ -1636,6 +1668,7 @@ ce_status spectrum_impl(ce_ctx* ctx, int ndim, const int* n, const double* h, in
 // the plan precision in scratch slot 12, column-major for the binning pass: [column][q0] in
 // 2-D, [q1][column][q0] in 3-D (the spectra's item layout transposed over q0).
 ce_status window_transform(ce_ctx* ctx, const ce_plan* plan, const float* mask, void** out, hipStream_t s) {
+  ScheduleScope scope(ctx, plan->ndim, plan->n, plan->prec);
   const int ndim = plan->ndim;
   const int N0 = plan->n[0], Nl = plan->n[ndim - 1];
   const int W = 2 * (Nl / 2 + 1);
@@ -1728,10 +1761,8 @@ ce_status ensure_lanes(ce_ctx* ctx, int nl) {
     ctx->lanes.push_back(lc);
   }
   for (ce_ctx* lc : ctx->lanes) {
-    std::copy(std::begin(ctx->lines_cap), std::end(ctx->lines_cap), std::begin(lc->lines_cap));
-    lc->noise_item_minor = ctx->noise_item_minor;
-    lc->noise_block = ctx->noise_block;
-    lc->bin_lds = ctx->bin_lds;
+    lc->opts = ctx->opts;
+    lc->tuned = ctx->tuned;
     lc->prof = ctx->prof;
   }
   return CE_OK;
@@ -1741,6 +1772,7 @@ ce_status ensure_lanes(ce_ctx* ctx, int nl) {
 ce_status run_batch_group(ce_ctx* c, const ce_batch_item* items, Group& g, const GroupKey& key, const char* d,
                           hipStream_t s) {
   const ce_plan* plan = items[g.idx[0]].plan;
+  ScheduleScope scope(c, plan->ndim, plan->n, plan->prec);
   const int nbins = std::get<9>(key);
   const auto* ddesc = reinterpret_cast<const PairDesc*>(d + g.off_desc);
   const auto* dslot = reinterpret_cast<const SlotOut*>(d + g.off_slot);
@@ -1974,6 +2006,7 @@ ce_status ce_generate_fields(ce_ctx* ctx, const ce_plan* plan, uint64_t seed, ui
   CE_HIP(hipSetDevice(ctx->device));
   hipStream_t s = as_stream(stream);
   ctx->last = s;
+  ScheduleScope scope(ctx, plan->ndim, plan->n, plan->prec);
   InverseSetup fs;
   CE_TRY(setup_ffts(ctx, plan, fs));
   const int64_t npairs = (count + 1) / 2;
@@ -2495,6 +2528,358 @@ ce_status ce_debug_noise(const ce_plan* plan, uint64_t seed, uint32_t request_id
   for (int d = 0; d < plan->ndim; ++d) cells *= plan->M[d];
   const NoiseArgs n = noise_args(plan, seed, request_id, 0);
   CE_HIP(launch_debug_noise(plan->prec, n, pair, cells, out, as_stream(stream)));
+  return CE_OK;
+}
+
+}  // extern "C"
+
+// ---- autotuner ----------------------------------------------------------------------
+
+namespace {
+
+ScheduleKey shape_key(int ndim, const int64_t* n, int prec) {
+  return ScheduleKey(ndim, (int)n[0], ndim >= 2 ? (int)n[1] : 1, ndim >= 3 ? (int)n[2] : 1, prec);
+}
+
+Schedule from_public(const ce_schedule& p) {
+  Schedule s;
+  s.lines[0] = p.lines_noise;
+  s.lines[1] = p.lines_inner;
+  s.lines[2] = p.lines_last;
+  s.lines[3] = p.lines_bins;
+  s.noise_order = p.noise_order;
+  s.noise_block = p.noise_block;
+  s.bin_lds = (size_t)p.bin_lds;
+  return s;
+}
+
+void to_public(const Schedule& s, ce_schedule* p) {
+  p->lines_noise = s.lines[0];
+  p->lines_inner = s.lines[1];
+  p->lines_last = s.lines[2];
+  p->lines_bins = s.lines[3];
+  p->noise_order = s.noise_order;
+  p->noise_block = s.noise_block;
+  p->bin_lds = (int64_t)s.bin_lds;
+}
+
+bool valid_schedule(const ce_schedule& p) {
+  for (int v : {p.lines_noise, p.lines_inner, p.lines_last, p.lines_bins})
+    if (v < 0 || v > 64 || (v & (v - 1))) return false;
+  return (p.noise_order == 0 || p.noise_order == 1) && p.noise_block >= 1 && p.noise_block <= 65536 &&
+         p.bin_lds >= 16384 && p.bin_lds <= 163840;
+}
+
+bool same(const Schedule& a, const Schedule& b) {
+  return std::equal(std::begin(a.lines), std::end(a.lines), std::begin(b.lines)) && a.noise_order == b.noise_order &&
+         a.noise_block == b.noise_block && a.bin_lds == b.bin_lds;
+}
+
+// A minimal reader for the schedule file this library writes: objects, arrays, numbers, strings.
+struct JsonReader {
+  const std::string& t;
+  size_t i = 0;
+  bool ok = true;
+  explicit JsonReader(const std::string& text) : t(text) {}
+  void ws() {
+    while (i < t.size() && std::isspace((unsigned char)t[i])) ++i;
+  }
+  bool eat(char c) {
+    ws();
+    if (i < t.size() && t[i] == c) {
+      ++i;
+      return true;
+    }
+    return false;
+  }
+  std::string str() {
+    ws();
+    std::string s;
+    if (i >= t.size() || t[i] != '"') {
+      ok = false;
+      return s;
+    }
+    for (++i; i < t.size() && t[i] != '"'; ++i) s.push_back(t[i]);
+    if (i < t.size()) ++i;
+    return s;
+  }
+  double num() {
+    ws();
+    const char* b = t.c_str() + i;
+    char* e = nullptr;
+    const double v = std::strtod(b, &e);
+    if (e == b) ok = false;
+    i += (size_t)(e - b);
+    return v;
+  }
+  // skips any value
+  void skip() {
+    ws();
+    if (i >= t.size()) {
+      ok = false;
+      return;
+    }
+    if (t[i] == '"') {
+      str();
+    } else if (t[i] == '{' || t[i] == '[') {
+      const char close = t[i] == '{' ? '}' : ']';
+      ++i;
+      if (eat(close)) return;
+      do {
+        if (close == '}') {
+          str();
+          if (!eat(':')) ok = false;
+        }
+        skip();
+      } while (ok && eat(','));
+      if (!eat(close)) ok = false;
+    } else if (t.compare(i, 4, "true") == 0 || t.compare(i, 4, "null") == 0) {
+      i += 4;
+    } else if (t.compare(i, 5, "false") == 0) {
+      i += 5;
+    } else {
+      num();
+    }
+  }
+};
+
+}  // namespace
+
+extern "C" {
+
+ce_status ce_schedule_set(ce_ctx* ctx, const ce_geometry* geom, ce_precision precision, const ce_schedule* schedule) {
+  if (!ctx || !geom || (precision != CE_F32 && precision != CE_F64)) return CE_E_INVALID;
+  CE_TRY(check_geometry(geom));
+  std::lock_guard<std::mutex> lock(ctx->mu);
+  const ScheduleKey key = shape_key(geom->ndim, geom->n, precision == CE_F64 ? 1 : 0);
+  if (!schedule) {
+    ctx->tuned.erase(key);
+    return CE_OK;
+  }
+  if (!valid_schedule(*schedule)) return CE_E_INVALID;
+  ctx->tuned[key] = from_public(*schedule);
+  return CE_OK;
+}
+
+ce_status ce_schedule_get(ce_ctx* ctx, const ce_geometry* geom, ce_precision precision, ce_schedule* out) {
+  if (!ctx || !geom || !out || (precision != CE_F32 && precision != CE_F64)) return CE_E_INVALID;
+  CE_TRY(check_geometry(geom));
+  std::lock_guard<std::mutex> lock(ctx->mu);
+  const auto it = ctx->tuned.find(shape_key(geom->ndim, geom->n, precision == CE_F64 ? 1 : 0));
+  if (it == ctx->tuned.end()) return CE_E_INVALID;
+  *out = ce_schedule{};
+  to_public(it->second, out);
+  return CE_OK;
+}
+
+ce_status ce_autotune(ce_ctx* ctx, const ce_plan* plan, int64_t count, double nbar, int32_t nbins, int32_t reps,
+                      ce_schedule* out) {
+  const double outputs_are_private = 0;  // pipeline_check wants a spectrum pointer; the tuner has its own
+  CE_TRY(pipeline_check(ctx, plan, 0, count, nbar, nbins, &outputs_are_private));
+  if (reps < 1 || reps > 100) return CE_E_INVALID;
+  std::lock_guard<std::mutex> lock(ctx->mu);
+  CE_HIP(hipSetDevice(ctx->device));
+  const int64_t cells = survey_cells(plan);
+  // private outputs (the timed steps write counts, N_tot, P(k) and the covariance, as the fused
+  // workload does)
+  const size_t b_pk = sizeof(double) * (size_t)(count * nbins), b_c = sizeof(int32_t) * (size_t)(count * cells),
+               b_n = sizeof(int64_t) * (size_t)count, b_cov = sizeof(double) * (size_t)nbins * nbins;
+  char* buf = nullptr;
+  CE_TRY(ctx->alloc(reinterpret_cast<void**>(&buf), b_pk + b_c + b_n + b_cov + 1024));
+  hipStream_t s = nullptr;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  auto cleanup = [&](ce_status st) {
+    if (s) (void)hipStreamSynchronize(s);
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    if (s) (void)hipStreamDestroy(s);
+    ctx->release(buf, b_pk + b_c + b_n + b_cov + 1024);
+    return st;
+  };
+  if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess || hipEventCreate(&e0) != hipSuccess ||
+      hipEventCreate(&e1) != hipSuccess)
+    return cleanup(CE_E_DEVICE);
+  auto* pk = reinterpret_cast<double*>(buf);
+  auto* cnt = reinterpret_cast<int32_t*>(buf + b_pk + 256);
+  auto* nt = reinterpret_cast<int64_t*>(buf + b_pk + b_c + 512);
+  auto* cov = reinterpret_cast<double*>(buf + b_pk + b_c + b_n + 768);
+  const ScheduleKey key = shape_key(plan->ndim, std::array<int64_t, 3>{plan->n[0], plan->n[1], plan->n[2]}.data(),
+                                    plan->prec);
+  ctx->tuned.erase(key);
+  const bool prof = ctx->prof;
+  ctx->prof = false;
+  ctx->last = s;
+  // median event time of `reps` steps under schedule sc (one untimed step first)
+  auto time_sched = [&](const Schedule& sc, double* ms) -> ce_status {
+    ctx->tuned[key] = sc;
+    std::vector<float> t;
+    for (int r = 0; r <= reps; ++r) {
+      CE_HIP(hipEventRecord(e0, s));
+      CE_TRY(pipeline_impl(ctx, plan, 1, 0, 0, count, nbar, nbins, nullptr, nullptr, cnt, nt, pk, cov, nullptr,
+                           nullptr, s));
+      CE_HIP(hipEventRecord(e1, s));
+      CE_HIP(hipEventSynchronize(e1));
+      float m = 0;
+      CE_HIP(hipEventElapsedTime(&m, e0, e1));
+      if (r) t.push_back(m);
+    }
+    std::sort(t.begin(), t.end());
+    *ms = t[t.size() / 2];
+    return CE_OK;
+  };
+  // coordinate descent from the default schedule over each knob's candidates, twice
+  const Schedule dflt = ctx->opts;
+  Schedule best = dflt;
+  double best_ms = 0, dflt_ms = 0;
+  ce_status st = time_sched(best, &dflt_ms);
+  best_ms = dflt_ms;
+  struct Knob {
+    int which;
+    std::vector<int64_t> vals;
+  };
+  std::vector<Knob> knobs = {{0, {2, 4, 8, 16, 32}}, {2, {1, 2, 4, 8}}, {3, {1, 2, 4, 8, 16}},
+                             {4, {81920, 163840}},   {5, {1, 2, 4, 8, 16}}, {6, {0, 1}}};
+  if (plan->ndim == 3) knobs.push_back({1, {1, 2, 4, 8, 16, 32}});
+  for (int pass = 0; pass < 2 && st == CE_OK; ++pass)
+    for (const Knob& k : knobs)
+      for (int64_t v : k.vals) {
+        if (st != CE_OK) break;
+        Schedule c = best;
+        if (k.which <= 3)
+          c.lines[k.which] = (int)v;
+        else if (k.which == 4)
+          c.bin_lds = (size_t)v;
+        else if (k.which == 5)
+          c.noise_block = (int)v;
+        else
+          c.noise_order = (int)v;
+        if (same(c, best)) continue;
+        double ms = 0;
+        st = time_sched(c, &ms);
+        if (st == CE_OK && ms < 0.99 * best_ms) {
+          best = c;
+          best_ms = ms;
+        }
+      }
+  ctx->prof = prof;
+  if (st != CE_OK) {
+    ctx->tuned.erase(key);
+    return cleanup(st);
+  }
+  ctx->tuned[key] = best;
+  if (out) {
+    *out = ce_schedule{};
+    to_public(best, out);
+    out->ms = best_ms;
+    out->default_ms = dflt_ms;
+  }
+  return cleanup(CE_OK);
+}
+
+ce_status ce_schedule_save(ce_ctx* ctx, const char* path) {
+  if (!ctx || !path) return CE_E_INVALID;
+  std::lock_guard<std::mutex> lock(ctx->mu);
+  hipDeviceProp_t prop{};
+  CE_HIP(hipGetDeviceProperties(&prop, ctx->device));
+  std::string arch(prop.gcnArchName);
+  arch = arch.substr(0, arch.find(':'));
+  std::string js = "{\"format\": \"cefield-schedules\", \"version\": 1, \"arch\": \"" + arch + "\", \"entries\": [";
+  bool first = true;
+  for (const auto& kv : ctx->tuned) {
+    const auto& k = kv.first;
+    const Schedule& sc = kv.second;
+    char line[512];
+    std::snprintf(line, sizeof(line),
+                  "%s\n  {\"ndim\": %d, \"n\": [%d, %d, %d], \"precision\": \"%s\", \"lines\": [%d, %d, %d, %d], "
+                  "\"noise_order\": %d, \"noise_block\": %d, \"bin_lds\": %zu}",
+                  first ? "" : ",", std::get<0>(k), std::get<1>(k), std::get<2>(k), std::get<3>(k),
+                  std::get<4>(k) ? "f64" : "f32", sc.lines[0], sc.lines[1], sc.lines[2], sc.lines[3], sc.noise_order,
+                  sc.noise_block, sc.bin_lds);
+    js += line;
+    first = false;
+  }
+  js += "\n]}\n";
+  FILE* f = std::fopen(path, "w");
+  if (!f) return CE_E_INVALID;
+  const bool ok = std::fwrite(js.data(), 1, js.size(), f) == js.size();
+  return std::fclose(f) == 0 && ok ? CE_OK : CE_E_INVALID;
+}
+
+ce_status ce_schedule_load(ce_ctx* ctx, const char* path) {
+  if (!ctx || !path) return CE_E_INVALID;
+  FILE* f = std::fopen(path, "r");
+  if (!f) return CE_E_INVALID;
+  std::string text;
+  char chunk[4096];
+  size_t got;
+  while ((got = std::fread(chunk, 1, sizeof(chunk), f)) > 0) text.append(chunk, got);
+  std::fclose(f);
+  JsonReader r(text);
+  std::map<ScheduleKey, Schedule> found;
+  if (!r.eat('{')) return CE_E_INVALID;
+  bool format_ok = false;
+  do {
+    const std::string key = r.str();
+    if (!r.eat(':')) return CE_E_INVALID;
+    if (key == "format") {
+      format_ok = r.str() == "cefield-schedules";
+    } else if (key == "entries") {
+      if (!r.eat('[')) return CE_E_INVALID;
+      if (!r.eat(']')) {
+        do {
+          if (!r.eat('{')) return CE_E_INVALID;
+          ce_geometry g{};
+          int prec = -1;
+          ce_schedule p{};
+          p.noise_block = 1;
+          p.bin_lds = (int64_t)kLdsBudget;
+          do {
+            const std::string f2 = r.str();
+            if (!r.eat(':')) return CE_E_INVALID;
+            if (f2 == "ndim") {
+              g.ndim = (int32_t)r.num();
+            } else if (f2 == "n") {
+              if (!r.eat('[')) return CE_E_INVALID;
+              for (int i = 0; i < 3; ++i) {
+                g.n[i] = (int64_t)r.num();
+                if (i < 2 && !r.eat(',')) return CE_E_INVALID;
+              }
+              if (!r.eat(']')) return CE_E_INVALID;
+            } else if (f2 == "precision") {
+              const std::string pv = r.str();
+              prec = pv == "f64" ? 1 : pv == "f32" ? 0 : -1;
+            } else if (f2 == "lines") {
+              if (!r.eat('[')) return CE_E_INVALID;
+              int32_t* dst[4] = {&p.lines_noise, &p.lines_inner, &p.lines_last, &p.lines_bins};
+              for (int i = 0; i < 4; ++i) {
+                *dst[i] = (int32_t)r.num();
+                if (i < 3 && !r.eat(',')) return CE_E_INVALID;
+              }
+              if (!r.eat(']')) return CE_E_INVALID;
+            } else if (f2 == "noise_order") {
+              p.noise_order = (int32_t)r.num();
+            } else if (f2 == "noise_block") {
+              p.noise_block = (int32_t)r.num();
+            } else if (f2 == "bin_lds") {
+              p.bin_lds = (int64_t)r.num();
+            } else {
+              r.skip();
+            }
+          } while (r.ok && r.eat(','));
+          if (!r.ok || !r.eat('}')) return CE_E_INVALID;
+          for (int i = 0; i < 3; ++i) g.h[i] = 1.0;
+          if (prec < 0 || check_geometry(&g) != CE_OK || !valid_schedule(p)) return CE_E_INVALID;
+          found[shape_key(g.ndim, g.n, prec)] = from_public(p);
+        } while (r.eat(','));
+        if (!r.eat(']')) return CE_E_INVALID;
+      }
+    } else {
+      r.skip();
+    }
+  } while (r.ok && r.eat(','));
+  if (!r.ok || !r.eat('}') || !format_ok) return CE_E_INVALID;
+  std::lock_guard<std::mutex> lock(ctx->mu);
+  for (auto& kv : found) ctx->tuned[kv.first] = kv.second;
   return CE_OK;
 }
 
