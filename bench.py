@@ -227,6 +227,8 @@ def parse():
     ap.add_argument("--serve-seconds", type=float, default=4.0, help="arrival window per rate")
     ap.add_argument("--serve-warmup", type=float, default=1.0, help="arrivals before the window (not counted)")
     ap.add_argument("--serve-slots", type=int, default=8)
+    ap.add_argument("--serve-offline", type=int, default=1,
+                    help="also run the saturation trace as one batched call (the serving-efficiency reference)")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="also run a plain device copy of this size (for counter calibration)")
     return ap.parse_args()
@@ -508,6 +510,40 @@ def serving_warm(b, torch, server, trace, nb=32):
         time.sleep(0.0005)
     dt = time.perf_counter() - t0
     return dt, len(trace) / dt, sum(request_alg_bytes(r["n"], r["realizations"]) for r in trace) / dt / 1e9
+
+
+def offline_batch(b, torch, trace, nb=32):
+    """The requests of a trace run as one ce_pipeline_run_batch call (plans built beforehand, the
+    item table prepared once; the same outputs as served: P(k), N_tot, covariance), after one
+    untimed call: the throughput the same work reaches without arrival order or admission."""
+    offs, pool = serving_outputs(torch, trace, nb)
+    ctx = b.ctx_create(0)
+    plans = {}
+    try:
+        items = []
+        for i, r in enumerate(trace):
+            key = (r["n"], tuple(sorted(r["xi"].items())))
+            if key not in plans:
+                plans[key] = b.plan_embedding(ctx, r["n"], r["h"], r["xi"], b.F32)
+            R, o = r["realizations"], offs[i]
+            items.append(dict(plan=plans[key], seed=r["seed"], request_id=r["request_id"], count=R, nbar=r["nbar"],
+                              nbins=nb, out_pk=pool[o:o + R * nb],
+                              out_ntot=pool[o + R * nb:o + R * nb + R].view(torch.int64),
+                              out_cov=pool[o + R * nb + R:o + R * nb + R + nb * nb] if R >= 2 else None))
+        prepared = b.prepare_batch(items)
+        b.pipeline_run_batch(ctx, prepared)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        b.pipeline_run_batch(ctx, prepared)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+    finally:
+        for p in plans.values():
+            p.release()
+        b.ctx_destroy(ctx)
+    return dict(seconds=round(dt, 4), requests_per_s=round(len(trace) / dt, 1),
+                alg_GBs=round(sum(request_alg_bytes(r["n"], r["realizations"]) for r in trace) / dt / 1e9, 1),
+                plans=len(plans))
 
 
 def small_request_leg(b, torch, slots):
@@ -935,20 +971,24 @@ def main():
                 print("serving leg %s" % json.dumps(leg), file=sys.stderr, flush=True)
         finally:
             b.server_destroy(server)
+        # the saturation trace's work as one batched call: what the server's closed loop is compared with
+        offline = offline_batch(b, torch, sat_trace) if args.serve_offline else None
         # sustainable: the backlog when the last request arrives stays within the slots and the
         # queue drains within 0.5 s of it
         ok = [g["offered_rate"] for g in legs
               if g["backlog_at_last_arrival"] is not None and g["backlog_at_last_arrival"] <= 2 * args.serve_slots
               and g["drain_s"] <= 0.5 and g["failed"] == 0]
         out["serving"] = dict(trace="open-loop Poisson arrivals, 50/50 2-D (sides 64..2048) / 3-D (32..256), "
-                                    "sides 16 x 7-smooth log-uniform, 1..64 realizations log-uniform, 16 two-point "
-                                    "functions, nbar in {0.1,0.3,1,5}, 32 shells, FP32; seed 5",
+                                    "sides every multiple of 16 drawn log-uniformly, 1..64 realizations log-uniform, "
+                                    "16 two-point functions, nbar in {0.1,0.3,1,5}, 32 shells, FP32; seed 5",
                               window_s=args.serve_seconds, warmup_s=args.serve_warmup, slots=args.serve_slots,
                               warm_pass=dict(requests=len(warm_trace), seconds=round(warm_s, 2)),
                               closed_loop=dict(requests=len(sat_trace), seconds=round(sat_s, 3),
                                                requests_per_s=round(sat_rps, 1), alg_GBs=round(sat_gbs, 1),
                                                realizations_per_s=round(sum(r["realizations"] for r in sat_trace)
                                                                         / sat_s, 1)),
+                              offline_batch=offline,
+                              served_over_offline=round(sat_gbs / offline["alg_GBs"], 3) if offline else None,
                               legs=legs, max_sustainable_rate_tested=max(ok) if ok else None)
         out["serving"]["small_requests"] = small_request_leg(b, torch, args.serve_slots)
         print("small requests %s" % json.dumps(out["serving"]["small_requests"]), file=sys.stderr, flush=True)

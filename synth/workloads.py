@@ -53,25 +53,15 @@ def uneven_batch(n_requests=4096, seed=4):
     return reqs
 
 
-def _smooth(j):
-    for p in (2, 3, 5, 7):
-        while j % p == 0:
-            j //= p
-    return j == 1
-
-
-def _log_uniform_smooth(rng, lo, hi):
-    """A 7-smooth integer in [lo, hi] drawn log-uniformly (embedding lengths 32 j then factor into
-    the radices the line FFTs run fastest)."""
-    while True:
-        j = int(np.round(np.exp(rng.uniform(np.log(lo), np.log(hi)))))
-        if _smooth(j):
-            return j
+def _log_uniform_int(rng, lo, hi):
+    """An integer in [lo, hi] drawn log-uniformly."""
+    return int(min(hi, max(lo, np.round(np.exp(rng.uniform(np.log(lo), np.log(hi)))))))
 
 
 def serving_trace(rate=2000.0, duration=20.0, seed=5, max_side_2d=2048, max_side_3d=256, max_realizations=64):
     """Poisson arrivals mixing 2-D and 3-D requests from a menu of 16 two-point functions.
-    Sides are 16 j with j 7-smooth; realizations log-uniform in 1 .. max_realizations."""
+    Sides are every multiple of 16 in range, drawn log-uniformly (16 j, j log-uniform: 2-D
+    64..max_side_2d, 3-D 32..max_side_3d); realizations log-uniform in 1 .. max_realizations."""
     rng = np.random.default_rng(seed)
     menu2 = [_powexp(s2, r0, 300.0) for s2, r0 in zip(np.linspace(0.2, 2.0, 8), np.linspace(2.0, 10.0, 8))]
     menu3 = [_powexp(s2, r0, rc) for s2, r0, rc in
@@ -84,10 +74,10 @@ def serving_trace(rate=2000.0, duration=20.0, seed=5, max_side_2d=2048, max_side
         if t > duration:
             break
         if rng.random() < 0.5:
-            N = 16 * _log_uniform_smooth(rng, 4, max_side_2d // 16)
+            N = 16 * _log_uniform_int(rng, 4, max_side_2d // 16)
             n, h, xi = (N, N), (1.0, 1.0), menu2[int(rng.integers(8))]
         else:
-            N = 16 * _log_uniform_smooth(rng, 2, max_side_3d // 16)
+            N = 16 * _log_uniform_int(rng, 2, max_side_3d // 16)
             n, h, xi = (N, N, N), (1.0, 1.0, 1.0), menu3[int(rng.integers(8))]
         R = int(np.round(np.exp(rng.uniform(0.0, np.log(max_realizations)))))
         reqs.append(dict(request_id=i, arrival=t, n=n, h=h, xi=xi, realizations=max(R, 1),
