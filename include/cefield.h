@@ -161,7 +161,11 @@ typedef enum {
   /* Schedule: ce_pipeline_run_batch runs its groups of different shapes concurrently on up to
    * this many internal streams (1 .. 16, default 4), each with its own scratch, forked from and
    * joined back into the call's stream. */
-  CE_OPT_BATCH_LANES = 9
+  CE_OPT_BATCH_LANES = 9,
+  /* Schedule: pairs each noise-pass workgroup generates for its lines, one after another (1 .. 64;
+   * 0 = automatic, the default: up to 16 while the pass keeps 4096 workgroups). The octant of
+   * sqrt(lambda) is fetched from HBM once per that many pairs. */
+  CE_OPT_NOISE_PAIRS = 10
 } ce_option;
 ce_status ce_ctx_set_option(ce_ctx* ctx, int32_t option, int64_t value);
 
@@ -536,13 +540,16 @@ void ce_server_destroy(ce_server* server);
 
 /* Launch schedule of the pipeline passes for one shape (ndim, sides, precision): lines per workgroup
  * of the noise pass (even, 2..32), the inner-axis passes (3-D), the last inverse pass and the
- * binning pass (powers of two up to 64; 0 = automatic), the noise pass's tile order (0/1) and
- * pair blocks (1..65536), and the binning pass's LDS budget (16384..163840 bytes).  Every schedule
+ * binning pass (powers of two up to 64; 0 = automatic), the noise pass's tile order (0/1), pair
+ * blocks (1..65536) and pairs per workgroup (1..64), and the binning pass's LDS budget
+ * (16384..163840 bytes).  Every schedule
  * gives bitwise identical results (fields, delta, counts, N_tot, P(k), covariance); the radix
  * plans of the line FFTs are fixed per length, since another order would change the rounding. */
 typedef struct {
   int32_t lines_noise, lines_inner, lines_last, lines_bins;
   int32_t noise_order, noise_block;
+  int32_t noise_pairs;  /* pairs each noise-pass workgroup generates for its lines (1..64; 0 = automatic) */
+  int32_t reserved;
   int64_t bin_lds;
   double ms, default_ms;  /* ce_autotune: median step time of the chosen and of the default schedule */
 } ce_schedule;

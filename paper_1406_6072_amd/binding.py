@@ -65,7 +65,8 @@ class Request(ctypes.Structure):
 
 class Schedule(ctypes.Structure):
     _fields_ = [("lines_noise", c_i32), ("lines_inner", c_i32), ("lines_last", c_i32), ("lines_bins", c_i32),
-                ("noise_order", c_i32), ("noise_block", c_i32), ("bin_lds", c_i64), ("ms", c_f64),
+                ("noise_order", c_i32), ("noise_block", c_i32), ("noise_pairs", c_i32), ("reserved", c_i32),
+                ("bin_lds", c_i64), ("ms", c_f64),
                 ("default_ms", c_f64)]
 
 
@@ -282,6 +283,7 @@ CIC_MAX_BINS = 4096
 OPT_LINES_NOISE, OPT_LINES_INNER, OPT_LINES_LAST, OPT_LINES_BINS, OPT_NOISE_ORDER, OPT_BIN_LDS = 2, 3, 4, 5, 6, 7
 OPT_NOISE_BLOCK = 8
 OPT_BATCH_LANES = 9
+OPT_NOISE_PAIRS = 10
 
 
 def ctx_set_option(ctx, option, value):
@@ -762,7 +764,7 @@ def schedule_set(ctx, n, h, precision, schedule):
         _check(_schedule_set(ctx, ctypes.byref(g), int(precision), None), "ce_schedule_set")
         return
     s = Schedule()
-    s.noise_block, s.bin_lds = 1, 81920
+    s.noise_block, s.noise_pairs, s.bin_lds = 1, 0, 81920
     for k, v in schedule.items():
         if k in ("ms", "default_ms"):
             continue

@@ -142,6 +142,7 @@ LineGeom make_geom(int L, int K, int64_t A, int64_t B, int64_t nitems, int64_t i
   g.R = R;
   const int64_t nlines = A * B;
   g.groups_per_item = (nlines + R - 1) / R;
+  g.items_total = nitems;
   return g;
 }
 
@@ -157,6 +158,7 @@ struct Schedule {
   int lines[4] = {0, 0, 0, 0};
   int noise_order = 0;
   int noise_block = 1;
+  int noise_pairs = 0;  // 0: automatic
   size_t bin_lds = kLdsBudget;
 };
 // Shape a schedule is tuned for: (ndim, N_0, N_1, N_2, precision).
@@ -1062,6 +1064,10 @@ ce_status ce_ctx_set_option(ce_ctx* ctx, int32_t option, int64_t value) {
       if (value < 1 || value > 65536) return CE_E_INVALID;
       ctx->opts.noise_block = (int)value;
       return CE_OK;
+    case CE_OPT_NOISE_PAIRS:
+      if (value < 0 || value > 64) return CE_E_INVALID;
+      ctx->opts.noise_pairs = (int)value;
+      return CE_OK;
     case CE_OPT_BATCH_LANES:
       if (value < 1 || value > 16) return CE_E_INVALID;
       ctx->batch_lanes = (int)value;
@@ -1390,6 +1396,16 @@ ce_status run_inverse(ce_ctx* ctx, const ce_plan* p, const InverseSetup& fs, uin
                           cap_lines(ctx, 0, 32));
   g1.item_minor = ctx->sch().noise_order;
   g1.item_block = ctx->sch().noise_block;
+  // each workgroup generates pairs_wg consecutive pairs of its lines, so the octant is fetched
+  // once per pairs_wg pairs; automatic: the most (at most 16) that leave 4096 workgroups
+  g1.pairs_wg = ctx->sch().noise_pairs;
+  if (g1.pairs_wg <= 0) {
+    g1.pairs_wg = 1;
+    while (g1.pairs_wg < 16 && (npairs + 2 * g1.pairs_wg - 1) / (2 * g1.pairs_wg) * g1.groups_per_item >= 4096)
+      g1.pairs_wg *= 2;
+  }
+  g1.items_total = npairs;
+  g1.nitems = (npairs + g1.pairs_wg - 1) / g1.pairs_wg;
   CE_PROF(ctx, "noise_inverse_axis0", s, launch_noise_pass(p->prec, g1, fs.fM[0], na, y1, s));
   const void* last_in = y1;
   int64_t rows = K0;
@@ -2549,6 +2565,7 @@ Schedule from_public(const ce_schedule& p) {
   s.lines[3] = p.lines_bins;
   s.noise_order = p.noise_order;
   s.noise_block = p.noise_block;
+  s.noise_pairs = p.noise_pairs;
   s.bin_lds = (size_t)p.bin_lds;
   return s;
 }
@@ -2560,6 +2577,7 @@ void to_public(const Schedule& s, ce_schedule* p) {
   p->lines_bins = s.lines[3];
   p->noise_order = s.noise_order;
   p->noise_block = s.noise_block;
+  p->noise_pairs = s.noise_pairs;
   p->bin_lds = (int64_t)s.bin_lds;
 }
 
@@ -2567,12 +2585,12 @@ bool valid_schedule(const ce_schedule& p) {
   for (int v : {p.lines_noise, p.lines_inner, p.lines_last, p.lines_bins})
     if (v < 0 || v > 64 || (v & (v - 1))) return false;
   return (p.noise_order == 0 || p.noise_order == 1) && p.noise_block >= 1 && p.noise_block <= 65536 &&
-         p.bin_lds >= 16384 && p.bin_lds <= 163840;
+         p.noise_pairs >= 0 && p.noise_pairs <= 64 && p.bin_lds >= 16384 && p.bin_lds <= 163840;
 }
 
 bool same(const Schedule& a, const Schedule& b) {
   return std::equal(std::begin(a.lines), std::end(a.lines), std::begin(b.lines)) && a.noise_order == b.noise_order &&
-         a.noise_block == b.noise_block && a.bin_lds == b.bin_lds;
+         a.noise_block == b.noise_block && a.noise_pairs == b.noise_pairs && a.bin_lds == b.bin_lds;
 }
 
 // A minimal reader for the schedule file this library writes: objects, arrays, numbers, strings.
@@ -2738,7 +2756,8 @@ ce_status ce_autotune(ce_ctx* ctx, const ce_plan* plan, int64_t count, double nb
     std::vector<int64_t> vals;
   };
   std::vector<Knob> knobs = {{0, {2, 4, 8, 16, 32}}, {2, {1, 2, 4, 8}}, {3, {1, 2, 4, 8, 16}},
-                             {4, {81920, 163840}},   {5, {1, 2, 4, 8, 16}}, {6, {0, 1}}};
+                             {4, {81920, 163840}},   {5, {1, 2, 4, 8, 16}}, {6, {0, 1}},
+                             {7, {0, 1, 4}}};
   if (plan->ndim == 3) knobs.push_back({1, {1, 2, 4, 8, 16, 32}});
   for (int pass = 0; pass < 2 && st == CE_OK; ++pass)
     for (const Knob& k : knobs)
@@ -2751,6 +2770,8 @@ ce_status ce_autotune(ce_ctx* ctx, const ce_plan* plan, int64_t count, double nb
           c.bin_lds = (size_t)v;
         else if (k.which == 5)
           c.noise_block = (int)v;
+        else if (k.which == 7)
+          c.noise_pairs = (int)v;
         else
           c.noise_order = (int)v;
         if (same(c, best)) continue;
@@ -2791,10 +2812,10 @@ ce_status ce_schedule_save(ce_ctx* ctx, const char* path) {
     char line[512];
     std::snprintf(line, sizeof(line),
                   "%s\n  {\"ndim\": %d, \"n\": [%d, %d, %d], \"precision\": \"%s\", \"lines\": [%d, %d, %d, %d], "
-                  "\"noise_order\": %d, \"noise_block\": %d, \"bin_lds\": %zu}",
+                  "\"noise_order\": %d, \"noise_block\": %d, \"noise_pairs\": %d, \"bin_lds\": %zu}",
                   first ? "" : ",", std::get<0>(k), std::get<1>(k), std::get<2>(k), std::get<3>(k),
                   std::get<4>(k) ? "f64" : "f32", sc.lines[0], sc.lines[1], sc.lines[2], sc.lines[3], sc.noise_order,
-                  sc.noise_block, sc.bin_lds);
+                  sc.noise_block, sc.noise_pairs, sc.bin_lds);
     js += line;
     first = false;
   }
@@ -2832,6 +2853,7 @@ ce_status ce_schedule_load(ce_ctx* ctx, const char* path) {
           int prec = -1;
           ce_schedule p{};
           p.noise_block = 1;
+          p.noise_pairs = 0;
           p.bin_lds = (int64_t)kLdsBudget;
           do {
             const std::string f2 = r.str();
@@ -2860,6 +2882,8 @@ ce_status ce_schedule_load(ce_ctx* ctx, const char* path) {
               p.noise_order = (int32_t)r.num();
             } else if (f2 == "noise_block") {
               p.noise_block = (int32_t)r.num();
+            } else if (f2 == "noise_pairs") {
+              p.noise_pairs = (int32_t)r.num();
             } else if (f2 == "bin_lds") {
               p.bin_lds = (int64_t)r.num();
             } else {

@@ -44,6 +44,10 @@ struct LineGeom {
   int32_t nbuf = 1;            // LDS buffers per line: 1 (in place) or 2 (ping-pong, mixed radix)
   int32_t item_minor = 0;      // tile order: 0 = item-major (groups of one item adjacent), 1 = group-major
   int32_t item_block = 1;      // item-major order over blocks of this many items (group-major inside a block)
+  // noise pass: each workgroup takes pairs_wg consecutive items (nitems counts such tiles of items;
+  // items_total is the number of items)
+  int32_t pairs_wg = 1;
+  int64_t items_total = 0;
   int32_t threads = 0;         // workgroup size when above R nlanes (the fused epilogue spreads its cells)
 };
 

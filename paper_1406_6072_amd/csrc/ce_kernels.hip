@@ -52,6 +52,17 @@ __device__ __forceinline__ PassPos pass_pos(const LineGeom& g) {
   return p;
 }
 
+// Line line0 + r of a group as (a, b), b = its index mod B: the group's first line is divided once
+// (uniform over the workgroup; no per-lane 64-bit division) and each line steps from it.
+__device__ __forceinline__ void split_line(int64_t line0, int r, int64_t B, int64_t& a, int64_t& b) {
+  a = line0 / B;
+  b = line0 - a * B + r;
+  while (b >= B) {
+    b -= B;
+    ++a;
+  }
+}
+
 template <typename T>
 __device__ __forceinline__ cpx<T>* lds_lines() {
   extern __shared__ __align__(16) unsigned char ce_smem[];
@@ -93,8 +104,8 @@ __device__ __forceinline__ void fetch_lines(LinePrefetch<T>& pf, const cpx<T>* _
     const int R = g.R;
     const int r = tid % R, c0 = tid / R, step = (int)blockDim.x / R;
     if (r < nl) {
-      const int64_t ln = line0 + r;
-      const int64_t a = ln / g.B, b = ln - a * g.B;
+      int64_t a, b;
+      split_line(line0, r, g.B, a, b);
       const cpx<T>* src = base + a * (int64_t)L * g.B + b;
 #pragma unroll
       for (int k = 0; k < P; ++k) {
@@ -170,8 +181,8 @@ __device__ __forceinline__ void store_lines(const cpx<T>* lds, cpx<T>* __restric
     const int R = g.R;
     const int r = tid % R, c0 = tid / R, step = nthr / R;
     if (r < pp.nl) {
-      const int64_t ln = pp.line0 + r;
-      const int64_t a = ln / g.B, b = ln - a * g.B;
+      int64_t a, b;
+      split_line(pp.line0, r, g.B, a, b);
       cpx<T>* dst = base + a * (int64_t)K * g.B + b;
       const cpx<T>* src = lds + r * g.lpitch;
       for (int i = c0; i < K; i += step) dst[(int64_t)i * g.B] = src[pidx(i)];
@@ -375,8 +386,8 @@ __global__ void __launch_bounds__(512) k_dct_axis(LineGeom g, FftDesc f, DctArgs
     const int R = g.R;
     const int r = tid % R, c0 = tid / R, step = nthr / R;
     if (r < pp.nl) {
-      const int64_t ln = pp.line0 + r;
-      const int64_t a = ln / g.B, b = ln - a * g.B;
+      int64_t a, b;
+      split_line(pp.line0, r, g.B, a, b);
       const double* src = d.in + a * (int64_t)Od * g.B + b;
       cpx<double>* dst = lds + r * g.lpitch;
       for (int i = c0; i < d.M; i += step) dst[pidx(i)] = {src[(int64_t)mirror(i, d.M) * g.B], 0.0};
@@ -391,8 +402,8 @@ __global__ void __launch_bounds__(512) k_dct_axis(LineGeom g, FftDesc f, DctArgs
     const int R = g.R;
     const int rr = tid % R, c0 = tid / R, step = nthr / R;
     if (rr < pp.nl) {
-      const int64_t ln = pp.line0 + rr;
-      const int64_t a = ln / g.B, b = ln - a * g.B;
+      int64_t a, b;
+      split_line(pp.line0, rr, g.B, a, b);
       double* dst = d.out + a * (int64_t)Od * g.B + b;
       const cpx<double>* src = res + rr * g.lpitch;
       for (int i = c0; i < Od; i += step) dst[(int64_t)i * g.B] = src[pidx(i)].x;
@@ -475,30 +486,39 @@ __device__ __forceinline__ uint32_t sq_line_offset(const NoiseArgs& n, uint32_t 
 template <typename T, int MIX>
 __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 4 : 2))) k_noise_pass(LineGeom g, FftDesc f, NoiseArgs n, cpx<T>* __restrict__ out) {
   cpx<T>* lds = lds_lines<T>();
-  const PassPos pp = pass_pos(g);
+  const PassPos pp0 = pass_pos(g);
   const int L = g.L;
   const int tid = threadIdx.x, nthr = blockDim.x;
-  const PairDesc* pd = n.desc ? n.desc + pp.item : nullptr;
-  const T* __restrict__ sq = static_cast<const T*>(pd ? pd->sq : n.sq);
-  const uint32_t pair =
-      pd ? pd->pair : (uint32_t)(n.first_pair + (n.pair_base ? *n.pair_base : 0ull) + pp.item);
-  const uint32_t rid = pd ? pd->rid : n.rid, k0 = pd ? pd->k0 : n.k0, k1 = pd ? pd->k1 : n.k1;
-  {
-    const int H = g.R / 2;  // line pairs
-    const int rp = tid % H, c0 = tid / H, step = nthr / H;
-    if (2 * rp < pp.nl) {
-      // even line id b = flattened index over axes 1..d-1; cells 2p, 2p+1 = (i, b), (i, b+1)
-      const uint32_t b = (uint32_t)(pp.line0 + 2 * rp);
-      const uint32_t half_b = (uint32_t)(g.B >> 1);
-      const T* __restrict__ sq0 = sq + sq_line_offset(n, b);
-      const T* __restrict__ sq1 = sq + sq_line_offset(n, b + 1);
+  const int H = g.R / 2;  // line pairs
+  const int rp = tid % H, c0 = tid / H, step = nthr / H;
+  const bool has_lines = 2 * rp < pp0.nl;
+  // even line id b = flattened index over axes 1..d-1; cells 2p, 2p+1 = (i, b), (i, b+1)
+  const uint32_t b = (uint32_t)(pp0.line0 + 2 * rp);
+  const uint32_t half_b = (uint32_t)(g.B >> 1);
+  const uint32_t off0 = sq_line_offset(n, b), off1 = sq_line_offset(n, b + 1);
+  // The workgroup generates pairs_wg pairs of the same lines one after another: the octant
+  // values it reads for the first pair are still in the caches for the next ones, so the octant
+  // comes from HBM once per pairs_wg pairs instead of once per pair.  The prime-butterfly
+  // variant takes one pair (its register footprint leaves no room for the loop).
+  const int npw = MIX == 2 ? 1 : g.pairs_wg;
+  for (int ip = 0; ip < npw; ++ip) {
+    PassPos pp = pp0;
+    pp.item = pp0.item * npw + ip;
+    if (pp.item >= g.items_total) break;  // uniform over the workgroup
+    const PairDesc* pd = n.desc ? n.desc + pp.item : nullptr;
+    const T* __restrict__ sq = static_cast<const T*>(pd ? pd->sq : n.sq);
+    const uint32_t pair =
+        pd ? pd->pair : (uint32_t)(n.first_pair + (n.pair_base ? *n.pair_base : 0ull) + pp.item);
+    const uint32_t rid = pd ? pd->rid : n.rid, k0 = pd ? pd->k0 : n.k0, k1 = pd ? pd->k1 : n.k1;
+    if (ip > 0) __syncthreads();  // the previous pair's lines have been stored
+    if (has_lines) {
       cpx<T>* d0 = lds + (2 * rp) * g.lpitch;
       cpx<T>* d1 = d0 + g.lpitch;
       for (int i = c0; i < L; i += step) {
         // both octant values are loaded before the generator runs (and before any LDS
         // store, which the compiler could not move them across), so their latency is hidden
         const uint32_t o0 = (uint32_t)mirror(i, n.M[0]);
-        const T s0 = sq0[o0], s1 = sq1[o0];
+        const T s0 = sq[off0 + o0], s1 = sq[off1 + o0];
         const uint32_t p = (uint32_t)i * half_b + (b >> 1);
         const Words4 w = philox4x32_10(p, pair, rid, 0u, k0, k1);
         const cpx<T> e0 = normal_pair<T>(w.x0, w.x1);
@@ -507,11 +527,15 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(sizeof
         d1[pidx(i)] = c_scale(e1, s1);
       }
     }
+    __syncthreads();
+    // the thread index is made opaque per pair so that the FFT's per-lane twiddles are not
+    // hoisted out of the pair loop (they would stay live across it and spill)
+    int tv = tid;
+    asm volatile("" : "+v"(tv));
+    const int r = tv / g.nlanes, lane = tv - r * g.nlanes;
+    line_fft<T, +1, MIX>(buf_a(lds, g, r), buf_b(lds, g, r), f, lane, g.nlanes, r < pp.nl, g.K);
+    store_lines(result_base<T, MIX>(lds, g, f), out, g, pp);
   }
-  __syncthreads();
-  const int r = tid / g.nlanes, lane = tid - r * g.nlanes;
-  line_fft<T, +1, MIX>(buf_a(lds, g, r), buf_b(lds, g, r), f, lane, g.nlanes, r < pp.nl, g.K);
-  store_lines(result_base<T, MIX>(lds, g, f), out, g, pp);
 }
 
 // Generic complex line pass (inner axes of 3-D transforms), pruned to K outputs.
@@ -791,14 +815,21 @@ __device__ __forceinline__ void bin_group(cpx<T>* res, const LineGeom& g, const 
   cpx<T>* line = res + r * g.lpitch;
   int64_t p2 = 0;
   double wgt = 1.0;
+  // line ln = line0 + r is (k1, kl) with kl = ln mod W: the group's first line is split once
+  // (uniform over the workgroup) and each line steps from it
+  const int64_t q0 = line0 / W;
+  const int kl0 = (int)(line0 - q0 * W);
   if (active) {
     const int64_t ln = line0 + r;
-    const int kl = (int)(ln % W);
+    int kl = kl0 + r, k1 = (int)q0;
+    while (kl >= W) {
+      kl -= W;
+      ++k1;
+    }
     const int s = kl >= Kh;
     const int kz = kl - s * Kh;
     p2 = bn.Tl * kz * kz;  // the line's fixed part of t
     if (bn.ndim == 3) {
-      int k1 = (int)(ln / W);
       if (k1 > bn.N1 / 2) k1 -= bn.N1;
       p2 += bn.T1 * k1 * k1;
     }
@@ -860,7 +891,8 @@ __device__ __forceinline__ void bin_group(cpx<T>* res, const LineGeom& g, const 
     const int s = sb / nb, b = sb - s * nb;
     double sum = 0.0;
     const int l1 = min(nl, (j + 1) * G);
-    int kl = (int)((line0 + j * G) % W);
+    int kl = kl0 + j * G;
+    while (kl >= W) kl -= W;
     for (int lr = j * G; lr < l1; ++lr) {
       if ((kl >= Kh) == s) {
         const double* ar = accr(lr);
@@ -1216,10 +1248,17 @@ hipError_t launch_sqrt_table(const double* lam, int ndim, const int32_t* O, doub
   return hipGetLastError();
 }
 
-hipError_t launch_noise_pass(int prec, const LineGeom& g, const FftDesc& f, const NoiseArgs& n, void* out,
+hipError_t launch_noise_pass(int prec, const LineGeom& g0, const FftDesc& f, const NoiseArgs& n, void* out,
                              hipStream_t s) {
   const int mix = fft_variant(f);
-  if (!nbuf_ok(g, mix) || g.R < 2 || (g.R & 1) || (g.B & 1)) return hipErrorInvalidValue;
+  if (!nbuf_ok(g0, mix) || g0.R < 2 || (g0.R & 1) || (g0.B & 1) || g0.pairs_wg < 1 ||
+      g0.nitems * g0.pairs_wg < g0.items_total)
+    return hipErrorInvalidValue;
+  LineGeom g = g0;
+  if (mix == 2 && g.pairs_wg > 1) {  // that variant generates one pair per workgroup
+    g.pairs_wg = 1;
+    g.nitems = g.items_total;
+  }
   with_variant(mix, [&](auto v) {
     constexpr int V = decltype(v)::value;
     if (prec == 0)

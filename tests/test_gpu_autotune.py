@@ -60,7 +60,7 @@ def test_tuned_schedule_is_bitwise_default(b, tmp_path, n, prec):
             b.schedule_load(ctx2, path)
             got2 = b.schedule_get(ctx2, n, h, prec)
             for k in ("lines_noise", "lines_inner", "lines_last", "lines_bins", "noise_order", "noise_block",
-                      "bin_lds"):
+                      "noise_pairs", "bin_lds"):
                 assert got2[k] == sch[k], k
             plan2 = b.plan_embedding(ctx2, n, h, xi, prec)
             got3 = run(b, ctx2, plan2, count, nb)
@@ -95,8 +95,9 @@ def test_schedule_applies_to_batch_groups(b):
 
         ref = batch()
         b.schedule_set(ctx, (96, 96), (1.0, 1.0), 0, dict(lines_noise=4, lines_last=1, lines_bins=16,
-                                                          noise_block=2, bin_lds=163840))
-        b.schedule_set(ctx, (64, 64), (1.0, 1.0), 1, dict(lines_noise=2, lines_bins=1, noise_order=1))
+                                                          noise_block=2, noise_pairs=3, bin_lds=163840))
+        b.schedule_set(ctx, (64, 64), (1.0, 1.0), 1, dict(lines_noise=2, lines_bins=1, noise_order=1,
+                                                          noise_pairs=8))
         got = batch()
         for r, g in zip(ref, got):
             for k in r:

@@ -37,7 +37,7 @@ def status_of(b, fn, *args, **kw):
 @pytest.mark.parametrize("n,h,want", [
     ((31, 32), (1.0, 1.0), "E_UNSUPPORTED"),        # odd side
     ((2, 8), (1.0, 1.0), "E_UNSUPPORTED"),          # below the smallest side
-    ((74, 74), (1.0, 1.0), "E_UNSUPPORTED"),        # 2N = 4 x 37: prime above 31
+    ((8, 2050), (1.0, 1.0), "E_UNSUPPORTED"),       # 2N above 4096 on the last axis
     ((4096, 8), (1.0, 1.0), "E_UNSUPPORTED"),       # 2N above 4096
     ((1024, 1024, 1024), (1.0,) * 3, "E_UNSUPPORTED"),  # embedding cells beyond 2^32
     ((16, 16), (1.0, 0.0), "E_INVALID"),            # cell side not positive

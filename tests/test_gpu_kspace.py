@@ -76,7 +76,7 @@ def test_box_plan_errors(ce):
     for args, want in [(((16, 16), (1.0, 1.0), 8, xi), b.E_INVALID),          # box smaller than the survey
                        (((16, 16), (1.0, 1.0), 33, xi), b.E_INVALID),         # odd box
                        (((16, 16), (1.0, 0.5), 32, xi), b.E_UNSUPPORTED),     # unequal cells
-                       (((16, 16), (1.0, 1.0), 74, xi), b.E_UNSUPPORTED),     # prime 37 in the box side
+                       (((16, 16), (1.0, 1.0), 4100, xi), b.E_UNSUPPORTED),   # box side above 4096
                        (((16, 16), (1.0, 1.0), 32, dict(xi, cell_average=True)), b.E_UNSUPPORTED),
                        (((16, 16), (1.0, 1.0), 32, dict(kind="powexp", sigma2=1.0, r0=1.0, gamma=0.7, rc=0.0)),
                         b.E_UNSUPPORTED)]:

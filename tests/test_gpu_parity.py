@@ -849,14 +849,15 @@ def test_prepared_mask_used_on_another_stream_and_ctx(ce):
 
 
 SCHEDULES = [dict(), dict(lines=(4, 4, 1, 4)), dict(lines=(32, 32, 8, 32), bin_lds=163840),
-             dict(noise_block=4), dict(noise_order=1, bin_lds=16384), dict(lines=(2, 1, 2, 1), noise_block=3)]
+             dict(noise_block=4), dict(noise_order=1, bin_lds=16384), dict(lines=(2, 1, 2, 1), noise_block=3),
+             dict(noise_pairs=4), dict(noise_pairs=5, noise_block=2), dict(noise_pairs=64, noise_order=1)]
 
 
 @pytest.mark.parametrize("n,prec,nb", [((128, 96), 0, 24), ((64, 64), 1, 16), ((16, 24, 20), 0, 6),
                                        ((1024, 1024), 0, 128)])
 def test_schedules_give_bitwise_identical_results(ce, n, prec, nb):
-    """Every schedule option (lines per workgroup of each pass, noise-pass tile order and blocks,
-    binning LDS) changes only the launch shape: fields, delta, counts, N_tot, P(k) and the
+    """Every schedule option (lines per workgroup of each pass, noise-pass tile order, blocks and
+    pairs per workgroup, binning LDS) changes only the launch shape: fields, delta, counts, N_tot, P(k) and the
     covariance are bitwise identical to the default schedule's."""
     b, _ = ce
     xi = dict(kind="exp", sigma2=0.9, a=3.0 if len(n) == 2 else 1.5)
@@ -874,6 +875,8 @@ def test_schedules_give_bitwise_identical_results(ce, n, prec, nb):
                 b.ctx_set_option(ctx, b.OPT_NOISE_BLOCK, sch["noise_block"])
             if "noise_order" in sch:
                 b.ctx_set_option(ctx, b.OPT_NOISE_ORDER, sch["noise_order"])
+            if "noise_pairs" in sch:
+                b.ctx_set_option(ctx, b.OPT_NOISE_PAIRS, sch["noise_pairs"])
             plan = b.plan_embedding(ctx, n, (1.0,) * len(n), xi, prec)
             o = dict(out_pk=torch.empty(count * nb, dtype=torch.float64, device="cuda"),
                      out_fields=torch.empty(count * plan.cells, dtype=plan.dtype, device="cuda"),
