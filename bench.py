@@ -77,6 +77,40 @@ def kernel_ops(name, n, pairs, nb, count, nbar):
     return 0
 
 
+SCHEDULE_FILE = os.path.join(ROOT, "paper_1406_6072_amd", "schedules_gfx950.json")
+
+
+def schedule_file(args):
+    """The launch-schedule file the run loads: --schedules, else the schedules shipped with the
+    package (none with --schedules none or --retune)."""
+    if args.schedules == "none" or (args.retune and not args.schedules):
+        return ""
+    if args.schedules:
+        return args.schedules
+    return SCHEDULE_FILE if os.path.exists(SCHEDULE_FILE) else ""
+
+
+def save_schedules(b, ctx, path):
+    """Merge ctx's schedules into the JSON file at path (entries keyed by shape and precision)."""
+    import tempfile
+    with tempfile.NamedTemporaryFile(suffix=".json", delete=False) as f:
+        tmp = f.name
+    try:
+        b.schedule_save(ctx, tmp)
+        new = json.load(open(tmp))
+    finally:
+        os.unlink(tmp)
+    if os.path.exists(path):
+        old = json.load(open(path))
+        key = lambda e: (e["ndim"], tuple(e["n"]), e["precision"])
+        merged = {key(e): e for e in old.get("entries", [])}
+        merged.update({key(e): e for e in new["entries"]})
+        new["entries"] = sorted(merged.values(), key=lambda e: (e["ndim"], e["n"], e["precision"]))
+    with open(path, "w") as f:
+        json.dump(new, f, indent=1)
+        f.write("\n")
+
+
 def counters_for(kernel, workload):
     """HBM bytes per launch (FETCH_SIZE + WRITE_SIZE, calibrated) and VALU busy of a kernel from the
     committed counter summary, if the kernel sources are unchanged since it was taken; else None."""
@@ -204,9 +238,14 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-accuracy", action="store_true", help="skip the oracle comparison of one timed pair")
     ap.add_argument("--no-tune", action="store_true",
-                    help="time the default launch schedules only (no ce_autotune before the timed steps)")
-    ap.add_argument("--schedules", default="", help="load tuned launch schedules (JSON) before timing")
-    ap.add_argument("--save-schedules", default="", help="write the tuned launch schedules (JSON) after tuning")
+                    help="run no ce_autotune: shapes without a loaded schedule keep the default one")
+    ap.add_argument("--schedules", default="",
+                    help="launch schedules (JSON) loaded before timing; default: the package's "
+                         "schedules_gfx950.json; 'none': default schedules (tuned unless --no-tune)")
+    ap.add_argument("--retune", action="store_true",
+                    help="load no schedule file (unless --schedules names one): tune every shape")
+    ap.add_argument("--save-schedules", default="",
+                    help="merge the schedules used (loaded or tuned) into this JSON file")
     ap.add_argument("--skip-main", action="store_true",
                     help="skip the headline step and its comparators (profiling of the other legs only)")
     ap.add_argument("--volume-steps", type=int, default=10, help="steps of the 3-D workload leg (0: skip it)")
@@ -355,7 +394,7 @@ def cpu_oracle_sample(w, seconds):
                 seconds=dt)
 
 
-def uneven_batch_leg(b, torch, nreq, reps, sample_every=32, tune=True):
+def uneven_batch_leg(b, torch, nreq, reps, sample_every=32, tune=True, schedules="", save=""):
     """The uneven batch (4096 requests of 2 realizations, 2-D sides 32..512 step 16, each with its
     own two-point function) through ce_pipeline_run_batch, FP32 and FP64 on identical Philox
     streams; plans are built before the timed region.  Also the same requests as one
@@ -411,16 +450,23 @@ def uneven_batch_leg(b, torch, nreq, reps, sample_every=32, tune=True):
             kept[tag] = [dict(pk=it["out_pk"].cpu().numpy(), counts=it["out_counts"].cpu().numpy(),
                               fields=it["out_fields"].cpu().numpy().astype(np.float64) if "out_fields" in it else None)
                          for it in items]
-            if prec == b.F32 and tune:
-                # the launch schedule of every distinct shape tuned on that shape's requests, then
-                # the same batch again
+            if prec == b.F32 and (tune or schedules):
+                # the launch schedules of the distinct shapes (from the schedule file; the shapes it
+                # lacks tuned on that shape's requests), then the same batch again
                 t0 = time.perf_counter()
+                if schedules:
+                    b.schedule_load(ctx, schedules)
                 seen = {}
                 for r, p in zip(reqs, plans):
-                    seen.setdefault(r["n"], [p, 0])[1] += r["realizations"]
-                for p, R in seen.values():
-                    b.autotune(ctx, p, R, 1.0, 32, reps=2)
+                    seen.setdefault(r["n"], [p, 0, r["h"]])[1] += r["realizations"]
+                ntuned = 0
+                for nn, (p, R, hh) in seen.items():
+                    if tune and b.schedule_get(ctx, nn, hh, b.F32) is None:
+                        b.autotune(ctx, p, R, 1.0, 32, reps=2)
+                        ntuned += 1
                 tune_s = time.perf_counter() - t0
+                if save:
+                    save_schedules(b, ctx, save)
                 b.pipeline_run_batch(ctx, prepared)
                 torch.cuda.synchronize()
                 tt = []
@@ -434,7 +480,8 @@ def uneven_batch_leg(b, torch, nreq, reps, sample_every=32, tune=True):
                 leg.update(value=round(2 * len(reqs) / (tms * 1e-3), 1), ms_per_batch=round(tms, 3),
                            alg_GBs=round(alg / (tms * 1e-3) / 1e9, 1),
                            hbm_frac=round(alg / (tms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
-                           tuned=dict(shapes=len(seen), tune_s=round(tune_s, 2)))
+                           tuned=dict(shapes=len(seen), tuned_here=ntuned, from_file=len(seen) - ntuned,
+                                      tune_s=round(tune_s, 2)))
             if prec == b.F32:
                 sub = items[:512]
                 for it in sub[:8]:
@@ -681,7 +728,10 @@ def timed_workload(b, torch, ctx, w, name, steps, warmup, stream, tune=False):
     if b.ctx_check(ctx) != 0:
         raise RuntimeError("device flagged a sampler condition during warm-up")
     sched = None
-    if tune:
+    installed = b.schedule_get(ctx, n, h, prec)
+    if tune or installed is not None:
+        if installed is not None:
+            b.schedule_set(ctx, n, h, prec, None)  # the default schedule is timed first
         nd = max(3, steps // 2)
         t0 = time.perf_counter()
         for i in range(nd):
@@ -689,10 +739,15 @@ def timed_workload(b, torch, ctx, w, name, steps, warmup, stream, tune=False):
         torch.cuda.synchronize()
         default_ms = 1e3 * (time.perf_counter() - t0) / nd
         t0 = time.perf_counter()
-        sched = b.autotune(ctx, plan, R, nbar, nb, reps=2)
-        sched = dict(chosen={k: v for k, v in sched.items() if k not in ("ms", "default_ms")},
-                     tune_s=round(time.perf_counter() - t0, 2), default_ms_per_step=round(default_ms, 4),
-                     tuner_ms=dict(chosen=round(sched["ms"], 4), default=round(sched["default_ms"], 4)))
+        if installed is not None:
+            b.schedule_set(ctx, n, h, prec, installed)
+            sched = dict(chosen={k: v for k, v in installed.items() if k not in ("ms", "default_ms")},
+                         source="schedule file", default_ms_per_step=round(default_ms, 4))
+        else:
+            s = b.autotune(ctx, plan, R, nbar, nb, reps=2)
+            sched = dict(chosen={k: v for k, v in s.items() if k not in ("ms", "default_ms")}, source="ce_autotune",
+                         tune_s=round(time.perf_counter() - t0, 2), default_ms_per_step=round(default_ms, 4),
+                         tuner_ms=dict(chosen=round(s["ms"], 4), default=round(s["default_ms"], 4)))
         for i in range(warmup):
             step(i)
         torch.cuda.synchronize()
@@ -764,11 +819,11 @@ def main_leg(args, b, torch, w, stream):
             b.ctx_set_option(ctx, opt, int(v))
     if args.noise_order >= 0:
         b.ctx_set_option(ctx, b.OPT_NOISE_ORDER, args.noise_order)
-    if args.schedules:
-        b.schedule_load(ctx, args.schedules)
+    if schedule_file(args):
+        b.schedule_load(ctx, schedule_file(args))
     leg = timed_workload(b, torch, ctx, w, args.workload, args.steps, args.warmup, stream, tune=not args.no_tune)
     if args.save_schedules:
-        b.schedule_save(ctx, args.save_schedules)
+        save_schedules(b, ctx, args.save_schedules)
     plan, bufs = leg.pop("_plan"), leg.pop("_bufs")
     pk_out, counts, ntot, cov, cnorm = bufs
     cells = plan.cells
@@ -883,7 +938,11 @@ def main():
         # same way: per-kernel events, algorithmic bytes and the roofline of its largest kernel
         vw = workloads.WORKLOADS["volume_3d"]
         vctx = b.ctx_create(0)
+        if schedule_file(args):
+            b.schedule_load(vctx, schedule_file(args))
         vleg = timed_workload(b, torch, vctx, vw, "volume_3d", args.volume_steps, 2, stream, tune=not args.no_tune)
+        if args.save_schedules:
+            save_schedules(b, vctx, args.save_schedules)
         vleg.pop("_plan").release()
         vleg.pop("_bufs")
         vleg["unit"] = "realizations/s"
@@ -949,7 +1008,8 @@ def main():
         print("information %s" % json.dumps(out["information"]), file=sys.stderr, flush=True)
 
     if args.batch_requests:
-        out["uneven_batch"] = uneven_batch_leg(b, torch, args.batch_requests, args.batch_reps, tune=not args.no_tune)
+        out["uneven_batch"] = uneven_batch_leg(b, torch, args.batch_requests, args.batch_reps, tune=not args.no_tune,
+                                               schedules=schedule_file(args), save=args.save_schedules)
         print("uneven batch %s" % json.dumps(out["uneven_batch"]), file=sys.stderr, flush=True)
 
     if args.serve_rates:

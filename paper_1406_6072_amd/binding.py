@@ -782,6 +782,10 @@ def schedule_get(ctx, n, h, precision):
     return _sched_dict(s)
 
 
+# launch schedules tuned on gfx950 for the shapes of the package's benchmark workloads
+DEFAULT_SCHEDULES = os.path.join(os.path.dirname(os.path.abspath(__file__)), "schedules_gfx950.json")
+
+
 def schedule_save(ctx, path):
     _check(_schedule_save(ctx, str(path).encode()), "ce_schedule_save")
 

@@ -99,3 +99,25 @@ def test_host_shell_table_rejects_irrational_cell_ratio():
     with pytest.raises(binding.CeError) as e:
         binding.shell_table((16, 16), (1.0, 0.5 ** 0.5), 4)
     assert e.value.status == binding.E_UNSUPPORTED
+
+
+def test_shipped_schedule_file_is_well_formed():
+    """The package's tuned launch schedules: one entry per shape and precision, values in the
+    ranges the library accepts (the GPU tests load the file through ce_schedule_load)."""
+    import json
+    from paper_1406_6072_amd import binding
+    rec = json.load(open(binding.DEFAULT_SCHEDULES))
+    assert rec["format"] == "cefield-schedules" and rec["arch"] == "gfx950"
+    keys = set()
+    for e in rec["entries"]:
+        key = (e["ndim"], tuple(e["n"]), e["precision"])
+        assert key not in keys
+        keys.add(key)
+        assert e["ndim"] in (2, 3) and e["precision"] in ("f32", "f64")
+        ln, li, ll, lb = e["lines"]
+        assert ln == 0 or (ln % 2 == 0 and 2 <= ln <= 32)
+        for v in (li, ll, lb):
+            assert v == 0 or (v & (v - 1) == 0 and v <= 64)
+        assert e["noise_order"] in (0, 1) and 1 <= e["noise_block"] <= 65536
+        assert 0 <= e["noise_pairs"] <= 64 and 16384 <= e["bin_lds"] <= 163840
+    assert (2, (1024, 1024, 1), "f32") in keys and (3, (256, 256, 256), "f32") in keys

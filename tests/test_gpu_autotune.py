@@ -132,3 +132,22 @@ def test_schedule_errors(b, tmp_path):
         plan.release()
     finally:
         b.ctx_destroy(ctx)
+
+
+def test_shipped_schedules_load_and_keep_results(b):
+    """The package's schedule file loads; the headline shape's entry changes no output bit."""
+    ctx = b.ctx_create(0)
+    try:
+        n, h = (1024, 1024), (1.0, 1.0)
+        xi = dict(kind="exp", sigma2=0.8, a=3.0)
+        plan = b.plan_embedding(ctx, n, h, xi, 0)
+        ref = run(b, ctx, plan, 4, 32)
+        b.schedule_load(ctx, b.DEFAULT_SCHEDULES)
+        assert b.schedule_get(ctx, n, h, 0) is not None
+        assert b.schedule_get(ctx, (256, 256, 256), (1.0,) * 3, 0) is not None
+        got = run(b, ctx, plan, 4, 32)
+        for k in ref:
+            assert torch.equal(got[k], ref[k]), k
+        plan.release()
+    finally:
+        b.ctx_destroy(ctx)
