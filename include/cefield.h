@@ -163,7 +163,7 @@ typedef enum {
    * joined back into the call's stream. */
   CE_OPT_BATCH_LANES = 9,
   /* Schedule: pairs each noise-pass workgroup generates for its lines, one after another (1 .. 64;
-   * 0 = automatic, the default: up to 16 while the pass keeps 4096 workgroups). The octant of
+   * 0 = automatic, the default: up to 8 while the pass keeps 4096 workgroups). The octant of
    * sqrt(lambda) is fetched from HBM once per that many pairs. */
   CE_OPT_NOISE_PAIRS = 10
 } ce_option;

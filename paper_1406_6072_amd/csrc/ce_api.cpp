@@ -1397,11 +1397,13 @@ ce_status run_inverse(ce_ctx* ctx, const ce_plan* p, const InverseSetup& fs, uin
   g1.item_minor = ctx->sch().noise_order;
   g1.item_block = ctx->sch().noise_block;
   // each workgroup generates pairs_wg consecutive pairs of its lines, so the octant is fetched
-  // once per pairs_wg pairs; automatic: the most (at most 16) that leave 4096 workgroups
+  // once per pairs_wg pairs; automatic: the most (at most 8) that leave 4096 workgroups.  More
+  // pairs per workgroup cut the octant reads further but let the workgroups that share the
+  // output's cache lines drift apart in time, so partial lines are written back more than once.
   g1.pairs_wg = ctx->sch().noise_pairs;
   if (g1.pairs_wg <= 0) {
     g1.pairs_wg = 1;
-    while (g1.pairs_wg < 16 && (npairs + 2 * g1.pairs_wg - 1) / (2 * g1.pairs_wg) * g1.groups_per_item >= 4096)
+    while (g1.pairs_wg < 8 && (npairs + 2 * g1.pairs_wg - 1) / (2 * g1.pairs_wg) * g1.groups_per_item >= 4096)
       g1.pairs_wg *= 2;
   }
   g1.items_total = npairs;
