@@ -251,10 +251,12 @@ ce_status ce_lognormal_poisson(ce_ctx* ctx, const ce_plan* plan, const void* fie
  * P_b = (h^d / N^d) (1/N_b) sum_{q in b} |F(q)|^2, F the DFT of the map (CE_MAP_FIELD) or of
  * delta_g = (N/f - N^)/N^ on f != 0 and 0 elsewhere, N^ = N_tot / sum f (CE_MAP_COUNTS_DELTAG;
  * ntot nullable -> computed; mask_f nullable -> f = 1).  Shells are linear in |k| on
- * (0, pi/h]: mode q (signed frequencies q~_i) is in shell b when
- * b < nbins 2 sqrt(sum_i (q~_i / N_i)^2) <= b+1, decided exactly in integers (with the least
- * common multiple of the N_i).  The cells must be square / cubic (equal h); the sides N_i may
- * differ (hyperrectangular surveys).  maps: count x N^d of float /
+ * (0, pi / max h_i]: mode q (signed frequencies q~_i) is in shell b when
+ * b < nbins |k| / (pi / max h_i) <= b+1, |k|^2 = sum_i (2 pi q~_i / (N_i h_i))^2, decided exactly
+ * in integers (square / cubic cells: b < nbins 2 sqrt(sum_i (q~_i / N_i)^2) <= b+1, with the least
+ * common multiple of the N_i).  The sides N_i may differ (hyperrectangular surveys) and so may
+ * the cell sides h_i, when their ratios are fractions of denominator <= 64 (an irrational ratio:
+ * CE_E_UNSUPPORTED).  h^d is the cell volume prod_i h_i.  maps: count x N^d of float /
  * double (FIELD, per `precision`) or int32 (COUNTS).  out_pk: count x nbins doubles (device).
  * out_nmodes (nullable, device, nbins int64), out_kmean (nullable, device, nbins doubles: the
  * mean |k| = 2 pi |q~| / (N h) of each shell).  Bin sums are accumulated in FP64 in a fixed
@@ -569,14 +571,14 @@ ce_status ce_schedule_set(ce_ctx* ctx, const ce_geometry* geom, ce_precision pre
 ce_status ce_schedule_get(ce_ctx* ctx, const ce_geometry* geom, ce_precision precision, ce_schedule* out);
 /* Persist the context's tuned schedules as JSON ({"format": "cefield-schedules", "version": 1,
  * "arch": ..., "entries": [{"ndim", "n": [3], "precision": "f32"|"f64", "lines": [4], "noise_order",
- * "noise_block", "bin_lds"}]}) and load such a file into a context (entries added or replaced; a
+ * "noise_block", "noise_pairs", "bin_lds"}]}) and load such a file into a context (entries added or replaced; a
  * malformed file or an invalid entry loads nothing).  path: host string.  Errors: CE_E_INVALID. */
 ce_status ce_schedule_save(ce_ctx* ctx, const char* path);
 ce_status ce_schedule_load(ce_ctx* ctx, const char* path);
 
 /* Shell table of a grid on the host: N_b and mean |k| per shell (same rule as ce_estimate_pk:
- * square / cubic cells, any even sides).  nmodes, kmean: host arrays of nbins.
- * Errors: CE_E_INVALID, CE_E_UNSUPPORTED (unequal cell sides). */
+ * any even sides, cell sides in ratios of small integers).  nmodes, kmean: host arrays of nbins.
+ * Errors: CE_E_INVALID, CE_E_UNSUPPORTED (an irrational cell-side ratio). */
 ce_status ce_shell_table(const ce_geometry* geom, int32_t nbins, int64_t* nmodes, double* kmean);
 
 /* FFT factorisation chosen for a line length (host; for inspection).  Writes up to 16 radices
