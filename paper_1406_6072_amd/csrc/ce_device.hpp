@@ -311,6 +311,7 @@ template <typename T, int R, int S>
 __device__ __forceinline__ void pingpong_stage(const cpx<T>* src, cpx<T>* dst, int L, int Ns, uint32_t nsm, int lane,
                                                int nlanes, bool active, const cpx<T>* __restrict__ tw,
                                                const cpx<T>* __restrict__ stw, int keep) {
+  asm volatile("" : "+v"(lane));  // per-stage lane (no indices kept live across stages)
   constexpr bool kPow2 = (R & (R - 1)) == 0;
   constexpr int H = (R - 1) / 2;
   const int nb = L / R;
@@ -355,6 +356,72 @@ __device__ __forceinline__ void pingpong_stage(const cpx<T>* src, cpx<T>* dst, i
   __syncthreads();
 }
 
+// In-place Stockham stage of a mixed-radix line (radix R <= 8, any supported L): each thread
+// loads the R inputs of all its butterflies j = lane + b nlanes (at most ceil(kEPT / R) of
+// them, since nlanes >= L / kEPT) into registers, the workgroup waits, and then each butterfly
+// is twiddled, transformed and stored into the same buffer.  One LDS buffer per line (the
+// ping-pong form needs two), and all of a thread's loads are in flight together.
+template <typename T, int R, int S>
+__device__ __forceinline__ void inplace_stage(cpx<T>* line, int L, int Ns, uint32_t nsm, int lane, int nlanes,
+                                              bool active, const cpx<T>* __restrict__ tw,
+                                              const cpx<T>* __restrict__ stw, int keep) {
+  constexpr bool kPow2 = (R & (R - 1)) == 0;
+  constexpr int H = (R - 1) / 2;
+  constexpr int NB = (kEPT + R - 1) / R;
+  const int nb = L / R;
+  // the lane index is made opaque per stage: otherwise the butterfly indices and LDS offsets,
+  // equal in every stage of one radix, are computed once and kept live across the whole
+  // transform (they spill)
+  asm volatile("" : "+v"(lane));
+  T cs[H + 1], sn[H + 1];
+  if constexpr (!kPow2) {
+#pragma unroll
+    for (int m = 1; m <= H; ++m) {
+      const cpx<T> w = tw[m * nb];
+      cs[m] = w.x;
+      sn[m] = -w.y;
+    }
+  }
+  cpx<T> v[NB][R];
+#pragma unroll
+  for (int b = 0; b < NB; ++b) {
+    const int j = lane + b * nlanes;
+    if (active && j < nb) {
+#pragma unroll
+      for (int r = 0; r < R; ++r) v[b][r] = line[pidx(j + r * nb)];
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int b = 0; b < NB; ++b) {
+    const int j = lane + b * nlanes;
+    if (active && j < nb) {
+      int k, base;
+      stage_index(j, Ns, nsm, R, k, base);
+      if (Ns > 1) {
+        const cpx<T>* w = stw + k * (R - 1);
+#pragma unroll
+        for (int r = 1; r < R; ++r) {
+          cpx<T> t = w[r - 1];
+          if (S > 0) t.y = -t.y;
+          v[b][r] = c_mul(v[b][r], t);
+        }
+      }
+      if constexpr (kPow2) {
+        Pow2Dft<R, S, T>::run(v[b]);
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          const int o = base + r * Ns;
+          if (o < keep) line[pidx(o)] = v[b][r];
+        }
+      } else {
+        odd_dft_store<R, S, T>(v[b], cs, sn, line, base, Ns, keep);
+      }
+    }
+  }
+  __syncthreads();
+}
+
 // Out-of-place stage of a prime radix R >= 11 with the inputs kept in LDS instead of
 // registers: each butterfly owns its R source slots, so it overwrites them with the
 // twiddled pair sums v[n] + v[R-n] and differences v[n] - v[R-n], then forms each output
@@ -364,6 +431,7 @@ template <typename T, int R, int S>
 __device__ __forceinline__ void pingpong_stage_lds(cpx<T>* src, cpx<T>* dst, int L, int Ns, uint32_t nsm, int lane,
                                                    int nlanes, bool active, const cpx<T>* __restrict__ tw,
                                                    const cpx<T>* __restrict__ stw, int keep) {
+  asm volatile("" : "+v"(lane));  // per-stage lane (no indices kept live across stages)
   constexpr int H = (R - 1) / 2;
   const int nb = L / R;
   T cs[H + 1], sn[H + 1];
@@ -438,6 +506,7 @@ __device__ __forceinline__ void pingpong_stage_generic(cpx<T>* src, cpx<T>* dst,
                                                        int lane, int nlanes, bool active,
                                                        const cpx<T>* __restrict__ tw, const cpx<T>* __restrict__ stw,
                                                        int keep) {
+  asm volatile("" : "+v"(lane));  // per-stage lane (no indices kept live across stages)
   const int H = (R - 1) / 2;
   const int nb = L / R;
   const int Lr = L / R;
@@ -540,10 +609,10 @@ __device__ __forceinline__ void pow2_fft(cpx<T>* a, int L, int lane, bool active
 }
 
 // Full line FFT.  Every thread of the workgroup must call it (barriers inside);
-// threads without a line pass active = false.  MIX = false: power-of-two
-// lengths, in place in buffer a, registers staged across each barrier.
-// MIX = 1 or 2: the stages of f.rad (radices 2, 4, 8 and odd primes up to 7, or up to
-// 31), ping-pong between a and b.
+// threads without a line pass active = false.  MIX = 0: power-of-two lengths, in place in
+// buffer a, registers staged across each barrier.  MIX = 1: the stages of f.rad (radices
+// 2, 4, 8 and the odd primes up to 7), in place in buffer a.  MIX = 2: lengths with a prime
+// factor of 11 or more, every stage ping-pong between a and b.
 // Returns the buffer that holds the result.
 template <typename T, int S, int MIX>
 __device__ __forceinline__ cpx<T>* line_fft(cpx<T>* a, cpx<T>* b, const FftDesc& f, int lane, int nlanes, bool active,
@@ -557,6 +626,25 @@ __device__ __forceinline__ cpx<T>* line_fft(cpx<T>* a, cpx<T>* b, const FftDesc&
     (void)tw;
     pow2_fft<T, S>(a, L, lane, active, static_cast<const cpx<T>*>(f.stw), keep);
     return a;
+  } else if constexpr (MIX == 1) {
+    (void)b;
+    const cpx<T>* __restrict__ stw0 = static_cast<const cpx<T>*>(f.stw);
+    for (int s = 0; s < f.nst; ++s) {
+      const int R = f.rad[s];
+      const int kp = (s == f.nst - 1) ? keep : L;
+      const uint32_t nm = f.nsm[s];
+      const cpx<T>* sw = stw0 + f.soff[s];
+      switch (R) {
+        case 2: inplace_stage<T, 2, S>(a, L, Ns, nm, lane, nlanes, active, tw, sw, kp); break;
+        case 4: inplace_stage<T, 4, S>(a, L, Ns, nm, lane, nlanes, active, tw, sw, kp); break;
+        case 8: inplace_stage<T, 8, S>(a, L, Ns, nm, lane, nlanes, active, tw, sw, kp); break;
+        case 3: inplace_stage<T, 3, S>(a, L, Ns, nm, lane, nlanes, active, tw, sw, kp); break;
+        case 5: inplace_stage<T, 5, S>(a, L, Ns, nm, lane, nlanes, active, tw, sw, kp); break;
+        default: inplace_stage<T, 7, S>(a, L, Ns, nm, lane, nlanes, active, tw, sw, kp); break;
+      }
+      Ns *= R;
+    }
+    return a;
   } else {
     cpx<T>* src = a;
     cpx<T>* dst = b;
@@ -566,33 +654,22 @@ __device__ __forceinline__ cpx<T>* line_fft(cpx<T>* a, cpx<T>* b, const FftDesc&
       const int kp = (s == f.nst - 1) ? keep : L;
       const uint32_t nm = f.nsm[s];
       const cpx<T>* sw = stw0 + f.soff[s];
-      // MIX 1 instantiates only the small radices, so its register footprint is that of
-      // radix 8; MIX 2 adds the primes 11..31 and the generic prime stage
+      // the primes 11..31 have their own butterflies, larger primes the generic stage
       switch (R) {
         case 2: pingpong_stage<T, 2, S>(src, dst, L, Ns, nm, lane, nlanes, active, tw, sw, kp); break;
         case 4: pingpong_stage<T, 4, S>(src, dst, L, Ns, nm, lane, nlanes, active, tw, sw, kp); break;
         case 8: pingpong_stage<T, 8, S>(src, dst, L, Ns, nm, lane, nlanes, active, tw, sw, kp); break;
         case 3: pingpong_stage<T, 3, S>(src, dst, L, Ns, nm, lane, nlanes, active, tw, sw, kp); break;
         case 5: pingpong_stage<T, 5, S>(src, dst, L, Ns, nm, lane, nlanes, active, tw, sw, kp); break;
-        default:
-          if constexpr (MIX == 1) {
-            pingpong_stage<T, 7, S>(src, dst, L, Ns, nm, lane, nlanes, active, tw, sw, kp);
-          } else {
-            switch (R) {
-              case 7: pingpong_stage<T, 7, S>(src, dst, L, Ns, nm, lane, nlanes, active, tw, sw, kp); break;
-              case 11: pingpong_stage_lds<T, 11, S>(src, dst, L, Ns, nm, lane, nlanes, active, tw, sw, kp); break;
-              case 13: pingpong_stage_lds<T, 13, S>(src, dst, L, Ns, nm, lane, nlanes, active, tw, sw, kp); break;
-              case 17: pingpong_stage_lds<T, 17, S>(src, dst, L, Ns, nm, lane, nlanes, active, tw, sw, kp); break;
-              case 19: pingpong_stage_lds<T, 19, S>(src, dst, L, Ns, nm, lane, nlanes, active, tw, sw, kp); break;
-              case 23: pingpong_stage_lds<T, 23, S>(src, dst, L, Ns, nm, lane, nlanes, active, tw, sw, kp); break;
-              case 29: pingpong_stage_lds<T, 29, S>(src, dst, L, Ns, nm, lane, nlanes, active, tw, sw, kp); break;
-              case 31: pingpong_stage_lds<T, 31, S>(src, dst, L, Ns, nm, lane, nlanes, active, tw, sw, kp); break;
-              default:
-                pingpong_stage_generic<T, S>(src, dst, L, R, Ns, nm, lane, nlanes, active, tw, sw, kp);
-                break;
-            }
-          }
-          break;
+        case 7: pingpong_stage<T, 7, S>(src, dst, L, Ns, nm, lane, nlanes, active, tw, sw, kp); break;
+        case 11: pingpong_stage_lds<T, 11, S>(src, dst, L, Ns, nm, lane, nlanes, active, tw, sw, kp); break;
+        case 13: pingpong_stage_lds<T, 13, S>(src, dst, L, Ns, nm, lane, nlanes, active, tw, sw, kp); break;
+        case 17: pingpong_stage_lds<T, 17, S>(src, dst, L, Ns, nm, lane, nlanes, active, tw, sw, kp); break;
+        case 19: pingpong_stage_lds<T, 19, S>(src, dst, L, Ns, nm, lane, nlanes, active, tw, sw, kp); break;
+        case 23: pingpong_stage_lds<T, 23, S>(src, dst, L, Ns, nm, lane, nlanes, active, tw, sw, kp); break;
+        case 29: pingpong_stage_lds<T, 29, S>(src, dst, L, Ns, nm, lane, nlanes, active, tw, sw, kp); break;
+        case 31: pingpong_stage_lds<T, 31, S>(src, dst, L, Ns, nm, lane, nlanes, active, tw, sw, kp); break;
+        default: pingpong_stage_generic<T, S>(src, dst, L, R, Ns, nm, lane, nlanes, active, tw, sw, kp); break;
       }
       cpx<T>* t = src;
       src = dst;

@@ -200,11 +200,12 @@ __device__ __forceinline__ cpx<T>* buf_b(cpx<T>* lds, const LineGeom& g, int r) 
   return lds + (g.R + r) * g.lpitch;
 }
 // Base of the buffer set that holds the result after an FFT of f.  MIX: 0 power-of-two
-// lengths (compile-time stages, in place), 1 lengths whose factors are 2, 3, 4, 5, 7, 8
-// (ping-pong), 2 lengths with a prime factor 11..31 (ping-pong, larger register footprint).
+// lengths (compile-time stages, in place), 1 lengths whose factors are 2, 3, 4, 5, 7, 8 (in
+// place), 2 lengths with a prime factor of 11 or more (ping-pong: the result is in buffer b
+// after an odd number of stages).
 template <typename T, int MIX>
 __device__ __forceinline__ cpx<T>* result_base(cpx<T>* lds, const LineGeom& g, const FftDesc& f) {
-  return (MIX != 0 && (f.nst & 1)) ? lds + g.R * g.lpitch : lds;
+  return (MIX == 2 && (f.nst & 1)) ? lds + g.R * g.lpitch : lds;
 }
 
 // ---------------------------------------------------------------------------
@@ -1193,7 +1194,8 @@ hipError_t launch_lag_octant(int ndim, const int32_t* O, const double* h, int ki
   return hipGetLastError();
 }
 
-static bool nbuf_ok(const LineGeom& g, int mix) { return (mix != 0) == (g.nbuf == 2); }
+// two LDS buffers per line exactly for the ping-pong variant (primes of 11 and more)
+static bool nbuf_ok(const LineGeom& g, int mix) { return (mix == 2) == (g.nbuf == 2); }
 
 // kernel variant of a transform (the MIX template argument)
 static int fft_variant(const FftDesc& f) {

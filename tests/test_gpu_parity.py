@@ -149,6 +149,11 @@ FIELD_CASES = [
     ("prime37_2d_f64", (74, 54), (1.0, 1.0), dict(kind="exp", sigma2=1.0, a=3.0), 1, 0, 2),
     ("prime127_2d_f32", (2032, 16), (1.0, 1.0), dict(kind="exp", sigma2=1.0, a=4.0), 0, 0, 2),
     ("prime41_3d_f32", (82, 20, 24), (1.0, 1.0, 1.0), dict(kind="exp", sigma2=0.8, a=1.5), 0, 0, 2),
+    # in-place mixed radix: every radix up to 8 (2N = 3000 = 3.5^3.8, 1260 = 3^2.5.7.4), FP64 beyond
+    # the two-buffer limit
+    ("mixed_large_2d_f64", (1500, 12), (1.0, 1.0), dict(kind="exp", sigma2=1.0, a=4.0), 1, 0, 2),
+    ("mixed_357_2d_f32", (630, 40), (1.0, 1.0), dict(kind="exp", sigma2=1.0, a=4.0), 0, 2, 3),
+    ("mixed_3d_f32", (30, 42, 36), (1.0, 1.0, 1.0), dict(kind="exp", sigma2=0.8, a=1.5), 0, 0, 2),
 ]
 
 
