@@ -28,7 +28,7 @@
  *    (any factorisation: powers of two in radices up to 16, the primes up to 31
  *    in dedicated butterflies, larger primes in a generic prime stage), each
  *    embedding with fewer than 2^32 cells; in FP64, a first periodic side whose
- *    length has a prime factor of 11 or more is at most ~2400 (two of its lines,
+ *    length has a prime factor above 31 is at most ~2400 (two of its lines,
  *    each with a second buffer for the ping-pong stages of such radices, must fit
  *    one workgroup's 160 KB of LDS).  Other sizes return CE_E_UNSUPPORTED.
  */

@@ -115,11 +115,11 @@ int line_pitch_host(int L, size_t elem) { return L + (L >> 4) + (elem == 8 ? 4 :
 
 // Lines of length L (FFT), K kept; A x B lines per item.  Chooses R (power of two,
 // lines per workgroup) within the LDS budget and the 1024-thread limit.
-// True when the line FFT of f ping-pongs between two LDS buffers: a prime radix of 11 or more
-// (the radices up to 8 run in place).
+// True when the line FFT of f ping-pongs between two LDS buffers: a prime radix above 31 (the
+// generic prime stage keeps its inputs in LDS; every other radix runs in place).
 bool mixed_radix(const FftDesc& f) {
   for (int i = 0; i < f.nst; ++i)
-    if ((f.rad[i] & (f.rad[i] - 1)) && f.rad[i] > 8) return true;
+    if ((f.rad[i] & (f.rad[i] - 1)) && f.rad[i] > 31) return true;
   return false;
 }
 
@@ -544,14 +544,14 @@ ce_status check_geometry(const ce_geometry* g) {
 
 // Every pass of a plan fits one workgroup's LDS at its smallest shape: the noise pass holds two
 // lines of the first periodic axis (cells 2p and 2p + 1 share a generator call), every other
-// pass one line; lengths with a prime factor of 11 or more need two buffers per line.
+// pass one line; lengths with a prime factor above 31 need two buffers per line.
 bool passes_fit(const int* M, const int* n, int ndim, int prec) {
   const size_t elem = prec ? 16 : 8;
   auto line_bytes = [&](int L) {
     std::vector<int> rad;
     if (!factor_length(L, rad)) return (size_t)0;
     bool mix = false;
-    for (int r : rad) mix |= (r & (r - 1)) != 0 && r > 8;
+    for (int r : rad) mix |= (r & (r - 1)) != 0 && r > 31;
     return (size_t)line_pitch_host(L, elem) * elem * (mix ? 2 : 1);
   };
   if (2 * line_bytes(M[0]) > kMaxLdsBytes) return false;

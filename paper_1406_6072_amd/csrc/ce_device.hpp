@@ -231,6 +231,47 @@ __device__ __forceinline__ void odd_dft_store(cpx<T>* v, const T* cs, const T* s
   }
 }
 
+// odd_dft_store with the cosines and sines read from the line's root table where they are
+// used (tw[m step] = exp(-2 pi i m / R)); the address is uniform over the wave, so the values
+// come through the scalar cache instead of occupying 2 (R - 1) / 2 vector registers.
+template <int R, int S, typename T>
+__device__ __forceinline__ void odd_dft_store_tw(cpx<T>* v, const cpx<T>* __restrict__ tw, int step, cpx<T>* dst,
+                                                 int base, int Ns, int keep) {
+  constexpr int H = (R - 1) / 2;
+#pragma unroll
+  for (int n = 1; n <= H; ++n) {
+    const cpx<T> p = v[n], q = v[R - n];
+    v[n] = c_add(p, q);
+    v[R - n] = c_sub(p, q);
+  }
+  cpx<T> x0 = v[0];
+#pragma unroll
+  for (int n = 1; n <= H; ++n) x0 = c_add(x0, v[n]);
+  if (base < keep) dst[pidx(base)] = x0;
+#pragma unroll
+  for (int k = 1; k <= H; ++k) {
+    cpx<T> a = v[0], b = {T(0), T(0)};
+#pragma unroll
+    for (int n = 1; n <= H; ++n) {
+      const int m = (n * k) % R;  // compile-time after unrolling
+      const int mm = m <= H ? m : R - m;
+      const cpx<T> w = tw[mm * step];
+      const T c = w.x;
+      const T s = m <= H ? -w.y : w.y;
+      const cpx<T> sp = v[n];
+      const cpx<T> dm = v[R - n];
+      a.x += sp.x * c;
+      a.y += sp.y * c;
+      b.x += dm.x * s;
+      b.y += dm.y * s;
+    }
+    const cpx<T> ib = c_rot<S>(b);
+    const int o1 = base + k * Ns, o2 = base + (R - k) * Ns;
+    if (o1 < keep) dst[pidx(o1)] = c_add(a, ib);
+    if (o2 < keep) dst[pidx(o2)] = c_sub(a, ib);
+  }
+}
+
 // One in-place Stockham stage of a power-of-two line FFT with every size known
 // at compile time (Govindaraju et al. 2008 indexing): butterfly j reads
 // elements j + r L/R, multiplies by exp(S 2 pi i r k/(Ns R)), k = j mod Ns, and
@@ -373,8 +414,9 @@ __device__ __forceinline__ void inplace_stage(cpx<T>* line, int L, int Ns, uint3
   // equal in every stage of one radix, are computed once and kept live across the whole
   // transform (they spill)
   asm volatile("" : "+v"(lane));
+  constexpr bool kTab = R >= 29;  // cosines and sines read where used
   T cs[H + 1], sn[H + 1];
-  if constexpr (!kPow2) {
+  if constexpr (!kPow2 && !kTab) {
 #pragma unroll
     for (int m = 1; m <= H; ++m) {
       const cpx<T> w = tw[m * nb];
@@ -414,6 +456,8 @@ __device__ __forceinline__ void inplace_stage(cpx<T>* line, int L, int Ns, uint3
           const int o = base + r * Ns;
           if (o < keep) line[pidx(o)] = v[b][r];
         }
+      } else if constexpr (kTab) {
+        odd_dft_store_tw<R, S, T>(v[b], tw, nb, line, base, Ns, keep);
       } else {
         odd_dft_store<R, S, T>(v[b], cs, sn, line, base, Ns, keep);
       }
@@ -611,8 +655,10 @@ __device__ __forceinline__ void pow2_fft(cpx<T>* a, int L, int lane, bool active
 // Full line FFT.  Every thread of the workgroup must call it (barriers inside);
 // threads without a line pass active = false.  MIX = 0: power-of-two lengths, in place in
 // buffer a, registers staged across each barrier.  MIX = 1: the stages of f.rad (radices
-// 2, 4, 8 and the odd primes up to 7), in place in buffer a.  MIX = 2: lengths with a prime
-// factor of 11 or more, every stage ping-pong between a and b.
+// 2, 4, 8 and the odd primes up to 7), in place in buffer a.  MIX = 2: the same with the
+// primes 11..31 too (a larger register footprint; 29 and 31 read their cosines and sines from
+// the root table where used).  MIX = 3: lengths with a prime factor above 31, every stage
+// ping-pong between a and b (the generic prime stage keeps its inputs in LDS).
 // Returns the buffer that holds the result.
 template <typename T, int S, int MIX>
 __device__ __forceinline__ cpx<T>* line_fft(cpx<T>* a, cpx<T>* b, const FftDesc& f, int lane, int nlanes, bool active,
@@ -626,7 +672,7 @@ __device__ __forceinline__ cpx<T>* line_fft(cpx<T>* a, cpx<T>* b, const FftDesc&
     (void)tw;
     pow2_fft<T, S>(a, L, lane, active, static_cast<const cpx<T>*>(f.stw), keep);
     return a;
-  } else if constexpr (MIX == 1) {
+  } else if constexpr (MIX == 1 || MIX == 2) {
     (void)b;
     const cpx<T>* __restrict__ stw0 = static_cast<const cpx<T>*>(f.stw);
     for (int s = 0; s < f.nst; ++s) {
@@ -640,7 +686,22 @@ __device__ __forceinline__ cpx<T>* line_fft(cpx<T>* a, cpx<T>* b, const FftDesc&
         case 8: inplace_stage<T, 8, S>(a, L, Ns, nm, lane, nlanes, active, tw, sw, kp); break;
         case 3: inplace_stage<T, 3, S>(a, L, Ns, nm, lane, nlanes, active, tw, sw, kp); break;
         case 5: inplace_stage<T, 5, S>(a, L, Ns, nm, lane, nlanes, active, tw, sw, kp); break;
-        default: inplace_stage<T, 7, S>(a, L, Ns, nm, lane, nlanes, active, tw, sw, kp); break;
+        default:
+          if constexpr (MIX == 1) {
+            inplace_stage<T, 7, S>(a, L, Ns, nm, lane, nlanes, active, tw, sw, kp);
+          } else {
+            switch (R) {
+              case 7: inplace_stage<T, 7, S>(a, L, Ns, nm, lane, nlanes, active, tw, sw, kp); break;
+              case 11: inplace_stage<T, 11, S>(a, L, Ns, nm, lane, nlanes, active, tw, sw, kp); break;
+              case 13: inplace_stage<T, 13, S>(a, L, Ns, nm, lane, nlanes, active, tw, sw, kp); break;
+              case 17: inplace_stage<T, 17, S>(a, L, Ns, nm, lane, nlanes, active, tw, sw, kp); break;
+              case 19: inplace_stage<T, 19, S>(a, L, Ns, nm, lane, nlanes, active, tw, sw, kp); break;
+              case 23: inplace_stage<T, 23, S>(a, L, Ns, nm, lane, nlanes, active, tw, sw, kp); break;
+              case 29: inplace_stage<T, 29, S>(a, L, Ns, nm, lane, nlanes, active, tw, sw, kp); break;
+              default: inplace_stage<T, 31, S>(a, L, Ns, nm, lane, nlanes, active, tw, sw, kp); break;
+            }
+          }
+          break;
       }
       Ns *= R;
     }

@@ -201,11 +201,11 @@ __device__ __forceinline__ cpx<T>* buf_b(cpx<T>* lds, const LineGeom& g, int r) 
 }
 // Base of the buffer set that holds the result after an FFT of f.  MIX: 0 power-of-two
 // lengths (compile-time stages, in place), 1 lengths whose factors are 2, 3, 4, 5, 7, 8 (in
-// place), 2 lengths with a prime factor of 11 or more (ping-pong: the result is in buffer b
-// after an odd number of stages).
+// place), 2 the same with primes 11..31 (in place), 3 lengths with a prime factor above 31
+// (ping-pong: the result is in buffer b after an odd number of stages).
 template <typename T, int MIX>
 __device__ __forceinline__ cpx<T>* result_base(cpx<T>* lds, const LineGeom& g, const FftDesc& f) {
-  return (MIX == 2 && (f.nst & 1)) ? lds + g.R * g.lpitch : lds;
+  return (MIX == 3 && (f.nst & 1)) ? lds + g.R * g.lpitch : lds;
 }
 
 // ---------------------------------------------------------------------------
@@ -500,8 +500,8 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(sizeof
   // The workgroup generates pairs_wg pairs of the same lines one after another: the octant
   // values it reads for the first pair are still in the caches for the next ones, so the octant
   // comes from HBM once per pairs_wg pairs instead of once per pair.  The prime-butterfly
-  // variant takes one pair (its register footprint leaves no room for the loop).
-  const int npw = MIX == 2 ? 1 : g.pairs_wg;
+  // variants take one pair (their register footprint leaves no room for the loop).
+  const int npw = MIX >= 2 ? 1 : g.pairs_wg;
   for (int ip = 0; ip < npw; ++ip) {
     PassPos pp = pp0;
     pp.item = pp0.item * npw + ip;
@@ -1194,15 +1194,15 @@ hipError_t launch_lag_octant(int ndim, const int32_t* O, const double* h, int ki
   return hipGetLastError();
 }
 
-// two LDS buffers per line exactly for the ping-pong variant (primes of 11 and more)
-static bool nbuf_ok(const LineGeom& g, int mix) { return (mix == 2) == (g.nbuf == 2); }
+// two LDS buffers per line exactly for the ping-pong variant (primes above 31)
+static bool nbuf_ok(const LineGeom& g, int mix) { return (mix == 3) == (g.nbuf == 2); }
 
 // kernel variant of a transform (the MIX template argument)
 static int fft_variant(const FftDesc& f) {
   int v = 0;
   for (int i = 0; i < f.nst; ++i) {
     const int r = f.rad[i];
-    if (r & (r - 1)) v = std::max(v, r <= 7 ? 1 : 2);
+    if (r & (r - 1)) v = std::max(v, r <= 7 ? 1 : r <= 31 ? 2 : 3);
   }
   return v;
 }
@@ -1214,7 +1214,9 @@ struct Variant {
 // calls fn(Variant<v>{}) for the run-time variant v
 template <typename F>
 static void with_variant(int v, F&& fn) {
-  if (v == 2)
+  if (v == 3)
+    fn(Variant<3>{});
+  else if (v == 2)
     fn(Variant<2>{});
   else if (v == 1)
     fn(Variant<1>{});
@@ -1257,7 +1259,7 @@ hipError_t launch_noise_pass(int prec, const LineGeom& g0, const FftDesc& f, con
       g0.nitems * g0.pairs_wg < g0.items_total)
     return hipErrorInvalidValue;
   LineGeom g = g0;
-  if (mix == 2 && g.pairs_wg > 1) {  // that variant generates one pair per workgroup
+  if (mix >= 2 && g.pairs_wg > 1) {  // those variants generate one pair per workgroup
     g.pairs_wg = 1;
     g.nitems = g.items_total;
   }
