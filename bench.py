@@ -436,16 +436,18 @@ def uneven_batch_leg(b, torch, nreq, reps, sample_every=32, tune=True, schedules
             if b.ctx_check(ctx) != 0:
                 raise RuntimeError("device flagged a sampler condition in the uneven batch")
             times = []
+            enq = []
             for _ in range(reps):
                 t0 = time.perf_counter()
                 b.pipeline_run_batch(ctx, prepared)
+                enq.append(time.perf_counter() - t0)
                 torch.cuda.synchronize()
                 times.append(time.perf_counter() - t0)
             ms = 1e3 * float(np.median(times))
             leg = dict(value=round(2 * len(reqs) / (ms * 1e-3), 1), unit="realizations/s", ms_per_batch=round(ms, 3),
                        alg_GB=round(alg / 1e9, 3), alg_GBs=round(alg / (ms * 1e-3) / 1e9, 1),
                        hbm_frac=round(alg / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4), plan_s=round(plan_s, 2),
-                       python_marshal_ms=round(marshal_ms, 2),
+                       python_marshal_ms=round(marshal_ms, 2), host_enqueue_ms=round(1e3 * float(np.median(enq)), 2),
                        form="ce_pipeline_run_batch on a prepared item table (one C call per batch)")
             kept[tag] = [dict(pk=it["out_pk"].cpu().numpy(), counts=it["out_counts"].cpu().numpy(),
                               fields=it["out_fields"].cpu().numpy().astype(np.float64) if "out_fields" in it else None)

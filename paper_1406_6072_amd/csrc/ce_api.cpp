@@ -1987,17 +1987,26 @@ ce_status pipeline_batch_impl(ce_ctx* ctx, const ce_batch_item* items, int64_t n
   }
   CE_HIP(hipEventRecord(ctx->fork, s));
   ce_status st = CE_OK;
+  size_t depth = 0;
   for (int l = 0; l < nl; ++l) {
     ce_ctx* lc = ctx->lanes[l];
-    hipStream_t ls = lc->own;
-    lc->last = ls;
-    if (st == CE_OK && hipStreamWaitEvent(ls, ctx->fork, 0) != hipSuccess) st = CE_E_DEVICE;
-    for (size_t i : assign[l]) {
-      if (st != CE_OK) break;
-      st = run_batch_group(lc, items, *order[i], *static_cast<const GroupKey*>(keys[i]), d, ls);
-    }
-    // the join is recorded even after a failure, so s never waits on an unrecorded event
-    if (hipEventRecord(lc->joined, ls) != hipSuccess || hipStreamWaitEvent(s, lc->joined, 0) != hipSuccess)
+    lc->last = lc->own;
+    if (st == CE_OK && hipStreamWaitEvent(lc->own, ctx->fork, 0) != hipSuccess) st = CE_E_DEVICE;
+    depth = std::max(depth, assign[l].size());
+  }
+  // the groups are enqueued round-robin over the lanes, so every lane has work on the device
+  // while the host is still enqueueing the rest
+  for (size_t p = 0; p < depth && st == CE_OK; ++p)
+    for (int l = 0; l < nl && st == CE_OK; ++l)
+      if (p < assign[l].size()) {
+        const size_t i = assign[l][p];
+        st = run_batch_group(ctx->lanes[l], items, *order[i], *static_cast<const GroupKey*>(keys[i]), d,
+                             ctx->lanes[l]->own);
+      }
+  // the joins are recorded even after a failure, so s never waits on an unrecorded event
+  for (int l = 0; l < nl; ++l) {
+    ce_ctx* lc = ctx->lanes[l];
+    if (hipEventRecord(lc->joined, lc->own) != hipSuccess || hipStreamWaitEvent(s, lc->joined, 0) != hipSuccess)
       st = st == CE_OK ? CE_E_DEVICE : st;
   }
   return st;
