@@ -242,6 +242,8 @@ def parse():
     ap.add_argument("--schedules", default="",
                     help="launch schedules (JSON) loaded before timing; default: the package's "
                          "schedules_gfx950.json; 'none': default schedules (tuned unless --no-tune)")
+    ap.add_argument("--batch-lanes", type=int, default=0,
+                    help="concurrent lanes of ce_pipeline_run_batch (0: the library's default)")
     ap.add_argument("--retune", action="store_true",
                     help="load no schedule file (unless --schedules names one): tune every shape")
     ap.add_argument("--save-schedules", default="",
@@ -394,7 +396,7 @@ def cpu_oracle_sample(w, seconds):
                 seconds=dt)
 
 
-def uneven_batch_leg(b, torch, nreq, reps, sample_every=32, tune=True, schedules="", save=""):
+def uneven_batch_leg(b, torch, nreq, reps, sample_every=32, tune=True, schedules="", save="", lanes=0):
     """The uneven batch (4096 requests of 2 realizations, 2-D sides 32..512 step 16, each with its
     own two-point function) through ce_pipeline_run_batch, FP32 and FP64 on identical Philox
     streams; plans are built before the timed region.  Also the same requests as one
@@ -407,6 +409,8 @@ def uneven_batch_leg(b, torch, nreq, reps, sample_every=32, tune=True, schedules
     from synth import workloads
     reqs = workloads.uneven_batch(nreq)
     ctx = b.ctx_create(0)
+    if lanes:
+        b.ctx_set_option(ctx, b.OPT_BATCH_LANES, lanes)
     out = dict(requests=len(reqs), realizations=2 * len(reqs),
                distinct_shapes=len({r["n"] for r in reqs}))
     kept = {}
@@ -1011,7 +1015,8 @@ def main():
 
     if args.batch_requests:
         out["uneven_batch"] = uneven_batch_leg(b, torch, args.batch_requests, args.batch_reps, tune=not args.no_tune,
-                                               schedules=schedule_file(args), save=args.save_schedules)
+                                               schedules=schedule_file(args), save=args.save_schedules,
+                                               lanes=args.batch_lanes)
         print("uneven batch %s" % json.dumps(out["uneven_batch"]), file=sys.stderr, flush=True)
 
     if args.serve_rates:
