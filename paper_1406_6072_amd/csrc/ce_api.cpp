@@ -70,23 +70,9 @@ bool factor_length(int L, std::vector<int>& rad) {
   for (int p : odd) n /= p;  // the power of two that remains
   int e = 0;
   while ((1 << e) < n) ++e;
+  // the power of two in radices of at most 16 (the compile-time stage sequences of the
+  // power-of-two kernels use the same split)
   std::vector<int> p2;
-  if (!odd.empty()) {
-    // mixed lengths run one butterfly at a time with the radix in registers: the power of two
-    // goes in radices of at most 8 (a radix-16 butterfly next to the odd ones spills)
-    int k = e;
-    if (k % 3 == 1 && k >= 4) {
-      p2.push_back(4);
-      p2.push_back(4);
-      k -= 4;
-    }
-    for (; k >= 3; k -= 3) p2.push_back(8);
-    if (k == 2) p2.push_back(4);
-    if (k == 1) p2.push_back(2);
-    for (int p : odd) rad.push_back(p);
-    for (int p : p2) rad.push_back(p);
-    return rad.size() <= (size_t)kMaxStages;
-  }
   int n4 = e / 4, rem = e % 4;
   if (rem == 1 && n4 >= 1) {
     for (int i = 0; i < n4 - 1; ++i) p2.push_back(16);
@@ -102,8 +88,12 @@ bool factor_length(int L, std::vector<int>& rad) {
     if (rem == 2) p2.push_back(4);
     if (rem == 1) p2.push_back(2);
   }
-  for (int p : odd) rad.push_back(p);
+  // mixed lengths: the power of two first, then the odd primes.  A stage writes its outputs
+  // with stride Ns (the product of the radices before it), so the small-stride writes fall on
+  // radices 16 and 8, whose strides the LDS padding spreads over the banks, and the odd radices
+  // write runs of Ns consecutive elements
   for (int p : p2) rad.push_back(p);
+  for (int p : odd) rad.push_back(p);
   if (rad.size() > (size_t)kMaxStages) return false;
   return !rad.empty();
 }

@@ -684,6 +684,7 @@ __device__ __forceinline__ cpx<T>* line_fft(cpx<T>* a, cpx<T>* b, const FftDesc&
         case 2: inplace_stage<T, 2, S>(a, L, Ns, nm, lane, nlanes, active, tw, sw, kp); break;
         case 4: inplace_stage<T, 4, S>(a, L, Ns, nm, lane, nlanes, active, tw, sw, kp); break;
         case 8: inplace_stage<T, 8, S>(a, L, Ns, nm, lane, nlanes, active, tw, sw, kp); break;
+        case 16: inplace_stage<T, 16, S>(a, L, Ns, nm, lane, nlanes, active, tw, sw, kp); break;
         case 3: inplace_stage<T, 3, S>(a, L, Ns, nm, lane, nlanes, active, tw, sw, kp); break;
         case 5: inplace_stage<T, 5, S>(a, L, Ns, nm, lane, nlanes, active, tw, sw, kp); break;
         default:
@@ -720,6 +721,7 @@ __device__ __forceinline__ cpx<T>* line_fft(cpx<T>* a, cpx<T>* b, const FftDesc&
         case 2: pingpong_stage<T, 2, S>(src, dst, L, Ns, nm, lane, nlanes, active, tw, sw, kp); break;
         case 4: pingpong_stage<T, 4, S>(src, dst, L, Ns, nm, lane, nlanes, active, tw, sw, kp); break;
         case 8: pingpong_stage<T, 8, S>(src, dst, L, Ns, nm, lane, nlanes, active, tw, sw, kp); break;
+        case 16: pingpong_stage<T, 16, S>(src, dst, L, Ns, nm, lane, nlanes, active, tw, sw, kp); break;
         case 3: pingpong_stage<T, 3, S>(src, dst, L, Ns, nm, lane, nlanes, active, tw, sw, kp); break;
         case 5: pingpong_stage<T, 5, S>(src, dst, L, Ns, nm, lane, nlanes, active, tw, sw, kp); break;
         case 7: pingpong_stage<T, 7, S>(src, dst, L, Ns, nm, lane, nlanes, active, tw, sw, kp); break;
