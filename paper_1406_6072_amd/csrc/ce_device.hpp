@@ -189,12 +189,14 @@ struct Pow2Dft {
 };
 
 // Odd radix R, streamed: pairs n, R-n share cosines and sines, so only
-// cos/sin(2 pi m / R) for m = 1..(R-1)/2 are needed (held in registers); each
-// output pair X_k, X_{R-k} is stored as soon as it is formed.  The line's root
-// table gives tw[m L / R] = exp(-2 pi i m / R).
-template <int R, int S, typename T>
-__device__ __forceinline__ void odd_dft_store(cpx<T>* v, const T* cs, const T* sn, cpx<T>* dst, int base, int Ns,
-                                              int keep) {
+// cos/sin(2 pi m / R) for m = 1..(R-1)/2 are needed; each output pair X_k, X_{R-k} is handed to
+// put(k, X) as soon as it is formed.  TAB = false: the cosines and sines are in registers (cs,
+// sn); TAB = true: they are read from the line's root table where used (tw[m step] =
+// exp(-2 pi i m / R)): the address is uniform over the wave, so the values come through the
+// scalar cache instead of occupying (R - 1) vector registers (radices 29 and 31).
+template <int R, int S, bool TAB, typename T, typename Put>
+__device__ __forceinline__ void odd_dft(cpx<T>* v, const T* cs, const T* sn, const cpx<T>* __restrict__ tw, int step,
+                                        Put&& put) {
   constexpr int H = (R - 1) / 2;
   // sums and differences of the pairs n, R - n replace them in place, so the live set is
   // the R inputs plus the (R - 1) / 2 cosines and sines
@@ -207,7 +209,7 @@ __device__ __forceinline__ void odd_dft_store(cpx<T>* v, const T* cs, const T* s
   cpx<T> x0 = v[0];
 #pragma unroll
   for (int n = 1; n <= H; ++n) x0 = c_add(x0, v[n]);
-  if (base < keep) dst[pidx(base)] = x0;
+  put(0, x0);
 #pragma unroll
   for (int k = 1; k <= H; ++k) {
     cpx<T> a = v[0], b = {T(0), T(0)};
@@ -215,8 +217,15 @@ __device__ __forceinline__ void odd_dft_store(cpx<T>* v, const T* cs, const T* s
     for (int n = 1; n <= H; ++n) {
       const int m = (n * k) % R;  // compile-time after unrolling
       const int mm = m <= H ? m : R - m;
-      const T c = cs[mm];
-      const T s = m <= H ? sn[mm] : -sn[mm];
+      T c, s;
+      if constexpr (TAB) {
+        const cpx<T> w = tw[mm * step];
+        c = w.x;
+        s = m <= H ? -w.y : w.y;
+      } else {
+        c = cs[mm];
+        s = m <= H ? sn[mm] : -sn[mm];
+      }
       const cpx<T> sp = v[n];
       const cpx<T> dm = v[R - n];
       a.x += sp.x * c;
@@ -225,51 +234,19 @@ __device__ __forceinline__ void odd_dft_store(cpx<T>* v, const T* cs, const T* s
       b.y += dm.y * s;
     }
     const cpx<T> ib = c_rot<S>(b);
-    const int o1 = base + k * Ns, o2 = base + (R - k) * Ns;
-    if (o1 < keep) dst[pidx(o1)] = c_add(a, ib);
-    if (o2 < keep) dst[pidx(o2)] = c_sub(a, ib);
+    put(k, c_add(a, ib));
+    put(R - k, c_sub(a, ib));
   }
 }
 
-// odd_dft_store with the cosines and sines read from the line's root table where they are
-// used (tw[m step] = exp(-2 pi i m / R)); the address is uniform over the wave, so the values
-// come through the scalar cache instead of occupying 2 (R - 1) / 2 vector registers.
+// odd_dft with output r stored at dst[pidx(base + r Ns)] when that index is below keep.
 template <int R, int S, typename T>
-__device__ __forceinline__ void odd_dft_store_tw(cpx<T>* v, const cpx<T>* __restrict__ tw, int step, cpx<T>* dst,
-                                                 int base, int Ns, int keep) {
-  constexpr int H = (R - 1) / 2;
-#pragma unroll
-  for (int n = 1; n <= H; ++n) {
-    const cpx<T> p = v[n], q = v[R - n];
-    v[n] = c_add(p, q);
-    v[R - n] = c_sub(p, q);
-  }
-  cpx<T> x0 = v[0];
-#pragma unroll
-  for (int n = 1; n <= H; ++n) x0 = c_add(x0, v[n]);
-  if (base < keep) dst[pidx(base)] = x0;
-#pragma unroll
-  for (int k = 1; k <= H; ++k) {
-    cpx<T> a = v[0], b = {T(0), T(0)};
-#pragma unroll
-    for (int n = 1; n <= H; ++n) {
-      const int m = (n * k) % R;  // compile-time after unrolling
-      const int mm = m <= H ? m : R - m;
-      const cpx<T> w = tw[mm * step];
-      const T c = w.x;
-      const T s = m <= H ? -w.y : w.y;
-      const cpx<T> sp = v[n];
-      const cpx<T> dm = v[R - n];
-      a.x += sp.x * c;
-      a.y += sp.y * c;
-      b.x += dm.x * s;
-      b.y += dm.y * s;
-    }
-    const cpx<T> ib = c_rot<S>(b);
-    const int o1 = base + k * Ns, o2 = base + (R - k) * Ns;
-    if (o1 < keep) dst[pidx(o1)] = c_add(a, ib);
-    if (o2 < keep) dst[pidx(o2)] = c_sub(a, ib);
-  }
+__device__ __forceinline__ void odd_dft_store(cpx<T>* v, const T* cs, const T* sn, cpx<T>* dst, int base, int Ns,
+                                              int keep) {
+  odd_dft<R, S, false>(v, cs, sn, static_cast<const cpx<T>*>(nullptr), 0, [&](int r, cpx<T> x) {
+    const int o = base + r * Ns;
+    if (o < keep) dst[pidx(o)] = x;
+  });
 }
 
 // One in-place Stockham stage of a power-of-two line FFT with every size known
@@ -409,12 +386,12 @@ __device__ __forceinline__ void inplace_stage(cpx<T>* line, int L, int Ns, uint3
   constexpr bool kPow2 = (R & (R - 1)) == 0;
   constexpr int H = (R - 1) / 2;
   constexpr int NB = (kEPT + R - 1) / R;
+  constexpr bool kTab = R >= 29;  // cosines and sines read where used
   const int nb = L / R;
   // the lane index is made opaque per stage: otherwise the butterfly indices and LDS offsets,
   // equal in every stage of one radix, are computed once and kept live across the whole
   // transform (they spill)
   asm volatile("" : "+v"(lane));
-  constexpr bool kTab = R >= 29;  // cosines and sines read where used
   T cs[H + 1], sn[H + 1];
   if constexpr (!kPow2 && !kTab) {
 #pragma unroll
@@ -424,13 +401,24 @@ __device__ __forceinline__ void inplace_stage(cpx<T>* line, int L, int Ns, uint3
       sn[m] = -w.y;
     }
   }
+  // With one pad element per 16, pidx(x + r s) = pidx(x) + r (s + s / 16) when 16 divides s:
+  // then a butterfly's R inputs (stride nb) or outputs (stride Ns) are one index plus a uniform
+  // stride each, instead of a padded index per element.
+  const bool lin_in = (nb & 15) == 0, lin_out = (Ns & 15) == 0;
+  const int nbp = nb + (nb >> 4), nsp = Ns + (Ns >> 4);
   cpx<T> v[NB][R];
 #pragma unroll
   for (int b = 0; b < NB; ++b) {
     const int j = lane + b * nlanes;
     if (active && j < nb) {
+      if (lin_in) {
+        const int p0 = pidx(j);
 #pragma unroll
-      for (int r = 0; r < R; ++r) v[b][r] = line[pidx(j + r * nb)];
+        for (int r = 0; r < R; ++r) v[b][r] = line[p0 + r * nbp];
+      } else {
+#pragma unroll
+        for (int r = 0; r < R; ++r) v[b][r] = line[pidx(j + r * nb)];
+      }
     }
   }
   __syncthreads();
@@ -449,17 +437,29 @@ __device__ __forceinline__ void inplace_stage(cpx<T>* line, int L, int Ns, uint3
           v[b][r] = c_mul(v[b][r], t);
         }
       }
-      if constexpr (kPow2) {
-        Pow2Dft<R, S, T>::run(v[b]);
+      if (lin_out && base + (R - 1) * Ns < keep) {
+        // every output kept, at one index plus a uniform stride
+        cpx<T>* o = line + pidx(base);
+        auto put = [&](int r, cpx<T> x) { o[r * nsp] = x; };
+        if constexpr (kPow2) {
+          Pow2Dft<R, S, T>::run(v[b]);
 #pragma unroll
-        for (int r = 0; r < R; ++r) {
-          const int o = base + r * Ns;
-          if (o < keep) line[pidx(o)] = v[b][r];
+          for (int r = 0; r < R; ++r) put(r, v[b][r]);
+        } else {
+          odd_dft<R, S, kTab>(v[b], cs, sn, tw, nb, put);
         }
-      } else if constexpr (kTab) {
-        odd_dft_store_tw<R, S, T>(v[b], tw, nb, line, base, Ns, keep);
       } else {
-        odd_dft_store<R, S, T>(v[b], cs, sn, line, base, Ns, keep);
+        auto put = [&](int r, cpx<T> x) {
+          const int o = base + r * Ns;
+          if (o < keep) line[pidx(o)] = x;
+        };
+        if constexpr (kPow2) {
+          Pow2Dft<R, S, T>::run(v[b]);
+#pragma unroll
+          for (int r = 0; r < R; ++r) put(r, v[b][r]);
+        } else {
+          odd_dft<R, S, kTab>(v[b], cs, sn, tw, nb, put);
+        }
       }
     }
   }
