@@ -859,7 +859,8 @@ SCHEDULES = [dict(), dict(lines=(4, 4, 1, 4)), dict(lines=(32, 32, 8, 32), bin_l
 
 
 @pytest.mark.parametrize("n,prec,nb", [((128, 96), 0, 24), ((64, 64), 1, 16), ((16, 24, 20), 0, 6),
-                                       ((1024, 1024), 0, 128)])
+                                       ((1024, 1024), 0, 128), ((44, 52), 0, 10), ((74, 38), 1, 10),
+                                       ((62, 34), 0, 12)])
 def test_schedules_give_bitwise_identical_results(ce, n, prec, nb):
     """Every schedule option (lines per workgroup of each pass, noise-pass tile order, blocks and
     pairs per workgroup, binning LDS) changes only the launch shape: fields, delta, counts, N_tot, P(k) and the

@@ -374,6 +374,13 @@ def test_batch_matches_items_alone(ce):
         ((32, 32), dict(kind="exp", sigma2=1.0, a=3.0), 0, 6, 2, 1.0, 16, True, True),  # other nbins
         ((96, 96), dict(kind="powexp", sigma2=1.0, r0=4.0, gamma=1.8, rc=300.0), 0, 0, 4, 0.3, 24, True, True),
         ((16, 16, 16), dict(kind="exp", sigma2=0.8, a=1.5), 0, 2, 4, 2.0, 6, True, True),
+        # every FFT variant in one batch: 2N = 60 = 4.3.5 and 84 (in place, radices up to 7),
+        # 88 = 8.11 and 104 = 8.13 (in place, primes 11..31), 148 = 4.37 (ping-pong, generic prime)
+        ((30, 42), dict(kind="exp", sigma2=0.9, a=3.0), 0, 0, 4, 1.0, 10, True, True),
+        ((44, 52), dict(kind="exp", sigma2=0.9, a=3.0), 0, 0, 3, 1.0, 10, True, True),
+        ((74, 38), dict(kind="exp", sigma2=0.9, a=3.0), 0, 0, 4, 1.0, 10, True, True),
+        ((44, 52), dict(kind="exp", sigma2=0.9, a=3.0), 1, 0, 2, 1.0, 10, True, True),
+        ((74, 38), dict(kind="exp", sigma2=0.9, a=3.0), 1, 2, 3, 1.0, 10, True, True),
         ((32, 32), dict(kind="exp", sigma2=1.0, a=3.0), 0, 0, 3, 1.0, 8, True, True),  # 1 x 0.5 cells
     ]
     cells_h = {len(specs) - 1: (1.0, 0.5)}  # same sides as item 0, other cell shape: its own group
