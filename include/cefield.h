@@ -552,7 +552,7 @@ typedef struct {
   int32_t lines_noise, lines_inner, lines_last, lines_bins;
   int32_t noise_order, noise_block;
   int32_t noise_pairs;  /* pairs each noise-pass workgroup generates for its lines (1..64; 0 = automatic) */
-  int32_t reserved;
+  int32_t reserved;     /* padding: ignored on input, 0 on output */
   int64_t bin_lds;
   double ms, default_ms;  /* ce_autotune: median step time of the chosen and of the default schedule */
 } ce_schedule;

@@ -1388,6 +1388,7 @@ ce_status run_inverse(ce_ctx* ctx, const ce_plan* p, const InverseSetup& fs, uin
                           cap_lines(ctx, 0, 32));
   g1.item_minor = ctx->sch().noise_order;
   g1.item_block = ctx->sch().noise_block;
+  g1.mirror_order = 1;
   // each workgroup generates pairs_wg consecutive pairs of its lines, so the octant is fetched
   // once per pairs_wg pairs; automatic: the most (at most 8) that leave 4096 workgroups.  More
   // pairs per workgroup cut the octant reads further but let the workgroups that share the
@@ -2581,6 +2582,7 @@ void to_public(const Schedule& s, ce_schedule* p) {
   p->noise_order = s.noise_order;
   p->noise_block = s.noise_block;
   p->noise_pairs = s.noise_pairs;
+  p->reserved = 0;
   p->bin_lds = (int64_t)s.bin_lds;
 }
 

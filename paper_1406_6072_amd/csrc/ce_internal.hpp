@@ -48,6 +48,9 @@ struct LineGeom {
   // items_total is the number of items)
   int32_t pairs_wg = 1;
   int64_t items_total = 0;
+  // noise pass: line groups taken in the order 0, G-1, 1, G-2, ... (G groups per item), so the
+  // groups whose lines mirror each other (b and M - b read one sqrt(lambda) line) run together
+  int32_t mirror_order = 0;
   int32_t threads = 0;         // workgroup size when above R nlanes (the fused epilogue spreads its cells)
 };
 

@@ -45,6 +45,7 @@ __device__ __forceinline__ PassPos pass_pos(const LineGeom& g) {
     p.item = t / g.groups_per_item;
     p.grp = t - p.item * g.groups_per_item;
   }
+  if (g.mirror_order) p.grp = (p.grp & 1) ? g.groups_per_item - 1 - (p.grp >> 1) : (p.grp >> 1);
   p.line0 = p.grp * g.R;
   const int64_t nlines = g.A * g.B;
   const int64_t left = nlines - p.line0;
