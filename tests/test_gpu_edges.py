@@ -88,7 +88,10 @@ def test_nbar_zero_gives_empty_maps_and_a_flag(ce):
     plan.release()
 
 
-@pytest.mark.parametrize("n,prec", [((4, 4), 1), ((4, 4, 4), 0), ((4, 6), 1)])
+@pytest.mark.parametrize("n,prec", [((4, 4), 1), ((4, 4, 4), 0), ((4, 6), 1),
+                                    # short mixed lines (one lane per line): 2N = 12, 44 = 4.11,
+                                    # 124 = 4.31, 148 = 4.37, 20 = 4.5, 28 = 4.7
+                                    ((6, 22), 0), ((62, 4), 0), ((4, 74), 1), ((6, 10, 14), 0), ((22, 6), 1)])
 def test_smallest_sides_match_oracle(ce, n, prec):
     b, ctx = ce
     xi = dict(kind="exp", sigma2=1.0, a=1.0)
