@@ -374,7 +374,7 @@ __device__ __forceinline__ void pingpong_stage(const cpx<T>* src, cpx<T>* dst, i
   __syncthreads();
 }
 
-// In-place Stockham stage of a mixed-radix line (radix R <= 8, any supported L): each thread
+// In-place Stockham stage of a mixed-radix line (R = 2, 4, 8, 16 or an odd prime up to 31): each thread
 // loads the R inputs of all its butterflies j = lane + b nlanes (at most ceil(kEPT / R) of
 // them, since nlanes >= L / kEPT) into registers, the workgroup waits, and then each butterfly
 // is twiddled, transformed and stored into the same buffer.  One LDS buffer per line (the
@@ -655,7 +655,7 @@ __device__ __forceinline__ void pow2_fft(cpx<T>* a, int L, int lane, bool active
 // Full line FFT.  Every thread of the workgroup must call it (barriers inside);
 // threads without a line pass active = false.  MIX = 0: power-of-two lengths, in place in
 // buffer a, registers staged across each barrier.  MIX = 1: the stages of f.rad (radices
-// 2, 4, 8 and the odd primes up to 7), in place in buffer a.  MIX = 2: the same with the
+// 2, 4, 8, 16 and the odd primes up to 7), in place in buffer a.  MIX = 2: the same with the
 // primes 11..31 too (a larger register footprint; 29 and 31 read their cosines and sines from
 // the root table where used).  MIX = 3: lengths with a prime factor above 31, every stage
 // ping-pong between a and b (the generic prime stage keeps its inputs in LDS).

@@ -41,7 +41,7 @@ struct LineGeom {
   int32_t L = 0, K = 0;
   int32_t R = 0, nlanes = 0;
   int32_t lpitch = 0;          // LDS elements per line buffer
-  int32_t nbuf = 1;            // LDS buffers per line: 1 (in place) or 2 (ping-pong, mixed radix)
+  int32_t nbuf = 1;            // LDS buffers per line: 1 (in place) or 2 (ping-pong: a prime above 31)
   int32_t item_minor = 0;      // tile order: 0 = item-major (groups of one item adjacent), 1 = group-major
   int32_t item_block = 1;      // item-major order over blocks of this many items (group-major inside a block)
   // noise pass: each workgroup takes pairs_wg consecutive items (nitems counts such tiles of items;
