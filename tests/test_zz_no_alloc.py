@@ -39,10 +39,13 @@ CALLS = [  # (n, xi, precision, count, nbins): the second call of each case is s
      ((32, 32), dict(kind="exp", sigma2=0.5, a=4.0), 1, 3, 8)],
     [((128, 128, 128), dict(kind="exp", sigma2=0.8, a=1.5), 0, 6, 12),
      ((16, 24, 20), dict(kind="exp", sigma2=0.8, a=1.5), 0, 3, 6)],
+    # prime radices: 2N = 148 = 4.37 (ping-pong), then 124 = 4.31 and 68 = 4.17 (in place)
+    [((74, 38), dict(kind="exp", sigma2=0.9, a=3.0), 0, 5, 10),
+     ((62, 34), dict(kind="exp", sigma2=0.9, a=3.0), 0, 3, 10)],
 ]
 
 
-@pytest.mark.parametrize("calls", CALLS, ids=["2d_f32", "2d_f64", "3d_f32"])
+@pytest.mark.parametrize("calls", CALLS, ids=["2d_f32", "2d_f64", "3d_f32", "primes_f32"])
 def test_noalloc_equals_pipeline_run(ce, calls):
     b, ctx = ce
     for k, (n, xi, prec, count, nb) in enumerate(calls):
