@@ -511,7 +511,10 @@ def test_masked_pipeline_without_counts(ce, n):
 
 @pytest.mark.parametrize("n,prec,nb", [((64, 64), 1, 16), ((96, 96), 0, 24), ((128, 128), 0, 20),
                                        ((96, 64), 0, 12), ((16, 16, 16), 0, 6), ((16, 24, 20), 1, 8),
-                                       ((32, 32, 32), 0, 10)])
+                                       ((32, 32, 32), 0, 10),
+                                       # prime radices in every pass: 2N = 124 = 4.31, 88 = 8.11 and
+                                       # N = 62, 44; 2N = 148 = 4.37 (ping-pong), 76 = 4.19
+                                       ((62, 44), 0, 10), ((74, 38), 1, 8)])
 def test_masked_pipeline_matches_unfused_and_oracle(ce, n, prec, nb):
     """Masked survey (Sec. 3.1 rate nbar f rho; Sec. 3.2 contrast on f != 0): the masked
     pipeline equals the unfused calls with the same mask (fields, delta, counts, N_tot bitwise;
@@ -579,7 +582,8 @@ def test_linear_edges_equal_default_shells(ce, n, prec):
     plan.release()
 
 
-@pytest.mark.parametrize("n,prec,masked", [((128, 128), 1, False), ((96, 64), 0, True), ((20, 16, 24), 0, False)])
+@pytest.mark.parametrize("n,prec,masked", [((128, 128), 1, False), ((96, 64), 0, True), ((20, 16, 24), 0, False),
+                                           ((62, 44), 0, True)])
 def test_log_edges_match_oracle(ce, n, prec, masked):
     """The paper's binning, 20 shells equally spaced in ln k up to the pixel scale, against the
     oracle (field maps; counts with a mask)."""
