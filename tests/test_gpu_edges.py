@@ -121,3 +121,22 @@ def test_largest_2d_side_matches_oracle(ce):
     ref_plan = embedding.plan(n, (1.0, 1.0), xi)
     ref = ofields.generate_fields(ref_plan, 3, 1, 0, 2)
     check_maps(got, ref, 1e-5, math.sqrt(ref_plan["sigma2"]), "2048^2 survey")
+
+
+@pytest.mark.parametrize("n,prec", [((2040, 2040), 0), ((1530, 12), 1)])
+def test_largest_mixed_sides_match_oracle(ce, n, prec):
+    """The largest sides whose embedding has odd factors: 2N = 4080 = 16.3.5.17 (FP32, one pair,
+    in-place prime stage on a 4080-point line) and a 3060-point first line in FP64
+    (3060 = 4.3.3.5.17, two lines of it in one workgroup's LDS)."""
+    b, ctx = ce
+    xi = dict(kind="powexp", sigma2=1.0, r0=4.0, gamma=1.8, rc=300.0)
+    print("largest mixed side", n, prec, b.fft_factors(2 * n[0]), flush=True)
+    plan = b.plan_embedding(ctx, n, (1.0, 1.0), xi, prec)
+    out = torch.empty(2 * plan.cells, dtype=plan.dtype, device="cuda")
+    b.generate_fields(ctx, plan, 6, 3, 0, 2, out)
+    torch.cuda.synchronize()
+    got = out.cpu().numpy().astype(np.float64).reshape((2,) + n)
+    plan.release()
+    ref_plan = embedding.plan(n, (1.0, 1.0), xi)
+    ref = ofields.generate_fields(ref_plan, 6, 3, 0, 2)
+    check_maps(got, ref, 1e-12 if prec == 1 else 1e-5, math.sqrt(ref_plan["sigma2"]), "mixed %s" % (n,))
